@@ -1,0 +1,202 @@
+"""SPAI preconditioner and its cheap update (test infrastructure only).
+
+Build (Section 3.1, eq. (3.1)): the right approximate inverse minimises
+||I - K P||_F over matrices P with a prescribed sparsity pattern; the square
+of the Frobenius norm splits into n independent least-squares problems, one
+per column, min ||e_j - K p_j||_2.  The paper reaches each column's minimum
+iteratively (a minimal-residual loop stopped at a tolerance); here each column
+problem is solved exactly, which is the limit that loop approaches, with the
+pattern fixed to the structural pattern of K(s):
+    J = pattern of column j (allowed nonzeros of p_j),
+    I = rows where K(:, J) has nonzeros,
+    p_J = argmin || e_j(I) - K(I, J) p ||_2   (a library least-squares solve).
+Rows outside I are zero on both sides, so this is the full column problem.
+
+Readings fixed here (each listed in the design notes):
+  * equilibrate: the column problems are posed for Khat = S K S with
+    S = diag(K)^{-1/2}; the result is mapped back as P = S Phat S.
+  * symmetrize (optional, off by default): Phat is replaced by
+    (Phat + Phat^T) / 2 before mapping back.  On the cantilever this average
+    is indefinite at the free tip, so the default keeps the right SPAI as the
+    paper defines it and lets CG use a direction update that does not need a
+    symmetric preconditioner.
+
+Update (Section 3.2): instead of a new SPAI for K_new, find Q minimising
+||K_old - K_new Q||_F column by column, starting from Q = alpha I with alpha
+the minimiser of ||K_old - alpha K_new||_F, i.e.
+    alpha = (1/2) trace(K_old^T K_new + K_new^T K_old) / trace(K_new^T K_new).
+A column whose residual at the start, k_old_j - alpha K_new e_j, is already
+within the tolerance keeps q_j = alpha e_j (the update algorithm never enters
+its inner loop for it); every other column is solved exactly on the pattern.
+The tolerance is read relative to ||k_old_j||.  With equilibration both
+matrices are scaled by the *new* diagonal, Khat_x = S_new K_x S_new, and the
+factor is mapped back as Q = S_new Qhat S_new^{-1}, so that K_new Q ~ K_old.
+The preconditioner after updates is the chain Q_z ... Q_2 P_1, applied factor
+by factor and never multiplied out (Section 3.2, last paragraph).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import scipy.sparse as sp
+
+
+@dataclasses.dataclass
+class Factor:
+    """One preconditioner factor on the structural pattern of K(s)."""
+
+    values: np.ndarray        # CSR-ordered values of the mapped-back factor
+    hat: np.ndarray           # CSR-ordered values before symmetrisation / mapping
+    objective: np.ndarray     # per column: least-squares residual norm (nan = not computed)
+    skipped: np.ndarray       # per column: True when kept at alpha e_j (update only)
+    alpha: float              # initial scaling (build: trace formula of Alg. 2; update: Alg. 4)
+    cols: np.ndarray          # columns actually computed
+    pattern: tuple            # (n, row_ptr, col_idx)
+
+    def matrix(self) -> sp.csr_matrix:
+        n, rp, ci = self.pattern
+        m = sp.csr_matrix((self.values, ci, rp), shape=(n, n))
+        return m
+
+    @property
+    def scalar_only(self) -> bool:
+        return bool(np.all(self.skipped))
+
+
+def _csc_positions(n, row_ptr, col_idx):
+    """For the CSC ordering of the pattern: (indptr, row indices, CSR position)."""
+    nnz = len(col_idx)
+    pos = sp.csr_matrix((np.arange(1, nnz + 1, dtype=np.int64), col_idx, row_ptr),
+                        shape=(n, n)).tocsc()
+    pos.sort_indices()
+    return pos.indptr, pos.indices, pos.data - 1
+
+
+def mirror_positions(n, row_ptr, col_idx):
+    """CSR position of entry (c, r) for every CSR entry (r, c); requires a
+    structurally symmetric pattern."""
+    nnz = len(col_idx)
+    t = sp.csr_matrix((np.arange(1, nnz + 1, dtype=np.int64), col_idx, row_ptr),
+                      shape=(n, n)).T.tocsr()
+    t.sort_indices()
+    if not (np.array_equal(t.indptr, np.asarray(row_ptr)) and
+            np.array_equal(t.indices, np.asarray(col_idx))):
+        raise ValueError("pattern is not structurally symmetric")
+    return t.data - 1
+
+
+def _rows_of(row_ptr, n):
+    return np.repeat(np.arange(n), np.diff(row_ptr))
+
+
+def _column_problem(indptr, rows, vals, j):
+    """I, J and the dense block Khat(I, J) for column j (CSC arrays)."""
+    jj = rows[indptr[j]:indptr[j + 1]]
+    parts = [rows[indptr[k]:indptr[k + 1]] for k in jj]
+    ii = np.unique(np.concatenate(parts))
+    blk = np.zeros((len(ii), len(jj)))
+    for t, k in enumerate(jj):
+        r = rows[indptr[k]:indptr[k + 1]]
+        blk[np.searchsorted(ii, r), t] = vals[indptr[k]:indptr[k + 1]]
+    return ii, jj, blk
+
+
+def _scaled_values(a_val, rows, cols, s_row, s_col):
+    return a_val * s_row[rows] * s_col[cols]
+
+
+def spai_build(a: sp.csr_matrix, *, equilibrate=True, symmetrize=False, cols=None) -> Factor:
+    """SPAI of K(s) on its own structural pattern (eq. (3.1)).
+
+    ``cols`` restricts the computation to a subset of columns (sampled checks
+    at large n); the returned values are then only meaningful for those.
+    """
+    n = a.shape[0]
+    rp, ci = a.indptr, a.indices
+    rows = _rows_of(rp, n)
+    d = a.diagonal()
+    s = 1.0 / np.sqrt(d) if equilibrate else np.ones(n)
+    khat = _scaled_values(a.data, rows, ci, s, s)
+    indptr, crow, cpos = _csc_positions(n, rp, ci)
+    cval = khat[cpos]
+    hat = np.full(len(ci), np.nan)
+    obj = np.full(n, np.nan)
+    todo = np.arange(n) if cols is None else np.asarray(cols)
+    for j in todo:
+        ii, jj, blk = _column_problem(indptr, crow, cval, j)
+        rhs = (ii == j).astype(np.float64)
+        p, *_ = np.linalg.lstsq(blk, rhs, rcond=None)
+        obj[j] = np.linalg.norm(rhs - blk @ p)
+        hat[cpos[indptr[j]:indptr[j + 1]]] = p
+    if symmetrize:
+        mir = mirror_positions(n, rp, ci)
+        sym = 0.5 * (hat + hat[mir])
+    else:
+        sym = hat
+    values = _scaled_values(sym, rows, ci, s, s)
+    # Alg. 2's initial scaling: trace(K) / trace(K K^T) (reported, not used by
+    # the exact column solves).
+    alpha = float(a.diagonal().sum() / (a @ a.T).diagonal().sum())
+    return Factor(values=values, hat=hat, objective=obj, skipped=np.zeros(n, bool),
+                  alpha=alpha, cols=todo, pattern=(n, rp, ci))
+
+
+def update_alpha(k_old: sp.csr_matrix, k_new: sp.csr_matrix) -> float:
+    """Minimiser of ||K_old - alpha K_new||_F as derived in Section 3.2."""
+    num = 0.5 * ((k_old.T @ k_new).diagonal().sum() + (k_new.T @ k_old).diagonal().sum())
+    return float(num / (k_new.T @ k_new).diagonal().sum())
+
+
+def spai_update(a_old: sp.csr_matrix, a_new: sp.csr_matrix, *, tol=0.01, equilibrate=True,
+                cols=None) -> Factor:
+    """Q with K_new Q ~ K_old (Section 3.2), on the structural pattern."""
+    n = a_new.shape[0]
+    rp, ci = a_new.indptr, a_new.indices
+    if not (np.array_equal(a_old.indptr, rp) and np.array_equal(a_old.indices, ci)):
+        raise ValueError("K_old and K_new must share one pattern")
+    rows = _rows_of(rp, n)
+    d = a_new.diagonal()
+    s = 1.0 / np.sqrt(d) if equilibrate else np.ones(n)
+    new_hat = _scaled_values(a_new.data, rows, ci, s, s)
+    old_hat = _scaled_values(a_old.data, rows, ci, s, s)
+    k_new_hat = sp.csr_matrix((new_hat, ci, rp), shape=(n, n))
+    k_old_hat = sp.csr_matrix((old_hat, ci, rp), shape=(n, n))
+    alpha = update_alpha(k_old_hat, k_new_hat)
+    indptr, crow, cpos = _csc_positions(n, rp, ci)
+    cnew = new_hat[cpos]
+    cold = old_hat[cpos]
+    hat = np.full(len(ci), np.nan)
+    obj = np.full(n, np.nan)
+    skipped = np.zeros(n, bool)
+    todo = np.arange(n) if cols is None else np.asarray(cols)
+    for j in todo:
+        sl = slice(indptr[j], indptr[j + 1])
+        jj = crow[sl]
+        kold_j = cold[sl]
+        r0 = kold_j - alpha * cnew[sl]
+        if np.linalg.norm(r0) <= tol * np.linalg.norm(kold_j):
+            skipped[j] = True
+            q = alpha * (jj == j).astype(np.float64)
+            obj[j] = np.linalg.norm(r0)
+        else:
+            ii, jj2, blk = _column_problem(indptr, crow, cnew, j)
+            rhs = np.zeros(len(ii))
+            rhs[np.searchsorted(ii, jj)] = kold_j
+            q, *_ = np.linalg.lstsq(blk, rhs, rcond=None)
+            obj[j] = np.linalg.norm(rhs - blk @ q)
+        hat[cpos[sl]] = q
+    # Q = S Qhat S^{-1}
+    values = hat * s[rows] / s[ci]
+    return Factor(values=values, hat=hat, objective=obj, skipped=skipped, alpha=alpha,
+                  cols=todo, pattern=(n, rp, ci))
+
+
+def chain_apply(factors, r: np.ndarray) -> np.ndarray:
+    """z = Q_z ( ... Q_2 ( P_1 r ) ): ``factors`` lists P_1 first, then each
+    update factor in the order it was computed; only products with vectors
+    are formed."""
+    z = np.asarray(r, dtype=np.float64)
+    for fac in factors:
+        z = fac.matrix() @ z
+    return z

@@ -1,0 +1,477 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+None of these re-types an oracle formula: each checks the oracle against a
+closed form, an invariant, a special case that reduces to a textbook or
+library routine, or brute force on tiny inputs.
+"""
+import fractions
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from oracle import direct, moments, pcg, pencil, spai
+from synthetic import beam
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "cantilever.json")
+
+
+def golden():
+    with open(GOLDEN) as fh:
+        return json.load(fh)
+
+
+def small_pencil(n_el=20, surrogate=True, lu=(0.5, 2.0), seed=3):
+    return beam.make_beam(n_el, ei_loguniform=lu, surrogate=surrogate, seed=seed)
+
+
+# ----------------------------------------------------------------- generator
+
+def test_beam_pattern_shape_and_symmetry():
+    p = beam.make_beam(37)
+    n = p.n
+    assert n == 74 and p.nnz == 6 * n - 8
+    m, k = beam.pencil_dense(p)
+    assert np.array_equal(m, m.T) and np.array_equal(k, k.T)
+    for r in range(n):
+        c = p.col_idx[p.row_ptr[r]:p.row_ptr[r + 1]]
+        assert np.all(np.diff(c) > 0)
+    assert np.all(np.linalg.eigvalsh(m) > 0) and np.all(np.linalg.eigvalsh(k) > 0)
+
+
+def test_beam_eigenvalues_converge_to_euler_bernoulli():
+    g = golden()["free_vibration"]
+    p = beam.make_beam(40)
+    m, k = beam.pencil_dense(p)
+    w = sla.eigh(k, m, eigvals_only=True)[:3]
+    exact = np.array(g["beta_L"]) ** 4
+    # Hermite cubics converge as h^4; at 40 elements the first three modes agree to:
+    assert abs(w[0] / exact[0] - 1) < 1e-8
+    assert abs(w[1] / exact[1] - 1) < 1e-6
+    assert abs(w[2] / exact[2] - 1) < 1e-5
+
+
+def test_beam_heterogeneous_ei_is_seeded():
+    a = beam.make_beam(50, ei_loguniform=(0.5, 2.0), seed=7)
+    b = beam.make_beam(50, ei_loguniform=(0.5, 2.0), seed=7)
+    c = beam.make_beam(50, ei_loguniform=(0.5, 2.0), seed=8)
+    assert np.array_equal(a.k_val, b.k_val) and not np.array_equal(a.k_val, c.k_val)
+    assert a.ei.min() >= 0.5 and a.ei.max() <= 2.0
+
+
+# ------------------------------------------------------------ shifted operator
+
+def test_shifted_operator_matches_expanded_form():
+    p = small_pencil()
+    m, k = beam.pencil_dense(p)
+    for s in (0.5, 3.0, 1e3):
+        a = pencil.shifted_operator(p, s).toarray()
+        other = (s * s + p.alpha * s) * m + (1 + p.beta * s) * k
+        assert np.allclose(a, other, rtol=1e-14, atol=1e-14 * np.abs(other).max())
+
+
+def test_shifted_operator_spd_for_positive_shift():
+    p = small_pencil(surrogate=False)
+    for s in (1e-3, 1.0, 1e4):
+        a = pencil.shifted_operator(p, s).toarray()
+        assert np.all(np.linalg.eigvalsh(a) > 0)
+        np.linalg.cholesky(a)
+
+
+def test_shift_dd_is_exactly_rounded():
+    """Double-double K(s) entries equal the exact rational value to ~2^-100."""
+    p = small_pencil(n_el=4)
+    s = 37.0 / 3.0
+    hi, lo, w = direct.shifted_band_dd(p, s)
+    mb, _ = direct.lower_band(pencil.csr(p.n, p.row_ptr, p.col_idx, p.m_val), w)
+    kb, _ = direct.lower_band(pencil.csr(p.n, p.row_ptr, p.col_idx, p.k_val), w)
+    F = fractions.Fraction
+    fs, fa, fb = F(s), F(p.alpha), F(p.beta)
+    for idx in np.ndindex(mb.shape):
+        exact = fs * fs * F(mb[idx]) + fs * (fa * F(mb[idx]) + fb * F(kb[idx])) + F(kb[idx])
+        got = F(hi[idx]) + F(lo[idx])
+        if exact == 0:
+            assert got == 0
+        else:
+            assert abs((got - exact) / exact) < F(1, 2 ** 100)
+
+
+def test_frobenius_diagnostics_dense():
+    p = small_pencil()
+    d1, d2 = pencil.frobenius_diagnostics(p, 2.0, 2.5)
+    a1 = pencil.shifted_operator(p, 2.0).toarray()
+    a2 = pencil.shifted_operator(p, 2.5).toarray()
+    assert np.isclose(d1, np.linalg.norm(np.eye(p.n) - a2, "fro"), rtol=1e-13)
+    assert np.isclose(d2, np.linalg.norm(a1 - a2, "fro"), rtol=1e-13)
+
+
+# ------------------------------------------------------------ reference solve
+
+def _random_band_spd(n, w, rng):
+    a = np.zeros((n, n))
+    for k in range(1, w + 1):
+        v = rng.uniform(-1, 1, n - k)
+        a += np.diag(v, k) + np.diag(v, -k)
+    a += np.diag(np.abs(a).sum(1) + rng.uniform(0.1, 1.0, n))
+    return a
+
+
+@pytest.mark.parametrize("n,w", [(1, 0), (7, 1), (50, 3), (200, 4)])
+def test_band_solve_matches_dense(n, w):
+    rng = np.random.default_rng(n + w)
+    a = _random_band_spd(n, w, rng)
+    ab, ww = direct.lower_band(sp.csr_matrix(a), w)
+    b = rng.standard_normal((3, n))
+    x = direct.band_solve(ab, ww, b, "f64")
+    xh, xl = direct.band_solve(ab, ww, b, "dd")
+    ref = np.linalg.solve(a, b.T).T
+    assert np.allclose(x, ref, rtol=1e-12, atol=1e-12)
+    assert np.allclose(xh + xl, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_band_solve_dd_recovers_integer_solution_of_ill_conditioned_matrix():
+    """Clamped biharmonic band [1 -4 6 -4 1]: kappa ~ n^4 (1e16 here); with an
+    integer solution the right-hand side is exact in binary64, so the
+    double-double solve must return it far below binary64's error."""
+    n = 10_000
+    a = sp.diags([np.ones(n - 2), -4 * np.ones(n - 1), 6 * np.ones(n), -4 * np.ones(n - 1),
+                  np.ones(n - 2)], [-2, -1, 0, 1, 2], format="csr")
+    a = a.tolil()
+    a[0, 0] = 7  # clamped-end modification keeps it SPD
+    a = a.tocsr()
+    rng = np.random.default_rng(0)
+    x = rng.integers(-1000, 1000, n).astype(np.float64)
+    b = a @ x
+    assert np.all(np.abs(b) < 2 ** 53)
+    ab, w = direct.lower_band(a)
+    xh, xl = direct.band_solve(ab, w, b, "dd")
+    err_dd = np.abs(xh + xl - x).max() / np.abs(x).max()
+    x64 = direct.band_solve(ab, w, b, "f64")
+    err_64 = np.abs(x64 - x).max() / np.abs(x).max()
+    assert err_dd < 1e-14
+    assert err_64 > 1e3 * err_dd  # the binary64 solve is visibly worse here
+
+
+@pytest.mark.parametrize("n_el", [64, 4096])
+def test_static_cantilever_closed_form(n_el):
+    """K w = e_tip gives w(x) = x^2 (3 - x) / 6, theta = x (2 - x) / 2 at every
+    node (L = EI = 1; h = 2^-k so M, K are exact in binary64)."""
+    g = golden()["static_tip_load"]
+    p = beam.make_beam(n_el)
+    f = beam.tip_load(p.n)
+    x = direct.reference_solve(p, 0.0, f, "dd")[0]
+    xs = np.arange(1, n_el + 1) / n_el
+    assert abs(x[-2] - g["tip_deflection"]) < 1e-15
+    assert abs(x[-1] - g["tip_rotation"]) < 1e-15
+    assert np.allclose(x[0::2], xs * xs * (3 - xs) / 6, rtol=0, atol=1e-15)
+    assert np.allclose(x[1::2], xs * (2 - xs) / 2, rtol=0, atol=1e-15)
+
+
+def test_reference_solve_residual_and_precisions_agree_when_well_conditioned():
+    p = beam.make_beam(2000, ei_loguniform=(0.5, 2.0), surrogate=True, seed=1)
+    rng = np.random.default_rng(0)
+    f, _ = beam.node_loads(p.n, 3, rng)
+    for s in (1.0, 100.0):
+        xd = direct.reference_solve(p, s, f, "dd")
+        x64 = direct.reference_solve(p, s, f, "f64")
+        assert np.linalg.norm(xd - x64) / np.linalg.norm(xd) < 1e-13
+        hi, lo, w = direct.shifted_band_dd(p, s)
+        r = direct.residual_dd(hi, w, f, xd, ab_lo=lo)
+        anorm = np.abs(hi).sum(1).max() * 2
+        assert np.linalg.norm(r) <= 1e-14 * anorm * np.linalg.norm(xd)
+
+
+def test_reference_solve_rejects_indefinite():
+    a = sp.csr_matrix(np.array([[1.0, 2.0], [2.0, 1.0]]))
+    ab, w = direct.lower_band(a)
+    with pytest.raises(np.linalg.LinAlgError):
+        direct.band_solve(ab, w, np.ones(2), "f64")
+    with pytest.raises(np.linalg.LinAlgError):
+        direct.band_solve(ab, w, np.ones(2), "dd")
+
+
+# ----------------------------------------------------------------------- SPAI
+
+def _normal_eq_residual(a_hat, fac, j, rhs_col):
+    """|| Khat(:,J)^T (rhs - Khat(:,J) p_J) || for column j (dense, small n)."""
+    n = a_hat.shape[0]
+    rp, ci = fac.pattern[1], fac.pattern[2]
+    csc = sp.csr_matrix((fac.hat, ci, rp), shape=(n, n)).tocsc()
+    jj = csc.indices[csc.indptr[j]:csc.indptr[j + 1]]
+    pj = csc.data[csc.indptr[j]:csc.indptr[j + 1]]
+    sub = a_hat[:, jj]
+    res = rhs_col - sub @ pj
+    return np.linalg.norm(sub.T @ res), np.linalg.norm(sub) * np.linalg.norm(res)
+
+
+def _equilibrated(a):
+    d = a.diagonal()
+    s = 1 / np.sqrt(d)
+    return (sp.diags(s) @ a @ sp.diags(s)).toarray(), s
+
+
+@pytest.mark.parametrize("sur,s", [(True, 1.0), (True, 1e3), (False, 100.0)])
+def test_spai_columns_are_least_squares_optimal(sur, s):
+    p = small_pencil(surrogate=sur)
+    a = pencil.shifted_operator(p, s)
+    fac = spai.spai_build(a)
+    ah, _ = _equilibrated(a)
+    for j in range(p.n):
+        g, scale = _normal_eq_residual(ah, fac, j, np.eye(p.n)[:, j])
+        assert g <= 1e-12 * max(scale, 1e-300)
+
+
+def test_spai_matches_full_column_lstsq():
+    """Restricting column j's problem to the rows I loses nothing: it equals
+    the least-squares fit over all n rows (rows outside I are zero)."""
+    p = small_pencil(n_el=12)
+    a = pencil.shifted_operator(p, 7.0)
+    fac = spai.spai_build(a)
+    ah, _ = _equilibrated(a)
+    csc = sp.csr_matrix((fac.hat, a.indices, a.indptr), shape=a.shape).tocsc()
+    for j in range(p.n):
+        jj = csc.indices[csc.indptr[j]:csc.indptr[j + 1]]
+        ref, *_ = np.linalg.lstsq(ah[:, jj], np.eye(p.n)[:, j], rcond=None)
+        assert np.allclose(csc.data[csc.indptr[j]:csc.indptr[j + 1]], ref, rtol=1e-10, atol=1e-12)
+        assert np.isclose(fac.objective[j], np.linalg.norm(np.eye(p.n)[:, j] - ah[:, jj] @ ref),
+                          rtol=1e-10, atol=1e-14)
+
+
+def test_spai_column_split_identity():
+    """eq. (3.1): ||I - Khat Phat||_F^2 = sum_j ||e_j - Khat p_j||^2."""
+    p = small_pencil(n_el=15)
+    a = pencil.shifted_operator(p, 3.0)
+    fac = spai.spai_build(a)
+    ah, _ = _equilibrated(a)
+    phat = sp.csr_matrix((fac.hat, a.indices, a.indptr), shape=a.shape).toarray()
+    lhs = np.linalg.norm(np.eye(p.n) - ah @ phat, "fro") ** 2
+    assert np.isclose(lhs, np.sum(fac.objective ** 2), rtol=1e-12)
+
+
+def test_spai_full_pattern_is_exact_inverse():
+    rng = np.random.default_rng(5)
+    a = _random_band_spd(9, 8, rng)  # dense SPD
+    fac = spai.spai_build(sp.csr_matrix(a), equilibrate=True)
+    assert np.allclose(fac.matrix().toarray(), np.linalg.inv(a), rtol=1e-10, atol=1e-12)
+    fac2 = spai.spai_build(sp.csr_matrix(a), equilibrate=False)
+    assert np.allclose(fac2.matrix().toarray(), np.linalg.inv(a), rtol=1e-10, atol=1e-12)
+    assert np.all(fac.objective < 1e-12)
+
+
+def test_spai_block_diagonal_pattern_gives_block_inverse():
+    rng = np.random.default_rng(6)
+    blocks = [_random_band_spd(k, k - 1, rng) for k in (1, 2, 3, 4)]
+    a = sla.block_diag(*blocks)
+    fac = spai.spai_build(sp.csr_matrix(a))
+    assert np.allclose(fac.matrix().toarray(), np.linalg.inv(a), rtol=1e-10, atol=1e-12)
+
+
+def test_spai_one_by_one():
+    fac = spai.spai_build(sp.csr_matrix(np.array([[4.0]])), equilibrate=False)
+    assert fac.values[0] == 0.25
+    assert fac.alpha == 0.25
+
+
+def test_spai_initial_alpha_is_frobenius_minimiser():
+    """Alg. 2's alpha = trace(K)/trace(K K^T) minimises ||I - alpha K||_F
+    (checked by brute force over alpha)."""
+    p = small_pencil(n_el=10)
+    a = pencil.shifted_operator(p, 2.0)
+    fac = spai.spai_build(a)
+    ad = a.toarray()
+    grid = fac.alpha * np.linspace(0.9, 1.1, 2001)
+    vals = [np.linalg.norm(np.eye(p.n) - g * ad, "fro") for g in grid]
+    assert abs(grid[int(np.argmin(vals))] / fac.alpha - 1) < 2e-4
+
+
+def test_spai_symmetrize_is_symmetric():
+    p = small_pencil()
+    a = pencil.shifted_operator(p, 10.0)
+    pm = spai.spai_build(a, symmetrize=True).matrix().toarray()
+    assert np.allclose(pm, pm.T, rtol=0, atol=1e-14 * np.abs(pm).max())
+
+
+def test_spai_sampled_columns_match_full():
+    p = small_pencil(n_el=30)
+    a = pencil.shifted_operator(p, 5.0)
+    full = spai.spai_build(a)
+    cols = np.array([0, 1, 17, 58, 59])
+    part = spai.spai_build(a, cols=cols)
+    assert np.allclose(part.objective[cols], full.objective[cols], rtol=0, atol=0)
+
+
+# --------------------------------------------------------------- SPAI update
+
+def test_update_same_shift_is_identity():
+    p = small_pencil()
+    a = pencil.shifted_operator(p, 4.0)
+    q = spai.spai_update(a, a, tol=0.01)
+    assert q.alpha == pytest.approx(1.0, abs=1e-15)
+    assert q.scalar_only
+    assert np.allclose(q.matrix().toarray(), np.eye(p.n), rtol=0, atol=1e-15)
+
+
+def test_update_alpha_is_frobenius_minimiser():
+    p = small_pencil(n_el=10)
+    a_old = pencil.shifted_operator(p, 2.0)
+    a_new = pencil.shifted_operator(p, 3.0)
+    al = spai.update_alpha(a_old, a_new)
+    o, nw = a_old.toarray(), a_new.toarray()
+    grid = al * np.linspace(0.9, 1.1, 2001)
+    vals = [np.linalg.norm(o - g * nw, "fro") for g in grid]
+    assert abs(grid[int(np.argmin(vals))] / al - 1) < 2e-4
+
+
+def test_update_columns_optimal_and_no_worse_than_start():
+    p = small_pencil()
+    a_old = pencil.shifted_operator(p, 2.0)
+    a_new = pencil.shifted_operator(p, 6.0)
+    q = spai.spai_update(a_old, a_new, tol=0.01)
+    assert not q.scalar_only
+    s = 1 / np.sqrt(a_new.diagonal())
+    nh = (sp.diags(s) @ a_new @ sp.diags(s)).toarray()
+    oh = (sp.diags(s) @ a_old @ sp.diags(s)).toarray()
+    for j in range(p.n):
+        start = np.linalg.norm(oh[:, j] - q.alpha * nh[:, j])
+        assert q.objective[j] <= start * (1 + 1e-12)
+        if not q.skipped[j]:
+            g, scale = _normal_eq_residual(nh, q, j, oh[:, j])
+            assert g <= 1e-12 * scale
+    # K_new Q ~ K_old, with the column objectives splitting the Frobenius norm
+    qh = sp.csr_matrix((q.hat, a_new.indices, a_new.indptr), shape=a_new.shape).toarray()
+    assert np.isclose(np.linalg.norm(oh - nh @ qh, "fro") ** 2, np.sum(q.objective ** 2), rtol=1e-12)
+    qm = q.matrix().toarray()
+    assert np.allclose(a_new.toarray() @ qm, np.diag(1 / s) @ nh @ qh @ np.diag(1 / s), rtol=1e-12,
+                       atol=1e-12 * np.abs(a_new.toarray() @ qm).max())
+
+
+def test_update_tolerance_limits():
+    p = small_pencil()
+    a_old = pencil.shifted_operator(p, 2.0)
+    a_new = pencil.shifted_operator(p, 2.2)
+    assert spai.spai_update(a_old, a_new, tol=np.inf).scalar_only
+    assert not np.any(spai.spai_update(a_old, a_new, tol=0.0).skipped)
+
+
+def test_chain_apply_equals_explicit_product():
+    p = small_pencil()
+    a1 = pencil.shifted_operator(p, 2.0)
+    a2 = pencil.shifted_operator(p, 3.0)
+    a3 = pencil.shifted_operator(p, 5.0)
+    p1 = spai.spai_build(a1)
+    q2 = spai.spai_update(a1, a2, tol=0.0)
+    q3 = spai.spai_update(a2, a3, tol=0.0)
+    r = np.random.default_rng(0).standard_normal(p.n)
+    explicit = q3.matrix().toarray() @ q2.matrix().toarray() @ p1.matrix().toarray() @ r
+    assert np.allclose(spai.chain_apply([p1, q2, q3], r), explicit, rtol=1e-13, atol=1e-13)
+
+
+# ------------------------------------------------------------------------ PCG
+
+def _spd(n, rng):
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    return q @ np.diag(rng.uniform(0.5, 4.0, n)) @ q.T
+
+
+def test_pcg_matches_direct_solve():
+    p = beam.make_beam(300, ei_loguniform=(0.5, 2.0), surrogate=True, seed=2)
+    f = beam.tip_load(p.n)[0]
+    for s in (1.0, 30.0, 1e4):
+        a = pencil.shifted_operator(p, s)
+        pm = spai.spai_build(a).matrix()
+        res = pcg.pcg(lambda v: a @ v, lambda v: pm @ v, f, tol=1e-12, max_iter=2000)
+        ref = direct.reference_solve(p, s, f[None], "dd")[0]
+        assert res.status == pcg.CONVERGED
+        assert np.linalg.norm(res.x - ref) / np.linalg.norm(ref) < 1e-9
+
+
+def test_pcg_finite_termination_and_galerkin_orthogonality():
+    rng = np.random.default_rng(1)
+    n = 16
+    a = _spd(n, rng)
+    c = _spd(n, rng)  # symmetric positive definite preconditioner
+    f = rng.standard_normal(n)
+    res = pcg.pcg(lambda v: a @ v, lambda v: c @ v, f, tol=1e-13, max_iter=200, keep=True)
+    assert res.status == pcg.CONVERGED and res.iters <= n + 3
+    # residuals are orthogonal to earlier search directions (Ritz-Galerkin)
+    for k in range(1, min(len(res.residuals), 8)):
+        for i in range(k):
+            pi, rk = res.directions[i], res.residuals[k]
+            assert abs(pi @ rk) <= 1e-9 * np.linalg.norm(pi) * np.linalg.norm(rk)
+    assert np.allclose(res.x, np.linalg.solve(a, f), rtol=1e-10)
+
+
+def test_pcg_beta_forms_agree_for_symmetric_preconditioner():
+    rng = np.random.default_rng(2)
+    n = 40
+    a = _spd(n, rng)
+    c = _spd(n, rng)
+    f = rng.standard_normal(n)
+    hs = [pcg.pcg(lambda v: a @ v, lambda v: c @ v, f, tol=1e-30, max_iter=6, beta=b).history
+          for b in ("flexible", "pr", "fr")]
+    assert np.allclose(hs[0], hs[1], rtol=1e-9) and np.allclose(hs[0], hs[2], rtol=1e-9)
+
+
+def test_pcg_statuses():
+    rng = np.random.default_rng(3)
+    n = 10
+    a = _spd(n, rng)
+    f = rng.standard_normal(n)
+    eye = lambda v: v  # noqa: E731
+    assert pcg.pcg(lambda v: a @ v, eye, f, tol=1e-14, max_iter=1).status == pcg.MAXIT
+    bad = f.copy()
+    bad[3] = np.nan
+    assert pcg.pcg(lambda v: a @ v, eye, bad).status == pcg.NONFINITE
+    assert pcg.pcg(lambda v: a @ v, lambda v: 0 * v, f).status == pcg.BREAKDOWN
+    assert pcg.pcg(lambda v: -(a @ v), eye, f).status == pcg.BREAKDOWN
+    z = pcg.pcg(lambda v: a @ v, eye, np.zeros(n))
+    assert z.status == pcg.CONVERGED and z.iters == 0 and not np.any(z.x)
+
+
+def test_pcg_warm_start_resumes():
+    rng = np.random.default_rng(4)
+    n = 30
+    a = _spd(n, rng)
+    f = rng.standard_normal(n)
+    first = pcg.pcg(lambda v: a @ v, lambda v: v, f, tol=1e-3, max_iter=100)
+    second = pcg.pcg(lambda v: a @ v, lambda v: v, f, tol=1e-12, max_iter=100, x0=first.x)
+    assert second.status == pcg.CONVERGED
+    assert np.allclose(second.x, np.linalg.solve(a, f), rtol=1e-9)
+
+
+# -------------------------------------------------------------- moment matching
+
+def test_galerkin_projection_interpolates_at_expansion_points():
+    """V spanning X(s_i) and dX/ds(s_i) makes the reduced transfer function and
+    its derivative match the full one there (Section 2 moment matching);
+    H is evaluated by an independent dense solve."""
+    p = beam.make_beam(60, ei_loguniform=(0.5, 2.0), surrogate=True, seed=4)
+    m, k = beam.pencil_dense(p)
+    f = beam.tip_load(p.n).T
+    cp = f.T
+    shifts = [1.5, 40.0, 900.0]
+    xs = []
+    for s in shifts:
+        x0 = direct.reference_solve(p, s, f.T, "dd").T
+        d = p.alpha * m + p.beta * k
+        rhs = -((2 * s) * m + d) @ x0  # first moment, eq. (2.2) second line
+        x1 = direct.reference_solve(p, s, rhs.T, "dd").T
+        xs += [x0, x1]
+    v = moments.orth_basis(xs)
+    red = moments.project(m, k, p.alpha, p.beta, f, cp, v)
+
+    def h_full(s):
+        return cp @ np.linalg.solve(s * s * m + s * (p.alpha * m + p.beta * k) + k, f)
+
+    for s in shifts:
+        hs = h_full(s)
+        assert np.allclose(moments.reduced_transfer(*red, s), hs, rtol=1e-9)
+        e = 1e-4 * s
+        dfull = (h_full(s + e) - h_full(s - e)) / (2 * e)
+        dred = (moments.reduced_transfer(*red, s + e) - moments.reduced_transfer(*red, s - e)) / (2 * e)
+        assert np.allclose(dred, dfull, rtol=1e-5)
+    # away from the expansion points the reduced model is only approximate
+    assert not np.allclose(moments.reduced_transfer(*red, 7.0), h_full(7.0), rtol=1e-9)
