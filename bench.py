@@ -1,0 +1,290 @@
+#!/usr/bin/env python3
+"""Benchmark of the shifted SPAI-preconditioned CG hot path on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input, inputs
+already resident in HBM:
+  pencil setup (sliced-ELL copy, float32 mirrors, transpose map)
+  -> SPAI build at every expansion point
+  -> batched mixed-precision PCG for all (shift, column) systems
+  -> SPAI update of every preconditioner to the next outer iteration's
+     (drifted) expansion points
+  -> batched mixed-precision PCG again, with the update chains.
+``value`` = systems solved to 1e-8 relative error (checked against the
+oracle's double-double reference) per second of step time.  Beside it: the
+plain float64 one-system-at-a-time GPU PCG on the same systems, SPAI
+build/update milliseconds, the roofline of the dominant kernel and the CPU
+oracle's rate.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4s]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from synthetic import beam  # noqa: E402
+
+METRIC = "PCG solves/s @1e-8 rel err, batched-mixed vs plain FP64; SPAI build/update ms"
+HBM_PEAK_GBS = 8000.0
+ERR_TOL = 1e-8
+
+# Workloads (seeded, synthetic).  "s" = the surrogate with every EI scaled by
+# h^4 (same n, pattern, loads, shifts, seeds and heterogeneity).
+WORKLOADS = {
+    "c4s": dict(base="c3", surrogate=True, desc="Hermite cantilever n=1,000,000 (EI=1 scaled by h^4), "
+                "m=4 seeded unit loads, 16 shifts logspace(0,4,16) then 16 drifted (x(1+1e-3 U(-1,1)))"),
+    "c5s": dict(base="c5", surrogate=True, desc="Hermite cantilever n=10,000,000 (EI log-uniform "
+                "[0.1,10], scaled by h^4), m=4, 32 shifts logspace(0,5,32) then 32 drifted"),
+    "c2s": dict(base="c2", surrogate=True, desc="Hermite cantilever n=100,000 (EI log-uniform "
+                "[0.5,2], scaled by h^4), tip load, 8 shifts logspace(0,4,8) then 8 drifted"),
+    "c1": dict(base="c1", surrogate=False, desc="Hermite cantilever n=1000, EI=1 (literal), tip "
+               "load, s=100"),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def build_inputs(name, seed=0):
+    w = WORKLOADS[name]
+    pen, f, shifts, rng = beam.make_workload(w["base"], surrogate=w["surrogate"], seed=seed)
+    drifted = beam.drift_shifts(shifts, 1e-3, rng)
+    return pen, f, np.asarray(shifts, float), np.asarray(drifted, float)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c4s", choices=sorted(WORKLOADS))
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain float64 comparator")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="timed steps only (for profilers)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_1606_01216_amd import airga
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log(f"[bench] building inputs {args.workload}")
+    pen, f, shifts, drifted = build_inputs(args.workload)
+    n, m, S = pen.n, f.shape[0], len(shifts)
+    B = S * m
+
+    def t(a, dt):
+        return torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)
+
+    rp, ci = t(pen.row_ptr, torch.int32), t(pen.col_idx, torch.int32)
+    mv, kv = t(pen.m_val, torch.float64), t(pen.k_val, torch.float64)
+    F = t(f, torch.float64)
+    X1 = torch.zeros((S, m, n), dtype=torch.float64, device=dev)
+    X2 = torch.zeros((S, m, n), dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+    ctx = airga.Context(0, stream)
+    solve_kw = dict(tol=args.tol, mode=airga.MODE_MIXED, inner_tol=1e-4, max_sweeps=12,
+                    max_iter=20000, poll_every=8)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def step(record=None, profile=False):
+        """One pass of the hot path; optional per-phase events on ctx.stream."""
+        marks = [ev() for _ in range(6)] if record is not None else None
+
+        def mark(i):
+            if marks is not None:
+                marks[i].record(stream)
+
+        with torch.cuda.stream(stream):
+            mark(0)
+            ctx.set_pencil(rp, ci, mv, kv, pen.alpha, pen.beta)
+            mark(1)
+            precs = [ctx.spai_build(s) for s in shifts]
+            mark(2)
+            _, st1 = ctx.pcg_solve(shifts, precs, F, X1, profile=profile, **solve_kw)
+            mark(3)
+            upd = [ctx.spai_update(p, s) for p, s in zip(precs, drifted)]
+            mark(4)
+            _, st2 = ctx.pcg_solve(drifted, upd, F, X2, profile=profile, **solve_kw)
+            mark(5)
+        if record is not None:
+            torch.cuda.synchronize()
+            record.append([marks[i].elapsed_time(marks[i + 1]) for i in range(5)])
+        return precs, upd, st1, st2
+
+    log(f"[bench] n={n} m={m} shifts={S} systems/step={2 * B}; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        precs, upd, st1, st2 = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    log(f"[bench] {ms_per_step:.2f} ms/step")
+    iters = [e["iters"] for e in st1 + st2]
+    conv = sum(e["status"] == airga.SYS_CONVERGED for e in st1 + st2)
+    if args.quick:
+        print(json.dumps({"metric": METRIC, "ms_per_step": ms_per_step, "converged": conv,
+                          "systems": 2 * B}))
+        return
+
+    # phase breakdown (one extra step with events on the context stream)
+    phases = []
+    step(record=phases)
+    ph = phases[0]
+    # profiled step: per-launch kernel timing with HIP events on ctx.stream
+    # (the handles of this last step stay valid for the comparator below: every
+    # step re-sets the pencil, which invalidates earlier handles)
+    precs, upd, _, _ = step(profile=True)
+    kt2 = ctx.kernel_times()
+    kw2 = ctx.kernel_work()
+    info = ctx.pencil_info()
+
+    # plain float64, one system at a time, same systems and preconditioners
+    plain = None
+    Xp1 = Xp2 = None
+    if not args.no_plain:
+        log("[bench] plain float64 one-system-at-a-time comparator")
+        Xp1 = torch.zeros_like(X1)
+        Xp2 = torch.zeros_like(X2)
+        # each system solves into a scratch (1, 1, n) block, copied into place
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        plain_stats = []
+        with torch.cuda.stream(stream):
+            for (ss, pp, XX) in ((shifts, precs, Xp1), (drifted, upd, Xp2)):
+                for k in range(S):
+                    for c in range(m):
+                        out = torch.empty((1, 1, n), dtype=torch.float64, device=dev)
+                        _, st = ctx.pcg_solve([ss[k]], [pp[k]], F[c:c + 1], out, tol=args.tol,
+                                              mode=airga.MODE_FP64, max_iter=20000, poll_every=8)
+                        XX[k, c].copy_(out[0, 0])
+                        plain_stats.append(st[0])
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        plain = dict(seconds=tb - ta, stats=plain_stats)
+
+    # ---- CPU baseline leg: the oracle's reference solves (double-double banded
+    # Cholesky) for every system of the step, timed on this host, and the
+    # accuracy of the GPU results against them.
+    errs_mixed, errs_plain, cpu = [], [], None
+    if not args.no_cpu_baseline:
+        from oracle import direct, spai as ospai, pencil as opencil
+        log("[bench] oracle reference solves (CPU)")
+        Xh1, Xh2 = X1.cpu().numpy(), X2.cpu().numpy()
+        Xq1 = Xp1.cpu().numpy() if Xp1 is not None else None
+        Xq2 = Xp2.cpu().numpy() if Xp2 is not None else None
+        tc0 = time.perf_counter()
+        refs = []
+        for ss in (shifts, drifted):
+            refs.append(np.stack([direct.reference_solve(pen, s, f, "dd") for s in ss]))
+        tc1 = time.perf_counter()
+        for Xg, Xq, R in ((Xh1, Xq1, refs[0]), (Xh2, Xq2, refs[1])):
+            for k in range(S):
+                for c in range(m):
+                    nr = np.linalg.norm(R[k, c])
+                    errs_mixed.append(float(np.linalg.norm(Xg[k, c] - R[k, c]) / nr))
+                    if Xq is not None:
+                        errs_plain.append(float(np.linalg.norm(Xq[k, c] - R[k, c]) / nr))
+        # oracle SPAI on a column sample of the first shift, scaled to n columns
+        rng = np.random.default_rng(0)
+        cols = np.sort(rng.choice(n, size=min(n, 4000), replace=False))
+        a0 = opencil.shifted_operator(pen, shifts[0])
+        ts0 = time.perf_counter()
+        ospai.spai_build(a0, cols=cols)
+        ts1 = time.perf_counter()
+        cpu = dict(seconds=tc1 - tc0, spai_sample_s=ts1 - ts0, spai_cols=len(cols))
+
+    n_ok = sum(e <= ERR_TOL for e in errs_mixed) if errs_mixed else conv
+    value = n_ok / (ms_per_step / 1e3)
+
+    # ---- roofline of the dominant row kernel (algorithmic bytes / duration)
+    stored = info.nnz_stored
+    w = 4  # float32 inner solves
+    def kbytes(name, launches, sysp, shp):
+        if name == "dir_spmv":
+            return launches * stored * (4 + 2 * w) + sysp * 4 * w * n
+        if name == "update_prec":
+            return launches * stored * 4 + shp * stored * w + sysp * 7 * w * n
+        if name == "init_prec":
+            return launches * stored * 4 + shp * stored * w + sysp * 2 * w * n
+        return None
+    rows = []
+    for name in ("dir_spmv", "update_prec", "init_prec", "chain", "ir_residual", "ir_update", "reduce"):
+        la, ms = kt2.get(name, (0, 0.0))
+        sysp, shp = kw2.get(name, (0, 0))
+        if la:
+            b = kbytes(name, la, sysp, shp)
+            rows.append(dict(kernel=name, launches=la, total_ms=ms, avg_us=1e3 * ms / la,
+                             gbs=(b / (ms * 1e-3) / 1e9) if b else None, bytes=b))
+    dom = max((r for r in rows if r["bytes"]), key=lambda r: r["total_ms"])
+    roofline = {"bound": "hbm", "kernel": dom["kernel"], "achieved": round(dom["gbs"], 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4),
+                "traffic": None, "avg_launch_us": round(dom["avg_us"], 2),
+                "bytes_per_launch": int(dom["bytes"] / dom["launches"])}
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]['desc']}", "n": n,
+                   "systems_per_step": 2 * B, "tol_relres": args.tol, "err_tol": ERR_TOL,
+                   "precision": "float32 inner PCG, float64 refinement"},
+        "solved_to_1e-8": n_ok, "max_rel_err": max(errs_mixed) if errs_mixed else None,
+        "iters_median": statistics.median(iters), "iters_max": max(iters),
+        "phases_ms": {"pencil_setup": round(ph[0], 3), "spai_build_total": round(ph[1], 3),
+                      "pcg_mixed_1": round(ph[2], 3), "spai_update_total": round(ph[3], 3),
+                      "pcg_mixed_2": round(ph[4], 3)},
+        "spai_build_ms_per_shift": round(ph[1] / S, 4),
+        "spai_update_ms_per_shift": round(ph[3] / S, 4),
+        "update_skipped_frac": round(float(np.mean([u.info().skipped_cols for u in upd])) / n, 4),
+        "batched_mixed_pcg_solves_per_s": round(2 * B / ((ph[2] + ph[4]) / 1e3), 2),
+        "kernels": rows,
+        "roofline": roofline,
+    }
+    if plain is not None:
+        pst = plain["stats"]
+        ok_p = sum(e <= ERR_TOL for e in errs_plain) if errs_plain else sum(
+            s["status"] == airga.SYS_CONVERGED for s in pst)
+        out["plain_fp64"] = {"pcg_solves_per_s": round(ok_p / plain["seconds"], 2),
+                             "seconds": round(plain["seconds"], 4), "solved_to_1e-8": ok_p,
+                             "max_rel_err": max(errs_plain) if errs_plain else None,
+                             "iters_median": statistics.median(s["iters"] for s in pst)}
+        out["speedup_pcg_vs_plain_fp64"] = round(out["batched_mixed_pcg_solves_per_s"] /
+                                                 max(out["plain_fp64"]["pcg_solves_per_s"], 1e-30), 2)
+    if cpu is not None:
+        out["cpu_baseline"] = {
+            "value": round(2 * B / cpu["seconds"], 3), "unit": "solves/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"all {2 * B} systems of one step: double-double banded Cholesky reference "
+                      f"solves ({cpu['seconds']:.1f} s); oracle SPAI on {cpu['spai_cols']} sampled "
+                      f"columns took {cpu['spai_sample_s']:.2f} s "
+                      f"(~{cpu['spai_sample_s'] * n / cpu['spai_cols']:.0f} s per full build)"}
+    print(json.dumps(out))
+    for p in precs + upd:
+        p.release()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

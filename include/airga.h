@@ -1,0 +1,270 @@
+/*
+ * airga.h -- C ABI of libairga, the MI355X (gfx950) library for the shifted
+ * sparse solves of AIRGA model reduction with SPAI-preconditioned CG, after
+ * Singh, Ahuja and Fassbender, "Preconditioned Iterative Solves in Model
+ * Reduction of Second Order Linear Dynamical Systems" (arXiv 1606.01216).
+ *
+ * The problem (Section 1, eq. (1.1); Section 2): a second-order system
+ * M x'' + D x' + K x = F u with proportional damping D = alpha M + beta K.
+ * Every linear system of the method has the coefficient matrix
+ *     K(s) = s^2 M + s D + K = (s^2 + alpha s) M + (1 + beta s) K
+ * at a real expansion point s, and right-hand sides F (n x m).  The library
+ * builds a sparse approximate inverse of K(s) (Section 3.1, eq. (3.1)),
+ * updates it cheaply to a new expansion point (Section 3.2), and solves
+ * K(s_k) X_k = F for many shifts at once with preconditioned CG.
+ *
+ * Conventions shared by every entry point
+ *   - Memory: every array argument named as "device" is GPU memory on the
+ *     context's device (for example a torch tensor's data pointer), owned by
+ *     the caller; the library never frees or keeps it beyond the call except
+ *     where stated.  Arguments named "host" are CPU memory.
+ *   - Streams: all GPU work of a context is ordered on one HIP stream (the
+ *     one given to airga_create, or a stream the context owns).  Calls that
+ *     return results to host memory synchronise that stream first.
+ *   - Errors: a negative airga_status; airga_last_error() then returns a
+ *     message for the calling thread.  On error no output is written unless
+ *     stated.  A context is not thread-safe; distinct contexts are.
+ *   - Indices are 0-based int32; n * (max row length) must stay below 2^31.
+ */
+#ifndef AIRGA_H
+#define AIRGA_H
+
+#include <stdint.h>
+
+/* Symbols of the C ABI are the only ones the library exports. */
+#define AIRGA_API __attribute__((visibility("default")))
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct airga_ctx_s* airga_ctx;
+typedef struct airga_prec_s* airga_prec;
+
+typedef enum {
+  AIRGA_OK = 0,
+  AIRGA_EINVAL = -1,      /* bad argument: null pointer, size, pattern, shift    */
+  AIRGA_ENOMEM = -2,      /* device or host allocation failed                    */
+  AIRGA_EHIP = -3,        /* a HIP runtime call failed                           */
+  AIRGA_ENOTSPD = -4,     /* K(s) has a non-positive diagonal entry              */
+  AIRGA_ESTATE = -5,      /* call out of order (e.g. no pencil set yet)          */
+  AIRGA_EUNSUPPORTED = -6 /* valid input outside the library's supported range   */
+} airga_status;
+
+/* Per-system outcome of a solve (airga_sys_stats.status). */
+enum {
+  AIRGA_SYS_CONVERGED = 0, /* ||F - K(s) X|| <= tol ||F|| (see airga_pcg_opts)    */
+  AIRGA_SYS_MAXIT = 1,     /* iteration cap reached                               */
+  AIRGA_SYS_BREAKDOWN = 2, /* (p, K(s) p) <= 0: K(s) not positive definite or p=0 */
+  AIRGA_SYS_NONFINITE = 3  /* a NaN or infinity appeared                          */
+};
+
+enum { AIRGA_MODE_FP64 = 0, AIRGA_MODE_MIXED = 1 };
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`.  `stream` is a hipStream_t to
+ * order all work on, or NULL for a context-owned stream (default priority).
+ * Errors: EINVAL (null out, bad device), EHIP. */
+AIRGA_API airga_status airga_create(airga_ctx* out, int device, void* stream);
+
+/* Release the context, its pencil and workspaces.  Preconditioner handles
+ * made by the context must be released before. NULL is ignored. */
+AIRGA_API void airga_destroy(airga_ctx ctx);
+
+/* Message for the last non-OK status returned on the calling thread. */
+AIRGA_API const char* airga_last_error(void);
+
+/* Library version as "major.minor.patch". */
+AIRGA_API const char* airga_version(void);
+
+/* ------------------------------------------------------------------ pencil */
+
+/* Set the pencil (M, K) and the damping coefficients (eq. (1.1):
+ * D = alpha M + beta K; D itself is never formed).
+ * M and K share ONE structural CSR pattern: row_ptr (device, n+1),
+ * col_idx (device, nnz, sorted and unique within each row, symmetric
+ * pattern, diagonal present; explicit zeros allowed and kept), values
+ * m_val, k_val (device, nnz, float64).  The library copies what it needs
+ * (a sliced-ELL copy with 64-row slices, float32 mirrors, the transpose map)
+ * and keeps no reference to the inputs.  Replaces any previous pencil;
+ * preconditioners built on an earlier pencil become invalid (ESTATE).
+ * Errors: EINVAL (n <= 0, nnz <= 0, null pointers, unsorted or out-of-range
+ * columns, missing diagonal, asymmetric pattern, alpha or beta < 0),
+ * EUNSUPPORTED (a row longer than 16 entries), ENOMEM, EHIP. */
+AIRGA_API airga_status airga_set_pencil(airga_ctx ctx, int32_t n, int64_t nnz, const int32_t* row_ptr,
+                              const int32_t* col_idx, const double* m_val, const double* k_val,
+                              double alpha, double beta);
+
+typedef struct {
+  int32_t n;
+  int32_t max_row_len;  /* longest row of the pattern                          */
+  int32_t bandwidth;    /* max |i - j| over the pattern                         */
+  int32_t slice_rows;   /* rows per slice of the sliced-ELL layout (64)         */
+  int64_t nnz;          /* entries of the CSR pattern                           */
+  int64_t nnz_stored;   /* entries of the sliced-ELL copy (with padding)        */
+  double gram_mm, gram_mk, gram_kk; /* <M,M>_F, <M,K>_F, <K,K>_F                */
+  double trace_m, trace_k;
+} airga_pencil_info;
+
+/* Describe the current pencil (host struct).  Errors: EINVAL, ESTATE. */
+AIRGA_API airga_status airga_get_pencil_info(airga_ctx ctx, airga_pencil_info* out);
+
+/* a_val (device, nnz, CSR order of the pattern) = entries of
+ * K(s) = (s^2 + alpha s) M + (1 + beta s) K (Section 2; the matrix of
+ * line 3 of the SPAI algorithm for AIRGA), computed as one fused
+ * multiply-add per entry in float64.  Asynchronous.
+ * Errors: EINVAL (null a_val, non-finite s), ESTATE (no pencil). */
+AIRGA_API airga_status airga_assemble_shift(airga_ctx ctx, double s, double* a_val);
+
+/* y = K(s) x for `count` vectors x (device, n each, leading dimension ldx)
+ * into y (device, ldy), float64.  Asynchronous.  Errors: EINVAL, ESTATE. */
+AIRGA_API airga_status airga_apply_shift(airga_ctx ctx, double s, int32_t count, const double* x,
+                               int64_t ldx, double* y, int64_t ldy);
+
+/* The two quantities the paper tabulates for every expansion point
+ * (Tables 6 and 7) and the two scalings of its SPAI algorithms, from the
+ * Gram scalars of the pencil (host output out[4]):
+ *   out[0] = ||I - K(s_new)||_F
+ *   out[1] = ||K(s_old) - K(s_new)||_F
+ *   out[2] = trace(K(s_new)) / trace(K(s_new) K(s_new)^T)       (SPAI start)
+ *   out[3] = <K(s_old), K(s_new)>_F / ||K(s_new)||_F^2          (update start)
+ * Errors: EINVAL, ESTATE. */
+AIRGA_API airga_status airga_shift_diagnostics(airga_ctx ctx, double s_old, double s_new, double* out);
+
+/* --------------------------------------------------------- preconditioners */
+
+typedef struct {
+  double tol;          /* update only: a column keeps q_j = alpha e_j when
+                          ||k_old_j - alpha k_new_j|| <= tol ||k_old_j||
+                          (the test that opens the inner loop of the update
+                          algorithm; the paper uses 0.01).  Default 0.01.      */
+  int32_t equilibrate; /* 1: pose the column problems for S K(s) S with
+                          S = diag(K(s))^{-1/2} and map back (default 1)      */
+  int32_t symmetrize;  /* build only, 1: replace Phat by (Phat + Phat^T)/2
+                          before mapping back (default 1)                      */
+} airga_spai_opts;
+
+AIRGA_API void airga_spai_opts_default(airga_spai_opts* opts);
+
+/* SPAI of K(s) on the structural pattern of K(s) (eq. (3.1)): for every
+ * column j, p_j = argmin || e_j - K(s) p ||_2 over vectors with the
+ * pattern of column j, solved exactly per column (Givens QR in float64,
+ * one column per GPU lane).  `opts` may be NULL (defaults).  The handle
+ * owns the factor (float64 and float32 copies) and must be released with
+ * airga_prec_release.  Asynchronous.
+ * Errors: EINVAL (s <= 0 or non-finite, null out), ESTATE (no pencil),
+ * ENOTSPD (a diagonal entry of K(s) <= 0, only detected when equilibrating),
+ * ENOMEM, EHIP. */
+AIRGA_API airga_status airga_spai_build(airga_ctx ctx, double s, const airga_spai_opts* opts,
+                              airga_prec* out);
+
+/* SPAI update (Section 3.2): Q with K(s_new) Q ~ K(s_old) column by column,
+ * from Q = alpha I with alpha = <K_old, K_new>_F / ||K_new||_F^2; columns
+ * failing the skip test are solved exactly on the pattern.  The result is
+ * the chain Q * (old chain): a new handle that references `old` (reference
+ * counted; `old` stays valid for the caller).  A factor whose columns all
+ * skip is the scalar alpha and is not applied (CG is invariant to a nonzero
+ * scaling of the preconditioner).  Errors: as airga_spai_build, plus EINVAL
+ * for a null or foreign `old`. */
+AIRGA_API airga_status airga_spai_update(airga_ctx ctx, airga_prec old, double s_new,
+                               const airga_spai_opts* opts, airga_prec* out);
+
+typedef struct {
+  double shift;         /* expansion point of the newest factor                 */
+  double alpha;         /* starting scaling of the newest factor                */
+  int32_t chain_len;    /* factors applied per application (scalars excluded)   */
+  int32_t scalar_only;  /* 1 when the newest factor collapsed to alpha I        */
+  int64_t skipped_cols; /* columns of the newest factor kept at alpha e_j       */
+} airga_prec_info;
+
+/* Describe a preconditioner (synchronises the context stream). */
+AIRGA_API airga_status airga_get_prec_info(airga_prec prec, airga_prec_info* out);
+
+/* Export the newest factor: values (device, nnz, CSR order, float64; the
+ * mapped-back factor as applied) and, if objective is not NULL, the per
+ * column least-squares residual norm in the scaled problem (device, n).
+ * A scalar-only factor exports alpha on the diagonal.  Asynchronous. */
+AIRGA_API airga_status airga_prec_export(airga_prec prec, double* values, double* objective);
+
+/* z = C r for `count` vectors (device, leading dimensions ldr, ldz),
+ * C the whole chain Q_z ... Q_2 P_1 applied factor by factor (float64).
+ * Asynchronous.  Errors: EINVAL. */
+AIRGA_API airga_status airga_prec_apply(airga_prec prec, int32_t count, const double* r, int64_t ldr,
+                              double* z, int64_t ldz);
+
+/* Drop the caller's reference.  NULL is ignored. */
+AIRGA_API void airga_prec_release(airga_prec prec);
+
+/* ------------------------------------------------------------------ solves */
+
+typedef struct {
+  double tol;          /* stop when ||F - K X|| <= tol ||F|| (float64 residual
+                          in MIXED mode, CG recurrence residual in FP64 mode).
+                          Default 1e-10.                                        */
+  int32_t max_iter;    /* CG iterations per system, summed over sweeps
+                          (default 20000)                                       */
+  int32_t mode;        /* AIRGA_MODE_FP64 or AIRGA_MODE_MIXED (float32 matrix,
+                          preconditioner and vectors inside float64 iterative
+                          refinement of the residual and the solution)          */
+  double inner_tol;    /* MIXED: relative residual reduction per sweep (1e-4)   */
+  int32_t max_sweeps;  /* MIXED: refinement sweeps (default 12)                 */
+  int32_t poll_every;  /* iterations between host checks of the active count
+                          (rounded up to even; default 8)                       */
+  int32_t x0_given;    /* 1: X holds the starting guess (resume); 0: X0 = 0     */
+  int32_t use_graph;   /* 1: replay iterations from a captured HIP graph        */
+  int32_t profile;     /* 1: time every launch of the dominant kernels with
+                          HIP events (no graph); see airga_get_kernel_times     */
+  int32_t reserved;
+} airga_pcg_opts;
+
+AIRGA_API void airga_pcg_opts_default(airga_pcg_opts* opts);
+
+typedef struct {
+  int32_t status;      /* AIRGA_SYS_*                                           */
+  int32_t iters;       /* CG iterations                                         */
+  int32_t sweeps;      /* refinement sweeps (MIXED), 1 for FP64                 */
+  int32_t reserved;
+  double relres;       /* ||F - K X|| / ||F|| from the float64 residual at exit */
+} airga_sys_stats;
+
+/* Solve K(s_k) X[:, c, k] = F[:, c] for every shift k < nshift and column
+ * c < m with preconditioned CG (the solves of lines 5 and 14 of the AIRGA
+ * algorithm; the SPAI variants of lines 5/11 and 17 of the algorithms with
+ * SPAI and SPAI update), all nshift*m systems batched in one set of kernels
+ * with per-system convergence masking.
+ *   shifts: host, nshift real expansion points (each > 0)
+ *   precs:  host, nshift handles (NULL entry = no preconditioner)
+ *   F:      device, n x m column-major, leading dimension ldf >= n
+ *   X:      device, n x m x nshift, column (c, k) at X + (k*m + c)*ldx,
+ *           ldx >= n; read as the starting guess when opts->x0_given
+ *   stats:  host, nshift*m entries in the same (k, c) order, may be NULL
+ * Returns after the stats are on the host.  Non-convergence is not an
+ * error: it is reported per system.  Errors: EINVAL, ESTATE, ENOMEM, EHIP. */
+AIRGA_API airga_status airga_pcg_solve(airga_ctx ctx, int32_t nshift, const double* shifts,
+                             const airga_prec* precs, int32_t m, const double* F, int64_t ldf,
+                             double* X, int64_t ldx, const airga_pcg_opts* opts,
+                             airga_sys_stats* stats);
+
+/* Kernel timings gathered by the last profiled solve (opts.profile = 1):
+ * for kernel id k < count (see airga_kernel_name), the number of launches
+ * and their summed duration in milliseconds (HIP events on the context
+ * stream).  Host arrays of at least `count` entries. */
+AIRGA_API int32_t airga_kernel_count(void);
+AIRGA_API const char* airga_kernel_name(int32_t id);
+AIRGA_API airga_status airga_get_kernel_times(airga_ctx ctx, int32_t count, int64_t* launches,
+                                    double* total_ms);
+
+/* Work done by the row kernels of the last profiled solve, for kernel id
+ * k < count: sys_passes[k] = (system, launch) pairs swept, shift_passes[k] =
+ * (shift, launch) pairs whose first preconditioner factor was read
+ * (update_prec) or further chain factors applied (chain).  Together with
+ * the pencil size these give the algorithmic bytes each kernel moved. */
+AIRGA_API airga_status airga_get_kernel_work(airga_ctx ctx, int32_t count, int64_t* sys_passes,
+                                             int64_t* shift_passes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AIRGA_H */

@@ -15,11 +15,11 @@ Rows outside I are zero on both sides, so this is the full column problem.
 Readings fixed here (each listed in the design notes):
   * equilibrate: the column problems are posed for Khat = S K S with
     S = diag(K)^{-1/2}; the result is mapped back as P = S Phat S.
-  * symmetrize (optional, off by default): Phat is replaced by
-    (Phat + Phat^T) / 2 before mapping back.  On the cantilever this average
-    is indefinite at the free tip, so the default keeps the right SPAI as the
-    paper defines it and lets CG use a direction update that does not need a
-    symmetric preconditioner.
+  * symmetrize (on by default): Phat is replaced by (Phat + Phat^T) / 2
+    before mapping back, so the preconditioner handed to CG is symmetric.
+    The average can be indefinite (on the cantilever, at the free tip), so CG
+    uses a step and direction update that stay defined then; without the
+    average the fixed-pattern right SPAI stalls CG on the stiff literal beam.
 
 Update (Section 3.2): instead of a new SPAI for K_new, find Q minimising
 ||K_old - K_new Q||_F column by column, starting from Q = alpha I with alpha
@@ -106,7 +106,7 @@ def _scaled_values(a_val, rows, cols, s_row, s_col):
     return a_val * s_row[rows] * s_col[cols]
 
 
-def spai_build(a: sp.csr_matrix, *, equilibrate=True, symmetrize=False, cols=None) -> Factor:
+def spai_build(a: sp.csr_matrix, *, equilibrate=True, symmetrize=True, cols=None) -> Factor:
     """SPAI of K(s) on its own structural pattern (eq. (3.1)).
 
     ``cols`` restricts the computation to a subset of columns (sampled checks

@@ -1,0 +1,352 @@
+"""Thin Python binding of libairga (C ABI in include/airga.h).
+
+Argument marshalling only: torch tensors supply device memory and the HIP
+stream; every computation runs in the library's HIP kernels.  There is no
+CPU fallback: if ``libairga.so`` is missing or cannot be loaded, every call
+raises.
+
+Names follow the C ABI: ``Context.set_pencil`` wraps ``airga_set_pencil``,
+``Context.spai_build`` wraps ``airga_spai_build`` and so on.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import weakref
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libairga.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTSPD, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+SYS_CONVERGED, SYS_MAXIT, SYS_BREAKDOWN, SYS_NONFINITE = 0, 1, 2, 3
+MODE_FP64, MODE_MIXED = 0, 1
+STATUS_NAMES = {SYS_CONVERGED: "converged", SYS_MAXIT: "maxit", SYS_BREAKDOWN: "breakdown",
+                SYS_NONFINITE: "nonfinite"}
+
+
+class AirgaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"airga status {status}: {msg}")
+        self.status = status
+
+
+class PencilInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("max_row_len", ctypes.c_int32),
+                ("bandwidth", ctypes.c_int32), ("slice_rows", ctypes.c_int32),
+                ("nnz", ctypes.c_int64), ("nnz_stored", ctypes.c_int64),
+                ("gram_mm", ctypes.c_double), ("gram_mk", ctypes.c_double),
+                ("gram_kk", ctypes.c_double), ("trace_m", ctypes.c_double),
+                ("trace_k", ctypes.c_double)]
+
+
+class SpaiOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("equilibrate", ctypes.c_int32),
+                ("symmetrize", ctypes.c_int32)]
+
+
+class PrecInfo(ctypes.Structure):
+    _fields_ = [("shift", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("chain_len", ctypes.c_int32), ("scalar_only", ctypes.c_int32),
+                ("skipped_cols", ctypes.c_int64)]
+
+
+class PcgOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("inner_tol", ctypes.c_double),
+                ("max_sweeps", ctypes.c_int32), ("poll_every", ctypes.c_int32),
+                ("x0_given", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class SysStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("relres", ctypes.c_double)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point
+_P = ctypes.c_void_p
+_SIGS = [
+    ("airga_create", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P]),
+    ("airga_destroy", None, [_P]),
+    ("airga_last_error", ctypes.c_char_p, []),
+    ("airga_version", ctypes.c_char_p, []),
+    ("airga_set_pencil", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P,
+                                        ctypes.c_double, ctypes.c_double]),
+    ("airga_get_pencil_info", ctypes.c_int, [_P, ctypes.POINTER(PencilInfo)]),
+    ("airga_assemble_shift", ctypes.c_int, [_P, ctypes.c_double, _P]),
+    ("airga_apply_shift", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32, _P, ctypes.c_int64,
+                                         _P, ctypes.c_int64]),
+    ("airga_shift_diagnostics", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double,
+                                               ctypes.POINTER(ctypes.c_double)]),
+    ("airga_spai_opts_default", None, [ctypes.POINTER(SpaiOpts)]),
+    ("airga_spai_build", ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(SpaiOpts),
+                                        ctypes.POINTER(_P)]),
+    ("airga_spai_update", ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.POINTER(SpaiOpts),
+                                         ctypes.POINTER(_P)]),
+    ("airga_get_prec_info", ctypes.c_int, [_P, ctypes.POINTER(PrecInfo)]),
+    ("airga_prec_export", ctypes.c_int, [_P, _P, _P]),
+    ("airga_prec_apply", ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64, _P,
+                                        ctypes.c_int64]),
+    ("airga_prec_release", None, [_P]),
+    ("airga_pcg_opts_default", None, [ctypes.POINTER(PcgOpts)]),
+    ("airga_pcg_solve", ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(_P), ctypes.c_int32, _P, ctypes.c_int64,
+                                       _P, ctypes.c_int64, ctypes.POINTER(PcgOpts),
+                                       ctypes.POINTER(SysStats)]),
+    ("airga_kernel_count", ctypes.c_int32, []),
+    ("airga_kernel_name", ctypes.c_char_p, [ctypes.c_int32]),
+    ("airga_get_kernel_times", ctypes.c_int, [_P, ctypes.c_int32,
+                                              ctypes.POINTER(ctypes.c_int64),
+                                              ctypes.POINTER(ctypes.c_double)]),
+    ("airga_get_kernel_work", ctypes.c_int, [_P, ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.POINTER(ctypes.c_int64)]),
+]
+
+EXPORTED = [s[0] for s in _SIGS]
+
+
+def lib():
+    """Load libairga.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = h
+    return _lib
+
+
+def _check(status: int):
+    if status != OK:
+        msg = lib().airga_last_error().decode(errors="replace")
+        raise AirgaError(status, msg)
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t: torch.Tensor, dtype, device) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.device != device or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} tensor on {device}, got "
+                         f"{t.dtype} on {t.device}")
+    return t
+
+
+class Context:
+    """airga_ctx on one GPU; all work is ordered on ``self.stream``, which is
+    joined with torch's current stream around every call."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        h = ctypes.c_void_p()
+        _check(lib().airga_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream)))
+        self._h = h
+        self.n = None
+        self.nnz = None
+        self._precs = weakref.WeakSet()
+
+    # stream joins
+    def _enter(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            # handles must go before their context
+            for p in list(self._precs):
+                p.release()
+            lib().airga_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- pencil
+    def set_pencil(self, row_ptr, col_idx, m_val, k_val, alpha: float, beta: float):
+        n = row_ptr.numel() - 1
+        _dev(row_ptr, torch.int32, self.device)
+        _dev(col_idx, torch.int32, self.device)
+        _dev(m_val, torch.float64, self.device)
+        _dev(k_val, torch.float64, self.device)
+        self._enter()
+        _check(lib().airga_set_pencil(self._h, n, col_idx.numel(), _ptr(row_ptr), _ptr(col_idx),
+                                      _ptr(m_val), _ptr(k_val), float(alpha), float(beta)))
+        self._leave()
+        self.n, self.nnz = n, col_idx.numel()
+
+    def pencil_info(self) -> PencilInfo:
+        info = PencilInfo()
+        _check(lib().airga_get_pencil_info(self._h, ctypes.byref(info)))
+        return info
+
+    def assemble_shift(self, s: float, out: torch.Tensor | None = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.nnz, dtype=torch.float64, device=self.device)
+        _dev(out, torch.float64, self.device)
+        self._enter()
+        _check(lib().airga_assemble_shift(self._h, float(s), _ptr(out)))
+        self._leave()
+        return out
+
+    def apply_shift(self, s: float, x: torch.Tensor) -> torch.Tensor:
+        """y = K(s) x for x of shape (count, n) (float64, contiguous)."""
+        _dev(x, torch.float64, self.device)
+        x2 = x.reshape(-1, self.n)
+        y = torch.empty_like(x2)
+        self._enter()
+        _check(lib().airga_apply_shift(self._h, float(s), x2.shape[0], _ptr(x2), self.n, _ptr(y),
+                                       self.n))
+        self._leave()
+        return y.reshape(x.shape)
+
+    def shift_diagnostics(self, s_old: float, s_new: float):
+        out = (ctypes.c_double * 4)()
+        _check(lib().airga_shift_diagnostics(self._h, float(s_old), float(s_new), out))
+        return tuple(out)
+
+    # ------------------------------------------------------- preconditioners
+    @staticmethod
+    def _spai_opts(tol, equilibrate, symmetrize):
+        o = SpaiOpts()
+        lib().airga_spai_opts_default(ctypes.byref(o))
+        if tol is not None:
+            o.tol = float(tol)
+        o.equilibrate = int(bool(equilibrate))
+        o.symmetrize = int(bool(symmetrize))
+        return o
+
+    def spai_build(self, s: float, *, equilibrate=True, symmetrize=True) -> "Prec":
+        o = self._spai_opts(None, equilibrate, symmetrize)
+        h = ctypes.c_void_p()
+        self._enter()
+        _check(lib().airga_spai_build(self._h, float(s), ctypes.byref(o), ctypes.byref(h)))
+        self._leave()
+        return Prec(self, h)
+
+    def spai_update(self, old: "Prec", s_new: float, *, tol=0.01, equilibrate=True) -> "Prec":
+        o = self._spai_opts(tol, equilibrate, False)
+        h = ctypes.c_void_p()
+        self._enter()
+        _check(lib().airga_spai_update(self._h, old._h, float(s_new), ctypes.byref(o),
+                                       ctypes.byref(h)))
+        self._leave()
+        return Prec(self, h)
+
+    # ---------------------------------------------------------------- solves
+    def pcg_solve(self, shifts, precs, F: torch.Tensor, X: torch.Tensor | None = None, *,
+                  tol=1e-10, max_iter=20000, mode=MODE_FP64, inner_tol=1e-4, max_sweeps=12,
+                  poll_every=8, x0_given=False, use_graph=True, profile=False):
+        """Solve K(s_k) X[k, c] = F[c] for all shifts k and columns c.
+
+        F: (m, n) float64 on the device; X: (nshift, m, n) float64 (allocated
+        when None).  precs: list of Prec or None per shift.  Returns
+        (X, stats) with stats a list of dicts in (k, c) order.
+        """
+        _dev(F, torch.float64, self.device)
+        m = F.shape[0]
+        shifts = [float(s) for s in shifts]
+        nshift = len(shifts)
+        if X is None:
+            X = torch.empty((nshift, m, self.n), dtype=torch.float64, device=self.device)
+        _dev(X, torch.float64, self.device)
+        if tuple(X.shape) != (nshift, m, self.n) or tuple(F.shape) != (m, self.n):
+            raise ValueError("F must be (m, n) and X (nshift, m, n)")
+        if precs is None:
+            precs = [None] * nshift
+        if len(precs) != nshift:
+            raise ValueError("one preconditioner (or None) per shift")
+        c_shifts = (ctypes.c_double * nshift)(*shifts)
+        c_precs = (ctypes.c_void_p * nshift)(*[p._h.value if p is not None else None for p in precs])
+        o = PcgOpts()
+        lib().airga_pcg_opts_default(ctypes.byref(o))
+        o.tol, o.max_iter, o.mode = float(tol), int(max_iter), int(mode)
+        o.inner_tol, o.max_sweeps, o.poll_every = float(inner_tol), int(max_sweeps), int(poll_every)
+        o.x0_given, o.use_graph, o.profile = int(bool(x0_given)), int(bool(use_graph)), int(bool(profile))
+        stats = (SysStats * (nshift * m))()
+        self._enter()
+        _check(lib().airga_pcg_solve(self._h, nshift, c_shifts, c_precs, m, _ptr(F), self.n,
+                                     _ptr(X), self.n, ctypes.byref(o), stats))
+        self._leave()
+        out = [dict(status=s.status, iters=s.iters, sweeps=s.sweeps, relres=s.relres)
+               for s in stats]
+        return X, out
+
+    def kernel_times(self) -> dict:
+        """{kernel: (launches, total ms)} of the last profiled solve."""
+        k = lib().airga_kernel_count()
+        launches = (ctypes.c_int64 * k)()
+        ms = (ctypes.c_double * k)()
+        _check(lib().airga_get_kernel_times(self._h, k, launches, ms))
+        return {lib().airga_kernel_name(i).decode(): (launches[i], ms[i]) for i in range(k)}
+
+    def kernel_work(self) -> dict:
+        """{kernel: (system passes, shift passes)} of the last profiled solve."""
+        k = lib().airga_kernel_count()
+        sysp = (ctypes.c_int64 * k)()
+        shp = (ctypes.c_int64 * k)()
+        _check(lib().airga_get_kernel_work(self._h, k, sysp, shp))
+        return {lib().airga_kernel_name(i).decode(): (sysp[i], shp[i]) for i in range(k)}
+
+
+class Prec:
+    """airga_prec handle (released on garbage collection)."""
+
+    def __init__(self, ctx: Context, h: ctypes.c_void_p):
+        self.ctx = ctx
+        self._h = h
+        ctx._precs.add(self)
+
+    def info(self) -> PrecInfo:
+        i = PrecInfo()
+        _check(lib().airga_get_prec_info(self._h, ctypes.byref(i)))
+        return i
+
+    def export(self):
+        """(values in CSR order (nnz,), per-column objective (n,)), float64."""
+        c = self.ctx
+        vals = torch.empty(c.nnz, dtype=torch.float64, device=c.device)
+        obj = torch.empty(c.n, dtype=torch.float64, device=c.device)
+        c._enter()
+        _check(lib().airga_prec_export(self._h, _ptr(vals), _ptr(obj)))
+        c._leave()
+        return vals, obj
+
+    def apply(self, r: torch.Tensor) -> torch.Tensor:
+        c = self.ctx
+        _dev(r, torch.float64, c.device)
+        r2 = r.reshape(-1, c.n)
+        z = torch.empty_like(r2)
+        c._enter()
+        _check(lib().airga_prec_apply(self._h, r2.shape[0], _ptr(r2), c.n, _ptr(z), c.n))
+        c._leave()
+        return z.reshape(r.shape)
+
+    def release(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().airga_prec_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass

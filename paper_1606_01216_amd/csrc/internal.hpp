@@ -1,0 +1,205 @@
+// Internal declarations of libairga (gfx950).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "airga.h"
+
+namespace airga {
+
+// Rows per slice of the sliced-ELL layout: one wavefront of 64 lanes, one row
+// per lane, so every matrix load of a wavefront is one contiguous 64-entry run.
+constexpr int kSlice = 64;
+// Longest row the pencil may have.
+constexpr int kMaxRow = 16;
+// Longest row the SPAI column kernels handle (the Givens factor of a column
+// problem lives in registers: kSpaiMaxJ*(kSpaiMaxJ+1)/2 doubles).
+constexpr int kSpaiMaxJ = 8;
+
+// ------------------------------------------------------------------ errors
+
+void set_error(const char* fmt, ...);
+airga_status fail(airga_status st, const char* fmt, ...);
+
+#define AIRGA_HIP(call)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return ::airga::fail(AIRGA_EHIP, "%s failed: %s (%s:%d)", #call,               \
+                           hipGetErrorString(e_), __FILE__, __LINE__);               \
+  } while (0)
+
+#define AIRGA_TRY(expr)                     \
+  do {                                      \
+    airga_status s_ = (expr);               \
+    if (s_ != AIRGA_OK) return s_;          \
+  } while (0)
+
+// ------------------------------------------------------------- device memory
+
+// A grow-only device allocation.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  airga_status reserve(size_t need);
+  void release();
+  template <typename T>
+  T* as() const { return static_cast<T*>(ptr); }
+  ~DevBuf() { release(); }
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+};
+
+// ------------------------------------------------------------------- pencil
+
+// Device view of the pencil in sliced-ELL form.  Slice s holds rows
+// [64 s, 64 s + 64); entry k of row r sits at slice_ptr[s] + 64 k + (r % 64)
+// for k < width(s) = (slice_ptr[s+1] - slice_ptr[s]) / 64.  Entries past a
+// row's length are padding: column = the row itself, value 0.
+struct PencilDev {
+  int32_t n;
+  int32_t n_slices;
+  const int32_t* slice_ptr;  // n_slices + 1
+  const int32_t* row_len;    // n_slices * 64 (0 for rows >= n)
+  const int32_t* col;        // stored entries
+  const int32_t* mirror;     // stored index of entry (c, r) for entry (r, c)
+  const int32_t* csr_pos;    // CSR position of each stored entry, -1 for padding
+  const int32_t* diag_pos;   // stored index of (r, r)
+  const double* m64;
+  const double* k64;
+  const float* m32;
+  const float* k32;
+};
+
+struct Pencil {
+  bool valid = false;
+  uint64_t generation = 0;
+  int32_t n = 0, n_slices = 0, max_len = 0, bandwidth = 0;
+  int64_t nnz = 0, nnz_stored = 0;
+  double alpha = 0, beta = 0;
+  double gram_mm = 0, gram_mk = 0, gram_kk = 0, tr_m = 0, tr_k = 0;
+  bool diag_ok = false;  // M_rr > 0 and K_rr >= 0 for every row
+  DevBuf slice_ptr, row_len, col, mirror, csr_pos, diag_pos, m64, k64, m32, k32;
+  PencilDev dev() const;
+  int64_t n_pad() const { return (int64_t)n_slices * kSlice; }
+};
+
+// ------------------------------------------------------------- kernel times
+
+enum KernelId {
+  K_DIR_SPMV = 0,   // direction update + shifted SpMV + (p, Kp)
+  K_UPDATE_PREC,    // x/r update + first preconditioner factor + dots
+  K_INIT_PREC,      // first preconditioner application of a (re)start
+  K_CHAIN,          // further chain factors
+  K_REDUCE,         // per-system scalar reductions
+  K_IR_RESIDUAL,    // float64 residual F - K X
+  K_IR_UPDATE,      // X += d
+  K_COUNT
+};
+
+// Per-kernel launch counts and summed durations (profiled solves), plus the
+// work each launch did: systems swept and shifts whose factor was read.
+struct KernelTimes {
+  int64_t launches[K_COUNT] = {};
+  double ms[K_COUNT] = {};
+  int64_t sys_passes[K_COUNT] = {};
+  int64_t shift_passes[K_COUNT] = {};
+  void clear() {
+    for (int i = 0; i < K_COUNT; ++i) {
+      launches[i] = 0;
+      ms[i] = 0;
+      sys_passes[i] = 0;
+      shift_passes[i] = 0;
+    }
+  }
+};
+
+// ------------------------------------------------------------------ context
+
+}  // namespace airga
+
+struct airga_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  airga::Pencil pen;
+  // Solve workspaces (grow-only).
+  airga::DevBuf ws_vec, ws_partial, ws_sys, ws_shift, ws_asm, ws_tmp;
+  void* host_pinned = nullptr;
+  size_t host_pinned_bytes = 0;
+  airga::KernelTimes times;
+  std::atomic<int> live_precs{0};
+  // Autotuned rows-per-lane choice, keyed by (n_slices, batch, precision).
+  struct Tune { int32_t n_slices, batch, prec, rows; };
+  std::vector<Tune> tuned;
+};
+
+struct airga_prec_s {
+  airga_ctx ctx = nullptr;
+  uint64_t generation = 0;
+  std::atomic<int> refs{1};
+  double shift = 0;
+  double alpha = 0;          // host copy once known (read lazily)
+  bool alpha_known = false;
+  bool is_update = false;
+  int64_t skipped = -1;      // host copy once known
+  bool scalar_only = false;  // decided on the host after the skip count is read
+  bool scalar_known = false;
+  airga_prec parent = nullptr;
+  airga::DevBuf v64, v32, objective, scal;  // scal: [alpha, skip count] on device
+};
+
+namespace airga {
+
+airga_status check_ctx(airga_ctx ctx);
+airga_status check_pencil(airga_ctx ctx);
+airga_status ensure_pinned(airga_ctx ctx, size_t bytes);
+
+// Resolve the lazy host-side facts of an update factor (synchronises).
+airga_status prec_resolve(airga_prec p);
+// Non-scalar factors of the chain, newest first.
+airga_status prec_chain(airga_prec p, std::vector<airga_prec>* out);
+
+// Shift coefficients a = s^2 + alpha s, b = 1 + beta s.
+inline void shift_coeffs(const Pencil& pen, double s, double* a, double* b) {
+  *a = s * s + pen.alpha * s;
+  *b = 1.0 + pen.beta * s;
+}
+
+// ----------------------------------------------------------- device helpers
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    T o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Launch-size helper.
+inline unsigned blocks_for(int64_t work, int per_block) {
+  return (unsigned)((work + per_block - 1) / per_block);
+}
+
+// Kernels shared between translation units.
+__global__ void k_fill_f64(double* p, int64_t count, double v);
+__global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v);
+
+}  // namespace airga

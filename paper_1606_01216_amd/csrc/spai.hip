@@ -1,0 +1,583 @@
+// SPAI build (Section 3.1, eq. (3.1)) and SPAI update (Section 3.2) on the
+// structural pattern of K(s), one GPU lane per column, plus the factor
+// handles and the chain application of the update algorithm.
+//
+// Column j of the build solves  min || e_j - Khat(:, J) p ||_2  and column j
+// of the update solves  min || khat_old_j - Khat_new(:, J) q ||_2, with
+// J = pattern of column j.  Only the rows I = union of the patterns of the
+// columns in J can be nonzero, so each lane streams the rows of Khat(I, J)
+// through a Givens QR held in registers (|J| <= kSpaiMaxJ), then solves the
+// triangular system.  Khat = S K S with S = diag(K)^{-1/2} when
+// equilibrating (S = I otherwise); every entry of K(s) is formed on the fly
+// as (s^2 + alpha s) M + (1 + beta s) K from the float64 pencil.
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace airga {
+
+// Packed upper-triangular index of (k, l), k <= l, in an MJ x MJ factor.
+template <int MJ>
+__device__ __host__ constexpr int tri(int k, int l) {
+  return k * MJ - (k * (k - 1)) / 2 + (l - k);
+}
+
+// Fold one row (v, rhs) of the least-squares problem into the triangular
+// factor R and Q^T b by Givens rotations; on return rhs holds the component
+// of the row left orthogonal to the column space.
+template <int MJ>
+__device__ __forceinline__ void givens_row(double (&R)[MJ * (MJ + 1) / 2], double (&qtb)[MJ],
+                                           double (&v)[MJ], double& rhs, int nj) {
+#pragma unroll
+  for (int k = 0; k < MJ; ++k) {
+    if (k < nj && v[k] != 0.0) {
+      const double rkk = R[tri<MJ>(k, k)];
+      const double h = hypot(rkk, v[k]);
+      const double c = rkk / h, s = v[k] / h;
+      R[tri<MJ>(k, k)] = h;
+#pragma unroll
+      for (int l = k + 1; l < MJ; ++l) {
+        if (l < nj) {
+          const double rl = R[tri<MJ>(k, l)], vl = v[l];
+          R[tri<MJ>(k, l)] = c * rl + s * vl;
+          v[l] = c * vl - s * rl;
+        }
+      }
+      const double qb = qtb[k];
+      qtb[k] = c * qb + s * rhs;
+      rhs = c * rhs - s * qb;
+    }
+  }
+}
+
+// dinv[r] = diag(K(s))_r^{-1/2} (or 1 without equilibration); padding rows 1.
+__global__ void k_dinv(PencilDev pd, double a, double b, int equilibrate, double* __restrict__ dinv) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= (int64_t)pd.n_slices * kSlice) return;
+  double v = 1.0;
+  if (r < pd.n && equilibrate) {
+    const int32_t q = pd.diag_pos[r];
+    v = 1.0 / sqrt(fma(a, pd.m64[q], b * pd.k64[q]));
+  }
+  dinv[r] = v;
+}
+
+// Per-block partial sums of <Khat_old, Khat_new>_F and ||Khat_new||_F^2 (both
+// scaled by the new diagonal), the numerator and denominator of the update's
+// starting scaling alpha (Section 3.2).
+__global__ void k_alpha_partial(PencilDev pd, double a, double b, double a_old, double b_old,
+                                const double* __restrict__ dinv, double* __restrict__ part) {
+  __shared__ double red[2][4];
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double num = 0, den = 0;
+  if (r < pd.n) {
+    const int32_t base = pd.slice_ptr[r / kSlice] + (int32_t)(r % kSlice);
+    const int len = pd.row_len[r];
+    const double sr = dinv[r];
+    for (int k = 0; k < len; ++k) {
+      const int32_t idx = base + k * kSlice;
+      const double sc = sr * dinv[pd.col[idx]];
+      const double m = pd.m64[idx], kk = pd.k64[idx];
+      const double an = fma(a, m, b * kk) * sc;
+      const double ao = fma(a_old, m, b_old * kk) * sc;
+      num = fma(ao, an, num);
+      den = fma(an, an, den);
+    }
+  }
+  num = wave_sum(num);
+  den = wave_sum(den);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = num;
+    red[1][w] = den;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0;
+    for (int i = 0; i < 4; ++i) t += red[threadIdx.x][i];
+    part[(int64_t)blockIdx.x * 2 + threadIdx.x] = t;
+  }
+}
+
+// alpha = num / den from the per-block partials, summed in a fixed order.
+__global__ void k_alpha_final(const double* __restrict__ part, int64_t nb, double* __restrict__ out) {
+  __shared__ double red[2][256];
+  const int t = threadIdx.x;
+  double num = 0, den = 0;
+  for (int64_t i = t; i < nb; i += blockDim.x) {
+    num += part[2 * i];
+    den += part[2 * i + 1];
+  }
+  red[0][t] = num;
+  red[1][t] = den;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      red[0][t] += red[0][t + h];
+      red[1][t] += red[1][t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) out[0] = red[0][0] / red[1][0];
+}
+
+// One lane per column j.  UPDATE selects the update's right-hand side
+// khat_old_j and its skip test; otherwise the right-hand side is e_j.
+template <int MJ, bool UPDATE>
+__global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, double a, double b,
+                                                   double a_old, double b_old,
+                                                   const double* __restrict__ dinv,
+                                                   const double* __restrict__ alpha_u, double tol,
+                                                   double* __restrict__ hat,
+                                                   double* __restrict__ obj,
+                                                   int32_t* __restrict__ skip_count) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  bool skipped = false;
+  if (j < pd.n) {
+    const int32_t base_j = pd.slice_ptr[j / kSlice] + (int32_t)(j % kSlice);
+    const int nj = pd.row_len[j];
+    int J[MJ];
+    int32_t jpos[MJ];
+#pragma unroll
+    for (int t = 0; t < MJ; ++t) {
+      J[t] = -1;
+      jpos[t] = 0;
+      if (t < nj) {
+        jpos[t] = base_j + t * kSlice;
+        J[t] = pd.col[jpos[t]];
+      }
+    }
+    const double sj = dinv[j];
+    if constexpr (UPDATE) {
+      // skip test on column j (= row j: K(s) and S are symmetric)
+      const double al = *alpha_u;
+      double n_old = 0, n_res = 0;
+#pragma unroll
+      for (int t = 0; t < MJ; ++t) {
+        if (t < nj) {
+          const int32_t idx = jpos[t];
+          const double sc = sj * dinv[J[t]];
+          const double m = pd.m64[idx], kk = pd.k64[idx];
+          const double vo = fma(a_old, m, b_old * kk) * sc;
+          const double vn = fma(a, m, b * kk) * sc;
+          const double d = vo - al * vn;
+          n_old = fma(vo, vo, n_old);
+          n_res = fma(d, d, n_res);
+        }
+      }
+      if (sqrt(n_res) <= tol * sqrt(n_old)) {
+        skipped = true;
+#pragma unroll
+        for (int t = 0; t < MJ; ++t)
+          if (t < nj) hat[pd.mirror[jpos[t]]] = J[t] == (int)j ? al : 0.0;
+        obj[j] = sqrt(n_res);
+      }
+    }
+    if (!skipped) {
+      double R[MJ * (MJ + 1) / 2];
+      double qtb[MJ];
+#pragma unroll
+      for (int q = 0; q < MJ * (MJ + 1) / 2; ++q) R[q] = 0.0;
+#pragma unroll
+      for (int q = 0; q < MJ; ++q) qtb[q] = 0.0;
+      double res2 = 0.0;
+#pragma unroll
+      for (int t = 0; t < MJ; ++t) {
+        if (t < nj) {
+          const int k = J[t];
+          const int32_t base_k = pd.slice_ptr[k / kSlice] + (k % kSlice);
+          const int nk = pd.row_len[k];
+          for (int e = 0; e < nk; ++e) {
+            const int i = pd.col[base_k + e * kSlice];
+            // Row i of Khat restricted to the columns J.  Row i is first met
+            // through the earliest column of J whose pattern holds it; later
+            // meetings are duplicates and are skipped.
+            const int32_t base_i = pd.slice_ptr[i / kSlice] + (i % kSlice);
+            const int ni = pd.row_len[i];
+            const double si = dinv[i];
+            double v[MJ];
+#pragma unroll
+            for (int u = 0; u < MJ; ++u) v[u] = 0.0;
+            int umin = MJ;
+            double rhs = 0.0;
+            for (int q = 0; q < ni; ++q) {
+              const int32_t idx = base_i + q * kSlice;
+              const int c = pd.col[idx];
+              const double m = pd.m64[idx], kk = pd.k64[idx];
+              const double sc = si * dinv[c];
+#pragma unroll
+              for (int u = 0; u < MJ; ++u) {
+                if (u < nj && J[u] == c) {
+                  v[u] += fma(a, m, b * kk) * sc;
+                  umin = u < umin ? u : umin;
+                }
+              }
+              if constexpr (UPDATE) {
+                if (c == (int)j) rhs = fma(a_old, m, b_old * kk) * sc;
+              }
+            }
+            if constexpr (!UPDATE) rhs = (i == (int)j) ? 1.0 : 0.0;
+            if (umin < t) continue;
+            givens_row<MJ>(R, qtb, v, rhs, nj);
+            res2 = fma(rhs, rhs, res2);
+          }
+        }
+      }
+      double p[MJ];
+#pragma unroll
+      for (int t = MJ - 1; t >= 0; --t) {
+        p[t] = 0.0;
+        if (t < nj) {
+          double acc = qtb[t];
+#pragma unroll
+          for (int u = t + 1; u < MJ; ++u)
+            if (u < nj) acc -= R[tri<MJ>(t, u)] * p[u];
+          const double d = R[tri<MJ>(t, t)];
+          p[t] = d != 0.0 ? acc / d : 0.0;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < MJ; ++t)
+        if (t < nj) hat[pd.mirror[jpos[t]]] = p[t];
+      obj[j] = sqrt(res2);
+    }
+  }
+  if constexpr (UPDATE) {
+    const unsigned long long bal = __ballot(skipped);
+    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(skip_count, (int32_t)__popcll(bal));
+  }
+}
+
+// Map the scaled factor back and store float64 and float32 copies:
+//   build:        P = S Phat S          (mode 0)
+//   build, sym:   P = S (Phat + Phat^T)/2 S   (mode 1)
+//   update:       Q = S Qhat S^{-1}     (mode 2)
+// Padding entries are 0.
+__global__ void k_spai_finalize(PencilDev pd, const double* __restrict__ hat,
+                                const double* __restrict__ dinv, int mode,
+                                double* __restrict__ v64, float* __restrict__ v32) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= (int64_t)pd.n_slices * kSlice) return;
+  const int64_t s = r / kSlice;
+  const int32_t base = pd.slice_ptr[s] + (int32_t)(r % kSlice);
+  const int w = (pd.slice_ptr[s + 1] - pd.slice_ptr[s]) / kSlice;
+  const int len = pd.row_len[r];
+  const double sr = dinv[r];
+  for (int k = 0; k < w; ++k) {
+    const int32_t idx = base + k * kSlice;
+    double val = 0.0;
+    if (k < len) {
+      const int c = pd.col[idx];
+      double h = hat[idx];
+      if (mode == 1) h = 0.5 * (h + hat[pd.mirror[idx]]);
+      val = mode == 2 ? h * sr / dinv[c] : h * sr * dinv[c];
+    }
+    v64[idx] = val;
+    v32[idx] = (float)val;
+  }
+}
+
+// out[e] (CSR order) = values[stored idx]
+__global__ void k_export(PencilDev pd, int64_t stored, const double* __restrict__ v,
+                         double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= stored) return;
+  const int32_t e = pd.csr_pos[i];
+  if (e >= 0) out[e] = v[i];
+}
+
+// y = scale * V x with V on the pattern (stored order), float64; blockIdx.y = vector.
+__global__ void k_factor_apply(PencilDev pd, const double* __restrict__ vals, double scale,
+                               const double* __restrict__ x, int64_t ldx, double* __restrict__ y,
+                               int64_t ldy) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= pd.n) return;
+  const double* xv = x + (int64_t)blockIdx.y * ldx;
+  const int64_t s = r / kSlice;
+  const int32_t base = pd.slice_ptr[s] + (int32_t)(r % kSlice);
+  const int w = (pd.slice_ptr[s + 1] - pd.slice_ptr[s]) / kSlice;
+  double acc = 0;
+  if (vals) {
+    for (int k = 0; k < w; ++k) {
+      const int32_t idx = base + k * kSlice;
+      acc = fma(vals[idx], xv[pd.col[idx]], acc);
+    }
+  } else {
+    acc = xv[r];
+  }
+  y[(int64_t)blockIdx.y * ldy + r] = scale * acc;
+}
+
+// ------------------------------------------------------------------- host
+
+static airga_status new_prec(airga_ctx ctx, double s, airga_prec* out) {
+  airga_prec p = new (std::nothrow) airga_prec_s();
+  if (!p) return fail(AIRGA_ENOMEM, "host allocation failed");
+  p->ctx = ctx;
+  p->generation = ctx->pen.generation;
+  p->shift = s;
+  const Pencil& pen = ctx->pen;
+  airga_status st;
+  if ((st = p->v64.reserve(sizeof(double) * pen.nnz_stored)) != AIRGA_OK ||
+      (st = p->v32.reserve(sizeof(float) * pen.nnz_stored)) != AIRGA_OK ||
+      (st = p->objective.reserve(sizeof(double) * pen.n)) != AIRGA_OK ||
+      (st = p->scal.reserve(64)) != AIRGA_OK) {
+    delete p;
+    return st;
+  }
+  ctx->live_precs++;
+  *out = p;
+  return AIRGA_OK;
+}
+
+static airga_status check_spai_args(airga_ctx ctx, double s, airga_prec* out) {
+  AIRGA_TRY(check_pencil(ctx));
+  if (!out) return fail(AIRGA_EINVAL, "null output handle");
+  if (!std::isfinite(s) || !(s > 0)) return fail(AIRGA_EINVAL, "shift must be finite and > 0");
+  if (!ctx->pen.diag_ok)
+    return fail(AIRGA_ENOTSPD, "a diagonal entry of M is <= 0 or of K is < 0: K(s) may not be SPD");
+  if (ctx->pen.max_len > kSpaiMaxJ)
+    return fail(AIRGA_EUNSUPPORTED, "SPAI needs rows of at most %d entries (longest row: %d)",
+                kSpaiMaxJ, ctx->pen.max_len);
+  return AIRGA_OK;
+}
+
+// Scratch for one SPAI call: [dinv (n_pad) | hat (stored) | partials].
+static airga_status spai_scratch(airga_ctx ctx, double** dinv, double** hat, double** part,
+                                 int64_t nb) {
+  const Pencil& pen = ctx->pen;
+  const size_t need = sizeof(double) * ((size_t)pen.n_pad() + (size_t)pen.nnz_stored + 2 * nb + 8);
+  AIRGA_TRY(ctx->ws_tmp.reserve(need));
+  *dinv = ctx->ws_tmp.as<double>();
+  *hat = *dinv + pen.n_pad();
+  *part = *hat + pen.nnz_stored;
+  return AIRGA_OK;
+}
+
+static airga_status run_build(airga_ctx ctx, double s, const airga_spai_opts& o, airga_prec p) {
+  const Pencil& pen = ctx->pen;
+  hipStream_t st = ctx->stream;
+  double a, b;
+  shift_coeffs(pen, s, &a, &b);
+  double *dinv, *hat, *part;
+  AIRGA_TRY(spai_scratch(ctx, &dinv, &hat, &part, 0));
+  const PencilDev pd = pen.dev();
+  k_dinv<<<blocks_for(pen.n_pad(), 256), 256, 0, st>>>(pd, a, b, o.equilibrate, dinv);
+  AIRGA_HIP(hipGetLastError());
+  k_spai_cols<kSpaiMaxJ, false><<<blocks_for(pen.n, 256), 256, 0, st>>>(
+      pd, a, b, 0.0, 0.0, dinv, nullptr, 0.0, hat, p->objective.as<double>(), nullptr);
+  AIRGA_HIP(hipGetLastError());
+  k_spai_finalize<<<blocks_for(pen.n_pad(), 256), 256, 0, st>>>(
+      pd, hat, dinv, o.symmetrize ? 1 : 0, p->v64.as<double>(), p->v32.as<float>());
+  AIRGA_HIP(hipGetLastError());
+  // Alg. 2's starting scaling trace(K) / trace(K K^T), from the Gram scalars.
+  const double nn = a * a * pen.gram_mm + 2 * a * b * pen.gram_mk + b * b * pen.gram_kk;
+  p->alpha = (a * pen.tr_m + b * pen.tr_k) / nn;
+  p->alpha_known = true;
+  p->skipped = 0;
+  p->scalar_only = false;
+  p->scalar_known = true;
+  return AIRGA_OK;
+}
+
+static airga_status run_update(airga_ctx ctx, airga_prec old, double s_new,
+                               const airga_spai_opts& o, airga_prec p) {
+  const Pencil& pen = ctx->pen;
+  hipStream_t st = ctx->stream;
+  double a, b, ao, bo;
+  shift_coeffs(pen, s_new, &a, &b);
+  shift_coeffs(pen, old->shift, &ao, &bo);
+  const unsigned nb = blocks_for(pen.n, 256);
+  double *dinv, *hat, *part;
+  AIRGA_TRY(spai_scratch(ctx, &dinv, &hat, &part, nb));
+  const PencilDev pd = pen.dev();
+  double* d_alpha = p->scal.as<double>();
+  int32_t* d_skip = reinterpret_cast<int32_t*>(p->scal.as<char>() + 8);
+  k_dinv<<<blocks_for(pen.n_pad(), 256), 256, 0, st>>>(pd, a, b, o.equilibrate, dinv);
+  AIRGA_HIP(hipGetLastError());
+  k_alpha_partial<<<nb, 256, 0, st>>>(pd, a, b, ao, bo, dinv, part);
+  AIRGA_HIP(hipGetLastError());
+  k_alpha_final<<<1, 256, 0, st>>>(part, nb, d_alpha);
+  AIRGA_HIP(hipGetLastError());
+  k_fill_i32<<<1, 64, 0, st>>>(d_skip, 1, 0);
+  AIRGA_HIP(hipGetLastError());
+  k_spai_cols<kSpaiMaxJ, true><<<nb, 256, 0, st>>>(pd, a, b, ao, bo, dinv, d_alpha, o.tol, hat,
+                                                   p->objective.as<double>(), d_skip);
+  AIRGA_HIP(hipGetLastError());
+  k_spai_finalize<<<blocks_for(pen.n_pad(), 256), 256, 0, st>>>(pd, hat, dinv, 2,
+                                                                p->v64.as<double>(),
+                                                                p->v32.as<float>());
+  AIRGA_HIP(hipGetLastError());
+  p->is_update = true;
+  p->parent = old;
+  old->refs++;
+  return AIRGA_OK;
+}
+
+airga_status prec_resolve(airga_prec p) {
+  if (p->scalar_known && p->alpha_known) return AIRGA_OK;
+  struct {
+    double alpha;
+    int32_t skipped, pad;
+  } h{};
+  AIRGA_HIP(hipMemcpyAsync(&h, p->scal.ptr, 16, hipMemcpyDeviceToHost, p->ctx->stream));
+  AIRGA_HIP(hipStreamSynchronize(p->ctx->stream));
+  p->alpha = h.alpha;
+  p->alpha_known = true;
+  p->skipped = h.skipped;
+  p->scalar_only = h.skipped == p->ctx->pen.n;
+  p->scalar_known = true;
+  return AIRGA_OK;
+}
+
+airga_status prec_chain(airga_prec p, std::vector<airga_prec>* out) {
+  out->clear();
+  for (airga_prec q = p; q; q = q->parent) {
+    AIRGA_TRY(prec_resolve(q));
+    if (!q->scalar_only) out->push_back(q);
+  }
+  return AIRGA_OK;
+}
+
+static airga_status check_prec(airga_prec p) {
+  if (!p) return fail(AIRGA_EINVAL, "null preconditioner");
+  AIRGA_TRY(check_pencil(p->ctx));
+  if (p->generation != p->ctx->pen.generation)
+    return fail(AIRGA_ESTATE, "preconditioner was built for an earlier pencil");
+  return AIRGA_OK;
+}
+
+}  // namespace airga
+
+using namespace airga;
+
+extern "C" {
+
+void airga_spai_opts_default(airga_spai_opts* o) {
+  if (!o) return;
+  o->tol = 0.01;
+  o->equilibrate = 1;
+  o->symmetrize = 1;
+}
+
+airga_status airga_spai_build(airga_ctx ctx, double s, const airga_spai_opts* opts,
+                              airga_prec* out) {
+  AIRGA_TRY(check_spai_args(ctx, s, out));
+  *out = nullptr;
+  airga_spai_opts o;
+  airga_spai_opts_default(&o);
+  if (opts) o = *opts;
+  double a, b;
+  shift_coeffs(ctx->pen, s, &a, &b);
+  airga_prec p = nullptr;
+  AIRGA_TRY(new_prec(ctx, s, &p));
+  airga_status st = run_build(ctx, s, o, p);
+  if (st != AIRGA_OK) {
+    airga_prec_release(p);
+    return st;
+  }
+  *out = p;
+  return AIRGA_OK;
+}
+
+airga_status airga_spai_update(airga_ctx ctx, airga_prec old, double s_new,
+                               const airga_spai_opts* opts, airga_prec* out) {
+  AIRGA_TRY(check_spai_args(ctx, s_new, out));
+  *out = nullptr;
+  AIRGA_TRY(check_prec(old));
+  if (old->ctx != ctx) return fail(AIRGA_EINVAL, "preconditioner belongs to another context");
+  airga_spai_opts o;
+  airga_spai_opts_default(&o);
+  if (opts) o = *opts;
+  if (!(o.tol >= 0)) return fail(AIRGA_EINVAL, "update tolerance must be >= 0");
+  airga_prec p = nullptr;
+  AIRGA_TRY(new_prec(ctx, s_new, &p));
+  airga_status st = run_update(ctx, old, s_new, o, p);
+  if (st != AIRGA_OK) {
+    airga_prec_release(p);
+    return st;
+  }
+  *out = p;
+  return AIRGA_OK;
+}
+
+airga_status airga_get_prec_info(airga_prec prec, airga_prec_info* out) {
+  AIRGA_TRY(check_prec(prec));
+  if (!out) return fail(AIRGA_EINVAL, "null output");
+  AIRGA_TRY(prec_resolve(prec));
+  std::vector<airga_prec> chain;
+  AIRGA_TRY(prec_chain(prec, &chain));
+  out->shift = prec->shift;
+  out->alpha = prec->alpha;
+  out->chain_len = (int32_t)chain.size();
+  out->scalar_only = prec->scalar_only ? 1 : 0;
+  out->skipped_cols = prec->skipped;
+  return AIRGA_OK;
+}
+
+airga_status airga_prec_export(airga_prec prec, double* values, double* objective) {
+  AIRGA_TRY(check_prec(prec));
+  airga_ctx ctx = prec->ctx;
+  if (values) {
+    k_export<<<blocks_for(ctx->pen.nnz_stored, 256), 256, 0, ctx->stream>>>(
+        ctx->pen.dev(), ctx->pen.nnz_stored, prec->v64.as<double>(), values);
+    AIRGA_HIP(hipGetLastError());
+  }
+  if (objective)
+    AIRGA_HIP(hipMemcpyAsync(objective, prec->objective.ptr, sizeof(double) * ctx->pen.n,
+                             hipMemcpyDeviceToDevice, ctx->stream));
+  return AIRGA_OK;
+}
+
+airga_status airga_prec_apply(airga_prec prec, int32_t count, const double* r, int64_t ldr,
+                              double* z, int64_t ldz) {
+  AIRGA_TRY(check_prec(prec));
+  airga_ctx ctx = prec->ctx;
+  const Pencil& pen = ctx->pen;
+  if (count < 0 || (count > 0 && (!r || !z))) return fail(AIRGA_EINVAL, "bad vectors");
+  if (count > 65535) return fail(AIRGA_EUNSUPPORTED, "more than 65535 vectors");
+  if (ldr < pen.n || ldz < pen.n) return fail(AIRGA_EINVAL, "leading dimension < n");
+  if (count == 0) return AIRGA_OK;
+  // factors oldest first: P_1, Q_2, ..., Q_z
+  std::vector<airga_prec> all;
+  for (airga_prec q = prec; q; q = q->parent) {
+    AIRGA_TRY(prec_resolve(q));
+    all.push_back(q);
+  }
+  const size_t per = (size_t)pen.n_pad();
+  AIRGA_TRY(ctx->ws_asm.reserve(sizeof(double) * per * 2 * (size_t)count));
+  double* tmp[2] = {ctx->ws_asm.as<double>(), ctx->ws_asm.as<double>() + per * count};
+  const double* src = r;
+  int64_t lds = ldr;
+  dim3 grid(blocks_for(pen.n, 256), (unsigned)count);
+  for (size_t f = all.size(); f-- > 0;) {
+    airga_prec q = all[f];
+    const bool last = f == 0;
+    double* dst = last ? z : tmp[f & 1];
+    const int64_t ldd = last ? ldz : (int64_t)per;
+    if (q->scalar_only)
+      k_factor_apply<<<grid, 256, 0, ctx->stream>>>(pen.dev(), nullptr, q->alpha, src, lds, dst, ldd);
+    else
+      k_factor_apply<<<grid, 256, 0, ctx->stream>>>(pen.dev(), q->v64.as<double>(), 1.0, src, lds,
+                                                    dst, ldd);
+    AIRGA_HIP(hipGetLastError());
+    src = dst;
+    lds = ldd;
+  }
+  return AIRGA_OK;
+}
+
+void airga_prec_release(airga_prec prec) {
+  while (prec) {
+    if (--prec->refs > 0) return;
+    airga_prec parent = prec->parent;
+    airga_ctx ctx = prec->ctx;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->live_precs--;
+    delete prec;
+    prec = parent;
+  }
+}
+
+}  // extern "C"
