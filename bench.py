@@ -157,6 +157,7 @@ def main():
     precs, upd, _, _ = step(profile=True)
     kt2 = ctx.kernel_times()
     kw2 = ctx.kernel_work()
+    tile = ctx.tile_config()
     info = ctx.pencil_info()
 
     # plain float64, one system at a time, same systems and preconditioners
@@ -249,7 +250,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]['desc']}", "n": n,
                    "systems_per_step": 2 * B, "tol_relres": args.tol, "err_tol": ERR_TOL,
-                   "precision": "float32 inner PCG, float64 refinement"},
+                   "precision": "float32 inner PCG, float64 refinement",
+                   "tile": {"rows_per_wave": tile[0], "systems_per_group": tile[1]}},
         "solved_to_1e-8": n_ok, "max_rel_err": max(errs_mixed) if errs_mixed else None,
         "iters_median": statistics.median(iters), "iters_max": max(iters),
         "phases_ms": {"pencil_setup": round(ph[0], 3), "spai_build_total": round(ph[1], 3),

@@ -255,6 +255,12 @@ AIRGA_API const char* airga_kernel_name(int32_t id);
 AIRGA_API airga_status airga_get_kernel_times(airga_ctx ctx, int32_t count, int64_t* launches,
                                     double* total_ms);
 
+/* Tile configuration the autotuner chose for the last solve on this
+ * context: matrix rows per wavefront (a multiple of 64) and systems swept
+ * together per group.  Errors: EINVAL, ESTATE (no solve yet). */
+AIRGA_API airga_status airga_get_tile_config(airga_ctx ctx, int32_t* rows_per_wave,
+                                             int32_t* systems_per_group);
+
 /* Work done by the row kernels of the last profiled solve, for kernel id
  * k < count: sys_passes[k] = (system, launch) pairs swept, shift_passes[k] =
  * (shift, launch) pairs whose first preconditioner factor was read

@@ -103,6 +103,8 @@ _SIGS = [
     ("airga_get_kernel_times", ctypes.c_int, [_P, ctypes.c_int32,
                                               ctypes.POINTER(ctypes.c_int64),
                                               ctypes.POINTER(ctypes.c_double)]),
+    ("airga_get_tile_config", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_int32)]),
     ("airga_get_kernel_work", ctypes.c_int, [_P, ctypes.c_int32,
                                              ctypes.POINTER(ctypes.c_int64),
                                              ctypes.POINTER(ctypes.c_int64)]),
@@ -297,6 +299,12 @@ class Context:
         ms = (ctypes.c_double * k)()
         _check(lib().airga_get_kernel_times(self._h, k, launches, ms))
         return {lib().airga_kernel_name(i).decode(): (launches[i], ms[i]) for i in range(k)}
+
+    def tile_config(self) -> tuple:
+        """(matrix rows per wavefront, systems per group) of the last solve."""
+        r, u = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().airga_get_tile_config(self._h, ctypes.byref(r), ctypes.byref(u)))
+        return r.value, u.value
 
     def kernel_work(self) -> dict:
         """{kernel: (system passes, shift passes)} of the last profiled solve."""

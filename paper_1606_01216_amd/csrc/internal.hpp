@@ -87,7 +87,9 @@ struct Pencil {
   double alpha = 0, beta = 0;
   double gram_mm = 0, gram_mk = 0, gram_kk = 0, tr_m = 0, tr_k = 0;
   bool diag_ok = false;  // M_rr > 0 and K_rr >= 0 for every row
+  bool uniform_width = false;  // every slice is max_len entries wide
   DevBuf slice_ptr, row_len, col, mirror, csr_pos, diag_pos, m64, k64, m32, k32;
+  DevBuf id64, id32;  // the identity on the pattern (solves without a preconditioner)
   PencilDev dev() const;
   int64_t n_pad() const { return (int64_t)n_slices * kSlice; }
 };
@@ -137,9 +139,11 @@ struct airga_ctx_s {
   size_t host_pinned_bytes = 0;
   airga::KernelTimes times;
   std::atomic<int> live_precs{0};
-  // Autotuned rows-per-lane choice, keyed by (n_slices, batch, precision).
-  struct Tune { int32_t n_slices, batch, prec, rows; };
+  // Autotuned tile configuration, keyed by (n_slices, batch, precision and
+  // matrix form, row-length class); ms = the winning timing.
+  struct Tune { int32_t n_slices, batch, prec, wclass, cfg; float ms; };
   std::vector<Tune> tuned;
+  int last_cfg = -1;  // tile configuration of the last solve
 };
 
 struct airga_prec_s {
@@ -192,6 +196,45 @@ __device__ __forceinline__ T wave_max(T v) {
   }
   return v;
 }
+
+// Wavefront-wide sum returned in every lane, built from DPP lane moves (no
+// LDS round trips): four row shifts make each 16-lane row an inclusive scan,
+// two row broadcasts carry the row totals into lane 63, which is then read
+// back as a scalar.  All 64 lanes must be active.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_add(float v) {
+  const int s = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xf, true);
+  return v + __int_as_float(s);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, CTRL, ROWMASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, ROWMASK, 0xf, true);
+  return v + __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane63(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ double lane63(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T>
+__device__ __forceinline__ T wave_total(T v) {
+  v = dpp_add<0x111, 0xf>(v);  // row_shr:1
+  v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+  v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+  v = dpp_add<0x118, 0xf>(v);  // row_shr:8
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return lane63(v);
+}
+
+// Make a wavefront-uniform value scalar (it then lives in an SGPR).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Launch-size helper.
 inline unsigned blocks_for(int64_t work, int per_block) {

@@ -1,0 +1,487 @@
+// Row kernels of the batched PCG (templates; instantiated per precision in
+// pcg_sets_f32.hip and pcg_sets_f64.hip).
+//
+// Data layout.  Matrices are in the pencil's sliced-ELL form (64-row slices,
+// one row per lane).  Every per-system vector is contiguous (length n_pad),
+// kind-major: vec(kind, b) = ws + (kind * B + b) * n_pad; rows past n are
+// padding and hold zeros, so the row kernels need no per-lane bounds test.
+// A wavefront owns R consecutive slices; it loads their column indices and
+// M, K (or factor) values once into registers and then sweeps the active
+// systems in groups of U, issuing every load of a group before its first
+// store, so the pencil is read once per kernel for the whole batch and each
+// wavefront keeps U systems' traffic in flight.  The shifted matrix is never
+// stored: K(s_k) p = a_k (M p) + b_k (K p).
+//
+// One CG iteration is two row kernels and two tiny reductions:
+//   A  p_new = z + beta p_old;  w = K(s) p_new;  partial (p_new, w)
+//   reduce -> alpha = (r, z) / (p, w)
+//   B  r_new = r - alpha w;  x += alpha p_new;  t = P_1 r_new;  partials of
+//      (r_new, r_new), (r_new, z), (z, w)      [z = t for a one-factor chain]
+//   [chain: z = Q_c ... Q_2 t, one kernel per further factor]
+//   reduce -> convergence; beta = -(z, w) / (p, w)
+// Neighbour values (p_new at a column, r_new at a column) are recomputed from
+// the previous iterate instead of being exchanged: p and r are double
+// buffered, so no kernel reads what another block of the same kernel writes.
+// The direction update keeps p_new K-conjugate to p_old, which needs no
+// symmetry of the preconditioner (a fixed-pattern right SPAI and every update
+// chain are non-symmetric); for a symmetric preconditioner it is the
+// classical CG ratio.
+#pragma once
+
+#include "internal.hpp"
+
+namespace airga {
+
+enum VecKind { KX = 0, KR0, KR1, KZ, KP0, KP1, KW, KT, KINDS };
+constexpr int kSlots = 4;  // partial slots per (system, wave): pw | rr, rz, zw
+enum { ST_CONV = AIRGA_SYS_CONVERGED, ST_MAXIT = AIRGA_SYS_MAXIT,
+       ST_BREAK = AIRGA_SYS_BREAKDOWN, ST_NONFIN = AIRGA_SYS_NONFINITE };
+
+// Per-system device state.
+struct SysDev {
+  double *rz, *pw, *alpha, *beta, *tol2, *ff, *relres;
+  int32_t *active, *first, *istat, *status, *iters, *sweeps, *outer;
+  int32_t* list;  // active systems in ascending order (compacted after each reduction)
+  int32_t* nact;  // [0] = active count, [1] = arrival counter of the reduction blocks
+};
+
+template <typename T>
+struct SolveArgs {
+  PencilDev pd;
+  const T* mv;               // M values in T (or the assembled K(s) when kv == nullptr)
+  const T* kv;               // K values in T
+  int32_t B, m, nshift, G;
+  int64_t ld;                // n_pad
+  T* ws;                     // vector workspace (the iterate x is kind KX)
+  const T* ca;               // per shift a_k = s_k^2 + alpha s_k
+  const T* cb;               // per shift b_k = 1 + beta s_k
+  const T* const* fac;       // per shift [maxc] factor values, fac[sh * maxc + q], oldest first
+  const int32_t* clen;       // per shift number of applied factors
+  int32_t maxc;
+  double* partial;           // [B][G][kSlots]
+  SysDev sys;
+  __device__ __forceinline__ T* vec(int kind, int b) const {
+    return ws + ((int64_t)kind * B + b) * ld;
+  }
+  __device__ __forceinline__ double* slot(int b, int g) const {
+    return partial + ((int64_t)b * G + g) * kSlots;
+  }
+};
+
+// Buffer written by chain position q (0 = the fused first factor) for a chain
+// of L factors: the last one lands in KZ, earlier ones alternate with KT.
+__device__ __forceinline__ int chain_dst(int q, int L) { return ((L - 1 - q) & 1) ? KT : KZ; }
+
+// Row set of one wavefront: R consecutive slices.  Slice data are uniform
+// across the wavefront (scalar loads).  Entries past a slice's width get the
+// row itself as column and value 0, so every loop runs WMAX entries with no
+// test; EXACT marks pencils whose slices are all WMAX wide.
+template <int WMAX, int R, bool EXACT>
+struct Rows {
+  int32_t col[R][WMAX];
+  int32_t idx0[R];
+  int32_t w[R];
+  bool valid[R];
+  int64_t row[R];
+  __device__ __forceinline__ void load(const PencilDev& pd, int wg, int lane) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int s = wg * R + i;
+      valid[i] = s < pd.n_slices;
+      // a slice past the end aliases row `lane` of slice 0: its loads stay in
+      // bounds and its results are never stored
+      row[i] = valid[i] ? (int64_t)s * kSlice + lane : lane;
+      w[i] = 0;
+      idx0[i] = 0;
+      if (valid[i]) {
+        const int sp0 = pd.slice_ptr[s];
+        w[i] = EXACT ? WMAX : (pd.slice_ptr[s + 1] - sp0) / kSlice;
+        idx0[i] = sp0 + lane;
+      }
+#pragma unroll
+      for (int k = 0; k < WMAX; ++k)
+        col[i][k] = (valid[i] && (EXACT || k < w[i])) ? pd.col[idx0[i] + k * kSlice] : (int32_t)row[i];
+    }
+  }
+  template <typename T>
+  __device__ __forceinline__ void values(const T* __restrict__ v, T (&out)[R][WMAX]) const {
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+      for (int k = 0; k < WMAX; ++k)
+        out[i][k] = (valid[i] && (EXACT || k < w[i])) ? v[idx0[i] + k * kSlice] : T(0);
+  }
+};
+
+// Systems of the next group: list[j0 + u] or -1 past the active count.
+template <int U>
+__device__ __forceinline__ void group_of(const int32_t* __restrict__ list, int j0, int nact,
+                                         int (&bs)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) bs[u] = (j0 + u < nact) ? list[j0 + u] : -1;
+}
+
+// ---- A: direction update + shifted SpMV + (p, w) -------------------------
+template <typename T, int WMAX, int R, int U, bool ASM, bool EXACT>
+__global__ void __launch_bounds__(256) k_dir_spmv(SolveArgs<T> A, int par) {
+  const int lane = threadIdx.x & 63;
+  const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wg >= A.G) return;
+  Rows<WMAX, R, EXACT> rows;
+  rows.load(A.pd, wg, lane);
+  T mv[R][WMAX], kv[R][WMAX];
+  rows.values(A.mv, mv);
+  if constexpr (!ASM) rows.values(A.kv, kv);
+  const int nact = A.sys.nact[0];
+  for (int j0 = 0; j0 < nact; j0 += U) {
+    int bs[U];
+    group_of<U>(A.sys.list, j0, nact, bs);
+    T pr[U][R], wr[U][R];
+    // compute phase: no branches, so every load of the group can be in
+    // flight at once (a missing system aliases the group's first one)
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = bs[u] >= 0 ? bs[u] : bs[0];
+      const bool first = A.sys.first[b] != 0;
+      const T beta = first ? T(0) : (T)A.sys.beta[b];
+      T ca = T(1), cb = T(0);
+      if constexpr (!ASM) {
+        ca = A.ca[b / A.m];
+        cb = A.cb[b / A.m];
+      }
+      const T* __restrict__ z = A.vec(KZ, b);
+      const T* __restrict__ pin = A.vec(KP0 + par, b);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        T am = T(0), ak = T(0);
+#pragma unroll
+        for (int k = 0; k < WMAX; ++k) {
+          const int c = rows.col[i][k];
+          const T po = pin[c];
+          const T pc = fma(beta, first ? T(0) : po, z[c]);
+          am = fma(mv[i][k], pc, am);
+          if constexpr (!ASM) ak = fma(kv[i][k], pc, ak);
+        }
+        const int64_t r = rows.row[i];
+        const T po = pin[r];
+        pr[u][i] = fma(beta, first ? T(0) : po, z[r]);
+        wr[u][i] = ASM ? am : fma(ca, am, cb * ak);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = bs[u];
+      if (b < 0) continue;
+      T* __restrict__ pout = A.vec(KP0 + (par ^ 1), b);
+      T* __restrict__ wv = A.vec(KW, b);
+      T dot = T(0);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        if (!rows.valid[i]) continue;
+        const int64_t r = rows.row[i];
+        pout[r] = pr[u][i];
+        wv[r] = wr[u][i];
+        dot = fma(pr[u][i], wr[u][i], dot);
+      }
+      dot = wave_total(dot);
+      if (lane == 0) A.slot(b, wg)[0] = (double)dot;
+    }
+  }
+}
+
+// ---- B: x/r update + first preconditioner factor + dots -------------------
+// INIT: no update; r is R0 as produced by the residual kernel.
+template <typename T, int WMAX, int R, int U, bool INIT, bool EXACT>
+__global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
+  const int lane = threadIdx.x & 63;
+  const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wg >= A.G) return;
+  Rows<WMAX, R, EXACT> rows;
+  rows.load(A.pd, wg, lane);
+  const int nact = A.sys.nact[0];
+  for (int j0 = 0; j0 < nact; j0 += U) {
+    int bs[U];
+    group_of<U>(A.sys.list, j0, nact, bs);
+    // compute phase: no branches, so every load of the group can be in
+    // flight at once (a missing system aliases the group's first one).  Each
+    // system's first preconditioner factor is loaded (systems of one shift
+    // hit the same cache lines); a missing preconditioner is an identity
+    // factor supplied by the host.
+    T pv[U][R][WMAX];
+    int Ls[U];
+    T rn[U][R], tz[U][R], xn[U][R], wrr[U][R];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = bs[u] >= 0 ? bs[u] : bs[0];
+      const int sh = b / A.m;
+      Ls[u] = A.clen[sh];
+      rows.values(A.fac[(int64_t)sh * A.maxc], pv[u]);
+      const T al = INIT ? T(0) : (T)A.sys.alpha[b];
+      const T* __restrict__ rin = A.vec(INIT ? KR0 : KR0 + par, b);
+      const T* __restrict__ wv = A.vec(KW, b);
+      const T* __restrict__ pcur = A.vec(KP0 + (par ^ 1), b);
+      const T* __restrict__ x = A.vec(KX, b);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int64_t r = rows.row[i];
+        T wr = T(0), v;
+        if constexpr (INIT) {
+          v = rin[r];
+        } else {
+          wr = wv[r];
+          v = fma(-al, wr, rin[r]);
+          xn[u][i] = fma(al, pcur[r], x[r]);
+        }
+        T t = T(0);
+#pragma unroll
+        for (int k = 0; k < WMAX; ++k) {
+          const int cc = rows.col[i][k];
+          const T rc = INIT ? rin[cc] : fma(-al, wv[cc], rin[cc]);
+          t = fma(pv[u][i][k], rc, t);
+        }
+        rn[u][i] = v;
+        tz[u][i] = t;
+        wrr[u][i] = wr;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = bs[u];
+      if (b < 0) continue;
+      const int L = Ls[u];
+      T* __restrict__ rout = A.vec(KR0 + (par ^ 1), b);
+      T* __restrict__ zo = A.vec(chain_dst(0, L), b);
+      T* __restrict__ x = A.vec(KX, b);
+      T rr = T(0), rz = T(0), zw = T(0);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        if (!rows.valid[i]) continue;
+        const int64_t r = rows.row[i];
+        if constexpr (!INIT) {
+          x[r] = xn[u][i];
+          rout[r] = rn[u][i];
+        }
+        zo[r] = tz[u][i];
+        rr = fma(rn[u][i], rn[u][i], rr);
+        rz = fma(rn[u][i], tz[u][i], rz);
+        zw = fma(tz[u][i], wrr[u][i], zw);
+      }
+      rr = wave_total(rr);
+      rz = wave_total(rz);
+      zw = wave_total(zw);
+      if (lane == 0) {
+        double* s = A.slot(b, wg);
+        s[1] = (double)rr;
+        s[2] = L > 1 ? 0.0 : (double)rz;
+        s[3] = L > 1 ? 0.0 : (double)zw;
+      }
+    }
+  }
+}
+
+// ---- chain factor q >= 1 (Q_{q+1} of the update chain) ---------------------
+template <typename T, int WMAX, int R, bool EXACT>
+__global__ void __launch_bounds__(256) k_chain(SolveArgs<T> A, int par, int q, int init) {
+  const int lane = threadIdx.x & 63;
+  const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wg >= A.G) return;
+  Rows<WMAX, R, EXACT> rows;
+  rows.load(A.pd, wg, lane);
+  const int rk = init ? KR0 : KR0 + (par ^ 1);
+  const int nact = A.sys.nact[0];
+  int loaded_sh = -1;
+  T fv[R][WMAX];
+  for (int j = 0; j < nact; ++j) {
+    const int b = A.sys.list[j];
+    const int sh = b / A.m;
+    const int L = A.clen[sh];
+    if (L <= q) continue;
+    if (sh != loaded_sh) {
+      rows.values(A.fac[(int64_t)sh * A.maxc + q], fv);
+      loaded_sh = sh;
+    }
+    const T* __restrict__ src = A.vec(chain_dst(q - 1, L), b);
+    T* __restrict__ dst = A.vec(chain_dst(q, L), b);
+    const bool last = q == L - 1;
+    const T* __restrict__ rv = A.vec(rk, b);
+    const T* __restrict__ wv = A.vec(KW, b);
+    T rz = T(0), zw = T(0);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if (!rows.valid[i]) continue;
+      const int64_t r = rows.row[i];
+      T t = T(0);
+#pragma unroll
+      for (int k = 0; k < WMAX; ++k) t = fma(fv[i][k], src[rows.col[i][k]], t);
+      dst[r] = t;
+      if (last) {
+        rz = fma(rv[r], t, rz);
+        if (!init) zw = fma(t, wv[r], zw);
+      }
+    }
+    if (last) {
+      rz = wave_total(rz);
+      zw = wave_total(zw);
+      if (lane == 0) {
+        double* s = A.slot(b, wg);
+        s[2] = (double)rz;
+        s[3] = (double)zw;
+      }
+    }
+  }
+}
+
+// ---- float64 residual r = F - K(s) X (and |F|^2), output in TO -------------
+//   xread: 1 = use X, 0 = take X as 0;   xzero: write zeros into X;
+//   kx:    0 = leave the iterate, 1 = zero it, 2 = copy X into it.
+// Rows past n write zeros.  Systems: those with outer[b] set.
+template <typename TO, int WMAX, int R, int U, bool EXACT>
+__global__ void __launch_bounds__(256) k_residual(SolveArgs<TO> A, const double* __restrict__ F,
+                                                  int64_t ldf, double* __restrict__ X,
+                                                  int64_t ldX, const double* __restrict__ ca64,
+                                                  const double* __restrict__ cb64, int xread,
+                                                  int xzero, int kx) {
+  const int lane = threadIdx.x & 63;
+  const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wg >= A.G) return;
+  Rows<WMAX, R, EXACT> rows;
+  rows.load(A.pd, wg, lane);
+  double mv[R][WMAX], kv[R][WMAX];
+  rows.values(A.pd.m64, mv);
+  rows.values(A.pd.k64, kv);
+  const int64_t n = A.pd.n;
+  for (int b0 = 0; b0 < A.B; b0 += U) {
+    int bs[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) bs[u] = (b0 + u < A.B && A.sys.outer[b0 + u]) ? b0 + u : -1;
+    double res[U][R], fr[U][R], xo[U][R];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = bs[u];
+      if (b < 0) continue;
+      const double a = ca64[b / A.m], cbv = cb64[b / A.m];
+      const double* __restrict__ f = F + (int64_t)(b % A.m) * ldf;
+      const double* __restrict__ x = X + (int64_t)b * ldX;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        res[u][i] = 0.0;
+        fr[u][i] = 0.0;
+        xo[u][i] = 0.0;
+        const int64_t row = rows.row[i];
+        if (rows.valid[i] && row < n) {
+          double am = 0, ak = 0;
+          if (xread) {
+#pragma unroll
+            for (int k = 0; k < WMAX; ++k) {
+              const double xc = x[rows.col[i][k]];
+              am = fma(mv[i][k], xc, am);
+              ak = fma(kv[i][k], xc, ak);
+            }
+            xo[u][i] = x[row];
+          }
+          fr[u][i] = f[row];
+          res[u][i] = fr[u][i] - fma(a, am, cbv * ak);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = bs[u];
+      if (b < 0) continue;
+      TO* __restrict__ r = A.vec(KR0, b);
+      TO* __restrict__ xi = A.vec(KX, b);
+      double* __restrict__ x = X + (int64_t)b * ldX;
+      double rr = 0, ff = 0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        if (!rows.valid[i]) continue;
+        const int64_t row = rows.row[i];
+        r[row] = (TO)res[u][i];
+        if (kx == 1) xi[row] = TO(0);
+        if (kx == 2) xi[row] = (TO)xo[u][i];
+        if (xzero && row < n) x[row] = 0.0;
+        rr = fma(res[u][i], res[u][i], rr);
+        ff = fma(fr[u][i], fr[u][i], ff);
+      }
+      rr = wave_total(rr);
+      ff = wave_total(ff);
+      if (lane == 0) {
+        double* s = A.slot(b, wg);
+        s[0] = rr;
+        s[1] = ff;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- dispatch
+
+template <typename T>
+struct KernelSet {
+  void (*dir)(SolveArgs<T>, int);
+  void (*dir_asm)(SolveArgs<T>, int);
+  void (*upd)(SolveArgs<T>, int);
+  void (*init)(SolveArgs<T>, int);
+  void (*chain)(SolveArgs<T>, int, int, int);
+  void (*resid)(SolveArgs<T>, const double*, int64_t, double*, int64_t, const double*,
+                const double*, int, int, int);
+};
+
+template <typename T, int WMAX, int R, int U, bool EXACT>
+KernelSet<T> make_set() {
+  KernelSet<T> s;
+  s.dir = k_dir_spmv<T, WMAX, R, U, false, EXACT>;
+  s.dir_asm = k_dir_spmv<T, WMAX, R, U, true, EXACT>;
+  s.upd = k_update_prec<T, WMAX, R, U, false, EXACT>;
+  s.init = k_update_prec<T, WMAX, R, U, true, EXACT>;
+  s.chain = k_chain<T, WMAX, R, EXACT>;
+  s.resid = k_residual<T, WMAX, R, U, EXACT>;
+  return s;
+}
+
+// Tile configurations (rows-of-64 slices per wavefront R, systems per group U)
+// the autotuner chooses from.  Rows of up to 16 entries use the small ones only.
+struct TileCfg { int rows, sys; };
+constexpr TileCfg kCfgs[] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}, {2, 2}, {2, 4}, {4, 1}};
+constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
+inline bool cfg_allowed(int wclass, int c) { return wclass < 2 || kCfgs[c].rows * kCfgs[c].sys <= 2; }
+
+// Row-length classes: rows of <= 6, <= 8, <= 16 entries.
+inline int wmax_class(int max_len) { return max_len <= 6 ? 0 : max_len <= 8 ? 1 : 2; }
+inline int wmax_of(int wclass) { return wclass == 0 ? 6 : wclass == 1 ? 8 : 16; }
+
+template <typename T, int WMAX, bool EXACT>
+KernelSet<T> set_for(int c) {
+  switch (c) {
+    case 0: return make_set<T, WMAX, 1, 1, EXACT>();
+    case 1: return make_set<T, WMAX, 1, 2, EXACT>();
+    case 2: return make_set<T, WMAX, 1, 4, EXACT>();
+    case 3: return make_set<T, WMAX, 2, 1, EXACT>();
+    case 4: return make_set<T, WMAX, 2, 2, EXACT>();
+    case 5: return make_set<T, WMAX, 2, 4, EXACT>();
+    default: return make_set<T, WMAX, 4, 1, EXACT>();
+  }
+}
+
+template <typename T>
+KernelSet<T> kernel_set_impl(int wclass, bool exact, int c) {
+  if (wclass == 0) return exact ? set_for<T, 6, true>(c) : set_for<T, 6, false>(c);
+  if (wclass == 1) return exact ? set_for<T, 8, true>(c) : set_for<T, 8, false>(c);
+  switch (c) {
+    case 1: return make_set<T, 16, 1, 2, false>();
+    case 3: return make_set<T, 16, 2, 1, false>();
+    default: return make_set<T, 16, 1, 1, false>();
+  }
+}
+
+// Defined in pcg_sets_f32.hip / pcg_sets_f64.hip.
+KernelSet<float> kernel_set_f32(int wclass, bool exact, int cfg);
+KernelSet<double> kernel_set_f64(int wclass, bool exact, int cfg);
+
+template <typename T>
+inline KernelSet<T> kernel_set(int wclass, bool exact, int cfg) {
+  if constexpr (sizeof(T) == 4) return kernel_set_f32(wclass, exact, cfg);
+  else return kernel_set_f64(wclass, exact, cfg);
+}
+
+}  // namespace airga

@@ -322,6 +322,23 @@ __global__ void k_sum_gram(const double* __restrict__ part, int64_t nb, double* 
   if (t < kGram) out[t] = red[t][0];
 }
 
+// The identity on the stored pattern: 1 at each diagonal entry, 0 elsewhere.
+__global__ void k_identity(PencilDev pd, int64_t n_pad, double* __restrict__ v64,
+                           float* __restrict__ v32) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= n_pad) return;
+  const int64_t s = r / kSlice;
+  const int32_t base = pd.slice_ptr[s] + (int32_t)(r % kSlice);
+  const int w = (pd.slice_ptr[s + 1] - pd.slice_ptr[s]) / kSlice;
+  const int len = pd.row_len[r];
+  for (int k = 0; k < w; ++k) {
+    const int32_t idx = base + k * kSlice;
+    const double v = (k < len && pd.col[idx] == r) ? 1.0 : 0.0;
+    v64[idx] = v;
+    v32[idx] = (float)v;
+  }
+}
+
 __global__ void k_assemble(PencilDev pd, int64_t stored, double a, double b,
                            double* __restrict__ out) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -431,10 +448,16 @@ static airga_status set_pencil_impl(airga_ctx ctx, int32_t n, int64_t nnz, const
   pen.n_slices = ns;
   pen.nnz = nnz;
   pen.nnz_stored = stored;
+  pen.uniform_width = stored == (int64_t)ns * kSlice * h.maxlen;
   pen.max_len = h.maxlen;
   pen.bandwidth = h.bw;
   pen.alpha = alpha;
   pen.beta = beta;
+  AIRGA_TRY(pen.id64.reserve(sizeof(double) * stored));
+  AIRGA_TRY(pen.id32.reserve(sizeof(float) * stored));
+  k_identity<<<blocks_for(n_pad, 256), 256, 0, st>>>(pen.dev(), n_pad, pen.id64.as<double>(),
+                                                     pen.id32.as<float>());
+  AIRGA_HIP(hipGetLastError());
   // Gram scalars
   const unsigned nb = blocks_for(n, 256);
   DevBuf gp;
