@@ -50,6 +50,18 @@ struct DevBuf {
   size_t bytes = 0;
   airga_status reserve(size_t need);
   void release();
+  // hand the allocation over (to a pool) / take one over (from a pool)
+  void detach(void** p, size_t* b) {
+    *p = ptr;
+    *b = bytes;
+    ptr = nullptr;
+    bytes = 0;
+  }
+  void adopt(void* p, size_t b) {
+    release();
+    ptr = p;
+    bytes = b;
+  }
   template <typename T>
   T* as() const { return static_cast<T*>(ptr); }
   ~DevBuf() { release(); }
@@ -144,6 +156,18 @@ struct airga_ctx_s {
   struct Tune { int32_t n_slices, batch, prec, wclass, cfg; float ms; };
   std::vector<Tune> tuned;
   int last_cfg = -1;  // tile configuration of the last solve
+  // Device buffers of released preconditioners, reused by later ones.  All
+  // work of a context is ordered on one stream, so a buffer handed back here
+  // can be reused by later work without waiting for earlier kernels.
+  std::vector<std::pair<void*, size_t>> pool;
+  // The last captured iteration graph and the launch arguments it was
+  // captured with; replayed as long as a sweep's arguments are identical.
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<char> graph_key;
+  ~airga_ctx_s() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    for (auto& b : pool) (void)hipFree(b.first);
+  }
 };
 
 struct airga_prec_s {
@@ -167,8 +191,13 @@ airga_status check_ctx(airga_ctx ctx);
 airga_status check_pencil(airga_ctx ctx);
 airga_status ensure_pinned(airga_ctx ctx, size_t bytes);
 
-// Resolve the lazy host-side facts of an update factor (synchronises).
+// Resolve the lazy host-side facts of update factors (one synchronisation
+// for the whole set).
 airga_status prec_resolve(airga_prec p);
+airga_status prec_resolve_many(airga_ctx ctx, const std::vector<airga_prec>& ps);
+// Device buffers from the context's pool (or fresh).
+airga_status pool_get(airga_ctx ctx, DevBuf* buf, size_t need);
+void pool_put(airga_ctx ctx, DevBuf* buf);
 // Non-scalar factors of the chain, newest first.
 airga_status prec_chain(airga_prec p, std::vector<airga_prec>* out);
 

@@ -6,8 +6,8 @@
 // pcg_kernels.hpp.
 //
 // Reductions are deterministic: one partial per (system, wavefront) and a
-// fixed-order sum per system.  The last reduction block to finish compacts
-// the list of still-active systems, which the next row kernels sweep.
+// fixed-order sum per system.  The row kernels sweep the systems whose
+// active flag is set.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -25,10 +25,11 @@ enum ReduceMode {
   RM_START = 4,     // after the float64 residual: record |F|^2 (FP64 mode)
   RM_OUTER = 5,     // after the float64 residual: refinement control (MIXED)
   RM_FINAL = 6,     // after the final float64 residual: relres only
+  RM_NONE = 7,      // sums only, no state change (autotuner timing)
 };
 
 struct ReduceArgs {
-  const double* partial;
+  const double* partial;  // [kSlots][B][G]
   int32_t G;
   int32_t B;
   SysDev sys;
@@ -38,124 +39,106 @@ struct ReduceArgs {
   double tol2_abs;  // tol^2 for RM_OUTER
 };
 
-__device__ __forceinline__ int load_flag(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__global__ void __launch_bounds__(256) k_reduce(ReduceArgs P, int mode) {
-  __shared__ double red[4][256];
-  __shared__ int sc[256];
-  __shared__ int is_last;
+// One block of NT threads per system: a fixed-order sum of the system's wave
+// partials (per thread, then across the wave, then across the waves), then
+// the mode's logic.  Blocks never communicate: the row kernels read the
+// active flags themselves, and the host's count of active systems is kept
+// by atomic increments of nact.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_reduce(ReduceArgs P, int mode) {
+  __shared__ double red[NT / 64][4];
   const int b = blockIdx.x;
   const int t = threadIdx.x;
-  const SysDev& S = P.sys;
+  const SysDev& Sy = P.sys;
   const bool use_outer = mode == RM_START || mode == RM_OUTER || mode == RM_FINAL;
-  const bool on = use_outer ? S.outer[b] != 0 : S.active[b] != 0;
-  if (on) {
-    double v[4] = {0, 0, 0, 0};
-    const double* base = P.partial + (int64_t)b * P.G * kSlots;
-    for (int g = t; g < P.G; g += blockDim.x)
+  if ((use_outer ? Sy.outer[b] : Sy.active[b]) == 0) return;
+  // partial slots this mode uses
+  const int q0 = (mode == RM_PW || use_outer || mode == RM_NONE) ? 0 : 1;
+  const int q1 = mode == RM_PW ? 0 : use_outer ? 1 : (mode == RM_ITER || mode == RM_NONE) ? 3 : 2;
+  double v[4] = {0, 0, 0, 0};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] += base[(int64_t)g * kSlots + q];
+  for (int q = 0; q < 4; ++q) {
+    if (q < q0 || q > q1) continue;
+    const double* __restrict__ base = P.partial + ((int64_t)q * P.B + b) * P.G;
+    double acc = 0.0;
+    for (int g = t; g < P.G; g += NT) acc += base[g];
+    v[q] = wave_total(acc);
+  }
+  if ((t & 63) == 0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) red[q][t] = v[q];
-    __syncthreads();
-    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-      if (t < h)
+    for (int q = 0; q < 4; ++q) red[t >> 6][q] = v[q];
+  }
+  __syncthreads();
+  if (t != 0) return;
+  double s4[4] = {0, 0, 0, 0};
+  for (int w = 0; w < NT / 64; ++w)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) red[q][t] += red[q][t + h];
-      __syncthreads();
+    for (int q = 0; q < 4; ++q) s4[q] += red[w][q];
+  const double s0 = s4[0], s1 = s4[1], rz = s4[2], zw = s4[3];
+  const int was_active = Sy.active[b];
+  int act = was_active;
+  switch (mode) {
+    case RM_PW: {
+      if (!isfinite(s0)) { Sy.istat[b] = ST_NONFIN; act = 0; }
+      else if (s0 <= 0.0) { Sy.istat[b] = ST_BREAK; act = 0; }
+      else { Sy.pw[b] = s0; Sy.alpha[b] = Sy.rz[b] / s0; }
+      break;
     }
-    if (t == 0) {
-      const double s0 = red[0][0], s1 = red[1][0], rz = red[2][0], zw = red[3][0];
-      switch (mode) {
-        case RM_PW: {
-          if (!isfinite(s0)) { S.istat[b] = ST_NONFIN; S.active[b] = 0; }
-          else if (s0 <= 0.0) { S.istat[b] = ST_BREAK; S.active[b] = 0; }
-          else { S.pw[b] = s0; S.alpha[b] = S.rz[b] / s0; }
-          break;
-        }
-        case RM_ITER: {
-          const int it = S.iters[b] + 1;
-          S.iters[b] = it;
-          if (!isfinite(s1) || !isfinite(rz) || !isfinite(zw)) { S.istat[b] = ST_NONFIN; S.active[b] = 0; }
-          else if (s1 <= S.tol2[b]) { S.istat[b] = ST_CONV; S.active[b] = 0; }
-          else if (it >= P.max_iter) { S.istat[b] = ST_MAXIT; S.active[b] = 0; }
-          else { S.beta[b] = -zw / S.pw[b]; S.rz[b] = rz; S.first[b] = 0; }
-          break;
-        }
-        case RM_INIT_ABS:
-        case RM_INIT_REL: {
-          if (mode == RM_INIT_REL) S.tol2[b] = P.tol2_rel * s1;
-          S.first[b] = 1;
-          S.beta[b] = 0.0;
-          if (!isfinite(s1) || !isfinite(rz)) { S.istat[b] = ST_NONFIN; S.active[b] = 0; }
-          else if (s1 <= S.tol2[b]) { S.istat[b] = ST_CONV; S.active[b] = 0; }
-          else if (S.iters[b] >= P.max_iter) { S.istat[b] = ST_MAXIT; S.active[b] = 0; }
-          else { S.rz[b] = rz; S.istat[b] = ST_MAXIT; }
-          break;
-        }
-        case RM_START: {
-          // residual kernel slots: 0 = |F - K X|^2, 1 = |F|^2
-          S.ff[b] = s1;
-          S.tol2[b] = P.tol2_rel * s1;
-          S.relres[b] = s1 > 0 ? sqrt(s0 / s1) : 0.0;
-          break;
-        }
-        case RM_OUTER: {
-          if (S.sweeps[b] == 0) S.ff[b] = s1;
-          const double ff = S.ff[b];
-          S.relres[b] = ff > 0 ? sqrt(s0 / ff) : 0.0;
-          if (!isfinite(s0)) { S.status[b] = ST_NONFIN; S.outer[b] = 0; }
-          else if (s0 <= P.tol2_abs * ff) { S.status[b] = ST_CONV; S.outer[b] = 0; }
-          else if (S.sweeps[b] > 0 && (S.istat[b] == ST_BREAK || S.istat[b] == ST_NONFIN)) {
-            S.status[b] = S.istat[b]; S.outer[b] = 0;
-          } else if (S.iters[b] >= P.max_iter || S.sweeps[b] >= P.max_sweeps) {
-            S.status[b] = ST_MAXIT; S.outer[b] = 0;
-          } else {
-            S.active[b] = 1;
-          }
-          break;
-        }
-        case RM_FINAL: {
-          const double ff = S.ff[b];
-          S.relres[b] = ff > 0 ? sqrt(s0 / ff) : 0.0;
-          break;
-        }
+    case RM_ITER: {
+      const int it = Sy.iters[b] + 1;
+      Sy.iters[b] = it;
+      if (!isfinite(s1) || !isfinite(rz) || !isfinite(zw)) { Sy.istat[b] = ST_NONFIN; act = 0; }
+      else if (s1 <= Sy.tol2[b]) { Sy.istat[b] = ST_CONV; act = 0; }
+      else if (it >= P.max_iter) { Sy.istat[b] = ST_MAXIT; act = 0; }
+      else { Sy.beta[b] = -zw / Sy.pw[b]; Sy.rz[b] = rz; Sy.first[b] = 0; }
+      break;
+    }
+    case RM_INIT_ABS:
+    case RM_INIT_REL: {
+      if (mode == RM_INIT_REL) Sy.tol2[b] = P.tol2_rel * s1;
+      Sy.first[b] = 1;
+      Sy.beta[b] = 0.0;
+      if (!isfinite(s1) || !isfinite(rz)) { Sy.istat[b] = ST_NONFIN; act = 0; }
+      else if (s1 <= Sy.tol2[b]) { Sy.istat[b] = ST_CONV; act = 0; }
+      else if (Sy.iters[b] >= P.max_iter) { Sy.istat[b] = ST_MAXIT; act = 0; }
+      else { Sy.rz[b] = rz; Sy.istat[b] = ST_MAXIT; }
+      break;
+    }
+    case RM_START: {
+      // residual kernel slots: 0 = |F - K X|^2, 1 = |F|^2
+      Sy.ff[b] = s1;
+      Sy.tol2[b] = P.tol2_rel * s1;
+      Sy.relres[b] = s1 > 0 ? sqrt(s0 / s1) : 0.0;
+      break;
+    }
+    case RM_OUTER: {
+      if (Sy.sweeps[b] == 0) Sy.ff[b] = s1;
+      const double ff = Sy.ff[b];
+      Sy.relres[b] = ff > 0 ? sqrt(s0 / ff) : 0.0;
+      if (!isfinite(s0)) { Sy.status[b] = ST_NONFIN; Sy.outer[b] = 0; }
+      else if (s0 <= P.tol2_abs * ff) { Sy.status[b] = ST_CONV; Sy.outer[b] = 0; }
+      else if (Sy.sweeps[b] > 0 && (Sy.istat[b] == ST_BREAK || Sy.istat[b] == ST_NONFIN)) {
+        Sy.status[b] = Sy.istat[b]; Sy.outer[b] = 0;
+      } else if (Sy.iters[b] >= P.max_iter || Sy.sweeps[b] >= P.max_sweeps) {
+        Sy.status[b] = ST_MAXIT; Sy.outer[b] = 0;
+      } else {
+        act = 1;
       }
+      break;
+    }
+    case RM_FINAL: {
+      const double ff = Sy.ff[b];
+      Sy.relres[b] = ff > 0 ? sqrt(s0 / ff) : 0.0;
+      break;
     }
   }
-  // The last block to arrive rebuilds the active list (ascending order).
-  if (t == 0) {
-    __threadfence();
-    is_last = atomicAdd(&S.nact[1], 1) == (int)gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  const int per = (P.B + 255) / 256;
-  const int lo = t * per;
-  const int hi = lo + per < P.B ? lo + per : P.B;
-  int cnt = 0;
-  for (int i = lo; i < hi; ++i) cnt += load_flag(&S.active[i]) != 0;
-  sc[t] = cnt;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const int v = t >= off ? sc[t - off] : 0;
-    __syncthreads();
-    sc[t] += v;
-    __syncthreads();
-  }
-  int pos = sc[t] - cnt;
-  for (int i = lo; i < hi; ++i)
-    if (load_flag(&S.active[i]) != 0) S.list[pos++] = i;
-  if (t == 255) {
-    S.nact[0] = sc[255];
-    S.nact[1] = 0;
+  if (act != was_active) {
+    Sy.active[b] = act;
+    atomicAdd(Sy.nact, act - was_active);
   }
 }
 
-// Fresh per-system state: every system active and outer-active, list 0..B-1.
+// Fresh per-system state: every system active and outer-active.
 __global__ void k_init_state(SysDev S, int B) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < B) {
@@ -163,12 +146,15 @@ __global__ void k_init_state(SysDev S, int B) {
     S.outer[b] = 1;
     S.istat[b] = ST_MAXIT;
     S.status[b] = ST_MAXIT;
-    S.list[b] = b;
   }
-  if (b == 0) {
-    S.nact[0] = B;
-    S.nact[1] = 0;
-  }
+  if (b == 0) S.nact[0] = B;
+}
+
+// No system inner-active (before a refinement reduction activates some).
+__global__ void k_clear_active(SysDev S, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) S.active[b] = 0;
+  if (b == 0) S.nact[0] = 0;
 }
 
 // Zero the padding rows [n, n_pad) of every workspace vector.
@@ -266,11 +252,21 @@ struct Plan {
   KernelSet<T> ks{};
   bool asm_path = false;
   unsigned grid = 0;
+  bool wide_reduce = false;  // 1024-thread reduction blocks (small batches)
   int cfg = 0;            // tile configuration (index into kCfgs)
   int max_chain_q = 0;    // largest chain length over shifts
   std::vector<int> clen;  // host copy
   size_t flags_off = 0;   // offset of the host flag arrays in the pinned buffer
 };
+
+// One reduction block per system.
+template <typename T>
+static void reduce(const Plan<T>& P, int mode) {
+  if (P.wide_reduce)
+    k_reduce<1024><<<(unsigned)P.a.B, 1024, 0, P.ctx->stream>>>(P.red, mode);
+  else
+    k_reduce<256><<<(unsigned)P.a.B, 256, 0, P.ctx->stream>>>(P.red, mode);
+}
 
 // Profiled solves only: count the systems and shifts the next row kernels
 // sweep (synchronises; kernel durations are unaffected).
@@ -307,11 +303,11 @@ static airga_status iteration(Plan<T>& P, Timer& tm, int par) {
     TIMED(K_DIR_SPMV, P.ks.dir_asm<<<P.grid, 256, 0, st>>>(P.a, par));
   else
     TIMED(K_DIR_SPMV, P.ks.dir<<<P.grid, 256, 0, st>>>(P.a, par));
-  TIMED(K_REDUCE, k_reduce<<<B, 256, 0, st>>>(P.red, RM_PW));
+  TIMED(K_REDUCE, reduce(P, RM_PW));
   TIMED(K_UPDATE_PREC, P.ks.upd<<<P.grid, 256, 0, st>>>(P.a, par));
   for (int q = 1; q < P.max_chain_q; ++q)
     TIMED(K_CHAIN, P.ks.chain<<<P.grid, 256, 0, st>>>(P.a, par, q, 0));
-  TIMED(K_REDUCE, k_reduce<<<B, 256, 0, st>>>(P.red, RM_ITER));
+  TIMED(K_REDUCE, reduce(P, RM_ITER));
   return AIRGA_OK;
 }
 
@@ -322,7 +318,7 @@ static airga_status start_inner(Plan<T>& P, Timer& tm, int rel) {
   TIMED(K_INIT_PREC, P.ks.init<<<P.grid, 256, 0, st>>>(P.a, 0));
   for (int q = 1; q < P.max_chain_q; ++q)
     TIMED(K_CHAIN, P.ks.chain<<<P.grid, 256, 0, st>>>(P.a, 0, q, 1));
-  TIMED(K_REDUCE, k_reduce<<<(unsigned)P.a.B, 256, 0, st>>>(P.red, rel ? RM_INIT_REL : RM_INIT_ABS));
+  TIMED(K_REDUCE, reduce(P, rel ? RM_INIT_REL : RM_INIT_ABS));
   return AIRGA_OK;
 }
 
@@ -333,25 +329,41 @@ static airga_status iterate(Plan<T>& P, Timer& tm, const airga_pcg_opts& o) {
   int32_t* h_nact = reinterpret_cast<int32_t*>(static_cast<char*>(P.ctx->host_pinned) + P.flags_off);
   int k = o.poll_every < 2 ? 2 : o.poll_every;
   k += k & 1;
-  hipGraphExec_t exec = nullptr;
-  hipGraph_t graph = nullptr;
+  airga_ctx ctx = P.ctx;
   const bool use_graph = o.use_graph && !o.profile;
   if (use_graph) {
-    AIRGA_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    airga_status s = AIRGA_OK;
-    for (int j = 0; j < k && s == AIRGA_OK; ++j) s = iteration(P, tm, j & 1);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(st, &g);
-    if (s != AIRGA_OK) {
-      if (g) (void)hipGraphDestroy(g);
-      return s;
-    }
-    if (e != hipSuccess) return fail(AIRGA_EHIP, "graph capture failed: %s", hipGetErrorString(e));
-    graph = g;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      (void)hipGraphDestroy(graph);
-      return fail(AIRGA_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    // launch arguments of the k captured iterations, byte for byte
+    std::vector<char> key(sizeof(P.a) + sizeof(P.red) + sizeof(P.ks) + 4 * sizeof(int));
+    char* kp = key.data();
+    std::memcpy(kp, &P.a, sizeof(P.a));
+    kp += sizeof(P.a);
+    std::memcpy(kp, &P.red, sizeof(P.red));
+    kp += sizeof(P.red);
+    std::memcpy(kp, &P.ks, sizeof(P.ks));
+    kp += sizeof(P.ks);
+    const int extra[4] = {k, P.asm_path ? 1 : 0, P.max_chain_q, (int)P.grid};
+    std::memcpy(kp, extra, sizeof extra);
+    if (!ctx->graph_exec || ctx->graph_key != key) {
+      if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+      ctx->graph_exec = nullptr;
+      ctx->graph_key.clear();
+      AIRGA_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      airga_status s = AIRGA_OK;
+      for (int j = 0; j < k && s == AIRGA_OK; ++j) s = iteration(P, tm, j & 1);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(st, &g);
+      if (s != AIRGA_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+      }
+      if (e != hipSuccess) return fail(AIRGA_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+      e = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        ctx->graph_exec = nullptr;
+        return fail(AIRGA_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+      }
+      ctx->graph_key = key;
     }
   }
   airga_status result = AIRGA_OK;
@@ -359,7 +371,7 @@ static airga_status iterate(Plan<T>& P, Timer& tm, const airga_pcg_opts& o) {
   const int64_t rounds = (int64_t)o.max_iter / k + 2;
   for (int64_t round = 0; round < rounds; ++round) {
     if (use_graph) {
-      hipError_t e = hipGraphLaunch(exec, st);
+      hipError_t e = hipGraphLaunch(ctx->graph_exec, st);
       if (e != hipSuccess) {
         result = fail(AIRGA_EHIP, "hipGraphLaunch: %s", hipGetErrorString(e));
         break;
@@ -377,8 +389,6 @@ static airga_status iterate(Plan<T>& P, Timer& tm, const airga_pcg_opts& o) {
     result = tm.flush();
     if (result != AIRGA_OK || *h_nact == 0) break;
   }
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
   return result;
 }
 
@@ -392,9 +402,18 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
   const int rows = kCfgs[cfg].rows;
   const int G = (int)((pen.n_slices + rows - 1) / rows);
   P.ctx = ctx;
+  // padding bytes too: the launch arguments key the graph cache
+  std::memset(static_cast<void*>(&P.a), 0, sizeof(P.a));
+  std::memset(static_cast<void*>(&P.red), 0, sizeof(P.red));
   // factor values per shift, oldest first; no preconditioner = the identity
   std::vector<std::vector<const T*>> chains(nshift);
   int maxc = 1;
+  {
+    std::vector<airga_prec> all;
+    for (int k = 0; k < nshift; ++k)
+      for (airga_prec q = precs ? precs[k] : nullptr; q; q = q->parent) all.push_back(q);
+    AIRGA_TRY(prec_resolve_many(ctx, all));
+  }
   for (int k = 0; k < nshift; ++k) {
     if (precs && precs[k]) {
       std::vector<airga_prec> ch;
@@ -414,7 +433,7 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
   const size_t vec_bytes = sizeof(T) * (size_t)KINDS * B * ld;
   AIRGA_TRY(ctx->ws_vec.reserve(vec_bytes));
   AIRGA_TRY(ctx->ws_partial.reserve(sizeof(double) * (size_t)B * G * kSlots));
-  const size_t sys_bytes = (7 * sizeof(double) + 9 * sizeof(int32_t)) * (size_t)B + 256;
+  const size_t sys_bytes = (7 * sizeof(double) + 7 * sizeof(int32_t)) * (size_t)B + 256;
   AIRGA_TRY(ctx->ws_sys.reserve(sys_bytes));
   const size_t shift_bytes = 4 * sizeof(double) * nshift + sizeof(void*) * (size_t)nshift * maxc +
                              sizeof(int32_t) * nshift + 256;
@@ -428,8 +447,8 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
   S.ff = d + 5 * B; S.relres = d + 6 * B;
   int32_t* iv = reinterpret_cast<int32_t*>(d + 7 * B);
   S.active = iv; S.first = iv + B; S.istat = iv + 2 * B; S.status = iv + 3 * B;
-  S.iters = iv + 4 * B; S.sweeps = iv + 5 * B; S.outer = iv + 6 * B; S.list = iv + 7 * B;
-  S.nact = iv + 8 * B;
+  S.iters = iv + 4 * B; S.sweeps = iv + 5 * B; S.outer = iv + 6 * B;
+  S.nact = iv + 7 * B;
   // per-shift block, staged in pinned memory and copied once
   char* hp = static_cast<char*>(ctx->host_pinned);
   double* h_ca64 = reinterpret_cast<double*>(hp);
@@ -495,6 +514,7 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
   P.red.max_iter = o.max_iter;
   P.red.max_sweeps = o.max_sweeps;
   P.grid = blocks_for(G, 4);
+  P.wide_reduce = B < 32;
   const bool exact = pen.uniform_width && pen.max_len == wmax_of(wmax_class(pen.max_len));
   P.ks = kernel_set<T>(wmax_class(pen.max_len), exact, cfg);
   P.cfg = cfg;
@@ -544,7 +564,9 @@ static airga_status autotune(airga_ctx ctx, int32_t nshift, const double* shifts
       if (rep == 1) e = hipEventRecord(e0, st);
       if (asm_path) P.ks.dir_asm<<<P.grid, 256, 0, st>>>(P.a, 0);
       else P.ks.dir<<<P.grid, 256, 0, st>>>(P.a, 0);
+      reduce(P, RM_NONE);
       P.ks.upd<<<P.grid, 256, 0, st>>>(P.a, 0);
+      reduce(P, RM_NONE);
     }
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipGetLastError();
@@ -627,14 +649,14 @@ static airga_status solve_fp64(airga_ctx ctx, int32_t nshift, const double* shif
   const int x0 = o.x0_given ? 1 : 0;
   TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, 0, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, x0,
                                                          1 - x0, x0 ? 2 : 1));
-  TIMED(K_REDUCE, k_reduce<<<(unsigned)B, 256, 0, st>>>(P.red, RM_START));
+  TIMED(K_REDUCE, reduce(P, RM_START));
   AIRGA_TRY(start_inner(P, tm, 0));
   AIRGA_TRY(iterate(P, tm, o));
   // result out, then its true residual
   TIMED(K_IR_UPDATE, (k_copy_out<<<dim3(blocks_for(pen.n, 256), (unsigned)B), 256, 0, st>>>(
                          P.a.ws + (int64_t)KX * B * P.a.ld, P.a.ld, pen.n, X, ldx)));
   TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, 0, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, 1, 0, 0));
-  TIMED(K_REDUCE, k_reduce<<<(unsigned)B, 256, 0, st>>>(P.red, RM_FINAL));
+  TIMED(K_REDUCE, reduce(P, RM_FINAL));
   AIRGA_TRY(tm.flush());
   return read_stats(ctx, P.a.sys, B, false, stats);
 }
@@ -660,9 +682,9 @@ static airga_status solve_mixed(airga_ctx ctx, int32_t nshift, const double* shi
   // sweep 0 residual; RM_OUTER then activates the systems to refine
   TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, 0, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, x0,
                                                          1 - x0, 1));
-  k_fill_i32<<<blocks_for(B, 256), 256, 0, st>>>(P.a.sys.active, B, 0);
+  k_clear_active<<<blocks_for(B, 256), 256, 0, st>>>(P.a.sys, B);
   AIRGA_HIP(hipGetLastError());
-  TIMED(K_REDUCE, k_reduce<<<(unsigned)B, 256, 0, st>>>(P.red, RM_OUTER));
+  TIMED(K_REDUCE, reduce(P, RM_OUTER));
   for (int sweep = 0; sweep <= o.max_sweeps; ++sweep) {
     AIRGA_HIP(hipMemcpyAsync(h_nact, P.a.sys.nact, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     AIRGA_HIP(hipStreamSynchronize(st));
@@ -672,7 +694,7 @@ static airga_status solve_mixed(airga_ctx ctx, int32_t nshift, const double* shi
     TIMED(K_IR_UPDATE,
           (k_ir_update<<<dim3(blocks_for(pen.n, 256), (unsigned)B), 256, 0, st>>>(P.a, X, ldx)));
     TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, 0, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, 1, 0, 1));
-    TIMED(K_REDUCE, k_reduce<<<(unsigned)B, 256, 0, st>>>(P.red, RM_OUTER));
+    TIMED(K_REDUCE, reduce(P, RM_OUTER));
   }
   AIRGA_TRY(tm.flush());
   return read_stats(ctx, P.a.sys, B, true, stats);

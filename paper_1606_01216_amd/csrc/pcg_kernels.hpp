@@ -41,8 +41,7 @@ enum { ST_CONV = AIRGA_SYS_CONVERGED, ST_MAXIT = AIRGA_SYS_MAXIT,
 struct SysDev {
   double *rz, *pw, *alpha, *beta, *tol2, *ff, *relres;
   int32_t *active, *first, *istat, *status, *iters, *sweeps, *outer;
-  int32_t* list;  // active systems in ascending order (compacted after each reduction)
-  int32_t* nact;  // [0] = active count, [1] = arrival counter of the reduction blocks
+  int32_t* nact;    // number of systems with active set (for the host's polling)
 };
 
 template <typename T>
@@ -58,13 +57,13 @@ struct SolveArgs {
   const T* const* fac;       // per shift [maxc] factor values, fac[sh * maxc + q], oldest first
   const int32_t* clen;       // per shift number of applied factors
   int32_t maxc;
-  double* partial;           // [B][G][kSlots]
+  double* partial;           // [kSlots][B][G], slot-major
   SysDev sys;
   __device__ __forceinline__ T* vec(int kind, int b) const {
     return ws + ((int64_t)kind * B + b) * ld;
   }
-  __device__ __forceinline__ double* slot(int b, int g) const {
-    return partial + ((int64_t)b * G + g) * kSlots;
+  __device__ __forceinline__ double& slot(int q, int b, int g) const {
+    return partial[((int64_t)q * B + b) * G + g];
   }
 };
 
@@ -113,13 +112,34 @@ struct Rows {
   }
 };
 
-// Systems of the next group: list[j0 + u] or -1 past the active count.
-template <int U>
-__device__ __forceinline__ void group_of(const int32_t* __restrict__ list, int j0, int nact,
-                                         int (&bs)[U]) {
+// Sweep of the systems whose flag is set, in ascending order, U at a time
+// (bs[u] = -1 past the last one).  The flags are read 64 at a time into a
+// wave-uniform bit mask, so the sweep needs no compacted list.
+struct FlagSweep {
+  const int32_t* __restrict__ flag;
+  int B, c;
+  uint64_t mask;
+  __device__ FlagSweep(const int32_t* f, int nb) : flag(f), B(nb), c(-64), mask(0) {}
+  template <int U>
+  __device__ __forceinline__ bool next(int (&bs)[U], int lane) {
+    while (mask == 0) {
+      c += 64;
+      if (c >= B) return false;
+      const int i = c + lane;
+      mask = __ballot(i < B && flag[i] != 0);
+    }
 #pragma unroll
-  for (int u = 0; u < U; ++u) bs[u] = (j0 + u < nact) ? list[j0 + u] : -1;
-}
+    for (int u = 0; u < U; ++u) {
+      if (mask) {
+        bs[u] = c + __builtin_ctzll(mask);
+        mask &= mask - 1;
+      } else {
+        bs[u] = -1;
+      }
+    }
+    return true;
+  }
+};
 
 // ---- A: direction update + shifted SpMV + (p, w) -------------------------
 template <typename T, int WMAX, int R, int U, bool ASM, bool EXACT>
@@ -132,10 +152,9 @@ __global__ void __launch_bounds__(256) k_dir_spmv(SolveArgs<T> A, int par) {
   T mv[R][WMAX], kv[R][WMAX];
   rows.values(A.mv, mv);
   if constexpr (!ASM) rows.values(A.kv, kv);
-  const int nact = A.sys.nact[0];
-  for (int j0 = 0; j0 < nact; j0 += U) {
-    int bs[U];
-    group_of<U>(A.sys.list, j0, nact, bs);
+  FlagSweep sweep(A.sys.active, A.B);
+  int bs[U];
+  while (sweep.next(bs, lane)) {
     T pr[U][R], wr[U][R];
     // compute phase: no branches, so every load of the group can be in
     // flight at once (a missing system aliases the group's first one)
@@ -184,7 +203,7 @@ __global__ void __launch_bounds__(256) k_dir_spmv(SolveArgs<T> A, int par) {
         dot = fma(pr[u][i], wr[u][i], dot);
       }
       dot = wave_total(dot);
-      if (lane == 0) A.slot(b, wg)[0] = (double)dot;
+      if (lane == 0) A.slot(0, b, wg) = (double)dot;
     }
   }
 }
@@ -198,10 +217,9 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
   if (wg >= A.G) return;
   Rows<WMAX, R, EXACT> rows;
   rows.load(A.pd, wg, lane);
-  const int nact = A.sys.nact[0];
-  for (int j0 = 0; j0 < nact; j0 += U) {
-    int bs[U];
-    group_of<U>(A.sys.list, j0, nact, bs);
+  FlagSweep sweep(A.sys.active, A.B);
+  int bs[U];
+  while (sweep.next(bs, lane)) {
     // compute phase: no branches, so every load of the group can be in
     // flight at once (a missing system aliases the group's first one).  Each
     // system's first preconditioner factor is loaded (systems of one shift
@@ -270,10 +288,9 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
       rz = wave_total(rz);
       zw = wave_total(zw);
       if (lane == 0) {
-        double* s = A.slot(b, wg);
-        s[1] = (double)rr;
-        s[2] = L > 1 ? 0.0 : (double)rz;
-        s[3] = L > 1 ? 0.0 : (double)zw;
+        A.slot(1, b, wg) = (double)rr;
+        A.slot(2, b, wg) = L > 1 ? 0.0 : (double)rz;
+        A.slot(3, b, wg) = L > 1 ? 0.0 : (double)zw;
       }
     }
   }
@@ -288,11 +305,12 @@ __global__ void __launch_bounds__(256) k_chain(SolveArgs<T> A, int par, int q, i
   Rows<WMAX, R, EXACT> rows;
   rows.load(A.pd, wg, lane);
   const int rk = init ? KR0 : KR0 + (par ^ 1);
-  const int nact = A.sys.nact[0];
+  FlagSweep sweep(A.sys.active, A.B);
+  int bs[1];
   int loaded_sh = -1;
   T fv[R][WMAX];
-  for (int j = 0; j < nact; ++j) {
-    const int b = A.sys.list[j];
+  while (sweep.next(bs, lane)) {
+    const int b = bs[0];
     const int sh = b / A.m;
     const int L = A.clen[sh];
     if (L <= q) continue;
@@ -323,9 +341,8 @@ __global__ void __launch_bounds__(256) k_chain(SolveArgs<T> A, int par, int q, i
       rz = wave_total(rz);
       zw = wave_total(zw);
       if (lane == 0) {
-        double* s = A.slot(b, wg);
-        s[2] = (double)rz;
-        s[3] = (double)zw;
+        A.slot(2, b, wg) = (double)rz;
+        A.slot(3, b, wg) = (double)zw;
       }
     }
   }
@@ -350,10 +367,9 @@ __global__ void __launch_bounds__(256) k_residual(SolveArgs<TO> A, const double*
   rows.values(A.pd.m64, mv);
   rows.values(A.pd.k64, kv);
   const int64_t n = A.pd.n;
-  for (int b0 = 0; b0 < A.B; b0 += U) {
-    int bs[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) bs[u] = (b0 + u < A.B && A.sys.outer[b0 + u]) ? b0 + u : -1;
+  FlagSweep sweep(A.sys.outer, A.B);
+  int bs[U];
+  while (sweep.next(bs, lane)) {
     double res[U][R], fr[U][R], xo[U][R];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -406,9 +422,8 @@ __global__ void __launch_bounds__(256) k_residual(SolveArgs<TO> A, const double*
       rr = wave_total(rr);
       ff = wave_total(ff);
       if (lane == 0) {
-        double* s = A.slot(b, wg);
-        s[0] = rr;
-        s[1] = ff;
+        A.slot(0, b, wg) = rr;
+        A.slot(1, b, wg) = ff;
       }
     }
   }

@@ -121,12 +121,30 @@ __global__ void k_alpha_final(const double* __restrict__ part, int64_t nb, doubl
   if (t == 0) out[0] = red[0][0] / red[1][0];
 }
 
-// One lane per column j.  UPDATE selects the update's right-hand side
-// khat_old_j and its skip test; otherwise the right-hand side is e_j.
+// Entries of Khat = S K(s) S on the stored pattern (0 on padding), with
+// K(s) = (s^2 + alpha s) M + (1 + beta s) K formed from the float64 pencil.
+__global__ void k_scaled_values(PencilDev pd, double a, double b, const double* __restrict__ dinv,
+                                double* __restrict__ out) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= (int64_t)pd.n_slices * kSlice) return;
+  const int64_t s = r / kSlice;
+  const int32_t base = pd.slice_ptr[s] + (int32_t)(r % kSlice);
+  const int w = (pd.slice_ptr[s + 1] - pd.slice_ptr[s]) / kSlice;
+  const int len = pd.row_len[r];
+  const double sr = dinv[r];
+  for (int k = 0; k < w; ++k) {
+    const int32_t idx = base + k * kSlice;
+    out[idx] = k < len ? fma(a, pd.m64[idx], b * pd.k64[idx]) * sr * dinv[pd.col[idx]] : 0.0;
+  }
+}
+
+// One lane per column j, on the scaled entries: ahat = Khat (build) or
+// Khat_new (update), aold = Khat_old scaled by the new diagonal (update).
+// UPDATE selects the update's right-hand side khat_old_j and its skip test;
+// otherwise the right-hand side is e_j.
 template <int MJ, bool UPDATE>
-__global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, double a, double b,
-                                                   double a_old, double b_old,
-                                                   const double* __restrict__ dinv,
+__global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, const double* __restrict__ ahat,
+                                                   const double* __restrict__ aold,
                                                    const double* __restrict__ alpha_u, double tol,
                                                    double* __restrict__ hat,
                                                    double* __restrict__ obj,
@@ -147,7 +165,6 @@ __global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, double a, doubl
         J[t] = pd.col[jpos[t]];
       }
     }
-    const double sj = dinv[j];
     if constexpr (UPDATE) {
       // skip test on column j (= row j: K(s) and S are symmetric)
       const double al = *alpha_u;
@@ -155,12 +172,8 @@ __global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, double a, doubl
 #pragma unroll
       for (int t = 0; t < MJ; ++t) {
         if (t < nj) {
-          const int32_t idx = jpos[t];
-          const double sc = sj * dinv[J[t]];
-          const double m = pd.m64[idx], kk = pd.k64[idx];
-          const double vo = fma(a_old, m, b_old * kk) * sc;
-          const double vn = fma(a, m, b * kk) * sc;
-          const double d = vo - al * vn;
+          const double vo = aold[jpos[t]];
+          const double d = vo - al * ahat[jpos[t]];
           n_old = fma(vo, vo, n_old);
           n_res = fma(d, d, n_res);
         }
@@ -194,7 +207,6 @@ __global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, double a, doubl
             // meetings are duplicates and are skipped.
             const int32_t base_i = pd.slice_ptr[i / kSlice] + (i % kSlice);
             const int ni = pd.row_len[i];
-            const double si = dinv[i];
             double v[MJ];
 #pragma unroll
             for (int u = 0; u < MJ; ++u) v[u] = 0.0;
@@ -203,17 +215,16 @@ __global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, double a, doubl
             for (int q = 0; q < ni; ++q) {
               const int32_t idx = base_i + q * kSlice;
               const int c = pd.col[idx];
-              const double m = pd.m64[idx], kk = pd.k64[idx];
-              const double sc = si * dinv[c];
+              const double val = ahat[idx];
 #pragma unroll
               for (int u = 0; u < MJ; ++u) {
                 if (u < nj && J[u] == c) {
-                  v[u] += fma(a, m, b * kk) * sc;
+                  v[u] += val;
                   umin = u < umin ? u : umin;
                 }
               }
               if constexpr (UPDATE) {
-                if (c == (int)j) rhs = fma(a_old, m, b_old * kk) * sc;
+                if (c == (int)j) rhs = aold[idx];
               }
             }
             if constexpr (!UPDATE) rhs = (i == (int)j) ? 1.0 : 0.0;
@@ -310,6 +321,28 @@ __global__ void k_factor_apply(PencilDev pd, const double* __restrict__ vals, do
 
 // ------------------------------------------------------------------- host
 
+airga_status pool_get(airga_ctx ctx, DevBuf* buf, size_t need) {
+  // smallest pooled buffer that fits
+  size_t best = ctx->pool.size();
+  for (size_t i = 0; i < ctx->pool.size(); ++i)
+    if (ctx->pool[i].second >= need &&
+        (best == ctx->pool.size() || ctx->pool[i].second < ctx->pool[best].second))
+      best = i;
+  if (best < ctx->pool.size()) {
+    buf->adopt(ctx->pool[best].first, ctx->pool[best].second);
+    ctx->pool.erase(ctx->pool.begin() + (long)best);
+    return AIRGA_OK;
+  }
+  return buf->reserve(need);
+}
+
+void pool_put(airga_ctx ctx, DevBuf* buf) {
+  void* p;
+  size_t b;
+  buf->detach(&p, &b);
+  if (p) ctx->pool.emplace_back(p, b);
+}
+
 static airga_status new_prec(airga_ctx ctx, double s, airga_prec* out) {
   airga_prec p = new (std::nothrow) airga_prec_s();
   if (!p) return fail(AIRGA_ENOMEM, "host allocation failed");
@@ -318,10 +351,14 @@ static airga_status new_prec(airga_ctx ctx, double s, airga_prec* out) {
   p->shift = s;
   const Pencil& pen = ctx->pen;
   airga_status st;
-  if ((st = p->v64.reserve(sizeof(double) * pen.nnz_stored)) != AIRGA_OK ||
-      (st = p->v32.reserve(sizeof(float) * pen.nnz_stored)) != AIRGA_OK ||
-      (st = p->objective.reserve(sizeof(double) * pen.n)) != AIRGA_OK ||
-      (st = p->scal.reserve(64)) != AIRGA_OK) {
+  if ((st = pool_get(ctx, &p->v64, sizeof(double) * pen.nnz_stored)) != AIRGA_OK ||
+      (st = pool_get(ctx, &p->v32, sizeof(float) * pen.nnz_stored)) != AIRGA_OK ||
+      (st = pool_get(ctx, &p->objective, sizeof(double) * pen.n)) != AIRGA_OK ||
+      (st = pool_get(ctx, &p->scal, 64)) != AIRGA_OK) {
+    pool_put(ctx, &p->v64);
+    pool_put(ctx, &p->v32);
+    pool_put(ctx, &p->objective);
+    pool_put(ctx, &p->scal);
     delete p;
     return st;
   }
@@ -342,16 +379,35 @@ static airga_status check_spai_args(airga_ctx ctx, double s, airga_prec* out) {
   return AIRGA_OK;
 }
 
-// Scratch for one SPAI call: [dinv (n_pad) | hat (stored) | partials].
-static airga_status spai_scratch(airga_ctx ctx, double** dinv, double** hat, double** part,
-                                 int64_t nb) {
+// Scratch for one SPAI call: [dinv (n_pad) | hat | ahat | aold (stored each) | partials].
+struct SpaiScratch {
+  double *dinv, *hat, *ahat, *aold, *part;
+};
+static airga_status spai_scratch(airga_ctx ctx, SpaiScratch* w, int64_t nb) {
   const Pencil& pen = ctx->pen;
-  const size_t need = sizeof(double) * ((size_t)pen.n_pad() + (size_t)pen.nnz_stored + 2 * nb + 8);
+  const size_t need =
+      sizeof(double) * ((size_t)pen.n_pad() + 3 * (size_t)pen.nnz_stored + 2 * nb + 8);
   AIRGA_TRY(ctx->ws_tmp.reserve(need));
-  *dinv = ctx->ws_tmp.as<double>();
-  *hat = *dinv + pen.n_pad();
-  *part = *hat + pen.nnz_stored;
+  w->dinv = ctx->ws_tmp.as<double>();
+  w->hat = w->dinv + pen.n_pad();
+  w->ahat = w->hat + pen.nnz_stored;
+  w->aold = w->ahat + pen.nnz_stored;
+  w->part = w->aold + pen.nnz_stored;
   return AIRGA_OK;
+}
+
+// Column kernels sized to the longest row.
+template <bool UPDATE>
+static void launch_cols(airga_ctx ctx, const SpaiScratch& w, const double* alpha_u, double tol,
+                        double* obj, int32_t* skip) {
+  const Pencil& pen = ctx->pen;
+  const unsigned nb = blocks_for(pen.n, 256);
+  if (pen.max_len <= 6)
+    k_spai_cols<6, UPDATE><<<nb, 256, 0, ctx->stream>>>(pen.dev(), w.ahat, w.aold, alpha_u, tol,
+                                                       w.hat, obj, skip);
+  else
+    k_spai_cols<kSpaiMaxJ, UPDATE><<<nb, 256, 0, ctx->stream>>>(pen.dev(), w.ahat, w.aold, alpha_u,
+                                                               tol, w.hat, obj, skip);
 }
 
 static airga_status run_build(airga_ctx ctx, double s, const airga_spai_opts& o, airga_prec p) {
@@ -359,16 +415,18 @@ static airga_status run_build(airga_ctx ctx, double s, const airga_spai_opts& o,
   hipStream_t st = ctx->stream;
   double a, b;
   shift_coeffs(pen, s, &a, &b);
-  double *dinv, *hat, *part;
-  AIRGA_TRY(spai_scratch(ctx, &dinv, &hat, &part, 0));
+  SpaiScratch w;
+  AIRGA_TRY(spai_scratch(ctx, &w, 0));
   const PencilDev pd = pen.dev();
-  k_dinv<<<blocks_for(pen.n_pad(), 256), 256, 0, st>>>(pd, a, b, o.equilibrate, dinv);
+  const unsigned nr = blocks_for(pen.n_pad(), 256);
+  k_dinv<<<nr, 256, 0, st>>>(pd, a, b, o.equilibrate, w.dinv);
   AIRGA_HIP(hipGetLastError());
-  k_spai_cols<kSpaiMaxJ, false><<<blocks_for(pen.n, 256), 256, 0, st>>>(
-      pd, a, b, 0.0, 0.0, dinv, nullptr, 0.0, hat, p->objective.as<double>(), nullptr);
+  k_scaled_values<<<nr, 256, 0, st>>>(pd, a, b, w.dinv, w.ahat);
   AIRGA_HIP(hipGetLastError());
-  k_spai_finalize<<<blocks_for(pen.n_pad(), 256), 256, 0, st>>>(
-      pd, hat, dinv, o.symmetrize ? 1 : 0, p->v64.as<double>(), p->v32.as<float>());
+  launch_cols<false>(ctx, w, nullptr, 0.0, p->objective.as<double>(), nullptr);
+  AIRGA_HIP(hipGetLastError());
+  k_spai_finalize<<<nr, 256, 0, st>>>(pd, w.hat, w.dinv, o.symmetrize ? 1 : 0,
+                                      p->v64.as<double>(), p->v32.as<float>());
   AIRGA_HIP(hipGetLastError());
   // Alg. 2's starting scaling trace(K) / trace(K K^T), from the Gram scalars.
   const double nn = a * a * pen.gram_mm + 2 * a * b * pen.gram_mk + b * b * pen.gram_kk;
@@ -388,25 +446,28 @@ static airga_status run_update(airga_ctx ctx, airga_prec old, double s_new,
   shift_coeffs(pen, s_new, &a, &b);
   shift_coeffs(pen, old->shift, &ao, &bo);
   const unsigned nb = blocks_for(pen.n, 256);
-  double *dinv, *hat, *part;
-  AIRGA_TRY(spai_scratch(ctx, &dinv, &hat, &part, nb));
+  SpaiScratch w;
+  AIRGA_TRY(spai_scratch(ctx, &w, nb));
   const PencilDev pd = pen.dev();
+  const unsigned nr = blocks_for(pen.n_pad(), 256);
   double* d_alpha = p->scal.as<double>();
   int32_t* d_skip = reinterpret_cast<int32_t*>(p->scal.as<char>() + 8);
-  k_dinv<<<blocks_for(pen.n_pad(), 256), 256, 0, st>>>(pd, a, b, o.equilibrate, dinv);
+  k_dinv<<<nr, 256, 0, st>>>(pd, a, b, o.equilibrate, w.dinv);
   AIRGA_HIP(hipGetLastError());
-  k_alpha_partial<<<nb, 256, 0, st>>>(pd, a, b, ao, bo, dinv, part);
+  k_scaled_values<<<nr, 256, 0, st>>>(pd, a, b, w.dinv, w.ahat);
   AIRGA_HIP(hipGetLastError());
-  k_alpha_final<<<1, 256, 0, st>>>(part, nb, d_alpha);
+  k_scaled_values<<<nr, 256, 0, st>>>(pd, ao, bo, w.dinv, w.aold);
+  AIRGA_HIP(hipGetLastError());
+  k_alpha_partial<<<nb, 256, 0, st>>>(pd, a, b, ao, bo, w.dinv, w.part);
+  AIRGA_HIP(hipGetLastError());
+  k_alpha_final<<<1, 256, 0, st>>>(w.part, nb, d_alpha);
   AIRGA_HIP(hipGetLastError());
   k_fill_i32<<<1, 64, 0, st>>>(d_skip, 1, 0);
   AIRGA_HIP(hipGetLastError());
-  k_spai_cols<kSpaiMaxJ, true><<<nb, 256, 0, st>>>(pd, a, b, ao, bo, dinv, d_alpha, o.tol, hat,
-                                                   p->objective.as<double>(), d_skip);
+  launch_cols<true>(ctx, w, d_alpha, o.tol, p->objective.as<double>(), d_skip);
   AIRGA_HIP(hipGetLastError());
-  k_spai_finalize<<<blocks_for(pen.n_pad(), 256), 256, 0, st>>>(pd, hat, dinv, 2,
-                                                                p->v64.as<double>(),
-                                                                p->v32.as<float>());
+  k_spai_finalize<<<nr, 256, 0, st>>>(pd, w.hat, w.dinv, 2, p->v64.as<double>(),
+                                      p->v32.as<float>());
   AIRGA_HIP(hipGetLastError());
   p->is_update = true;
   p->parent = old;
@@ -414,28 +475,43 @@ static airga_status run_update(airga_ctx ctx, airga_prec old, double s_new,
   return AIRGA_OK;
 }
 
-airga_status prec_resolve(airga_prec p) {
-  if (p->scalar_known && p->alpha_known) return AIRGA_OK;
-  struct {
+airga_status prec_resolve_many(airga_ctx ctx, const std::vector<airga_prec>& ps) {
+  std::vector<airga_prec> todo;
+  for (airga_prec p : ps)
+    if (!(p->scalar_known && p->alpha_known)) todo.push_back(p);
+  if (todo.empty()) return AIRGA_OK;
+  struct Facts {
     double alpha;
     int32_t skipped, pad;
-  } h{};
-  AIRGA_HIP(hipMemcpyAsync(&h, p->scal.ptr, 16, hipMemcpyDeviceToHost, p->ctx->stream));
-  AIRGA_HIP(hipStreamSynchronize(p->ctx->stream));
-  p->alpha = h.alpha;
-  p->alpha_known = true;
-  p->skipped = h.skipped;
-  p->scalar_only = h.skipped == p->ctx->pen.n;
-  p->scalar_known = true;
+  };
+  AIRGA_TRY(ensure_pinned(ctx, sizeof(Facts) * todo.size()));
+  Facts* h = static_cast<Facts*>(ctx->host_pinned);
+  for (size_t i = 0; i < todo.size(); ++i)
+    AIRGA_HIP(hipMemcpyAsync(&h[i], todo[i]->scal.ptr, sizeof(Facts), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  AIRGA_HIP(hipStreamSynchronize(ctx->stream));
+  for (size_t i = 0; i < todo.size(); ++i) {
+    airga_prec p = todo[i];
+    p->alpha = h[i].alpha;
+    p->alpha_known = true;
+    p->skipped = h[i].skipped;
+    p->scalar_only = h[i].skipped == ctx->pen.n;
+    p->scalar_known = true;
+  }
   return AIRGA_OK;
+}
+
+airga_status prec_resolve(airga_prec p) {
+  return prec_resolve_many(p->ctx, std::vector<airga_prec>{p});
 }
 
 airga_status prec_chain(airga_prec p, std::vector<airga_prec>* out) {
   out->clear();
-  for (airga_prec q = p; q; q = q->parent) {
-    AIRGA_TRY(prec_resolve(q));
+  std::vector<airga_prec> all;
+  for (airga_prec q = p; q; q = q->parent) all.push_back(q);
+  AIRGA_TRY(prec_resolve_many(p->ctx, all));
+  for (airga_prec q : all)
     if (!q->scalar_only) out->push_back(q);
-  }
   return AIRGA_OK;
 }
 
@@ -572,8 +648,11 @@ void airga_prec_release(airga_prec prec) {
     if (--prec->refs > 0) return;
     airga_prec parent = prec->parent;
     airga_ctx ctx = prec->ctx;
-    (void)hipSetDevice(ctx->device);
-    (void)hipStreamSynchronize(ctx->stream);
+    // buffers go back to the context's stream-ordered pool
+    pool_put(ctx, &prec->v64);
+    pool_put(ctx, &prec->v32);
+    pool_put(ctx, &prec->objective);
+    pool_put(ctx, &prec->scal);
     ctx->live_precs--;
     delete prec;
     prec = parent;
