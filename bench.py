@@ -63,6 +63,120 @@ def build_inputs(name, seed=0):
     return pen, f, np.asarray(shifts, float), np.asarray(drifted, float)
 
 
+# ---------------------------------------------------------------- profiles
+#
+# HBM traffic of the row kernels comes from two rocprofv3 counter passes
+# (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) over one quick step with a
+# forced tile, each scaled by what the same counter reads for a plain 1 GiB
+# device copy in the same run.  The table is keyed by the hash of the row
+# kernels' source: after any change to them it no longer applies.
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1606_01216_amd", "csrc", "pcg_kernels.hpp")
+PROFILES = os.path.join(ROOT, "profiles")
+PMC_KERNELS = {"update_prec": "k_update_prec<float, {w}, {r}, {u}, false",
+               "dir_spmv": "k_dir_spmv<float, {w}, {r}, {u}, false"}
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_file(workload):
+    return os.path.join(PROFILES, f"row_kernels_{workload}_hbm_traffic.json")
+
+
+def measured_traffic(workload, tile, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter table, or
+    None when there is none for this tile or the kernels changed since."""
+    path = traffic_file(workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        tab = json.load(fh)
+    if tab.get("source_hash") != kernel_source_hash():
+        return None
+    ent = tab.get("tiles", {}).get(f"{tile[0]}x{tile[1]}", {}).get(kernel)
+    return None if ent is None else ent["hbm_bytes_per_launch"]
+
+
+def _read_counters(path):
+    import csv
+    with open(path) as fh:
+        rows = list(csv.DictReader(fh))
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return rows
+
+
+def summarize_pmc(args):
+    import glob
+    root = args.summarize_pmc
+    out = {"workload": args.workload, "source_hash": kernel_source_hash(),
+           "counters": "FETCH_SIZE and WRITE_SIZE (KiB per dispatch), one rocprofv3 pass each",
+           "scaling": "each counter times (copied bytes / counter reading) of a 1 GiB device "
+                      "copy (__amd_rocclr_copyBuffer) in the same run",
+           "launches": "the second mixed-precision solve of the step (after its k_clear_active)",
+           "command": args.command, "tiles": {}}
+    for fdir in sorted(glob.glob(os.path.join(root, "*_fetch"))):
+        tile = os.path.basename(fdir)[:-len("_fetch")]
+        r, u = (int(v) for v in tile.split("x"))
+        per = {}
+        for counter, d in (("FETCH_SIZE", fdir), ("WRITE_SIZE", fdir[:-len("fetch")] + "write")):
+            rows = _read_counters(glob.glob(os.path.join(d, "*counter_collection.csv"))[0])
+            rows = [x for x in rows if x["Counter_Name"] == counter]
+            copies = [float(x["Counter_Value"]) for x in rows
+                      if "copyBuffer" in x["Kernel_Name"] and int(x["Grid_Size"]) >= 1 << 17]
+            factor = 1024.0 * 1024.0 / (sum(copies) / len(copies))
+            last = max(int(x["Dispatch_Id"]) for x in rows if "k_clear_active" in x["Kernel_Name"])
+            for kname, pat in PMC_KERNELS.items():
+                pat = pat.format(w=6, r=r // 64, u=u)
+                vals = [float(x["Counter_Value"]) * 1024.0 * factor for x in rows
+                        if pat in x["Kernel_Name"] and int(x["Dispatch_Id"]) > last]
+                ent = per.setdefault(kname, {"launches": len(vals)})
+                ent[counter.lower() + "_bytes_per_launch"] = int(sum(vals) / len(vals))
+                ent[counter.lower() + "_scale"] = round(factor, 4)
+        for ent in per.values():
+            ent["hbm_bytes_per_launch"] = ent["fetch_size_bytes_per_launch"] + \
+                ent["write_size_bytes_per_launch"]
+        out["tiles"][tile] = per
+    path = args.out or traffic_file(args.workload)
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(out, indent=1))
+
+
+def summarize_trace(args):
+    import csv
+    with open(args.summarize_trace) as fh:
+        rows = list(csv.DictReader(fh))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# rocprofv3 kernel statistics", "", "Command:", "", "```", args.command, "```", "",
+             "| kernel | calls | total ms | avg us | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows[:20]:
+        name = r["Name"].replace("|", "/")
+        lines.append(f"| `{name[:110]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    if args.bench_json:
+        with open(args.bench_json) as fh:
+            b = json.loads(fh.read().strip().splitlines()[-1])
+        rf = b["roofline"]
+        r, u = b["config"]["tile"]["rows_per_wave"] // 64, b["config"]["tile"]["systems_per_group"]
+        pat = PMC_KERNELS[rf["kernel"]].format(w=6, r=r, u=u)
+        hit = [x for x in rows if pat in x["Name"]]
+        lines += ["", f"Dominant kernel `{rf['kernel']}` (tile {r * 64} rows x {u} systems): bench.py "
+                  f"events {rf['avg_launch_us']} us per launch over the profiled solve; rocprofv3 "
+                  f"average over all its launches in the run: "
+                  + (f"{float(hit[0]['AverageNs']) / 1e3:.1f} us" if hit else "not found"),
+                  f"bench line: value {b['value']} {b['unit']}, {b['ms_per_step']} ms/step, "
+                  f"achieved {rf['achieved']} GB/s ({rf['frac']} of {rf['peak']})."]
+    text = "\n".join(lines) + "\n"
+    if args.out:
+        with open(args.out, "w") as fh:
+            fh.write(text)
+    print(text)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,7 +187,26 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain float64 comparator")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="timed steps only (for profilers)")
+    ap.add_argument("--tile", default=None,
+                    help="force the tile 'ROWS,SYSTEMS' (matrix rows per wavefront, systems per "
+                         "group) instead of the autotuner's choice")
+    ap.add_argument("--summarize-pmc", metavar="DIR", default=None,
+                    help="CPU only: turn DIR/<tile>_{fetch,write}/*counter_collection.csv into "
+                         "the traffic table (written to --out)")
+    ap.add_argument("--summarize-trace", metavar="CSV", default=None,
+                    help="CPU only: turn a rocprofv3 kernel_stats.csv into a text summary "
+                         "(written to --out), checked against --bench-json")
+    ap.add_argument("--bench-json", default=None)
+    ap.add_argument("--command", default="", help="the profiling command, recorded in the summary")
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="with --quick: afterwards copy a buffer of this many MiB three times "
+                         "(a plain copy kernel of known size, to scale hardware byte counters)")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        return summarize_pmc(args)
+    if args.summarize_trace:
+        return summarize_trace(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
@@ -101,6 +234,8 @@ def main():
     ctx = airga.Context(0, stream)
     solve_kw = dict(tol=args.tol, mode=airga.MODE_MIXED, inner_tol=1e-4, max_sweeps=12,
                     max_iter=20000, poll_every=8)
+    if args.tile:
+        solve_kw["tile"] = tuple(int(v) for v in args.tile.split(","))
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
 
     def step(record=None, profile=False):
@@ -143,6 +278,14 @@ def main():
     iters = [e["iters"] for e in st1 + st2]
     conv = sum(e["status"] == airga.SYS_CONVERGED for e in st1 + st2)
     if args.quick:
+        if args.copy_mib > 0:
+            src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            log(f"[bench] copied {args.copy_mib} MiB three times")
         print(json.dumps({"metric": METRIC, "ms_per_step": ms_per_step, "converged": conv,
                           "systems": 2 * B}))
         return
@@ -238,9 +381,10 @@ def main():
             rows.append(dict(kernel=name, launches=la, total_ms=ms, avg_us=1e3 * ms / la,
                              gbs=(b / (ms * 1e-3) / 1e9) if b else None, bytes=b))
     dom = max((r for r in rows if r["bytes"]), key=lambda r: r["total_ms"])
+    traffic = measured_traffic(args.workload, tile, dom["kernel"])
     roofline = {"bound": "hbm", "kernel": dom["kernel"], "achieved": round(dom["gbs"], 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_launch_us": round(dom["avg_us"], 2),
+                "traffic": traffic, "avg_launch_us": round(dom["avg_us"], 2),
                 "bytes_per_launch": int(dom["bytes"] / dom["launches"])}
 
     out = {

@@ -215,6 +215,10 @@ typedef struct {
   int32_t use_graph;   /* 1: replay iterations from a captured HIP graph        */
   int32_t profile;     /* 1: time every launch of the dominant kernels with
                           HIP events (no graph); see airga_get_kernel_times     */
+  int32_t tile_rows;   /* 0 (default): the autotuner picks the tile; otherwise
+                          matrix rows per wavefront (64, 128 or 256) ...        */
+  int32_t tile_sys;    /* ... and systems per group (1, 2 or 4) of an allowed
+                          tile (see airga_get_tile_config); EINVAL if not one   */
   int32_t reserved;
 } airga_pcg_opts;
 

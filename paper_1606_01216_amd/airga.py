@@ -57,7 +57,8 @@ class PcgOpts(ctypes.Structure):
                 ("mode", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("max_sweeps", ctypes.c_int32), ("poll_every", ctypes.c_int32),
                 ("x0_given", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("tile_sys", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class SysStats(ctypes.Structure):
@@ -256,12 +257,13 @@ class Context:
     # ---------------------------------------------------------------- solves
     def pcg_solve(self, shifts, precs, F: torch.Tensor, X: torch.Tensor | None = None, *,
                   tol=1e-10, max_iter=20000, mode=MODE_FP64, inner_tol=1e-4, max_sweeps=12,
-                  poll_every=8, x0_given=False, use_graph=True, profile=False):
+                  poll_every=8, x0_given=False, use_graph=True, profile=False, tile=None):
         """Solve K(s_k) X[k, c] = F[c] for all shifts k and columns c.
 
         F: (m, n) float64 on the device; X: (nshift, m, n) float64 (allocated
         when None).  precs: list of Prec or None per shift.  Returns
-        (X, stats) with stats a list of dicts in (k, c) order.
+        (X, stats) with stats a list of dicts in (k, c) order.  tile: None (the
+        autotuner picks) or (matrix rows per wavefront, systems per group).
         """
         _dev(F, torch.float64, self.device)
         m = F.shape[0]
@@ -283,6 +285,8 @@ class Context:
         o.tol, o.max_iter, o.mode = float(tol), int(max_iter), int(mode)
         o.inner_tol, o.max_sweeps, o.poll_every = float(inner_tol), int(max_sweeps), int(poll_every)
         o.x0_given, o.use_graph, o.profile = int(bool(x0_given)), int(bool(use_graph)), int(bool(profile))
+        if tile is not None:
+            o.tile_rows, o.tile_sys = int(tile[0]), int(tile[1])
         stats = (SysStats * (nshift * m))()
         self._enter()
         _check(lib().airga_pcg_solve(self._h, nshift, c_shifts, c_precs, m, _ptr(F), self.n,

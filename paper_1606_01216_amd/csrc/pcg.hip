@@ -28,9 +28,11 @@ enum ReduceMode {
   RM_NONE = 7,      // sums only, no state change (autotuner timing)
 };
 
+constexpr int kReduceThreads = 1024;
+
 struct ReduceArgs {
   const double* partial;  // [kSlots][B][G]
-  int32_t G;
+  int32_t G;              // partial columns per system
   int32_t B;
   SysDev sys;
   int32_t max_iter;
@@ -55,15 +57,21 @@ __global__ void __launch_bounds__(NT) k_reduce(ReduceArgs P, int mode) {
   // partial slots this mode uses
   const int q0 = (mode == RM_PW || use_outer || mode == RM_NONE) ? 0 : 1;
   const int q1 = mode == RM_PW ? 0 : use_outer ? 1 : (mode == RM_ITER || mode == RM_NONE) ? 3 : 2;
+  // all slots in one pass, so every load of a thread is in flight together
+  // (unused slots are read too and ignored: the columns are short)
+  const double* __restrict__ base = P.partial + (int64_t)b * P.G;
+  const int64_t qs = (int64_t)P.B * P.G;
   double v[4] = {0, 0, 0, 0};
+#pragma unroll 2
+  for (int g = t; g < P.G; g += NT) {
+    double x[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (q < q0 || q > q1) continue;
-    const double* __restrict__ base = P.partial + ((int64_t)q * P.B + b) * P.G;
-    double acc = 0.0;
-    for (int g = t; g < P.G; g += NT) acc += base[g];
-    v[q] = wave_total(acc);
+    for (int q = 0; q < 4; ++q) x[q] = base[q * qs + g];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] += x[q];
   }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = (q < q0 || q > q1) ? 0.0 : wave_total(v[q]);
   if ((t & 63) == 0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) red[t >> 6][q] = v[q];
@@ -252,7 +260,7 @@ struct Plan {
   KernelSet<T> ks{};
   bool asm_path = false;
   unsigned grid = 0;
-  bool wide_reduce = false;  // 1024-thread reduction blocks (small batches)
+  size_t lds = 0;          // dynamic LDS of the row kernels (block pre-sum of partials)
   int cfg = 0;            // tile configuration (index into kCfgs)
   int max_chain_q = 0;    // largest chain length over shifts
   std::vector<int> clen;  // host copy
@@ -262,10 +270,7 @@ struct Plan {
 // One reduction block per system.
 template <typename T>
 static void reduce(const Plan<T>& P, int mode) {
-  if (P.wide_reduce)
-    k_reduce<1024><<<(unsigned)P.a.B, 1024, 0, P.ctx->stream>>>(P.red, mode);
-  else
-    k_reduce<256><<<(unsigned)P.a.B, 256, 0, P.ctx->stream>>>(P.red, mode);
+  k_reduce<kReduceThreads><<<(unsigned)P.a.B, kReduceThreads, 0, P.ctx->stream>>>(P.red, mode);
 }
 
 // Profiled solves only: count the systems and shifts the next row kernels
@@ -300,13 +305,13 @@ static airga_status iteration(Plan<T>& P, Timer& tm, int par) {
   const unsigned B = (unsigned)P.a.B;
   AIRGA_TRY(count_work(P, tm, true));
   if (P.asm_path)
-    TIMED(K_DIR_SPMV, P.ks.dir_asm<<<P.grid, 256, 0, st>>>(P.a, par));
+    TIMED(K_DIR_SPMV, P.ks.dir_asm<<<P.grid, 256, P.lds, st>>>(P.a, par));
   else
-    TIMED(K_DIR_SPMV, P.ks.dir<<<P.grid, 256, 0, st>>>(P.a, par));
+    TIMED(K_DIR_SPMV, P.ks.dir<<<P.grid, 256, P.lds, st>>>(P.a, par));
   TIMED(K_REDUCE, reduce(P, RM_PW));
-  TIMED(K_UPDATE_PREC, P.ks.upd<<<P.grid, 256, 0, st>>>(P.a, par));
+  TIMED(K_UPDATE_PREC, P.ks.upd<<<P.grid, 256, P.lds, st>>>(P.a, par));
   for (int q = 1; q < P.max_chain_q; ++q)
-    TIMED(K_CHAIN, P.ks.chain<<<P.grid, 256, 0, st>>>(P.a, par, q, 0));
+    TIMED(K_CHAIN, P.ks.chain<<<P.grid, 256, P.lds, st>>>(P.a, par, q, 0));
   TIMED(K_REDUCE, reduce(P, RM_ITER));
   return AIRGA_OK;
 }
@@ -315,9 +320,9 @@ template <typename T>
 static airga_status start_inner(Plan<T>& P, Timer& tm, int rel) {
   hipStream_t st = P.ctx->stream;
   AIRGA_TRY(count_work(P, tm, false));
-  TIMED(K_INIT_PREC, P.ks.init<<<P.grid, 256, 0, st>>>(P.a, 0));
+  TIMED(K_INIT_PREC, P.ks.init<<<P.grid, 256, P.lds, st>>>(P.a, 0));
   for (int q = 1; q < P.max_chain_q; ++q)
-    TIMED(K_CHAIN, P.ks.chain<<<P.grid, 256, 0, st>>>(P.a, 0, q, 1));
+    TIMED(K_CHAIN, P.ks.chain<<<P.grid, 256, P.lds, st>>>(P.a, 0, q, 1));
   TIMED(K_REDUCE, reduce(P, rel ? RM_INIT_REL : RM_INIT_ABS));
   return AIRGA_OK;
 }
@@ -432,7 +437,11 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
   // memory
   const size_t vec_bytes = sizeof(T) * (size_t)KINDS * B * ld;
   AIRGA_TRY(ctx->ws_vec.reserve(vec_bytes));
-  AIRGA_TRY(ctx->ws_partial.reserve(sizeof(double) * (size_t)B * G * kSlots));
+  // partial columns: one per block when its 4 wavefronts pre-sum in LDS
+  const unsigned grid = blocks_for(G, 4);
+  const bool blk = partial_lds_bytes(B) <= 64 * 1024;
+  const int GP = blk ? (int)grid : 4 * (int)grid;
+  AIRGA_TRY(ctx->ws_partial.reserve(sizeof(double) * (size_t)B * GP * kSlots));
   const size_t sys_bytes = (7 * sizeof(double) + 7 * sizeof(int32_t)) * (size_t)B + 256;
   AIRGA_TRY(ctx->ws_sys.reserve(sys_bytes));
   const size_t shift_bytes = 4 * sizeof(double) * nshift + sizeof(void*) * (size_t)nshift * maxc +
@@ -506,15 +515,17 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
   A.clen = reinterpret_cast<const int32_t*>(sd + off_fac + sizeof(void*) * (size_t)nshift * maxc);
   A.maxc = maxc;
   A.partial = ctx->ws_partial.as<double>();
+  A.GP = GP;
+  A.blk = blk ? 1 : 0;
   A.sys = S;
   P.red.partial = A.partial;
-  P.red.G = G;
+  P.red.G = GP;
   P.red.B = B;
   P.red.sys = S;
   P.red.max_iter = o.max_iter;
   P.red.max_sweeps = o.max_sweeps;
-  P.grid = blocks_for(G, 4);
-  P.wide_reduce = B < 32;
+  P.grid = grid;
+  P.lds = blk ? partial_lds_bytes(B) : 0;
   const bool exact = pen.uniform_width && pen.max_len == wmax_of(wmax_class(pen.max_len));
   P.ks = kernel_set<T>(wmax_class(pen.max_len), exact, cfg);
   P.cfg = cfg;
@@ -562,10 +573,10 @@ static airga_status autotune(airga_ctx ctx, int32_t nshift, const double* shifts
     hipError_t e = hipMemsetAsync(P.a.ws, 0, sizeof(T) * (size_t)KINDS * P.a.B * P.a.ld, st);
     for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
       if (rep == 1) e = hipEventRecord(e0, st);
-      if (asm_path) P.ks.dir_asm<<<P.grid, 256, 0, st>>>(P.a, 0);
-      else P.ks.dir<<<P.grid, 256, 0, st>>>(P.a, 0);
+      if (asm_path) P.ks.dir_asm<<<P.grid, 256, P.lds, st>>>(P.a, 0);
+      else P.ks.dir<<<P.grid, 256, P.lds, st>>>(P.a, 0);
       reduce(P, RM_NONE);
-      P.ks.upd<<<P.grid, 256, 0, st>>>(P.a, 0);
+      P.ks.upd<<<P.grid, 256, P.lds, st>>>(P.a, 0);
       reduce(P, RM_NONE);
     }
     if (e == hipSuccess) e = hipEventRecord(e1, st);
@@ -615,6 +626,20 @@ static airga_status read_stats(airga_ctx ctx, const SysDev& S, int B, bool mixed
   return AIRGA_OK;
 }
 
+// The tile the caller forces (opts.tile_rows/tile_sys), if any.
+static airga_status forced_cfg(const Pencil& pen, const airga_pcg_opts& o, int* cfg) {
+  *cfg = -1;
+  if (o.tile_rows == 0 && o.tile_sys == 0) return AIRGA_OK;
+  const int wc = wmax_class(pen.max_len);
+  for (int c = 0; c < kNumCfgs; ++c)
+    if (kCfgs[c].rows * kSlice == o.tile_rows && kCfgs[c].sys == o.tile_sys && cfg_allowed(wc, c)) {
+      *cfg = c;
+      return AIRGA_OK;
+    }
+  return fail(AIRGA_EINVAL, "tile (%d rows, %d systems) is not an allowed configuration",
+              o.tile_rows, o.tile_sys);
+}
+
 static airga_status solve_fp64(airga_ctx ctx, int32_t nshift, const double* shifts,
                                const airga_prec* precs, int32_t m, const double* F, int64_t ldf,
                                double* X, int64_t ldx, const airga_pcg_opts& o,
@@ -633,8 +658,10 @@ static airga_status solve_fp64(airga_ctx ctx, int32_t nshift, const double* shif
     AIRGA_HIP(hipGetLastError());
   }
   int cfg = 0;
-  AIRGA_TRY(autotune<double>(ctx, nshift, shifts, precs, m, o, asm_path,
-                             ctx->ws_asm.as<double>(), &cfg));
+  AIRGA_TRY(forced_cfg(pen, o, &cfg));
+  if (cfg < 0)
+    AIRGA_TRY(autotune<double>(ctx, nshift, shifts, precs, m, o, asm_path,
+                               ctx->ws_asm.as<double>(), &cfg));
   Plan<double> P;
   AIRGA_TRY(prepare<double>(ctx, P, nshift, shifts, precs, m, o, cfg));
   if (asm_path) {
@@ -647,7 +674,7 @@ static airga_status solve_fp64(airga_ctx ctx, int32_t nshift, const double* shif
   P.red.tol2_rel = o.tol * o.tol;
   Timer tm{ctx, o.profile != 0, {}, {}};
   const int x0 = o.x0_given ? 1 : 0;
-  TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, 0, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, x0,
+  TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, x0,
                                                          1 - x0, x0 ? 2 : 1));
   TIMED(K_REDUCE, reduce(P, RM_START));
   AIRGA_TRY(start_inner(P, tm, 0));
@@ -655,7 +682,7 @@ static airga_status solve_fp64(airga_ctx ctx, int32_t nshift, const double* shif
   // result out, then its true residual
   TIMED(K_IR_UPDATE, (k_copy_out<<<dim3(blocks_for(pen.n, 256), (unsigned)B), 256, 0, st>>>(
                          P.a.ws + (int64_t)KX * B * P.a.ld, P.a.ld, pen.n, X, ldx)));
-  TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, 0, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, 1, 0, 0));
+  TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, 1, 0, 0));
   TIMED(K_REDUCE, reduce(P, RM_FINAL));
   AIRGA_TRY(tm.flush());
   return read_stats(ctx, P.a.sys, B, false, stats);
@@ -669,7 +696,8 @@ static airga_status solve_mixed(airga_ctx ctx, int32_t nshift, const double* shi
   hipStream_t st = ctx->stream;
   const int B = nshift * m;
   int cfg = 0;
-  AIRGA_TRY(autotune<float>(ctx, nshift, shifts, precs, m, o, false, nullptr, &cfg));
+  AIRGA_TRY(forced_cfg(pen, o, &cfg));
+  if (cfg < 0) AIRGA_TRY(autotune<float>(ctx, nshift, shifts, precs, m, o, false, nullptr, &cfg));
   Plan<float> P;
   AIRGA_TRY(prepare<float>(ctx, P, nshift, shifts, precs, m, o, cfg));
   const double* ca64 = reinterpret_cast<const double*>(ctx->ws_shift.ptr);
@@ -680,7 +708,7 @@ static airga_status solve_mixed(airga_ctx ctx, int32_t nshift, const double* shi
   int32_t* h_nact = reinterpret_cast<int32_t*>(static_cast<char*>(ctx->host_pinned) + P.flags_off);
   const int x0 = o.x0_given ? 1 : 0;
   // sweep 0 residual; RM_OUTER then activates the systems to refine
-  TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, 0, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, x0,
+  TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, x0,
                                                          1 - x0, 1));
   k_clear_active<<<blocks_for(B, 256), 256, 0, st>>>(P.a.sys, B);
   AIRGA_HIP(hipGetLastError());
@@ -693,7 +721,7 @@ static airga_status solve_mixed(airga_ctx ctx, int32_t nshift, const double* shi
     AIRGA_TRY(iterate(P, tm, o));
     TIMED(K_IR_UPDATE,
           (k_ir_update<<<dim3(blocks_for(pen.n, 256), (unsigned)B), 256, 0, st>>>(P.a, X, ldx)));
-    TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, 0, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, 1, 0, 1));
+    TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, 1, 0, 1));
     TIMED(K_REDUCE, reduce(P, RM_OUTER));
   }
   AIRGA_TRY(tm.flush());

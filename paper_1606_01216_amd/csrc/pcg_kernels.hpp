@@ -57,15 +57,44 @@ struct SolveArgs {
   const T* const* fac;       // per shift [maxc] factor values, fac[sh * maxc + q], oldest first
   const int32_t* clen;       // per shift number of applied factors
   int32_t maxc;
-  double* partial;           // [kSlots][B][G], slot-major
+  double* partial;           // [kSlots][B][GP], slot-major
+  int32_t GP;                // partial columns per system (blocks if blk, else wavefronts)
+  int32_t blk;               // 1: the 4 wavefronts of a block pre-sum their partials in LDS
   SysDev sys;
   __device__ __forceinline__ T* vec(int kind, int b) const {
     return ws + ((int64_t)kind * B + b) * ld;
   }
   __device__ __forceinline__ double& slot(int q, int b, int g) const {
-    return partial[((int64_t)q * B + b) * G + g];
+    return partial[((int64_t)q * B + b) * GP + g];
+  }
+  // Wave partial of slot q for system b (lane 0 holds the wave total).
+  __device__ __forceinline__ void put(double* lds, int q, int b, int wg, int lane, double v) const {
+    if (lane != 0) return;
+    if (blk) lds[((int)(threadIdx.x >> 6) * B + b) * kSlots + q] = v;
+    else slot(q, b, wg) = v;
   }
 };
+
+// Bytes of LDS a row kernel needs for the block pre-sum.
+inline size_t partial_lds_bytes(int B) { return sizeof(double) * 4 * kSlots * (size_t)B; }
+
+// End of a row kernel in block mode: every (system, slot) the kernel wrote,
+// as chosen by sel(b), gets the sum of its 4 wave partials in wave order.
+template <typename T, typename Sel>
+__device__ __forceinline__ void flush_partials(const SolveArgs<T>& A, const double* lds, int q0,
+                                               int q1, Sel sel) {
+  if (!A.blk) return;
+  __syncthreads();
+  const int nq = q1 - q0 + 1;
+  for (int idx = threadIdx.x; idx < A.B * nq; idx += blockDim.x) {
+    const int b = idx / nq, q = q0 + idx % nq;
+    if (!sel(b)) continue;
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) s += lds[(w * A.B + b) * kSlots + q];
+    A.slot(q, b, blockIdx.x) = s;
+  }
+}
 
 // Buffer written by chain position q (0 = the fused first factor) for a chain
 // of L factors: the last one lands in KZ, earlier ones alternate with KT.
@@ -146,7 +175,7 @@ template <typename T, int WMAX, int R, int U, bool ASM, bool EXACT>
 __global__ void __launch_bounds__(256) k_dir_spmv(SolveArgs<T> A, int par) {
   const int lane = threadIdx.x & 63;
   const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (wg >= A.G) return;
+  extern __shared__ double lds_part[];
   Rows<WMAX, R, EXACT> rows;
   rows.load(A.pd, wg, lane);
   T mv[R][WMAX], kv[R][WMAX];
@@ -203,9 +232,10 @@ __global__ void __launch_bounds__(256) k_dir_spmv(SolveArgs<T> A, int par) {
         dot = fma(pr[u][i], wr[u][i], dot);
       }
       dot = wave_total(dot);
-      if (lane == 0) A.slot(0, b, wg) = (double)dot;
+      A.put(lds_part, 0, b, wg, lane, (double)dot);
     }
   }
+  flush_partials(A, lds_part, 0, 0, [&](int b) { return A.sys.active[b] != 0; });
 }
 
 // ---- B: x/r update + first preconditioner factor + dots -------------------
@@ -214,7 +244,7 @@ template <typename T, int WMAX, int R, int U, bool INIT, bool EXACT>
 __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
   const int lane = threadIdx.x & 63;
   const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (wg >= A.G) return;
+  extern __shared__ double lds_part[];
   Rows<WMAX, R, EXACT> rows;
   rows.load(A.pd, wg, lane);
   FlagSweep sweep(A.sys.active, A.B);
@@ -287,13 +317,12 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
       rr = wave_total(rr);
       rz = wave_total(rz);
       zw = wave_total(zw);
-      if (lane == 0) {
-        A.slot(1, b, wg) = (double)rr;
-        A.slot(2, b, wg) = L > 1 ? 0.0 : (double)rz;
-        A.slot(3, b, wg) = L > 1 ? 0.0 : (double)zw;
-      }
+      A.put(lds_part, 1, b, wg, lane, (double)rr);
+      A.put(lds_part, 2, b, wg, lane, L > 1 ? 0.0 : (double)rz);
+      A.put(lds_part, 3, b, wg, lane, L > 1 ? 0.0 : (double)zw);
     }
   }
+  flush_partials(A, lds_part, 1, 3, [&](int b) { return A.sys.active[b] != 0; });
 }
 
 // ---- chain factor q >= 1 (Q_{q+1} of the update chain) ---------------------
@@ -301,7 +330,7 @@ template <typename T, int WMAX, int R, bool EXACT>
 __global__ void __launch_bounds__(256) k_chain(SolveArgs<T> A, int par, int q, int init) {
   const int lane = threadIdx.x & 63;
   const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (wg >= A.G) return;
+  extern __shared__ double lds_part[];
   Rows<WMAX, R, EXACT> rows;
   rows.load(A.pd, wg, lane);
   const int rk = init ? KR0 : KR0 + (par ^ 1);
@@ -340,12 +369,12 @@ __global__ void __launch_bounds__(256) k_chain(SolveArgs<T> A, int par, int q, i
     if (last) {
       rz = wave_total(rz);
       zw = wave_total(zw);
-      if (lane == 0) {
-        A.slot(2, b, wg) = (double)rz;
-        A.slot(3, b, wg) = (double)zw;
-      }
+      A.put(lds_part, 2, b, wg, lane, (double)rz);
+      A.put(lds_part, 3, b, wg, lane, (double)zw);
     }
   }
+  flush_partials(A, lds_part, 2, 3,
+                 [&](int b) { return A.sys.active[b] != 0 && A.clen[b / A.m] == q + 1; });
 }
 
 // ---- float64 residual r = F - K(s) X (and |F|^2), output in TO -------------
@@ -360,7 +389,7 @@ __global__ void __launch_bounds__(256) k_residual(SolveArgs<TO> A, const double*
                                                   int xzero, int kx) {
   const int lane = threadIdx.x & 63;
   const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (wg >= A.G) return;
+  extern __shared__ double lds_part[];
   Rows<WMAX, R, EXACT> rows;
   rows.load(A.pd, wg, lane);
   double mv[R][WMAX], kv[R][WMAX];
@@ -421,12 +450,11 @@ __global__ void __launch_bounds__(256) k_residual(SolveArgs<TO> A, const double*
       }
       rr = wave_total(rr);
       ff = wave_total(ff);
-      if (lane == 0) {
-        A.slot(0, b, wg) = rr;
-        A.slot(1, b, wg) = ff;
-      }
+      A.put(lds_part, 0, b, wg, lane, rr);
+      A.put(lds_part, 1, b, wg, lane, ff);
     }
   }
+  flush_partials(A, lds_part, 0, 1, [&](int b) { return A.sys.outer[b] != 0; });
 }
 
 // ------------------------------------------------------------- dispatch
