@@ -143,6 +143,10 @@ typedef struct {
                           S = diag(K(s))^{-1/2} and map back (default 1)      */
   int32_t symmetrize;  /* build only, 1: replace Phat by (Phat + Phat^T)/2
                           before mapping back (default 1)                      */
+  int32_t general_only; /* 1: the general column kernels even for a pencil of
+                          bandwidth <= 64 (whose kernels otherwise stage the
+                          rows in LDS; same arithmetic, same results)          */
+  int32_t reserved;
 } airga_spai_opts;
 
 AIRGA_API void airga_spai_opts_default(airga_spai_opts* opts);
@@ -219,7 +223,9 @@ typedef struct {
                           matrix rows per wavefront (64, 128 or 256) ...        */
   int32_t tile_sys;    /* ... and systems per group (1, 2 or 4) of an allowed
                           tile (see airga_get_tile_config); EINVAL if not one   */
-  int32_t reserved;
+  int32_t general_only; /* 1: general sliced-ELL kernels even for a pencil of
+                          bandwidth <= 64 (whose kernels otherwise stage the
+                          neighbour entries in LDS; same arithmetic)             */
 } airga_pcg_opts;
 
 AIRGA_API void airga_pcg_opts_default(airga_pcg_opts* opts);

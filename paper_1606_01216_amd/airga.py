@@ -43,7 +43,8 @@ class PencilInfo(ctypes.Structure):
 
 class SpaiOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("equilibrate", ctypes.c_int32),
-                ("symmetrize", ctypes.c_int32)]
+                ("symmetrize", ctypes.c_int32), ("general_only", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class PrecInfo(ctypes.Structure):
@@ -58,7 +59,7 @@ class PcgOpts(ctypes.Structure):
                 ("max_sweeps", ctypes.c_int32), ("poll_every", ctypes.c_int32),
                 ("x0_given", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-                ("tile_sys", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tile_sys", ctypes.c_int32), ("general_only", ctypes.c_int32)]
 
 
 class SysStats(ctypes.Structure):
@@ -228,25 +229,28 @@ class Context:
 
     # ------------------------------------------------------- preconditioners
     @staticmethod
-    def _spai_opts(tol, equilibrate, symmetrize):
+    def _spai_opts(tol, equilibrate, symmetrize, general_only=False):
         o = SpaiOpts()
         lib().airga_spai_opts_default(ctypes.byref(o))
         if tol is not None:
             o.tol = float(tol)
         o.equilibrate = int(bool(equilibrate))
         o.symmetrize = int(bool(symmetrize))
+        o.general_only = int(bool(general_only))
         return o
 
-    def spai_build(self, s: float, *, equilibrate=True, symmetrize=True) -> "Prec":
-        o = self._spai_opts(None, equilibrate, symmetrize)
+    def spai_build(self, s: float, *, equilibrate=True, symmetrize=True,
+                   general_only=False) -> "Prec":
+        o = self._spai_opts(None, equilibrate, symmetrize, general_only)
         h = ctypes.c_void_p()
         self._enter()
         _check(lib().airga_spai_build(self._h, float(s), ctypes.byref(o), ctypes.byref(h)))
         self._leave()
         return Prec(self, h)
 
-    def spai_update(self, old: "Prec", s_new: float, *, tol=0.01, equilibrate=True) -> "Prec":
-        o = self._spai_opts(tol, equilibrate, False)
+    def spai_update(self, old: "Prec", s_new: float, *, tol=0.01, equilibrate=True,
+                    general_only=False) -> "Prec":
+        o = self._spai_opts(tol, equilibrate, False, general_only)
         h = ctypes.c_void_p()
         self._enter()
         _check(lib().airga_spai_update(self._h, old._h, float(s_new), ctypes.byref(o),
@@ -257,7 +261,8 @@ class Context:
     # ---------------------------------------------------------------- solves
     def pcg_solve(self, shifts, precs, F: torch.Tensor, X: torch.Tensor | None = None, *,
                   tol=1e-10, max_iter=20000, mode=MODE_FP64, inner_tol=1e-4, max_sweeps=12,
-                  poll_every=8, x0_given=False, use_graph=True, profile=False, tile=None):
+                  poll_every=8, x0_given=False, use_graph=True, profile=False, tile=None,
+                  general_only=False):
         """Solve K(s_k) X[k, c] = F[c] for all shifts k and columns c.
 
         F: (m, n) float64 on the device; X: (nshift, m, n) float64 (allocated
@@ -285,6 +290,7 @@ class Context:
         o.tol, o.max_iter, o.mode = float(tol), int(max_iter), int(mode)
         o.inner_tol, o.max_sweeps, o.poll_every = float(inner_tol), int(max_sweeps), int(poll_every)
         o.x0_given, o.use_graph, o.profile = int(bool(x0_given)), int(bool(use_graph)), int(bool(profile))
+        o.general_only = int(bool(general_only))
         if tile is not None:
             o.tile_rows, o.tile_sys = int(tile[0]), int(tile[1])
         stats = (SysStats * (nshift * m))()

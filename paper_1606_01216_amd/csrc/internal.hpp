@@ -265,6 +265,14 @@ __device__ __forceinline__ T wave_total(T v) {
 // Make a wavefront-uniform value scalar (it then lives in an SGPR).
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Load of a wave-uniform address through the constant address space, so it
+// becomes a scalar load: it is counted apart from the vector loads in flight
+// and does not wait for them.  For data no kernel writes while it runs.
+template <typename V>
+__device__ __forceinline__ V sload(const V* p) {
+  return *(const __attribute__((address_space(4))) V*)p;
+}
+
 // Launch-size helper.
 inline unsigned blocks_for(int64_t work, int per_block) {
   return (unsigned)((work + per_block - 1) / per_block);

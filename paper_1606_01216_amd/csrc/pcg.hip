@@ -260,7 +260,8 @@ struct Plan {
   KernelSet<T> ks{};
   bool asm_path = false;
   unsigned grid = 0;
-  size_t lds = 0;          // dynamic LDS of the row kernels (block pre-sum of partials)
+  size_t lds = 0;          // dynamic LDS of the row kernels (partial pre-sum + windows)
+  size_t lds_res = 0;      // same for the float64 residual kernel
   int cfg = 0;            // tile configuration (index into kCfgs)
   int max_chain_q = 0;    // largest chain length over shifts
   std::vector<int> clen;  // host copy
@@ -439,7 +440,11 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
   AIRGA_TRY(ctx->ws_vec.reserve(vec_bytes));
   // partial columns: one per block when its 4 wavefronts pre-sum in LDS
   const unsigned grid = blocks_for(G, 4);
-  const bool blk = partial_lds_bytes(B) <= 64 * 1024;
+  const int wc = wmax_class(pen.max_len);
+  const bool band = !o.general_only && wc < 2 && pen.bandwidth <= kBandMax;
+  const size_t win = band ? window_lds_bytes(sizeof(T), rows, kCfgs[cfg].sys) : 0;
+  const size_t win_res = band ? window_lds_bytes(sizeof(double), rows, kCfgs[cfg].sys) : 0;
+  const bool blk = partial_lds_bytes(B) + (win > win_res ? win : win_res) <= 64 * 1024;
   const int GP = blk ? (int)grid : 4 * (int)grid;
   AIRGA_TRY(ctx->ws_partial.reserve(sizeof(double) * (size_t)B * GP * kSlots));
   const size_t sys_bytes = (7 * sizeof(double) + 7 * sizeof(int32_t)) * (size_t)B + 256;
@@ -525,9 +530,13 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
   P.red.max_iter = o.max_iter;
   P.red.max_sweeps = o.max_sweeps;
   P.grid = grid;
-  P.lds = blk ? partial_lds_bytes(B) : 0;
+  const size_t part = blk ? partial_lds_bytes(B) : 0;
+  P.lds = part + win;
+  P.lds_res = part + win_res;
+  A.bw = pen.bandwidth;
+  A.stage_off = (int32_t)(part / sizeof(double));
   const bool exact = pen.uniform_width && pen.max_len == wmax_of(wmax_class(pen.max_len));
-  P.ks = kernel_set<T>(wmax_class(pen.max_len), exact, cfg);
+  P.ks = kernel_set<T>(wc, exact, band, cfg);
   P.cfg = cfg;
   ctx->last_cfg = cfg;
   return AIRGA_OK;
@@ -674,7 +683,7 @@ static airga_status solve_fp64(airga_ctx ctx, int32_t nshift, const double* shif
   P.red.tol2_rel = o.tol * o.tol;
   Timer tm{ctx, o.profile != 0, {}, {}};
   const int x0 = o.x0_given ? 1 : 0;
-  TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, x0,
+  TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds_res, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, x0,
                                                          1 - x0, x0 ? 2 : 1));
   TIMED(K_REDUCE, reduce(P, RM_START));
   AIRGA_TRY(start_inner(P, tm, 0));
@@ -682,7 +691,7 @@ static airga_status solve_fp64(airga_ctx ctx, int32_t nshift, const double* shif
   // result out, then its true residual
   TIMED(K_IR_UPDATE, (k_copy_out<<<dim3(blocks_for(pen.n, 256), (unsigned)B), 256, 0, st>>>(
                          P.a.ws + (int64_t)KX * B * P.a.ld, P.a.ld, pen.n, X, ldx)));
-  TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, 1, 0, 0));
+  TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds_res, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, 1, 0, 0));
   TIMED(K_REDUCE, reduce(P, RM_FINAL));
   AIRGA_TRY(tm.flush());
   return read_stats(ctx, P.a.sys, B, false, stats);
@@ -708,7 +717,7 @@ static airga_status solve_mixed(airga_ctx ctx, int32_t nshift, const double* shi
   int32_t* h_nact = reinterpret_cast<int32_t*>(static_cast<char*>(ctx->host_pinned) + P.flags_off);
   const int x0 = o.x0_given ? 1 : 0;
   // sweep 0 residual; RM_OUTER then activates the systems to refine
-  TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, x0,
+  TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds_res, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, x0,
                                                          1 - x0, 1));
   k_clear_active<<<blocks_for(B, 256), 256, 0, st>>>(P.a.sys, B);
   AIRGA_HIP(hipGetLastError());
@@ -721,7 +730,7 @@ static airga_status solve_mixed(airga_ctx ctx, int32_t nshift, const double* shi
     AIRGA_TRY(iterate(P, tm, o));
     TIMED(K_IR_UPDATE,
           (k_ir_update<<<dim3(blocks_for(pen.n, 256), (unsigned)B), 256, 0, st>>>(P.a, X, ldx)));
-    TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, 1, 0, 1));
+    TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds_res, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, 1, 0, 1));
     TIMED(K_REDUCE, reduce(P, RM_OUTER));
   }
   AIRGA_TRY(tm.flush());

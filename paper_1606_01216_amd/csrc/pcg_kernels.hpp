@@ -60,6 +60,8 @@ struct SolveArgs {
   double* partial;           // [kSlots][B][GP], slot-major
   int32_t GP;                // partial columns per system (blocks if blk, else wavefronts)
   int32_t blk;               // 1: the 4 wavefronts of a block pre-sum their partials in LDS
+  int32_t bw;                // pencil bandwidth max |c - r| (banded kernels: <= 64)
+  int32_t stage_off;         // doubles of dynamic LDS before the banded staging area
   SysDev sys;
   __device__ __forceinline__ T* vec(int kind, int b) const {
     return ws + ((int64_t)kind * B + b) * ld;
@@ -170,8 +172,61 @@ struct FlagSweep {
   }
 };
 
+// Banded staging (pencils of bandwidth <= 64).  A wavefront's R slices and
+// the bw rows on each side of them are staged in LDS, one (R + 2) x 64
+// window per system of the group, so the column entries of a row are read
+// from LDS instead of being gathered from global memory.  Window row j holds
+// global row base - 64 + 64 j + lane; with bandwidth <= 64 every column of an
+// own row lies in the window.  Loads are issued for every lane (a lane whose
+// row is not needed reads an own row instead, already in cache) and the
+// value is dropped by a select, so the staging loads have no branches.
+template <int WMAX, int R>
+struct Window {
+  int off[R][WMAX];  // window index of each entry's column
+  int64_t base;      // first own row
+  int64_t src[R + 2];  // row each lane loads for window row j
+  bool keep[R + 2];    // lane's window row j is needed
+  template <bool EXACT>
+  __device__ __forceinline__ void init(const Rows<WMAX, R, EXACT>& rows, int wg, int n_slices,
+                                       int bw, int lane) {
+    base = (int64_t)wg * R * kSlice;
+    const bool pre = wg > 0 && wg * R <= n_slices;
+    const bool post = (int64_t)wg * R + R < n_slices;
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+      for (int k = 0; k < WMAX; ++k)
+        off[i][k] = rows.valid[i] ? (int)(rows.col[i][k] - base) + kSlice : (i + 1) * kSlice + lane;
+#pragma unroll
+    for (int j = 0; j < R + 2; ++j) {
+      const int64_t row = base - kSlice + (int64_t)j * kSlice + lane;
+      if (j == 0) keep[j] = pre && lane >= kSlice - bw;
+      else if (j == R + 1) keep[j] = post && lane < bw;
+      else keep[j] = rows.valid[j - 1];
+      // fallback: an own row of the same lane (its first or last valid
+      // slice), or row `lane` for a wavefront past the end
+      const int64_t own = j == 0 ? rows.row[0] : j == R + 1 ? rows.row[R - 1] : rows.row[j - 1];
+      src[j] = keep[j] ? row : own;
+    }
+  }
+};
+
+template <typename T, int R>
+__device__ __forceinline__ T* window_base(double* lds, const SolveArgs<T>& A, int U) {
+  return reinterpret_cast<T*>(lds + A.stage_off) + (int)(threadIdx.x >> 6) * U * (R + 2) * kSlice;
+}
+template <typename TS, int R>
+__device__ __forceinline__ TS* window_base_as(double* lds, int stage_off, int U) {
+  return reinterpret_cast<TS*>(lds + stage_off) + (int)(threadIdx.x >> 6) * U * (R + 2) * kSlice;
+}
+
+// Bytes of LDS for the windows of one block (4 wavefronts, U systems).
+inline size_t window_lds_bytes(size_t elem, int R, int U) {
+  return elem * 4 * (size_t)U * (R + 2) * kSlice;
+}
+
 // ---- A: direction update + shifted SpMV + (p, w) -------------------------
-template <typename T, int WMAX, int R, int U, bool ASM, bool EXACT>
+template <typename T, int WMAX, int R, int U, bool ASM, bool EXACT, bool BAND>
 __global__ void __launch_bounds__(256) k_dir_spmv(SolveArgs<T> A, int par) {
   const int lane = threadIdx.x & 63;
   const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
@@ -181,39 +236,92 @@ __global__ void __launch_bounds__(256) k_dir_spmv(SolveArgs<T> A, int par) {
   T mv[R][WMAX], kv[R][WMAX];
   rows.values(A.mv, mv);
   if constexpr (!ASM) rows.values(A.kv, kv);
+  Window<WMAX, R> win;
+  T* stg = nullptr;
+  if constexpr (BAND) {
+    win.init(rows, wg, A.pd.n_slices, A.bw, lane);
+    stg = window_base<T, R>(lds_part, A, U);
+  }
   FlagSweep sweep(A.sys.active, A.B);
   int bs[U];
   while (sweep.next(bs, lane)) {
     T pr[U][R], wr[U][R];
-    // compute phase: no branches, so every load of the group can be in
-    // flight at once (a missing system aliases the group's first one)
+    if constexpr (BAND) {
+      // p_new over the window of each system, then the SpMV from LDS
+      T pw[U][R + 2];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int b = bs[u] >= 0 ? bs[u] : bs[0];
-      const bool first = A.sys.first[b] != 0;
-      const T beta = first ? T(0) : (T)A.sys.beta[b];
-      T ca = T(1), cb = T(0);
-      if constexpr (!ASM) {
-        ca = A.ca[b / A.m];
-        cb = A.cb[b / A.m];
-      }
-      const T* __restrict__ z = A.vec(KZ, b);
-      const T* __restrict__ pin = A.vec(KP0 + par, b);
+      for (int u = 0; u < U; ++u) {
+        const int b = bs[u] >= 0 ? bs[u] : bs[0];
+        const bool first = sload(A.sys.first + b) != 0;
+        const T beta = first ? T(0) : (T)sload(A.sys.beta + b);
+        const T* __restrict__ z = A.vec(KZ, b);
+        const T* __restrict__ pin = A.vec(KP0 + par, b);
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
-        T am = T(0), ak = T(0);
-#pragma unroll
-        for (int k = 0; k < WMAX; ++k) {
-          const int c = rows.col[i][k];
-          const T po = pin[c];
-          const T pc = fma(beta, first ? T(0) : po, z[c]);
-          am = fma(mv[i][k], pc, am);
-          if constexpr (!ASM) ak = fma(kv[i][k], pc, ak);
+        for (int j = 0; j < R + 2; ++j) {
+          const T po = pin[win.src[j]];
+          pw[u][j] = fma(beta, first ? T(0) : po, z[win.src[j]]);
         }
-        const int64_t r = rows.row[i];
-        const T po = pin[r];
-        pr[u][i] = fma(beta, first ? T(0) : po, z[r]);
-        wr[u][i] = ASM ? am : fma(ca, am, cb * ak);
+      }
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int j = 0; j < R + 2; ++j)
+          stg[(u * (R + 2) + j) * kSlice + lane] = win.keep[j] ? pw[u][j] : T(0);
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int b = bs[u] >= 0 ? bs[u] : bs[0];
+        T ca = T(1), cb = T(0);
+        if constexpr (!ASM) {
+          ca = sload(A.ca + b / A.m);
+          cb = sload(A.cb + b / A.m);
+        }
+        const T* w0 = stg + u * (R + 2) * kSlice;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          T am = T(0), ak = T(0);
+#pragma unroll
+          for (int k = 0; k < WMAX; ++k) {
+            const T pc = w0[win.off[i][k]];
+            am = fma(mv[i][k], pc, am);
+            if constexpr (!ASM) ak = fma(kv[i][k], pc, ak);
+          }
+          pr[u][i] = pw[u][i + 1];
+          wr[u][i] = ASM ? am : fma(ca, am, cb * ak);
+        }
+      }
+    } else {
+      // compute phase: no branches, so every load of the group can be in
+      // flight at once (a missing system aliases the group's first one)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int b = bs[u] >= 0 ? bs[u] : bs[0];
+        const bool first = sload(A.sys.first + b) != 0;
+        const T beta = first ? T(0) : (T)sload(A.sys.beta + b);
+        T ca = T(1), cb = T(0);
+        if constexpr (!ASM) {
+          ca = sload(A.ca + b / A.m);
+          cb = sload(A.cb + b / A.m);
+        }
+        const T* __restrict__ z = A.vec(KZ, b);
+        const T* __restrict__ pin = A.vec(KP0 + par, b);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          T am = T(0), ak = T(0);
+#pragma unroll
+          for (int k = 0; k < WMAX; ++k) {
+            const int c = rows.col[i][k];
+            const T po = pin[c];
+            const T pc = fma(beta, first ? T(0) : po, z[c]);
+            am = fma(mv[i][k], pc, am);
+            if constexpr (!ASM) ak = fma(kv[i][k], pc, ak);
+          }
+          const int64_t r = rows.row[i];
+          const T po = pin[r];
+          pr[u][i] = fma(beta, first ? T(0) : po, z[r]);
+          wr[u][i] = ASM ? am : fma(ca, am, cb * ak);
+        }
       }
     }
 #pragma unroll
@@ -240,13 +348,19 @@ __global__ void __launch_bounds__(256) k_dir_spmv(SolveArgs<T> A, int par) {
 
 // ---- B: x/r update + first preconditioner factor + dots -------------------
 // INIT: no update; r is R0 as produced by the residual kernel.
-template <typename T, int WMAX, int R, int U, bool INIT, bool EXACT>
+template <typename T, int WMAX, int R, int U, bool INIT, bool EXACT, bool BAND>
 __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
   const int lane = threadIdx.x & 63;
   const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
   extern __shared__ double lds_part[];
   Rows<WMAX, R, EXACT> rows;
   rows.load(A.pd, wg, lane);
+  Window<WMAX, R> win;
+  T* stg = nullptr;
+  if constexpr (BAND) {
+    win.init(rows, wg, A.pd.n_slices, A.bw, lane);
+    stg = window_base<T, R>(lds_part, A, U);
+  }
   FlagSweep sweep(A.sys.active, A.B);
   int bs[U];
   while (sweep.next(bs, lane)) {
@@ -258,38 +372,93 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
     T pv[U][R][WMAX];
     int Ls[U];
     T rn[U][R], tz[U][R], xn[U][R], wrr[U][R];
+    if constexpr (BAND) {
+      // r_new over the window of each system, then the factor from LDS
+      T rw[U][R + 2], ww[U][R + 2];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int b = bs[u] >= 0 ? bs[u] : bs[0];
-      const int sh = b / A.m;
-      Ls[u] = A.clen[sh];
-      rows.values(A.fac[(int64_t)sh * A.maxc], pv[u]);
-      const T al = INIT ? T(0) : (T)A.sys.alpha[b];
-      const T* __restrict__ rin = A.vec(INIT ? KR0 : KR0 + par, b);
-      const T* __restrict__ wv = A.vec(KW, b);
-      const T* __restrict__ pcur = A.vec(KP0 + (par ^ 1), b);
-      const T* __restrict__ x = A.vec(KX, b);
+      for (int u = 0; u < U; ++u) {
+        const int b = bs[u] >= 0 ? bs[u] : bs[0];
+        const int sh = b / A.m;
+        Ls[u] = sload(A.clen + sh);
+        rows.values(sload(A.fac + (int64_t)sh * A.maxc), pv[u]);
+        const T al = INIT ? T(0) : (T)sload(A.sys.alpha + b);
+        const T* __restrict__ rin = A.vec(INIT ? KR0 : KR0 + par, b);
+        const T* __restrict__ wv = A.vec(KW, b);
+        const T* __restrict__ pcur = A.vec(KP0 + (par ^ 1), b);
+        const T* __restrict__ x = A.vec(KX, b);
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const int64_t r = rows.row[i];
-        T wr = T(0), v;
-        if constexpr (INIT) {
-          v = rin[r];
-        } else {
-          wr = wv[r];
-          v = fma(-al, wr, rin[r]);
-          xn[u][i] = fma(al, pcur[r], x[r]);
+        for (int j = 0; j < R + 2; ++j) {
+          const T rv = rin[win.src[j]];
+          if constexpr (INIT) {
+            ww[u][j] = T(0);
+            rw[u][j] = rv;
+          } else {
+            ww[u][j] = wv[win.src[j]];
+            rw[u][j] = fma(-al, ww[u][j], rv);
+          }
         }
-        T t = T(0);
+        if constexpr (!INIT) {
 #pragma unroll
-        for (int k = 0; k < WMAX; ++k) {
-          const int cc = rows.col[i][k];
-          const T rc = INIT ? rin[cc] : fma(-al, wv[cc], rin[cc]);
-          t = fma(pv[u][i][k], rc, t);
+          for (int i = 0; i < R; ++i) {
+            const int64_t r = rows.row[i];
+            xn[u][i] = fma(al, pcur[r], x[r]);
+          }
         }
-        rn[u][i] = v;
-        tz[u][i] = t;
-        wrr[u][i] = wr;
+      }
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int j = 0; j < R + 2; ++j)
+          stg[(u * (R + 2) + j) * kSlice + lane] = win.keep[j] ? rw[u][j] : T(0);
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const T* w0 = stg + u * (R + 2) * kSlice;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          T t = T(0);
+#pragma unroll
+          for (int k = 0; k < WMAX; ++k) t = fma(pv[u][i][k], w0[win.off[i][k]], t);
+          rn[u][i] = rw[u][i + 1];
+          tz[u][i] = t;
+          wrr[u][i] = ww[u][i + 1];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int b = bs[u] >= 0 ? bs[u] : bs[0];
+        const int sh = b / A.m;
+        Ls[u] = sload(A.clen + sh);
+        rows.values(sload(A.fac + (int64_t)sh * A.maxc), pv[u]);
+        const T al = INIT ? T(0) : (T)sload(A.sys.alpha + b);
+        const T* __restrict__ rin = A.vec(INIT ? KR0 : KR0 + par, b);
+        const T* __restrict__ wv = A.vec(KW, b);
+        const T* __restrict__ pcur = A.vec(KP0 + (par ^ 1), b);
+        const T* __restrict__ x = A.vec(KX, b);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const int64_t r = rows.row[i];
+          T wr = T(0), v;
+          if constexpr (INIT) {
+            v = rin[r];
+          } else {
+            wr = wv[r];
+            v = fma(-al, wr, rin[r]);
+            xn[u][i] = fma(al, pcur[r], x[r]);
+          }
+          T t = T(0);
+#pragma unroll
+          for (int k = 0; k < WMAX; ++k) {
+            const int cc = rows.col[i][k];
+            const T rc = INIT ? rin[cc] : fma(-al, wv[cc], rin[cc]);
+            t = fma(pv[u][i][k], rc, t);
+          }
+          rn[u][i] = v;
+          tz[u][i] = t;
+          wrr[u][i] = wr;
+        }
       }
     }
 #pragma unroll
@@ -341,10 +510,10 @@ __global__ void __launch_bounds__(256) k_chain(SolveArgs<T> A, int par, int q, i
   while (sweep.next(bs, lane)) {
     const int b = bs[0];
     const int sh = b / A.m;
-    const int L = A.clen[sh];
+    const int L = sload(A.clen + sh);
     if (L <= q) continue;
     if (sh != loaded_sh) {
-      rows.values(A.fac[(int64_t)sh * A.maxc + q], fv);
+      rows.values(sload(A.fac + (int64_t)sh * A.maxc + q), fv);
       loaded_sh = sh;
     }
     const T* __restrict__ src = A.vec(chain_dst(q - 1, L), b);
@@ -380,8 +549,10 @@ __global__ void __launch_bounds__(256) k_chain(SolveArgs<T> A, int par, int q, i
 // ---- float64 residual r = F - K(s) X (and |F|^2), output in TO -------------
 //   xread: 1 = use X, 0 = take X as 0;   xzero: write zeros into X;
 //   kx:    0 = leave the iterate, 1 = zero it, 2 = copy X into it.
-// Rows past n write zeros.  Systems: those with outer[b] set.
-template <typename TO, int WMAX, int R, int U, bool EXACT>
+// Rows past n write zeros.  Systems: those with outer[b] set.  X and F have
+// n rows only, so every index into them is clamped to n - 1 and the value
+// dropped by a select where the row is past n.
+template <typename TO, int WMAX, int R, int U, bool EXACT, bool BAND>
 __global__ void __launch_bounds__(256) k_residual(SolveArgs<TO> A, const double* __restrict__ F,
                                                   int64_t ldf, double* __restrict__ X,
                                                   int64_t ldX, const double* __restrict__ ca64,
@@ -396,37 +567,96 @@ __global__ void __launch_bounds__(256) k_residual(SolveArgs<TO> A, const double*
   rows.values(A.pd.m64, mv);
   rows.values(A.pd.k64, kv);
   const int64_t n = A.pd.n;
+  Window<WMAX, R> win;
+  double* stg = nullptr;
+  if constexpr (BAND) {
+    win.init(rows, wg, A.pd.n_slices, A.bw, lane);
+    stg = window_base_as<double, R>(lds_part, A.stage_off, U);
+  }
   FlagSweep sweep(A.sys.outer, A.B);
   int bs[U];
   while (sweep.next(bs, lane)) {
     double res[U][R], fr[U][R], xo[U][R];
+    double am[U][R], ak[U][R];
+    if (xread) {
+      if constexpr (BAND) {
+        double xw[U][R + 2];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int b = bs[u];
-      if (b < 0) continue;
-      const double a = ca64[b / A.m], cbv = cb64[b / A.m];
-      const double* __restrict__ f = F + (int64_t)(b % A.m) * ldf;
-      const double* __restrict__ x = X + (int64_t)b * ldX;
+        for (int u = 0; u < U; ++u) {
+          const int b = bs[u] >= 0 ? bs[u] : bs[0];
+          const double* __restrict__ x = X + (int64_t)b * ldX;
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
-        res[u][i] = 0.0;
-        fr[u][i] = 0.0;
-        xo[u][i] = 0.0;
-        const int64_t row = rows.row[i];
-        if (rows.valid[i] && row < n) {
-          double am = 0, ak = 0;
-          if (xread) {
+          for (int j = 0; j < R + 2; ++j) {
+            const int64_t rs = win.src[j];
+            xw[u][j] = x[rs < n ? rs : n - 1];
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int j = 0; j < R + 2; ++j)
+            stg[(u * (R + 2) + j) * kSlice + lane] =
+                (win.keep[j] && win.src[j] < n) ? xw[u][j] : 0.0;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const double* w0 = stg + u * (R + 2) * kSlice;
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            double sm = 0, sk = 0;
 #pragma unroll
             for (int k = 0; k < WMAX; ++k) {
-              const double xc = x[rows.col[i][k]];
-              am = fma(mv[i][k], xc, am);
-              ak = fma(kv[i][k], xc, ak);
+              const double xc = w0[win.off[i][k]];
+              sm = fma(mv[i][k], xc, sm);
+              sk = fma(kv[i][k], xc, sk);
             }
-            xo[u][i] = x[row];
+            am[u][i] = sm;
+            ak[u][i] = sk;
+            xo[u][i] = xw[u][i + 1];
           }
-          fr[u][i] = f[row];
-          res[u][i] = fr[u][i] - fma(a, am, cbv * ak);
         }
+      } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int b = bs[u] >= 0 ? bs[u] : bs[0];
+          const double* __restrict__ x = X + (int64_t)b * ldX;
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            double sm = 0, sk = 0;
+#pragma unroll
+            for (int k = 0; k < WMAX; ++k) {
+              const int64_t c = rows.col[i][k];
+              const double xc = x[c < n ? c : n - 1];
+              sm = fma(mv[i][k], xc, sm);
+              sk = fma(kv[i][k], xc, sk);
+            }
+            am[u][i] = sm;
+            ak[u][i] = sk;
+            const int64_t row = rows.row[i];
+            xo[u][i] = x[row < n ? row : n - 1];
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int i = 0; i < R; ++i) am[u][i] = ak[u][i] = xo[u][i] = 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = bs[u] >= 0 ? bs[u] : bs[0];
+      const double a = sload(ca64 + b / A.m), cbv = sload(cb64 + b / A.m);
+      const double* __restrict__ f = F + (int64_t)(b % A.m) * ldf;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int64_t row = rows.row[i];
+        const bool in = row < n;
+        const double fv = f[in ? row : n - 1];
+        fr[u][i] = in ? fv : 0.0;
+        res[u][i] = in ? fv - fma(a, am[u][i], cbv * ak[u][i]) : 0.0;
+        xo[u][i] = in ? xo[u][i] : 0.0;
       }
     }
 #pragma unroll
@@ -470,15 +700,15 @@ struct KernelSet {
                 const double*, int, int, int);
 };
 
-template <typename T, int WMAX, int R, int U, bool EXACT>
+template <typename T, int WMAX, int R, int U, bool EXACT, bool BAND>
 KernelSet<T> make_set() {
   KernelSet<T> s;
-  s.dir = k_dir_spmv<T, WMAX, R, U, false, EXACT>;
-  s.dir_asm = k_dir_spmv<T, WMAX, R, U, true, EXACT>;
-  s.upd = k_update_prec<T, WMAX, R, U, false, EXACT>;
-  s.init = k_update_prec<T, WMAX, R, U, true, EXACT>;
+  s.dir = k_dir_spmv<T, WMAX, R, U, false, EXACT, BAND>;
+  s.dir_asm = k_dir_spmv<T, WMAX, R, U, true, EXACT, BAND>;
+  s.upd = k_update_prec<T, WMAX, R, U, false, EXACT, BAND>;
+  s.init = k_update_prec<T, WMAX, R, U, true, EXACT, BAND>;
   s.chain = k_chain<T, WMAX, R, EXACT>;
-  s.resid = k_residual<T, WMAX, R, U, EXACT>;
+  s.resid = k_residual<T, WMAX, R, U, EXACT, BAND>;
   return s;
 }
 
@@ -493,38 +723,47 @@ inline bool cfg_allowed(int wclass, int c) { return wclass < 2 || kCfgs[c].rows 
 inline int wmax_class(int max_len) { return max_len <= 6 ? 0 : max_len <= 8 ? 1 : 2; }
 inline int wmax_of(int wclass) { return wclass == 0 ? 6 : wclass == 1 ? 8 : 16; }
 
-template <typename T, int WMAX, bool EXACT>
+// Banded kernels: bandwidth <= 64 (every column within one slice of its row),
+// for rows of up to 8 entries.
+constexpr int kBandMax = kSlice;
+
+template <typename T, int WMAX, bool EXACT, bool BAND>
 KernelSet<T> set_for(int c) {
   switch (c) {
-    case 0: return make_set<T, WMAX, 1, 1, EXACT>();
-    case 1: return make_set<T, WMAX, 1, 2, EXACT>();
-    case 2: return make_set<T, WMAX, 1, 4, EXACT>();
-    case 3: return make_set<T, WMAX, 2, 1, EXACT>();
-    case 4: return make_set<T, WMAX, 2, 2, EXACT>();
-    case 5: return make_set<T, WMAX, 2, 4, EXACT>();
-    default: return make_set<T, WMAX, 4, 1, EXACT>();
+    case 0: return make_set<T, WMAX, 1, 1, EXACT, BAND>();
+    case 1: return make_set<T, WMAX, 1, 2, EXACT, BAND>();
+    case 2: return make_set<T, WMAX, 1, 4, EXACT, BAND>();
+    case 3: return make_set<T, WMAX, 2, 1, EXACT, BAND>();
+    case 4: return make_set<T, WMAX, 2, 2, EXACT, BAND>();
+    case 5: return make_set<T, WMAX, 2, 4, EXACT, BAND>();
+    default: return make_set<T, WMAX, 4, 1, EXACT, BAND>();
   }
 }
 
-template <typename T>
+template <typename T, bool BAND>
 KernelSet<T> kernel_set_impl(int wclass, bool exact, int c) {
-  if (wclass == 0) return exact ? set_for<T, 6, true>(c) : set_for<T, 6, false>(c);
-  if (wclass == 1) return exact ? set_for<T, 8, true>(c) : set_for<T, 8, false>(c);
+  if (wclass == 0) return exact ? set_for<T, 6, true, BAND>(c) : set_for<T, 6, false, BAND>(c);
+  return exact ? set_for<T, 8, true, BAND>(c) : set_for<T, 8, false, BAND>(c);
+}
+
+template <typename T>
+KernelSet<T> kernel_set_wide(int c) {
   switch (c) {
-    case 1: return make_set<T, 16, 1, 2, false>();
-    case 3: return make_set<T, 16, 2, 1, false>();
-    default: return make_set<T, 16, 1, 1, false>();
+    case 1: return make_set<T, 16, 1, 2, false, false>();
+    case 3: return make_set<T, 16, 2, 1, false, false>();
+    default: return make_set<T, 16, 1, 1, false, false>();
   }
 }
 
-// Defined in pcg_sets_f32.hip / pcg_sets_f64.hip.
-KernelSet<float> kernel_set_f32(int wclass, bool exact, int cfg);
-KernelSet<double> kernel_set_f64(int wclass, bool exact, int cfg);
+// Defined in pcg_sets_f32.hip / pcg_sets_f64.hip (banded and general sets in
+// separate files so they compile in parallel).
+KernelSet<float> kernel_set_f32(int wclass, bool exact, bool band, int cfg);
+KernelSet<double> kernel_set_f64(int wclass, bool exact, bool band, int cfg);
 
 template <typename T>
-inline KernelSet<T> kernel_set(int wclass, bool exact, int cfg) {
-  if constexpr (sizeof(T) == 4) return kernel_set_f32(wclass, exact, cfg);
-  else return kernel_set_f64(wclass, exact, cfg);
+inline KernelSet<T> kernel_set(int wclass, bool exact, bool band, int cfg) {
+  if constexpr (sizeof(T) == 4) return kernel_set_f32(wclass, exact, band, cfg);
+  else return kernel_set_f64(wclass, exact, band, cfg);
 }
 
 }  // namespace airga

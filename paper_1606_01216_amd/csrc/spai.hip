@@ -11,6 +11,7 @@
 // equilibrating (S = I otherwise); every entry of K(s) is formed on the fly
 // as (s^2 + alpha s) M + (1 + beta s) K from the float64 pencil.
 #include <cmath>
+#include <cstring>
 
 #include "internal.hpp"
 
@@ -32,8 +33,12 @@ __device__ __forceinline__ void givens_row(double (&R)[MJ * (MJ + 1) / 2], doubl
   for (int k = 0; k < MJ; ++k) {
     if (k < nj && v[k] != 0.0) {
       const double rkk = R[tri<MJ>(k, k)];
-      const double h = hypot(rkk, v[k]);
-      const double c = rkk / h, s = v[k] / h;
+      // h = hypot(rkk, v_k) from the squares; the scaled library routine
+      // only where they would under- or overflow
+      const double h2 = fma(rkk, rkk, v[k] * v[k]);
+      const double h = (h2 > 1e-290 && h2 < 1e290) ? sqrt(h2) : hypot(rkk, v[k]);
+      const double ih = 1.0 / h;
+      const double c = rkk * ih, s = v[k] * ih;
       R[tri<MJ>(k, k)] = h;
 #pragma unroll
       for (int l = k + 1; l < MJ; ++l) {
@@ -141,7 +146,10 @@ __global__ void k_scaled_values(PencilDev pd, double a, double b, const double* 
 // One lane per column j, on the scaled entries: ahat = Khat (build) or
 // Khat_new (update), aold = Khat_old scaled by the new diagonal (update).
 // UPDATE selects the update's right-hand side khat_old_j and its skip test;
-// otherwise the right-hand side is e_j.
+// otherwise the right-hand side is e_j.  Column j of the solution is stored
+// at the positions of row j's entries (hat[pos(j, J_t)] = p_t; the pattern
+// is symmetric), so the stores are coalesced; the finalize kernel reads it
+// through the transpose map.
 template <int MJ, bool UPDATE>
 __global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, const double* __restrict__ ahat,
                                                    const double* __restrict__ aold,
@@ -182,7 +190,7 @@ __global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, const double* _
         skipped = true;
 #pragma unroll
         for (int t = 0; t < MJ; ++t)
-          if (t < nj) hat[pd.mirror[jpos[t]]] = J[t] == (int)j ? al : 0.0;
+          if (t < nj) hat[jpos[t]] = J[t] == (int)j ? al : 0.0;
         obj[j] = sqrt(n_res);
       }
     }
@@ -249,7 +257,204 @@ __global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, const double* _
       }
 #pragma unroll
       for (int t = 0; t < MJ; ++t)
-        if (t < nj) hat[pd.mirror[jpos[t]]] = p[t];
+        if (t < nj) hat[jpos[t]] = p[t];
+      obj[j] = sqrt(res2);
+    }
+  }
+  if constexpr (UPDATE) {
+    const unsigned long long bal = __ballot(skipped);
+    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(skip_count, (int32_t)__popcll(bal));
+  }
+}
+
+// Banded pencils (bandwidth bw <= 64): the same least-squares solves, with
+// the rows the block's 256 columns can touch (rows j0 - 2 bw .. j0 + 255 +
+// 2 bw) staged in LDS first, their scaled entries formed on the fly from the
+// float64 pencil.  Every access of the solve then hits LDS instead of a chain
+// of dependent global loads.  RANGE = false folds the rows in the same order
+// as k_spai_cols (identical results); RANGE = true (narrow bands) folds the
+// span of rows once each in ascending order, with no duplicate search.
+//   LDS: vn[MJ][S] (Khat or Khat_new), vo[MJ][S] (Khat_old, update only),
+//        cl[MJ][S] (column), ln[S] (row length); S = 256 + 4 bw.
+template <int MJ>
+__host__ __device__ inline size_t spai_band_lds(int bw, bool update) {
+  const size_t S = 256 + 4 * (size_t)bw;
+  return S * (MJ * (sizeof(double) * (update ? 2 : 1) + sizeof(int32_t)) + sizeof(int32_t));
+}
+
+template <int MJ, bool UPDATE, bool RANGE>
+__global__ void __launch_bounds__(256) k_spai_band(PencilDev pd, double a, double b, double ao,
+                                                   double bo, const double* __restrict__ dinv,
+                                                   int bw, const double* __restrict__ alpha_u,
+                                                   double tol, double* __restrict__ hat,
+                                                   double* __restrict__ obj,
+                                                   int32_t* __restrict__ skip_count) {
+  extern __shared__ double lds[];
+  const int S = 256 + 4 * bw;
+  double* vn = lds;
+  double* vo = vn + MJ * S;
+  int32_t* cl = reinterpret_cast<int32_t*>(UPDATE ? vo + MJ * S : vo);
+  int32_t* ln = cl + MJ * S;
+  const int64_t j0 = (int64_t)blockIdx.x * 256;
+  const int64_t w0 = j0 - 2 * bw > 0 ? j0 - 2 * bw : 0;
+  const int64_t w1 = j0 + 256 + 2 * bw < pd.n ? j0 + 256 + 2 * bw : pd.n;
+  const int t = threadIdx.x;
+  // stage rows [w0, w1); every load is issued unconditionally (entries past
+  // the slice width read the last one of the row's slice; padding entries
+  // hold the row itself as column) and the values past the row length are
+  // dropped by a select
+  for (int64_t row = w0 + t; row < w1; row += 256) {
+    const int r = (int)(row - w0);
+    const int64_t sl = row / kSlice;
+    const int32_t sp0 = pd.slice_ptr[sl];
+    const int32_t base = sp0 + (int32_t)(row % kSlice);
+    const int w = (pd.slice_ptr[sl + 1] - sp0) / kSlice;
+    const int len = pd.row_len[row];
+    const double sr = dinv[row];
+    ln[r] = len;
+    int32_t c[MJ];
+    double m[MJ], kk[MJ], dc[MJ];
+#pragma unroll
+    for (int k = 0; k < MJ; ++k) {
+      const int32_t idx = base + (k < w ? k : w - 1) * kSlice;
+      c[k] = pd.col[idx];
+      m[k] = pd.m64[idx];
+      kk[k] = pd.k64[idx];
+    }
+#pragma unroll
+    for (int k = 0; k < MJ; ++k) dc[k] = dinv[c[k]];
+#pragma unroll
+    for (int k = 0; k < MJ; ++k) {
+      const bool in = k < len;
+      // same association as k_scaled_values
+      cl[k * S + r] = in ? c[k] : -1;
+      vn[k * S + r] = in ? fma(a, m[k], b * kk[k]) * sr * dc[k] : 0.0;
+      if constexpr (UPDATE) vo[k * S + r] = in ? fma(ao, m[k], bo * kk[k]) * sr * dc[k] : 0.0;
+    }
+  }
+  __syncthreads();
+  const int64_t j = j0 + t;
+  bool skipped = false;
+  if (j < pd.n) {
+    const int jr = (int)(j - w0);
+    const int32_t base_j = pd.slice_ptr[j / kSlice] + (int32_t)(j % kSlice);
+    const int nj = ln[jr];
+    int J[MJ];
+    // -2 past the row: never equal to a staged column (padding holds -1)
+#pragma unroll
+    for (int u = 0; u < MJ; ++u) J[u] = u < nj ? cl[u * S + jr] : -2;
+    if constexpr (UPDATE) {
+      const double al = *alpha_u;
+      double n_old = 0, n_res = 0;
+#pragma unroll
+      for (int u = 0; u < MJ; ++u) {
+        if (u < nj) {
+          const double v_o = vo[u * S + jr];
+          const double d = v_o - al * vn[u * S + jr];
+          n_old = fma(v_o, v_o, n_old);
+          n_res = fma(d, d, n_res);
+        }
+      }
+      if (sqrt(n_res) <= tol * sqrt(n_old)) {
+        skipped = true;
+#pragma unroll
+        for (int u = 0; u < MJ; ++u)
+          if (u < nj) hat[base_j + u * kSlice] = J[u] == (int)j ? al : 0.0;
+        obj[j] = sqrt(n_res);
+      }
+    }
+    if (!skipped) {
+      double R[MJ * (MJ + 1) / 2];
+      double qtb[MJ];
+#pragma unroll
+      for (int q = 0; q < MJ * (MJ + 1) / 2; ++q) R[q] = 0.0;
+#pragma unroll
+      for (int q = 0; q < MJ; ++q) qtb[q] = 0.0;
+      double res2 = 0.0;
+      if constexpr (RANGE) {
+        // Narrow band: the rows I lie in [lo, hi], the span of the patterns
+        // of the columns J; each row in it is folded once, in ascending
+        // order (rows outside I have v = 0 and rhs = 0 and change nothing).
+        int lo = (int)j, hi = (int)j;
+#pragma unroll
+        for (int u = 0; u < MJ; ++u) {
+          if (u < nj) {
+            const int kr = (int)(J[u] - w0);
+            const int first = cl[kr], last = cl[(ln[kr] - 1) * S + kr];
+            lo = first < lo ? first : lo;
+            hi = last > hi ? last : hi;
+          }
+        }
+        for (int i = lo; i <= hi; ++i) {
+          const int ir = (int)(i - w0);
+          double v[MJ];
+#pragma unroll
+          for (int u = 0; u < MJ; ++u) v[u] = 0.0;
+          double rhs = (!UPDATE && i == (int)j) ? 1.0 : 0.0;
+#pragma unroll
+          for (int q = 0; q < MJ; ++q) {
+            const int c = cl[q * S + ir];
+            const double val = vn[q * S + ir];
+#pragma unroll
+            for (int u = 0; u < MJ; ++u) v[u] = J[u] == c ? val : v[u];
+            if constexpr (UPDATE) rhs = c == (int)j ? vo[q * S + ir] : rhs;
+          }
+          givens_row<MJ>(R, qtb, v, rhs, nj);
+          res2 = fma(rhs, rhs, res2);
+        }
+      } else {
+#pragma unroll
+      for (int tt = 0; tt < MJ; ++tt) {
+        if (tt < nj) {
+          const int kr = (int)(J[tt] - w0);
+          const int nk = ln[kr];
+          for (int e = 0; e < nk; ++e) {
+            const int i = cl[e * S + kr];
+            const int ir = (int)(i - w0);
+            const int ni = ln[ir];
+            double v[MJ];
+#pragma unroll
+            for (int u = 0; u < MJ; ++u) v[u] = 0.0;
+            int umin = MJ;
+            double rhs = 0.0;
+            for (int q = 0; q < ni; ++q) {
+              const int c = cl[q * S + ir];
+              const double val = vn[q * S + ir];
+#pragma unroll
+              for (int u = 0; u < MJ; ++u) {
+                if (u < nj && J[u] == c) {
+                  v[u] += val;
+                  umin = u < umin ? u : umin;
+                }
+              }
+              if constexpr (UPDATE) {
+                if (c == (int)j) rhs = vo[q * S + ir];
+              }
+            }
+            if constexpr (!UPDATE) rhs = (i == (int)j) ? 1.0 : 0.0;
+            if (umin < tt) continue;
+            givens_row<MJ>(R, qtb, v, rhs, nj);
+            res2 = fma(rhs, rhs, res2);
+          }
+        }
+      }
+      }
+      double p[MJ];
+#pragma unroll
+      for (int q = MJ - 1; q >= 0; --q) {
+        p[q] = 0.0;
+        if (q < nj) {
+          double acc = qtb[q];
+#pragma unroll
+          for (int u = q + 1; u < MJ; ++u)
+            if (u < nj) acc -= R[tri<MJ>(q, u)] * p[u];
+          const double d = R[tri<MJ>(q, q)];
+          p[q] = d != 0.0 ? acc / d : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < MJ; ++u)
+        if (u < nj) hat[base_j + u * kSlice] = p[u];
       obj[j] = sqrt(res2);
     }
   }
@@ -279,8 +484,9 @@ __global__ void k_spai_finalize(PencilDev pd, const double* __restrict__ hat,
     double val = 0.0;
     if (k < len) {
       const int c = pd.col[idx];
-      double h = hat[idx];
-      if (mode == 1) h = 0.5 * (h + hat[pd.mirror[idx]]);
+      // hat holds column c's solution at the position of (c, r)
+      double h = hat[pd.mirror[idx]];
+      if (mode == 1) h = 0.5 * (h + hat[idx]);
       val = mode == 2 ? h * sr / dinv[c] : h * sr * dinv[c];
     }
     v64[idx] = val;
@@ -396,6 +602,44 @@ static airga_status spai_scratch(airga_ctx ctx, SpaiScratch* w, int64_t nb) {
   return AIRGA_OK;
 }
 
+// LDS-staged column kernels apply (bandwidth <= 64 and the window fits).
+static bool spai_banded(const Pencil& pen, const airga_spai_opts& o, bool update) {
+  if (o.general_only || pen.bandwidth > kSlice) return false;
+  const size_t lds = pen.max_len <= 6 ? spai_band_lds<6>(pen.bandwidth, update)
+                                      : spai_band_lds<kSpaiMaxJ>(pen.bandwidth, update);
+  return lds <= 64 * 1024;
+}
+
+template <bool UPDATE>
+static void launch_band(airga_ctx ctx, double a, double b, double ao, double bo,
+                        const double* dinv, const double* alpha_u, double tol, double* hat,
+                        double* obj, int32_t* skip) {
+  const Pencil& pen = ctx->pen;
+  const unsigned nb = blocks_for(pen.n, 256);
+  const int bw = pen.bandwidth;
+  // fold the row span when it is no longer than the (column, entry) pairs
+  const bool range = 4 * bw + 1 <= pen.max_len * pen.max_len;
+  hipStream_t st = ctx->stream;
+  const PencilDev pd = pen.dev();
+  if (pen.max_len <= 6) {
+    const size_t lds = spai_band_lds<6>(bw, UPDATE);
+    if (range)
+      k_spai_band<6, UPDATE, true><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw, alpha_u, tol,
+                                                         hat, obj, skip);
+    else
+      k_spai_band<6, UPDATE, false><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw, alpha_u, tol,
+                                                          hat, obj, skip);
+  } else {
+    const size_t lds = spai_band_lds<kSpaiMaxJ>(bw, UPDATE);
+    if (range)
+      k_spai_band<kSpaiMaxJ, UPDATE, true><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw,
+                                                                 alpha_u, tol, hat, obj, skip);
+    else
+      k_spai_band<kSpaiMaxJ, UPDATE, false><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw,
+                                                                  alpha_u, tol, hat, obj, skip);
+  }
+}
+
 // Column kernels sized to the longest row.
 template <bool UPDATE>
 static void launch_cols(airga_ctx ctx, const SpaiScratch& w, const double* alpha_u, double tol,
@@ -421,9 +665,14 @@ static airga_status run_build(airga_ctx ctx, double s, const airga_spai_opts& o,
   const unsigned nr = blocks_for(pen.n_pad(), 256);
   k_dinv<<<nr, 256, 0, st>>>(pd, a, b, o.equilibrate, w.dinv);
   AIRGA_HIP(hipGetLastError());
-  k_scaled_values<<<nr, 256, 0, st>>>(pd, a, b, w.dinv, w.ahat);
-  AIRGA_HIP(hipGetLastError());
-  launch_cols<false>(ctx, w, nullptr, 0.0, p->objective.as<double>(), nullptr);
+  if (spai_banded(pen, o, false)) {
+    launch_band<false>(ctx, a, b, 0.0, 0.0, w.dinv, nullptr, 0.0, w.hat,
+                       p->objective.as<double>(), nullptr);
+  } else {
+    k_scaled_values<<<nr, 256, 0, st>>>(pd, a, b, w.dinv, w.ahat);
+    AIRGA_HIP(hipGetLastError());
+    launch_cols<false>(ctx, w, nullptr, 0.0, p->objective.as<double>(), nullptr);
+  }
   AIRGA_HIP(hipGetLastError());
   k_spai_finalize<<<nr, 256, 0, st>>>(pd, w.hat, w.dinv, o.symmetrize ? 1 : 0,
                                       p->v64.as<double>(), p->v32.as<float>());
@@ -452,19 +701,26 @@ static airga_status run_update(airga_ctx ctx, airga_prec old, double s_new,
   const unsigned nr = blocks_for(pen.n_pad(), 256);
   double* d_alpha = p->scal.as<double>();
   int32_t* d_skip = reinterpret_cast<int32_t*>(p->scal.as<char>() + 8);
+  const bool band = spai_banded(pen, o, true);
   k_dinv<<<nr, 256, 0, st>>>(pd, a, b, o.equilibrate, w.dinv);
   AIRGA_HIP(hipGetLastError());
-  k_scaled_values<<<nr, 256, 0, st>>>(pd, a, b, w.dinv, w.ahat);
-  AIRGA_HIP(hipGetLastError());
-  k_scaled_values<<<nr, 256, 0, st>>>(pd, ao, bo, w.dinv, w.aold);
-  AIRGA_HIP(hipGetLastError());
+  if (!band) {
+    k_scaled_values<<<nr, 256, 0, st>>>(pd, a, b, w.dinv, w.ahat);
+    AIRGA_HIP(hipGetLastError());
+    k_scaled_values<<<nr, 256, 0, st>>>(pd, ao, bo, w.dinv, w.aold);
+    AIRGA_HIP(hipGetLastError());
+  }
   k_alpha_partial<<<nb, 256, 0, st>>>(pd, a, b, ao, bo, w.dinv, w.part);
   AIRGA_HIP(hipGetLastError());
   k_alpha_final<<<1, 256, 0, st>>>(w.part, nb, d_alpha);
   AIRGA_HIP(hipGetLastError());
   k_fill_i32<<<1, 64, 0, st>>>(d_skip, 1, 0);
   AIRGA_HIP(hipGetLastError());
-  launch_cols<true>(ctx, w, d_alpha, o.tol, p->objective.as<double>(), d_skip);
+  if (band)
+    launch_band<true>(ctx, a, b, ao, bo, w.dinv, d_alpha, o.tol, w.hat, p->objective.as<double>(),
+                      d_skip);
+  else
+    launch_cols<true>(ctx, w, d_alpha, o.tol, p->objective.as<double>(), d_skip);
   AIRGA_HIP(hipGetLastError());
   k_spai_finalize<<<nr, 256, 0, st>>>(pd, w.hat, w.dinv, 2, p->v64.as<double>(),
                                       p->v32.as<float>());
@@ -531,6 +787,7 @@ extern "C" {
 
 void airga_spai_opts_default(airga_spai_opts* o) {
   if (!o) return;
+  std::memset(o, 0, sizeof *o);
   o->tol = 0.01;
   o->equilibrate = 1;
   o->symmetrize = 1;
