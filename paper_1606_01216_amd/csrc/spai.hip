@@ -143,6 +143,34 @@ __global__ void k_scaled_values(PencilDev pd, double a, double b, const double* 
   }
 }
 
+// Number of lanes of the block with flag set, stored at part[blockIdx.x]
+// (one plain store per block; k_sum_counts adds the blocks in order).
+__device__ __forceinline__ void block_count(bool flag, int32_t* __restrict__ part) {
+  __shared__ int32_t cnt[4];
+  const unsigned long long bal = __ballot(flag);
+  if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = (int32_t)__popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t c = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) c += cnt[w];
+    part[blockIdx.x] = c;
+  }
+}
+
+// out[0] = sum of the nb per-block counts, in block order.
+__global__ void k_sum_counts(const int32_t* __restrict__ part, int64_t nb, int32_t* __restrict__ out) {
+  __shared__ int64_t red[256];
+  int64_t c = 0;
+  for (int64_t i = threadIdx.x; i < nb; i += blockDim.x) c += part[i];
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = (int32_t)red[0];
+}
+
 // One lane per column j, on the scaled entries: ahat = Khat (build) or
 // Khat_new (update), aold = Khat_old scaled by the new diagonal (update).
 // UPDATE selects the update's right-hand side khat_old_j and its skip test;
@@ -261,10 +289,7 @@ __global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, const double* _
       obj[j] = sqrt(res2);
     }
   }
-  if constexpr (UPDATE) {
-    const unsigned long long bal = __ballot(skipped);
-    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(skip_count, (int32_t)__popcll(bal));
-  }
+  if constexpr (UPDATE) block_count(skipped, skip_count);
 }
 
 // Banded pencils (bandwidth bw <= 64): the same least-squares solves, with
@@ -458,22 +483,23 @@ __global__ void __launch_bounds__(256) k_spai_band(PencilDev pd, double a, doubl
       obj[j] = sqrt(res2);
     }
   }
-  if constexpr (UPDATE) {
-    const unsigned long long bal = __ballot(skipped);
-    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(skip_count, (int32_t)__popcll(bal));
-  }
+  if constexpr (UPDATE) block_count(skipped, skip_count);
 }
 
 // Map the scaled factor back and store float64 and float32 copies:
 //   build:        P = S Phat S          (mode 0)
 //   build, sym:   P = S (Phat + Phat^T)/2 S   (mode 1)
 //   update:       Q = S Qhat S^{-1}     (mode 2)
-// Padding entries are 0.
+// Padding entries are 0.  An update whose every column was skipped
+// (skip_total = n) is the scalar alpha I: it is never applied as a factor,
+// so nothing is written.
 __global__ void k_spai_finalize(PencilDev pd, const double* __restrict__ hat,
                                 const double* __restrict__ dinv, int mode,
+                                const int32_t* __restrict__ skip_total,
                                 double* __restrict__ v64, float* __restrict__ v32) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= (int64_t)pd.n_slices * kSlice) return;
+  if (skip_total && *skip_total == pd.n) return;
   const int64_t s = r / kSlice;
   const int32_t base = pd.slice_ptr[s] + (int32_t)(r % kSlice);
   const int w = (pd.slice_ptr[s + 1] - pd.slice_ptr[s]) / kSlice;
@@ -501,6 +527,19 @@ __global__ void k_export(PencilDev pd, int64_t stored, const double* __restrict_
   if (i >= stored) return;
   const int32_t e = pd.csr_pos[i];
   if (e >= 0) out[e] = v[i];
+}
+
+// The scalar factor alpha I in CSR order: alpha on the diagonal, 0 elsewhere.
+__global__ void k_export_scalar(PencilDev pd, double alpha, double* __restrict__ out) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= pd.n) return;
+  const int64_t s = r / kSlice;
+  const int32_t base = pd.slice_ptr[s] + (int32_t)(r % kSlice);
+  const int len = pd.row_len[r];
+  for (int k = 0; k < len; ++k) {
+    const int32_t idx = base + k * kSlice;
+    out[pd.csr_pos[idx]] = pd.col[idx] == (int32_t)r ? alpha : 0.0;
+  }
 }
 
 // y = scale * V x with V on the pattern (stored order), float64; blockIdx.y = vector.
@@ -585,20 +624,23 @@ static airga_status check_spai_args(airga_ctx ctx, double s, airga_prec* out) {
   return AIRGA_OK;
 }
 
-// Scratch for one SPAI call: [dinv (n_pad) | hat | ahat | aold (stored each) | partials].
+// Scratch for one SPAI call: [dinv (n_pad) | hat | ahat | aold (stored each) |
+// alpha partials (2 nb) | per-block skip counts (nb int32)].
 struct SpaiScratch {
   double *dinv, *hat, *ahat, *aold, *part;
+  int32_t* skip_part;
 };
 static airga_status spai_scratch(airga_ctx ctx, SpaiScratch* w, int64_t nb) {
   const Pencil& pen = ctx->pen;
-  const size_t need =
-      sizeof(double) * ((size_t)pen.n_pad() + 3 * (size_t)pen.nnz_stored + 2 * nb + 8);
+  const size_t need = sizeof(double) * ((size_t)pen.n_pad() + 3 * (size_t)pen.nnz_stored +
+                                        2 * nb + (nb + 1) / 2 + 8);
   AIRGA_TRY(ctx->ws_tmp.reserve(need));
   w->dinv = ctx->ws_tmp.as<double>();
   w->hat = w->dinv + pen.n_pad();
   w->ahat = w->hat + pen.nnz_stored;
   w->aold = w->ahat + pen.nnz_stored;
   w->part = w->aold + pen.nnz_stored;
+  w->skip_part = reinterpret_cast<int32_t*>(w->part + 2 * nb);
   return AIRGA_OK;
 }
 
@@ -674,7 +716,7 @@ static airga_status run_build(airga_ctx ctx, double s, const airga_spai_opts& o,
     launch_cols<false>(ctx, w, nullptr, 0.0, p->objective.as<double>(), nullptr);
   }
   AIRGA_HIP(hipGetLastError());
-  k_spai_finalize<<<nr, 256, 0, st>>>(pd, w.hat, w.dinv, o.symmetrize ? 1 : 0,
+  k_spai_finalize<<<nr, 256, 0, st>>>(pd, w.hat, w.dinv, o.symmetrize ? 1 : 0, nullptr,
                                       p->v64.as<double>(), p->v32.as<float>());
   AIRGA_HIP(hipGetLastError());
   // Alg. 2's starting scaling trace(K) / trace(K K^T), from the Gram scalars.
@@ -714,15 +756,15 @@ static airga_status run_update(airga_ctx ctx, airga_prec old, double s_new,
   AIRGA_HIP(hipGetLastError());
   k_alpha_final<<<1, 256, 0, st>>>(w.part, nb, d_alpha);
   AIRGA_HIP(hipGetLastError());
-  k_fill_i32<<<1, 64, 0, st>>>(d_skip, 1, 0);
-  AIRGA_HIP(hipGetLastError());
   if (band)
     launch_band<true>(ctx, a, b, ao, bo, w.dinv, d_alpha, o.tol, w.hat, p->objective.as<double>(),
-                      d_skip);
+                      w.skip_part);
   else
-    launch_cols<true>(ctx, w, d_alpha, o.tol, p->objective.as<double>(), d_skip);
+    launch_cols<true>(ctx, w, d_alpha, o.tol, p->objective.as<double>(), w.skip_part);
   AIRGA_HIP(hipGetLastError());
-  k_spai_finalize<<<nr, 256, 0, st>>>(pd, w.hat, w.dinv, 2, p->v64.as<double>(),
+  k_sum_counts<<<1, 256, 0, st>>>(w.skip_part, nb, d_skip);
+  AIRGA_HIP(hipGetLastError());
+  k_spai_finalize<<<nr, 256, 0, st>>>(pd, w.hat, w.dinv, 2, d_skip, p->v64.as<double>(),
                                       p->v32.as<float>());
   AIRGA_HIP(hipGetLastError());
   p->is_update = true;
@@ -852,8 +894,14 @@ airga_status airga_prec_export(airga_prec prec, double* values, double* objectiv
   AIRGA_TRY(check_prec(prec));
   airga_ctx ctx = prec->ctx;
   if (values) {
-    k_export<<<blocks_for(ctx->pen.nnz_stored, 256), 256, 0, ctx->stream>>>(
-        ctx->pen.dev(), ctx->pen.nnz_stored, prec->v64.as<double>(), values);
+    // an update with every column skipped holds no factor values
+    AIRGA_TRY(prec_resolve(prec));
+    if (prec->is_update && prec->scalar_only)
+      k_export_scalar<<<blocks_for(ctx->pen.n, 256), 256, 0, ctx->stream>>>(ctx->pen.dev(),
+                                                                            prec->alpha, values);
+    else
+      k_export<<<blocks_for(ctx->pen.nnz_stored, 256), 256, 0, ctx->stream>>>(
+          ctx->pen.dev(), ctx->pen.nnz_stored, prec->v64.as<double>(), values);
     AIRGA_HIP(hipGetLastError());
   }
   if (objective)
