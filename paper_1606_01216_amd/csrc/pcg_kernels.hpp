@@ -363,13 +363,19 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
   }
   FlagSweep sweep(A.sys.active, A.B);
   int bs[U];
+  // First preconditioner factor of each group slot, kept in registers while
+  // the systems swept through the slot belong to the same shift (systems
+  // are numbered shift-major), so a shift's factor is read once per
+  // wavefront, not once per system.  A missing preconditioner is an
+  // identity factor supplied by the host.
+  T pv[U][R][WMAX];
+  int csh[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) csh[u] = -1;
   while (sweep.next(bs, lane)) {
-    // compute phase: no branches, so every load of the group can be in
-    // flight at once (a missing system aliases the group's first one).  Each
-    // system's first preconditioner factor is loaded (systems of one shift
-    // hit the same cache lines); a missing preconditioner is an identity
-    // factor supplied by the host.
-    T pv[U][R][WMAX];
+    // compute phase: no branches on lane data, so every load of the group
+    // can be in flight at once (a missing system aliases the group's first
+    // one)
     int Ls[U];
     T rn[U][R], tz[U][R], xn[U][R], wrr[U][R];
     if constexpr (BAND) {
@@ -380,7 +386,10 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
         const int b = bs[u] >= 0 ? bs[u] : bs[0];
         const int sh = b / A.m;
         Ls[u] = sload(A.clen + sh);
-        rows.values(sload(A.fac + (int64_t)sh * A.maxc), pv[u]);
+        if (sh != csh[u]) {
+          rows.values(sload(A.fac + (int64_t)sh * A.maxc), pv[u]);
+          csh[u] = sh;
+        }
         const T al = INIT ? T(0) : (T)sload(A.sys.alpha + b);
         const T* __restrict__ rin = A.vec(INIT ? KR0 : KR0 + par, b);
         const T* __restrict__ wv = A.vec(KW, b);
@@ -431,7 +440,10 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
         const int b = bs[u] >= 0 ? bs[u] : bs[0];
         const int sh = b / A.m;
         Ls[u] = sload(A.clen + sh);
-        rows.values(sload(A.fac + (int64_t)sh * A.maxc), pv[u]);
+        if (sh != csh[u]) {
+          rows.values(sload(A.fac + (int64_t)sh * A.maxc), pv[u]);
+          csh[u] = sh;
+        }
         const T al = INIT ? T(0) : (T)sload(A.sys.alpha + b);
         const T* __restrict__ rin = A.vec(INIT ? KR0 : KR0 + par, b);
         const T* __restrict__ wv = A.vec(KW, b);
