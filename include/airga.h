@@ -156,10 +156,12 @@ AIRGA_API void airga_spai_opts_default(airga_spai_opts* opts);
  * pattern of column j, solved exactly per column (Givens QR in float64,
  * one column per GPU lane).  `opts` may be NULL (defaults).  The handle
  * owns the factor (float64 and float32 copies) and must be released with
- * airga_prec_release.  Asynchronous.
+ * airga_prec_release.  Asynchronous.  Pencils of bandwidth <= 64 use
+ * kernels that stage each block's rows in LDS (see general_only).
  * Errors: EINVAL (s <= 0 or non-finite, null out), ESTATE (no pencil),
- * ENOTSPD (a diagonal entry of K(s) <= 0, only detected when equilibrating),
- * ENOMEM, EHIP. */
+ * ENOTSPD (the pencil has a diagonal entry of M <= 0 or of K < 0, so K(s)
+ * need not be SPD), EUNSUPPORTED (a row of more than 8 entries: the column
+ * problems are held in registers), ENOMEM, EHIP. */
 AIRGA_API airga_status airga_spai_build(airga_ctx ctx, double s, const airga_spai_opts* opts,
                               airga_prec* out);
 
@@ -169,8 +171,9 @@ AIRGA_API airga_status airga_spai_build(airga_ctx ctx, double s, const airga_spa
  * the chain Q * (old chain): a new handle that references `old` (reference
  * counted; `old` stays valid for the caller).  A factor whose columns all
  * skip is the scalar alpha and is not applied (CG is invariant to a nonzero
- * scaling of the preconditioner).  Errors: as airga_spai_build, plus EINVAL
- * for a null or foreign `old`. */
+ * scaling of the preconditioner); no factor values are written for it and
+ * airga_prec_export returns alpha I.  Errors: as airga_spai_build, plus
+ * EINVAL for a null or foreign `old`. */
 AIRGA_API airga_status airga_spai_update(airga_ctx ctx, airga_prec old, double s_new,
                                const airga_spai_opts* opts, airga_prec* out);
 
@@ -188,7 +191,8 @@ AIRGA_API airga_status airga_get_prec_info(airga_prec prec, airga_prec_info* out
 /* Export the newest factor: values (device, nnz, CSR order, float64; the
  * mapped-back factor as applied) and, if objective is not NULL, the per
  * column least-squares residual norm in the scaled problem (device, n).
- * A scalar-only factor exports alpha on the diagonal.  Asynchronous. */
+ * A scalar-only factor exports alpha on the diagonal.  Asynchronous, except
+ * that exporting values waits once for an update's skip count. */
 AIRGA_API airga_status airga_prec_export(airga_prec prec, double* values, double* objective);
 
 /* z = C r for `count` vectors (device, leading dimensions ldr, ldz),

@@ -379,3 +379,48 @@ def test_literal_cantilever_c1(ctx):
     ref = reference(pen, shifts, f)
     assert st[0]["status"] == airga.SYS_CONVERGED, st
     assert rel_err(X.cpu().numpy()[0, 0], ref[0, 0]) < 1e-7
+
+
+# --------------------------------------------------------- moment matching
+
+def test_gpu_solves_make_the_projection_interpolate():
+    """Galerkin projection onto GPU solves X(s_i) and first moments (RHS
+    -(2 s M + D) X(s_i), Section 2) interpolates the full transfer function
+    and its derivative at the expansion points; H from an independent dense
+    solve.  Pins the solve chain as a whole."""
+    from oracle import moments
+    c = airga.Context(0)
+    try:
+        p = beam.make_beam(190, ei_loguniform=(0.5, 2.0), surrogate=True, seed=4)
+        set_pencil(c, p)
+        m, k = beam.pencil_dense(p)
+        d = p.alpha * m + p.beta * k
+        f = beam.tip_load(p.n)          # (1, n)
+        cp = f.copy()
+        shifts = [1.5, 40.0, 900.0]
+        precs = [c.spai_build(s) for s in shifts]
+        X0, st0 = c.pcg_solve(shifts, precs, to_dev(f, torch.float64), tol=1e-12,
+                              mode=airga.MODE_MIXED)
+        assert all(e["status"] == airga.SYS_CONVERGED for e in st0)
+        x0 = X0.cpu().numpy()[:, 0, :]  # (nshift, n)
+        xs = []
+        for i, s in enumerate(shifts):
+            rhs = -((2 * s) * m + d) @ x0[i]
+            X1, st1 = c.pcg_solve([s], [precs[i]], to_dev(rhs[None, :], torch.float64),
+                                  tol=1e-12, mode=airga.MODE_FP64)
+            assert st1[0]["status"] == airga.SYS_CONVERGED
+            xs += [x0[i][:, None], X1.cpu().numpy()[0, 0][:, None]]
+        v = moments.orth_basis(xs)
+        red = moments.project(m, k, p.alpha, p.beta, f.T, cp, v)
+
+        def h_full(s):
+            return cp @ np.linalg.solve(s * s * m + s * d + k, f.T)
+
+        for s in shifts:
+            assert np.allclose(moments.reduced_transfer(*red, s), h_full(s), rtol=1e-9)
+            e = 1e-4 * s
+            dfull = (h_full(s + e) - h_full(s - e)) / (2 * e)
+            dred = (moments.reduced_transfer(*red, s + e) - moments.reduced_transfer(*red, s - e)) / (2 * e)
+            assert np.allclose(dred, dfull, rtol=1e-5)
+    finally:
+        c.close()
