@@ -232,7 +232,7 @@ def main():
     X2 = torch.zeros((S, m, n), dtype=torch.float64, device=dev)
     stream = torch.cuda.Stream(device=dev)
     ctx = airga.Context(0, stream)
-    solve_kw = dict(tol=args.tol, mode=airga.MODE_MIXED, inner_tol=1e-4, max_sweeps=12,
+    solve_kw = dict(tol=args.tol, mode=airga.MODE_MIXED, max_sweeps=12,
                     max_iter=20000, poll_every=8)
     if args.tile:
         solve_kw["tile"] = tuple(int(v) for v in args.tile.split(","))

@@ -206,6 +206,8 @@ AIRGA_API void airga_prec_release(airga_prec prec);
 
 /* ------------------------------------------------------------------ solves */
 
+enum { AIRGA_BETA_FLEXIBLE = 0, AIRGA_BETA_CLASSICAL = 1 };
+
 typedef struct {
   double tol;          /* stop when ||F - K X|| <= tol ||F|| (float64 residual
                           in MIXED mode, CG recurrence residual in FP64 mode).
@@ -215,7 +217,7 @@ typedef struct {
   int32_t mode;        /* AIRGA_MODE_FP64 or AIRGA_MODE_MIXED (float32 matrix,
                           preconditioner and vectors inside float64 iterative
                           refinement of the residual and the solution)          */
-  double inner_tol;    /* MIXED: relative residual reduction per sweep (1e-4)   */
+  double inner_tol;    /* MIXED: relative residual reduction per sweep (1e-3)   */
   int32_t max_sweeps;  /* MIXED: refinement sweeps (default 12)                 */
   int32_t poll_every;  /* iterations between host checks of the active count
                           (rounded up to even; default 8)                       */
@@ -230,6 +232,18 @@ typedef struct {
   int32_t general_only; /* 1: general sliced-ELL kernels even for a pencil of
                           bandwidth <= 64 (whose kernels otherwise stage the
                           neighbour entries in LDS; same arithmetic)             */
+  int32_t beta_form;   /* direction update: AIRGA_BETA_FLEXIBLE (default)
+                          beta = -(z_new, K p) / (p, K p), valid for any
+                          preconditioner and the more robust one in float32;
+                          AIRGA_BETA_CLASSICAL the ratio (r,z)_new / (r,z)_old,
+                          for symmetric preconditioners only                    */
+  int32_t inner_max;   /* MIXED: float32 iterations per sweep (default 96,
+                          rounded up to a multiple of poll_every).  A system
+                          still iterating at the cap keeps that sweep's
+                          correction and is finished by a float64 solve from
+                          its current X, batched with the others that hit it:
+                          float32 cannot resolve systems whose condition number
+                          approaches 1/eps_32, and they would stall the batch  */
 } airga_pcg_opts;
 
 AIRGA_API void airga_pcg_opts_default(airga_pcg_opts* opts);
@@ -238,7 +252,8 @@ typedef struct {
   int32_t status;      /* AIRGA_SYS_*                                           */
   int32_t iters;       /* CG iterations                                         */
   int32_t sweeps;      /* refinement sweeps (MIXED), 1 for FP64                 */
-  int32_t reserved;
+  int32_t finished_fp64; /* MIXED: 1 if handed to the float64 finish (iters
+                          and sweeps include both stages)                      */
   double relres;       /* ||F - K X|| / ||F|| from the float64 residual at exit */
 } airga_sys_stats;
 

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libairga.so")
 OK, EINVAL, ENOMEM, EHIP, ENOTSPD, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 SYS_CONVERGED, SYS_MAXIT, SYS_BREAKDOWN, SYS_NONFINITE = 0, 1, 2, 3
 MODE_FP64, MODE_MIXED = 0, 1
+BETA_FLEXIBLE, BETA_CLASSICAL = 0, 1
 STATUS_NAMES = {SYS_CONVERGED: "converged", SYS_MAXIT: "maxit", SYS_BREAKDOWN: "breakdown",
                 SYS_NONFINITE: "nonfinite"}
 
@@ -59,12 +60,13 @@ class PcgOpts(ctypes.Structure):
                 ("max_sweeps", ctypes.c_int32), ("poll_every", ctypes.c_int32),
                 ("x0_given", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-                ("tile_sys", ctypes.c_int32), ("general_only", ctypes.c_int32)]
+                ("tile_sys", ctypes.c_int32), ("general_only", ctypes.c_int32),
+                ("beta_form", ctypes.c_int32), ("inner_max", ctypes.c_int32)]
 
 
 class SysStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
-                ("sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sweeps", ctypes.c_int32), ("finished_fp64", ctypes.c_int32),
                 ("relres", ctypes.c_double)]
 
 
@@ -260,15 +262,16 @@ class Context:
 
     # ---------------------------------------------------------------- solves
     def pcg_solve(self, shifts, precs, F: torch.Tensor, X: torch.Tensor | None = None, *,
-                  tol=1e-10, max_iter=20000, mode=MODE_FP64, inner_tol=1e-4, max_sweeps=12,
+                  tol=1e-10, max_iter=20000, mode=MODE_FP64, inner_tol=None, max_sweeps=12,
                   poll_every=8, x0_given=False, use_graph=True, profile=False, tile=None,
-                  general_only=False):
+                  general_only=False, beta_form=0, inner_max=None):
         """Solve K(s_k) X[k, c] = F[c] for all shifts k and columns c.
 
         F: (m, n) float64 on the device; X: (nshift, m, n) float64 (allocated
         when None).  precs: list of Prec or None per shift.  Returns
         (X, stats) with stats a list of dicts in (k, c) order.  tile: None (the
         autotuner picks) or (matrix rows per wavefront, systems per group).
+        inner_tol / inner_max: None for the library defaults.
         """
         _dev(F, torch.float64, self.device)
         m = F.shape[0]
@@ -288,9 +291,14 @@ class Context:
         o = PcgOpts()
         lib().airga_pcg_opts_default(ctypes.byref(o))
         o.tol, o.max_iter, o.mode = float(tol), int(max_iter), int(mode)
-        o.inner_tol, o.max_sweeps, o.poll_every = float(inner_tol), int(max_sweeps), int(poll_every)
+        if inner_tol is not None:
+            o.inner_tol = float(inner_tol)
+        if inner_max is not None:
+            o.inner_max = int(inner_max)
+        o.max_sweeps, o.poll_every = int(max_sweeps), int(poll_every)
         o.x0_given, o.use_graph, o.profile = int(bool(x0_given)), int(bool(use_graph)), int(bool(profile))
         o.general_only = int(bool(general_only))
+        o.beta_form = int(beta_form)
         if tile is not None:
             o.tile_rows, o.tile_sys = int(tile[0]), int(tile[1])
         stats = (SysStats * (nshift * m))()
@@ -298,8 +306,8 @@ class Context:
         _check(lib().airga_pcg_solve(self._h, nshift, c_shifts, c_precs, m, _ptr(F), self.n,
                                      _ptr(X), self.n, ctypes.byref(o), stats))
         self._leave()
-        out = [dict(status=s.status, iters=s.iters, sweeps=s.sweeps, relres=s.relres)
-               for s in stats]
+        out = [dict(status=s.status, iters=s.iters, sweeps=s.sweeps, relres=s.relres,
+                    finished_fp64=s.finished_fp64) for s in stats]
         return X, out
 
     def kernel_times(self) -> dict:

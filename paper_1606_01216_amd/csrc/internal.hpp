@@ -160,12 +160,15 @@ struct airga_ctx_s {
   // work of a context is ordered on one stream, so a buffer handed back here
   // can be reused by later work without waiting for earlier kernels.
   std::vector<std::pair<void*, size_t>> pool;
-  // The last captured iteration graph and the launch arguments it was
-  // captured with; replayed as long as a sweep's arguments are identical.
-  hipGraphExec_t graph_exec = nullptr;
-  std::vector<char> graph_key;
+  // Captured iteration graphs, keyed by the launch arguments they were
+  // captured with (most recently used last); a graph is replayed whenever a
+  // sweep's arguments are identical.  At most kGraphs are kept.
+  static constexpr size_t kGraphs = 8;
+  std::vector<std::pair<std::vector<char>, hipGraphExec_t>> graphs;
+  // Column-gather area of the float64 finish of mixed solves.
+  airga::DevBuf ws_gather;
   ~airga_ctx_s() {
-    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
     for (auto& b : pool) (void)hipFree(b.first);
   }
 };

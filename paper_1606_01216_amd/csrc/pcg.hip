@@ -8,6 +8,7 @@
 // Reductions are deterministic: one partial per (system, wavefront) and a
 // fixed-order sum per system.  The row kernels sweep the systems whose
 // active flag is set.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -39,6 +40,8 @@ struct ReduceArgs {
   int32_t max_sweeps;
   double tol2_rel;  // tol^2 (outer) or inner_tol^2
   double tol2_abs;  // tol^2 for RM_OUTER
+  const int32_t* flex;  // per shift: 1 = flexible beta, 0 = classical ratio
+  int32_t m;            // systems per shift
 };
 
 // One block of NT threads per system: a fixed-order sum of the system's wave
@@ -98,7 +101,13 @@ __global__ void __launch_bounds__(NT) k_reduce(ReduceArgs P, int mode) {
       if (!isfinite(s1) || !isfinite(rz) || !isfinite(zw)) { Sy.istat[b] = ST_NONFIN; act = 0; }
       else if (s1 <= Sy.tol2[b]) { Sy.istat[b] = ST_CONV; act = 0; }
       else if (it >= P.max_iter) { Sy.istat[b] = ST_MAXIT; act = 0; }
-      else { Sy.beta[b] = -zw / Sy.pw[b]; Sy.rz[b] = rz; Sy.first[b] = 0; }
+      else {
+        // flexible: keeps p K-conjugate to the previous direction under any
+        // preconditioner; classical: the (r, z) ratio, for a symmetric one
+        Sy.beta[b] = P.flex[b / P.m] ? -zw / Sy.pw[b] : rz / Sy.rz[b];
+        Sy.rz[b] = rz;
+        Sy.first[b] = 0;
+      }
       break;
     }
     case RM_INIT_ABS:
@@ -154,8 +163,40 @@ __global__ void k_init_state(SysDev S, int B) {
     S.outer[b] = 1;
     S.istat[b] = ST_MAXIT;
     S.status[b] = ST_MAXIT;
+    S.handed[b] = 0;
   }
   if (b == 0) S.nact[0] = B;
+}
+
+// Systems still iterating when a sweep reaches its iteration cap leave the
+// float32 sweeps (their correction of that sweep is already applied): they
+// are marked for the float64 finish and are no longer refined.
+__global__ void k_handover(SysDev S, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B && S.active[b]) {
+    S.handed[b] = 1;
+    S.active[b] = 0;
+    S.outer[b] = 0;
+  }
+  if (b == 0) S.nact[0] = 0;
+}
+
+// dst column i = src column idx[i] (rows < n), float64.
+__global__ void k_gather_cols(const double* __restrict__ src, int64_t lds,
+                              const int32_t* __restrict__ idx, int64_t n,
+                              double* __restrict__ dst, int64_t ldd) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (r < n) dst[(int64_t)i * ldd + r] = src[(int64_t)idx[i] * lds + r];
+}
+
+// dst column idx[i] = src column i (rows < n), float64.
+__global__ void k_scatter_cols(const double* __restrict__ src, int64_t lds,
+                               const int32_t* __restrict__ idx, int64_t n,
+                               double* __restrict__ dst, int64_t ldd) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (r < n) dst[(int64_t)idx[i] * ldd + r] = src[(int64_t)i * lds + r];
 }
 
 // No system inner-active (before a refinement reduction activates some).
@@ -330,13 +371,17 @@ static airga_status start_inner(Plan<T>& P, Timer& tm, int rel) {
 
 // Run CG iterations until no system is active (bounded by max_iter).
 template <typename T>
-static airga_status iterate(Plan<T>& P, Timer& tm, const airga_pcg_opts& o) {
+// capped: set when the iteration budget of this call (cap_iters > 0) ran
+// out with systems still active.
+static airga_status iterate(Plan<T>& P, Timer& tm, const airga_pcg_opts& o, int64_t cap_iters,
+                            bool* capped) {
   hipStream_t st = P.ctx->stream;
   int32_t* h_nact = reinterpret_cast<int32_t*>(static_cast<char*>(P.ctx->host_pinned) + P.flags_off);
   int k = o.poll_every < 2 ? 2 : o.poll_every;
   k += k & 1;
   airga_ctx ctx = P.ctx;
   const bool use_graph = o.use_graph && !o.profile;
+  hipGraphExec_t exec = nullptr;
   if (use_graph) {
     // launch arguments of the k captured iterations, byte for byte
     std::vector<char> key(sizeof(P.a) + sizeof(P.red) + sizeof(P.ks) + 4 * sizeof(int));
@@ -349,10 +394,15 @@ static airga_status iterate(Plan<T>& P, Timer& tm, const airga_pcg_opts& o) {
     kp += sizeof(P.ks);
     const int extra[4] = {k, P.asm_path ? 1 : 0, P.max_chain_q, (int)P.grid};
     std::memcpy(kp, extra, sizeof extra);
-    if (!ctx->graph_exec || ctx->graph_key != key) {
-      if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
-      ctx->graph_exec = nullptr;
-      ctx->graph_key.clear();
+    size_t found = ctx->graphs.size();
+    for (size_t i = 0; i < ctx->graphs.size(); ++i)
+      if (ctx->graphs[i].first == key) found = i;
+    if (found < ctx->graphs.size()) {
+      // most recently used last
+      std::rotate(ctx->graphs.begin() + (long)found, ctx->graphs.begin() + (long)found + 1,
+                  ctx->graphs.end());
+      exec = ctx->graphs.back().second;
+    } else {
       AIRGA_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
       airga_status s = AIRGA_OK;
       for (int j = 0; j < k && s == AIRGA_OK; ++j) s = iteration(P, tm, j & 1);
@@ -363,21 +413,24 @@ static airga_status iterate(Plan<T>& P, Timer& tm, const airga_pcg_opts& o) {
         return s;
       }
       if (e != hipSuccess) return fail(AIRGA_EHIP, "graph capture failed: %s", hipGetErrorString(e));
-      e = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+      e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
-      if (e != hipSuccess) {
-        ctx->graph_exec = nullptr;
-        return fail(AIRGA_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+      if (e != hipSuccess) return fail(AIRGA_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+      if (ctx->graphs.size() == airga_ctx_s::kGraphs) {
+        (void)hipGraphExecDestroy(ctx->graphs.front().second);
+        ctx->graphs.erase(ctx->graphs.begin());
       }
-      ctx->graph_key = key;
+      ctx->graphs.emplace_back(std::move(key), exec);
     }
   }
   airga_status result = AIRGA_OK;
   // every system stops at max_iter, so max_iter / k + 2 rounds always suffice
-  const int64_t rounds = (int64_t)o.max_iter / k + 2;
+  int64_t rounds = (int64_t)o.max_iter / k + 2;
+  if (cap_iters > 0) rounds = std::min<int64_t>(rounds, (cap_iters + k - 1) / k);
+  if (capped) *capped = false;
   for (int64_t round = 0; round < rounds; ++round) {
     if (use_graph) {
-      hipError_t e = hipGraphLaunch(ctx->graph_exec, st);
+      hipError_t e = hipGraphLaunch(exec, st);
       if (e != hipSuccess) {
         result = fail(AIRGA_EHIP, "hipGraphLaunch: %s", hipGetErrorString(e));
         break;
@@ -395,6 +448,7 @@ static airga_status iterate(Plan<T>& P, Timer& tm, const airga_pcg_opts& o) {
     result = tm.flush();
     if (result != AIRGA_OK || *h_nact == 0) break;
   }
+  if (capped && result == AIRGA_OK && cap_iters > 0 && *h_nact > 0) *capped = true;
   return result;
 }
 
@@ -447,10 +501,10 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
   const bool blk = partial_lds_bytes(B) + (win > win_res ? win : win_res) <= 64 * 1024;
   const int GP = blk ? (int)grid : 4 * (int)grid;
   AIRGA_TRY(ctx->ws_partial.reserve(sizeof(double) * (size_t)B * GP * kSlots));
-  const size_t sys_bytes = (7 * sizeof(double) + 7 * sizeof(int32_t)) * (size_t)B + 256;
+  const size_t sys_bytes = (7 * sizeof(double) + 8 * sizeof(int32_t)) * (size_t)B + 256;
   AIRGA_TRY(ctx->ws_sys.reserve(sys_bytes));
   const size_t shift_bytes = 4 * sizeof(double) * nshift + sizeof(void*) * (size_t)nshift * maxc +
-                             sizeof(int32_t) * nshift + 256;
+                             2 * sizeof(int32_t) * nshift + 256;
   AIRGA_TRY(ctx->ws_shift.reserve(shift_bytes));
   P.flags_off = (shift_bytes + 4095) & ~(size_t)4095;
   AIRGA_TRY(ensure_pinned(ctx, P.flags_off + sizeof(int32_t) * 8 * (size_t)B + 64));
@@ -463,6 +517,7 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
   S.active = iv; S.first = iv + B; S.istat = iv + 2 * B; S.status = iv + 3 * B;
   S.iters = iv + 4 * B; S.sweeps = iv + 5 * B; S.outer = iv + 6 * B;
   S.nact = iv + 7 * B;
+  S.handed = iv + 7 * B + 64;
   // per-shift block, staged in pinned memory and copied once
   char* hp = static_cast<char*>(ctx->host_pinned);
   double* h_ca64 = reinterpret_cast<double*>(hp);
@@ -472,6 +527,7 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
   const size_t off_fac = 4 * sizeof(double) * nshift;
   const T** h_fac = reinterpret_cast<const T**>(hp + off_fac);
   int32_t* h_clen = reinterpret_cast<int32_t*>(hp + off_fac + sizeof(void*) * (size_t)nshift * maxc);
+  int32_t* h_flex = h_clen + nshift;
   P.clen.assign(nshift, 0);
   P.max_chain_q = 0;
   for (int k = 0; k < nshift; ++k) {
@@ -486,6 +542,7 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
     P.clen[k] = L;
     P.max_chain_q = L > P.max_chain_q ? L : P.max_chain_q;
     for (int q = 0; q < maxc; ++q) h_fac[(size_t)k * maxc + q] = q < L ? chains[k][q] : nullptr;
+    h_flex[k] = o.beta_form == AIRGA_BETA_FLEXIBLE;
   }
   AIRGA_HIP(hipMemcpyAsync(ctx->ws_shift.ptr, hp, shift_bytes - 256, hipMemcpyHostToDevice, st));
   char* sd = ctx->ws_shift.as<char>();
@@ -518,6 +575,8 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
   A.cb = A.ca + nshift;
   A.fac = reinterpret_cast<const T* const*>(sd + off_fac);
   A.clen = reinterpret_cast<const int32_t*>(sd + off_fac + sizeof(void*) * (size_t)nshift * maxc);
+  P.red.flex = A.clen + nshift;
+  P.red.m = m;
   A.maxc = maxc;
   A.partial = ctx->ws_partial.as<double>();
   A.GP = GP;
@@ -629,7 +688,7 @@ static airga_status read_stats(airga_ctx ctx, const SysDev& S, int B, bool mixed
     stats[b].status = mixed ? (out[b] ? ST_MAXIT : sta[b]) : ist[b];
     stats[b].iters = its[b];
     stats[b].sweeps = mixed ? swp[b] : 1;
-    stats[b].reserved = 0;
+    stats[b].finished_fp64 = 0;
     stats[b].relres = rel[b];
   }
   return AIRGA_OK;
@@ -649,10 +708,11 @@ static airga_status forced_cfg(const Pencil& pen, const airga_pcg_opts& o, int* 
               o.tile_rows, o.tile_sys);
 }
 
+// fmap (device, optional): column of F for each system instead of b % m.
 static airga_status solve_fp64(airga_ctx ctx, int32_t nshift, const double* shifts,
                                const airga_prec* precs, int32_t m, const double* F, int64_t ldf,
                                double* X, int64_t ldx, const airga_pcg_opts& o,
-                               airga_sys_stats* stats) {
+                               airga_sys_stats* stats, const int32_t* fmap = nullptr) {
   const Pencil& pen = ctx->pen;
   hipStream_t st = ctx->stream;
   const int B = nshift * m;
@@ -678,6 +738,7 @@ static airga_status solve_fp64(airga_ctx ctx, int32_t nshift, const double* shif
     P.a.kv = nullptr;
     P.asm_path = true;
   }
+  P.a.fmap = fmap;
   const double* ca64 = reinterpret_cast<const double*>(ctx->ws_shift.ptr);
   const double* cb64 = ca64 + nshift;
   P.red.tol2_rel = o.tol * o.tol;
@@ -687,7 +748,7 @@ static airga_status solve_fp64(airga_ctx ctx, int32_t nshift, const double* shif
                                                          1 - x0, x0 ? 2 : 1));
   TIMED(K_REDUCE, reduce(P, RM_START));
   AIRGA_TRY(start_inner(P, tm, 0));
-  AIRGA_TRY(iterate(P, tm, o));
+  AIRGA_TRY(iterate(P, tm, o, 0, nullptr));
   // result out, then its true residual
   TIMED(K_IR_UPDATE, (k_copy_out<<<dim3(blocks_for(pen.n, 256), (unsigned)B), 256, 0, st>>>(
                          P.a.ws + (int64_t)KX * B * P.a.ld, P.a.ld, pen.n, X, ldx)));
@@ -695,6 +756,60 @@ static airga_status solve_fp64(airga_ctx ctx, int32_t nshift, const double* shif
   TIMED(K_REDUCE, reduce(P, RM_FINAL));
   AIRGA_TRY(tm.flush());
   return read_stats(ctx, P.a.sys, B, false, stats);
+}
+
+// Float32 iterations per refinement sweep before a system still iterating
+// is handed to the float64 finish.
+constexpr int64_t kInnerMax = 96;
+
+// Float64 finish of a mixed solve: the systems `sys` (indices k*m + c) are
+// gathered into a contiguous batch, solved by the float64 path from their
+// current X, and scattered back; their stats absorb the float64 stage.
+static airga_status finish_fp64(airga_ctx ctx, const double* shifts, const airga_prec* precs,
+                                int32_t m, const double* F, int64_t ldf, double* X, int64_t ldx,
+                                const airga_pcg_opts& o, const std::vector<int>& sys,
+                                airga_sys_stats* stats) {
+  const Pencil& pen = ctx->pen;
+  hipStream_t st = ctx->stream;
+  const int Bp = (int)sys.size();
+  const int64_t n = pen.n;
+  const size_t idx_bytes = (2 * sizeof(int32_t) * (size_t)Bp + 255) & ~(size_t)255;
+  AIRGA_TRY(ctx->ws_gather.reserve(idx_bytes + sizeof(double) * (size_t)Bp * n));
+  int32_t* d_idx = ctx->ws_gather.as<int32_t>();
+  double* Xp = reinterpret_cast<double*>(ctx->ws_gather.as<char>() + idx_bytes);
+  AIRGA_TRY(ensure_pinned(ctx, 2 * sizeof(int32_t) * (size_t)Bp));
+  int32_t* h_idx = static_cast<int32_t*>(ctx->host_pinned);
+  std::vector<double> sh(Bp);
+  std::vector<airga_prec> pr(Bp);
+  for (int i = 0; i < Bp; ++i) {
+    h_idx[i] = sys[i] % m;        // column of F
+    h_idx[Bp + i] = sys[i];       // column of X
+    sh[i] = shifts[sys[i] / m];
+    pr[i] = precs ? precs[sys[i] / m] : nullptr;
+  }
+  AIRGA_HIP(hipMemcpyAsync(d_idx, h_idx, 2 * sizeof(int32_t) * Bp, hipMemcpyHostToDevice, st));
+  // the pinned staging area is rewritten by the solve below
+  AIRGA_HIP(hipStreamSynchronize(st));
+  const dim3 grid(blocks_for(n, 256), (unsigned)Bp);
+  k_gather_cols<<<grid, 256, 0, st>>>(X, ldx, d_idx + Bp, n, Xp, n);
+  AIRGA_HIP(hipGetLastError());
+  airga_pcg_opts o64 = o;
+  o64.mode = AIRGA_MODE_FP64;
+  o64.x0_given = 1;
+  std::vector<airga_sys_stats> s64(Bp);
+  // each system keeps its own column of F through the column map
+  AIRGA_TRY(solve_fp64(ctx, Bp, sh.data(), pr.data(), 1, F, ldf, Xp, n, o64, s64.data(), d_idx));
+  k_scatter_cols<<<grid, 256, 0, st>>>(Xp, n, d_idx + Bp, n, X, ldx);
+  AIRGA_HIP(hipGetLastError());
+  for (int i = 0; i < Bp; ++i) {
+    airga_sys_stats& e = stats[sys[i]];
+    e.status = s64[i].status;
+    e.iters += s64[i].iters;
+    e.sweeps += 1;
+    e.relres = s64[i].relres;
+    e.finished_fp64 = 1;
+  }
+  return AIRGA_OK;
 }
 
 static airga_status solve_mixed(airga_ctx ctx, int32_t nshift, const double* shifts,
@@ -722,19 +837,40 @@ static airga_status solve_mixed(airga_ctx ctx, int32_t nshift, const double* shi
   k_clear_active<<<blocks_for(B, 256), 256, 0, st>>>(P.a.sys, B);
   AIRGA_HIP(hipGetLastError());
   TIMED(K_REDUCE, reduce(P, RM_OUTER));
+  const int64_t cap = o.inner_max > 0 ? o.inner_max : kInnerMax;
+  bool any_handed = false;
   for (int sweep = 0; sweep <= o.max_sweeps; ++sweep) {
     AIRGA_HIP(hipMemcpyAsync(h_nact, P.a.sys.nact, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     AIRGA_HIP(hipStreamSynchronize(st));
     if (*h_nact == 0) break;
     AIRGA_TRY(start_inner(P, tm, 1));
-    AIRGA_TRY(iterate(P, tm, o));
+    bool capped = false;
+    AIRGA_TRY(iterate(P, tm, o, cap, &capped));
     TIMED(K_IR_UPDATE,
           (k_ir_update<<<dim3(blocks_for(pen.n, 256), (unsigned)B), 256, 0, st>>>(P.a, X, ldx)));
+    if (capped) {
+      k_handover<<<blocks_for(B, 256), 256, 0, st>>>(P.a.sys, B);
+      AIRGA_HIP(hipGetLastError());
+      any_handed = true;
+    }
     TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds_res, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, 1, 0, 1));
     TIMED(K_REDUCE, reduce(P, RM_OUTER));
   }
   AIRGA_TRY(tm.flush());
-  return read_stats(ctx, P.a.sys, B, true, stats);
+  std::vector<airga_sys_stats> mixed(B);
+  AIRGA_TRY(read_stats(ctx, P.a.sys, B, true, mixed.data()));
+  std::vector<int> handed;
+  if (any_handed) {
+    std::vector<int32_t> h(B);
+    AIRGA_HIP(hipMemcpyAsync(h.data(), P.a.sys.handed, sizeof(int32_t) * B, hipMemcpyDeviceToHost, st));
+    AIRGA_HIP(hipStreamSynchronize(st));
+    for (int b = 0; b < B; ++b)
+      if (h[b]) handed.push_back(b);
+  }
+  if (!handed.empty())
+    AIRGA_TRY(finish_fp64(ctx, shifts, precs, m, F, ldf, X, ldx, o, handed, mixed.data()));
+  if (stats) std::copy(mixed.begin(), mixed.end(), stats);
+  return AIRGA_OK;
 }
 
 }  // namespace airga
@@ -749,7 +885,7 @@ void airga_pcg_opts_default(airga_pcg_opts* o) {
   o->tol = 1e-10;
   o->max_iter = 20000;
   o->mode = AIRGA_MODE_FP64;
-  o->inner_tol = 1e-4;
+  o->inner_tol = 1e-3;
   o->max_sweeps = 12;
   o->poll_every = 8;
   o->x0_given = 0;
@@ -779,7 +915,8 @@ airga_status airga_pcg_solve(airga_ctx ctx, int32_t nshift, const double* shifts
   airga_pcg_opts o;
   airga_pcg_opts_default(&o);
   if (opts) o = *opts;
-  if (!(o.tol >= 0) || o.max_iter < 0 || (o.mode != AIRGA_MODE_FP64 && o.mode != AIRGA_MODE_MIXED))
+  if (!(o.tol >= 0) || o.max_iter < 0 || (o.mode != AIRGA_MODE_FP64 && o.mode != AIRGA_MODE_MIXED) ||
+      o.beta_form < AIRGA_BETA_FLEXIBLE || o.beta_form > AIRGA_BETA_CLASSICAL)
     return fail(AIRGA_EINVAL, "bad solver options");
   if (o.mode == AIRGA_MODE_MIXED && (!(o.inner_tol > 0 && o.inner_tol < 1) || o.max_sweeps < 0))
     return fail(AIRGA_EINVAL, "bad refinement options");

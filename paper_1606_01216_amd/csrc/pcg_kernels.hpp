@@ -42,6 +42,7 @@ struct SysDev {
   double *rz, *pw, *alpha, *beta, *tol2, *ff, *relres;
   int32_t *active, *first, *istat, *status, *iters, *sweeps, *outer;
   int32_t* nact;    // number of systems with active set (for the host's polling)
+  int32_t* handed;  // mixed mode: 1 = left the float32 sweeps for the float64 finish
 };
 
 template <typename T>
@@ -62,6 +63,7 @@ struct SolveArgs {
   int32_t blk;               // 1: the 4 wavefronts of a block pre-sum their partials in LDS
   int32_t bw;                // pencil bandwidth max |c - r| (banded kernels: <= 64)
   int32_t stage_off;         // doubles of dynamic LDS before the banded staging area
+  const int32_t* fmap;       // column of F for system b (nullptr: b % m)
   SysDev sys;
   __device__ __forceinline__ T* vec(int kind, int b) const {
     return ws + ((int64_t)kind * B + b) * ld;
@@ -660,7 +662,8 @@ __global__ void __launch_bounds__(256) k_residual(SolveArgs<TO> A, const double*
     for (int u = 0; u < U; ++u) {
       const int b = bs[u] >= 0 ? bs[u] : bs[0];
       const double a = sload(ca64 + b / A.m), cbv = sload(cb64 + b / A.m);
-      const double* __restrict__ f = F + (int64_t)(b % A.m) * ldf;
+      const int fc = A.fmap ? sload(A.fmap + b) : b % A.m;
+      const double* __restrict__ f = F + (int64_t)fc * ldf;
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         const int64_t row = rows.row[i];

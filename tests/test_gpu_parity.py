@@ -253,23 +253,30 @@ def test_batched_solve_matches_reference(ctx, mode):
             assert rel_err(Xh[k, c], ref[k, c]) < SOLVE_TOL, (s, c)
 
 
-def test_fp64_iterates_follow_the_oracle_recurrence(ctx):
+@pytest.mark.parametrize("form,oracle_beta", [(airga.BETA_FLEXIBLE, "flexible"),
+                                              (airga.BETA_CLASSICAL, "fr")])
+def test_fp64_iterates_follow_the_oracle_recurrence(ctx, form, oracle_beta):
+    """Both direction updates against the oracle's (the symmetrised build is a
+    symmetric factor, so the classical ratio applies too)."""
     pen = sur_beam(700)
     set_pencil(ctx, pen)
     f = beam.tip_load(pen.n)
     for s in (1.0, 100.0):
         a = pencil.shifted_operator(pen, s)
         pm = spai.spai_build(a).matrix()
-        ref = opcg.pcg(lambda v: a @ v, lambda v: pm @ v, f[0], tol=1e-10, max_iter=5000)
-        X, st = ctx.pcg_solve([s], [ctx.spai_build(s)], to_dev(f, torch.float64), tol=1e-10)
+        ref = opcg.pcg(lambda v: a @ v, lambda v: pm @ v, f[0], tol=1e-10, max_iter=5000,
+                       beta=oracle_beta)
+        X, st = ctx.pcg_solve([s], [ctx.spai_build(s)], to_dev(f, torch.float64), tol=1e-10,
+                              beta_form=form)
         assert st[0]["status"] == airga.SYS_CONVERGED
         assert abs(st[0]["iters"] - ref.iters) <= 2, (st[0], ref.iters)
         assert rel_err(X.cpu().numpy()[0, 0], ref.x) < 1e-9
         # stopping after exactly the oracle's iteration count gives the same iterate
         k = min(ref.iters, 6)
-        r6 = opcg.pcg(lambda v: a @ v, lambda v: pm @ v, f[0], tol=0.0, max_iter=k)
+        r6 = opcg.pcg(lambda v: a @ v, lambda v: pm @ v, f[0], tol=0.0, max_iter=k,
+                      beta=oracle_beta)
         X6, st6 = ctx.pcg_solve([s], [ctx.spai_build(s)], to_dev(f, torch.float64), tol=0.0,
-                                max_iter=k)
+                                max_iter=k, beta_form=form)
         assert st6[0]["status"] == airga.SYS_MAXIT and st6[0]["iters"] == k
         assert rel_err(X6.cpu().numpy()[0, 0], r6.x) < 1e-12
 
@@ -379,6 +386,49 @@ def test_literal_cantilever_c1(ctx):
     ref = reference(pen, shifts, f)
     assert st[0]["status"] == airga.SYS_CONVERGED, st
     assert rel_err(X.cpu().numpy()[0, 0], ref[0, 0]) < 1e-7
+    # mixed precision: float32 cannot resolve this system (condition number
+    # near 1/eps_32), so the first capped sweep hands it to the float64 finish
+    Xm, sm = ctx.pcg_solve(list(shifts), [p], to_dev(f, torch.float64), tol=1e-10, max_iter=40000,
+                           mode=airga.MODE_MIXED)
+    assert sm[0]["status"] == airga.SYS_CONVERGED and sm[0]["finished_fp64"] == 1, sm
+    assert rel_err(Xm.cpu().numpy()[0, 0], ref[0, 0]) < 1e-7
+
+
+@pytest.mark.parametrize("inner_max", [8, 16])
+def test_mixed_handover_to_float64_finish(ctx, inner_max):
+    """Systems still iterating at the per-sweep cap leave the float32 sweeps
+    and finish in float64 from their current X, batched; every system still
+    meets the oracle tolerance, the flags name the handed ones, and a cap
+    too large to bind hands none over."""
+    pen = beam.make_beam(1500, ei_loguniform=(0.1, 10.0), surrogate=True, seed=6)
+    set_pencil(ctx, pen)
+    rng = np.random.default_rng(2)
+    f = np.stack([beam.tip_load(pen.n)[0], rng.standard_normal(pen.n)])
+    shifts = [1.0, 8.0, 300.0]
+    precs = [ctx.spai_build(s) for s in shifts]
+    ref = reference(pen, shifts, f)
+    F = to_dev(f, torch.float64)
+    X, st = ctx.pcg_solve(shifts, precs, F, tol=1e-10, mode=airga.MODE_MIXED, inner_max=inner_max)
+    Xh = X.cpu().numpy()
+    for k in range(3):
+        for c in range(2):
+            e = st[2 * k + c]
+            assert e["status"] == airga.SYS_CONVERGED, e
+            assert rel_err(Xh[k, c], ref[k, c]) < SOLVE_TOL, (k, c, e)
+    assert any(e["finished_fp64"] for e in st)
+    # without the cap nothing is handed over; float32 refinement alone then
+    # fails on the low shift (its condition number defeats float32), and
+    # says so: every system reported converged meets the tolerance
+    X2, st2 = ctx.pcg_solve(shifts, precs, F, tol=1e-10, mode=airga.MODE_MIXED, inner_max=100000)
+    assert not any(e["finished_fp64"] for e in st2)
+    Xh2 = X2.cpu().numpy()
+    for k in range(3):
+        for c in range(2):
+            e = st2[2 * k + c]
+            if e["status"] == airga.SYS_CONVERGED:
+                assert rel_err(Xh2[k, c], ref[k, c]) < SOLVE_TOL, (k, c, e)
+            else:
+                assert e["status"] == airga.SYS_MAXIT and e["relres"] > 1e-10, e
 
 
 # --------------------------------------------------------- moment matching
