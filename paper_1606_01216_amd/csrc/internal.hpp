@@ -85,6 +85,7 @@ struct PencilDev {
   const int32_t* mirror;     // stored index of entry (c, r) for entry (r, c)
   const int32_t* csr_pos;    // CSR position of each stored entry, -1 for padding
   const int32_t* diag_pos;   // stored index of (r, r)
+  const int8_t* coff;        // column - row of each stored entry (bandwidth <= 64 only)
   const double* m64;
   const double* k64;
   const float* m32;
@@ -101,6 +102,7 @@ struct Pencil {
   bool diag_ok = false;  // M_rr > 0 and K_rr >= 0 for every row
   bool uniform_width = false;  // every slice is max_len entries wide
   DevBuf slice_ptr, row_len, col, mirror, csr_pos, diag_pos, m64, k64, m32, k32;
+  DevBuf coff;        // int8 column offsets (banded pencils)
   DevBuf id64, id32;  // the identity on the pattern (solves without a preconditioner)
   PencilDev dev() const;
   int64_t n_pad() const { return (int64_t)n_slices * kSlice; }

@@ -371,10 +371,14 @@ static airga_status start_inner(Plan<T>& P, Timer& tm, int rel) {
 
 // Run CG iterations until no system is active (bounded by max_iter).
 template <typename T>
-// capped: set when the iteration budget of this call (cap_iters > 0) ran
-// out with systems still active.
+// Mixed sweeps (cap_iters > 0): the sweep ends for the systems still active
+// when cap_iters iterations have run, or earlier once at most a quarter of
+// the nact0 systems it started with remain and they have had four times the
+// rounds half of the batch needed (plus one): stragglers are then handed to
+// the float64 finish instead of holding the batch.  capped reports such an
+// end with systems still active.
 static airga_status iterate(Plan<T>& P, Timer& tm, const airga_pcg_opts& o, int64_t cap_iters,
-                            bool* capped) {
+                            int nact0, bool* capped) {
   hipStream_t st = P.ctx->stream;
   int32_t* h_nact = reinterpret_cast<int32_t*>(static_cast<char*>(P.ctx->host_pinned) + P.flags_off);
   int k = o.poll_every < 2 ? 2 : o.poll_every;
@@ -428,6 +432,7 @@ static airga_status iterate(Plan<T>& P, Timer& tm, const airga_pcg_opts& o, int6
   int64_t rounds = (int64_t)o.max_iter / k + 2;
   if (cap_iters > 0) rounds = std::min<int64_t>(rounds, (cap_iters + k - 1) / k);
   if (capped) *capped = false;
+  int64_t half_rounds = -1;  // rounds until at most half of nact0 was left
   for (int64_t round = 0; round < rounds; ++round) {
     if (use_graph) {
       hipError_t e = hipGraphLaunch(exec, st);
@@ -447,6 +452,10 @@ static airga_status iterate(Plan<T>& P, Timer& tm, const airga_pcg_opts& o, int6
     }
     result = tm.flush();
     if (result != AIRGA_OK || *h_nact == 0) break;
+    if (cap_iters > 0 && nact0 >= 8) {
+      if (half_rounds < 0 && 2 * *h_nact <= nact0) half_rounds = round + 1;
+      if (half_rounds > 0 && 4 * *h_nact <= nact0 && round + 1 >= 4 * half_rounds + 1) break;
+    }
   }
   if (capped && result == AIRGA_OK && cap_iters > 0 && *h_nact > 0) *capped = true;
   return result;
@@ -748,7 +757,7 @@ static airga_status solve_fp64(airga_ctx ctx, int32_t nshift, const double* shif
                                                          1 - x0, x0 ? 2 : 1));
   TIMED(K_REDUCE, reduce(P, RM_START));
   AIRGA_TRY(start_inner(P, tm, 0));
-  AIRGA_TRY(iterate(P, tm, o, 0, nullptr));
+  AIRGA_TRY(iterate(P, tm, o, 0, 0, nullptr));
   // result out, then its true residual
   TIMED(K_IR_UPDATE, (k_copy_out<<<dim3(blocks_for(pen.n, 256), (unsigned)B), 256, 0, st>>>(
                          P.a.ws + (int64_t)KX * B * P.a.ld, P.a.ld, pen.n, X, ldx)));
@@ -845,7 +854,7 @@ static airga_status solve_mixed(airga_ctx ctx, int32_t nshift, const double* shi
     if (*h_nact == 0) break;
     AIRGA_TRY(start_inner(P, tm, 1));
     bool capped = false;
-    AIRGA_TRY(iterate(P, tm, o, cap, &capped));
+    AIRGA_TRY(iterate(P, tm, o, cap, *h_nact, &capped));
     TIMED(K_IR_UPDATE,
           (k_ir_update<<<dim3(blocks_for(pen.n, 256), (unsigned)B), 256, 0, st>>>(P.a, X, ldx)));
     if (capped) {

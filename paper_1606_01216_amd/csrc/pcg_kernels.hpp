@@ -107,7 +107,8 @@ __device__ __forceinline__ int chain_dst(int q, int L) { return ((L - 1 - q) & 1
 // Row set of one wavefront: R consecutive slices.  Slice data are uniform
 // across the wavefront (scalar loads).  Entries past a slice's width get the
 // row itself as column and value 0, so every loop runs WMAX entries with no
-// test; EXACT marks pencils whose slices are all WMAX wide.
+// test; EXACT marks pencils whose slices are all WMAX wide.  OFF8 (banded
+// pencils) reads the 1-byte offsets column - row instead of 4-byte columns.
 template <int WMAX, int R, bool EXACT>
 struct Rows {
   int32_t col[R][WMAX];
@@ -115,6 +116,7 @@ struct Rows {
   int32_t w[R];
   bool valid[R];
   int64_t row[R];
+  template <bool OFF8 = false>
   __device__ __forceinline__ void load(const PencilDev& pd, int wg, int lane) {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
@@ -131,8 +133,13 @@ struct Rows {
         idx0[i] = sp0 + lane;
       }
 #pragma unroll
-      for (int k = 0; k < WMAX; ++k)
-        col[i][k] = (valid[i] && (EXACT || k < w[i])) ? pd.col[idx0[i] + k * kSlice] : (int32_t)row[i];
+      for (int k = 0; k < WMAX; ++k) {
+        const bool in = valid[i] && (EXACT || k < w[i]);
+        if constexpr (OFF8)
+          col[i][k] = (int32_t)row[i] + (in ? (int32_t)pd.coff[idx0[i] + k * kSlice] : 0);
+        else
+          col[i][k] = in ? pd.col[idx0[i] + k * kSlice] : (int32_t)row[i];
+      }
     }
   }
   template <typename T>
@@ -234,7 +241,7 @@ __global__ void __launch_bounds__(256) k_dir_spmv(SolveArgs<T> A, int par) {
   const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
   extern __shared__ double lds_part[];
   Rows<WMAX, R, EXACT> rows;
-  rows.load(A.pd, wg, lane);
+  rows.template load<BAND>(A.pd, wg, lane);
   T mv[R][WMAX], kv[R][WMAX];
   rows.values(A.mv, mv);
   if constexpr (!ASM) rows.values(A.kv, kv);
@@ -356,7 +363,7 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
   const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
   extern __shared__ double lds_part[];
   Rows<WMAX, R, EXACT> rows;
-  rows.load(A.pd, wg, lane);
+  rows.template load<BAND>(A.pd, wg, lane);
   Window<WMAX, R> win;
   T* stg = nullptr;
   if constexpr (BAND) {
@@ -576,7 +583,7 @@ __global__ void __launch_bounds__(256) k_residual(SolveArgs<TO> A, const double*
   const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
   extern __shared__ double lds_part[];
   Rows<WMAX, R, EXACT> rows;
-  rows.load(A.pd, wg, lane);
+  rows.template load<BAND>(A.pd, wg, lane);
   double mv[R][WMAX], kv[R][WMAX];
   rows.values(A.pd.m64, mv);
   rows.values(A.pd.k64, kv);

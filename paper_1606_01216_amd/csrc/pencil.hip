@@ -60,6 +60,7 @@ PencilDev Pencil::dev() const {
   d.mirror = mirror.as<int32_t>();
   d.csr_pos = csr_pos.as<int32_t>();
   d.diag_pos = diag_pos.as<int32_t>();
+  d.coff = bandwidth <= kSlice ? coff.as<int8_t>() : nullptr;
   d.m64 = m64.as<double>();
   d.k64 = k64.as<double>();
   d.m32 = m32.as<float>();
@@ -195,7 +196,8 @@ __global__ void k_scatter(int32_t n, int64_t n_pad, const int32_t* __restrict__ 
                           const int32_t* __restrict__ row_len, int32_t* __restrict__ col,
                           int32_t* __restrict__ csr_pos, int32_t* __restrict__ diag_pos,
                           double* __restrict__ m64, double* __restrict__ k64,
-                          float* __restrict__ m32, float* __restrict__ k32) {
+                          float* __restrict__ m32, float* __restrict__ k32,
+                          int8_t* __restrict__ coff) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= n_pad) return;
   const int64_t s = r / kSlice;
@@ -210,6 +212,7 @@ __global__ void k_scatter(int32_t n, int64_t n_pad, const int32_t* __restrict__ 
       const int64_t e = rp[r] + k;
       const int32_t c = ci[e];
       col[idx] = c;
+      if (coff) coff[idx] = (int8_t)(c - r);
       csr_pos[idx] = (int32_t)e;
       const double a = mv[e], b = kv[e];
       m64[idx] = a;
@@ -219,6 +222,7 @@ __global__ void k_scatter(int32_t n, int64_t n_pad, const int32_t* __restrict__ 
       if (c == r) diag_pos[r] = idx;
     } else {
       col[idx] = (int32_t)r;
+      if (coff) coff[idx] = 0;
       csr_pos[idx] = -1;
       m64[idx] = 0.0;
       k64[idx] = 0.0;
@@ -433,11 +437,13 @@ static airga_status set_pencil_impl(airga_ctx ctx, int32_t n, int64_t nnz, const
   AIRGA_TRY(pen.k64.reserve(sizeof(double) * stored));
   AIRGA_TRY(pen.m32.reserve(sizeof(float) * stored));
   AIRGA_TRY(pen.k32.reserve(sizeof(float) * stored));
+  const bool banded = h.bw <= kSlice;
+  if (banded) AIRGA_TRY(pen.coff.reserve(stored));
   k_scatter<<<blocks_for(n_pad, 256), 256, 0, st>>>(
       n, n_pad, row_ptr, col_idx, m_val, k_val, pen.slice_ptr.as<int32_t>(),
       pen.row_len.as<int32_t>(), pen.col.as<int32_t>(), pen.csr_pos.as<int32_t>(),
       pen.diag_pos.as<int32_t>(), pen.m64.as<double>(), pen.k64.as<double>(),
-      pen.m32.as<float>(), pen.k32.as<float>());
+      pen.m32.as<float>(), pen.k32.as<float>(), banded ? pen.coff.as<int8_t>() : nullptr);
   AIRGA_HIP(hipGetLastError());
   k_mirror<<<blocks_for(n_pad, 256), 256, 0, st>>>(n, n_pad, row_ptr, col_idx,
                                                    pen.slice_ptr.as<int32_t>(),
