@@ -364,13 +364,16 @@ def main():
     # ---- roofline of the dominant row kernel (algorithmic bytes / duration)
     stored = info.nnz_stored
     w = 4  # float32 inner solves
+    # column information per stored entry: a 1-byte offset for banded
+    # pencils (bandwidth <= 64, the LDS-window kernels), else a 4-byte index
+    ib = 1 if info.bandwidth <= 64 else 4
     def kbytes(name, launches, sysp, shp):
         if name == "dir_spmv":
-            return launches * stored * (4 + 2 * w) + sysp * 4 * w * n
+            return launches * stored * (ib + 2 * w) + sysp * 4 * w * n
         if name == "update_prec":
-            return launches * stored * 4 + shp * stored * w + sysp * 7 * w * n
+            return launches * stored * ib + shp * stored * w + sysp * 7 * w * n
         if name == "init_prec":
-            return launches * stored * 4 + shp * stored * w + sysp * 2 * w * n
+            return launches * stored * ib + shp * stored * w + sysp * 2 * w * n
         return None
     rows = []
     for name in ("dir_spmv", "update_prec", "init_prec", "chain", "ir_residual", "ir_update", "reduce"):

@@ -103,6 +103,8 @@ struct Pencil {
   bool uniform_width = false;  // every slice is max_len entries wide
   DevBuf slice_ptr, row_len, col, mirror, csr_pos, diag_pos, m64, k64, m32, k32;
   DevBuf coff;        // int8 column offsets (banded pencils)
+  DevBuf setup;       // scratch of set_pencil (pattern summary, per-slice data)
+  DevBuf gram_ws;     // scratch of set_pencil (Gram partial sums)
   DevBuf id64, id32;  // the identity on the pattern (solves without a preconditioner)
   PencilDev dev() const;
   int64_t n_pad() const { return (int64_t)n_slices * kSlice; }

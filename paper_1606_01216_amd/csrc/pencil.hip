@@ -113,10 +113,13 @@ enum PatternFlag : int32_t {
 };
 
 // One thread per (padded) row; a 256-thread block covers four slices, so each
-// wavefront is exactly one slice.  stats[0] = bandwidth, stats[1] = longest row.
+// wavefront is exactly one slice.  Per slice: longest row (slice_w), widest
+// band (slice_b) and pattern flags (slice_f), plain stores reduced by
+// k_scan_slices (no same-address atomics).
 __global__ void k_rows_check(int32_t n, int64_t nnz, int64_t n_pad, const int32_t* __restrict__ rp,
                              const int32_t* __restrict__ ci, int32_t* __restrict__ row_len,
-                             int32_t* __restrict__ slice_w, int32_t* flags, int32_t* stats) {
+                             int32_t* __restrict__ slice_w, int32_t* __restrict__ slice_b,
+                             int32_t* __restrict__ slice_f) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int len = 0, bw = 0, bad = 0;
   if (r < n) {
@@ -154,24 +157,50 @@ __global__ void k_rows_check(int32_t n, int64_t nnz, int64_t n_pad, const int32_
   for (int off = 32; off > 0; off >>= 1) bor |= __shfl_xor(bor, off, 64);
   if ((threadIdx.x & 63) == 0 && r < n_pad) {
     slice_w[r / kSlice] = lmax;
-    atomicMax(&stats[0], bmax);
-    atomicMax(&stats[1], lmax);
-    if (bor) atomicOr(flags, bor);
+    slice_b[r / kSlice] = bmax;
+    slice_f[r / kSlice] = bor;
   }
 }
 
-// Exclusive scan of slice widths * 64 into slice_ptr (one 1024-thread block).
-__global__ void k_scan_slices(int32_t ns, const int32_t* __restrict__ w, int32_t* __restrict__ sp,
+// Exclusive scan of slice widths * 64 into slice_ptr (one 1024-thread
+// block), plus the pattern summary: info = {flags (OR), bandwidth (max),
+// longest row (max)} and the stored total.
+__global__ void k_scan_slices(int32_t ns, const int32_t* __restrict__ w,
+                              const int32_t* __restrict__ b, const int32_t* __restrict__ f,
+                              int32_t* __restrict__ sp, int32_t* __restrict__ info,
                               int64_t* total) {
   __shared__ int64_t part[1024];
+  __shared__ int32_t red[3][1024];
   const int t = threadIdx.x;
   const int64_t chunk = ((int64_t)ns + 1023) / 1024;
   const int64_t lo = t * chunk;
   const int64_t hi = lo + chunk < ns ? lo + chunk : ns;
   int64_t s = 0;
-  for (int64_t i = lo; i < hi; ++i) s += (int64_t)w[i] * kSlice;
+  int32_t fo = 0, bm = 0, wm = 0;
+  for (int64_t i = lo; i < hi; ++i) {
+    s += (int64_t)w[i] * kSlice;
+    fo |= f[i];
+    bm = b[i] > bm ? b[i] : bm;
+    wm = w[i] > wm ? w[i] : wm;
+  }
+  red[0][t] = fo;
+  red[1][t] = bm;
+  red[2][t] = wm;
   part[t] = s;
   __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if (t < h) {
+      red[0][t] |= red[0][t + h];
+      red[1][t] = red[1][t + h] > red[1][t] ? red[1][t + h] : red[1][t];
+      red[2][t] = red[2][t + h] > red[2][t] ? red[2][t + h] : red[2][t];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    info[0] = red[0][0];
+    info[1] = red[1][0];
+    info[2] = red[2][0];
+  }
   for (int off = 1; off < 1024; off <<= 1) {
     const int64_t v = t >= off ? part[t - off] : 0;
     __syncthreads();
@@ -391,28 +420,29 @@ static airga_status set_pencil_impl(airga_ctx ctx, int32_t n, int64_t nnz, const
   hipStream_t st = ctx->stream;
   const int32_t ns = (int32_t)((n + kSlice - 1) / kSlice);
   const int64_t n_pad = (int64_t)ns * kSlice;
-  DevBuf scratch;  // flags, stats, total, slice widths
+  // setup scratch, kept with the pencil: [info (3) | total | per-slice
+  // widths, bands, flags]
   const size_t off_w = 64;
-  AIRGA_TRY(scratch.reserve(off_w + sizeof(int32_t) * (size_t)ns));
-  int32_t* flags = scratch.as<int32_t>();
-  int32_t* stats = flags + 2;
-  int64_t* total = reinterpret_cast<int64_t*>(scratch.as<char>() + 32);
-  int32_t* slice_w = reinterpret_cast<int32_t*>(scratch.as<char>() + off_w);
-  AIRGA_HIP(hipMemsetAsync(scratch.ptr, 0, off_w, st));
+  AIRGA_TRY(pen.setup.reserve(off_w + 3 * sizeof(int32_t) * (size_t)ns));
+  int32_t* info = pen.setup.as<int32_t>();
+  int64_t* total = reinterpret_cast<int64_t*>(pen.setup.as<char>() + 16);
+  int32_t* slice_w = reinterpret_cast<int32_t*>(pen.setup.as<char>() + off_w);
+  int32_t* slice_b = slice_w + ns;
+  int32_t* slice_f = slice_b + ns;
   AIRGA_TRY(pen.row_len.reserve(sizeof(int32_t) * n_pad));
   AIRGA_TRY(pen.slice_ptr.reserve(sizeof(int32_t) * (ns + 1)));
   k_rows_check<<<blocks_for(n_pad, 256), 256, 0, st>>>(n, nnz, n_pad, row_ptr, col_idx,
-                                                       pen.row_len.as<int32_t>(), slice_w, flags,
-                                                       stats);
+                                                       pen.row_len.as<int32_t>(), slice_w, slice_b,
+                                                       slice_f);
   AIRGA_HIP(hipGetLastError());
-  k_scan_slices<<<1, 1024, 0, st>>>(ns, slice_w, pen.slice_ptr.as<int32_t>(), total);
+  k_scan_slices<<<1, 1024, 0, st>>>(ns, slice_w, slice_b, slice_f, pen.slice_ptr.as<int32_t>(),
+                                    info, total);
   AIRGA_HIP(hipGetLastError());
   struct {
-    int32_t flags, pad, bw, maxlen;
+    int32_t flags, bw, maxlen, pad;
     int64_t total;
   } h{};
-  AIRGA_HIP(hipMemcpyAsync(&h, scratch.ptr, 24, hipMemcpyDeviceToHost, st));
-  AIRGA_HIP(hipMemcpyAsync(&h.total, total, 8, hipMemcpyDeviceToHost, st));
+  AIRGA_HIP(hipMemcpyAsync(&h, pen.setup.ptr, 24, hipMemcpyDeviceToHost, st));
   AIRGA_HIP(hipStreamSynchronize(st));
   if (h.flags & F_TOO_LONG)
     return fail(AIRGA_EUNSUPPORTED, "pattern has a row longer than %d entries", kMaxRow);
@@ -448,7 +478,7 @@ static airga_status set_pencil_impl(airga_ctx ctx, int32_t n, int64_t nnz, const
   k_mirror<<<blocks_for(n_pad, 256), 256, 0, st>>>(n, n_pad, row_ptr, col_idx,
                                                    pen.slice_ptr.as<int32_t>(),
                                                    pen.row_len.as<int32_t>(),
-                                                   pen.mirror.as<int32_t>(), flags);
+                                                   pen.mirror.as<int32_t>(), info);
   AIRGA_HIP(hipGetLastError());
   pen.n = n;
   pen.n_slices = ns;
@@ -466,7 +496,7 @@ static airga_status set_pencil_impl(airga_ctx ctx, int32_t n, int64_t nnz, const
   AIRGA_HIP(hipGetLastError());
   // Gram scalars
   const unsigned nb = blocks_for(n, 256);
-  DevBuf gp;
+  DevBuf& gp = pen.gram_ws;
   AIRGA_TRY(gp.reserve(sizeof(double) * (kGram * (size_t)nb + kGram)));
   k_gram_partial<<<nb, 256, 0, st>>>(pen.dev(), gp.as<double>());
   AIRGA_HIP(hipGetLastError());
@@ -475,7 +505,7 @@ static airga_status set_pencil_impl(airga_ctx ctx, int32_t n, int64_t nnz, const
   double g[kGram];
   int32_t flags2 = 0;
   AIRGA_HIP(hipMemcpyAsync(g, gp.as<double>() + kGram * (size_t)nb, sizeof g, hipMemcpyDeviceToHost, st));
-  AIRGA_HIP(hipMemcpyAsync(&flags2, flags, 4, hipMemcpyDeviceToHost, st));
+  AIRGA_HIP(hipMemcpyAsync(&flags2, info, 4, hipMemcpyDeviceToHost, st));
   AIRGA_HIP(hipStreamSynchronize(st));
   if (flags2 & F_ASYM) return fail(AIRGA_EINVAL, "invalid pattern: not structurally symmetric");
   pen.gram_mm = g[0];
