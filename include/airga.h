@@ -111,8 +111,8 @@ typedef struct {
 AIRGA_API airga_status airga_get_pencil_info(airga_ctx ctx, airga_pencil_info* out);
 
 /* a_val (device, nnz, CSR order of the pattern) = entries of
- * K(s) = (s^2 + alpha s) M + (1 + beta s) K (Section 2; the matrix of
- * line 3 of the SPAI algorithm for AIRGA), computed as one fused
+ * K(s) = (s^2 + alpha s) M + (1 + beta s) K (Section 2; the coefficient
+ * matrix of every shifted solve of Algorithms 1, 3 and 5), computed as one fused
  * multiply-add per entry in float64.  Asynchronous.
  * Errors: EINVAL (null a_val, non-finite s), ESTATE (no pencil). */
 AIRGA_API airga_status airga_assemble_shift(airga_ctx ctx, double s, double* a_val);
@@ -258,9 +258,9 @@ typedef struct {
 } airga_sys_stats;
 
 /* Solve K(s_k) X[:, c, k] = F[:, c] for every shift k < nshift and column
- * c < m with preconditioned CG (the solves of lines 5 and 14 of the AIRGA
- * algorithm; the SPAI variants of lines 5/11 and 17 of the algorithms with
- * SPAI and SPAI update), all nshift*m systems batched in one set of kernels
+ * c < m with preconditioned CG (the shifted solves of the AIRGA algorithm,
+ * Algorithm 1, and of its SPAI and SPAI-update variants, Algorithms 3 and
+ * 5), all nshift*m systems batched in one set of kernels
  * with per-system convergence masking.
  *   shifts: host, nshift real expansion points (each > 0)
  *   precs:  host, nshift handles (NULL entry = no preconditioner)

@@ -1,8 +1,8 @@
 """Reference solve X(s) = K(s)^{-1} F by banded Cholesky (test infrastructure only).
 
 This is the plain definition of what every shifted solve of the paper
-computes (the state X(s) of Section 2; the systems at lines 5 and 14 of the
-AIRGA algorithm), written out as a direct factorisation of the symmetric
+computes (the state X(s) of Section 2; the shifted systems of Algorithm 1),
+written out as a direct factorisation of the symmetric
 positive definite band matrix.  Two precisions are provided (binary64 and
 double-double); the double-double path can also assemble K(s) itself in
 double-double from the exact binary64 M and K, so its result is the solution
