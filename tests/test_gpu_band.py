@@ -85,11 +85,15 @@ def test_solves_staged_equal_general(ctx, name, mode):
     F = to_dev(f, torch.float64)
     shifts = [1.5, 30.0, 400.0]
     precs = [ctx.spai_build(s) for s in shifts]
-    for tile in TILES[:1] + TILES[4:5]:
-        Xa, sa = ctx.pcg_solve(shifts, precs, F, mode=mode, tile=tile)
-        Xg, sg = ctx.pcg_solve(shifts, precs, F, mode=mode, tile=tile, general_only=True)
-        assert torch.equal(Xa, Xg), (name, tile)
-        assert sa == sg
+    # update chains too (a second real factor: the direction kernel then
+    # stores w in full for the chain kernel)
+    upd = [ctx.spai_update(p, s * 1.1, tol=0.0) for p, s in zip(precs, shifts)]
+    for pr, sh in ((precs, shifts), (upd, [s * 1.1 for s in shifts])):
+        for tile in TILES[:1] + TILES[4:5] + TILES[6:]:
+            Xa, sa = ctx.pcg_solve(sh, pr, F, mode=mode, tile=tile)
+            Xg, sg = ctx.pcg_solve(sh, pr, F, mode=mode, tile=tile, general_only=True)
+            assert torch.equal(Xa, Xg), (name, tile)
+            assert sa == sg
 
 
 @pytest.mark.parametrize("tile", TILES)
