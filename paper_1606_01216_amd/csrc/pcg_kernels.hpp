@@ -237,6 +237,9 @@ inline size_t window_lds_bytes(size_t elem, int R, int U) {
 // ---- A: direction update + shifted SpMV + (p, w) -------------------------
 template <typename T, int WMAX, int R, int U, bool ASM, bool EXACT, bool BAND>
 __global__ void __launch_bounds__(256) k_dir_spmv(SolveArgs<T> A, int par) {
+  // nothing to do once every system has stopped (the rest of a replayed
+  // round of iterations): return before touching the pencil
+  if (sload(A.sys.nact) == 0) return;
   const int lane = threadIdx.x & 63;
   const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
   extern __shared__ double lds_part[];
@@ -359,6 +362,9 @@ __global__ void __launch_bounds__(256) k_dir_spmv(SolveArgs<T> A, int par) {
 // INIT: no update; r is R0 as produced by the residual kernel.
 template <typename T, int WMAX, int R, int U, bool INIT, bool EXACT, bool BAND>
 __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
+  // nothing to do once every system has stopped (the rest of a replayed
+  // round of iterations): return before touching the pencil
+  if (sload(A.sys.nact) == 0) return;
   const int lane = threadIdx.x & 63;
   const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
   extern __shared__ double lds_part[];
@@ -518,6 +524,9 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
 // ---- chain factor q >= 1 (Q_{q+1} of the update chain) ---------------------
 template <typename T, int WMAX, int R, bool EXACT>
 __global__ void __launch_bounds__(256) k_chain(SolveArgs<T> A, int par, int q, int init) {
+  // nothing to do once every system has stopped (the rest of a replayed
+  // round of iterations): return before touching the pencil
+  if (sload(A.sys.nact) == 0) return;
   const int lane = threadIdx.x & 63;
   const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
   extern __shared__ double lds_part[];
