@@ -7,7 +7,7 @@ already resident in HBM:
   -> SPAI build at every expansion point
   -> batched mixed-precision PCG for all (shift, column) systems
   -> SPAI update of every preconditioner to the next outer iteration's
-     (drifted) expansion points
+     (drifted) expansion points (one batched call)
   -> batched mixed-precision PCG again, with the update chains.
 ``value`` = systems solved to 1e-8 relative error (checked against the
 oracle's double-double reference) per second of step time.  Beside it: the
@@ -254,7 +254,7 @@ def main():
             mark(2)
             _, st1 = ctx.pcg_solve(shifts, precs, F, X1, profile=profile, **solve_kw)
             mark(3)
-            upd = [ctx.spai_update(p, s) for p, s in zip(precs, drifted)]
+            upd = ctx.spai_update_many(precs, list(drifted))
             mark(4)
             _, st2 = ctx.pcg_solve(drifted, upd, F, X2, profile=profile, **solve_kw)
             mark(5)

@@ -92,6 +92,8 @@ _SIGS = [
                                         ctypes.POINTER(_P)]),
     ("airga_spai_update", ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.POINTER(SpaiOpts),
                                          ctypes.POINTER(_P)]),
+    ("airga_spai_update_many", ctypes.c_int, [_P, ctypes.c_int32, _P, _P,
+                                              ctypes.POINTER(SpaiOpts), _P]),
     ("airga_get_prec_info", ctypes.c_int, [_P, ctypes.POINTER(PrecInfo)]),
     ("airga_prec_export", ctypes.c_int, [_P, _P, _P]),
     ("airga_prec_apply", ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64, _P,
@@ -259,6 +261,21 @@ class Context:
                                        ctypes.byref(h)))
         self._leave()
         return Prec(self, h)
+
+    def spai_update_many(self, olds, s_new, *, tol=0.01, equilibrate=True,
+                         general_only=False) -> list:
+        """[update of olds[i] to s_new[i]], the pencil read once per batch."""
+        k = len(olds)
+        if len(s_new) != k:
+            raise ValueError("one new shift per preconditioner")
+        o = self._spai_opts(tol, equilibrate, False, general_only)
+        c_old = (ctypes.c_void_p * max(k, 1))(*[p._h.value for p in olds])
+        c_s = (ctypes.c_double * max(k, 1))(*[float(v) for v in s_new])
+        c_out = (ctypes.c_void_p * max(k, 1))()
+        self._enter()
+        _check(lib().airga_spai_update_many(self._h, k, c_old, c_s, ctypes.byref(o), c_out))
+        self._leave()
+        return [Prec(self, ctypes.c_void_p(c_out[i])) for i in range(k)]
 
     # ---------------------------------------------------------------- solves
     def pcg_solve(self, shifts, precs, F: torch.Tensor, X: torch.Tensor | None = None, *,

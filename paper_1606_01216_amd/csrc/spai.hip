@@ -44,13 +44,14 @@ __device__ __forceinline__ void givens_row(double (&R)[MJ * (MJ + 1) / 2], doubl
       for (int l = k + 1; l < MJ; ++l) {
         if (l < nj) {
           const double rl = R[tri<MJ>(k, l)], vl = v[l];
-          R[tri<MJ>(k, l)] = c * rl + s * vl;
-          v[l] = c * vl - s * rl;
+          // explicit fma: every kernel that folds rows rounds the same way
+          R[tri<MJ>(k, l)] = fma(c, rl, s * vl);
+          v[l] = fma(c, vl, -(s * rl));
         }
       }
       const double qb = qtb[k];
-      qtb[k] = c * qb + s * rhs;
-      rhs = c * rhs - s * qb;
+      qtb[k] = fma(c, qb, s * rhs);
+      rhs = fma(c, rhs, -(s * qb));
     }
   }
 }
@@ -105,7 +106,8 @@ __global__ void k_alpha_partial(PencilDev pd, double a, double b, double a_old, 
 }
 
 // alpha = num / den from the per-block partials, summed in a fixed order.
-__global__ void k_alpha_final(const double* __restrict__ part, int64_t nb, double* __restrict__ out) {
+__device__ __forceinline__ void alpha_final_block(const double* __restrict__ part, int64_t nb,
+                                                  double* __restrict__ out) {
   __shared__ double red[2][256];
   const int t = threadIdx.x;
   double num = 0, den = 0;
@@ -124,6 +126,10 @@ __global__ void k_alpha_final(const double* __restrict__ part, int64_t nb, doubl
     __syncthreads();
   }
   if (t == 0) out[0] = red[0][0] / red[1][0];
+}
+
+__global__ void k_alpha_final(const double* __restrict__ part, int64_t nb, double* __restrict__ out) {
+  alpha_final_block(part, nb, out);
 }
 
 // Entries of Khat = S K(s) S on the stored pattern (0 on padding), with
@@ -158,7 +164,8 @@ __device__ __forceinline__ void block_count(bool flag, int32_t* __restrict__ par
 }
 
 // out[0] = sum of the nb per-block counts, in block order.
-__global__ void k_sum_counts(const int32_t* __restrict__ part, int64_t nb, int32_t* __restrict__ out) {
+__device__ __forceinline__ void sum_counts_block(const int32_t* __restrict__ part, int64_t nb,
+                                                 int32_t* __restrict__ out) {
   __shared__ int64_t red[256];
   int64_t c = 0;
   for (int64_t i = threadIdx.x; i < nb; i += blockDim.x) c += part[i];
@@ -169,6 +176,10 @@ __global__ void k_sum_counts(const int32_t* __restrict__ part, int64_t nb, int32
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = (int32_t)red[0];
+}
+
+__global__ void k_sum_counts(const int32_t* __restrict__ part, int64_t nb, int32_t* __restrict__ out) {
+  sum_counts_block(part, nb, out);
 }
 
 // One lane per column j, on the scaled entries: ahat = Khat (build) or
@@ -209,7 +220,7 @@ __global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, const double* _
       for (int t = 0; t < MJ; ++t) {
         if (t < nj) {
           const double vo = aold[jpos[t]];
-          const double d = vo - al * ahat[jpos[t]];
+          const double d = fma(-al, ahat[jpos[t]], vo);
           n_old = fma(vo, vo, n_old);
           n_res = fma(d, d, n_res);
         }
@@ -278,7 +289,7 @@ __global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, const double* _
           double acc = qtb[t];
 #pragma unroll
           for (int u = t + 1; u < MJ; ++u)
-            if (u < nj) acc -= R[tri<MJ>(t, u)] * p[u];
+            if (u < nj) acc = fma(-R[tri<MJ>(t, u)], p[u], acc);
           const double d = R[tri<MJ>(t, t)];
           p[t] = d != 0.0 ? acc / d : 0.0;
         }
@@ -307,60 +318,19 @@ __host__ __device__ inline size_t spai_band_lds(int bw, bool update) {
   return S * (MJ * (sizeof(double) * (update ? 2 : 1) + sizeof(int32_t)) + sizeof(int32_t));
 }
 
+// One column's least-squares solve on the staged rows (vn = Khat or
+// Khat_new, vo = Khat_old, cl = columns, ln = lengths, window rows from
+// w0, S per entry slot); update: skip test first (al = the update's alpha).
+// Returns whether the column was skipped.
 template <int MJ, bool UPDATE, bool RANGE>
-__global__ void __launch_bounds__(256) k_spai_band(PencilDev pd, double a, double b, double ao,
-                                                   double bo, const double* __restrict__ dinv,
-                                                   int bw, const double* __restrict__ alpha_u,
-                                                   double tol, double* __restrict__ hat,
-                                                   double* __restrict__ obj,
-                                                   int32_t* __restrict__ skip_count) {
-  extern __shared__ double lds[];
-  const int S = 256 + 4 * bw;
-  double* vn = lds;
-  double* vo = vn + MJ * S;
-  int32_t* cl = reinterpret_cast<int32_t*>(UPDATE ? vo + MJ * S : vo);
-  int32_t* ln = cl + MJ * S;
-  const int64_t j0 = (int64_t)blockIdx.x * 256;
-  const int64_t w0 = j0 - 2 * bw > 0 ? j0 - 2 * bw : 0;
-  const int64_t w1 = j0 + 256 + 2 * bw < pd.n ? j0 + 256 + 2 * bw : pd.n;
-  const int t = threadIdx.x;
-  // stage rows [w0, w1); every load is issued unconditionally (entries past
-  // the slice width read the last one of the row's slice; padding entries
-  // hold the row itself as column) and the values past the row length are
-  // dropped by a select
-  for (int64_t row = w0 + t; row < w1; row += 256) {
-    const int r = (int)(row - w0);
-    const int64_t sl = row / kSlice;
-    const int32_t sp0 = pd.slice_ptr[sl];
-    const int32_t base = sp0 + (int32_t)(row % kSlice);
-    const int w = (pd.slice_ptr[sl + 1] - sp0) / kSlice;
-    const int len = pd.row_len[row];
-    const double sr = dinv[row];
-    ln[r] = len;
-    int32_t c[MJ];
-    double m[MJ], kk[MJ], dc[MJ];
-#pragma unroll
-    for (int k = 0; k < MJ; ++k) {
-      const int32_t idx = base + (k < w ? k : w - 1) * kSlice;
-      c[k] = pd.col[idx];
-      m[k] = pd.m64[idx];
-      kk[k] = pd.k64[idx];
-    }
-#pragma unroll
-    for (int k = 0; k < MJ; ++k) dc[k] = dinv[c[k]];
-#pragma unroll
-    for (int k = 0; k < MJ; ++k) {
-      const bool in = k < len;
-      // same association as k_scaled_values
-      cl[k * S + r] = in ? c[k] : -1;
-      vn[k * S + r] = in ? fma(a, m[k], b * kk[k]) * sr * dc[k] : 0.0;
-      if constexpr (UPDATE) vo[k * S + r] = in ? fma(ao, m[k], bo * kk[k]) * sr * dc[k] : 0.0;
-    }
-  }
-  __syncthreads();
-  const int64_t j = j0 + t;
+__device__ __forceinline__ bool spai_band_column(const PencilDev& pd, const double* vn,
+                                                 const double* vo, const int32_t* cl,
+                                                 const int32_t* ln, int S, int64_t w0,
+                                                 int64_t j, double al, double tol,
+                                                 double* __restrict__ hat,
+                                                 double* __restrict__ obj) {
   bool skipped = false;
-  if (j < pd.n) {
+  {
     const int jr = (int)(j - w0);
     const int32_t base_j = pd.slice_ptr[j / kSlice] + (int32_t)(j % kSlice);
     const int nj = ln[jr];
@@ -369,13 +339,12 @@ __global__ void __launch_bounds__(256) k_spai_band(PencilDev pd, double a, doubl
 #pragma unroll
     for (int u = 0; u < MJ; ++u) J[u] = u < nj ? cl[u * S + jr] : -2;
     if constexpr (UPDATE) {
-      const double al = *alpha_u;
       double n_old = 0, n_res = 0;
 #pragma unroll
       for (int u = 0; u < MJ; ++u) {
         if (u < nj) {
           const double v_o = vo[u * S + jr];
-          const double d = v_o - al * vn[u * S + jr];
+          const double d = fma(-al, vn[u * S + jr], v_o);
           n_old = fma(v_o, v_o, n_old);
           n_res = fma(d, d, n_res);
         }
@@ -472,7 +441,7 @@ __global__ void __launch_bounds__(256) k_spai_band(PencilDev pd, double a, doubl
           double acc = qtb[q];
 #pragma unroll
           for (int u = q + 1; u < MJ; ++u)
-            if (u < nj) acc -= R[tri<MJ>(q, u)] * p[u];
+            if (u < nj) acc = fma(-R[tri<MJ>(q, u)], p[u], acc);
           const double d = R[tri<MJ>(q, q)];
           p[q] = d != 0.0 ? acc / d : 0.0;
         }
@@ -483,7 +452,233 @@ __global__ void __launch_bounds__(256) k_spai_band(PencilDev pd, double a, doubl
       obj[j] = sqrt(res2);
     }
   }
+  return skipped;
+}
+
+template <int MJ, bool UPDATE, bool RANGE>
+__global__ void __launch_bounds__(256) k_spai_band(PencilDev pd, double a, double b, double ao,
+                                                   double bo, const double* __restrict__ dinv,
+                                                   int bw, const double* __restrict__ alpha_u,
+                                                   double tol, double* __restrict__ hat,
+                                                   double* __restrict__ obj,
+                                                   int32_t* __restrict__ skip_count) {
+  extern __shared__ double lds[];
+  const int S = 256 + 4 * bw;
+  double* vn = lds;
+  double* vo = vn + MJ * S;
+  int32_t* cl = reinterpret_cast<int32_t*>(UPDATE ? vo + MJ * S : vo);
+  int32_t* ln = cl + MJ * S;
+  const int64_t j0 = (int64_t)blockIdx.x * 256;
+  const int64_t w0 = j0 - 2 * bw > 0 ? j0 - 2 * bw : 0;
+  const int64_t w1 = j0 + 256 + 2 * bw < pd.n ? j0 + 256 + 2 * bw : pd.n;
+  const int t = threadIdx.x;
+  // stage rows [w0, w1); every load is issued unconditionally (entries past
+  // the slice width read the last one of the row's slice; padding entries
+  // hold the row itself as column) and the values past the row length are
+  // dropped by a select
+  for (int64_t row = w0 + t; row < w1; row += 256) {
+    const int r = (int)(row - w0);
+    const int64_t sl = row / kSlice;
+    const int32_t sp0 = pd.slice_ptr[sl];
+    const int32_t base = sp0 + (int32_t)(row % kSlice);
+    const int w = (pd.slice_ptr[sl + 1] - sp0) / kSlice;
+    const int len = pd.row_len[row];
+    const double sr = dinv[row];
+    ln[r] = len;
+    int32_t c[MJ];
+    double m[MJ], kk[MJ], dc[MJ];
+#pragma unroll
+    for (int k = 0; k < MJ; ++k) {
+      const int32_t idx = base + (k < w ? k : w - 1) * kSlice;
+      c[k] = pd.col[idx];
+      m[k] = pd.m64[idx];
+      kk[k] = pd.k64[idx];
+    }
+#pragma unroll
+    for (int k = 0; k < MJ; ++k) dc[k] = dinv[c[k]];
+#pragma unroll
+    for (int k = 0; k < MJ; ++k) {
+      const bool in = k < len;
+      // same association as k_scaled_values
+      cl[k * S + r] = in ? c[k] : -1;
+      vn[k * S + r] = in ? fma(a, m[k], b * kk[k]) * sr * dc[k] : 0.0;
+      if constexpr (UPDATE) vo[k * S + r] = in ? fma(ao, m[k], bo * kk[k]) * sr * dc[k] : 0.0;
+    }
+  }
+  __syncthreads();
+  const int64_t j = j0 + t;
+  bool skipped = false;
+  if (j < pd.n)
+    skipped = spai_band_column<MJ, UPDATE, RANGE>(pd, vn, vo, cl, ln, S, w0, j,
+                                                  UPDATE ? *alpha_u : 0.0, tol, hat, obj);
   if constexpr (UPDATE) block_count(skipped, skip_count);
+}
+
+// ---- batched update: several shifts, the pencil read once ---------------
+//
+// The update of each factor is exactly the single-factor one (same
+// arithmetic in the same order, so the same results); what is shared is
+// the reading of M, K and the pattern, and the launches.
+constexpr int kManyMax = 16;  // updates per batched launch
+
+struct UpdMany {
+  int32_t count;
+  double a[kManyMax], b[kManyMax];    // new shift coefficients
+  double ao[kManyMax], bo[kManyMax];  // old shift coefficients
+  double* alpha[kManyMax];            // each new factor's alpha (device)
+  int32_t* skip[kManyMax];            // each new factor's skipped-column count
+  double* obj[kManyMax];              // each new factor's objective
+};
+
+// dinv of every shift of the batch: [count][n_pad].
+__global__ void k_dinv_many(PencilDev pd, UpdMany U, int equilibrate, int64_t n_pad,
+                            double* __restrict__ dinv) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (r >= n_pad) return;
+  double v = 1.0;
+  if (r < pd.n && equilibrate) {
+    const int32_t q = pd.diag_pos[r];
+    v = 1.0 / sqrt(fma(U.a[s], pd.m64[q], U.b[s] * pd.k64[q]));
+  }
+  dinv[(int64_t)s * n_pad + r] = v;
+}
+
+// k_alpha_partial for every shift, each row of the pencil read once:
+// part[(s * nb + block) * 2 + {0, 1}].
+__global__ void k_alpha_partial_many(PencilDev pd, UpdMany U, const double* __restrict__ dinv,
+                                     int64_t n_pad, double* __restrict__ part) {
+  __shared__ double red[kManyMax][2][4];
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int w = threadIdx.x >> 6;
+  const int64_t nb = gridDim.x;
+  int len = 0;
+  int32_t c[kSpaiMaxJ];
+  double m[kSpaiMaxJ], kk[kSpaiMaxJ];
+  if (r < pd.n) {
+    const int32_t base = pd.slice_ptr[r / kSlice] + (int32_t)(r % kSlice);
+    len = pd.row_len[r];
+#pragma unroll
+    for (int k = 0; k < kSpaiMaxJ; ++k) {
+      const int32_t idx = base + (k < len ? k : 0) * kSlice;
+      c[k] = pd.col[idx];
+      m[k] = pd.m64[idx];
+      kk[k] = pd.k64[idx];
+    }
+  }
+  for (int s = 0; s < U.count; ++s) {
+    const double* __restrict__ dv = dinv + (int64_t)s * n_pad;
+    double num = 0, den = 0;
+    if (r < pd.n) {
+      const double sr = dv[r];
+#pragma unroll
+      for (int k = 0; k < kSpaiMaxJ; ++k) {
+        if (k < len) {
+          const double sc = sr * dv[c[k]];
+          const double an = fma(U.a[s], m[k], U.b[s] * kk[k]) * sc;
+          const double ao = fma(U.ao[s], m[k], U.bo[s] * kk[k]) * sc;
+          num = fma(ao, an, num);
+          den = fma(an, an, den);
+        }
+      }
+    }
+    num = wave_sum(num);
+    den = wave_sum(den);
+    if ((threadIdx.x & 63) == 0) {
+      red[s][0][w] = num;
+      red[s][1][w] = den;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < 2 * U.count) {
+    const int s = threadIdx.x >> 1, q = threadIdx.x & 1;
+    double t = 0;
+    for (int i = 0; i < 4; ++i) t += red[s][q][i];
+    part[((int64_t)s * nb + blockIdx.x) * 2 + q] = t;
+  }
+}
+
+__global__ void k_alpha_final_many(UpdMany U, const double* __restrict__ part, int64_t nb) {
+  alpha_final_block(part + (int64_t)blockIdx.x * nb * 2, nb, U.alpha[blockIdx.x]);
+}
+
+__global__ void k_sum_counts_many(UpdMany U, const int32_t* __restrict__ part, int64_t nb) {
+  sum_counts_block(part + (int64_t)blockIdx.x * nb, nb, U.skip[blockIdx.x]);
+}
+
+// LDS of k_spai_update_many: M, K, the scaled new and old values (double)
+// and the columns per entry slot, plus the row lengths.
+template <int MJ>
+__host__ __device__ inline size_t spai_many_lds(int bw) {
+  const size_t S = 256 + 4 * (size_t)bw;
+  return S * (MJ * (4 * sizeof(double) + sizeof(int32_t)) + sizeof(int32_t));
+}
+
+// The banded update column kernel for every shift of the batch: the block's
+// rows are staged once (M, K, columns), then per shift their scaled values
+// are formed and the columns solved as in k_spai_band.  hat: [count][stored].
+template <int MJ, bool RANGE>
+__global__ void __launch_bounds__(256) k_spai_update_many(PencilDev pd, UpdMany U,
+                                                          const double* __restrict__ dinv,
+                                                          int64_t n_pad, int64_t stored, int bw,
+                                                          double tol, double* __restrict__ hat,
+                                                          int32_t* __restrict__ skip_part) {
+  extern __shared__ double lds[];
+  const int S = 256 + 4 * bw;
+  double* mm = lds;
+  double* kq = mm + MJ * S;
+  double* vn = kq + MJ * S;
+  double* vo = vn + MJ * S;
+  int32_t* cl = reinterpret_cast<int32_t*>(vo + MJ * S);
+  int32_t* ln = cl + MJ * S;
+  const int64_t j0 = (int64_t)blockIdx.x * 256;
+  const int64_t w0 = j0 - 2 * bw > 0 ? j0 - 2 * bw : 0;
+  const int64_t w1 = j0 + 256 + 2 * bw < pd.n ? j0 + 256 + 2 * bw : pd.n;
+  const int t = threadIdx.x;
+  for (int64_t row = w0 + t; row < w1; row += 256) {
+    const int r = (int)(row - w0);
+    const int64_t sl = row / kSlice;
+    const int32_t sp0 = pd.slice_ptr[sl];
+    const int32_t base = sp0 + (int32_t)(row % kSlice);
+    const int w = (pd.slice_ptr[sl + 1] - sp0) / kSlice;
+    const int len = pd.row_len[row];
+    ln[r] = len;
+#pragma unroll
+    for (int k = 0; k < MJ; ++k) {
+      const int32_t idx = base + (k < w ? k : w - 1) * kSlice;
+      const bool in = k < len;
+      const int32_t c = pd.col[idx];
+      cl[k * S + r] = in ? c : -1;
+      mm[k * S + r] = pd.m64[idx];
+      kq[k * S + r] = pd.k64[idx];
+    }
+  }
+  const int64_t nb = gridDim.x;
+  for (int s = 0; s < U.count; ++s) {
+    const double* __restrict__ dv = dinv + (int64_t)s * n_pad;
+    __syncthreads();  // staged rows ready; the previous shift's columns done
+    for (int64_t row = w0 + t; row < w1; row += 256) {
+      const int r = (int)(row - w0);
+      const double sr = dv[row];
+      const int len = ln[r];
+#pragma unroll
+      for (int k = 0; k < MJ; ++k) {
+        const bool in = k < len;
+        const int32_t c = cl[k * S + r];
+        const double dc = dv[in ? c : row];
+        // same association as k_scaled_values
+        vn[k * S + r] = in ? fma(U.a[s], mm[k * S + r], U.b[s] * kq[k * S + r]) * sr * dc : 0.0;
+        vo[k * S + r] = in ? fma(U.ao[s], mm[k * S + r], U.bo[s] * kq[k * S + r]) * sr * dc : 0.0;
+      }
+    }
+    __syncthreads();
+    const int64_t j = j0 + t;
+    bool skipped = false;
+    if (j < pd.n)
+      skipped = spai_band_column<MJ, true, RANGE>(pd, vn, vo, cl, ln, S, w0, j, *U.alpha[s], tol,
+                                                  hat + (int64_t)s * stored, U.obj[s]);
+    block_count(skipped, skip_part + (int64_t)s * nb);
+  }
 }
 
 // Map the scaled factor back and store float64 and float32 copies:
@@ -773,6 +968,76 @@ static airga_status run_update(airga_ctx ctx, airga_prec old, double s_new,
   return AIRGA_OK;
 }
 
+// Several updates at once (banded pencils whose staged rows fit in LDS);
+// otherwise one after the other.
+static airga_status run_update_many(airga_ctx ctx, int32_t count, const airga_prec* olds,
+                                    const double* s_new, const airga_spai_opts& o,
+                                    airga_prec* ps) {
+  const Pencil& pen = ctx->pen;
+  const bool fits = spai_banded(pen, o, true) && pen.max_len <= 6 &&
+                    spai_many_lds<6>(pen.bandwidth) <= 64 * 1024;
+  if (!fits) {
+    for (int i = 0; i < count; ++i) AIRGA_TRY(run_update(ctx, olds[i], s_new[i], o, ps[i]));
+    return AIRGA_OK;
+  }
+  hipStream_t st = ctx->stream;
+  const PencilDev pd = pen.dev();
+  const int64_t n_pad = pen.n_pad(), stored = pen.nnz_stored;
+  const unsigned nb = blocks_for(pen.n, 256);
+  const int bw = pen.bandwidth;
+  const bool range = 4 * bw + 1 <= pen.max_len * pen.max_len;
+  for (int i0 = 0; i0 < count; i0 += kManyMax) {
+    const int cnt = count - i0 < kManyMax ? count - i0 : kManyMax;
+    // scratch: [dinv (cnt n_pad) | hat (cnt stored) | alpha partials | skip counts]
+    const size_t need = sizeof(double) * ((size_t)cnt * (n_pad + stored) + 2 * (size_t)cnt * nb) +
+                        sizeof(int32_t) * (size_t)cnt * nb + 64;
+    AIRGA_TRY(ctx->ws_tmp.reserve(need));
+    double* dinv = ctx->ws_tmp.as<double>();
+    double* hat = dinv + (size_t)cnt * n_pad;
+    double* part = hat + (size_t)cnt * stored;
+    int32_t* skp = reinterpret_cast<int32_t*>(part + 2 * (size_t)cnt * nb);
+    UpdMany U;
+    std::memset(static_cast<void*>(&U), 0, sizeof U);
+    U.count = cnt;
+    for (int i = 0; i < cnt; ++i) {
+      const airga_prec p = ps[i0 + i];
+      shift_coeffs(pen, s_new[i0 + i], &U.a[i], &U.b[i]);
+      shift_coeffs(pen, olds[i0 + i]->shift, &U.ao[i], &U.bo[i]);
+      U.alpha[i] = p->scal.as<double>();
+      U.skip[i] = reinterpret_cast<int32_t*>(p->scal.as<char>() + 8);
+      U.obj[i] = p->objective.as<double>();
+    }
+    k_dinv_many<<<dim3(blocks_for(n_pad, 256), (unsigned)cnt), 256, 0, st>>>(pd, U, o.equilibrate,
+                                                                             n_pad, dinv);
+    AIRGA_HIP(hipGetLastError());
+    k_alpha_partial_many<<<nb, 256, 0, st>>>(pd, U, dinv, n_pad, part);
+    AIRGA_HIP(hipGetLastError());
+    k_alpha_final_many<<<(unsigned)cnt, 256, 0, st>>>(U, part, nb);
+    AIRGA_HIP(hipGetLastError());
+    const size_t lds = spai_many_lds<6>(bw);
+    if (range)
+      k_spai_update_many<6, true><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, o.tol, hat,
+                                                        skp);
+    else
+      k_spai_update_many<6, false><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, o.tol,
+                                                         hat, skp);
+    AIRGA_HIP(hipGetLastError());
+    k_sum_counts_many<<<(unsigned)cnt, 256, 0, st>>>(U, skp, nb);
+    AIRGA_HIP(hipGetLastError());
+    const unsigned nr = blocks_for(n_pad, 256);
+    for (int i = 0; i < cnt; ++i) {
+      const airga_prec p = ps[i0 + i];
+      k_spai_finalize<<<nr, 256, 0, st>>>(pd, hat + (size_t)i * stored, dinv + (size_t)i * n_pad, 2,
+                                          U.skip[i], p->v64.as<double>(), p->v32.as<float>());
+      AIRGA_HIP(hipGetLastError());
+      p->is_update = true;
+      p->parent = olds[i0 + i];
+      olds[i0 + i]->refs++;
+    }
+  }
+  return AIRGA_OK;
+}
+
 airga_status prec_resolve_many(airga_ctx ctx, const std::vector<airga_prec>& ps) {
   std::vector<airga_prec> todo;
   for (airga_prec p : ps)
@@ -873,6 +1138,35 @@ airga_status airga_spai_update(airga_ctx ctx, airga_prec old, double s_new,
     return st;
   }
   *out = p;
+  return AIRGA_OK;
+}
+
+airga_status airga_spai_update_many(airga_ctx ctx, int32_t count, const airga_prec* olds,
+                                    const double* s_new, const airga_spai_opts* opts,
+                                    airga_prec* out) {
+  AIRGA_TRY(check_pencil(ctx));
+  if (count < 0 || (count > 0 && (!olds || !s_new || !out)))
+    return fail(AIRGA_EINVAL, "bad update batch");
+  for (int32_t i = 0; i < count; ++i) {
+    out[i] = nullptr;
+    airga_prec dummy;
+    AIRGA_TRY(check_spai_args(ctx, s_new[i], &dummy));
+    AIRGA_TRY(check_prec(olds[i]));
+    if (olds[i]->ctx != ctx) return fail(AIRGA_EINVAL, "preconditioner belongs to another context");
+  }
+  airga_spai_opts o;
+  airga_spai_opts_default(&o);
+  if (opts) o = *opts;
+  if (!(o.tol >= 0)) return fail(AIRGA_EINVAL, "update tolerance must be >= 0");
+  std::vector<airga_prec> ps(count, nullptr);
+  airga_status st = AIRGA_OK;
+  for (int32_t i = 0; i < count && st == AIRGA_OK; ++i) st = new_prec(ctx, s_new[i], &ps[i]);
+  if (st == AIRGA_OK) st = run_update_many(ctx, count, olds, s_new, o, ps.data());
+  if (st != AIRGA_OK) {
+    for (airga_prec p : ps) airga_prec_release(p);
+    return st;
+  }
+  for (int32_t i = 0; i < count; ++i) out[i] = ps[i];
   return AIRGA_OK;
 }
 

@@ -130,3 +130,29 @@ def test_forced_tile_rejects_unknown_configuration(ctx):
     with pytest.raises(airga.AirgaError) as ei:
         ctx.pcg_solve([1.0], None, F, tile=(192, 1))
     assert ei.value.status == airga.EINVAL
+
+
+@pytest.mark.parametrize("name", ["beam", "grid8", "grid65"])
+def test_batched_updates_equal_single_updates(ctx, name):
+    """airga_spai_update_many gives exactly the single updates: factor values,
+    objectives, alpha and skip counts, for skipped and solved columns, over
+    more than one batch of 16 (and through the one-by-one fallback where the
+    staged rows do not fit, or with general_only)."""
+    pen = {"beam": beam.make_beam(1037, ei_loguniform=(0.5, 2.0), surrogate=True, seed=5),
+           "grid8": grid_pencil(8, 150, seed=3), "grid65": grid_pencil(65, 9, seed=2)}[name]
+    set_pencil(ctx, pen)
+    base = [1.0 * 1.6 ** k for k in range(18)]
+    olds = [ctx.spai_build(s) for s in base]
+    # drifts from none (all columns skip) to large (columns solved)
+    new = [s * (1.0 + (0.0 if k % 3 == 0 else 1e-4 if k % 3 == 1 else 0.2)) for k, s in enumerate(base)]
+    for tol, general in ((0.01, False), (0.0, False), (0.01, True)):
+        many = ctx.spai_update_many(olds, new, tol=tol, general_only=general)
+        for k, (p, s) in enumerate(zip(olds, new)):
+            one = ctx.spai_update(p, s, tol=tol, general_only=general)
+            vm, om = (t.cpu().numpy() for t in many[k].export())
+            vo, oo = (t.cpu().numpy() for t in one.export())
+            im, io = many[k].info(), one.info()
+            assert np.array_equal(vm, vo) and np.array_equal(om, oo), (name, k, tol)
+            assert im.alpha == io.alpha and im.skipped_cols == io.skipped_cols, (name, k)
+            assert im.scalar_only == io.scalar_only and im.chain_len == io.chain_len
+    assert ctx.spai_update_many([], []) == []
