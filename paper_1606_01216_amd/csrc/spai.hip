@@ -530,18 +530,20 @@ struct UpdMany {
   double* obj[kManyMax];              // each new factor's objective
 };
 
-// dinv of every shift of the batch: [count][n_pad].
+// dinv of every shift of the batch: [count][n_pad]; the diagonal is read once.
 __global__ void k_dinv_many(PencilDev pd, UpdMany U, int equilibrate, int64_t n_pad,
                             double* __restrict__ dinv) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int s = blockIdx.y;
   if (r >= n_pad) return;
-  double v = 1.0;
-  if (r < pd.n && equilibrate) {
+  const bool eq = r < pd.n && equilibrate;
+  double m = 0, k = 0;
+  if (eq) {
     const int32_t q = pd.diag_pos[r];
-    v = 1.0 / sqrt(fma(U.a[s], pd.m64[q], U.b[s] * pd.k64[q]));
+    m = pd.m64[q];
+    k = pd.k64[q];
   }
-  dinv[(int64_t)s * n_pad + r] = v;
+  for (int s = 0; s < U.count; ++s)
+    dinv[(int64_t)s * n_pad + r] = eq ? 1.0 / sqrt(fma(U.a[s], m, U.b[s] * k)) : 1.0;
 }
 
 // k_alpha_partial for every shift, each row of the pencil read once:
@@ -611,7 +613,8 @@ __global__ void k_sum_counts_many(UpdMany U, const int32_t* __restrict__ part, i
 template <int MJ>
 __host__ __device__ inline size_t spai_many_lds(int bw) {
   const size_t S = 256 + 4 * (size_t)bw;
-  return S * (MJ * (4 * sizeof(double) + sizeof(int32_t)) + sizeof(int32_t));
+  return S * (MJ * (4 * sizeof(double) + sizeof(int32_t)) + sizeof(int32_t)) +
+         sizeof(double) * (S + 2 * (size_t)bw);
 }
 
 // The banded update column kernel for every shift of the batch: the block's
@@ -629,11 +632,14 @@ __global__ void __launch_bounds__(256) k_spai_update_many(PencilDev pd, UpdMany 
   double* kq = mm + MJ * S;
   double* vn = kq + MJ * S;
   double* vo = vn + MJ * S;
-  int32_t* cl = reinterpret_cast<int32_t*>(vo + MJ * S);
+  double* dl = vo + MJ * S;  // dinv of rows [d0, d1): the window and bw beyond
+  int32_t* cl = reinterpret_cast<int32_t*>(dl + S + 2 * bw);
   int32_t* ln = cl + MJ * S;
   const int64_t j0 = (int64_t)blockIdx.x * 256;
   const int64_t w0 = j0 - 2 * bw > 0 ? j0 - 2 * bw : 0;
   const int64_t w1 = j0 + 256 + 2 * bw < pd.n ? j0 + 256 + 2 * bw : pd.n;
+  const int64_t d0 = w0 - bw > 0 ? w0 - bw : 0;
+  const int64_t d1 = w1 + bw < pd.n ? w1 + bw : pd.n;
   const int t = threadIdx.x;
   for (int64_t row = w0 + t; row < w1; row += 256) {
     const int r = (int)(row - w0);
@@ -657,15 +663,17 @@ __global__ void __launch_bounds__(256) k_spai_update_many(PencilDev pd, UpdMany 
   for (int s = 0; s < U.count; ++s) {
     const double* __restrict__ dv = dinv + (int64_t)s * n_pad;
     __syncthreads();  // staged rows ready; the previous shift's columns done
+    for (int64_t row = d0 + t; row < d1; row += 256) dl[row - d0] = dv[row];
+    __syncthreads();
     for (int64_t row = w0 + t; row < w1; row += 256) {
       const int r = (int)(row - w0);
-      const double sr = dv[row];
+      const double sr = dl[row - d0];
       const int len = ln[r];
 #pragma unroll
       for (int k = 0; k < MJ; ++k) {
         const bool in = k < len;
         const int32_t c = cl[k * S + r];
-        const double dc = dv[in ? c : row];
+        const double dc = dl[(in ? c : row) - d0];
         // same association as k_scaled_values
         vn[k * S + r] = in ? fma(U.a[s], mm[k * S + r], U.b[s] * kq[k * S + r]) * sr * dc : 0.0;
         vo[k * S + r] = in ? fma(U.ao[s], mm[k * S + r], U.bo[s] * kq[k * S + r]) * sr * dc : 0.0;
@@ -1007,8 +1015,7 @@ static airga_status run_update_many(airga_ctx ctx, int32_t count, const airga_pr
       U.skip[i] = reinterpret_cast<int32_t*>(p->scal.as<char>() + 8);
       U.obj[i] = p->objective.as<double>();
     }
-    k_dinv_many<<<dim3(blocks_for(n_pad, 256), (unsigned)cnt), 256, 0, st>>>(pd, U, o.equilibrate,
-                                                                             n_pad, dinv);
+    k_dinv_many<<<blocks_for(n_pad, 256), 256, 0, st>>>(pd, U, o.equilibrate, n_pad, dinv);
     AIRGA_HIP(hipGetLastError());
     k_alpha_partial_many<<<nb, 256, 0, st>>>(pd, U, dinv, n_pad, part);
     AIRGA_HIP(hipGetLastError());
