@@ -228,7 +228,7 @@ typedef struct {
   int32_t mode;        /* AIRGA_MODE_FP64 or AIRGA_MODE_MIXED (float32 matrix,
                           preconditioner and vectors inside float64 iterative
                           refinement of the residual and the solution)          */
-  double inner_tol;    /* MIXED: relative residual reduction per sweep (1e-3)   */
+  double inner_tol;    /* MIXED: relative residual reduction per sweep (5e-4)   */
   int32_t max_sweeps;  /* MIXED: refinement sweeps (default 12)                 */
   int32_t poll_every;  /* iterations between host checks of the active count
                           (rounded up to even; default 8)                       */
