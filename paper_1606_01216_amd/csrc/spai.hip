@@ -662,29 +662,62 @@ __global__ void __launch_bounds__(256) k_spai_update_many(PencilDev pd, UpdMany 
   const int64_t nb = gridDim.x;
   for (int s = 0; s < U.count; ++s) {
     const double* __restrict__ dv = dinv + (int64_t)s * n_pad;
+    double* __restrict__ hs = hat + (int64_t)s * stored;
     __syncthreads();  // staged rows ready; the previous shift's columns done
     for (int64_t row = d0 + t; row < d1; row += 256) dl[row - d0] = dv[row];
     __syncthreads();
-    for (int64_t row = w0 + t; row < w1; row += 256) {
-      const int r = (int)(row - w0);
-      const double sr = dl[row - d0];
-      const int len = ln[r];
+    // skip test of column j straight from the staged rows (the scaled
+    // values below and in spai_band_column are formed the same way)
+    const int64_t j = j0 + t;
+    const double al = *U.alpha[s];
+    bool skipped = false, solve = false;
+    if (j < pd.n) {
+      const int jr = (int)(j - w0);
+      const int nj = ln[jr];
+      const double sr = dl[j - d0];
+      double n_old = 0, n_res = 0;
 #pragma unroll
-      for (int k = 0; k < MJ; ++k) {
-        const bool in = k < len;
-        const int32_t c = cl[k * S + r];
-        const double dc = dl[(in ? c : row) - d0];
-        // same association as k_scaled_values
-        vn[k * S + r] = in ? fma(U.a[s], mm[k * S + r], U.b[s] * kq[k * S + r]) * sr * dc : 0.0;
-        vo[k * S + r] = in ? fma(U.ao[s], mm[k * S + r], U.bo[s] * kq[k * S + r]) * sr * dc : 0.0;
+      for (int u = 0; u < MJ; ++u) {
+        if (u < nj) {
+          const int32_t c = cl[u * S + jr];
+          const double dc = dl[c - d0];
+          const double v_n = fma(U.a[s], mm[u * S + jr], U.b[s] * kq[u * S + jr]) * sr * dc;
+          const double v_o = fma(U.ao[s], mm[u * S + jr], U.bo[s] * kq[u * S + jr]) * sr * dc;
+          const double d = fma(-al, v_n, v_o);
+          n_old = fma(v_o, v_o, n_old);
+          n_res = fma(d, d, n_res);
+        }
+      }
+      if (sqrt(n_res) <= tol * sqrt(n_old)) {
+        skipped = true;
+        const int32_t base_j = pd.slice_ptr[j / kSlice] + (int32_t)(j % kSlice);
+#pragma unroll
+        for (int u = 0; u < MJ; ++u)
+          if (u < nj) hs[base_j + u * kSlice] = cl[u * S + jr] == (int)j ? al : 0.0;
+        U.obj[s][j] = sqrt(n_res);
+      } else {
+        solve = true;
       }
     }
-    __syncthreads();
-    const int64_t j = j0 + t;
-    bool skipped = false;
-    if (j < pd.n)
-      skipped = spai_band_column<MJ, true, RANGE>(pd, vn, vo, cl, ln, S, w0, j, *U.alpha[s], tol,
-                                                  hat + (int64_t)s * stored, U.obj[s]);
+    // scaled values of the window only when some column needs its solve
+    if (__syncthreads_or(solve)) {
+      for (int64_t row = w0 + t; row < w1; row += 256) {
+        const int r = (int)(row - w0);
+        const double sr = dl[row - d0];
+        const int len = ln[r];
+#pragma unroll
+        for (int k = 0; k < MJ; ++k) {
+          const bool in = k < len;
+          const int32_t c = cl[k * S + r];
+          const double dc = dl[(in ? c : row) - d0];
+          // same association as k_scaled_values
+          vn[k * S + r] = in ? fma(U.a[s], mm[k * S + r], U.b[s] * kq[k * S + r]) * sr * dc : 0.0;
+          vo[k * S + r] = in ? fma(U.ao[s], mm[k * S + r], U.bo[s] * kq[k * S + r]) * sr * dc : 0.0;
+        }
+      }
+      __syncthreads();
+      if (solve) spai_band_column<MJ, true, RANGE>(pd, vn, vo, cl, ln, S, w0, j, al, tol, hs, U.obj[s]);
+    }
     block_count(skipped, skip_part + (int64_t)s * nb);
   }
 }
