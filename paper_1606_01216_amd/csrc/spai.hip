@@ -195,7 +195,8 @@ __global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, const double* _
                                                    const double* __restrict__ alpha_u, double tol,
                                                    double* __restrict__ hat,
                                                    double* __restrict__ obj,
-                                                   int32_t* __restrict__ skip_count) {
+                                                   int32_t* __restrict__ skip_count,
+                                                   int8_t* __restrict__ skipf) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   bool skipped = false;
   if (j < pd.n) {
@@ -225,13 +226,12 @@ __global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, const double* _
           n_res = fma(d, d, n_res);
         }
       }
+      // a skipped column (alpha e_j) is only flagged; the finalize forms it
       if (sqrt(n_res) <= tol * sqrt(n_old)) {
         skipped = true;
-#pragma unroll
-        for (int t = 0; t < MJ; ++t)
-          if (t < nj) hat[jpos[t]] = J[t] == (int)j ? al : 0.0;
         obj[j] = sqrt(n_res);
       }
+      skipf[j] = skipped ? 1 : 0;
     }
     if (!skipped) {
       double R[MJ * (MJ + 1) / 2];
@@ -328,7 +328,8 @@ __device__ __forceinline__ bool spai_band_column(const PencilDev& pd, const doub
                                                  const int32_t* ln, int S, int64_t w0,
                                                  int64_t j, double al, double tol,
                                                  double* __restrict__ hat,
-                                                 double* __restrict__ obj) {
+                                                 double* __restrict__ obj,
+                                                 int8_t* __restrict__ skipf) {
   bool skipped = false;
   {
     const int jr = (int)(j - w0);
@@ -349,13 +350,12 @@ __device__ __forceinline__ bool spai_band_column(const PencilDev& pd, const doub
           n_res = fma(d, d, n_res);
         }
       }
+      // a skipped column (alpha e_j) is only flagged; the finalize forms it
       if (sqrt(n_res) <= tol * sqrt(n_old)) {
         skipped = true;
-#pragma unroll
-        for (int u = 0; u < MJ; ++u)
-          if (u < nj) hat[base_j + u * kSlice] = J[u] == (int)j ? al : 0.0;
         obj[j] = sqrt(n_res);
       }
+      skipf[j] = skipped ? 1 : 0;
     }
     if (!skipped) {
       double R[MJ * (MJ + 1) / 2];
@@ -461,7 +461,8 @@ __global__ void __launch_bounds__(256) k_spai_band(PencilDev pd, double a, doubl
                                                    int bw, const double* __restrict__ alpha_u,
                                                    double tol, double* __restrict__ hat,
                                                    double* __restrict__ obj,
-                                                   int32_t* __restrict__ skip_count) {
+                                                   int32_t* __restrict__ skip_count,
+                                                   int8_t* __restrict__ skipf) {
   extern __shared__ double lds[];
   const int S = 256 + 4 * bw;
   double* vn = lds;
@@ -510,7 +511,7 @@ __global__ void __launch_bounds__(256) k_spai_band(PencilDev pd, double a, doubl
   bool skipped = false;
   if (j < pd.n)
     skipped = spai_band_column<MJ, UPDATE, RANGE>(pd, vn, vo, cl, ln, S, w0, j,
-                                                  UPDATE ? *alpha_u : 0.0, tol, hat, obj);
+                                                  UPDATE ? *alpha_u : 0.0, tol, hat, obj, skipf);
   if constexpr (UPDATE) block_count(skipped, skip_count);
 }
 
@@ -528,6 +529,7 @@ struct UpdMany {
   double* alpha[kManyMax];            // each new factor's alpha (device)
   int32_t* skip[kManyMax];            // each new factor's skipped-column count
   double* obj[kManyMax];              // each new factor's objective
+  int8_t* skipf[kManyMax];            // each new factor's skipped-column flags
 };
 
 // dinv of every shift of the batch: [count][n_pad]; the diagonal is read once.
@@ -690,11 +692,8 @@ __global__ void __launch_bounds__(256) k_spai_update_many(PencilDev pd, UpdMany 
       }
       if (sqrt(n_res) <= tol * sqrt(n_old)) {
         skipped = true;
-        const int32_t base_j = pd.slice_ptr[j / kSlice] + (int32_t)(j % kSlice);
-#pragma unroll
-        for (int u = 0; u < MJ; ++u)
-          if (u < nj) hs[base_j + u * kSlice] = cl[u * S + jr] == (int)j ? al : 0.0;
         U.obj[s][j] = sqrt(n_res);
+        U.skipf[s][j] = 1;
       } else {
         solve = true;
       }
@@ -716,7 +715,9 @@ __global__ void __launch_bounds__(256) k_spai_update_many(PencilDev pd, UpdMany 
         }
       }
       __syncthreads();
-      if (solve) spai_band_column<MJ, true, RANGE>(pd, vn, vo, cl, ln, S, w0, j, al, tol, hs, U.obj[s]);
+      if (solve)
+        spai_band_column<MJ, true, RANGE>(pd, vn, vo, cl, ln, S, w0, j, al, tol, hs, U.obj[s],
+                                          U.skipf[s]);
     }
     block_count(skipped, skip_part + (int64_t)s * nb);
   }
@@ -732,6 +733,7 @@ __global__ void __launch_bounds__(256) k_spai_update_many(PencilDev pd, UpdMany 
 __global__ void k_spai_finalize(PencilDev pd, const double* __restrict__ hat,
                                 const double* __restrict__ dinv, int mode,
                                 const int32_t* __restrict__ skip_total,
+                                const int8_t* __restrict__ skipf, const double* __restrict__ alpha,
                                 double* __restrict__ v64, float* __restrict__ v32) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= (int64_t)pd.n_slices * kSlice) return;
@@ -746,8 +748,9 @@ __global__ void k_spai_finalize(PencilDev pd, const double* __restrict__ hat,
     double val = 0.0;
     if (k < len) {
       const int c = pd.col[idx];
-      // hat holds column c's solution at the position of (c, r)
-      double h = hat[pd.mirror[idx]];
+      // hat holds column c's solution at the position of (c, r); a skipped
+      // column c (update) is alpha e_c
+      double h = (skipf && skipf[c]) ? (c == (int)r ? *alpha : 0.0) : hat[pd.mirror[idx]];
       if (mode == 1) h = 0.5 * (h + hat[idx]);
       val = mode == 2 ? h * sr / dinv[c] : h * sr * dinv[c];
     }
@@ -824,6 +827,10 @@ void pool_put(airga_ctx ctx, DevBuf* buf) {
   if (p) ctx->pool.emplace_back(p, b);
 }
 
+// Device scalars of a factor: alpha (8 bytes), the skip count (4), padding to
+// 64, then one byte per column, set when the update kept alpha e_j there.
+static int8_t* skip_flags(airga_prec p) { return p->scal.as<int8_t>() + 64; }
+
 static airga_status new_prec(airga_ctx ctx, double s, airga_prec* out) {
   airga_prec p = new (std::nothrow) airga_prec_s();
   if (!p) return fail(AIRGA_ENOMEM, "host allocation failed");
@@ -835,7 +842,7 @@ static airga_status new_prec(airga_ctx ctx, double s, airga_prec* out) {
   if ((st = pool_get(ctx, &p->v64, sizeof(double) * pen.nnz_stored)) != AIRGA_OK ||
       (st = pool_get(ctx, &p->v32, sizeof(float) * pen.nnz_stored)) != AIRGA_OK ||
       (st = pool_get(ctx, &p->objective, sizeof(double) * pen.n)) != AIRGA_OK ||
-      (st = pool_get(ctx, &p->scal, 64)) != AIRGA_OK) {
+      (st = pool_get(ctx, &p->scal, 64 + (size_t)pen.n_pad())) != AIRGA_OK) {
     pool_put(ctx, &p->v64);
     pool_put(ctx, &p->v32);
     pool_put(ctx, &p->objective);
@@ -891,7 +898,7 @@ static bool spai_banded(const Pencil& pen, const airga_spai_opts& o, bool update
 template <bool UPDATE>
 static void launch_band(airga_ctx ctx, double a, double b, double ao, double bo,
                         const double* dinv, const double* alpha_u, double tol, double* hat,
-                        double* obj, int32_t* skip) {
+                        double* obj, int32_t* skip, int8_t* skipf) {
   const Pencil& pen = ctx->pen;
   const unsigned nb = blocks_for(pen.n, 256);
   const int bw = pen.bandwidth;
@@ -903,33 +910,33 @@ static void launch_band(airga_ctx ctx, double a, double b, double ao, double bo,
     const size_t lds = spai_band_lds<6>(bw, UPDATE);
     if (range)
       k_spai_band<6, UPDATE, true><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw, alpha_u, tol,
-                                                         hat, obj, skip);
+                                                         hat, obj, skip, skipf);
     else
       k_spai_band<6, UPDATE, false><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw, alpha_u, tol,
-                                                          hat, obj, skip);
+                                                          hat, obj, skip, skipf);
   } else {
     const size_t lds = spai_band_lds<kSpaiMaxJ>(bw, UPDATE);
     if (range)
       k_spai_band<kSpaiMaxJ, UPDATE, true><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw,
-                                                                 alpha_u, tol, hat, obj, skip);
+                                                                 alpha_u, tol, hat, obj, skip, skipf);
     else
       k_spai_band<kSpaiMaxJ, UPDATE, false><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw,
-                                                                  alpha_u, tol, hat, obj, skip);
+                                                                  alpha_u, tol, hat, obj, skip, skipf);
   }
 }
 
 // Column kernels sized to the longest row.
 template <bool UPDATE>
 static void launch_cols(airga_ctx ctx, const SpaiScratch& w, const double* alpha_u, double tol,
-                        double* obj, int32_t* skip) {
+                        double* obj, int32_t* skip, int8_t* skipf) {
   const Pencil& pen = ctx->pen;
   const unsigned nb = blocks_for(pen.n, 256);
   if (pen.max_len <= 6)
     k_spai_cols<6, UPDATE><<<nb, 256, 0, ctx->stream>>>(pen.dev(), w.ahat, w.aold, alpha_u, tol,
-                                                       w.hat, obj, skip);
+                                                       w.hat, obj, skip, skipf);
   else
     k_spai_cols<kSpaiMaxJ, UPDATE><<<nb, 256, 0, ctx->stream>>>(pen.dev(), w.ahat, w.aold, alpha_u,
-                                                               tol, w.hat, obj, skip);
+                                                               tol, w.hat, obj, skip, skipf);
 }
 
 static airga_status run_build(airga_ctx ctx, double s, const airga_spai_opts& o, airga_prec p) {
@@ -945,15 +952,15 @@ static airga_status run_build(airga_ctx ctx, double s, const airga_spai_opts& o,
   AIRGA_HIP(hipGetLastError());
   if (spai_banded(pen, o, false)) {
     launch_band<false>(ctx, a, b, 0.0, 0.0, w.dinv, nullptr, 0.0, w.hat,
-                       p->objective.as<double>(), nullptr);
+                       p->objective.as<double>(), nullptr, nullptr);
   } else {
     k_scaled_values<<<nr, 256, 0, st>>>(pd, a, b, w.dinv, w.ahat);
     AIRGA_HIP(hipGetLastError());
-    launch_cols<false>(ctx, w, nullptr, 0.0, p->objective.as<double>(), nullptr);
+    launch_cols<false>(ctx, w, nullptr, 0.0, p->objective.as<double>(), nullptr, nullptr);
   }
   AIRGA_HIP(hipGetLastError());
-  k_spai_finalize<<<nr, 256, 0, st>>>(pd, w.hat, w.dinv, o.symmetrize ? 1 : 0, nullptr,
-                                      p->v64.as<double>(), p->v32.as<float>());
+  k_spai_finalize<<<nr, 256, 0, st>>>(pd, w.hat, w.dinv, o.symmetrize ? 1 : 0, nullptr, nullptr,
+                                      nullptr, p->v64.as<double>(), p->v32.as<float>());
   AIRGA_HIP(hipGetLastError());
   // Alg. 2's starting scaling trace(K) / trace(K K^T), from the Gram scalars.
   const double nn = a * a * pen.gram_mm + 2 * a * b * pen.gram_mk + b * b * pen.gram_kk;
@@ -994,14 +1001,15 @@ static airga_status run_update(airga_ctx ctx, airga_prec old, double s_new,
   AIRGA_HIP(hipGetLastError());
   if (band)
     launch_band<true>(ctx, a, b, ao, bo, w.dinv, d_alpha, o.tol, w.hat, p->objective.as<double>(),
-                      w.skip_part);
+                      w.skip_part, skip_flags(p));
   else
-    launch_cols<true>(ctx, w, d_alpha, o.tol, p->objective.as<double>(), w.skip_part);
+    launch_cols<true>(ctx, w, d_alpha, o.tol, p->objective.as<double>(), w.skip_part,
+                      skip_flags(p));
   AIRGA_HIP(hipGetLastError());
   k_sum_counts<<<1, 256, 0, st>>>(w.skip_part, nb, d_skip);
   AIRGA_HIP(hipGetLastError());
-  k_spai_finalize<<<nr, 256, 0, st>>>(pd, w.hat, w.dinv, 2, d_skip, p->v64.as<double>(),
-                                      p->v32.as<float>());
+  k_spai_finalize<<<nr, 256, 0, st>>>(pd, w.hat, w.dinv, 2, d_skip, skip_flags(p), d_alpha,
+                                      p->v64.as<double>(), p->v32.as<float>());
   AIRGA_HIP(hipGetLastError());
   p->is_update = true;
   p->parent = old;
@@ -1047,6 +1055,7 @@ static airga_status run_update_many(airga_ctx ctx, int32_t count, const airga_pr
       U.alpha[i] = p->scal.as<double>();
       U.skip[i] = reinterpret_cast<int32_t*>(p->scal.as<char>() + 8);
       U.obj[i] = p->objective.as<double>();
+      U.skipf[i] = skip_flags(p);
     }
     k_dinv_many<<<blocks_for(n_pad, 256), 256, 0, st>>>(pd, U, o.equilibrate, n_pad, dinv);
     AIRGA_HIP(hipGetLastError());
@@ -1068,7 +1077,8 @@ static airga_status run_update_many(airga_ctx ctx, int32_t count, const airga_pr
     for (int i = 0; i < cnt; ++i) {
       const airga_prec p = ps[i0 + i];
       k_spai_finalize<<<nr, 256, 0, st>>>(pd, hat + (size_t)i * stored, dinv + (size_t)i * n_pad, 2,
-                                          U.skip[i], p->v64.as<double>(), p->v32.as<float>());
+                                          U.skip[i], U.skipf[i], U.alpha[i], p->v64.as<double>(),
+                                          p->v32.as<float>());
       AIRGA_HIP(hipGetLastError());
       p->is_update = true;
       p->parent = olds[i0 + i];
