@@ -364,6 +364,7 @@ def main():
     # ---- roofline of the dominant row kernel (algorithmic bytes / duration)
     stored = info.nnz_stored
     w = 4  # float32 inner solves
+    fw = 2  # their preconditioner values: bfloat16
     # column information per stored entry: a 1-byte offset for banded
     # pencils (bandwidth <= 64, the LDS-window kernels), else a 4-byte index
     ib = 1 if info.bandwidth <= 64 else 4
@@ -371,9 +372,9 @@ def main():
         if name == "dir_spmv":
             return launches * stored * (ib + 2 * w) + sysp * 4 * w * n
         if name == "update_prec":
-            return launches * stored * ib + shp * stored * w + sysp * 7 * w * n
+            return launches * stored * ib + shp * stored * fw + sysp * 7 * w * n
         if name == "init_prec":
-            return launches * stored * ib + shp * stored * w + sysp * 2 * w * n
+            return launches * stored * ib + shp * stored * fw + sysp * 2 * w * n
         return None
     rows = []
     for name in ("dir_spmv", "update_prec", "init_prec", "chain", "ir_residual", "ir_update", "reduce"):

@@ -155,7 +155,8 @@ AIRGA_API void airga_spai_opts_default(airga_spai_opts* opts);
  * column j, p_j = argmin || e_j - K(s) p ||_2 over vectors with the
  * pattern of column j, solved exactly per column (Givens QR in float64,
  * one column per GPU lane).  `opts` may be NULL (defaults).  The handle
- * owns the factor (float64 and float32 copies) and must be released with
+ * owns the factor (a float64 copy, and a bfloat16 copy for the float32
+ * inner solves of MIXED mode) and must be released with
  * airga_prec_release.  Asynchronous.  Pencils of bandwidth <= 64 use
  * kernels that stage each block's rows in LDS (see general_only).
  * Errors: EINVAL (s <= 0 or non-finite, null out), ESTATE (no pencil),
@@ -226,8 +227,9 @@ typedef struct {
   int32_t max_iter;    /* CG iterations per system, summed over sweeps
                           (default 20000)                                       */
   int32_t mode;        /* AIRGA_MODE_FP64 or AIRGA_MODE_MIXED (float32 matrix,
-                          preconditioner and vectors inside float64 iterative
-                          refinement of the residual and the solution)          */
+                          arithmetic and vectors, preconditioner values stored
+                          as bfloat16, inside float64 iterative refinement of
+                          the residual and the solution)                        */
   double inner_tol;    /* MIXED: relative residual reduction per sweep (5e-4)   */
   int32_t max_sweeps;  /* MIXED: refinement sweeps (default 12)                 */
   int32_t poll_every;  /* iterations between host checks of the active count

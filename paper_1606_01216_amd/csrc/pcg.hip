@@ -475,7 +475,7 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
   std::memset(static_cast<void*>(&P.a), 0, sizeof(P.a));
   std::memset(static_cast<void*>(&P.red), 0, sizeof(P.red));
   // factor values per shift, oldest first; no preconditioner = the identity
-  std::vector<std::vector<const T*>> chains(nshift);
+  std::vector<std::vector<const fac_t<T>*>> chains(nshift);
   int maxc = 1;
   {
     std::vector<airga_prec> all;
@@ -488,12 +488,12 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
       std::vector<airga_prec> ch;
       AIRGA_TRY(prec_chain(precs[k], &ch));
       for (auto it = ch.rbegin(); it != ch.rend(); ++it) {
-        if constexpr (sizeof(T) == 4) chains[k].push_back((*it)->v32.as<float>());
+        if constexpr (sizeof(T) == 4) chains[k].push_back((*it)->v16.as<uint16_t>());
         else chains[k].push_back((*it)->v64.as<double>());
       }
     }
     if (chains[k].empty()) {
-      if constexpr (sizeof(T) == 4) chains[k].push_back(pen.id32.as<float>());
+      if constexpr (sizeof(T) == 4) chains[k].push_back(pen.id16.as<uint16_t>());
       else chains[k].push_back(pen.id64.as<double>());
     }
     maxc = (int)chains[k].size() > maxc ? (int)chains[k].size() : maxc;
@@ -534,7 +534,7 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
   T* h_ca = reinterpret_cast<T*>(h_cb64 + nshift);
   T* h_cb = h_ca + nshift;
   const size_t off_fac = 4 * sizeof(double) * nshift;
-  const T** h_fac = reinterpret_cast<const T**>(hp + off_fac);
+  const fac_t<T>** h_fac = reinterpret_cast<const fac_t<T>**>(hp + off_fac);
   int32_t* h_clen = reinterpret_cast<int32_t*>(hp + off_fac + sizeof(void*) * (size_t)nshift * maxc);
   int32_t* h_flex = h_clen + nshift;
   P.clen.assign(nshift, 0);
@@ -582,7 +582,7 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
   A.ws = ctx->ws_vec.as<T>();
   A.ca = reinterpret_cast<const T*>(sd + 2 * sizeof(double) * nshift);
   A.cb = A.ca + nshift;
-  A.fac = reinterpret_cast<const T* const*>(sd + off_fac);
+  A.fac = reinterpret_cast<const fac_t<T>* const*>(sd + off_fac);
   A.clen = reinterpret_cast<const int32_t*>(sd + off_fac + sizeof(void*) * (size_t)nshift * maxc);
   P.red.flex = A.clen + nshift;
   P.red.m = m;

@@ -45,6 +45,16 @@ struct SysDev {
   int32_t* handed;  // mixed mode: 1 = left the float32 sweeps for the float64 finish
 };
 
+// Storage of preconditioner values: bfloat16 bits for the float32 inner
+// solves (the factor is an approximate inverse; its rounding to 8 mantissa
+// bits leaves the operator and the vectors in float32), float64 otherwise.
+template <typename T> struct FacStore;
+template <> struct FacStore<float> { using type = uint16_t; };
+template <> struct FacStore<double> { using type = double; };
+template <typename T> using fac_t = typename FacStore<T>::type;
+__device__ __forceinline__ float fac_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ double fac_value(double v) { return v; }
+
 template <typename T>
 struct SolveArgs {
   PencilDev pd;
@@ -55,7 +65,7 @@ struct SolveArgs {
   T* ws;                     // vector workspace (the iterate x is kind KX)
   const T* ca;               // per shift a_k = s_k^2 + alpha s_k
   const T* cb;               // per shift b_k = 1 + beta s_k
-  const T* const* fac;       // per shift [maxc] factor values, fac[sh * maxc + q], oldest first
+  const fac_t<T>* const* fac;  // per shift [maxc] factor values, fac[sh * maxc + q], oldest first
   const int32_t* clen;       // per shift number of applied factors
   int32_t maxc;
   double* partial;           // [kSlots][B][GP], slot-major
@@ -149,6 +159,15 @@ struct Rows {
 #pragma unroll
       for (int k = 0; k < WMAX; ++k)
         out[i][k] = (valid[i] && (EXACT || k < w[i])) ? v[idx0[i] + k * kSlice] : T(0);
+  }
+  // factor values in their storage type, widened to T
+  template <typename TS, typename T>
+  __device__ __forceinline__ void factor(const TS* __restrict__ v, T (&out)[R][WMAX]) const {
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+      for (int k = 0; k < WMAX; ++k)
+        out[i][k] = (valid[i] && (EXACT || k < w[i])) ? (T)fac_value(v[idx0[i] + k * kSlice]) : T(0);
   }
 };
 
@@ -402,7 +421,7 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
         const int sh = b / A.m;
         Ls[u] = sload(A.clen + sh);
         if (sh != csh[u]) {
-          rows.values(sload(A.fac + (int64_t)sh * A.maxc), pv[u]);
+          rows.factor(sload(A.fac + (int64_t)sh * A.maxc), pv[u]);
           csh[u] = sh;
         }
         const T al = INIT ? T(0) : (T)sload(A.sys.alpha + b);
@@ -456,7 +475,7 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
         const int sh = b / A.m;
         Ls[u] = sload(A.clen + sh);
         if (sh != csh[u]) {
-          rows.values(sload(A.fac + (int64_t)sh * A.maxc), pv[u]);
+          rows.factor(sload(A.fac + (int64_t)sh * A.maxc), pv[u]);
           csh[u] = sh;
         }
         const T al = INIT ? T(0) : (T)sload(A.sys.alpha + b);
@@ -543,7 +562,7 @@ __global__ void __launch_bounds__(256) k_chain(SolveArgs<T> A, int par, int q, i
     const int L = sload(A.clen + sh);
     if (L <= q) continue;
     if (sh != loaded_sh) {
-      rows.values(sload(A.fac + (int64_t)sh * A.maxc + q), fv);
+      rows.factor(sload(A.fac + (int64_t)sh * A.maxc + q), fv);
       loaded_sh = sh;
     }
     const T* __restrict__ src = A.vec(chain_dst(q - 1, L), b);

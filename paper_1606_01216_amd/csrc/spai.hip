@@ -734,7 +734,7 @@ __global__ void k_spai_finalize(PencilDev pd, const double* __restrict__ hat,
                                 const double* __restrict__ dinv, int mode,
                                 const int32_t* __restrict__ skip_total,
                                 const int8_t* __restrict__ skipf, const double* __restrict__ alpha,
-                                double* __restrict__ v64, float* __restrict__ v32) {
+                                double* __restrict__ v64, uint16_t* __restrict__ v16) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= (int64_t)pd.n_slices * kSlice) return;
   if (skip_total && *skip_total == pd.n) return;
@@ -755,7 +755,7 @@ __global__ void k_spai_finalize(PencilDev pd, const double* __restrict__ hat,
       val = mode == 2 ? h * sr / dinv[c] : h * sr * dinv[c];
     }
     v64[idx] = val;
-    v32[idx] = (float)val;
+    v16[idx] = to_bf16(val);
   }
 }
 
@@ -840,11 +840,11 @@ static airga_status new_prec(airga_ctx ctx, double s, airga_prec* out) {
   const Pencil& pen = ctx->pen;
   airga_status st;
   if ((st = pool_get(ctx, &p->v64, sizeof(double) * pen.nnz_stored)) != AIRGA_OK ||
-      (st = pool_get(ctx, &p->v32, sizeof(float) * pen.nnz_stored)) != AIRGA_OK ||
+      (st = pool_get(ctx, &p->v16, sizeof(uint16_t) * pen.nnz_stored)) != AIRGA_OK ||
       (st = pool_get(ctx, &p->objective, sizeof(double) * pen.n)) != AIRGA_OK ||
       (st = pool_get(ctx, &p->scal, 64 + (size_t)pen.n_pad())) != AIRGA_OK) {
     pool_put(ctx, &p->v64);
-    pool_put(ctx, &p->v32);
+    pool_put(ctx, &p->v16);
     pool_put(ctx, &p->objective);
     pool_put(ctx, &p->scal);
     delete p;
@@ -960,7 +960,7 @@ static airga_status run_build(airga_ctx ctx, double s, const airga_spai_opts& o,
   }
   AIRGA_HIP(hipGetLastError());
   k_spai_finalize<<<nr, 256, 0, st>>>(pd, w.hat, w.dinv, o.symmetrize ? 1 : 0, nullptr, nullptr,
-                                      nullptr, p->v64.as<double>(), p->v32.as<float>());
+                                      nullptr, p->v64.as<double>(), p->v16.as<uint16_t>());
   AIRGA_HIP(hipGetLastError());
   // Alg. 2's starting scaling trace(K) / trace(K K^T), from the Gram scalars.
   const double nn = a * a * pen.gram_mm + 2 * a * b * pen.gram_mk + b * b * pen.gram_kk;
@@ -1009,7 +1009,7 @@ static airga_status run_update(airga_ctx ctx, airga_prec old, double s_new,
   k_sum_counts<<<1, 256, 0, st>>>(w.skip_part, nb, d_skip);
   AIRGA_HIP(hipGetLastError());
   k_spai_finalize<<<nr, 256, 0, st>>>(pd, w.hat, w.dinv, 2, d_skip, skip_flags(p), d_alpha,
-                                      p->v64.as<double>(), p->v32.as<float>());
+                                      p->v64.as<double>(), p->v16.as<uint16_t>());
   AIRGA_HIP(hipGetLastError());
   p->is_update = true;
   p->parent = old;
@@ -1078,7 +1078,7 @@ static airga_status run_update_many(airga_ctx ctx, int32_t count, const airga_pr
       const airga_prec p = ps[i0 + i];
       k_spai_finalize<<<nr, 256, 0, st>>>(pd, hat + (size_t)i * stored, dinv + (size_t)i * n_pad, 2,
                                           U.skip[i], U.skipf[i], U.alpha[i], p->v64.as<double>(),
-                                          p->v32.as<float>());
+                                          p->v16.as<uint16_t>());
       AIRGA_HIP(hipGetLastError());
       p->is_update = true;
       p->parent = olds[i0 + i];
@@ -1299,7 +1299,7 @@ void airga_prec_release(airga_prec prec) {
     airga_ctx ctx = prec->ctx;
     // buffers go back to the context's stream-ordered pool
     pool_put(ctx, &prec->v64);
-    pool_put(ctx, &prec->v32);
+    pool_put(ctx, &prec->v16);
     pool_put(ctx, &prec->objective);
     pool_put(ctx, &prec->scal);
     ctx->live_precs--;
