@@ -98,6 +98,8 @@ __global__ void __launch_bounds__(NT) k_reduce(ReduceArgs P, int mode) {
     case RM_ITER: {
       const int it = Sy.iters[b] + 1;
       Sy.iters[b] = it;
+      // the iterate has been written (x = 0 + alpha p, at least)
+      Sy.first[b] = 0;
       if (!isfinite(s1) || !isfinite(rz) || !isfinite(zw)) { Sy.istat[b] = ST_NONFIN; act = 0; }
       else if (s1 <= Sy.tol2[b]) { Sy.istat[b] = ST_CONV; act = 0; }
       else if (it >= P.max_iter) { Sy.istat[b] = ST_MAXIT; act = 0; }
@@ -106,7 +108,6 @@ __global__ void __launch_bounds__(NT) k_reduce(ReduceArgs P, int mode) {
         // preconditioner; classical: the (r, z) ratio, for a symmetric one
         Sy.beta[b] = P.flex[b / P.m] ? -zw / Sy.pw[b] : rz / Sy.rz[b];
         Sy.rz[b] = rz;
-        Sy.first[b] = 0;
       }
       break;
     }
@@ -224,12 +225,20 @@ __global__ void k_copy_out(const double* __restrict__ ws_x, int64_t ld, int64_t 
 }
 
 // X += inner solution (float32 -> float64) for systems refined this sweep.
-__global__ void k_ir_update(SolveArgs<float> A, double* __restrict__ X, int64_t ldX) {
+__global__ void k_ir_update(SolveArgs<float> A, double* __restrict__ X, int64_t ldX, int assign) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int b = blockIdx.y;
-  if (!A.sys.outer[b] || A.sys.istat[b] == ST_NONFIN) return;
-  if (r < A.pd.n) X[(int64_t)b * ldX + r] += (double)A.vec(KX, b)[r];
-  if (r == 0) A.sys.sweeps[b] += 1;
+  const bool swept = A.sys.outer[b] && A.sys.istat[b] != ST_NONFIN;
+  // the float32 iterate holds a correction only if the sweep updated it
+  // (first is set at the start of an inner solve and cleared by its first
+  // update); assign: X has not been written yet (no starting guess)
+  const bool add = swept && A.sys.first[b] == 0;
+  if (r < A.pd.n) {
+    double* __restrict__ x = X + (int64_t)b * ldX + r;
+    if (add) *x = (assign ? 0.0 : *x) + (double)A.vec(KX, b)[r];
+    else if (assign) *x = 0.0;
+  }
+  if (r == 0 && swept) A.sys.sweeps[b] += 1;
 }
 
 // K(s) in stored (sliced-ELL) order, for the single-shift float64 path.
@@ -590,6 +599,7 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
   A.partial = ctx->ws_partial.as<double>();
   A.GP = GP;
   A.blk = blk ? 1 : 0;
+  A.xz = 0;
   A.sys = S;
   P.red.partial = A.partial;
   P.red.G = GP;
@@ -840,14 +850,20 @@ static airga_status solve_mixed(airga_ctx ctx, int32_t nshift, const double* shi
   Timer tm{ctx, o.profile != 0, {}, {}};
   int32_t* h_nact = reinterpret_cast<int32_t*>(static_cast<char*>(ctx->host_pinned) + P.flags_off);
   const int x0 = o.x0_given ? 1 : 0;
+  // Every inner solve starts from a zero iterate that is never stored (the
+  // first update of a sweep writes it), and without a starting guess X is
+  // first assigned by the sweep-0 correction instead of zeroed beforehand.
+  P.a.xz = 1;
   // sweep 0 residual; RM_OUTER then activates the systems to refine
   TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds_res, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, x0,
-                                                         1 - x0, 1));
+                                                         0, 0));
   k_clear_active<<<blocks_for(B, 256), 256, 0, st>>>(P.a.sys, B);
   AIRGA_HIP(hipGetLastError());
   TIMED(K_REDUCE, reduce(P, RM_OUTER));
   const int64_t cap = o.inner_max > 0 ? o.inner_max : kInnerMax;
   bool any_handed = false;
+  bool assign = x0 == 0;  // X still unwritten
+  const dim3 ir_grid(blocks_for(pen.n, 256), (unsigned)B);
   for (int sweep = 0; sweep <= o.max_sweeps; ++sweep) {
     AIRGA_HIP(hipMemcpyAsync(h_nact, P.a.sys.nact, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     AIRGA_HIP(hipStreamSynchronize(st));
@@ -855,15 +871,20 @@ static airga_status solve_mixed(airga_ctx ctx, int32_t nshift, const double* shi
     AIRGA_TRY(start_inner(P, tm, 1));
     bool capped = false;
     AIRGA_TRY(iterate(P, tm, o, cap, *h_nact, &capped));
-    TIMED(K_IR_UPDATE,
-          (k_ir_update<<<dim3(blocks_for(pen.n, 256), (unsigned)B), 256, 0, st>>>(P.a, X, ldx)));
+    TIMED(K_IR_UPDATE, (k_ir_update<<<ir_grid, 256, 0, st>>>(P.a, X, ldx, assign ? 1 : 0)));
+    assign = false;
     if (capped) {
       k_handover<<<blocks_for(B, 256), 256, 0, st>>>(P.a.sys, B);
       AIRGA_HIP(hipGetLastError());
       any_handed = true;
     }
-    TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds_res, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, 1, 0, 1));
+    TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds_res, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, 1, 0, 0));
     TIMED(K_REDUCE, reduce(P, RM_OUTER));
+  }
+  // no sweep ran (every system settled by the first residual): X = 0
+  if (assign) {
+    k_ir_update<<<ir_grid, 256, 0, st>>>(P.a, X, ldx, 1);
+    AIRGA_HIP(hipGetLastError());
   }
   AIRGA_TRY(tm.flush());
   std::vector<airga_sys_stats> mixed(B);

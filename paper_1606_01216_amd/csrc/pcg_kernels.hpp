@@ -71,6 +71,8 @@ struct SolveArgs {
   double* partial;           // [kSlots][B][GP], slot-major
   int32_t GP;                // partial columns per system (blocks if blk, else wavefronts)
   int32_t blk;               // 1: the 4 wavefronts of a block pre-sum their partials in LDS
+  int32_t xz;                // 1: each inner solve starts from x = 0, which is never stored:
+                             //    its first update writes x = alpha p without reading x
   int32_t bw;                // pencil bandwidth max |c - r| (banded kernels: <= 64)
   int32_t stage_off;         // doubles of dynamic LDS before the banded staging area
   const int32_t* fmap;       // column of F for system b (nullptr: b % m)
@@ -441,10 +443,14 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
           }
         }
         if constexpr (!INIT) {
+          // a zero start reads p again (in cache) instead of x, and drops it
+          const bool x0 = A.xz && sload(A.sys.first + b) != 0;
+          const T* __restrict__ xs = x0 ? pcur : x;
 #pragma unroll
           for (int i = 0; i < R; ++i) {
             const int64_t r = rows.row[i];
-            xn[u][i] = fma(al, pcur[r], x[r]);
+            const T xv = xs[r];
+            xn[u][i] = fma(al, pcur[r], x0 ? T(0) : xv);
           }
         }
       }
@@ -483,6 +489,9 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
         const T* __restrict__ wv = A.vec(KW, b);
         const T* __restrict__ pcur = A.vec(KP0 + (par ^ 1), b);
         const T* __restrict__ x = A.vec(KX, b);
+        // a zero start reads p again (in cache) instead of x, and drops it
+        const bool x0 = !INIT && A.xz && sload(A.sys.first + b) != 0;
+        const T* __restrict__ xs = x0 ? pcur : x;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
           const int64_t r = rows.row[i];
@@ -492,7 +501,8 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
           } else {
             wr = wv[r];
             v = fma(-al, wr, rin[r]);
-            xn[u][i] = fma(al, pcur[r], x[r]);
+            const T xv = xs[r];
+            xn[u][i] = fma(al, pcur[r], x0 ? T(0) : xv);
           }
           T t = T(0);
 #pragma unroll
