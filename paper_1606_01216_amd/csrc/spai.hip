@@ -23,6 +23,19 @@ __device__ __host__ constexpr int tri(int k, int l) {
   return k * MJ - (k * (k - 1)) / 2 + (l - k);
 }
 
+// 1 / sqrt(x) for a normal positive x: the hardware estimate refined by two
+// Newton-Raphson steps y <- y + y (1 - x y^2) / 2 (each roughly doubles the
+// correct bits), which leaves an error of a few ulp.
+__device__ __forceinline__ double rsqrt_newton(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double e = fma(-x, y * y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
 // Fold one row (v, rhs) of the least-squares problem into the triangular
 // factor R and Q^T b by Givens rotations; on return rhs holds the component
 // of the row left orthogonal to the column space.
@@ -33,11 +46,18 @@ __device__ __forceinline__ void givens_row(double (&R)[MJ * (MJ + 1) / 2], doubl
   for (int k = 0; k < MJ; ++k) {
     if (k < nj && v[k] != 0.0) {
       const double rkk = R[tri<MJ>(k, k)];
-      // h = hypot(rkk, v_k) from the squares; the scaled library routine
-      // only where they would under- or overflow
+      // h = hypot(rkk, v_k) and 1 / h from the squares through one
+      // reciprocal square root; the scaled library routine only where the
+      // squares would under- or overflow
       const double h2 = fma(rkk, rkk, v[k] * v[k]);
-      const double h = (h2 > 1e-290 && h2 < 1e290) ? sqrt(h2) : hypot(rkk, v[k]);
-      const double ih = 1.0 / h;
+      double h, ih;
+      if (h2 > 1e-290 && h2 < 1e290) {
+        ih = rsqrt_newton(h2);
+        h = h2 * ih;
+      } else {
+        h = hypot(rkk, v[k]);
+        ih = 1.0 / h;
+      }
       const double c = rkk * ih, s = v[k] * ih;
       R[tri<MJ>(k, k)] = h;
 #pragma unroll

@@ -336,6 +336,18 @@ def test_edge_cases(ctx):
         _, st1 = ctx.pcg_solve([3.0], [p], to_dev(f[1:2], torch.float64), mode=mode, max_iter=1,
                                tol=1e-14)
         assert st1[0]["status"] == airga.SYS_MAXIT and st1[0]["iters"] == 1
+        # without a starting guess X is written whatever it held: zero for a
+        # zero right-hand side (also when no system iterates at all)
+        ref1 = reference(pen, [3.0], f[1:2])
+        for fx in (f[:2], np.zeros((2, n))):
+            Xn = torch.full((1, 2, n), float("nan"), dtype=torch.float64, device="cuda")
+            _, st2 = ctx.pcg_solve([3.0], [p], to_dev(fx, torch.float64), Xn, mode=mode)
+            Xh2 = Xn.cpu().numpy()
+            assert not np.any(Xh2[0, 0]) and st2[0]["status"] == airga.SYS_CONVERGED
+            if fx[1].any():
+                assert rel_err(Xh2[0, 1], ref1[0, 0]) < SOLVE_TOL
+            else:
+                assert not np.any(Xh2[0, 1])
     # no preconditioner at all
     X, st = ctx.pcg_solve([3.0], [None], to_dev(f[1:2], torch.float64))
     ref = reference(pen, [3.0], f[1:2])
