@@ -475,3 +475,75 @@ def test_galerkin_projection_interpolates_at_expansion_points():
         assert np.allclose(dred, dfull, rtol=1e-5)
     # away from the expansion points the reduced model is only approximate
     assert not np.allclose(moments.reduced_transfer(*red, 7.0), h_full(7.0), rtol=1e-9)
+
+
+# ------------------------------------------------ moment sequence blocks
+
+def test_pencil_apply_special_cases_match_dense_operators():
+    p = small_pencil(15)
+    m, k = beam.pencil_dense(p)
+    ms = pencil.csr(p.n, p.row_ptr, p.col_idx, p.m_val)
+    ks = pencil.csr(p.n, p.row_ptr, p.col_idx, p.k_val)
+    x = np.random.default_rng(0).standard_normal((p.n, 3))
+    # a = 1, b = 0 is M X (the moment right-hand side); the shift
+    # coefficients give K(s) X, the pinned operator
+    assert np.allclose(moments.pencil_apply(ms, ks, 1.0, 0.0, x), m @ x, rtol=0, atol=1e-13)
+    s = 7.0
+    a, b = s * s + p.alpha * s, 1.0 + p.beta * s
+    ref = pencil.shifted_operator(p, s).toarray() @ x
+    assert np.allclose(moments.pencil_apply(ms, ks, a, b, x), ref, rtol=1e-13, atol=1e-12)
+
+
+def test_global_orth_hand_example_follows_the_loop_order():
+    # n = 2, m = 1: V1 = e1, V2 = (1, 1)/sqrt 2, X = (3, 4).  In the
+    # algorithm's order gamma_1 = 3, X = (0, 4), gamma_2 = <V2, (0, 4)> =
+    # 2 sqrt 2, X = (-2, 2).  Products with the unchanged X (classical
+    # Gram-Schmidt) would give gamma_2 = 7 / sqrt 2 instead.
+    v1 = np.array([[1.0], [0.0]])
+    v2 = np.array([[1.0], [1.0]]) / np.sqrt(2.0)
+    x, g, f = moments.global_orth([v1, v2], np.array([[3.0], [4.0]]))
+    assert np.allclose(g, [3.0, 2.0 * np.sqrt(2.0)], rtol=0, atol=1e-15)
+    assert np.allclose(x, [[-2.0], [2.0]], rtol=0, atol=1e-15)
+    assert abs(f - np.sqrt(8.0)) < 1e-15
+
+
+def test_global_orth_orthonormal_basis_invariants():
+    rng = np.random.default_rng(4)
+    n, m, j = 50, 3, 5
+    # blocks orthonormal in the trace inner product: orthonormal vec(V_t)
+    q, _ = np.linalg.qr(rng.standard_normal((n * m, j)))
+    vs = [q[:, t].reshape(n, m) for t in range(j)]
+    for t in range(j):
+        for u in range(j):
+            assert abs(np.trace(vs[t].T @ vs[u]) - (t == u)) < 1e-13
+    x0 = rng.standard_normal((n, m))
+    x, g, f = moments.global_orth(vs, x0)
+    # orthogonal to every block, coefficients are the plain projections,
+    # and X0 is recovered from the result and the coefficients
+    for t in range(j):
+        assert abs(np.trace(vs[t].T @ x)) < 1e-12
+        assert abs(g[t] - np.trace(vs[t].T @ x0)) < 1e-12
+    assert np.allclose(x + sum(g[t] * vs[t] for t in range(j)), x0, rtol=0, atol=1e-13)
+    assert abs(f - np.linalg.norm(x)) < 1e-13
+    # Pythagoras in the trace inner product
+    assert abs(f * f + np.sum(g * g) - np.linalg.norm(x0) ** 2) < 1e-10
+
+
+def test_thin_qr_is_unique_factorisation_and_matches_gram_schmidt():
+    rng = np.random.default_rng(5)
+    w = rng.standard_normal((40, 6))
+    q, r = moments.thin_qr(w)
+    assert np.allclose(q.T @ q, np.eye(6), atol=1e-14)
+    assert np.allclose(np.tril(r, -1), 0.0) and np.all(np.diag(r) > 0)
+    assert np.allclose(q @ r, w, atol=1e-13)
+    # brute force: classical Gram-Schmidt, column by column
+    qg = np.zeros_like(w)
+    rg = np.zeros((6, 6))
+    for j in range(6):
+        v = w[:, j].copy()
+        for i in range(j):
+            rg[i, j] = qg[:, i] @ w[:, j]
+            v -= rg[i, j] * qg[:, i]
+        rg[j, j] = np.linalg.norm(v)
+        qg[:, j] = v / rg[j, j]
+    assert np.allclose(q, qg, atol=1e-12) and np.allclose(r, rg, atol=1e-12)
