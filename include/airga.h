@@ -311,6 +311,60 @@ AIRGA_API airga_status airga_get_tile_config(airga_ctx ctx, int32_t* rows_per_wa
 AIRGA_API airga_status airga_get_kernel_work(airga_ctx ctx, int32_t count, int64_t* sys_passes,
                                              int64_t* shift_passes);
 
+/* ------------------------------------------------ moment sequence blocks
+ *
+ * The block operations around the shifted solves of AIRGA's moment sequence
+ * (Section 2, Algorithm 1; Algorithm 3 keeps them and changes the solves):
+ * right-hand sides M V_j, orthogonalisation of the n x m solution blocks in
+ * the trace inner product (global Arnoldi), the thin QR of the collected
+ * blocks and the Galerkin projection of eq. (1.4).  All matrices are device
+ * float64, column-major, with n = the pencil's row count and leading
+ * dimensions >= n; the caller owns every array.  Products over the n rows
+ * are fixed-order sums: repeated calls give identical bits. */
+
+/* y_c = (a M + b K) x_c for `count` vectors (as airga_apply_shift, with the
+ * coefficients given): M V_j is a = 1, b = 0 (Algorithm 1's right-hand side
+ * of the moment solves).  Asynchronous.  Errors: EINVAL, ESTATE,
+ * EUNSUPPORTED (count > 65535). */
+AIRGA_API airga_status airga_pencil_apply(airga_ctx ctx, double a, double b, int32_t count,
+                                          const double* x, int64_t ldx, double* y, int64_t ldy);
+
+/* G (device, k x l, column-major, leading dimension k) = A^T B for the
+ * n x k matrix A and the n x l matrix B.  Asynchronous.  Errors: EINVAL,
+ * ESTATE, EUNSUPPORTED (k or l > 256). */
+AIRGA_API airga_status airga_gram(airga_ctx ctx, int32_t k, const double* A, int64_t lda,
+                                  int32_t l, const double* B, int64_t ldb, double* G);
+
+/* Global Arnoldi orthogonalisation (Algorithm 1, the loop over t): each of
+ * the nx blocks X_x = X(:, x m : x m + m) is orthogonalised against the nb
+ * blocks V_t = V(:, t m : t m + m) in the trace inner product <A, B> =
+ * trace(A^T B), in the algorithm's order: for t = 1..nb, gamma_t =
+ * <V_t, X_x>, X_x <- X_x - gamma_t V_t.  X is overwritten; gamma (host,
+ * nx * nb, gamma[x * nb + t]) and fro (host, nx) = ||X_x||_F after the
+ * subtraction are returned; normalize = 1 then divides X_x by fro[x] (a
+ * zero block stays zero), which makes the W_i and V_j of Algorithm 1.
+ * Synchronous.  Errors: EINVAL, ESTATE, EUNSUPPORTED (nb > 16, or nb m or
+ * nx m > 256). */
+AIRGA_API airga_status airga_global_orth(airga_ctx ctx, int32_t m, int32_t nb, const double* V,
+                                         int64_t ldv, int32_t nx, double* X, int64_t ldx,
+                                         int32_t normalize, double* gamma, double* fro);
+
+/* Thin QR of the n x k block W (Algorithm 1's qr of the collected blocks):
+ * W is overwritten by Q with orthonormal columns and R (host, k x k,
+ * column-major, upper triangular with a positive diagonal) satisfies
+ * W_in = Q R.  Computed by a shifted Cholesky QR followed by two Cholesky QR
+ * passes.  Synchronous.  Errors: EINVAL (k > n), ESTATE, EUNSUPPORTED
+ * (k > 64), ENOTSPD (the columns are numerically dependent: W is left
+ * partly transformed). */
+AIRGA_API airga_status airga_block_qr(airga_ctx ctx, int32_t k, double* W, int64_t ldw, double* R);
+
+/* Galerkin projection onto the n x k basis W (eq. (1.4)): mhat, khat (host,
+ * k x k, column-major) = W^T M W and W^T K W; D_hat = alpha mhat + beta
+ * khat for Rayleigh damping.  Synchronous.  Errors: EINVAL, ESTATE,
+ * EUNSUPPORTED (k > 64), ENOMEM. */
+AIRGA_API airga_status airga_project(airga_ctx ctx, int32_t k, const double* W, int64_t ldw,
+                                     double* mhat, double* khat);
+
 #ifdef __cplusplus
 }
 #endif

@@ -114,6 +114,19 @@ _SIGS = [
     ("airga_get_kernel_work", ctypes.c_int, [_P, ctypes.c_int32,
                                              ctypes.POINTER(ctypes.c_int64),
                                              ctypes.POINTER(ctypes.c_int64)]),
+    ("airga_pencil_apply", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                          _P, ctypes.c_int64, _P, ctypes.c_int64]),
+    ("airga_gram", ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_int32, _P,
+                                  ctypes.c_int64, _P]),
+    ("airga_global_orth", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64,
+                                         ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]),
+    ("airga_block_qr", ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_double)]),
+    ("airga_project", ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64,
+                                     ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]),
 ]
 
 EXPORTED = [s[0] for s in _SIGS]
@@ -225,6 +238,82 @@ class Context:
                                        self.n))
         self._leave()
         return y.reshape(x.shape)
+
+    # ------------------------------------------------ moment sequence blocks
+    #
+    # Blocks of k vectors are (k, n) tensors: vector c is row c (the C ABI's
+    # column-major n x k with leading dimension n).
+
+    def _block(self, t: torch.Tensor) -> torch.Tensor:
+        _dev(t, torch.float64, self.device)
+        if t.dim() != 2 or t.shape[1] != self.n:
+            raise ValueError(f"expected a (k, {self.n}) block")
+        return t
+
+    def pencil_apply(self, a: float, b: float, x: torch.Tensor) -> torch.Tensor:
+        """(a M + b K) x for the rows of x (k, n)."""
+        x = self._block(x)
+        y = torch.empty_like(x)
+        self._enter()
+        _check(lib().airga_pencil_apply(self._h, float(a), float(b), x.shape[0], _ptr(x), self.n,
+                                        _ptr(y), self.n))
+        self._leave()
+        return y
+
+    def gram(self, a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+        """(k, l) device tensor of the products a_i . b_j over the n rows."""
+        a, b = self._block(a), self._block(b)
+        g = torch.empty((b.shape[0], a.shape[0]), dtype=torch.float64, device=self.device)
+        self._enter()
+        _check(lib().airga_gram(self._h, a.shape[0], _ptr(a), self.n, b.shape[0], _ptr(b), self.n,
+                                _ptr(g)))
+        self._leave()
+        return g.t()
+
+    def global_orth(self, v: torch.Tensor | None, x: torch.Tensor, m: int,
+                    normalize: bool = False):
+        """Orthogonalise the n x m blocks of x (rows x m .. x m + m - 1) in
+        place against those of v in the trace inner product; returns gamma
+        (nx, nb) and the Frobenius norms (nx,) as numpy arrays."""
+        import numpy as np
+        x = self._block(x)
+        nb = 0 if v is None else self._block(v).shape[0] // m
+        nx = x.shape[0] // m
+        if x.shape[0] != nx * m or (v is not None and v.shape[0] != nb * m):
+            raise ValueError("block rows must be a multiple of m")
+        gam = (ctypes.c_double * max(1, nx * nb))()
+        fro = (ctypes.c_double * max(1, nx))()
+        self._enter()
+        _check(lib().airga_global_orth(self._h, int(m), nb, _ptr(v), self.n, nx, _ptr(x), self.n,
+                                       1 if normalize else 0, gam, fro))
+        self._leave()
+        return (np.array(gam[:nx * nb], dtype=float).reshape(nx, nb),
+                np.array(fro[:nx], dtype=float))
+
+    def block_qr(self, w: torch.Tensor):
+        """Thin QR of the k columns (rows of w): w becomes Q; returns R
+        (k, k) as a numpy array, w_in = R^T Q in the (k, n) layout."""
+        import numpy as np
+        w = self._block(w)
+        k = w.shape[0]
+        r = (ctypes.c_double * max(1, k * k))()
+        self._enter()
+        _check(lib().airga_block_qr(self._h, k, _ptr(w), self.n, r))
+        self._leave()
+        return np.array(r[:k * k], dtype=float).reshape(k, k).T
+
+    def project(self, w: torch.Tensor):
+        """(W^T M W, W^T K W) as numpy arrays for the k columns of w."""
+        import numpy as np
+        w = self._block(w)
+        k = w.shape[0]
+        mh = (ctypes.c_double * max(1, k * k))()
+        kh = (ctypes.c_double * max(1, k * k))()
+        self._enter()
+        _check(lib().airga_project(self._h, k, _ptr(w), self.n, mh, kh))
+        self._leave()
+        return (np.array(mh[:k * k], dtype=float).reshape(k, k).T,
+                np.array(kh[:k * k], dtype=float).reshape(k, k).T)
 
     def shift_diagnostics(self, s_old: float, s_new: float):
         out = (ctypes.c_double * 4)()

@@ -151,6 +151,9 @@ struct airga_ctx_s {
   airga::Pencil pen;
   // Solve workspaces (grow-only).
   airga::DevBuf ws_vec, ws_partial, ws_sys, ws_shift, ws_asm, ws_tmp;
+  // Block operations of the moment sequence: per-block partial sums, and
+  // small results (Gram blocks, coefficients) on their way to the host.
+  airga::DevBuf ws_gram, ws_small;
   void* host_pinned = nullptr;
   size_t host_pinned_bytes = 0;
   airga::KernelTimes times;
@@ -289,6 +292,18 @@ template <typename V>
 __device__ __forceinline__ V sload(const V* p) {
   return *(const __attribute__((address_space(4))) V*)p;
 }
+
+// Makes `dev` the current device for the scope of a C-ABI call.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
 
 // Launch-size helper.
 inline unsigned blocks_for(int64_t work, int per_block) {

@@ -1,0 +1,464 @@
+// Block operations of the moment sequence of AIRGA (Section 2, Algorithms 1
+// and 3): right-hand sides (a M + b K) X, tall-skinny products A^T B over
+// the pencil's n rows, orthogonalisation of n x m blocks in the trace inner
+// product (global Arnoldi), the thin QR of the collected blocks, and the
+// Galerkin projection of eq. (1.4).  Every product over the n rows is a
+// fixed-order sum (per-block partials, then one reduction), so results do not
+// depend on scheduling.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace airga {
+
+__global__ void k_apply_shift(PencilDev pd, double a, double b, const double* __restrict__ x,
+                              int64_t ldx, double* __restrict__ y, int64_t ldy);
+
+// ------------------------------------------------------------ A^T B kernel
+//
+// A block sums kGramRowsPerBlock rows for one 64 x 64 tile of the output
+// (grid.y, grid.z index the tile).  Rows are staged kGramStage at a time in
+// LDS; thread t owns the 4 x 4 outputs (4 (t / 16) + u, 4 (t % 16) + v).
+constexpr int kGT = 64;
+constexpr int kGramStage = 32;
+constexpr int64_t kGramRowsPerBlock = 1024;
+// Widest operand of a product (the partials take (k/64)(l/64) n/128 KiB).
+constexpr int kGramMax = 256;
+
+__global__ void __launch_bounds__(256) k_gram_partial(int64_t n, int32_t k,
+                                                      const double* __restrict__ A, int64_t lda,
+                                                      int32_t l, const double* __restrict__ B,
+                                                      int64_t ldb, double* __restrict__ part) {
+  // +1 column: the staging stores of a wavefront (32 consecutive rows of one
+  // column) fall in distinct banks
+  __shared__ double As[kGramStage][kGT + 1];
+  __shared__ double Bs[kGramStage][kGT + 1];
+  const int t = threadIdx.x;
+  const int ti = t >> 4, tj = t & 15;
+  const int ca0 = blockIdx.y * kGT, cb0 = blockIdx.z * kGT;
+  const int64_t r0 = (int64_t)blockIdx.x * kGramRowsPerBlock;
+  const int64_t r1 = r0 + kGramRowsPerBlock < n ? r0 + kGramRowsPerBlock : n;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int64_t rb = r0; rb < r1; rb += kGramStage) {
+    // element e = t + 256 q of the stage: row e % 32, column e / 32
+#pragma unroll
+    for (int q = 0; q < kGramStage * kGT / 256; ++q) {
+      const int e = t + 256 * q;
+      const int rr = e & (kGramStage - 1), cc = e / kGramStage;
+      const int64_t row = rb + rr;
+      const int ca = ca0 + cc, cb = cb0 + cc;
+      As[rr][cc] = (row < r1 && ca < k) ? A[row + (int64_t)ca * lda] : 0.0;
+      Bs[rr][cc] = (row < r1 && cb < l) ? B[row + (int64_t)cb * ldb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < kGramStage; ++rr) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = As[rr][4 * ti + u];
+        b[u] = Bs[rr][4 * tj + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+  double* out = part + ((int64_t)(blockIdx.y * gridDim.z + blockIdx.z) * gridDim.x + blockIdx.x) *
+                           (kGT * kGT);
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[(4 * ti + u) * kGT + 4 * tj + v] = acc[u][v];
+}
+
+// G[i + j ldg] = sum over the row blocks of the tile partials, in block order.
+__global__ void k_gram_reduce(int32_t k, int32_t l, int nblk, int tiles_l,
+                              const double* __restrict__ part, double* __restrict__ G,
+                              int64_t ldg) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)k * l) return;
+  // consecutive threads take consecutive j: contiguous partial reads
+  const int i = (int)(idx / l), j = (int)(idx % l);
+  const int il = i % kGT, jl = j % kGT;
+  const double* p = part + (int64_t)((i / kGT) * tiles_l + j / kGT) * nblk * (kGT * kGT) +
+                    il * kGT + jl;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += p[(int64_t)b * (kGT * kGT)];
+  G[i + (int64_t)j * ldg] = s;
+}
+
+// G (device, k x l, column-major with leading dimension ldg) = A^T B over n
+// rows.  Partials go to the context's Gram workspace.
+static airga_status gram(airga_ctx ctx, int64_t n, int32_t k, const double* A, int64_t lda,
+                         int32_t l, const double* B, int64_t ldb, double* G, int64_t ldg) {
+  if (k == 0 || l == 0) return AIRGA_OK;
+  const int nblk = (int)((n + kGramRowsPerBlock - 1) / kGramRowsPerBlock);
+  const int tk = (k + kGT - 1) / kGT, tl = (l + kGT - 1) / kGT;
+  if (n == 0) {
+    k_fill_f64<<<blocks_for((int64_t)ldg * l, 256), 256, 0, ctx->stream>>>(G, ldg * l, 0.0);
+    AIRGA_HIP(hipGetLastError());
+    return AIRGA_OK;
+  }
+  AIRGA_TRY(ctx->ws_gram.reserve(sizeof(double) * (size_t)tk * tl * nblk * kGT * kGT));
+  double* part = ctx->ws_gram.as<double>();
+  k_gram_partial<<<dim3((unsigned)nblk, (unsigned)tk, (unsigned)tl), 256, 0, ctx->stream>>>(
+      n, k, A, lda, l, B, ldb, part);
+  AIRGA_HIP(hipGetLastError());
+  k_gram_reduce<<<blocks_for((int64_t)k * l, 256), 256, 0, ctx->stream>>>(k, l, nblk, tl, part, G,
+                                                                         ldg);
+  AIRGA_HIP(hipGetLastError());
+  return AIRGA_OK;
+}
+
+// Host copy of a device k x l result (synchronises the context stream).
+static airga_status to_host(airga_ctx ctx, const double* d, size_t count, double* h) {
+  AIRGA_TRY(ensure_pinned(ctx, sizeof(double) * count));
+  AIRGA_HIP(hipMemcpyAsync(ctx->host_pinned, d, sizeof(double) * count, hipMemcpyDeviceToHost,
+                           ctx->stream));
+  AIRGA_HIP(hipStreamSynchronize(ctx->stream));
+  std::memcpy(h, ctx->host_pinned, sizeof(double) * count);
+  return AIRGA_OK;
+}
+
+// Device copy of a host array, through the pinned area (synchronises first,
+// since the area may still feed an earlier copy).
+static airga_status to_device(airga_ctx ctx, const double* h, size_t count, double* d) {
+  AIRGA_HIP(hipStreamSynchronize(ctx->stream));
+  AIRGA_TRY(ensure_pinned(ctx, sizeof(double) * count));
+  std::memcpy(ctx->host_pinned, h, sizeof(double) * count);
+  AIRGA_HIP(hipMemcpyAsync(d, ctx->host_pinned, sizeof(double) * count, hipMemcpyHostToDevice,
+                           ctx->stream));
+  AIRGA_HIP(hipStreamSynchronize(ctx->stream));
+  return AIRGA_OK;
+}
+
+// ------------------------------------------------- global orthogonalisation
+//
+// For the nx blocks X_x (n x m) and the nb blocks V_t:
+//   X_x <- X_x - sum_t gamma[x][t] V_t,   squared Frobenius norms of X_x.
+// One thread per (row, column c): the nb entries V_t(row, c) stay in
+// registers while the thread walks the blocks X_x.
+constexpr int kOrthMaxBlocks = 16;
+
+__global__ void __launch_bounds__(256) k_orth_update(int64_t n, int32_t m, int32_t nb,
+                                                     const double* __restrict__ V, int64_t ldv,
+                                                     int32_t nx, double* __restrict__ X,
+                                                     int64_t ldx, const double* __restrict__ gam,
+                                                     double* __restrict__ part) {
+  __shared__ double red[4];
+  const int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool in = item < n * m;
+  const int64_t row = in ? item / m : 0;
+  const int c = in ? (int)(item % m) : 0;
+  double v[kOrthMaxBlocks];
+#pragma unroll
+  for (int t = 0; t < kOrthMaxBlocks; ++t)
+    v[t] = (in && t < nb) ? V[row + (int64_t)(t * m + c) * ldv] : 0.0;
+  for (int x = 0; x < nx; ++x) {
+    double s = 0.0;
+    if (in) {
+      double* px = X + row + (int64_t)(x * m + c) * ldx;
+      double xv = *px;
+      const double* g = gam + (int64_t)x * nb;
+#pragma unroll
+      for (int t = 0; t < kOrthMaxBlocks; ++t)
+        if (t < nb) xv = fma(-sload(g + t), v[t], xv);
+      *px = xv;
+      s = xv * xv;
+    }
+    s = wave_total(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(int64_t)x * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+  }
+}
+
+// out[x] = sum over the blocks of part[x][*], in block order.
+__global__ void k_sum_rows(int32_t rows, int nblk, const double* __restrict__ part,
+                           double* __restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= rows) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)x * nblk + b];
+  out[x] = s;
+}
+
+// X_x <- X_x * scale[x] for the nx blocks of m columns.
+__global__ void k_scale_blocks(int64_t n, int32_t m, double* __restrict__ X, int64_t ldx,
+                               const double* __restrict__ scale) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int col = blockIdx.y;
+  if (r >= n) return;
+  X[r + (int64_t)col * ldx] *= sload(scale + col / m);
+}
+
+// ------------------------------------------------------------ thin QR
+//
+// W <- W T for an upper-triangular k x k T (k <= 64): output column j of a
+// row is sum_{i <= j} W(row, i) T(i, j).  One thread per row, 32 output
+// columns at a time, the upper half first: columns j only read W(:, i <= j),
+// so the lower half still finds the entries it needs unchanged.
+constexpr int kQrMax = 64;
+
+__global__ void __launch_bounds__(256) k_right_trmm(int64_t n, int32_t k, double* __restrict__ W,
+                                                    int64_t ldw, const double* __restrict__ T) {
+  __shared__ double Ts[kQrMax * kQrMax];
+  for (int e = threadIdx.x; e < kQrMax * kQrMax; e += blockDim.x) {
+    const int i = e / kQrMax, j = e % kQrMax;  // Ts row-major: row i of T
+    Ts[e] = (i < k && j < k) ? T[i + (int64_t)j * k] : 0.0;
+  }
+  __syncthreads();
+  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  double* w = W + row;
+  for (int j0 = ((k - 1) / 32) * 32; j0 >= 0; j0 -= 32) {
+    double acc[32];
+#pragma unroll
+    for (int jj = 0; jj < 32; ++jj) acc[jj] = 0.0;
+    const int iend = j0 + 32 < k ? j0 + 32 : k;
+    for (int i = 0; i < iend; ++i) {
+      const double wi = w[(int64_t)i * ldw];
+      const double* trow = Ts + i * kQrMax + j0;
+#pragma unroll
+      for (int jj = 0; jj < 32; ++jj) acc[jj] = fma(wi, trow[jj], acc[jj]);
+    }
+#pragma unroll
+    for (int jj = 0; jj < 32; ++jj)
+      if (j0 + jj < k) w[(int64_t)(j0 + jj) * ldw] = acc[jj];
+  }
+}
+
+// Upper Cholesky factor R (R^T R = G) of a k x k column-major G, in place of
+// its upper triangle (the strict lower triangle is zeroed).  False when a
+// pivot is not positive.
+static bool cholesky_upper(int k, double* G) {
+  for (int j = 0; j < k; ++j) {
+    double d = G[j + j * k];
+    for (int p = 0; p < j; ++p) d -= G[p + j * k] * G[p + j * k];
+    if (!(d > 0.0) || !std::isfinite(d)) return false;
+    const double rjj = std::sqrt(d);
+    G[j + j * k] = rjj;
+    for (int i = j + 1; i < k; ++i) {
+      double s = G[j + i * k];
+      for (int p = 0; p < j; ++p) s -= G[p + j * k] * G[p + i * k];
+      G[j + i * k] = s / rjj;
+    }
+    for (int i = j + 1; i < k; ++i) G[i + j * k] = 0.0;
+  }
+  return true;
+}
+
+// Inverse of an upper-triangular k x k R (column-major) by back
+// substitution, column by column.
+static void upper_inverse(int k, const double* R, double* T) {
+  for (int e = 0; e < k * k; ++e) T[e] = 0.0;
+  for (int j = 0; j < k; ++j) {
+    T[j + j * k] = 1.0 / R[j + j * k];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int p = i + 1; p <= j; ++p) s += R[i + p * k] * T[p + j * k];
+      T[i + j * k] = -s / R[i + i * k];
+    }
+  }
+}
+
+}  // namespace airga
+
+using namespace airga;
+
+extern "C" {
+
+airga_status airga_pencil_apply(airga_ctx ctx, double a, double b, int32_t count, const double* x,
+                                int64_t ldx, double* y, int64_t ldy) {
+  AIRGA_TRY(check_pencil(ctx));
+  DeviceGuard g(ctx->device);
+  if (count < 0 || (count > 0 && (!x || !y))) return fail(AIRGA_EINVAL, "bad vectors");
+  if (count > 65535) return fail(AIRGA_EUNSUPPORTED, "more than 65535 vectors");
+  if (ldx < ctx->pen.n || ldy < ctx->pen.n) return fail(AIRGA_EINVAL, "leading dimension < n");
+  if (!std::isfinite(a) || !std::isfinite(b)) return fail(AIRGA_EINVAL, "coefficients must be finite");
+  if (count == 0) return AIRGA_OK;
+  const dim3 grid(blocks_for(ctx->pen.n, 256), (unsigned)count);
+  k_apply_shift<<<grid, 256, 0, ctx->stream>>>(ctx->pen.dev(), a, b, x, ldx, y, ldy);
+  AIRGA_HIP(hipGetLastError());
+  return AIRGA_OK;
+}
+
+airga_status airga_gram(airga_ctx ctx, int32_t k, const double* A, int64_t lda, int32_t l,
+                        const double* B, int64_t ldb, double* G) {
+  AIRGA_TRY(check_pencil(ctx));
+  DeviceGuard g(ctx->device);
+  const int64_t n = ctx->pen.n;
+  if (k < 0 || l < 0) return fail(AIRGA_EINVAL, "negative column count");
+  if ((k > 0 && !A) || (l > 0 && !B) || (k > 0 && l > 0 && !G))
+    return fail(AIRGA_EINVAL, "null matrix");
+  if ((k > 0 && lda < n) || (l > 0 && ldb < n)) return fail(AIRGA_EINVAL, "leading dimension < n");
+  if (k > kGramMax || l > kGramMax) return fail(AIRGA_EUNSUPPORTED, "more than %d columns", kGramMax);
+  return gram(ctx, n, k, A, lda, l, B, ldb, G, k);
+}
+
+airga_status airga_global_orth(airga_ctx ctx, int32_t m, int32_t nb, const double* V, int64_t ldv,
+                               int32_t nx, double* X, int64_t ldx, int32_t normalize,
+                               double* gamma, double* fro) {
+  AIRGA_TRY(check_pencil(ctx));
+  DeviceGuard g(ctx->device);
+  const int64_t n = ctx->pen.n;
+  if (m <= 0 || nb < 0 || nx < 0) return fail(AIRGA_EINVAL, "bad block sizes");
+  if (nb > kOrthMaxBlocks) return fail(AIRGA_EUNSUPPORTED, "more than %d basis blocks", kOrthMaxBlocks);
+  if ((int64_t)nx * m > kGramMax || (int64_t)nb * m > kGramMax)
+    return fail(AIRGA_EUNSUPPORTED, "more than %d columns of blocks", kGramMax);
+  if ((nb > 0 && (!V || ldv < n)) || (nx > 0 && (!X || ldx < n)))
+    return fail(AIRGA_EINVAL, "null block or leading dimension < n");
+  if ((nb > 0 && nx > 0 && !gamma) || (nx > 0 && !fro)) return fail(AIRGA_EINVAL, "null output");
+  if (nx == 0) return AIRGA_OK;
+  const int kv = nb * m, kx = nx * m;
+  // device scratch: G_VX (kv x kx), G_VV (kv x kv), gamma (nx x nb), norms (nx)
+  const size_t scratch = (size_t)kv * kx + (size_t)kv * kv + (size_t)nx * nb + nx;
+  AIRGA_TRY(ctx->ws_small.reserve(sizeof(double) * scratch));
+  double* gvx = ctx->ws_small.as<double>();
+  double* gvv = gvx + (size_t)kv * kx;
+  double* dgam = gvv + (size_t)kv * kv;
+  double* dnrm = dgam + (size_t)nx * nb;
+  std::vector<double> gam((size_t)nx * nb, 0.0);
+  if (nb > 0) {
+    AIRGA_TRY(gram(ctx, n, kv, V, ldv, kx, X, ldx, gvx, kv));
+    AIRGA_TRY(gram(ctx, n, kv, V, ldv, kv, V, ldv, gvv, kv));
+    std::vector<double> h((size_t)kv * kx + (size_t)kv * kv);
+    AIRGA_TRY(to_host(ctx, gvx, h.size(), h.data()));
+    const double* hvx = h.data();
+    const double* hvv = h.data() + (size_t)kv * kx;
+    // trace inner products of the blocks: <V_t, X_x> and <V_t, V_u>
+    auto tvx = [&](int t, int x) {
+      double s = 0.0;
+      for (int c = 0; c < m; ++c) s += hvx[(t * m + c) + (size_t)(x * m + c) * kv];
+      return s;
+    };
+    auto tvv = [&](int t, int u) {
+      double s = 0.0;
+      for (int c = 0; c < m; ++c) s += hvv[(t * m + c) + (size_t)(u * m + c) * kv];
+      return s;
+    };
+    // Algorithm 1's loop over t subtracts gamma_t V_t from X before the next
+    // product, so <V_t, X> there is <V_t, X_0> - sum_{u<t} gamma_u <V_t, V_u>
+    for (int x = 0; x < nx; ++x)
+      for (int t = 0; t < nb; ++t) {
+        double s = tvx(t, x);
+        for (int u = 0; u < t; ++u) s -= gam[(size_t)x * nb + u] * tvv(t, u);
+        gam[(size_t)x * nb + t] = s;
+      }
+    AIRGA_TRY(to_device(ctx, gam.data(), gam.size(), dgam));
+  }
+  const int64_t items = n * m;
+  const unsigned nblk = blocks_for(items, 256);
+  AIRGA_TRY(ctx->ws_gram.reserve(sizeof(double) * (size_t)nx * nblk));
+  double* part = ctx->ws_gram.as<double>();
+  k_orth_update<<<nblk, 256, 0, ctx->stream>>>(n, m, nb, V, ldv, nx, X, ldx, dgam, part);
+  AIRGA_HIP(hipGetLastError());
+  k_sum_rows<<<blocks_for(nx, 256), 256, 0, ctx->stream>>>(nx, (int)nblk, part, dnrm);
+  AIRGA_HIP(hipGetLastError());
+  std::vector<double> nrm(nx);
+  AIRGA_TRY(to_host(ctx, dnrm, nx, nrm.data()));
+  for (int x = 0; x < nx; ++x) {
+    fro[x] = std::sqrt(nrm[x]);
+    for (int t = 0; t < nb; ++t) gamma[(size_t)x * nb + t] = gam[(size_t)x * nb + t];
+  }
+  if (normalize) {
+    for (int x = 0; x < nx; ++x) nrm[x] = fro[x] > 0.0 ? 1.0 / fro[x] : 0.0;
+    AIRGA_TRY(to_device(ctx, nrm.data(), nx, dnrm));
+    k_scale_blocks<<<dim3(blocks_for(n, 256), (unsigned)kx), 256, 0, ctx->stream>>>(n, m, X, ldx,
+                                                                                  dnrm);
+    AIRGA_HIP(hipGetLastError());
+  }
+  return AIRGA_OK;
+}
+
+airga_status airga_block_qr(airga_ctx ctx, int32_t k, double* W, int64_t ldw, double* R) {
+  AIRGA_TRY(check_pencil(ctx));
+  DeviceGuard g(ctx->device);
+  const int64_t n = ctx->pen.n;
+  if (k < 0 || (k > 0 && (!W || !R))) return fail(AIRGA_EINVAL, "bad matrix");
+  if (k > kQrMax) return fail(AIRGA_EUNSUPPORTED, "more than %d columns", kQrMax);
+  if (k > n) return fail(AIRGA_EINVAL, "more columns than rows");
+  if (k > 0 && ldw < n) return fail(AIRGA_EINVAL, "leading dimension < n");
+  if (k == 0) return AIRGA_OK;
+  const size_t kk = (size_t)k * k;
+  AIRGA_TRY(ctx->ws_small.reserve(sizeof(double) * 2 * kk));
+  double* dG = ctx->ws_small.as<double>();
+  double* dT = dG + kk;
+  std::vector<double> G(kk), T(kk), Racc(kk, 0.0), tmp(kk);
+  for (int i = 0; i < k; ++i) Racc[i + (size_t)i * k] = 1.0;
+  // Shifted Cholesky QR followed by Cholesky QR twice (Fukaya, Kannan,
+  // Nakatsukasa, Yamamoto, Yanagisawa, SIAM J. Sci. Comput. 2020): the shift
+  // of the first pass keeps its Cholesky factorisation defined for
+  // condition numbers up to about 1/eps; the two plain passes then restore
+  // orthogonality to working precision.
+  for (int pass = 0; pass < 3; ++pass) {
+    AIRGA_TRY(gram(ctx, n, k, W, ldw, k, W, ldw, dG, k));
+    AIRGA_TRY(to_host(ctx, dG, kk, G.data()));
+    if (pass == 0) {
+      double tr = 0.0;
+      for (int i = 0; i < k; ++i) tr += G[i + (size_t)i * k];
+      const double sh = 11.0 * ((double)n * k + (double)k * (k + 1)) * 0x1p-53 * tr;
+      for (int i = 0; i < k; ++i) G[i + (size_t)i * k] += sh;
+    }
+    if (!cholesky_upper(k, G.data()))
+      return fail(AIRGA_ENOTSPD, "block QR: the Gram matrix is not positive definite (pass %d): "
+                                 "the columns are numerically dependent", pass);
+    upper_inverse(k, G.data(), T.data());
+    AIRGA_TRY(to_device(ctx, T.data(), kk, dT));
+    k_right_trmm<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, k, W, ldw, dT);
+    AIRGA_HIP(hipGetLastError());
+    // R <- R_pass R (both upper triangular)
+    for (int j = 0; j < k; ++j)
+      for (int i = 0; i <= j; ++i) {
+        double s = 0.0;
+        for (int p = i; p <= j; ++p) s += G[i + (size_t)p * k] * Racc[p + (size_t)j * k];
+        tmp[i + (size_t)j * k] = s;
+      }
+    for (int j = 0; j < k; ++j)
+      for (int i = 0; i < k; ++i) Racc[i + (size_t)j * k] = i <= j ? tmp[i + (size_t)j * k] : 0.0;
+  }
+  AIRGA_HIP(hipStreamSynchronize(ctx->stream));
+  std::memcpy(R, Racc.data(), sizeof(double) * kk);
+  return AIRGA_OK;
+}
+
+airga_status airga_project(airga_ctx ctx, int32_t k, const double* W, int64_t ldw, double* mhat,
+                           double* khat) {
+  AIRGA_TRY(check_pencil(ctx));
+  DeviceGuard g(ctx->device);
+  const int64_t n = ctx->pen.n;
+  if (k < 0 || (k > 0 && (!W || !mhat || !khat))) return fail(AIRGA_EINVAL, "bad matrix");
+  if (k > kQrMax) return fail(AIRGA_EUNSUPPORTED, "more than %d columns", kQrMax);
+  if (k > 0 && ldw < n) return fail(AIRGA_EINVAL, "leading dimension < n");
+  if (k == 0) return AIRGA_OK;
+  const size_t kk = (size_t)k * k;
+  AIRGA_TRY(ctx->ws_tmp.reserve(sizeof(double) * (size_t)n * k));
+  AIRGA_TRY(ctx->ws_small.reserve(sizeof(double) * 2 * kk));
+  double* Y = ctx->ws_tmp.as<double>();
+  double* dG = ctx->ws_small.as<double>();
+  const dim3 grid(blocks_for(n, 256), (unsigned)k);
+  // M_hat = W^T (M W), K_hat = W^T (K W)   (eq. (1.4))
+  k_apply_shift<<<grid, 256, 0, ctx->stream>>>(ctx->pen.dev(), 1.0, 0.0, W, ldw, Y, n);
+  AIRGA_HIP(hipGetLastError());
+  AIRGA_TRY(gram(ctx, n, k, W, ldw, k, Y, n, dG, k));
+  k_apply_shift<<<grid, 256, 0, ctx->stream>>>(ctx->pen.dev(), 0.0, 1.0, W, ldw, Y, n);
+  AIRGA_HIP(hipGetLastError());
+  AIRGA_TRY(gram(ctx, n, k, W, ldw, k, Y, n, dG + kk, k));
+  std::vector<double> h(2 * kk);
+  AIRGA_TRY(to_host(ctx, dG, 2 * kk, h.data()));
+  std::memcpy(mhat, h.data(), sizeof(double) * kk);
+  std::memcpy(khat, h.data() + kk, sizeof(double) * kk);
+  return AIRGA_OK;
+}
+
+}  // extern "C"

@@ -400,16 +400,7 @@ __global__ void k_apply_shift(PencilDev pd, double a, double b, const double* __
 }
 
 // RAII: make the context's device current for the duration of an API call.
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
+
 
 static airga_status set_pencil_impl(airga_ctx ctx, int32_t n, int64_t nnz, const int32_t* row_ptr,
                                     const int32_t* col_idx, const double* m_val,
