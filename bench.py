@@ -36,6 +36,7 @@ from synthetic import beam  # noqa: E402
 
 METRIC = "PCG solves/s @1e-8 rel err, batched-mixed vs plain FP64; SPAI build/update ms"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # MI355X dense float64 (vector and matrix)
 ERR_TOL = 1e-8
 
 # Workloads (seeded, synthetic).  "s" = the surrogate with every EI scaled by
@@ -175,6 +176,70 @@ def summarize_trace(args):
         with open(args.out, "w") as fh:
             fh.write(text)
     print(text)
+
+
+def measure_moments(ctx, stream, dev, n, m, nblocks, nb=4, reps=5):
+    """The block operations of one pass of the moment sequence (Algorithm 1)
+    at the workload's size, outside the timed step: the right-hand side
+    M V_j, the orthogonalisation of the nblocks solution blocks (n x m)
+    against nb earlier basis blocks with normalisation, the thin QR of the
+    nblocks * m collected columns, and the projection onto them.  Seeded
+    random blocks stand in for the solutions (timing does not depend on the
+    values).  Also the A^T B kernel alone for 64 x 64 columns, timed with
+    HIP events on the context stream."""
+    import torch
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    k = nblocks * m
+    with torch.cuda.stream(stream):
+        v = torch.randn((nb * m, n), dtype=torch.float64, device=dev, generator=gen)
+        ctx.block_qr(v)                       # orthonormal columns
+        ctx.global_orth(None, v, m, normalize=True)   # blocks of unit Frobenius norm
+        x0 = torch.randn((k, n), dtype=torch.float64, device=dev, generator=gen)
+        y = torch.randn((k, n), dtype=torch.float64, device=dev, generator=gen)
+        torch.cuda.synchronize()
+
+        def wall(fn, setup):
+            ts = []
+            for _ in range(reps):
+                arg = setup()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fn(arg)
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t0) * 1e3)
+            return statistics.median(ts)
+
+        def events(fn):
+            ts = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            return statistics.median(ts)
+
+        t_rhs = events(lambda: ctx.pencil_apply(1.0, 0.0, v[:m]))
+        t_orth = wall(lambda xx: ctx.global_orth(v, xx, m, normalize=True), lambda: x0.clone())
+        xo = x0.clone()
+        ctx.global_orth(v, xo, m, normalize=True)
+        t_qr = wall(lambda w: ctx.block_qr(w), lambda: xo.clone())
+        w = xo.clone()
+        ctx.block_qr(w)
+        t_proj = wall(lambda w_: ctx.project(w_), lambda: w)
+        t_gram = events(lambda: ctx.gram(w, y))
+    gb = 2 * k * n * 8 / 1e9
+    tf = 2.0 * k * k * n / 1e12
+    return {"n": n, "m": m, "blocks": nblocks, "basis_blocks": nb,
+            "rhs_apply_ms": round(t_rhs, 4), "orth_ms": round(t_orth, 3),
+            "qr_ms": round(t_qr, 3), "project_ms": round(t_proj, 3),
+            "gram": {"columns": [k, k], "ms": round(t_gram, 4),
+                     "gbs": round(gb / (t_gram * 1e-3), 1),
+                     "tflops": round(tf / (t_gram * 1e-3), 2),
+                     "frac_hbm": round(gb / (t_gram * 1e-3) / HBM_PEAK_GBS, 4),
+                     "frac_fp64": round(tf / (t_gram * 1e-3) / FP64_PEAK_TFLOPS, 4)}}
 
 
 def main():
@@ -425,6 +490,8 @@ def main():
                              "iters_median": statistics.median(s["iters"] for s in pst)}
         out["speedup_pcg_vs_plain_fp64"] = round(out["batched_mixed_pcg_solves_per_s"] /
                                                  max(out["plain_fp64"]["pcg_solves_per_s"], 1e-30), 2)
+    log("[bench] moment-sequence block operations")
+    out["moments"] = measure_moments(ctx, stream, dev, n, m, S)
     if cpu is not None:
         out["cpu_baseline"] = {
             "value": round(2 * B / cpu["seconds"], 3), "unit": "solves/s", "cores": 1,

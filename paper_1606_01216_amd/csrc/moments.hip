@@ -13,16 +13,82 @@
 
 namespace airga {
 
-__global__ void k_apply_shift(PencilDev pd, double a, double b, const double* __restrict__ x,
-                              int64_t ldx, double* __restrict__ y, int64_t ldy);
+// ------------------------------------------------------- pencil products
+//
+// Y1 = (a1 M + b1 K) X and, when Y2 is given, Y2 = (a2 M + b2 K) X for the
+// count columns of X.  One thread per row keeps the row's entries in
+// registers and walks the columns, so the pencil is read once for all of
+// them (entries past a slice's width act as padding: the row itself, value
+// 0).  Each row sums its entries in stored order, as the single-vector
+// product does.
+template <int WMAX>
+__global__ void __launch_bounds__(256) k_spmm_pencil(PencilDev pd, int32_t count,
+                                                     const double* __restrict__ X, int64_t ldx,
+                                                     double a1, double b1, double* __restrict__ Y1,
+                                                     int64_t ldy1, double a2, double b2,
+                                                     double* __restrict__ Y2, int64_t ldy2) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= pd.n) return;
+  const int64_t s = r / kSlice;
+  const int32_t base = pd.slice_ptr[s] + (int32_t)(r % kSlice);
+  const int w = (pd.slice_ptr[s + 1] - pd.slice_ptr[s]) / kSlice;
+  int32_t col[WMAX];
+  double mv[WMAX], kv[WMAX];
+#pragma unroll
+  for (int k = 0; k < WMAX; ++k) {
+    const bool in = k < w;
+    const int32_t idx = base + k * kSlice;
+    col[k] = in ? pd.col[idx] : (int32_t)r;
+    mv[k] = in ? pd.m64[idx] : 0.0;
+    kv[k] = in ? pd.k64[idx] : 0.0;
+  }
+  for (int c = 0; c < count; ++c) {
+    const double* __restrict__ x = X + (int64_t)c * ldx;
+    double am = 0, ak = 0;
+#pragma unroll
+    for (int k = 0; k < WMAX; ++k) {
+      const double xc = x[col[k]];
+      am = fma(mv[k], xc, am);
+      ak = fma(kv[k], xc, ak);
+    }
+    Y1[(int64_t)c * ldy1 + r] = fma(a1, am, b1 * ak);
+    if (Y2) Y2[(int64_t)c * ldy2 + r] = fma(a2, am, b2 * ak);
+  }
+}
+
+static void spmm_pencil(airga_ctx ctx, int32_t count, const double* X, int64_t ldx, double a1,
+                        double b1, double* Y1, int64_t ldy1, double a2, double b2, double* Y2,
+                        int64_t ldy2) {
+  const Pencil& pen = ctx->pen;
+  const unsigned grid = blocks_for(pen.n, 256);
+  const PencilDev pd = pen.dev();
+  if (pen.max_len <= 6)
+    k_spmm_pencil<6><<<grid, 256, 0, ctx->stream>>>(pd, count, X, ldx, a1, b1, Y1, ldy1, a2, b2,
+                                                    Y2, ldy2);
+  else if (pen.max_len <= 8)
+    k_spmm_pencil<8><<<grid, 256, 0, ctx->stream>>>(pd, count, X, ldx, a1, b1, Y1, ldy1, a2, b2,
+                                                    Y2, ldy2);
+  else
+    k_spmm_pencil<kMaxRow><<<grid, 256, 0, ctx->stream>>>(pd, count, X, ldx, a1, b1, Y1, ldy1, a2,
+                                                          b2, Y2, ldy2);
+}
 
 // ------------------------------------------------------------ A^T B kernel
 //
 // A block sums kGramRowsPerBlock rows for one 64 x 64 tile of the output
-// (grid.y, grid.z index the tile).  Rows are staged kGramStage at a time in
-// LDS; thread t owns the 4 x 4 outputs (4 (t / 16) + u, 4 (t % 16) + v).
+// (grid.y, grid.z index the tile), kGramStage rows at a time staged in LDS.
+// The products run on the matrix cores: wavefront w owns output rows
+// 16 w .. 16 w + 15 and all four 16-column tiles, and each
+// v_mfma_f64_16x16x4f64 adds the contribution of 4 staged rows to one
+// 16 x 16 tile (operand A = the 16 x 4 slice of A^T, lane i + 16 q holding
+// A(row q, column i); operand B = the 4 x 16 slice of B, lane j + 16 q
+// holding B(row q, column j); element v of the accumulator holds output
+// (lane / 16 + 4 v, lane % 16)).  Block b takes the stages b, b + nblk, ...:
+// the blocks running together read consecutive stages.  The next stage's
+// loads are issued into registers before the current one is multiplied, so
+// they are in flight during the matrix-core work.
 constexpr int kGT = 64;
-constexpr int kGramStage = 32;
+constexpr int kGramStage = 16;
 constexpr int64_t kGramRowsPerBlock = 1024;
 // Widest operand of a product (the partials take (k/64)(l/64) n/128 KiB).
 constexpr int kGramMax = 256;
@@ -31,69 +97,92 @@ __global__ void __launch_bounds__(256) k_gram_partial(int64_t n, int32_t k,
                                                       const double* __restrict__ A, int64_t lda,
                                                       int32_t l, const double* __restrict__ B,
                                                       int64_t ldb, double* __restrict__ part) {
-  // +1 column: the staging stores of a wavefront (32 consecutive rows of one
+  // +1 column: the staging stores of a wavefront (consecutive rows of one
   // column) fall in distinct banks
   __shared__ double As[kGramStage][kGT + 1];
   __shared__ double Bs[kGramStage][kGT + 1];
+  typedef double d4 __attribute__((ext_vector_type(4)));
   const int t = threadIdx.x;
-  const int ti = t >> 4, tj = t & 15;
+  const int wv = t >> 6, lane = t & 63;
+  const int li = lane & 15, lq = lane >> 4;
   const int ca0 = blockIdx.y * kGT, cb0 = blockIdx.z * kGT;
-  const int64_t r0 = (int64_t)blockIdx.x * kGramRowsPerBlock;
-  const int64_t r1 = r0 + kGramRowsPerBlock < n ? r0 + kGramRowsPerBlock : n;
-  double acc[4][4];
+  d4 acc[4];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int jt = 0; jt < 4; ++jt) acc[jt] = d4{0.0, 0.0, 0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * kGramStage;
+  // element e = t + 256 q of a stage: row e % kGramStage, column e / kGramStage
+  constexpr int Q = kGramStage * kGT / 256;
+  double pa[Q], pb[Q];
+  auto fetch = [&](int64_t rb) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-  for (int64_t rb = r0; rb < r1; rb += kGramStage) {
-    // element e = t + 256 q of the stage: row e % 32, column e / 32
-#pragma unroll
-    for (int q = 0; q < kGramStage * kGT / 256; ++q) {
+    for (int q = 0; q < Q; ++q) {
       const int e = t + 256 * q;
-      const int rr = e & (kGramStage - 1), cc = e / kGramStage;
-      const int64_t row = rb + rr;
-      const int ca = ca0 + cc, cb = cb0 + cc;
-      As[rr][cc] = (row < r1 && ca < k) ? A[row + (int64_t)ca * lda] : 0.0;
-      Bs[rr][cc] = (row < r1 && cb < l) ? B[row + (int64_t)cb * ldb] : 0.0;
+      const int64_t row = rb + (e & (kGramStage - 1));
+      const int ca = ca0 + e / kGramStage, cb = cb0 + e / kGramStage;
+      pa[q] = (row < n && ca < k) ? A[row + (int64_t)ca * lda] : 0.0;
+      pb[q] = (row < n && cb < l) ? B[row + (int64_t)cb * ldb] : 0.0;
+    }
+  };
+  int64_t rb = (int64_t)blockIdx.x * kGramStage;
+  if (rb < n) fetch(rb);
+  for (; rb < n; rb += stride) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = t + 256 * q;
+      As[e & (kGramStage - 1)][e / kGramStage] = pa[q];
+      Bs[e & (kGramStage - 1)][e / kGramStage] = pb[q];
     }
     __syncthreads();
-#pragma unroll 4
-    for (int rr = 0; rr < kGramStage; ++rr) {
-      double a[4], b[4];
+    if (rb + stride < n) fetch(rb + stride);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = As[rr][4 * ti + u];
-        b[u] = Bs[rr][4 * tj + u];
+    for (int s4 = 0; s4 < kGramStage; s4 += 4) {
+      const double a = As[s4 + lq][16 * wv + li];
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt) {
+        const double b = Bs[s4 + lq][16 * jt + li];
+        acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[jt], 0, 0, 0);
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
     }
     __syncthreads();
   }
   double* out = part + ((int64_t)(blockIdx.y * gridDim.z + blockIdx.z) * gridDim.x + blockIdx.x) *
                            (kGT * kGT);
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int jt = 0; jt < 4; ++jt)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) out[(4 * ti + u) * kGT + 4 * tj + v] = acc[u][v];
+    for (int v = 0; v < 4; ++v) out[(16 * wv + lq + 4 * v) * kGT + 16 * jt + li] = acc[jt][v];
 }
 
-// G[i + j ldg] = sum over the row blocks of the tile partials, in block order.
-__global__ void k_gram_reduce(int32_t k, int32_t l, int nblk, int tiles_l,
-                              const double* __restrict__ part, double* __restrict__ G,
-                              int64_t ldg) {
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)k * l) return;
-  // consecutive threads take consecutive j: contiguous partial reads
-  const int i = (int)(idx / l), j = (int)(idx % l);
-  const int il = i % kGT, jl = j % kGT;
+// G[i + j ldg] = sum over the row blocks of the tile partials, in a fixed
+// order: a block takes 16 outputs (consecutive j, so the partial reads of a
+// step are contiguous) and 16 splits of the row blocks; split s sums its
+// contiguous range, then the 16 split sums are added in split order.
+constexpr int kRedOut = 16, kRedSplit = 16;
+
+__global__ void __launch_bounds__(256) k_gram_reduce(int32_t k, int32_t l, int nblk, int tiles_l,
+                                                     const double* __restrict__ part,
+                                                     double* __restrict__ G, int64_t ldg) {
+  __shared__ double red[kRedSplit][kRedOut];
+  const int to = threadIdx.x % kRedOut, sp = threadIdx.x / kRedOut;
+  const int64_t idx = (int64_t)blockIdx.x * kRedOut + to;
+  const bool in = idx < (int64_t)k * l;
+  const int i = in ? (int)(idx / l) : 0, j = in ? (int)(idx % l) : 0;
   const double* p = part + (int64_t)((i / kGT) * tiles_l + j / kGT) * nblk * (kGT * kGT) +
-                    il * kGT + jl;
+                    (i % kGT) * kGT + j % kGT;
+  const int chunk = (nblk + kRedSplit - 1) / kRedSplit;
+  const int b0 = sp * chunk, b1 = b0 + chunk < nblk ? b0 + chunk : nblk;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += p[(int64_t)b * (kGT * kGT)];
-  G[i + (int64_t)j * ldg] = s;
+  if (in) {
+#pragma unroll 8
+    for (int b = b0; b < b1; ++b) s += p[(int64_t)b * (kGT * kGT)];
+  }
+  red[sp][to] = s;
+  __syncthreads();
+  if (sp == 0 && in) {
+    double t = 0.0;
+    for (int q = 0; q < kRedSplit; ++q) t += red[q][to];
+    G[i + (int64_t)j * ldg] = t;
+  }
 }
 
 // G (device, k x l, column-major with leading dimension ldg) = A^T B over n
@@ -113,8 +202,8 @@ static airga_status gram(airga_ctx ctx, int64_t n, int32_t k, const double* A, i
   k_gram_partial<<<dim3((unsigned)nblk, (unsigned)tk, (unsigned)tl), 256, 0, ctx->stream>>>(
       n, k, A, lda, l, B, ldb, part);
   AIRGA_HIP(hipGetLastError());
-  k_gram_reduce<<<blocks_for((int64_t)k * l, 256), 256, 0, ctx->stream>>>(k, l, nblk, tl, part, G,
-                                                                         ldg);
+  k_gram_reduce<<<blocks_for((int64_t)k * l, kRedOut), 256, 0, ctx->stream>>>(k, l, nblk, tl, part,
+                                                                             G, ldg);
   AIRGA_HIP(hipGetLastError());
   return AIRGA_OK;
 }
@@ -149,12 +238,15 @@ static airga_status to_device(airga_ctx ctx, const double* h, size_t count, doub
 // registers while the thread walks the blocks X_x.
 constexpr int kOrthMaxBlocks = 16;
 
+// part[x * (4 gridDim.x) + wave]: one partial per wavefront and block, so the
+// walk over the blocks needs no barrier.
 __global__ void __launch_bounds__(256) k_orth_update(int64_t n, int32_t m, int32_t nb,
                                                      const double* __restrict__ V, int64_t ldv,
                                                      int32_t nx, double* __restrict__ X,
                                                      int64_t ldx, const double* __restrict__ gam,
                                                      double* __restrict__ part) {
-  __shared__ double red[4];
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
   const int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const bool in = item < n * m;
   const int64_t row = in ? item / m : 0;
@@ -176,21 +268,26 @@ __global__ void __launch_bounds__(256) k_orth_update(int64_t n, int32_t m, int32
       s = xv * xv;
     }
     s = wave_total(s);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) part[(int64_t)x * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-    __syncthreads();
+    if ((threadIdx.x & 63) == 0) part[(int64_t)x * nwaves + wave] = s;
   }
 }
 
-// out[x] = sum over the blocks of part[x][*], in block order.
-__global__ void k_sum_rows(int32_t rows, int nblk, const double* __restrict__ part,
-                           double* __restrict__ out) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= rows) return;
+// out[x] = sum of part[x][0 .. np): one block per row x; thread t sums the
+// entries t, t + 256, ... in order, then thread 0 adds the 256 sums in order.
+__global__ void __launch_bounds__(256) k_sum_rows(int64_t np, const double* __restrict__ part,
+                                                  double* __restrict__ out) {
+  __shared__ double red[256];
+  const double* p = part + (int64_t)blockIdx.x * np;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)x * nblk + b];
-  out[x] = s;
+#pragma unroll 8
+  for (int64_t b = threadIdx.x; b < np; b += 256) s += p[b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < 256; ++q) t += red[q];
+    out[blockIdx.x] = t;
+  }
 }
 
 // X_x <- X_x * scale[x] for the nx blocks of m columns.
@@ -287,8 +384,7 @@ airga_status airga_pencil_apply(airga_ctx ctx, double a, double b, int32_t count
   if (ldx < ctx->pen.n || ldy < ctx->pen.n) return fail(AIRGA_EINVAL, "leading dimension < n");
   if (!std::isfinite(a) || !std::isfinite(b)) return fail(AIRGA_EINVAL, "coefficients must be finite");
   if (count == 0) return AIRGA_OK;
-  const dim3 grid(blocks_for(ctx->pen.n, 256), (unsigned)count);
-  k_apply_shift<<<grid, 256, 0, ctx->stream>>>(ctx->pen.dev(), a, b, x, ldx, y, ldy);
+  spmm_pencil(ctx, count, x, ldx, a, b, y, ldy, 0.0, 0.0, nullptr, 0);
   AIRGA_HIP(hipGetLastError());
   return AIRGA_OK;
 }
@@ -359,11 +455,11 @@ airga_status airga_global_orth(airga_ctx ctx, int32_t m, int32_t nb, const doubl
   }
   const int64_t items = n * m;
   const unsigned nblk = blocks_for(items, 256);
-  AIRGA_TRY(ctx->ws_gram.reserve(sizeof(double) * (size_t)nx * nblk));
+  AIRGA_TRY(ctx->ws_gram.reserve(sizeof(double) * (size_t)nx * nblk * 4));
   double* part = ctx->ws_gram.as<double>();
   k_orth_update<<<nblk, 256, 0, ctx->stream>>>(n, m, nb, V, ldv, nx, X, ldx, dgam, part);
   AIRGA_HIP(hipGetLastError());
-  k_sum_rows<<<blocks_for(nx, 256), 256, 0, ctx->stream>>>(nx, (int)nblk, part, dnrm);
+  k_sum_rows<<<(unsigned)nx, 256, 0, ctx->stream>>>((int64_t)nblk * 4, part, dnrm);
   AIRGA_HIP(hipGetLastError());
   std::vector<double> nrm(nx);
   AIRGA_TRY(to_host(ctx, dnrm, nx, nrm.data()));
@@ -442,18 +538,15 @@ airga_status airga_project(airga_ctx ctx, int32_t k, const double* W, int64_t ld
   if (k > 0 && ldw < n) return fail(AIRGA_EINVAL, "leading dimension < n");
   if (k == 0) return AIRGA_OK;
   const size_t kk = (size_t)k * k;
-  AIRGA_TRY(ctx->ws_tmp.reserve(sizeof(double) * (size_t)n * k));
+  AIRGA_TRY(ctx->ws_tmp.reserve(sizeof(double) * (size_t)n * 2 * k));
   AIRGA_TRY(ctx->ws_small.reserve(sizeof(double) * 2 * kk));
   double* Y = ctx->ws_tmp.as<double>();
   double* dG = ctx->ws_small.as<double>();
-  const dim3 grid(blocks_for(n, 256), (unsigned)k);
-  // M_hat = W^T (M W), K_hat = W^T (K W)   (eq. (1.4))
-  k_apply_shift<<<grid, 256, 0, ctx->stream>>>(ctx->pen.dev(), 1.0, 0.0, W, ldw, Y, n);
+  // [M W | K W] in one pass over the pencil, then W^T [M W | K W] =
+  // [M_hat | K_hat]   (eq. (1.4))
+  spmm_pencil(ctx, k, W, ldw, 1.0, 0.0, Y, n, 0.0, 1.0, Y + (size_t)n * k, n);
   AIRGA_HIP(hipGetLastError());
-  AIRGA_TRY(gram(ctx, n, k, W, ldw, k, Y, n, dG, k));
-  k_apply_shift<<<grid, 256, 0, ctx->stream>>>(ctx->pen.dev(), 0.0, 1.0, W, ldw, Y, n);
-  AIRGA_HIP(hipGetLastError());
-  AIRGA_TRY(gram(ctx, n, k, W, ldw, k, Y, n, dG + kk, k));
+  AIRGA_TRY(gram(ctx, n, k, W, ldw, 2 * k, Y, n, dG, k));
   std::vector<double> h(2 * kk);
   AIRGA_TRY(to_host(ctx, dG, 2 * kk, h.data()));
   std::memcpy(mhat, h.data(), sizeof(double) * kk);

@@ -105,3 +105,40 @@ def test_c5_surrogate_full_size_sampled(ctx):
         Xk = X[k].cpu().numpy()
         for c in range(f.shape[0]):
             assert rel_err(Xk[c], ref[c]) < 1e-8, (k, c)
+
+
+def test_moment_blocks_full_size(ctx):
+    """The moment-sequence block operations at n = 1e6 in the sizes the
+    benchmark times: the 16 blocks (m = 4) of one pass orthogonalised
+    against 4 earlier blocks, the thin QR of the 64 collected columns and
+    the projection onto them.  Checked against the oracle on the full
+    vectors (numpy)."""
+    from oracle import moments
+    pen, f, shifts, rng = beam.make_workload("c3", surrogate=True)
+    set_pencil(ctx, pen)
+    n, m, nb, nx = pen.n, 4, 4, 16
+    g = np.random.default_rng(21)
+    q, _ = np.linalg.qr(g.standard_normal((n * m, nb)))
+    vs = [q[:, t].reshape(n, m) for t in range(nb)]
+    xs = [g.standard_normal((n, m)) for _ in range(nx)]
+    x = to_dev(np.hstack(xs).T, torch.float64)
+    gam, fro = ctx.global_orth(to_dev(np.hstack(vs).T, torch.float64), x, m, normalize=True)
+    for i in (0, 7, 15):
+        rx, rg, rf = moments.global_orth(vs, xs[i])
+        assert np.all(np.abs(gam[i] - rg) <= 1e-12 * np.abs(rg).max())
+        assert abs(fro[i] - rf) <= 1e-12 * rf
+    w = x.clone()
+    r = ctx.block_qr(w)
+    wq = w.cpu().numpy().T
+    assert np.abs(wq.T @ wq - np.eye(nx * m)).max() < 1e-12
+    w0 = x.cpu().numpy().T
+    assert rel_err(wq @ r, w0) < 1e-13
+    mh, kh = ctx.project(w)
+    ms = pencil.csr(n, pen.row_ptr, pen.col_idx, pen.m_val)
+    ks = pencil.csr(n, pen.row_ptr, pen.col_idx, pen.k_val)
+    rm, _, rk, _, _ = moments.project(ms, ks, pen.alpha, pen.beta, np.zeros((n, 1)),
+                                      np.zeros((1, n)), wq)
+    assert np.abs(mh - rm).max() < 1e-12 * np.abs(rm).max()
+    assert np.abs(kh - rk).max() < 1e-12 * np.abs(rk).max()
+    y = ctx.pencil_apply(1.0, 0.0, x[:m]).cpu().numpy().T
+    assert rel_err(y, moments.pencil_apply(ms, ks, 1.0, 0.0, w0[:, :m])) < 1e-14
