@@ -42,6 +42,7 @@ __global__ void __launch_bounds__(256) k_spmm_pencil(PencilDev pd, int32_t count
     mv[k] = in ? pd.m64[idx] : 0.0;
     kv[k] = in ? pd.k64[idx] : 0.0;
   }
+#pragma unroll 4
   for (int c = 0; c < count; ++c) {
     const double* __restrict__ x = X + (int64_t)c * ldx;
     double am = 0, ak = 0;
@@ -304,7 +305,9 @@ __global__ void k_scale_blocks(int64_t n, int32_t m, double* __restrict__ X, int
 // W <- W T for an upper-triangular k x k T (k <= 64): output column j of a
 // row is sum_{i <= j} W(row, i) T(i, j).  One thread per row, 32 output
 // columns at a time, the upper half first: columns j only read W(:, i <= j),
-// so the lower half still finds the entries it needs unchanged.
+// so the lower half still finds the entries it needs unchanged.  The row's
+// entries are loaded 8 at a time, the next 8 while the current ones are
+// multiplied.
 constexpr int kQrMax = 64;
 
 __global__ void __launch_bounds__(256) k_right_trmm(int64_t n, int32_t k, double* __restrict__ W,
@@ -323,11 +326,24 @@ __global__ void __launch_bounds__(256) k_right_trmm(int64_t n, int32_t k, double
 #pragma unroll
     for (int jj = 0; jj < 32; ++jj) acc[jj] = 0.0;
     const int iend = j0 + 32 < k ? j0 + 32 : k;
-    for (int i = 0; i < iend; ++i) {
-      const double wi = w[(int64_t)i * ldw];
-      const double* trow = Ts + i * kQrMax + j0;
+    double wc[8], wn[8];
 #pragma unroll
-      for (int jj = 0; jj < 32; ++jj) acc[jj] = fma(wi, trow[jj], acc[jj]);
+    for (int u = 0; u < 8; ++u) wc[u] = u < iend ? w[(int64_t)u * ldw] : 0.0;
+    for (int i0 = 0; i0 < iend; i0 += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + 8 + u;
+        wn[u] = i < iend ? w[(int64_t)i * ldw] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        // rows i >= k of Ts are zero, so a chunk past iend adds nothing
+        const double* trow = Ts + (i0 + u) * kQrMax + j0;
+#pragma unroll
+        for (int jj = 0; jj < 32; ++jj) acc[jj] = fma(wc[u], trow[jj], acc[jj]);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) wc[u] = wn[u];
     }
 #pragma unroll
     for (int jj = 0; jj < 32; ++jj)
