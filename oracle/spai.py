@@ -33,6 +33,18 @@ matrices are scaled by the *new* diagonal, Khat_x = S_new K_x S_new, and the
 factor is mapped back as Q = S_new Qhat S_new^{-1}, so that K_new Q ~ K_old.
 The preconditioner after updates is the chain Q_z ... Q_2 P_1, applied factor
 by factor and never multiplied out (Section 3.2, last paragraph).
+
+Minimal-residual mode (mr_iters > 0): the columns follow the loops of
+Algorithms 2 and 4 as printed instead of the exact solve.  Starting from
+p_j = alpha e_j (q_j = alpha e_j), r = t - K p_j with t = e_j (k_old_j), and
+while ||r|| > tol ||t||:  d = P r,  w = K d,  a = (r, w) / (w, w),
+p_j += a d,  r -= a w.  As printed, P (Q) stays alpha I inside the column
+loop, so d = alpha r; d is dropped to the pattern J of column j, which keeps
+p_j on the pattern of K(s) (the structural reading above).  r then lives on
+the rows I, so the loop runs on the column's local block exactly.  The loop is
+capped at mr_iters steps, because on a fixed pattern the residual may never
+reach tol.  The build's alpha is trace(Khat) / trace(Khat Khat^T) of the
+matrix whose inverse is sought (Algorithm 2, first line).
 """
 from __future__ import annotations
 
@@ -53,6 +65,9 @@ class Factor:
     alpha: float              # initial scaling (build: trace formula of Alg. 2; update: Alg. 4)
     cols: np.ndarray          # columns actually computed
     pattern: tuple            # (n, row_ptr, col_idx)
+    iters: np.ndarray = None  # minimal-residual mode: steps per column
+    margin: np.ndarray = None  # minimal-residual mode: closest approach of
+                               # ||r|| / (tol ||t||) to 1 over the column's tests
 
     def matrix(self) -> sp.csr_matrix:
         n, rp, ci = self.pattern
@@ -106,11 +121,40 @@ def _scaled_values(a_val, rows, cols, s_row, s_col):
     return a_val * s_row[rows] * s_col[cols]
 
 
-def spai_build(a: sp.csr_matrix, *, equilibrate=True, symmetrize=True, cols=None) -> Factor:
+def _mr_column(blk, rhs, jpos, p, alpha, tol, mr_iters):
+    """The minimal-residual loop of Algorithms 2 / 4 on one column's local
+    block: blk = Khat(I, J), rhs = t(I), jpos = positions of J in I, p the
+    start on J.  Returns (p, ||r||, steps, margin)."""
+    r = rhs - blk @ p
+    thr = tol * np.linalg.norm(rhs)
+    margin = np.inf
+    it = 0
+    while True:
+        nr = np.linalg.norm(r)
+        if thr > 0:
+            margin = min(margin, abs(nr / thr - 1.0))
+        if not (nr > thr) or it >= mr_iters:
+            break
+        d = alpha * r[jpos]          # d = P r with P = alpha I, on the pattern J
+        w = blk @ d                  # w = K d
+        ww = w @ w
+        if not ww > 0:
+            break
+        a = (r @ w) / ww
+        p = p + a * d
+        r = r - a * w
+        it += 1
+    return p, float(np.linalg.norm(r)), it, margin
+
+
+def spai_build(a: sp.csr_matrix, *, equilibrate=True, symmetrize=True, cols=None,
+               mr_iters=0, tol=0.01) -> Factor:
     """SPAI of K(s) on its own structural pattern (eq. (3.1)).
 
     ``cols`` restricts the computation to a subset of columns (sampled checks
     at large n); the returned values are then only meaningful for those.
+    ``mr_iters`` > 0 selects the minimal-residual loop of Algorithm 2 with
+    stopping tolerance ``tol`` instead of the exact column solves.
     """
     n = a.shape[0]
     rp, ci = a.indptr, a.indices
@@ -122,12 +166,22 @@ def spai_build(a: sp.csr_matrix, *, equilibrate=True, symmetrize=True, cols=None
     cval = khat[cpos]
     hat = np.full(len(ci), np.nan)
     obj = np.full(n, np.nan)
+    iters = np.zeros(n, np.int64)
+    margin = np.full(n, np.inf)
     todo = np.arange(n) if cols is None else np.asarray(cols)
+    if mr_iters > 0:
+        kh = sp.csr_matrix((khat, ci, rp), shape=(n, n))
+        alpha_hat = float(kh.diagonal().sum() / (kh @ kh.T).diagonal().sum())
     for j in todo:
         ii, jj, blk = _column_problem(indptr, crow, cval, j)
         rhs = (ii == j).astype(np.float64)
-        p, *_ = np.linalg.lstsq(blk, rhs, rcond=None)
-        obj[j] = np.linalg.norm(rhs - blk @ p)
+        if mr_iters > 0:
+            p0 = alpha_hat * (jj == j).astype(np.float64)
+            p, obj[j], iters[j], margin[j] = _mr_column(blk, rhs, np.searchsorted(ii, jj), p0,
+                                                        alpha_hat, tol, mr_iters)
+        else:
+            p, *_ = np.linalg.lstsq(blk, rhs, rcond=None)
+            obj[j] = np.linalg.norm(rhs - blk @ p)
         hat[cpos[indptr[j]:indptr[j + 1]]] = p
     if symmetrize:
         mir = mirror_positions(n, rp, ci)
@@ -136,10 +190,11 @@ def spai_build(a: sp.csr_matrix, *, equilibrate=True, symmetrize=True, cols=None
         sym = hat
     values = _scaled_values(sym, rows, ci, s, s)
     # Alg. 2's initial scaling: trace(K) / trace(K K^T) (reported, not used by
-    # the exact column solves).
-    alpha = float(a.diagonal().sum() / (a @ a.T).diagonal().sum())
+    # the exact column solves; the minimal-residual loop uses it for Khat).
+    alpha = alpha_hat if mr_iters > 0 else float(a.diagonal().sum() / (a @ a.T).diagonal().sum())
     return Factor(values=values, hat=hat, objective=obj, skipped=np.zeros(n, bool),
-                  alpha=alpha, cols=todo, pattern=(n, rp, ci))
+                  alpha=alpha, cols=todo, pattern=(n, rp, ci),
+                  iters=iters if mr_iters > 0 else None, margin=margin if mr_iters > 0 else None)
 
 
 def update_alpha(k_old: sp.csr_matrix, k_new: sp.csr_matrix) -> float:
@@ -149,8 +204,9 @@ def update_alpha(k_old: sp.csr_matrix, k_new: sp.csr_matrix) -> float:
 
 
 def spai_update(a_old: sp.csr_matrix, a_new: sp.csr_matrix, *, tol=0.01, equilibrate=True,
-                cols=None) -> Factor:
-    """Q with K_new Q ~ K_old (Section 3.2), on the structural pattern."""
+                cols=None, mr_iters=0) -> Factor:
+    """Q with K_new Q ~ K_old (Section 3.2), on the structural pattern;
+    ``mr_iters`` > 0 selects the minimal-residual loop of Algorithm 4."""
     n = a_new.shape[0]
     rp, ci = a_new.indptr, a_new.indices
     if not (np.array_equal(a_old.indptr, rp) and np.array_equal(a_old.indices, ci)):
@@ -169,27 +225,39 @@ def spai_update(a_old: sp.csr_matrix, a_new: sp.csr_matrix, *, tol=0.01, equilib
     hat = np.full(len(ci), np.nan)
     obj = np.full(n, np.nan)
     skipped = np.zeros(n, bool)
+    iters = np.zeros(n, np.int64)
+    margin = np.full(n, np.inf)
     todo = np.arange(n) if cols is None else np.asarray(cols)
     for j in todo:
         sl = slice(indptr[j], indptr[j + 1])
         jj = crow[sl]
         kold_j = cold[sl]
         r0 = kold_j - alpha * cnew[sl]
-        if np.linalg.norm(r0) <= tol * np.linalg.norm(kold_j):
+        thr = tol * np.linalg.norm(kold_j)
+        if thr > 0:
+            margin[j] = abs(np.linalg.norm(r0) / thr - 1.0)
+        if np.linalg.norm(r0) <= thr:
             skipped[j] = True
             q = alpha * (jj == j).astype(np.float64)
             obj[j] = np.linalg.norm(r0)
         else:
             ii, jj2, blk = _column_problem(indptr, crow, cnew, j)
             rhs = np.zeros(len(ii))
-            rhs[np.searchsorted(ii, jj)] = kold_j
-            q, *_ = np.linalg.lstsq(blk, rhs, rcond=None)
-            obj[j] = np.linalg.norm(rhs - blk @ q)
+            jpos = np.searchsorted(ii, jj)
+            rhs[jpos] = kold_j
+            if mr_iters > 0:
+                q0 = alpha * (jj == j).astype(np.float64)
+                q, obj[j], iters[j], m2 = _mr_column(blk, rhs, jpos, q0, alpha, tol, mr_iters)
+                margin[j] = min(margin[j], m2)
+            else:
+                q, *_ = np.linalg.lstsq(blk, rhs, rcond=None)
+                obj[j] = np.linalg.norm(rhs - blk @ q)
         hat[cpos[sl]] = q
     # Q = S Qhat S^{-1}
     values = hat * s[rows] / s[ci]
     return Factor(values=values, hat=hat, objective=obj, skipped=skipped, alpha=alpha,
-                  cols=todo, pattern=(n, rp, ci))
+                  cols=todo, pattern=(n, rp, ci),
+                  iters=iters if mr_iters > 0 else None, margin=margin if mr_iters > 0 else None)
 
 
 def chain_apply(factors, r: np.ndarray) -> np.ndarray:

@@ -547,3 +547,83 @@ def test_thin_qr_is_unique_factorisation_and_matches_gram_schmidt():
         rg[j, j] = np.linalg.norm(v)
         qg[:, j] = v / rg[j, j]
     assert np.allclose(q, qg, atol=1e-12) and np.allclose(r, rg, atol=1e-12)
+
+
+# ------------------------------------------- SPAI minimal-residual mode
+
+def test_spai_mr_one_step_closed_form():
+    # one step of Algorithm 2 from p = alpha e_j, computed densely by hand:
+    # r0 = e_j - alpha K e_j, d = alpha r0 on the pattern J, w = K d,
+    # a = (r0, w) / (w, w), p = alpha e_j + a d
+    p = small_pencil(8)
+    a = pencil.shifted_operator(p, 3.0)
+    k = a.toarray()
+    f = spai.spai_build(a, equilibrate=False, symmetrize=False, mr_iters=1, tol=0.0)
+    alpha = np.trace(k) / np.trace(k @ k.T)
+    assert abs(f.alpha - alpha) < 1e-15 * abs(alpha)
+    got = f.matrix().toarray()
+    for j in (0, 5, p.n - 1):
+        e = np.zeros(p.n)
+        e[j] = 1.0
+        r0 = e - alpha * k[:, j]
+        mask = k[:, j] != 0
+        mask |= np.arange(p.n) == j
+        d = np.where(mask, alpha * r0, 0.0)
+        w = k @ d
+        step = (r0 @ w) / (w @ w)
+        ref = alpha * e + step * d
+        assert np.allclose(got[:, j], ref, rtol=0, atol=1e-14 * np.abs(ref).max())
+
+
+def test_spai_mr_steps_decrease_residual_and_stop_at_tol():
+    p = small_pencil(30)
+    a = pencil.shifted_operator(p, 12.0)
+    prev = None
+    for it in (1, 2, 4, 8, 16):
+        f = spai.spai_build(a, mr_iters=it, tol=0.0)
+        if prev is not None:
+            # each minimal-residual step can only lower a column's residual
+            assert np.all(f.objective <= prev * (1 + 1e-12))
+        prev = f.objective
+    # the loop stops as soon as ||r|| <= tol (||e_j|| = 1)
+    f = spai.spai_build(a, mr_iters=500, tol=0.3)
+    stopped = f.iters < 500
+    assert np.all(f.objective[stopped] <= 0.3)
+    assert np.all(f.iters >= 0)
+    # tolerance above the start: no step, P = alpha I
+    f0 = spai.spai_build(a, symmetrize=False, mr_iters=5, tol=10.0)
+    assert np.all(f0.iters == 0)
+    d = f0.matrix().diagonal()
+    n = p.n
+    s = 1.0 / np.sqrt(a.diagonal())
+    assert np.allclose(d, f0.alpha * s * s, rtol=1e-14)
+    assert abs(f0.matrix().sum() - d.sum()) < 1e-12 * abs(d.sum())
+
+
+def test_spai_mr_full_pattern_converges_to_inverse():
+    # on a full pattern nothing is dropped: d = alpha r is the plain
+    # minimal-residual iteration for K p = e_j, which converges to the inverse
+    rng = np.random.default_rng(2)
+    b = rng.standard_normal((6, 6))
+    k = b @ b.T + 6 * np.eye(6)
+    a = sp.csr_matrix(k)
+    f = spai.spai_build(a, equilibrate=False, symmetrize=False, mr_iters=4000, tol=1e-13)
+    assert np.allclose(f.matrix().toarray(), np.linalg.inv(k), atol=1e-11)
+
+
+def test_spai_mr_update_skips_exactly_the_exact_mode_skips():
+    p = small_pencil(40)
+    a_old = pencil.shifted_operator(p, 4.0)
+    a_new = pencil.shifted_operator(p, 4.4)
+    ex = spai.spai_update(a_old, a_new, tol=0.05)
+    mr = spai.spai_update(a_old, a_new, tol=0.05, mr_iters=20)
+    # the start residual and the test are the same, so the columns that take
+    # no step are exactly those the exact mode keeps at alpha e_j
+    assert np.array_equal(ex.skipped, mr.skipped) and 0 < ex.skipped.sum() < p.n
+    assert np.all(mr.iters[mr.skipped] == 0) and np.all(mr.iters[~mr.skipped] > 0)
+    # entries of the skipped columns (CSR entry (r, c) belongs to column c)
+    sel = ex.skipped[p.col_idx]
+    assert np.array_equal(ex.hat[sel], mr.hat[sel])
+    # minimal residual never beats the exact least squares of a column
+    solved = ~ex.skipped
+    assert np.all(mr.objective[solved] >= ex.objective[solved] * (1 - 1e-12))
