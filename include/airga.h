@@ -135,10 +135,12 @@ AIRGA_API airga_status airga_shift_diagnostics(airga_ctx ctx, double s_old, doub
 /* --------------------------------------------------------- preconditioners */
 
 typedef struct {
-  double tol;          /* update only: a column keeps q_j = alpha e_j when
+  double tol;          /* update: a column keeps q_j = alpha e_j when
                           ||k_old_j - alpha k_new_j|| <= tol ||k_old_j||
                           (the test that opens the inner loop of the update
-                          algorithm; the paper uses 0.01).  Default 0.01.      */
+                          algorithm; the paper uses 0.01).  With mr_iters > 0
+                          also the loops' stopping test ||r|| <= tol ||t||,
+                          build included.  Default 0.01.                      */
   int32_t equilibrate; /* 1: pose the column problems for S K(s) S with
                           S = diag(K(s))^{-1/2} and map back (default 1)      */
   int32_t symmetrize;  /* build only, 1: replace Phat by (Phat + Phat^T)/2
@@ -146,7 +148,13 @@ typedef struct {
   int32_t general_only; /* 1: the general column kernels even for a pencil of
                           bandwidth <= 64 (whose kernels otherwise stage the
                           rows in LDS; same arithmetic, same results)          */
-  int32_t reserved;
+  int32_t mr_iters;    /* 0 (default): each column's least-squares problem on
+                          the pattern is solved exactly.  > 0: the paper's
+                          minimal-residual column loop (Algorithms 2 and 4):
+                          from alpha e_j, steps d = alpha r dropped to the
+                          pattern of the column, a = (r, w) / (w, w) with
+                          w = K d, until ||r|| <= tol ||t|| (t = e_j or
+                          k_old_j), at most mr_iters steps (<= 100000).       */
 } airga_spai_opts;
 
 AIRGA_API void airga_spai_opts_default(airga_spai_opts* opts);

@@ -45,7 +45,7 @@ class PencilInfo(ctypes.Structure):
 class SpaiOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("equilibrate", ctypes.c_int32),
                 ("symmetrize", ctypes.c_int32), ("general_only", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("mr_iters", ctypes.c_int32)]
 
 
 class PrecInfo(ctypes.Structure):
@@ -322,7 +322,7 @@ class Context:
 
     # ------------------------------------------------------- preconditioners
     @staticmethod
-    def _spai_opts(tol, equilibrate, symmetrize, general_only=False):
+    def _spai_opts(tol, equilibrate, symmetrize, general_only=False, mr_iters=0):
         o = SpaiOpts()
         lib().airga_spai_opts_default(ctypes.byref(o))
         if tol is not None:
@@ -330,11 +330,15 @@ class Context:
         o.equilibrate = int(bool(equilibrate))
         o.symmetrize = int(bool(symmetrize))
         o.general_only = int(bool(general_only))
+        o.mr_iters = int(mr_iters)
         return o
 
     def spai_build(self, s: float, *, equilibrate=True, symmetrize=True,
-                   general_only=False) -> "Prec":
-        o = self._spai_opts(None, equilibrate, symmetrize, general_only)
+                   general_only=False, mr_iters=0, tol=None) -> "Prec":
+        """SPAI of K(s); mr_iters > 0 selects the paper's minimal-residual
+        column loop (stopping tolerance tol, default 0.01) instead of the exact
+        column solves."""
+        o = self._spai_opts(tol, equilibrate, symmetrize, general_only, mr_iters)
         h = ctypes.c_void_p()
         self._enter()
         _check(lib().airga_spai_build(self._h, float(s), ctypes.byref(o), ctypes.byref(h)))
@@ -342,8 +346,8 @@ class Context:
         return Prec(self, h)
 
     def spai_update(self, old: "Prec", s_new: float, *, tol=0.01, equilibrate=True,
-                    general_only=False) -> "Prec":
-        o = self._spai_opts(tol, equilibrate, False, general_only)
+                    general_only=False, mr_iters=0) -> "Prec":
+        o = self._spai_opts(tol, equilibrate, False, general_only, mr_iters)
         h = ctypes.c_void_p()
         self._enter()
         _check(lib().airga_spai_update(self._h, old._h, float(s_new), ctypes.byref(o),
@@ -352,12 +356,12 @@ class Context:
         return Prec(self, h)
 
     def spai_update_many(self, olds, s_new, *, tol=0.01, equilibrate=True,
-                         general_only=False) -> list:
+                         general_only=False, mr_iters=0) -> list:
         """[update of olds[i] to s_new[i]], the pencil read once per batch."""
         k = len(olds)
         if len(s_new) != k:
             raise ValueError("one new shift per preconditioner")
-        o = self._spai_opts(tol, equilibrate, False, general_only)
+        o = self._spai_opts(tol, equilibrate, False, general_only, mr_iters)
         c_old = (ctypes.c_void_p * max(k, 1))(*[p._h.value for p in olds])
         c_s = (ctypes.c_double * max(k, 1))(*[float(v) for v in s_new])
         c_out = (ctypes.c_void_p * max(k, 1))()

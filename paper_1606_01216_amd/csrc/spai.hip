@@ -126,6 +126,41 @@ __global__ void k_alpha_partial(PencilDev pd, double a, double b, double a_old, 
 }
 
 // alpha = num / den from the per-block partials, summed in a fixed order.
+// Per-block partial sums of trace(Khat) and ||Khat||_F^2 for Khat = S K(s) S
+// (S = diag(dinv)): the numerator and denominator of the build's starting
+// scaling alpha = trace(Khat) / trace(Khat Khat^T) (Algorithm 2, first line).
+__global__ void k_alpha_build_partial(PencilDev pd, double a, double b,
+                                      const double* __restrict__ dinv, double* __restrict__ part) {
+  __shared__ double red[2][4];
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double num = 0, den = 0;
+  if (r < pd.n) {
+    const int32_t base = pd.slice_ptr[r / kSlice] + (int32_t)(r % kSlice);
+    const int len = pd.row_len[r];
+    const double sr = dinv[r];
+    for (int k = 0; k < len; ++k) {
+      const int32_t idx = base + k * kSlice;
+      const int c = pd.col[idx];
+      const double v = fma(a, pd.m64[idx], b * pd.k64[idx]) * (sr * dinv[c]);
+      if (c == (int)r) num += v;
+      den = fma(v, v, den);
+    }
+  }
+  num = wave_sum(num);
+  den = wave_sum(den);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = num;
+    red[1][w] = den;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0;
+    for (int i = 0; i < 4; ++i) t += red[threadIdx.x][i];
+    part[(int64_t)blockIdx.x * 2 + threadIdx.x] = t;
+  }
+}
+
 __device__ __forceinline__ void alpha_final_block(const double* __restrict__ part, int64_t nb,
                                                   double* __restrict__ out) {
   __shared__ double red[2][256];
@@ -318,6 +353,176 @@ __global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, const double* _
       for (int t = 0; t < MJ; ++t)
         if (t < nj) hat[jpos[t]] = p[t];
       obj[j] = sqrt(res2);
+    }
+  }
+  if constexpr (UPDATE) block_count(skipped, skip_count);
+}
+
+// The paper's minimal-residual column loop (Algorithm 2; Algorithm 4 for the
+// update), one lane per column j.  As printed, P (Q) stays alpha I inside the
+// loop, so the direction is d = alpha r, dropped to the pattern J of column
+// j: p_j stays on J and r on the rows I.  The loop then needs only the
+// column's local data, gathered once while the rows of I stream past:
+//   G = Khat(I,J)^T Khat(I,J),  g = Khat(I,J)^T t,  |t|^2,  Khat(J,J), t(J),
+// with t = e_j (build) or khat_old_j (update).  With w = Khat d:
+//   (r, w) = g.d - p^T G d,  (w, w) = d^T G d,  a = (r, w) / (w, w),
+//   p += a d,  r(J) -= a Khat(J,J) d,  |r|^2 = |t|^2 - 2 g.p + p^T G p.
+// It stops once |r| <= tol |t|, when (w, w) is not positive, or after maxit
+// steps.  The update's start test is the exact mode's skip test, so a column
+// that takes no step is flagged as alpha e_j.
+template <int MJ, bool UPDATE>
+__global__ void __launch_bounds__(256) k_spai_mr(PencilDev pd, const double* __restrict__ ahat,
+                                                 const double* __restrict__ aold,
+                                                 const double* __restrict__ alpha_d, double tol,
+                                                 int maxit, double* __restrict__ hat,
+                                                 double* __restrict__ obj,
+                                                 int32_t* __restrict__ skip_count,
+                                                 int8_t* __restrict__ skipf) {
+  constexpr int NT = MJ * (MJ + 1) / 2;
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  bool skipped = false;
+  if (j < pd.n) {
+    const int32_t base_j = pd.slice_ptr[j / kSlice] + (int32_t)(j % kSlice);
+    const int nj = pd.row_len[j];
+    int J[MJ];
+    int32_t jpos[MJ];
+#pragma unroll
+    for (int t = 0; t < MJ; ++t) {
+      J[t] = -1;
+      jpos[t] = 0;
+      if (t < nj) {
+        jpos[t] = base_j + t * kSlice;
+        J[t] = pd.col[jpos[t]];
+      }
+    }
+    const double al = *alpha_d;
+    if constexpr (UPDATE) {
+      double n_old = 0, n_res = 0;
+#pragma unroll
+      for (int t = 0; t < MJ; ++t) {
+        if (t < nj) {
+          const double vo = aold[jpos[t]];
+          const double d = fma(-al, ahat[jpos[t]], vo);
+          n_old = fma(vo, vo, n_old);
+          n_res = fma(d, d, n_res);
+        }
+      }
+      if (sqrt(n_res) <= tol * sqrt(n_old)) {
+        skipped = true;
+        obj[j] = sqrt(n_res);
+      }
+      skipf[j] = skipped ? 1 : 0;
+    }
+    if (!skipped) {
+      double G[NT], KJ[NT], g[MJ], tJ[MJ];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) G[q] = KJ[q] = 0.0;
+#pragma unroll
+      for (int q = 0; q < MJ; ++q) g[q] = tJ[q] = 0.0;
+      double t2 = 0.0;
+#pragma unroll
+      for (int t = 0; t < MJ; ++t) {
+        if (t < nj) {
+          const int k = J[t];
+          const int32_t base_k = pd.slice_ptr[k / kSlice] + (k % kSlice);
+          const int nk = pd.row_len[k];
+          for (int e = 0; e < nk; ++e) {
+            const int i = pd.col[base_k + e * kSlice];
+            // row i of Khat restricted to J, met first through the earliest
+            // column of J whose pattern holds it (later meetings skipped)
+            const int32_t base_i = pd.slice_ptr[i / kSlice] + (i % kSlice);
+            const int ni = pd.row_len[i];
+            double v[MJ];
+#pragma unroll
+            for (int u = 0; u < MJ; ++u) v[u] = 0.0;
+            int umin = MJ;
+            double rhs = 0.0;
+            for (int q = 0; q < ni; ++q) {
+              const int32_t idx = base_i + q * kSlice;
+              const int c = pd.col[idx];
+              const double val = ahat[idx];
+#pragma unroll
+              for (int u = 0; u < MJ; ++u) {
+                if (u < nj && J[u] == c) {
+                  v[u] += val;
+                  umin = u < umin ? u : umin;
+                }
+              }
+              if constexpr (UPDATE) {
+                if (c == (int)j) rhs = aold[idx];
+              }
+            }
+            if constexpr (!UPDATE) rhs = (i == (int)j) ? 1.0 : 0.0;
+            if (umin < t) continue;
+#pragma unroll
+            for (int u = 0; u < MJ; ++u) {
+#pragma unroll
+              for (int w = u; w < MJ; ++w) G[tri<MJ>(u, w)] = fma(v[u], v[w], G[tri<MJ>(u, w)]);
+              g[u] = fma(v[u], rhs, g[u]);
+            }
+            t2 = fma(rhs, rhs, t2);
+#pragma unroll
+            for (int w = 0; w < MJ; ++w) {
+              if (w < nj && J[w] == i) {
+                tJ[w] = rhs;
+#pragma unroll
+                for (int u = w; u < MJ; ++u) KJ[tri<MJ>(w, u)] = v[u];
+              }
+            }
+          }
+        }
+      }
+      // symmetric packed products
+      auto symv = [&](const double (&S)[NT], const double (&x)[MJ], double (&y)[MJ]) {
+#pragma unroll
+        for (int u = 0; u < MJ; ++u) {
+          double acc = 0.0;
+#pragma unroll
+          for (int w = 0; w < MJ; ++w)
+            acc = fma(S[u <= w ? tri<MJ>(u, w) : tri<MJ>(w, u)], x[w], acc);
+          y[u] = acc;
+        }
+      };
+      auto resid2 = [&](const double (&x)[MJ]) {
+        double gx[MJ];
+        symv(G, x, gx);
+        double s = t2;
+#pragma unroll
+        for (int u = 0; u < MJ; ++u) s = fma(x[u], fma(-2.0, g[u], gx[u]), s);
+        return s;
+      };
+      double p[MJ], rJ[MJ], d[MJ], y[MJ];
+#pragma unroll
+      for (int u = 0; u < MJ; ++u) p[u] = (u < nj && J[u] == (int)j) ? al : 0.0;
+      symv(KJ, p, y);
+#pragma unroll
+      for (int u = 0; u < MJ; ++u) rJ[u] = tJ[u] - y[u];
+      double r2 = resid2(p);
+      const double thr = tol * tol * t2;
+      for (int it = 0; it < maxit && r2 > thr; ++it) {
+#pragma unroll
+        for (int u = 0; u < MJ; ++u) d[u] = u < nj ? al * rJ[u] : 0.0;
+        symv(G, d, y);
+        double rw = 0.0, ww = 0.0;
+#pragma unroll
+        for (int u = 0; u < MJ; ++u) {
+          rw = fma(g[u], d[u], rw);
+          rw = fma(-p[u], y[u], rw);
+          ww = fma(d[u], y[u], ww);
+        }
+        if (!(ww > 0.0)) break;
+        const double a = rw / ww;
+#pragma unroll
+        for (int u = 0; u < MJ; ++u) p[u] = fma(a, d[u], p[u]);
+        symv(KJ, d, y);
+#pragma unroll
+        for (int u = 0; u < MJ; ++u) rJ[u] = fma(-a, y[u], rJ[u]);
+        r2 = resid2(p);
+      }
+#pragma unroll
+      for (int t = 0; t < MJ; ++t)
+        if (t < nj) hat[jpos[t]] = p[t];
+      obj[j] = sqrt(r2 > 0.0 ? r2 : 0.0);
     }
   }
   if constexpr (UPDATE) block_count(skipped, skip_count);
@@ -909,7 +1114,7 @@ static airga_status spai_scratch(airga_ctx ctx, SpaiScratch* w, int64_t nb) {
 
 // LDS-staged column kernels apply (bandwidth <= 64 and the window fits).
 static bool spai_banded(const Pencil& pen, const airga_spai_opts& o, bool update) {
-  if (o.general_only || pen.bandwidth > kSlice) return false;
+  if (o.general_only || o.mr_iters > 0 || pen.bandwidth > kSlice) return false;
   const size_t lds = pen.max_len <= 6 ? spai_band_lds<6>(pen.bandwidth, update)
                                       : spai_band_lds<kSpaiMaxJ>(pen.bandwidth, update);
   return lds <= 64 * 1024;
@@ -959,13 +1164,32 @@ static void launch_cols(airga_ctx ctx, const SpaiScratch& w, const double* alpha
                                                                tol, w.hat, obj, skip, skipf);
 }
 
+// Largest step cap of the minimal-residual mode.
+constexpr int kMrMaxIters = 100000;
+
+// The minimal-residual column kernels, sized to the longest row.
+template <bool UPDATE>
+static void launch_mr(airga_ctx ctx, const SpaiScratch& w, const double* alpha, double tol,
+                      int maxit, double* obj, int32_t* skip, int8_t* skipf) {
+  const Pencil& pen = ctx->pen;
+  const unsigned nb = blocks_for(pen.n, 256);
+  if (pen.max_len <= 6)
+    k_spai_mr<6, UPDATE><<<nb, 256, 0, ctx->stream>>>(pen.dev(), w.ahat, w.aold, alpha, tol, maxit,
+                                                     w.hat, obj, skip, skipf);
+  else
+    k_spai_mr<kSpaiMaxJ, UPDATE><<<nb, 256, 0, ctx->stream>>>(pen.dev(), w.ahat, w.aold, alpha, tol,
+                                                             maxit, w.hat, obj, skip, skipf);
+}
+
 static airga_status run_build(airga_ctx ctx, double s, const airga_spai_opts& o, airga_prec p) {
   const Pencil& pen = ctx->pen;
   hipStream_t st = ctx->stream;
   double a, b;
   shift_coeffs(pen, s, &a, &b);
+  const bool mr = o.mr_iters > 0;
+  const unsigned nb = blocks_for(pen.n, 256);
   SpaiScratch w;
-  AIRGA_TRY(spai_scratch(ctx, &w, 0));
+  AIRGA_TRY(spai_scratch(ctx, &w, mr ? nb : 0));
   const PencilDev pd = pen.dev();
   const unsigned nr = blocks_for(pen.n_pad(), 256);
   k_dinv<<<nr, 256, 0, st>>>(pd, a, b, o.equilibrate, w.dinv);
@@ -976,16 +1200,30 @@ static airga_status run_build(airga_ctx ctx, double s, const airga_spai_opts& o,
   } else {
     k_scaled_values<<<nr, 256, 0, st>>>(pd, a, b, w.dinv, w.ahat);
     AIRGA_HIP(hipGetLastError());
-    launch_cols<false>(ctx, w, nullptr, 0.0, p->objective.as<double>(), nullptr, nullptr);
+    if (mr) {
+      // Algorithm 2: alpha of Khat on the device, no skipped columns
+      double* d_alpha = p->scal.as<double>();
+      k_alpha_build_partial<<<nb, 256, 0, st>>>(pd, a, b, w.dinv, w.part);
+      AIRGA_HIP(hipGetLastError());
+      k_alpha_final<<<1, 256, 0, st>>>(w.part, nb, d_alpha);
+      AIRGA_HIP(hipGetLastError());
+      k_fill_i32<<<1, 64, 0, st>>>(reinterpret_cast<int32_t*>(p->scal.as<char>() + 8), 1, 0);
+      AIRGA_HIP(hipGetLastError());
+      launch_mr<false>(ctx, w, d_alpha, o.tol, o.mr_iters, p->objective.as<double>(), nullptr,
+                       nullptr);
+    } else {
+      launch_cols<false>(ctx, w, nullptr, 0.0, p->objective.as<double>(), nullptr, nullptr);
+    }
   }
   AIRGA_HIP(hipGetLastError());
   k_spai_finalize<<<nr, 256, 0, st>>>(pd, w.hat, w.dinv, o.symmetrize ? 1 : 0, nullptr, nullptr,
                                       nullptr, p->v64.as<double>(), p->v16.as<uint16_t>());
   AIRGA_HIP(hipGetLastError());
-  // Alg. 2's starting scaling trace(K) / trace(K K^T), from the Gram scalars.
+  // Alg. 2's starting scaling trace(K) / trace(K K^T), from the Gram scalars
+  // (minimal-residual mode: that of Khat, read from the device when needed).
   const double nn = a * a * pen.gram_mm + 2 * a * b * pen.gram_mk + b * b * pen.gram_kk;
   p->alpha = (a * pen.tr_m + b * pen.tr_k) / nn;
-  p->alpha_known = true;
+  p->alpha_known = !mr;
   p->skipped = 0;
   p->scalar_only = false;
   p->scalar_known = true;
@@ -1022,6 +1260,9 @@ static airga_status run_update(airga_ctx ctx, airga_prec old, double s_new,
   if (band)
     launch_band<true>(ctx, a, b, ao, bo, w.dinv, d_alpha, o.tol, w.hat, p->objective.as<double>(),
                       w.skip_part, skip_flags(p));
+  else if (o.mr_iters > 0)
+    launch_mr<true>(ctx, w, d_alpha, o.tol, o.mr_iters, p->objective.as<double>(), w.skip_part,
+                    skip_flags(p));
   else
     launch_cols<true>(ctx, w, d_alpha, o.tol, p->objective.as<double>(), w.skip_part,
                       skip_flags(p));
@@ -1177,8 +1418,9 @@ airga_status airga_spai_build(airga_ctx ctx, double s, const airga_spai_opts* op
   airga_spai_opts o;
   airga_spai_opts_default(&o);
   if (opts) o = *opts;
-  double a, b;
-  shift_coeffs(ctx->pen, s, &a, &b);
+  if (o.mr_iters < 0 || o.mr_iters > kMrMaxIters)
+    return fail(AIRGA_EINVAL, "mr_iters must be in [0, %d]", kMrMaxIters);
+  if (!(o.tol >= 0)) return fail(AIRGA_EINVAL, "tolerance must be >= 0");
   airga_prec p = nullptr;
   AIRGA_TRY(new_prec(ctx, s, &p));
   airga_status st = run_build(ctx, s, o, p);
@@ -1200,6 +1442,8 @@ airga_status airga_spai_update(airga_ctx ctx, airga_prec old, double s_new,
   airga_spai_opts_default(&o);
   if (opts) o = *opts;
   if (!(o.tol >= 0)) return fail(AIRGA_EINVAL, "update tolerance must be >= 0");
+  if (o.mr_iters < 0 || o.mr_iters > kMrMaxIters)
+    return fail(AIRGA_EINVAL, "mr_iters must be in [0, %d]", kMrMaxIters);
   airga_prec p = nullptr;
   AIRGA_TRY(new_prec(ctx, s_new, &p));
   airga_status st = run_update(ctx, old, s_new, o, p);
@@ -1228,6 +1472,8 @@ airga_status airga_spai_update_many(airga_ctx ctx, int32_t count, const airga_pr
   airga_spai_opts_default(&o);
   if (opts) o = *opts;
   if (!(o.tol >= 0)) return fail(AIRGA_EINVAL, "update tolerance must be >= 0");
+  if (o.mr_iters < 0 || o.mr_iters > kMrMaxIters)
+    return fail(AIRGA_EINVAL, "mr_iters must be in [0, %d]", kMrMaxIters);
   std::vector<airga_prec> ps(count, nullptr);
   airga_status st = AIRGA_OK;
   for (int32_t i = 0; i < count && st == AIRGA_OK; ++i) st = new_prec(ctx, s_new[i], &ps[i]);
