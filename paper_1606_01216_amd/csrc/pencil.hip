@@ -30,6 +30,9 @@ airga_status fail(airga_status st, const char* fmt, ...) {
 
 airga_status DevBuf::reserve(size_t need) {
   if (ptr && need <= bytes) return AIRGA_OK;
+  // growing: queued kernels may still use the old allocation (workspaces are
+  // shared between calls on the context stream), so wait for them first
+  if (ptr) (void)hipDeviceSynchronize();
   release();
   if (need == 0) return AIRGA_OK;
   hipError_t e = hipMalloc(&ptr, need);
