@@ -524,7 +524,8 @@ def main():
         out["speedup_pcg_vs_plain_fp64"] = round(out["batched_mixed_pcg_solves_per_s"] /
                                                  max(out["plain_fp64"]["pcg_solves_per_s"], 1e-30), 2)
     log("[bench] moment-sequence block operations")
-    out["moments"] = measure_moments(ctx, stream, dev, n, m, S)
+    # the collected blocks of one pass, up to the 64 columns the thin QR takes
+    out["moments"] = measure_moments(ctx, stream, dev, n, m, min(S, 64 // m))
     log("[bench] minimal-residual SPAI mode")
     out["spai_mr"] = measure_spai_mr(ctx, stream, list(shifts), precs, F, X1, solve_kw)
     if cpu is not None:
