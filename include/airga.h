@@ -238,7 +238,8 @@ typedef struct {
                           arithmetic and vectors, preconditioner values stored
                           as bfloat16, inside float64 iterative refinement of
                           the residual and the solution)                        */
-  double inner_tol;    /* MIXED: relative residual reduction per sweep (5e-4)   */
+  double inner_tol;    /* MIXED: relative residual reduction per sweep (1e-5:
+                          two sweeps reach the default tol of 1e-10)          */
   int32_t max_sweeps;  /* MIXED: refinement sweeps (default 12)                 */
   int32_t poll_every;  /* iterations between host checks of the active count
                           (rounded up to even; default 8)                       */

@@ -915,7 +915,7 @@ void airga_pcg_opts_default(airga_pcg_opts* o) {
   o->tol = 1e-10;
   o->max_iter = 20000;
   o->mode = AIRGA_MODE_FP64;
-  o->inner_tol = 5e-4;
+  o->inner_tol = 1e-5;
   o->max_sweeps = 12;
   o->poll_every = 8;
   o->x0_given = 0;
