@@ -70,8 +70,11 @@ def build_inputs(name, seed=0):
 # (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) over one quick step with a
 # forced tile, each scaled by what the same counter reads for a plain 1 GiB
 # device copy in the same run.  The table is keyed by the hash of the row
-# kernels' source: after any change to them it no longer applies.
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1606_01216_amd", "csrc", "pcg_kernels.hpp")
+# kernels' source and of the solve that drives them (its options set how many
+# systems an average launch sweeps): after any change to either it no longer
+# applies.
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1606_01216_amd", "csrc", f)
+                  for f in ("pcg_kernels.hpp", "pcg.hip")]
 PROFILES = os.path.join(ROOT, "profiles")
 PMC_KERNELS = {"update_prec": "k_update_prec<float, {w}, {r}, {u}, false",
                "dir_spmv": "k_dir_spmv<float, {w}, {r}, {u}, false"}
@@ -79,8 +82,11 @@ PMC_KERNELS = {"update_prec": "k_update_prec<float, {w}, {r}, {u}, false",
 
 def kernel_source_hash():
     import hashlib
-    with open(KERNEL_SOURCE, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_file(workload):
@@ -278,8 +284,8 @@ def measure_spai_mr(ctx, stream, shifts, precs, F, X, solve_kw, mr_iters=20, tol
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=60)
     ap.add_argument("--workload", default="c4s", choices=sorted(WORKLOADS))
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain float64 comparator")
