@@ -172,7 +172,8 @@ def test_block_ops_reject_bad_sizes(ctx):
 
 def test_moment_sequence_pass_interpolates(ctx):
     """One pass of Algorithm 1 on the GPU (m = 2 inputs, three expansion
-    points): solves X(s_i) = K(s_i)^{-1} F, their thin QR per block (line 6),
+    points): solves X(s_i) = K(s_i)^{-1} F, the thin QR of each block (the
+    algorithm's first step after the solves),
     V_1 = X(sigma) / ||X(sigma)||_F, the moment solve with right-hand side
     M V_1, orthogonalisation of every block against V_1 in the trace inner
     product, the thin QR of the collected blocks together with V_1, and the
@@ -192,7 +193,7 @@ def test_moment_sequence_pass_interpolates(ctx):
     X, st = ctx.pcg_solve(shifts, precs, to_dev(f, torch.float64), tol=1e-12)
     assert all(e["status"] == airga.SYS_CONVERGED for e in st)
     blocks = X.reshape(len(shifts) * m, n).contiguous()      # rows: (shift, column)
-    # line 6: X(s_i) <- Q of its thin QR, block by block
+    # X(s_i) <- Q of its thin QR, block by block
     for i in range(len(shifts)):
         b = blocks[i * m:(i + 1) * m].clone()
         ctx.block_qr(b)
