@@ -354,7 +354,7 @@ def main():
             mark(0)
             ctx.set_pencil(rp, ci, mv, kv, pen.alpha, pen.beta)
             mark(1)
-            precs = [ctx.spai_build(s) for s in shifts]
+            precs = ctx.spai_build_many(list(shifts))
             mark(2)
             _, st1 = ctx.pcg_solve(shifts, precs, F, X1, profile=profile, **solve_kw)
             mark(3)

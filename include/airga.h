@@ -186,6 +186,16 @@ AIRGA_API airga_status airga_spai_build(airga_ctx ctx, double s, const airga_spa
 AIRGA_API airga_status airga_spai_update(airga_ctx ctx, airga_prec old, double s_new,
                                const airga_spai_opts* opts, airga_prec* out);
 
+/* Several SPAI builds at once: out[i] = the SPAI of K(shifts[i]), exactly
+ * as airga_spai_build(ctx, shifts[i], opts, &out[i]) would give, for
+ * i < count (host arrays).  On a banded pencil (bandwidth <= 64, rows of at
+ * most 6 entries; exact column solves) each block's rows are staged once per
+ * batch of 16 shifts; otherwise the builds run one after the other.  On
+ * error no handle is returned (out[i] = NULL).  Errors: as
+ * airga_spai_build, plus EINVAL for count < 0 or null arrays. */
+AIRGA_API airga_status airga_spai_build_many(airga_ctx ctx, int32_t count, const double* shifts,
+                                             const airga_spai_opts* opts, airga_prec* out);
+
 /* Several SPAI updates at once: out[i] = the update of olds[i] to s_new[i],
  * exactly as airga_spai_update(ctx, olds[i], s_new[i], opts, &out[i]) would
  * give, for i < count (host arrays).  On a banded pencil (bandwidth <= 64,

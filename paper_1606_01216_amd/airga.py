@@ -94,6 +94,8 @@ _SIGS = [
                                          ctypes.POINTER(_P)]),
     ("airga_spai_update_many", ctypes.c_int, [_P, ctypes.c_int32, _P, _P,
                                               ctypes.POINTER(SpaiOpts), _P]),
+    ("airga_spai_build_many", ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.POINTER(SpaiOpts),
+                                             _P]),
     ("airga_get_prec_info", ctypes.c_int, [_P, ctypes.POINTER(PrecInfo)]),
     ("airga_prec_export", ctypes.c_int, [_P, _P, _P]),
     ("airga_prec_apply", ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64, _P,
@@ -344,6 +346,18 @@ class Context:
         _check(lib().airga_spai_build(self._h, float(s), ctypes.byref(o), ctypes.byref(h)))
         self._leave()
         return Prec(self, h)
+
+    def spai_build_many(self, shifts, *, equilibrate=True, symmetrize=True, general_only=False,
+                        mr_iters=0, tol=None) -> list:
+        """[SPAI of K(s) for s in shifts], each block's rows staged once per batch."""
+        k = len(shifts)
+        o = self._spai_opts(tol, equilibrate, symmetrize, general_only, mr_iters)
+        c_s = (ctypes.c_double * max(k, 1))(*[float(v) for v in shifts])
+        c_out = (ctypes.c_void_p * max(k, 1))()
+        self._enter()
+        _check(lib().airga_spai_build_many(self._h, k, c_s, ctypes.byref(o), c_out))
+        self._leave()
+        return [Prec(self, ctypes.c_void_p(c_out[i])) for i in range(k)]
 
     def spai_update(self, old: "Prec", s_new: float, *, tol=0.01, equilibrate=True,
                     general_only=False, mr_iters=0) -> "Prec":

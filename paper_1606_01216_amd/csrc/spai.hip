@@ -844,6 +844,82 @@ __host__ __device__ inline size_t spai_many_lds(int bw) {
          sizeof(double) * (S + 2 * (size_t)bw);
 }
 
+// LDS of k_spai_build_many: M, K and the scaled values (double), the
+// window's dinv, columns and lengths.
+template <int MJ>
+__host__ __device__ inline size_t spai_build_many_lds(int bw) {
+  const size_t S = 256 + 4 * (size_t)bw;
+  return S * (MJ * (3 * sizeof(double) + sizeof(int32_t)) + sizeof(int32_t)) +
+         sizeof(double) * (S + 2 * (size_t)bw);
+}
+
+// The banded build column kernel for every shift of the batch (Section 3.1
+// for each shift): the block's rows are staged once (M, K, columns), then per
+// shift the window's diagonal scaling is staged, the scaled values formed as
+// k_spai_band forms them and the columns solved.  hat: [count][stored].
+template <int MJ, bool RANGE>
+__global__ void __launch_bounds__(256) k_spai_build_many(PencilDev pd, UpdMany U,
+                                                         const double* __restrict__ dinv,
+                                                         int64_t n_pad, int64_t stored, int bw,
+                                                         double* __restrict__ hat) {
+  extern __shared__ double lds[];
+  const int S = 256 + 4 * bw;
+  double* mm = lds;
+  double* kq = mm + MJ * S;
+  double* vn = kq + MJ * S;
+  double* dl = vn + MJ * S;  // dinv of rows [d0, d1): the window and bw beyond
+  int32_t* cl = reinterpret_cast<int32_t*>(dl + S + 2 * bw);
+  int32_t* ln = cl + MJ * S;
+  const int64_t j0 = (int64_t)blockIdx.x * 256;
+  const int64_t w0 = j0 - 2 * bw > 0 ? j0 - 2 * bw : 0;
+  const int64_t w1 = j0 + 256 + 2 * bw < pd.n ? j0 + 256 + 2 * bw : pd.n;
+  const int64_t d0 = w0 - bw > 0 ? w0 - bw : 0;
+  const int64_t d1 = w1 + bw < pd.n ? w1 + bw : pd.n;
+  const int t = threadIdx.x;
+  for (int64_t row = w0 + t; row < w1; row += 256) {
+    const int r = (int)(row - w0);
+    const int64_t sl = row / kSlice;
+    const int32_t sp0 = pd.slice_ptr[sl];
+    const int32_t base = sp0 + (int32_t)(row % kSlice);
+    const int w = (pd.slice_ptr[sl + 1] - sp0) / kSlice;
+    const int len = pd.row_len[row];
+    ln[r] = len;
+#pragma unroll
+    for (int k = 0; k < MJ; ++k) {
+      const int32_t idx = base + (k < w ? k : w - 1) * kSlice;
+      const bool in = k < len;
+      const int32_t c = pd.col[idx];
+      cl[k * S + r] = in ? c : -1;
+      mm[k * S + r] = pd.m64[idx];
+      kq[k * S + r] = pd.k64[idx];
+    }
+  }
+  const int64_t j = j0 + t;
+  for (int s = 0; s < U.count; ++s) {
+    const double* __restrict__ dv = dinv + (int64_t)s * n_pad;
+    __syncthreads();  // staged rows ready; the previous shift's columns done
+    for (int64_t row = d0 + t; row < d1; row += 256) dl[row - d0] = dv[row];
+    __syncthreads();
+    for (int64_t row = w0 + t; row < w1; row += 256) {
+      const int r = (int)(row - w0);
+      const double sr = dl[row - d0];
+      const int len = ln[r];
+#pragma unroll
+      for (int k = 0; k < MJ; ++k) {
+        const bool in = k < len;
+        const int32_t c = cl[k * S + r];
+        const double dc = dl[(in ? c : row) - d0];
+        // same association as k_scaled_values
+        vn[k * S + r] = in ? fma(U.a[s], mm[k * S + r], U.b[s] * kq[k * S + r]) * sr * dc : 0.0;
+      }
+    }
+    __syncthreads();
+    if (j < pd.n)
+      spai_band_column<MJ, false, RANGE>(pd, vn, nullptr, cl, ln, S, w0, j, 0.0, 0.0,
+                                         hat + (int64_t)s * stored, U.obj[s], nullptr);
+  }
+}
+
 // The banded update column kernel for every shift of the batch: the block's
 // rows are staged once (M, K, columns), then per shift their scaled values
 // are formed and the columns solved as in k_spai_band.  hat: [count][stored].
@@ -1280,6 +1356,64 @@ static airga_status run_update(airga_ctx ctx, airga_prec old, double s_new,
 
 // Several updates at once (banded pencils whose staged rows fit in LDS);
 // otherwise one after the other.
+// Several builds at once (banded pencils whose staged rows fit in LDS);
+// otherwise one after the other.  Each factor equals its single build.
+static airga_status run_build_many(airga_ctx ctx, int32_t count, const double* shifts,
+                                   const airga_spai_opts& o, airga_prec* ps) {
+  const Pencil& pen = ctx->pen;
+  const bool fits = spai_banded(pen, o, false) && pen.max_len <= 6 &&
+                    spai_build_many_lds<6>(pen.bandwidth) <= 64 * 1024;
+  if (!fits) {
+    for (int i = 0; i < count; ++i) AIRGA_TRY(run_build(ctx, shifts[i], o, ps[i]));
+    return AIRGA_OK;
+  }
+  hipStream_t st = ctx->stream;
+  const PencilDev pd = pen.dev();
+  const int64_t n_pad = pen.n_pad(), stored = pen.nnz_stored;
+  const unsigned nb = blocks_for(pen.n, 256);
+  const unsigned nr = blocks_for(n_pad, 256);
+  const int bw = pen.bandwidth;
+  const bool range = 4 * bw + 1 <= pen.max_len * pen.max_len;
+  const size_t lds = spai_build_many_lds<6>(bw);
+  for (int i0 = 0; i0 < count; i0 += kManyMax) {
+    const int cnt = count - i0 < kManyMax ? count - i0 : kManyMax;
+    // scratch: [dinv (cnt n_pad) | hat (cnt stored)]
+    AIRGA_TRY(ctx->ws_tmp.reserve(sizeof(double) * (size_t)cnt * (n_pad + stored)));
+    double* dinv = ctx->ws_tmp.as<double>();
+    double* hat = dinv + (size_t)cnt * n_pad;
+    UpdMany U;
+    std::memset(static_cast<void*>(&U), 0, sizeof U);
+    U.count = cnt;
+    for (int i = 0; i < cnt; ++i) {
+      shift_coeffs(pen, shifts[i0 + i], &U.a[i], &U.b[i]);
+      U.obj[i] = ps[i0 + i]->objective.as<double>();
+    }
+    k_dinv_many<<<nr, 256, 0, st>>>(pd, U, o.equilibrate, n_pad, dinv);
+    AIRGA_HIP(hipGetLastError());
+    if (range)
+      k_spai_build_many<6, true><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, hat);
+    else
+      k_spai_build_many<6, false><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, hat);
+    AIRGA_HIP(hipGetLastError());
+    for (int i = 0; i < cnt; ++i) {
+      const airga_prec p = ps[i0 + i];
+      k_spai_finalize<<<nr, 256, 0, st>>>(pd, hat + (size_t)i * stored, dinv + (size_t)i * n_pad,
+                                          o.symmetrize ? 1 : 0, nullptr, nullptr, nullptr,
+                                          p->v64.as<double>(), p->v16.as<uint16_t>());
+      AIRGA_HIP(hipGetLastError());
+      // Alg. 2's starting scaling trace(K) / trace(K K^T), from the Gram scalars
+      const double a = U.a[i], b = U.b[i];
+      const double nn = a * a * pen.gram_mm + 2 * a * b * pen.gram_mk + b * b * pen.gram_kk;
+      p->alpha = (a * pen.tr_m + b * pen.tr_k) / nn;
+      p->alpha_known = true;
+      p->skipped = 0;
+      p->scalar_only = false;
+      p->scalar_known = true;
+    }
+  }
+  return AIRGA_OK;
+}
+
 static airga_status run_update_many(airga_ctx ctx, int32_t count, const airga_prec* olds,
                                     const double* s_new, const airga_spai_opts& o,
                                     airga_prec* ps) {
@@ -1452,6 +1586,33 @@ airga_status airga_spai_update(airga_ctx ctx, airga_prec old, double s_new,
     return st;
   }
   *out = p;
+  return AIRGA_OK;
+}
+
+airga_status airga_spai_build_many(airga_ctx ctx, int32_t count, const double* shifts,
+                                   const airga_spai_opts* opts, airga_prec* out) {
+  AIRGA_TRY(check_pencil(ctx));
+  if (count < 0 || (count > 0 && (!shifts || !out))) return fail(AIRGA_EINVAL, "bad build batch");
+  for (int32_t i = 0; i < count; ++i) {
+    out[i] = nullptr;
+    airga_prec dummy;
+    AIRGA_TRY(check_spai_args(ctx, shifts[i], &dummy));
+  }
+  airga_spai_opts o;
+  airga_spai_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.mr_iters < 0 || o.mr_iters > kMrMaxIters)
+    return fail(AIRGA_EINVAL, "mr_iters must be in [0, %d]", kMrMaxIters);
+  if (!(o.tol >= 0)) return fail(AIRGA_EINVAL, "tolerance must be >= 0");
+  std::vector<airga_prec> ps(count, nullptr);
+  airga_status st = AIRGA_OK;
+  for (int32_t i = 0; i < count && st == AIRGA_OK; ++i) st = new_prec(ctx, shifts[i], &ps[i]);
+  if (st == AIRGA_OK) st = run_build_many(ctx, count, shifts, o, ps.data());
+  if (st != AIRGA_OK) {
+    for (airga_prec p : ps) airga_prec_release(p);
+    return st;
+  }
+  for (int32_t i = 0; i < count; ++i) out[i] = ps[i];
   return AIRGA_OK;
 }
 

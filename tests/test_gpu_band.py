@@ -156,3 +156,24 @@ def test_batched_updates_equal_single_updates(ctx, name):
             assert im.alpha == io.alpha and im.skipped_cols == io.skipped_cols, (name, k)
             assert im.scalar_only == io.scalar_only and im.chain_len == io.chain_len
     assert ctx.spai_update_many([], []) == []
+
+
+@pytest.mark.parametrize("name", ["beam", "grid8", "grid65"])
+def test_batched_builds_equal_single_builds(ctx, name):
+    """airga_spai_build_many gives exactly the single builds (values,
+    objectives, alpha) over more than one batch of 16, with and without
+    equilibration and symmetrisation; grid65 (bandwidth 65) and general_only
+    take the one-by-one path."""
+    pen = {"beam": beam.make_beam(1037, ei_loguniform=(0.5, 2.0), surrogate=True, seed=5),
+           "grid8": grid_pencil(8, 150, seed=3), "grid65": grid_pencil(65, 9, seed=2)}[name]
+    set_pencil(ctx, pen)
+    shifts = [0.7 * 1.7 ** k for k in range(18)]
+    for eq, sym, general in ((True, True, False), (False, False, False), (True, True, True)):
+        many = ctx.spai_build_many(shifts, equilibrate=eq, symmetrize=sym, general_only=general)
+        for k, s in enumerate(shifts):
+            one = ctx.spai_build(s, equilibrate=eq, symmetrize=sym, general_only=general)
+            vm, om = (t.cpu().numpy() for t in many[k].export())
+            vo, oo = (t.cpu().numpy() for t in one.export())
+            assert np.array_equal(vm, vo) and np.array_equal(om, oo), (name, k, eq, sym)
+            assert many[k].info().alpha == one.info().alpha
+    assert ctx.spai_build_many([]) == []
