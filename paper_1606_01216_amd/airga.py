@@ -184,10 +184,14 @@ class Context:
 
     # stream joins
     def _enter(self):
-        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
 
     def _leave(self):
-        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -690,18 +690,28 @@ static airga_status autotune(airga_ctx ctx, int32_t nshift, const double* shifts
 
 // ------------------------------------------------------------------ solves
 
+// Per-system results, read back in one copy into pinned memory: relres and
+// the int32 arrays after it in the state block (statuses, counts, nact and the
+// hand-over flags).  handed (mixed solves): the systems left for the float64
+// finish.
 static airga_status read_stats(airga_ctx ctx, const SysDev& S, int B, bool mixed,
-                               airga_sys_stats* stats) {
+                               airga_sys_stats* stats, std::vector<int>* handed) {
   hipStream_t st = ctx->stream;
-  std::vector<int32_t> sta(B), ist(B), its(B), swp(B), out(B);
-  std::vector<double> rel(B);
-  AIRGA_HIP(hipMemcpyAsync(sta.data(), S.status, 4 * B, hipMemcpyDeviceToHost, st));
-  AIRGA_HIP(hipMemcpyAsync(ist.data(), S.istat, 4 * B, hipMemcpyDeviceToHost, st));
-  AIRGA_HIP(hipMemcpyAsync(its.data(), S.iters, 4 * B, hipMemcpyDeviceToHost, st));
-  AIRGA_HIP(hipMemcpyAsync(swp.data(), S.sweeps, 4 * B, hipMemcpyDeviceToHost, st));
-  AIRGA_HIP(hipMemcpyAsync(out.data(), S.outer, 4 * B, hipMemcpyDeviceToHost, st));
-  AIRGA_HIP(hipMemcpyAsync(rel.data(), S.relres, 8 * B, hipMemcpyDeviceToHost, st));
+  const char* lo = reinterpret_cast<const char*>(S.relres);
+  const size_t bytes = (size_t)(reinterpret_cast<const char*>(S.handed + B) - lo);
+  AIRGA_TRY(ensure_pinned(ctx, bytes));
+  const char* h = static_cast<const char*>(ctx->host_pinned);
+  AIRGA_HIP(hipMemcpyAsync(ctx->host_pinned, lo, bytes, hipMemcpyDeviceToHost, st));
   AIRGA_HIP(hipStreamSynchronize(st));
+  auto host = [&](const int32_t* d) {
+    return reinterpret_cast<const int32_t*>(h + (reinterpret_cast<const char*>(d) - lo));
+  };
+  const double* rel = reinterpret_cast<const double*>(h);
+  const int32_t *sta = host(S.status), *ist = host(S.istat), *its = host(S.iters);
+  const int32_t *swp = host(S.sweeps), *out = host(S.outer), *hnd = host(S.handed);
+  if (handed)
+    for (int b = 0; b < B; ++b)
+      if (hnd[b]) handed->push_back(b);
   if (!stats) return AIRGA_OK;
   for (int b = 0; b < B; ++b) {
     stats[b].status = mixed ? (out[b] ? ST_MAXIT : sta[b]) : ist[b];
@@ -774,7 +784,7 @@ static airga_status solve_fp64(airga_ctx ctx, int32_t nshift, const double* shif
   TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds_res, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, 1, 0, 0));
   TIMED(K_REDUCE, reduce(P, RM_FINAL));
   AIRGA_TRY(tm.flush());
-  return read_stats(ctx, P.a.sys, B, false, stats);
+  return read_stats(ctx, P.a.sys, B, false, stats, nullptr);
 }
 
 // Float32 iterations per refinement sweep before a system still iterating
@@ -888,15 +898,8 @@ static airga_status solve_mixed(airga_ctx ctx, int32_t nshift, const double* shi
   }
   AIRGA_TRY(tm.flush());
   std::vector<airga_sys_stats> mixed(B);
-  AIRGA_TRY(read_stats(ctx, P.a.sys, B, true, mixed.data()));
   std::vector<int> handed;
-  if (any_handed) {
-    std::vector<int32_t> h(B);
-    AIRGA_HIP(hipMemcpyAsync(h.data(), P.a.sys.handed, sizeof(int32_t) * B, hipMemcpyDeviceToHost, st));
-    AIRGA_HIP(hipStreamSynchronize(st));
-    for (int b = 0; b < B; ++b)
-      if (h[b]) handed.push_back(b);
-  }
+  AIRGA_TRY(read_stats(ctx, P.a.sys, B, true, mixed.data(), any_handed ? &handed : nullptr));
   if (!handed.empty())
     AIRGA_TRY(finish_fp64(ctx, shifts, precs, m, F, ldf, X, ldx, o, handed, mixed.data()));
   if (stats) std::copy(mixed.begin(), mixed.end(), stats);

@@ -364,12 +364,15 @@ __global__ void __launch_bounds__(256) k_dir_spmv(SolveArgs<T> A, int par) {
       T* __restrict__ pout = A.vec(KP0 + (par ^ 1), b);
       T* __restrict__ wv = A.vec(KW, b);
       T dot = T(0);
+      // streaming stores: the vectors of all systems exceed the caches, so
+      // each kernel's writes go out to HBM while it runs instead of being
+      // left as dirty lines for the next kernel to write back
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         if (!rows.valid[i]) continue;
         const int64_t r = rows.row[i];
-        pout[r] = pr[u][i];
-        wv[r] = wr[u][i];
+        __builtin_nontemporal_store(pr[u][i], &pout[r]);
+        __builtin_nontemporal_store(wr[u][i], &wv[r]);
         dot = fma(pr[u][i], wr[u][i], dot);
       }
       dot = wave_total(dot);
@@ -443,14 +446,15 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
           }
         }
         if constexpr (!INIT) {
-          // a zero start reads p again (in cache) instead of x, and drops it
+          // a zero start reads p again (in cache) instead of x, and drops it;
+          // own-row x and p are read once, with streaming loads
           const bool x0 = A.xz && sload(A.sys.first + b) != 0;
           const T* __restrict__ xs = x0 ? pcur : x;
 #pragma unroll
           for (int i = 0; i < R; ++i) {
             const int64_t r = rows.row[i];
-            const T xv = xs[r];
-            xn[u][i] = fma(al, pcur[r], x0 ? T(0) : xv);
+            const T xv = __builtin_nontemporal_load(&xs[r]);
+            xn[u][i] = fma(al, __builtin_nontemporal_load(&pcur[r]), x0 ? T(0) : xv);
           }
         }
       }
@@ -501,8 +505,8 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
           } else {
             wr = wv[r];
             v = fma(-al, wr, rin[r]);
-            const T xv = xs[r];
-            xn[u][i] = fma(al, pcur[r], x0 ? T(0) : xv);
+            const T xv = __builtin_nontemporal_load(&xs[r]);
+            xn[u][i] = fma(al, __builtin_nontemporal_load(&pcur[r]), x0 ? T(0) : xv);
           }
           T t = T(0);
 #pragma unroll
@@ -530,11 +534,12 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
       for (int i = 0; i < R; ++i) {
         if (!rows.valid[i]) continue;
         const int64_t r = rows.row[i];
+        // streaming stores, as in the direction kernel
         if constexpr (!INIT) {
-          x[r] = xn[u][i];
-          rout[r] = rn[u][i];
+          __builtin_nontemporal_store(xn[u][i], &x[r]);
+          __builtin_nontemporal_store(rn[u][i], &rout[r]);
         }
-        zo[r] = tz[u][i];
+        __builtin_nontemporal_store(tz[u][i], &zo[r]);
         rr = fma(rn[u][i], rn[u][i], rr);
         rz = fma(rn[u][i], tz[u][i], rz);
         zw = fma(tz[u][i], wrr[u][i], zw);

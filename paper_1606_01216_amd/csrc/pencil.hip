@@ -432,12 +432,16 @@ static airga_status set_pencil_impl(airga_ctx ctx, int32_t n, int64_t nnz, const
   k_scan_slices<<<1, 1024, 0, st>>>(ns, slice_w, slice_b, slice_f, pen.slice_ptr.as<int32_t>(),
                                     info, total);
   AIRGA_HIP(hipGetLastError());
-  struct {
+  struct Summary {
     int32_t flags, bw, maxlen, pad;
     int64_t total;
-  } h{};
-  AIRGA_HIP(hipMemcpyAsync(&h, pen.setup.ptr, 24, hipMemcpyDeviceToHost, st));
+  };
+  // host reads go through the context's pinned buffer (asynchronous copies)
+  AIRGA_TRY(ensure_pinned(ctx, 4096));
+  AIRGA_HIP(hipMemcpyAsync(ctx->host_pinned, pen.setup.ptr, sizeof(Summary), hipMemcpyDeviceToHost, st));
   AIRGA_HIP(hipStreamSynchronize(st));
+  Summary h;
+  std::memcpy(&h, ctx->host_pinned, sizeof h);
   if (h.flags & F_TOO_LONG)
     return fail(AIRGA_EUNSUPPORTED, "pattern has a row longer than %d entries", kMaxRow);
   if (h.flags) {
@@ -498,9 +502,12 @@ static airga_status set_pencil_impl(airga_ctx ctx, int32_t n, int64_t nnz, const
   AIRGA_HIP(hipGetLastError());
   double g[kGram];
   int32_t flags2 = 0;
-  AIRGA_HIP(hipMemcpyAsync(g, gp.as<double>() + kGram * (size_t)nb, sizeof g, hipMemcpyDeviceToHost, st));
-  AIRGA_HIP(hipMemcpyAsync(&flags2, info, 4, hipMemcpyDeviceToHost, st));
+  char* hp = static_cast<char*>(ctx->host_pinned);
+  AIRGA_HIP(hipMemcpyAsync(hp, gp.as<double>() + kGram * (size_t)nb, sizeof g, hipMemcpyDeviceToHost, st));
+  AIRGA_HIP(hipMemcpyAsync(hp + sizeof g, info, 4, hipMemcpyDeviceToHost, st));
   AIRGA_HIP(hipStreamSynchronize(st));
+  std::memcpy(g, hp, sizeof g);
+  std::memcpy(&flags2, hp + sizeof g, 4);
   if (flags2 & F_ASYM) return fail(AIRGA_EINVAL, "invalid pattern: not structurally symmetric");
   pen.gram_mm = g[0];
   pen.gram_mk = g[1];

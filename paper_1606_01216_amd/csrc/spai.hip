@@ -10,6 +10,7 @@
 // triangular system.  Khat = S K S with S = diag(K)^{-1/2} when
 // equilibrating (S = I otherwise); every entry of K(s) is formed on the fly
 // as (s^2 + alpha s) M + (1 + beta s) K from the float64 pencil.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -1483,6 +1484,17 @@ static airga_status run_update_many(airga_ctx ctx, int32_t count, const airga_pr
   return AIRGA_OK;
 }
 
+// The first 16 bytes of up to kFactsMax factors' device scalars (alpha, the
+// skip count), gathered into one block so the host reads them in one copy.
+constexpr int kFactsMax = 64;
+struct FactsSrc {
+  const int4* p[kFactsMax];
+};
+__global__ void k_gather_facts(FactsSrc src, int count, int4* out) {
+  const int i = threadIdx.x;
+  if (i < count) out[i] = src.p[i][0];
+}
+
 airga_status prec_resolve_many(airga_ctx ctx, const std::vector<airga_prec>& ps) {
   std::vector<airga_prec> todo;
   for (airga_prec p : ps)
@@ -1492,11 +1504,20 @@ airga_status prec_resolve_many(airga_ctx ctx, const std::vector<airga_prec>& ps)
     double alpha;
     int32_t skipped, pad;
   };
+  static_assert(sizeof(Facts) == sizeof(int4), "one 16-byte record per factor");
   AIRGA_TRY(ensure_pinned(ctx, sizeof(Facts) * todo.size()));
+  AIRGA_TRY(ctx->ws_small.reserve(sizeof(Facts) * kFactsMax));
   Facts* h = static_cast<Facts*>(ctx->host_pinned);
-  for (size_t i = 0; i < todo.size(); ++i)
-    AIRGA_HIP(hipMemcpyAsync(&h[i], todo[i]->scal.ptr, sizeof(Facts), hipMemcpyDeviceToHost,
+  int4* staged = ctx->ws_small.as<int4>();
+  for (size_t i0 = 0; i0 < todo.size(); i0 += kFactsMax) {
+    const int cnt = (int)std::min(todo.size() - i0, (size_t)kFactsMax);
+    FactsSrc src{};
+    for (int i = 0; i < cnt; ++i) src.p[i] = todo[i0 + i]->scal.as<int4>();
+    k_gather_facts<<<1, kFactsMax, 0, ctx->stream>>>(src, cnt, staged);
+    AIRGA_HIP(hipGetLastError());
+    AIRGA_HIP(hipMemcpyAsync(&h[i0], staged, sizeof(Facts) * cnt, hipMemcpyDeviceToHost,
                              ctx->stream));
+  }
   AIRGA_HIP(hipStreamSynchronize(ctx->stream));
   for (size_t i = 0; i < todo.size(); ++i) {
     airga_prec p = todo[i];
