@@ -20,6 +20,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4s]
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import statistics
@@ -367,6 +368,12 @@ def main():
             record.append([marks[i].elapsed_time(marks[i + 1]) for i in range(5)])
         return precs, upd, st1, st2
 
+    # The objects alive now (torch's import alone leaves ~170k) are moved out
+    # of the cyclic garbage collector's reach: a full pass over them stalls
+    # the host for ~50 ms, and one falls at an unpredictable step every ~100
+    # steps.  Later passes only scan objects created after this point.
+    gc.collect()
+    gc.freeze()
     log(f"[bench] n={n} m={m} shifts={S} systems/step={2 * B}; warmup {args.warmup}")
     for _ in range(args.warmup):
         step()
