@@ -627,3 +627,134 @@ def test_spai_mr_update_skips_exactly_the_exact_mode_skips():
     # minimal residual never beats the exact least squares of a column
     solved = ~ex.skipped
     assert np.all(mr.objective[solved] >= ex.objective[solved] * (1 - 1e-12))
+
+
+# ------------------------------------------------- AIRGA's outer iteration
+
+from oracle import airga_loop  # noqa: E402
+
+
+def one_dof(m, d, k, cv=0.0, cp=1.0):
+    a = np.array([[m]])
+    return airga_loop.Model(a, np.array([[d]]), np.array([[k]]), np.array([[1.0]]),
+                            np.array([[cp]]), np.array([[cv]]))
+
+
+@pytest.mark.parametrize("m,d,k", [(2.0, 0.3, 5.0), (1.5, 9.0, 4.0)])
+def test_qep_poles_one_dof_are_the_quadratic_roots(m, d, k):
+    lam = np.sort_complex(airga_loop.qep_poles(np.array([[m]]), np.array([[d]]), np.array([[k]])))
+    disc = complex(d * d - 4 * m * k)
+    want = np.sort_complex(np.array([(-d + np.sqrt(disc)) / (2 * m), (-d - np.sqrt(disc)) / (2 * m)]))
+    assert np.allclose(lam, want, rtol=1e-12, atol=0)
+
+
+def test_qep_poles_make_the_pencil_singular():
+    rng = np.random.default_rng(4)
+    g = rng.standard_normal((4, 4))
+    mh = g @ g.T + 4 * np.eye(4)
+    g = rng.standard_normal((4, 4))
+    kh = g @ g.T + np.eye(4)
+    dh = 0.05 * mh + 0.02 * kh
+    lam = airga_loop.qep_poles(mh, dh, kh)
+    assert lam.size == 8
+    # closed under conjugation, and each makes lambda^2 M + lambda D + K singular
+    assert np.allclose(np.sort_complex(lam), np.sort_complex(lam.conj()), atol=1e-12)
+    for x in lam:
+        sv = np.linalg.svd(x * x * mh + x * dh + kh, compute_uv=False)
+        assert sv[-1] <= 1e-10 * sv[0]
+
+
+@pytest.mark.parametrize("m,d,k", [(1.0, 0.4, 3.0), (2.5, 1.7, 0.6)])
+def test_h2_one_dof_closed_forms(m, d, k):
+    # (1 / 2 pi) int |1 / (k - m w^2 + i d w)|^2 dw = 1 / (2 d k); with the
+    # velocity output s / (...) it is 1 / (2 m d)
+    pos = airga_loop.h2_distance(one_dof(m, d, k))
+    vel = airga_loop.h2_distance(one_dof(m, d, k, cv=1.0, cp=0.0))
+    assert abs(pos ** 2 - 1 / (2 * d * k)) <= 1e-12 / (2 * d * k)
+    assert abs(vel ** 2 - 1 / (2 * m * d)) <= 1e-12 / (2 * m * d)
+
+
+def random_model(rng, r, m=2, p=1, alpha=0.05, beta=0.02):
+    g = rng.standard_normal((r, r))
+    mh = g @ g.T + r * np.eye(r)
+    g = rng.standard_normal((r, r))
+    kh = g @ g.T + 0.5 * np.eye(r)
+    return airga_loop.Model(mh, alpha * mh + beta * kh, kh, rng.standard_normal((r, m)),
+                            rng.standard_normal((p, r)), rng.standard_normal((p, r)))
+
+
+def test_h2_distance_equals_the_frequency_integral():
+    import scipy.integrate as si
+    rng = np.random.default_rng(8)
+    a, b = random_model(rng, 3), random_model(rng, 2)
+
+    def dens(w):
+        h = a.transfer(1j * w) - b.transfer(1j * w)
+        return float(np.sum(np.abs(h) ** 2))
+    # |H(-iw)| = |H(iw)| for real models: twice the half line, over 2 pi
+    val = 0.0
+    for lo, hi in ((0, 1), (1, 10), (10, 100), (100, np.inf)):
+        val += si.quad(dens, lo, hi, epsabs=0, epsrel=1e-11, limit=400)[0]
+    want = np.sqrt(val / np.pi)
+    assert abs(airga_loop.h2_distance(a, b) - want) <= 1e-7 * want
+
+
+def test_h2_distance_is_a_norm_of_the_difference():
+    rng = np.random.default_rng(9)
+    a = random_model(rng, 4)
+    assert airga_loop.h2_distance(a, a) <= 1e-7 * airga_loop.h2_distance(a)
+    half = airga_loop.Model(a.mh, a.dh, a.kh, 0.5 * a.fh, a.cph, a.cvh)
+    assert abs(airga_loop.h2_distance(a, half) - 0.5 * airga_loop.h2_distance(a)) <= \
+        1e-9 * airga_loop.h2_distance(a)
+
+
+def test_next_shifts_reading_on_a_hand_example():
+    # candidates by |lambda|: -0.5 +- 2i (|.| 2.06) -> 0.5, -3 -> 3,
+    # -1 +- 10i (10.05) -> 1, -40 -> 40; the first three, ascending
+    poles = np.array([-1 + 10j, -1 - 10j, -0.5 + 2j, -0.5 - 2j, -3.0 + 0j, -40.0 + 0j])
+    assert np.array_equal(airga_loop.next_shifts(poles, 3), [0.5, 1.0, 3.0])
+    assert np.array_equal(airga_loop.next_shifts(poles, 4), [0.5, 1.0, 3.0, 40.0])
+    with pytest.raises(ValueError):
+        airga_loop.next_shifts(poles, 5)
+
+
+def beam_system(n_el=60, m=2, alpha=0.1, beta=0.02, seed=3):
+    pen = beam.make_beam(n_el, ei_loguniform=(0.5, 2.0), surrogate=True, seed=seed,
+                         alpha=alpha, beta=beta)
+    n = pen.n
+    ms = pencil.csr(n, pen.row_ptr, pen.col_idx, pen.m_val)
+    ks = pencil.csr(n, pen.row_ptr, pen.col_idx, pen.k_val)
+    f, _ = beam.node_loads(n, m, np.random.default_rng(1))
+    cp = np.zeros((1, n))
+    cp[0, n - 2] = 1.0
+    return pen, ms, ks, f.T, cp
+
+
+def test_airga_iteration_interpolates_at_its_first_expansion_point():
+    # V_1 is the QR of X(sigma_1) = K(sigma_1)^{-1} F, and every final basis
+    # holds it, so each iteration's reduced model equals the full transfer
+    # function at sigma_1 (Section 2)
+    pen, ms, ks, f, cp = beam_system()
+    _, _, hist = airga_loop.airga(ms, ks, pen.alpha, pen.beta, f, cp, None, [1.0, 30.0, 500.0],
+                                  rmax=12, max_outer=3)
+    assert len(hist) == 3
+    for h in hist:
+        s = h["shifts"][h["sigmas"][0]]
+        ksp = (s * s + pen.alpha * s) * ms + (1 + pen.beta * s) * ks
+        full = cp @ np.linalg.solve(ksp.toarray(), f)
+        red = h["model"].transfer(s)
+        assert np.allclose(red, full, rtol=1e-8, atol=1e-14 * np.abs(full).max())
+        assert h["J"] == 12 // 2 and len(h["sigmas"]) == h["J"]
+
+
+def test_real_part_expansion_points_fall_below_the_low_modes():
+    # after the first iteration the new points are |Re lambda| = (alpha +
+    # beta w^2) / 2 of the lowest reduced modes: far below those modes'
+    # frequencies on a lightly damped beam, so the solves there nearly
+    # coincide (the behaviour the design notes record)
+    pen, ms, ks, f, cp = beam_system(alpha=0.01, beta=0.001)
+    _, _, hist = airga_loop.airga(ms, ks, pen.alpha, pen.beta, f, cp, None, [1.0, 30.0, 500.0],
+                                  rmax=12, max_outer=2)
+    lam = airga_loop.qep_poles(hist[0]["model"].mh, hist[0]["model"].dh, hist[0]["model"].kh)
+    w_low = np.sort(np.abs(lam))[0]
+    assert np.all(hist[1]["shifts"] < 0.1 * w_low)
