@@ -17,11 +17,12 @@ H2 change below 1e-6 (Section 5).
 
 The paper leaves these to Bonin et al. and does not fix them; the readings
 taken here (also listed with the design notes) are:
-  A1  the moment error at s_i is ||X^{(j)}(s_i)||_F after the
-      orthogonalisation against V_1..V_j (the part of the newest moment
-      block at s_i the basis does not hold yet); sigma_{j+1} is the s_i
-      with the largest one.  sigma_1 = s_1, since before the first V every
-      block is orthonormal and all errors are equal.
+  A1  the moment error at s_i is the fraction of the newest moment block
+      X^{(j)}(s_i) that the orthogonalisation against V_1..V_j leaves,
+      ||X after||_F / ||X before||_F (the part the basis does not hold
+      yet, independent of the block's scale, which falls like s^-2);
+      sigma_{j+1} is the s_i with the largest one.  sigma_1 = s_1, since
+      before the first V there is nothing to compare.
   A2  "s_i == sigma_j" compares indices, not values.
   A3  the moment loop runs while j < floor(r_max / m), so the final basis
       [V_1..V_J] has J <= floor(r_max / m) blocks.
@@ -148,6 +149,7 @@ def airga(mv, kv, alpha, beta, f, cp, cv, shifts0, rmax, tol_outer=1e-6, tol_inn
         vs = []
         errors = None
         sigmas = []
+        step_errors = []
         inner_changes = []
         prev_int = None
         j = 1
@@ -156,12 +158,15 @@ def airga(mv, kv, alpha, beta, f, cp, cv, shifts0, rmax, tol_outer=1e-6, tol_inn
             sigmas.append(q)
             vs.append(xs[q] / np.linalg.norm(xs[q]))
             xs[q] = -solve(shifts[q], mv @ vs[-1])                       # A2
-            errors = []
+            errors, norms = [], []
             for i in range(l):
+                before = np.linalg.norm(xs[i])
                 xs[i], _, fro = moments.global_orth(vs, xs[i])
-                errors.append(fro)
+                errors.append(fro / before)
+                norms.append(fro)
             errors = np.array(errors)
-            w, _ = moments.thin_qr(np.hstack([xs[i] / errors[i] for i in range(l)]))
+            step_errors.append(errors.copy())
+            w, _ = moments.thin_qr(np.hstack([xs[i] / norms[i] for i in range(l)]))
             model_int = reduce(mv, kv, alpha, beta, f, cp, cv, w)
             if prev_int is not None:
                 change = h2_distance(model_int, prev_int) / h2_distance(model_int)  # A5
@@ -182,6 +187,7 @@ def airga(mv, kv, alpha, beta, f, cp, cv, shifts0, rmax, tol_outer=1e-6, tol_inn
             change = h2_distance(final, prev_final) / h2_distance(final)
         history.append(dict(shifts=shifts.copy(), sigmas=sigmas, J=len(vs),
                             errors=None if errors is None else errors.copy(),
+                            step_errors=step_errors,
                             inner_changes=inner_changes, model=final, change=change))
         prev_final = final
         if change is not None and change < tol_outer:
