@@ -249,6 +249,38 @@ def measure_moments(ctx, stream, dev, n, m, nblocks, nb=4, reps=5):
                      "frac_fp64": round(tf / (t_gram * 1e-3) / FP64_PEAK_TFLOPS, 4)}}
 
 
+def measure_outer(r=64, m=4, p=1, l=16, reps=20, seed=0):
+    """The decisions of AIRGA's outer iteration (host code of the library) at
+    the largest reduced order the block operations take: poles of an order-r
+    reduced pencil, the next l expansion points, and the H2 distance of two
+    order-r models.  Random symmetric positive definite reduced matrices
+    with Rayleigh damping; mean wall time of `reps` calls."""
+    from paper_1606_01216_amd import airga
+    rng = np.random.default_rng(seed)
+
+    def model():
+        g = rng.standard_normal((r, r))
+        mh = g @ g.T + r * np.eye(r)
+        g = rng.standard_normal((r, r))
+        kh = g @ g.T + np.eye(r)
+        return (mh, kh, rng.standard_normal((r, m)), rng.standard_normal((p, r)), None)
+    a, b = model(), model()
+    alpha, beta = 0.05, 0.02
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        poles = airga.qep_poles(a[0], a[1], alpha, beta)
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        airga.next_shifts(poles, l)
+    t2 = time.perf_counter()
+    for _ in range(reps):
+        airga.h2_distance(a, b, alpha, beta)
+    t3 = time.perf_counter()
+    ms = lambda dt: round(dt * 1e3 / reps, 4)  # noqa: E731
+    return {"r": r, "m": m, "p": p, "l": l, "qep_poles_ms": ms(t1 - t0),
+            "next_shifts_ms": ms(t2 - t1), "h2_distance_ms": ms(t3 - t2)}
+
+
 def measure_spai_mr(ctx, stream, shifts, precs, F, X, solve_kw, mr_iters=20, tol=0.01):
     """The paper's minimal-residual SPAI loop (Algorithm 2, option mr_iters)
     against the exact column solves, outside the timed step: build time per
@@ -541,6 +573,8 @@ def main():
     out["moments"] = measure_moments(ctx, stream, dev, n, m, min(S, 64 // m))
     log("[bench] minimal-residual SPAI mode")
     out["spai_mr"] = measure_spai_mr(ctx, stream, list(shifts), precs, F, X1, solve_kw)
+    log("[bench] outer-iteration decisions")
+    out["outer_decisions"] = measure_outer(l=min(S, 64 // m) if m else S)
     if cpu is not None:
         out["cpu_baseline"] = {
             "value": round(2 * B / cpu["seconds"], 3), "unit": "solves/s", "cores": 1,

@@ -384,6 +384,58 @@ AIRGA_API airga_status airga_block_qr(airga_ctx ctx, int32_t k, double* W, int64
 AIRGA_API airga_status airga_project(airga_ctx ctx, int32_t k, const double* W, int64_t ldw,
                                      double* mhat, double* khat);
 
+/* ------------------------------------------ outer iteration decisions
+ *
+ * Host computations behind the decisions of AIRGA's outer iteration
+ * (Algorithm 1): the poles of the reduced quadratic pencil, whose real parts
+ * give the next expansion points (Section 5), and the H2 distance between
+ * reduced models, which ends both of the algorithm's loops (Section 5 uses
+ * 1e-6 for both).  They run on the calling thread, need no context and no
+ * GPU, and are synchronous.  Reduced matrices are host float64,
+ * column-major; the caller owns every array. */
+
+typedef struct {
+  int32_t r, m, p;     /* order, inputs, outputs                          */
+  const double* mhat;  /* r x r, symmetric positive definite              */
+  const double* khat;  /* r x r, symmetric                                */
+  const double* fhat;  /* r x m                                           */
+  const double* cphat; /* p x r: position output                          */
+  const double* cvhat; /* p x r: velocity output, or NULL for none        */
+} airga_reduced_model;
+
+/* The 2r poles of lambda^2 Mh + lambda (alpha Mh + beta Kh) + Kh, the
+ * damping of a projected Rayleigh-damped model (eq. (1.4)): mode by mode in
+ * ascending undamped frequency, two entries per mode in re and im (host,
+ * 2r each): a complex pair as (+im, -im), two real roots the smaller in
+ * magnitude first.  Errors: EINVAL (r <= 0, null arrays, non-finite alpha
+ * or beta), ENOTSPD (Mh not positive definite). */
+AIRGA_API airga_status airga_qep_poles(int32_t r, const double* mhat, const double* khat,
+                                       double alpha, double beta, double* re, double* im);
+
+/* The next l expansion points (shifts, host, l values, ascending) from
+ * `count` poles (re, im, host): each conjugate pair gives one candidate
+ * -Re(lambda), the real part the paper takes (Section 5); each real pole
+ * (|im| <= 1e-12 |lambda|) gives -lambda.  Candidates are ranked by
+ * |lambda|, smallest first, and the first l are taken.  Which poles become
+ * expansion points the paper leaves to Bonin et al.; this ranking is the
+ * library's reading.  Errors: EINVAL (fewer than l candidates, count < 0,
+ * l <= 0, null arrays). */
+AIRGA_API airga_status airga_next_shifts(int32_t count, const double* re, const double* im,
+                                         int32_t l, double* shifts);
+
+/* out = ||H_a - H_b||_H2 (b NULL: ||H_a||_H2) for reduced models with
+ * damping alpha Mh + beta Kh and transfer function
+ * H(s) = (C_p + s C_v) (s^2 Mh + s Dh + Kh)^-1 F_h, from their modal forms
+ * (a closed-form 2 x 2 cross Gramian for each pair of modes).  The models
+ * must share m, p and whether C_v is given.  The distance of nearly equal
+ * models is a difference of squared norms: it is resolved to about 1e-8 of
+ * ||H_a||.  Errors: EINVAL (sizes, null arrays, a mode with
+ * alpha + beta w^2 <= 0, whose norm is infinite), ENOTSPD (an Mh not
+ * positive definite). */
+AIRGA_API airga_status airga_h2_distance(const airga_reduced_model* a,
+                                         const airga_reduced_model* b, double alpha, double beta,
+                                         double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -70,6 +70,12 @@ class SysStats(ctypes.Structure):
                 ("relres", ctypes.c_double)]
 
 
+class ReducedModel(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int32), ("m", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("mhat", ctypes.c_void_p), ("khat", ctypes.c_void_p), ("fhat", ctypes.c_void_p),
+                ("cphat", ctypes.c_void_p), ("cvhat", ctypes.c_void_p)]
+
+
 _lib = None
 
 # (name, restype, argtypes) of every exported entry point
@@ -129,6 +135,12 @@ _SIGS = [
     ("airga_project", ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64,
                                      ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]),
+    ("airga_qep_poles", ctypes.c_int, [ctypes.c_int32, _P, _P, ctypes.c_double, ctypes.c_double,
+                                       _P, _P]),
+    ("airga_next_shifts", ctypes.c_int, [ctypes.c_int32, _P, _P, ctypes.c_int32, _P]),
+    ("airga_h2_distance", ctypes.c_int, [ctypes.POINTER(ReducedModel),
+                                         ctypes.POINTER(ReducedModel), ctypes.c_double,
+                                         ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
 ]
 
 EXPORTED = [s[0] for s in _SIGS]
@@ -166,6 +178,66 @@ def _dev(t: torch.Tensor, dtype, device) -> torch.Tensor:
         raise ValueError(f"expected a contiguous {dtype} tensor on {device}, got "
                          f"{t.dtype} on {t.device}")
     return t
+
+
+# ---- decisions of the outer iteration (host computations, no GPU) --------
+
+def _host(a):
+    """Column-major float64 copy of a host matrix, and its address."""
+    import numpy as np
+    arr = np.asfortranarray(np.asarray(a, dtype=np.float64))
+    return arr, ctypes.c_void_p(arr.ctypes.data)
+
+
+def qep_poles(mh, kh, alpha: float, beta: float):
+    """The 2r poles of lambda^2 Mh + lambda (alpha Mh + beta Kh) + Kh
+    (complex numpy array, two per mode, modes in ascending frequency)."""
+    import numpy as np
+    r = int(np.shape(mh)[0])
+    m_arr, m_p = _host(mh)
+    k_arr, k_p = _host(kh)
+    re = np.zeros(2 * r)
+    im = np.zeros(2 * r)
+    _check(lib().airga_qep_poles(r, m_p, k_p, float(alpha), float(beta),
+                                 ctypes.c_void_p(re.ctypes.data),
+                                 ctypes.c_void_p(im.ctypes.data)))
+    return re + 1j * im
+
+
+def next_shifts(poles, l: int):
+    """The next l expansion points from the poles (ascending numpy array)."""
+    import numpy as np
+    poles = np.asarray(poles, dtype=complex)
+    re = np.ascontiguousarray(poles.real, dtype=np.float64)
+    im = np.ascontiguousarray(poles.imag, dtype=np.float64)
+    out = np.zeros(max(int(l), 1))
+    _check(lib().airga_next_shifts(poles.size, ctypes.c_void_p(re.ctypes.data),
+                                   ctypes.c_void_p(im.ctypes.data), int(l),
+                                   ctypes.c_void_p(out.ctypes.data)))
+    return out[:l]
+
+
+def _model(mod, keep):
+    """ReducedModel for (mh, kh, fh, cph, cvh or None); keep holds the arrays."""
+    mh, kh, fh, cph, cvh = mod
+    arrs = [_host(x) for x in (mh, kh, fh, cph)]
+    cv = _host(cvh) if cvh is not None else (None, None)
+    keep.extend(a for a, _ in arrs)
+    keep.append(cv[0])
+    r, m = arrs[2][0].shape
+    p = arrs[3][0].shape[0]
+    return ReducedModel(r, m, p, arrs[0][1], arrs[1][1], arrs[2][1], arrs[3][1], cv[1])
+
+
+def h2_distance(a, b, alpha: float, beta: float) -> float:
+    """||H_a - H_b||_H2 (b None: ||H_a||_H2); a, b = (mh, kh, fh, cph, cvh or None)."""
+    keep = []
+    ma = _model(a, keep)
+    mb = _model(b, keep) if b is not None else None
+    out = ctypes.c_double()
+    _check(lib().airga_h2_distance(ctypes.byref(ma), ctypes.byref(mb) if mb is not None else None,
+                                   float(alpha), float(beta), ctypes.byref(out)))
+    return out.value
 
 
 class Context:
