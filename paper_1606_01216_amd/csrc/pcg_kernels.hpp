@@ -180,14 +180,24 @@ struct FlagSweep {
   const int32_t* __restrict__ flag;
   int B, c;
   uint64_t mask;
-  __device__ FlagSweep(const int32_t* f, int nb) : flag(f), B(nb), c(-64), mask(0) {}
+  bool pre;    // f0 holds the first chunk's flag of this lane
+  int32_t f0;
+  __device__ FlagSweep(const int32_t* f, int nb) : flag(f), B(nb), c(-64), mask(0), pre(false), f0(0) {}
+  // Loads the first chunk's flags at once, so their latency overlaps the
+  // kernel's set-up loads instead of following them.
+  __device__ FlagSweep(const int32_t* f, int nb, int lane)
+      : flag(f), B(nb), c(-64), mask(0), pre(true), f0(lane < nb ? f[lane] : 0) {}
   template <int U>
   __device__ __forceinline__ bool next(int (&bs)[U], int lane) {
     while (mask == 0) {
       c += 64;
       if (c >= B) return false;
-      const int i = c + lane;
-      mask = __ballot(i < B && flag[i] != 0);
+      if (pre && c == 0) {
+        mask = __ballot(f0 != 0);
+      } else {
+        const int i = c + lane;
+        mask = __ballot(i < B && flag[i] != 0);
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -259,13 +269,17 @@ inline size_t window_lds_bytes(size_t elem, int R, int U) {
 template <typename T, int WMAX, int R, int U, bool ASM, bool EXACT, bool BAND>
 __global__ void __launch_bounds__(256) k_dir_spmv(SolveArgs<T> A, int par) {
   // nothing to do once every system has stopped (the rest of a replayed
-  // round of iterations): return before touching the pencil
-  if (sload(A.sys.nact) == 0) return;
+  // round of iterations): return before the pencil's values are read.  The
+  // count and the first 64 activity flags are fetched beside the slice data,
+  // not ahead of it.
+  const int32_t nact = sload(A.sys.nact);
   const int lane = threadIdx.x & 63;
+  FlagSweep sweep(A.sys.active, A.B, lane);
   const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
   extern __shared__ double lds_part[];
   Rows<WMAX, R, EXACT> rows;
   rows.template load<BAND>(A.pd, wg, lane);
+  if (nact == 0) return;
   T mv[R][WMAX], kv[R][WMAX];
   rows.values(A.mv, mv);
   if constexpr (!ASM) rows.values(A.kv, kv);
@@ -275,7 +289,6 @@ __global__ void __launch_bounds__(256) k_dir_spmv(SolveArgs<T> A, int par) {
     win.init(rows, wg, A.pd.n_slices, A.bw, lane);
     stg = window_base<T, R>(lds_part, A, U);
   }
-  FlagSweep sweep(A.sys.active, A.B);
   int bs[U];
   while (sweep.next(bs, lane)) {
     T pr[U][R], wr[U][R];
@@ -387,20 +400,23 @@ __global__ void __launch_bounds__(256) k_dir_spmv(SolveArgs<T> A, int par) {
 template <typename T, int WMAX, int R, int U, bool INIT, bool EXACT, bool BAND>
 __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
   // nothing to do once every system has stopped (the rest of a replayed
-  // round of iterations): return before touching the pencil
-  if (sload(A.sys.nact) == 0) return;
+  // round of iterations): return before the pencil's values are read.  The
+  // count and the first 64 activity flags are fetched beside the slice data,
+  // not ahead of it.
+  const int32_t nact = sload(A.sys.nact);
   const int lane = threadIdx.x & 63;
+  FlagSweep sweep(A.sys.active, A.B, lane);
   const int wg = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
   extern __shared__ double lds_part[];
   Rows<WMAX, R, EXACT> rows;
   rows.template load<BAND>(A.pd, wg, lane);
+  if (nact == 0) return;
   Window<WMAX, R> win;
   T* stg = nullptr;
   if constexpr (BAND) {
     win.init(rows, wg, A.pd.n_slices, A.bw, lane);
     stg = window_base<T, R>(lds_part, A, U);
   }
-  FlagSweep sweep(A.sys.active, A.B);
   int bs[U];
   // First preconditioner factor of each group slot, kept in registers while
   // the systems swept through the slot belong to the same shift (systems
