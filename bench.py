@@ -249,6 +249,28 @@ def measure_moments(ctx, stream, dev, n, m, nblocks, nb=4, reps=5):
                      "frac_fp64": round(tf / (t_gram * 1e-3) / FP64_PEAK_TFLOPS, 4)}}
 
 
+def measure_copy(stream, dev, mib=1024, reps=5):
+    """A plain device copy of `mib` MiB (float32) on the context stream: read
+    plus written bytes over the median of `reps` event-timed copies, the
+    practical streaming ceiling the row kernels are compared with."""
+    import torch
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    times = []
+    with torch.cuda.stream(stream):
+        dst.copy_(src)
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            dst.copy_(src)
+            e1.record(stream)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+    del src, dst
+    return 2.0 * (mib << 20) / (statistics.median(times) * 1e-3) / 1e9
+
+
 def measure_outer(r=64, m=4, p=1, l=16, reps=20, seed=0):
     """The decisions of AIRGA's outer iteration (host code of the library) at
     the largest reduced order the block operations take: poles of an order-r
@@ -536,6 +558,9 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "avg_launch_us": round(dom["avg_us"], 2),
                 "bytes_per_launch": int(dom["bytes"] / dom["launches"])}
+    copy_gbs = measure_copy(stream, dev)
+    roofline["copy_gbs"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(dom["gbs"] / copy_gbs, 4)
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1,
