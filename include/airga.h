@@ -46,7 +46,9 @@ typedef enum {
   AIRGA_EINVAL = -1,      /* bad argument: null pointer, size, pattern, shift    */
   AIRGA_ENOMEM = -2,      /* device or host allocation failed                    */
   AIRGA_EHIP = -3,        /* a HIP runtime call failed                           */
-  AIRGA_ENOTSPD = -4,     /* K(s) has a non-positive diagonal entry              */
+  AIRGA_ENOTSPD = -4,     /* a matrix that must be positive definite is not:     */
+                          /* K(s) with a non-positive diagonal entry, a reduced  */
+                          /* M, or the Gram matrix of dependent QR columns       */
   AIRGA_ESTATE = -5,      /* call out of order (e.g. no pencil set yet)          */
   AIRGA_EUNSUPPORTED = -6 /* valid input outside the library's supported range   */
 } airga_status;
