@@ -271,6 +271,90 @@ def measure_copy(stream, dev, mib=1024, reps=5):
     return 2.0 * (mib << 20) / (statistics.median(times) * 1e-3) / 1e9
 
 
+def measure_airga_iteration(ctx, stream, F, n, alpha, beta, shifts=(1.0, 30.0, 500.0), rmax=24,
+                            solve_kw=None, tol_inner=1e-6):
+    """One outer iteration of Algorithm 1 at full size, composed from the
+    library's entry points with readings A1-A6 (as the GPU tests run it):
+    SPAI builds and solves at the l expansion points, thin QR of each block,
+    the moment loop (sigma_j by the moment error, moment solves, trace
+    orthogonalisation, intermediate models and their H2 changes), the final
+    basis and model, and the next expansion points.  Output: tip deflection.
+    Wall time of the whole iteration (host decisions included)."""
+    import torch
+    from paper_1606_01216_amd import airga
+    kw = dict(solve_kw or {})
+    m = F.shape[0]
+    l = len(shifts)
+    cp = torch.zeros((1, n), dtype=torch.float64, device=F.device)
+    cp[0, n - 2] = 1.0
+    out = {"n": n, "m": m, "l": l, "rmax": rmax, "shifts": list(shifts)}
+    try:
+        with torch.cuda.stream(stream):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            precs = ctx.spai_build_many(list(shifts))
+            X, _ = ctx.pcg_solve(list(shifts), precs, F, **kw)
+            xs = X.reshape(l * m, n).contiguous()
+            for i in range(l):
+                b = xs[i * m:(i + 1) * m].clone()
+                ctx.block_qr(b)
+                xs[i * m:(i + 1) * m] = b
+
+            def model_of(w):
+                mh, kh = ctx.project(w)
+                return (mh, kh, ctx.gram(w, F).cpu().numpy(), ctx.gram(w, cp).cpu().numpy().T, None)
+
+            def block(q):
+                v = xs[q * m:(q + 1) * m].clone()
+                ctx.global_orth(None, v, m, normalize=True)
+                return v
+            vs, sigmas, changes, iters = [], [], [], []
+            errors, prev = None, None
+            j = 1
+            while j < rmax // m:
+                q = 0 if errors is None else int(np.argmax(errors))
+                sigmas.append(q)
+                vs.append(block(q))
+                y, st = ctx.pcg_solve([shifts[q]], [precs[q]], ctx.pencil_apply(1.0, 0.0, vs[-1]), **kw)
+                iters.append(max(e["iters"] for e in st))
+                xs[q * m:(q + 1) * m] = -y[0]
+                _, before = ctx.global_orth(None, xs.clone(), m)
+                _, after = ctx.global_orth(torch.cat(vs).contiguous(), xs, m)
+                errors = after / before
+                w = xs.clone()
+                ctx.global_orth(None, w, m, normalize=True)
+                ctx.block_qr(w)
+                mi = model_of(w)
+                if prev is not None:
+                    # relative H2 change; None where the norm is not resolved
+                    # (no positive finite value), which never stops the loop
+                    norm = airga.h2_distance(mi, None, alpha, beta)
+                    ch = (airga.h2_distance(mi, prev, alpha, beta) / norm
+                          if np.isfinite(norm) and norm > 0 else None)
+                    changes.append(ch)
+                    if ch is not None and ch < tol_inner:
+                        j += 1
+                        break
+                prev = mi
+                j += 1
+            q = 0 if errors is None else int(np.argmax(errors))
+            sigmas.append(q)
+            vs.append(block(q))
+            v = torch.cat(vs).contiguous()
+            ctx.block_qr(v)
+            final = model_of(v)
+            nxt = airga.next_shifts(airga.qep_poles(final[0], final[1], alpha, beta), l)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        out.update({"ms": round((t1 - t0) * 1e3, 2), "J": len(vs), "sigmas": sigmas,
+                    "moment_solve_iters_max": iters,
+                    "inner_h2_changes": [None if c is None else float(f"{c:.3e}") for c in changes],
+                    "next_shifts": [float(f"{s:.6g}") for s in nxt]})
+    except airga.AirgaError as e:
+        out["error"] = str(e)
+    return out
+
+
 def measure_outer(r=64, m=4, p=1, l=16, reps=20, seed=0):
     """The decisions of AIRGA's outer iteration (host code of the library) at
     the largest reduced order the block operations take: poles of an order-r
@@ -600,6 +684,9 @@ def main():
     out["spai_mr"] = measure_spai_mr(ctx, stream, list(shifts), precs, F, X1, solve_kw)
     log("[bench] outer-iteration decisions")
     out["outer_decisions"] = measure_outer(l=min(S, 64 // m) if m else S)
+    log("[bench] one AIRGA outer iteration")
+    out["airga_iteration"] = measure_airga_iteration(ctx, stream, F, n, pen.alpha, pen.beta,
+                                                     solve_kw=solve_kw)
     if cpu is not None:
         out["cpu_baseline"] = {
             "value": round(2 * B / cpu["seconds"], 3), "unit": "solves/s", "cores": 1,
