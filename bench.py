@@ -429,6 +429,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain float64 comparator")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-airga-iteration", action="store_true",
+                    help="skip the full-size AIRGA iteration (its small solves would enter a "
+                         "profiler's per-kernel averages)")
     ap.add_argument("--quick", action="store_true", help="timed steps only (for profilers)")
     ap.add_argument("--tile", default=None,
                     help="force the tile 'ROWS,SYSTEMS' (matrix rows per wavefront, systems per "
@@ -684,13 +687,14 @@ def main():
     out["spai_mr"] = measure_spai_mr(ctx, stream, list(shifts), precs, F, X1, solve_kw)
     log("[bench] outer-iteration decisions")
     out["outer_decisions"] = measure_outer(l=min(S, 64 // m) if m else S)
-    log("[bench] one AIRGA outer iteration")
-    # the first run also tunes and captures the solves of the new batch
-    # sizes (l m and m systems): reported apart, the second run is `ms`
-    first = measure_airga_iteration(ctx, stream, F, n, pen.alpha, pen.beta, solve_kw=solve_kw)
-    out["airga_iteration"] = measure_airga_iteration(ctx, stream, F, n, pen.alpha, pen.beta,
-                                                     solve_kw=solve_kw)
-    out["airga_iteration"]["first_ms"] = first.get("ms")
+    if not args.no_airga_iteration:
+        log("[bench] one AIRGA outer iteration")
+        # the first run also tunes and captures the solves of the new batch
+        # sizes (l m and m systems): reported apart, the second run is `ms`
+        first = measure_airga_iteration(ctx, stream, F, n, pen.alpha, pen.beta, solve_kw=solve_kw)
+        out["airga_iteration"] = measure_airga_iteration(ctx, stream, F, n, pen.alpha, pen.beta,
+                                                         solve_kw=solve_kw)
+        out["airga_iteration"]["first_ms"] = first.get("ms")
     if cpu is not None:
         out["cpu_baseline"] = {
             "value": round(2 * B / cpu["seconds"], 3), "unit": "solves/s", "cores": 1,

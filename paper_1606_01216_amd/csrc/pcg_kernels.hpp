@@ -427,7 +427,36 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
   int csh[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) csh[u] = -1;
-  while (sweep.next(bs, lane)) {
+  // The restart (INIT, banded, one system per group) moves 8 bytes per row
+  // and system, so each system would otherwise wait out a full load latency:
+  // the next system's r window is loaded before the current one is used.
+  constexpr bool PIPE = INIT && BAND && U == 1;
+  T rpre[R + 2];
+  bool more = sweep.next(bs, lane);
+  if constexpr (PIPE) {
+    if (more) {
+      const T* __restrict__ rin = A.vec(KR0, bs[0]);
+#pragma unroll
+      for (int j = 0; j < R + 2; ++j) rpre[j] = rin[win.src[j]];
+    }
+  }
+  while (more) {
+    int cb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) cb[u] = bs[u];
+    T rcur[R + 2];
+    if constexpr (PIPE) {
+#pragma unroll
+      for (int j = 0; j < R + 2; ++j) rcur[j] = rpre[j];
+    }
+    more = sweep.next(bs, lane);
+    if constexpr (PIPE) {
+      if (more) {
+        const T* __restrict__ rin = A.vec(KR0, bs[0]);
+#pragma unroll
+        for (int j = 0; j < R + 2; ++j) rpre[j] = rin[win.src[j]];
+      }
+    }
     // compute phase: no branches on lane data, so every load of the group
     // can be in flight at once (a missing system aliases the group's first
     // one)
@@ -438,7 +467,7 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
       T rw[U][R + 2], ww[U][R + 2];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int b = bs[u] >= 0 ? bs[u] : bs[0];
+        const int b = cb[u] >= 0 ? cb[u] : cb[0];
         const int sh = b / A.m;
         Ls[u] = sload(A.clen + sh);
         if (sh != csh[u]) {
@@ -452,7 +481,9 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
         const T* __restrict__ x = A.vec(KX, b);
 #pragma unroll
         for (int j = 0; j < R + 2; ++j) {
-          const T rv = rin[win.src[j]];
+          T rv;
+          if constexpr (PIPE) rv = rcur[j];
+          else rv = rin[win.src[j]];
           if constexpr (INIT) {
             ww[u][j] = T(0);
             rw[u][j] = rv;
@@ -497,7 +528,7 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
     } else {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int b = bs[u] >= 0 ? bs[u] : bs[0];
+        const int b = cb[u] >= 0 ? cb[u] : cb[0];
         const int sh = b / A.m;
         Ls[u] = sload(A.clen + sh);
         if (sh != csh[u]) {
@@ -539,7 +570,7 @@ __global__ void __launch_bounds__(256) k_update_prec(SolveArgs<T> A, int par) {
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int b = bs[u];
+      const int b = cb[u];
       if (b < 0) continue;
       const int L = Ls[u];
       T* __restrict__ rout = A.vec(KR0 + (par ^ 1), b);
