@@ -131,3 +131,14 @@ def test_outer_functions_reject_bad_input():
     with pytest.raises(airga.AirgaError) as ei:
         airga.h2_distance(model, other, 0.1, 0.1)
     assert ei.value.status == airga.EINVAL
+
+
+def test_bench_times_the_decisions():
+    # bench.py's host-side measurement runs without a GPU and reports each call
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import bench
+    out = bench.measure_outer(r=8, m=2, p=1, l=3, reps=2)
+    assert out["r"] == 8 and out["l"] == 3
+    assert all(out[k] >= 0 for k in ("qep_poles_ms", "next_shifts_ms", "h2_distance_ms"))
