@@ -402,9 +402,6 @@ __global__ void k_apply_shift(PencilDev pd, double a, double b, const double* __
   y[(int64_t)blockIdx.y * ldy + r] = fma(a, am, b * ak);
 }
 
-// RAII: make the context's device current for the duration of an API call.
-
-
 static airga_status set_pencil_impl(airga_ctx ctx, int32_t n, int64_t nnz, const int32_t* row_ptr,
                                     const int32_t* col_idx, const double* m_val,
                                     const double* k_val, double alpha, double beta) {
