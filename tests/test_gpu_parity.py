@@ -361,6 +361,28 @@ def test_edge_cases(ctx):
     assert st[0]["status"] == airga.SYS_CONVERGED and rel_err(X.cpu().numpy()[0, 0], ref[0, 0]) < 1e-12
 
 
+def test_batch_with_a_ragged_second_chunk_of_systems(ctx):
+    """70 systems (14 shifts x 5 columns): the row kernels read the systems'
+    activity flags 64 at a time, so the second chunk holds 6 systems; they
+    converge at different iterations across both chunks."""
+    pen = sur_beam(300)
+    set_pencil(ctx, pen)
+    rng = np.random.default_rng(21)
+    f = rng.standard_normal((5, pen.n))
+    shifts = list(np.logspace(0, 3, 14))
+    precs = ctx.spai_build_many(shifts)
+    ref = reference(pen, shifts, f)
+    for mode in (airga.MODE_FP64, airga.MODE_MIXED):
+        X, st = ctx.pcg_solve(shifts, precs, to_dev(f, torch.float64), mode=mode, tol=1e-10)
+        assert len(st) == 70 and all(e["status"] == airga.SYS_CONVERGED for e in st)
+        iters = [e["iters"] for e in st]
+        assert len(set(iters)) > 1
+        Xh = X.cpu().numpy()
+        for k in range(14):
+            for c in range(5):
+                assert rel_err(Xh[k, c], ref[k, c]) < SOLVE_TOL, (mode, k, c)
+
+
 def test_warm_start_graph_and_profile_agree(ctx):
     pen = sur_beam(1037)
     set_pencil(ctx, pen)
