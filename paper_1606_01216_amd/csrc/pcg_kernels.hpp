@@ -212,6 +212,44 @@ struct FlagSweep {
   }
 };
 
+// FlagSweep's systems grouped by column: within each chunk of 64 systems,
+// those with b % m == 0 first, then b % m == 1, and so on (ascending within a
+// column).  Systems are numbered shift-major (b = shift * m + column), so a
+// wavefront meets each right-hand-side column once per chunk and can keep
+// its values.  m = 1 gives FlagSweep's order.
+struct ColumnSweep {
+  const int32_t* __restrict__ flag;
+  int B, m, c, col;
+  uint64_t chunk, mask;
+  __device__ ColumnSweep(const int32_t* f, int nb, int mcols)
+      : flag(f), B(nb), m(mcols), c(-64), col(0), chunk(0), mask(0) {}
+  template <int U>
+  __device__ __forceinline__ bool next(int (&bs)[U], int lane) {
+    while (mask == 0) {
+      if (chunk != 0 && ++col < m) {
+        mask = chunk & __ballot(((c + lane) % m) == col);
+        continue;
+      }
+      c += 64;
+      if (c >= B) return false;
+      const int i = c + lane;
+      chunk = __ballot(i < B && flag[i] != 0);
+      col = 0;
+      mask = chunk & __ballot((i % m) == 0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (mask) {
+        bs[u] = c + __builtin_ctzll(mask);
+        mask &= mask - 1;
+      } else {
+        bs[u] = -1;
+      }
+    }
+    return true;
+  }
+};
+
 // Banded staging (pencils of bandwidth <= 64).  A wavefront's R slices and
 // the bw rows on each side of them are staged in LDS, one (R + 2) x 64
 // window per system of the group, so the column entries of a row are read
@@ -684,7 +722,12 @@ __global__ void __launch_bounds__(256) k_residual(SolveArgs<TO> A, const double*
     win.init(rows, wg, A.pd.n_slices, A.bw, lane);
     stg = window_base_as<double, R>(lds_part, A.stage_off, U);
   }
-  FlagSweep sweep(A.sys.outer, A.B);
+  // systems grouped by column of F, whose own-row values are then loaded
+  // once per column and chunk instead of once per system (without a column
+  // map; with one, each system loads its own)
+  ColumnSweep sweep(A.sys.outer, A.B, A.fmap ? 1 : A.m);
+  double fcache[R];
+  int fcol = -1;
   int bs[U];
   while (sweep.next(bs, lane)) {
     double res[U][R], fr[U][R], xo[U][R];
@@ -755,17 +798,26 @@ __global__ void __launch_bounds__(256) k_residual(SolveArgs<TO> A, const double*
 #pragma unroll
         for (int i = 0; i < R; ++i) am[u][i] = ak[u][i] = xo[u][i] = 0.0;
     }
+    if (!A.fmap && bs[0] % A.m != fcol) {
+      // every system of the group has this column
+      fcol = bs[0] % A.m;
+      const double* __restrict__ f = F + (int64_t)fcol * ldf;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int64_t row = rows.row[i];
+        fcache[i] = f[row < n ? row : n - 1];
+      }
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int b = bs[u] >= 0 ? bs[u] : bs[0];
       const double a = sload(ca64 + b / A.m), cbv = sload(cb64 + b / A.m);
-      const int fc = A.fmap ? sload(A.fmap + b) : b % A.m;
-      const double* __restrict__ f = F + (int64_t)fc * ldf;
+      const double* __restrict__ f = A.fmap ? F + (int64_t)sload(A.fmap + b) * ldf : nullptr;
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         const int64_t row = rows.row[i];
         const bool in = row < n;
-        const double fv = f[in ? row : n - 1];
+        const double fv = A.fmap ? f[in ? row : n - 1] : fcache[i];
         fr[u][i] = in ? fv : 0.0;
         res[u][i] = in ? fv - fma(a, am[u][i], cbv * ak[u][i]) : 0.0;
         xo[u][i] = in ? xo[u][i] : 0.0;
