@@ -101,6 +101,7 @@ struct Pencil {
   double gram_mm = 0, gram_mk = 0, gram_kk = 0, tr_m = 0, tr_k = 0;
   bool diag_ok = false;  // M_rr > 0 and K_rr >= 0 for every row
   bool uniform_width = false;  // every slice is max_len entries wide
+  bool contiguous = false;     // every row's columns are consecutive
   DevBuf slice_ptr, row_len, col, mirror, csr_pos, diag_pos, m64, k64, m32, k32;
   DevBuf coff;        // int8 column offsets (banded pencils)
   DevBuf setup;       // scratch of set_pencil (pattern summary, per-slice data)

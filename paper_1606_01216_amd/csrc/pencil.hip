@@ -113,6 +113,7 @@ enum PatternFlag : int32_t {
   F_NO_DIAG = 16,    // diagonal missing
   F_ENDS = 32,       // row_ptr[0] != 0 or row_ptr[n] != nnz
   F_ASYM = 64,       // pattern not structurally symmetric
+  F_GAPPED = 128,    // not an error: a row's columns are not consecutive
 };
 
 // One thread per (padded) row; a 256-thread block covers four slices, so each
@@ -143,6 +144,7 @@ __global__ void k_rows_check(int32_t n, int64_t nnz, int64_t n_pad, const int32_
           continue;
         }
         if (c <= prev) bad |= F_UNSORTED;
+        if (prev >= 0 && c != prev + 1) bad |= F_GAPPED;
         prev = c;
         if (c == r) diag = true;
         const int d = c > r ? (int)(c - r) : (int)(r - c);
@@ -441,7 +443,7 @@ static airga_status set_pencil_impl(airga_ctx ctx, int32_t n, int64_t nnz, const
   std::memcpy(&h, ctx->host_pinned, sizeof h);
   if (h.flags & F_TOO_LONG)
     return fail(AIRGA_EUNSUPPORTED, "pattern has a row longer than %d entries", kMaxRow);
-  if (h.flags) {
+  if (h.flags & ~F_GAPPED) {
     std::string why;
     if (h.flags & F_ROWPTR) why += " row_ptr out of order or range;";
     if (h.flags & F_COL_RANGE) why += " column index out of range;";
@@ -480,6 +482,7 @@ static airga_status set_pencil_impl(airga_ctx ctx, int32_t n, int64_t nnz, const
   pen.nnz = nnz;
   pen.nnz_stored = stored;
   pen.uniform_width = stored == (int64_t)ns * kSlice * h.maxlen;
+  pen.contiguous = (h.flags & F_GAPPED) == 0;
   pen.max_len = h.maxlen;
   pen.bandwidth = h.bw;
   pen.alpha = alpha;

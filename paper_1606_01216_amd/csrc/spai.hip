@@ -548,7 +548,7 @@ __host__ __device__ inline size_t spai_band_lds(int bw, bool update) {
 // Khat_new, vo = Khat_old, cl = columns, ln = lengths, window rows from
 // w0, S per entry slot); update: skip test first (al = the update's alpha).
 // Returns whether the column was skipped.
-template <int MJ, bool UPDATE, bool RANGE>
+template <int MJ, bool UPDATE, int RANGE>
 __device__ __forceinline__ bool spai_band_column(const PencilDev& pd, const double* vn,
                                                  const double* vo, const int32_t* cl,
                                                  const int32_t* ln, int S, int64_t w0,
@@ -591,7 +591,7 @@ __device__ __forceinline__ bool spai_band_column(const PencilDev& pd, const doub
 #pragma unroll
       for (int q = 0; q < MJ; ++q) qtb[q] = 0.0;
       double res2 = 0.0;
-      if constexpr (RANGE) {
+      if constexpr (RANGE != 0) {
         // Narrow band: the rows I lie in [lo, hi], the span of the patterns
         // of the columns J; each row in it is folded once, in ascending
         // order (rows outside I have v = 0 and rhs = 0 and change nothing).
@@ -605,6 +605,36 @@ __device__ __forceinline__ bool spai_band_column(const PencilDev& pd, const doub
             hi = last > hi ? last : hi;
           }
         }
+        if constexpr (RANGE == 2) {
+          // every row's columns are consecutive, and so are the columns J:
+          // column J_0 + u of row i sits in its slot J_0 + u - (row i's first
+          // column), so each value is one indexed read instead of a match
+          // against every slot (the same values, folded in the same order)
+          const int J0 = J[0];
+          for (int i = lo; i <= hi; ++i) {
+            const int ir = (int)(i - w0);
+            const int i0 = cl[ir], li = ln[ir];
+            double v[MJ];
+#pragma unroll
+            for (int u = 0; u < MJ; ++u) {
+              const int q = J0 + u - i0;
+              const bool ok = u < nj && q >= 0 && q < li;
+              const double val = vn[(ok ? q : 0) * S + ir];
+              v[u] = ok ? val : 0.0;
+            }
+            double rhs;
+            if constexpr (UPDATE) {
+              const int qj = (int)j - i0;
+              const bool okj = qj >= 0 && qj < li;
+              const double vj = vo[(okj ? qj : 0) * S + ir];
+              rhs = okj ? vj : 0.0;
+            } else {
+              rhs = i == (int)j ? 1.0 : 0.0;
+            }
+            givens_row<MJ>(R, qtb, v, rhs, nj);
+            res2 = fma(rhs, rhs, res2);
+          }
+        } else {
         for (int i = lo; i <= hi; ++i) {
           const int ir = (int)(i - w0);
           double v[MJ];
@@ -621,6 +651,7 @@ __device__ __forceinline__ bool spai_band_column(const PencilDev& pd, const doub
           }
           givens_row<MJ>(R, qtb, v, rhs, nj);
           res2 = fma(rhs, rhs, res2);
+        }
         }
       } else {
 #pragma unroll
@@ -681,7 +712,7 @@ __device__ __forceinline__ bool spai_band_column(const PencilDev& pd, const doub
   return skipped;
 }
 
-template <int MJ, bool UPDATE, bool RANGE>
+template <int MJ, bool UPDATE, int RANGE>
 __global__ void __launch_bounds__(256) k_spai_band(PencilDev pd, double a, double b, double ao,
                                                    double bo, const double* __restrict__ dinv,
                                                    int bw, const double* __restrict__ alpha_u,
@@ -858,7 +889,7 @@ __host__ __device__ inline size_t spai_build_many_lds(int bw) {
 // for each shift): the block's rows are staged once (M, K, columns), then per
 // shift the window's diagonal scaling is staged, the scaled values formed as
 // k_spai_band forms them and the columns solved.  hat: [count][stored].
-template <int MJ, bool RANGE>
+template <int MJ, int RANGE>
 __global__ void __launch_bounds__(256) k_spai_build_many(PencilDev pd, UpdMany U,
                                                          const double* __restrict__ dinv,
                                                          int64_t n_pad, int64_t stored, int bw,
@@ -924,7 +955,7 @@ __global__ void __launch_bounds__(256) k_spai_build_many(PencilDev pd, UpdMany U
 // The banded update column kernel for every shift of the batch: the block's
 // rows are staged once (M, K, columns), then per shift their scaled values
 // are formed and the columns solved as in k_spai_band.  hat: [count][stored].
-template <int MJ, bool RANGE>
+template <int MJ, int RANGE>
 __global__ void __launch_bounds__(256) k_spai_update_many(PencilDev pd, UpdMany U,
                                                           const double* __restrict__ dinv,
                                                           int64_t n_pad, int64_t stored, int bw,
@@ -1210,20 +1241,26 @@ static void launch_band(airga_ctx ctx, double a, double b, double ao, double bo,
   const PencilDev pd = pen.dev();
   if (pen.max_len <= 6) {
     const size_t lds = spai_band_lds<6>(bw, UPDATE);
-    if (range)
-      k_spai_band<6, UPDATE, true><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw, alpha_u, tol,
-                                                         hat, obj, skip, skipf);
+    if (range && pen.contiguous)
+      k_spai_band<6, UPDATE, 2><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw, alpha_u, tol,
+                                                      hat, obj, skip, skipf);
+    else if (range)
+      k_spai_band<6, UPDATE, 1><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw, alpha_u, tol,
+                                                      hat, obj, skip, skipf);
     else
-      k_spai_band<6, UPDATE, false><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw, alpha_u, tol,
-                                                          hat, obj, skip, skipf);
+      k_spai_band<6, UPDATE, 0><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw, alpha_u, tol,
+                                                      hat, obj, skip, skipf);
   } else {
     const size_t lds = spai_band_lds<kSpaiMaxJ>(bw, UPDATE);
-    if (range)
-      k_spai_band<kSpaiMaxJ, UPDATE, true><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw,
-                                                                 alpha_u, tol, hat, obj, skip, skipf);
+    if (range && pen.contiguous)
+      k_spai_band<kSpaiMaxJ, UPDATE, 2><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw,
+                                                              alpha_u, tol, hat, obj, skip, skipf);
+    else if (range)
+      k_spai_band<kSpaiMaxJ, UPDATE, 1><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw,
+                                                              alpha_u, tol, hat, obj, skip, skipf);
     else
-      k_spai_band<kSpaiMaxJ, UPDATE, false><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw,
-                                                                  alpha_u, tol, hat, obj, skip, skipf);
+      k_spai_band<kSpaiMaxJ, UPDATE, 0><<<nb, 256, lds, st>>>(pd, a, b, ao, bo, dinv, bw,
+                                                              alpha_u, tol, hat, obj, skip, skipf);
   }
 }
 
@@ -1391,10 +1428,12 @@ static airga_status run_build_many(airga_ctx ctx, int32_t count, const double* s
     }
     k_dinv_many<<<nr, 256, 0, st>>>(pd, U, o.equilibrate, n_pad, dinv);
     AIRGA_HIP(hipGetLastError());
-    if (range)
-      k_spai_build_many<6, true><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, hat);
+    if (range && pen.contiguous)
+      k_spai_build_many<6, 2><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, hat);
+    else if (range)
+      k_spai_build_many<6, 1><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, hat);
     else
-      k_spai_build_many<6, false><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, hat);
+      k_spai_build_many<6, 0><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, hat);
     AIRGA_HIP(hipGetLastError());
     for (int i = 0; i < cnt; ++i) {
       const airga_prec p = ps[i0 + i];
@@ -1460,12 +1499,15 @@ static airga_status run_update_many(airga_ctx ctx, int32_t count, const airga_pr
     k_alpha_final_many<<<(unsigned)cnt, 256, 0, st>>>(U, part, nb);
     AIRGA_HIP(hipGetLastError());
     const size_t lds = spai_many_lds<6>(bw);
-    if (range)
-      k_spai_update_many<6, true><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, o.tol, hat,
-                                                        skp);
+    if (range && pen.contiguous)
+      k_spai_update_many<6, 2><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, o.tol, hat,
+                                                     skp);
+    else if (range)
+      k_spai_update_many<6, 1><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, o.tol, hat,
+                                                     skp);
     else
-      k_spai_update_many<6, false><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, o.tol,
-                                                         hat, skp);
+      k_spai_update_many<6, 0><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, o.tol, hat,
+                                                     skp);
     AIRGA_HIP(hipGetLastError());
     k_sum_counts_many<<<(unsigned)cnt, 256, 0, st>>>(U, skp, nb);
     AIRGA_HIP(hipGetLastError());
