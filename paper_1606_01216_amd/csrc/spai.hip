@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, const double* _
 // It stops once |r| <= tol |t|, when (w, w) is not positive, or after maxit
 // steps.  The update's start test is the exact mode's skip test, so a column
 // that takes no step is flagged as alpha e_j.
-template <int MJ, bool UPDATE>
+template <int MJ, bool UPDATE, bool CONTIG>
 __global__ void __launch_bounds__(256) k_spai_mr(PencilDev pd, const double* __restrict__ ahat,
                                                  const double* __restrict__ aold,
                                                  const double* __restrict__ alpha_d, double tol,
@@ -421,6 +421,64 @@ __global__ void __launch_bounds__(256) k_spai_mr(PencilDev pd, const double* __r
 #pragma unroll
       for (int q = 0; q < MJ; ++q) g[q] = tJ[q] = 0.0;
       double t2 = 0.0;
+      // folds one row (v, rhs) of Khat(I, J) and t(I) into the local data
+      auto fold = [&](int i, const double (&v)[MJ], double rhs) {
+#pragma unroll
+        for (int u = 0; u < MJ; ++u) {
+#pragma unroll
+          for (int w = u; w < MJ; ++w) G[tri<MJ>(u, w)] = fma(v[u], v[w], G[tri<MJ>(u, w)]);
+          g[u] = fma(v[u], rhs, g[u]);
+        }
+        t2 = fma(rhs, rhs, t2);
+#pragma unroll
+        for (int w = 0; w < MJ; ++w) {
+          if (w < nj && J[w] == i) {
+            tJ[w] = rhs;
+#pragma unroll
+            for (int u = w; u < MJ; ++u) KJ[tri<MJ>(w, u)] = v[u];
+          }
+        }
+      };
+      if constexpr (CONTIG) {
+        // every row's columns are consecutive: the rows I are the span of
+        // the patterns of J, each met once in ascending order, and column
+        // J_0 + u of row i sits in its slot J_0 + u - (row i's first column)
+        const int J0 = J[0];
+        int lo = (int)j, hi = (int)j;
+#pragma unroll
+        for (int t = 0; t < MJ; ++t) {
+          if (t < nj) {
+            const int k = J[t];
+            const int32_t base_k = pd.slice_ptr[k / kSlice] + (k % kSlice);
+            const int first = pd.col[base_k], last = pd.col[base_k + (pd.row_len[k] - 1) * kSlice];
+            lo = first < lo ? first : lo;
+            hi = last > hi ? last : hi;
+          }
+        }
+        for (int i = lo; i <= hi; ++i) {
+          const int32_t base_i = pd.slice_ptr[i / kSlice] + (i % kSlice);
+          const int ni = pd.row_len[i];
+          const int i0 = pd.col[base_i];
+          double v[MJ];
+#pragma unroll
+          for (int u = 0; u < MJ; ++u) {
+            const int q = J0 + u - i0;
+            const bool ok = u < nj && q >= 0 && q < ni;
+            const double val = ahat[base_i + (ok ? q : 0) * kSlice];
+            v[u] = ok ? val : 0.0;
+          }
+          double rhs;
+          if constexpr (UPDATE) {
+            const int qj = (int)j - i0;
+            const bool okj = qj >= 0 && qj < ni;
+            const double vj = aold[base_i + (okj ? qj : 0) * kSlice];
+            rhs = okj ? vj : 0.0;
+          } else {
+            rhs = i == (int)j ? 1.0 : 0.0;
+          }
+          fold(i, v, rhs);
+        }
+      } else {
 #pragma unroll
       for (int t = 0; t < MJ; ++t) {
         if (t < nj) {
@@ -455,23 +513,10 @@ __global__ void __launch_bounds__(256) k_spai_mr(PencilDev pd, const double* __r
             }
             if constexpr (!UPDATE) rhs = (i == (int)j) ? 1.0 : 0.0;
             if (umin < t) continue;
-#pragma unroll
-            for (int u = 0; u < MJ; ++u) {
-#pragma unroll
-              for (int w = u; w < MJ; ++w) G[tri<MJ>(u, w)] = fma(v[u], v[w], G[tri<MJ>(u, w)]);
-              g[u] = fma(v[u], rhs, g[u]);
-            }
-            t2 = fma(rhs, rhs, t2);
-#pragma unroll
-            for (int w = 0; w < MJ; ++w) {
-              if (w < nj && J[w] == i) {
-                tJ[w] = rhs;
-#pragma unroll
-                for (int u = w; u < MJ; ++u) KJ[tri<MJ>(w, u)] = v[u];
-              }
-            }
+            fold(i, v, rhs);
           }
         }
+      }
       }
       // symmetric packed products
       auto symv = [&](const double (&S)[NT], const double (&x)[MJ], double (&y)[MJ]) {
@@ -1287,12 +1332,19 @@ static void launch_mr(airga_ctx ctx, const SpaiScratch& w, const double* alpha, 
                       int maxit, double* obj, int32_t* skip, int8_t* skipf) {
   const Pencil& pen = ctx->pen;
   const unsigned nb = blocks_for(pen.n, 256);
-  if (pen.max_len <= 6)
-    k_spai_mr<6, UPDATE><<<nb, 256, 0, ctx->stream>>>(pen.dev(), w.ahat, w.aold, alpha, tol, maxit,
-                                                     w.hat, obj, skip, skipf);
+  const PencilDev pd = pen.dev();
+  if (pen.max_len <= 6 && pen.contiguous)
+    k_spai_mr<6, UPDATE, true><<<nb, 256, 0, ctx->stream>>>(pd, w.ahat, w.aold, alpha, tol, maxit,
+                                                           w.hat, obj, skip, skipf);
+  else if (pen.max_len <= 6)
+    k_spai_mr<6, UPDATE, false><<<nb, 256, 0, ctx->stream>>>(pd, w.ahat, w.aold, alpha, tol, maxit,
+                                                            w.hat, obj, skip, skipf);
+  else if (pen.contiguous)
+    k_spai_mr<kSpaiMaxJ, UPDATE, true><<<nb, 256, 0, ctx->stream>>>(pd, w.ahat, w.aold, alpha, tol,
+                                                                   maxit, w.hat, obj, skip, skipf);
   else
-    k_spai_mr<kSpaiMaxJ, UPDATE><<<nb, 256, 0, ctx->stream>>>(pen.dev(), w.ahat, w.aold, alpha, tol,
-                                                             maxit, w.hat, obj, skip, skipf);
+    k_spai_mr<kSpaiMaxJ, UPDATE, false><<<nb, 256, 0, ctx->stream>>>(pd, w.ahat, w.aold, alpha, tol,
+                                                                    maxit, w.hat, obj, skip, skipf);
 }
 
 static airga_status run_build(airga_ctx ctx, double s, const airga_spai_opts& o, airga_prec p) {
