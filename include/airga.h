@@ -409,8 +409,8 @@ typedef struct {
  * damping of a projected Rayleigh-damped model (eq. (1.4)): mode by mode in
  * ascending undamped frequency, two entries per mode in re and im (host,
  * 2r each): a complex pair as (+im, -im), two real roots the smaller in
- * magnitude first.  Errors: EINVAL (r <= 0, null arrays, non-finite alpha
- * or beta), ENOTSPD (Mh not positive definite). */
+ * magnitude first.  Errors: EINVAL (r <= 0, null arrays, non-finite alpha,
+ * beta or matrix entries), ENOTSPD (Mh not positive definite). */
 AIRGA_API airga_status airga_qep_poles(int32_t r, const double* mhat, const double* khat,
                                        double alpha, double beta, double* re, double* im);
 
@@ -421,7 +421,7 @@ AIRGA_API airga_status airga_qep_poles(int32_t r, const double* mhat, const doub
  * |lambda|, smallest first, and the first l are taken.  Which poles become
  * expansion points the paper leaves to Bonin et al.; this ranking is the
  * library's reading.  Errors: EINVAL (fewer than l candidates, count < 0,
- * l <= 0, null arrays). */
+ * l <= 0, null arrays, non-finite poles). */
 AIRGA_API airga_status airga_next_shifts(int32_t count, const double* re, const double* im,
                                          int32_t l, double* shifts);
 
@@ -431,9 +431,9 @@ AIRGA_API airga_status airga_next_shifts(int32_t count, const double* re, const 
  * (a closed-form 2 x 2 cross Gramian for each pair of modes).  The models
  * must share m, p and whether C_v is given.  The distance of nearly equal
  * models is a difference of squared norms: it is resolved to about 1e-8 of
- * ||H_a||.  Errors: EINVAL (sizes, null arrays, a mode with
- * alpha + beta w^2 <= 0, whose norm is infinite), ENOTSPD (an Mh not
- * positive definite). */
+ * ||H_a||.  Errors: EINVAL (sizes, null arrays, non-finite alpha, beta or
+ * matrix entries, a mode with alpha + beta w^2 <= 0, whose norm is
+ * infinite), ENOTSPD (an Mh not positive definite). */
 AIRGA_API airga_status airga_h2_distance(const airga_reduced_model* a,
                                          const airga_reduced_model* b, double alpha, double beta,
                                          double* out);

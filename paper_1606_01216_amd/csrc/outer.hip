@@ -113,7 +113,15 @@ struct Modal {
   std::vector<double> w2, phi;
 };
 
+bool all_finite(const double* v, size_t count) {
+  for (size_t i = 0; i < count; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
 airga_status modal(int r, const double* mh, const double* kh, Modal* out) {
+  if (!all_finite(mh, (size_t)r * r) || !all_finite(kh, (size_t)r * r))
+    return fail(AIRGA_EINVAL, "reduced M and K must be finite");
   std::vector<double> l(mh, mh + (size_t)r * r);
   // symmetric part of the input (projections are symmetric to rounding)
   for (int j = 0; j < r; ++j)
@@ -229,6 +237,10 @@ airga_status check_model(const airga_reduced_model* a) {
   if (!a || a->r <= 0 || a->m <= 0 || a->p <= 0 || !a->mhat || !a->khat || !a->fhat ||
       !a->cphat)
     return fail(AIRGA_EINVAL, "reduced model: r, m, p must be positive and M, K, F, C_p given");
+  const size_t rm = (size_t)a->r * a->m, pr = (size_t)a->p * a->r;
+  if (!all_finite(a->fhat, rm) || !all_finite(a->cphat, pr) ||
+      (a->cvhat && !all_finite(a->cvhat, pr)))
+    return fail(AIRGA_EINVAL, "reduced model: F and C must be finite");
   return AIRGA_OK;
 }
 
@@ -272,6 +284,8 @@ airga_status airga_next_shifts(int32_t count, const double* re, const double* im
                                double* shifts) {
   if (count < 0 || l <= 0 || !re || !im || !shifts)
     return fail(AIRGA_EINVAL, "next_shifts: count >= 0, l > 0 and every array given");
+  if (!all_finite(re, (size_t)count) || !all_finite(im, (size_t)count))
+    return fail(AIRGA_EINVAL, "next_shifts: poles must be finite");
   struct Cand {
     double mag, shift;
   };
@@ -293,6 +307,8 @@ airga_status airga_next_shifts(int32_t count, const double* re, const double* im
 airga_status airga_h2_distance(const airga_reduced_model* a, const airga_reduced_model* b,
                                double alpha, double beta, double* out) {
   if (!out) return fail(AIRGA_EINVAL, "h2_distance: null output");
+  if (!std::isfinite(alpha) || !std::isfinite(beta))
+    return fail(AIRGA_EINVAL, "h2_distance: alpha and beta must be finite");
   AIRGA_TRY(check_model(a));
   if (b) {
     AIRGA_TRY(check_model(b));

@@ -131,6 +131,25 @@ def test_outer_functions_reject_bad_input():
     with pytest.raises(airga.AirgaError) as ei:
         airga.h2_distance(model, other, 0.1, 0.1)
     assert ei.value.status == airga.EINVAL
+    # non-finite entries anywhere are rejected, not carried into the result
+    bad = eye.copy()
+    bad[0, 1] = bad[1, 0] = np.nan
+    for mh, kh in ((bad, eye), (eye, bad)):
+        with pytest.raises(airga.AirgaError) as ei:
+            airga.qep_poles(mh, kh, 0.1, 0.1)
+        assert ei.value.status == airga.EINVAL
+    for m_ in ((bad, eye, np.ones((3, 1)), np.ones((1, 3)), None),
+               (eye, eye, np.full((3, 1), np.inf), np.ones((1, 3)), None),
+               (eye, eye, np.ones((3, 1)), np.ones((1, 3)), np.full((1, 3), np.nan))):
+        with pytest.raises(airga.AirgaError) as ei:
+            airga.h2_distance(m_, None, 0.1, 0.1)
+        assert ei.value.status == airga.EINVAL
+    with pytest.raises(airga.AirgaError) as ei:
+        airga.h2_distance(model, None, float("nan"), 0.1)
+    assert ei.value.status == airga.EINVAL
+    with pytest.raises(airga.AirgaError) as ei:
+        airga.next_shifts(np.array([1.0, np.nan]) + 0j, 1)
+    assert ei.value.status == airga.EINVAL
 
 
 def test_bench_times_the_decisions():
