@@ -1,0 +1,79 @@
+"""Host-side logic of bench.py, without a GPU: the one-GPU refusal, the HBM
+traffic table (looked up only while the row kernels' sources are unchanged)
+and the scaling of hardware byte counters by a copy of known size."""
+import argparse
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    msg = json.loads(p.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_traffic_table_applies_only_to_the_sources_it_was_taken_on(monkeypatch):
+    path = bench.traffic_file("c4s")
+    with open(path) as fh:
+        tab = json.load(fh)
+    tile = next(iter(tab["tiles"]))
+    r, u = (int(v) for v in tile.split("x"))
+    want = tab["tiles"][tile]["update_prec"]["hbm_bytes_per_launch"]
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: tab["source_hash"])
+    assert bench.measured_traffic("c4s", (r, u), "update_prec") == want
+    assert bench.measured_traffic("c4s", (r + 1, u), "update_prec") is None
+    assert bench.measured_traffic("no-such-workload", (r, u), "update_prec") is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.measured_traffic("c4s", (r, u), "update_prec") is None
+
+
+def _counter_csv(path, counter, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Grid_Size",
+                                           "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for i, (name, grid, value) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i, "Kernel_Name": name, "Grid_Size": grid,
+                        "Counter_Name": counter, "Counter_Value": value})
+
+
+def test_counters_are_scaled_by_the_copy_and_taken_after_the_last_clear(tmp_path):
+    # A 1 GiB copy whose FETCH_SIZE reads half of its bytes (in KiB) and whose
+    # WRITE_SIZE reads all of them: fetch counts are doubled, writes kept.
+    # Only launches after the last k_clear_active count (the second solve).
+    upd = "void airga::k_update_prec<float, 6, 4, 1, false, true, true>(airga::SolveArgs<float>, int)"
+    dsp = "void airga::k_dir_spmv<float, 6, 4, 1, false, true, true>(airga::SolveArgs<float>, int)"
+    clear = "airga::k_clear_active(airga::SysDev, int)"
+    copy = "__amd_rocclr_copyBuffer"
+    gib_kib = 1024.0 * 1024.0
+    for counter, copy_kib, scale in (("FETCH_SIZE", gib_kib / 2, 2.0), ("WRITE_SIZE", gib_kib, 1.0)):
+        sub = "fetch" if counter == "FETCH_SIZE" else "write"
+        rows = [(upd, 1000, 999999.0), (clear, 64, 1.0),
+                (upd, 1000, 100.0), (dsp, 1000, 40.0), (upd, 1000, 300.0), (dsp, 1000, 60.0),
+                (copy, 1 << 17, copy_kib), (copy, 512, 3.0)]
+        _counter_csv(str(tmp_path / "pmc" / f"256x1_{sub}" / "c4s_counter_collection.csv"),
+                     counter, rows)
+    out = tmp_path / "table.json"
+    args = argparse.Namespace(summarize_pmc=str(tmp_path / "pmc"), workload="c4s",
+                              command="(test)", out=str(out))
+    bench.summarize_pmc(args)
+    tab = json.loads(out.read_text())
+    ent = tab["tiles"]["256x1"]
+    assert ent["update_prec"]["launches"] == 2 and ent["dir_spmv"]["launches"] == 2
+    assert ent["update_prec"]["fetch_size_bytes_per_launch"] == int(200.0 * 1024 * 2.0)
+    assert ent["update_prec"]["write_size_bytes_per_launch"] == int(200.0 * 1024 * 1.0)
+    assert ent["dir_spmv"]["hbm_bytes_per_launch"] == int(50.0 * 1024 * 2.0) + int(50.0 * 1024)
+    assert ent["update_prec"]["fetch_size_scale"] == pytest.approx(2.0)
+    assert tab["source_hash"] == bench.kernel_source_hash()
