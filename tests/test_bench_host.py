@@ -1,6 +1,7 @@
 """Host-side logic of bench.py, without a GPU: the one-GPU refusal, the HBM
-traffic table (looked up only while the row kernels' sources are unchanged)
-and the scaling of hardware byte counters by a copy of known size."""
+traffic table (looked up only while the row kernels' sources are unchanged),
+the scaling of hardware byte counters by a copy of known size, and the
+kernel-statistics summary that sets the trace's average beside the events'."""
 import argparse
 import csv
 import json
@@ -77,3 +78,31 @@ def test_counters_are_scaled_by_the_copy_and_taken_after_the_last_clear(tmp_path
     assert ent["dir_spmv"]["hbm_bytes_per_launch"] == int(50.0 * 1024 * 2.0) + int(50.0 * 1024)
     assert ent["update_prec"]["fetch_size_scale"] == pytest.approx(2.0)
     assert tab["source_hash"] == bench.kernel_source_hash()
+
+
+def test_trace_summary_names_both_averages_of_the_dominant_kernel(tmp_path):
+    stats = tmp_path / "c4s_kernel_stats.csv"
+    upd = "void airga::k_update_prec<float, 6, 4, 1, false, true, true>(airga::SolveArgs<float>, int)"
+    with open(stats, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Name", "Calls", "TotalDurationNs", "AverageNs",
+                                           "Percentage"])
+        w.writeheader()
+        w.writerow({"Name": "airga::k_reduce<1024>(airga::ReduceArgs, int)", "Calls": 10,
+                    "TotalDurationNs": 50000, "AverageNs": 5000, "Percentage": 1.0})
+        w.writerow({"Name": upd, "Calls": 32, "TotalDurationNs": 5152000, "AverageNs": 161000,
+                    "Percentage": 20.0})
+    line = {"value": 5500.0, "unit": "solves/s", "ms_per_step": 23.3,
+            "config": {"tile": {"rows_per_wave": 256, "systems_per_group": 1}},
+            "roofline": {"kernel": "update_prec", "avg_launch_us": 163.5, "achieved": 4796.6,
+                         "frac": 0.5996, "peak": 8000.0}}
+    bj = tmp_path / "bench.json"
+    bj.write_text("[bench] log line\n" + json.dumps(line) + "\n")
+    out = tmp_path / "summary.md"
+    args = argparse.Namespace(summarize_trace=str(stats), bench_json=str(bj),
+                              command="rocprofv3 ... (test)", out=str(out))
+    bench.summarize_trace(args)
+    text = out.read_text()
+    rows = [x for x in text.splitlines() if x.startswith("| `")]
+    assert "k_update_prec" in rows[0] and "| 32 | 5.15 | 161.0 | 20.0 |" in rows[0]
+    assert "bench.py events 163.5 us" in text and "all its launches in the run: 161.0 us" in text
+    assert "rocprofv3 ... (test)" in text
