@@ -356,6 +356,24 @@ AIRGA_API airga_status airga_pencil_apply(airga_ctx ctx, double a, double b, int
 AIRGA_API airga_status airga_gram(airga_ctx ctx, int32_t k, const double* A, int64_t lda,
                                   int32_t l, const double* B, int64_t ldb, double* G);
 
+/* airga_gram for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, result and errors as airga_gram; it calls no hipMalloc or
+ * hipFree and allocates nothing, on the device or the host.  Its partial sums
+ * live in a fixed 32 MiB device array, one per GPU, held from the first
+ * airga_create on that GPU until the process ends.  The array holds 1024
+ * partial 64 x 64 tiles: for k, l <= 64 and n <= 1,048,576 the sums are
+ * formed exactly as in airga_gram (identical bits); beyond that each block of
+ * the product covers more rows, so results agree with airga_gram to rounding.
+ * No size within airga_gram's limits is refused for lack of scratch; a
+ * product that would need more than the array is refused with
+ * EUNSUPPORTED.  Every call on one GPU shares the array, from any context:
+ * calls that overlap on one GPU (on different streams, or from several
+ * threads) race and must be ordered by the caller.  Nothing in the array
+ * needs clearing between calls.  Asynchronous. */
+AIRGA_API airga_status airga_gram_noalloc(airga_ctx ctx, int32_t k, const double* A, int64_t lda,
+                                          int32_t l, const double* B, int64_t ldb, double* G);
+
 /* Global Arnoldi orthogonalisation (Algorithm 1, the loop over t): each of
  * the nx blocks X_x = X(:, x m : x m + m) is orthogonalised against the nb
  * blocks V_t = V(:, t m : t m + m) in the trace inner product <A, B> =

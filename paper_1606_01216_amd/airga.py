@@ -126,6 +126,8 @@ _SIGS = [
                                           _P, ctypes.c_int64, _P, ctypes.c_int64]),
     ("airga_gram", ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_int32, _P,
                                   ctypes.c_int64, _P]),
+    ("airga_gram_noalloc", ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_int32,
+                                          _P, ctypes.c_int64, _P]),
     ("airga_global_orth", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64,
                                          ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_double),
@@ -347,6 +349,19 @@ class Context:
                                 _ptr(g)))
         self._leave()
         return g.t()
+
+    def gram_noalloc(self, a: torch.Tensor, b: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """airga_gram_noalloc into out, an (l, k) float64 device tensor (the
+        column-major k x l result); returns out.t(), the (k, l) products."""
+        a, b = self._block(a), self._block(b)
+        _dev(out, torch.float64, self.device)
+        if tuple(out.shape) != (b.shape[0], a.shape[0]):
+            raise ValueError("out must be (l, k)")
+        self._enter()
+        _check(lib().airga_gram_noalloc(self._h, a.shape[0], _ptr(a), self.n, b.shape[0], _ptr(b),
+                                        self.n, _ptr(out)))
+        self._leave()
+        return out.t()
 
     def global_orth(self, v: torch.Tensor | None, x: torch.Tensor, m: int,
                     normalize: bool = False):

@@ -175,6 +175,9 @@ struct airga_ctx_s {
   std::vector<std::pair<std::vector<char>, hipGraphExec_t>> graphs;
   // Column-gather area of the float64 finish of mixed solves.
   airga::DevBuf ws_gather;
+  // Device address of the fixed partial-sum array of airga_gram_noalloc on
+  // this context's GPU (looked up when the context is created).
+  double* gram_scratch = nullptr;
   ~airga_ctx_s() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
     for (auto& b : pool) (void)hipFree(b.first);
@@ -310,6 +313,10 @@ struct DeviceGuard {
 inline unsigned blocks_for(int64_t work, int per_block) {
   return (unsigned)((work + per_block - 1) / per_block);
 }
+
+// Device address of the fixed partial-sum array of airga_gram_noalloc on
+// `device` (looked up once per device, with that device current).
+airga_status gram_scratch_address(int device, double** out);
 
 // Kernels shared between translation units.
 __global__ void k_fill_f64(double* p, int64_t count, double v);

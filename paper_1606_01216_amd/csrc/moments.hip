@@ -7,6 +7,7 @@
 // depend on scheduling.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
@@ -186,26 +187,75 @@ __global__ void __launch_bounds__(256) k_gram_reduce(int32_t k, int32_t l, int n
   }
 }
 
-// G (device, k x l, column-major with leading dimension ldg) = A^T B over n
-// rows.  Partials go to the context's Gram workspace.
-static airga_status gram(airga_ctx ctx, int64_t n, int32_t k, const double* A, int64_t lda,
-                         int32_t l, const double* B, int64_t ldb, double* G, int64_t ldg) {
-  if (k == 0 || l == 0) return AIRGA_OK;
-  const int nblk = (int)((n + kGramRowsPerBlock - 1) / kGramRowsPerBlock);
+// Launch of the two Gram kernels with nblk row blocks per output tile and
+// the partials in part (tk * tl * nblk * 64 * 64 doubles, every one written
+// by k_gram_partial, so part needs no clearing).  Block b of a tile takes the
+// row stages b, b + nblk, ..., so any nblk >= 1 covers all n rows.
+static airga_status gram_launch(airga_ctx ctx, int64_t n, int32_t k, const double* A, int64_t lda,
+                                int32_t l, const double* B, int64_t ldb, double* G, int64_t ldg,
+                                int nblk, double* part) {
   const int tk = (k + kGT - 1) / kGT, tl = (l + kGT - 1) / kGT;
-  if (n == 0) {
-    k_fill_f64<<<blocks_for((int64_t)ldg * l, 256), 256, 0, ctx->stream>>>(G, ldg * l, 0.0);
-    AIRGA_HIP(hipGetLastError());
-    return AIRGA_OK;
-  }
-  AIRGA_TRY(ctx->ws_gram.reserve(sizeof(double) * (size_t)tk * tl * nblk * kGT * kGT));
-  double* part = ctx->ws_gram.as<double>();
   k_gram_partial<<<dim3((unsigned)nblk, (unsigned)tk, (unsigned)tl), 256, 0, ctx->stream>>>(
       n, k, A, lda, l, B, ldb, part);
   AIRGA_HIP(hipGetLastError());
   k_gram_reduce<<<blocks_for((int64_t)k * l, kRedOut), 256, 0, ctx->stream>>>(k, l, nblk, tl, part,
                                                                              G, ldg);
   AIRGA_HIP(hipGetLastError());
+  return AIRGA_OK;
+}
+
+// G = 0 for a product over no rows.
+static airga_status gram_zero(airga_ctx ctx, int32_t l, double* G, int64_t ldg) {
+  k_fill_f64<<<blocks_for((int64_t)ldg * l, 256), 256, 0, ctx->stream>>>(G, ldg * l, 0.0);
+  AIRGA_HIP(hipGetLastError());
+  return AIRGA_OK;
+}
+
+// G (device, k x l, column-major with leading dimension ldg) = A^T B over n
+// rows.  Partials go to the context's Gram workspace.
+static airga_status gram(airga_ctx ctx, int64_t n, int32_t k, const double* A, int64_t lda,
+                         int32_t l, const double* B, int64_t ldb, double* G, int64_t ldg) {
+  if (k == 0 || l == 0) return AIRGA_OK;
+  if (n == 0) return gram_zero(ctx, l, G, ldg);
+  const int nblk = (int)((n + kGramRowsPerBlock - 1) / kGramRowsPerBlock);
+  const int tk = (k + kGT - 1) / kGT, tl = (l + kGT - 1) / kGT;
+  AIRGA_TRY(ctx->ws_gram.reserve(sizeof(double) * (size_t)tk * tl * nblk * kGT * kGT));
+  return gram_launch(ctx, n, k, A, lda, l, B, ldb, G, ldg, nblk, ctx->ws_gram.as<double>());
+}
+
+// ------------------------------------------ A^T B without allocation
+//
+// The partials of airga_gram_noalloc live in a fixed device array, one per
+// GPU, held until the process ends.  32 MiB holds 1024 partial tiles of
+// 64 x 64: up to 1024 row blocks of 1024 rows for one output tile (so
+// products over n <= 1,048,576 rows with k, l <= 64 are summed exactly as
+// airga_gram sums them), and 1024 / (tiles of the output) blocks per tile
+// for wider products, each block then taking more rows.  Calls that overlap
+// on one GPU share the array and race.
+constexpr size_t kGramScratchBytes = size_t(32) << 20;
+constexpr int64_t kGramScratchTiles = (int64_t)(kGramScratchBytes / (sizeof(double) * kGT * kGT));
+static __device__ __align__(256) double scratch[kGramScratchBytes / sizeof(double)];
+
+// Device address of `scratch` per GPU, looked up once per device (host code
+// must not pass the array's own name to a kernel: on the host it is only a
+// stand-in for the device symbol).
+static std::mutex g_scratch_mu;
+static std::vector<double*> g_scratch_addr;
+
+airga_status gram_scratch_address(int device, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0) return fail(AIRGA_EINVAL, "bad device %d", device);
+  if ((size_t)device >= g_scratch_addr.size()) g_scratch_addr.resize(device + 1, nullptr);
+  if (!g_scratch_addr[device]) {
+    DeviceGuard g(device);
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(AIRGA_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                  hipGetErrorString(e));
+    g_scratch_addr[device] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_addr[device];
   return AIRGA_OK;
 }
 
@@ -416,6 +466,29 @@ airga_status airga_gram(airga_ctx ctx, int32_t k, const double* A, int64_t lda, 
   if ((k > 0 && lda < n) || (l > 0 && ldb < n)) return fail(AIRGA_EINVAL, "leading dimension < n");
   if (k > kGramMax || l > kGramMax) return fail(AIRGA_EUNSUPPORTED, "more than %d columns", kGramMax);
   return gram(ctx, n, k, A, lda, l, B, ldb, G, k);
+}
+
+airga_status airga_gram_noalloc(airga_ctx ctx, int32_t k, const double* A, int64_t lda, int32_t l,
+                                const double* B, int64_t ldb, double* G) {
+  AIRGA_TRY(check_pencil(ctx));
+  DeviceGuard g(ctx->device);
+  const int64_t n = ctx->pen.n;
+  if (k < 0 || l < 0) return fail(AIRGA_EINVAL, "negative column count");
+  if ((k > 0 && !A) || (l > 0 && !B) || (k > 0 && l > 0 && !G))
+    return fail(AIRGA_EINVAL, "null matrix");
+  if ((k > 0 && lda < n) || (l > 0 && ldb < n)) return fail(AIRGA_EINVAL, "leading dimension < n");
+  if (k > kGramMax || l > kGramMax) return fail(AIRGA_EUNSUPPORTED, "more than %d columns", kGramMax);
+  if (k == 0 || l == 0) return AIRGA_OK;
+  if (n == 0) return gram_zero(ctx, l, G, k);
+  if (!ctx->gram_scratch) return fail(AIRGA_ESTATE, "no scratch address for device %d", ctx->device);
+  const int64_t tiles = (int64_t)((k + kGT - 1) / kGT) * ((l + kGT - 1) / kGT);
+  const int64_t full = (n + kGramRowsPerBlock - 1) / kGramRowsPerBlock;
+  const int64_t cap = kGramScratchTiles / tiles;
+  const int64_t nblk = full < cap ? full : cap;
+  if (nblk < 1 || tiles * nblk * kGT * kGT * (int64_t)sizeof(double) > (int64_t)kGramScratchBytes)
+    return fail(AIRGA_EUNSUPPORTED, "%lld x %d output tiles exceed the %zu-byte scratch",
+                (long long)tiles, (int)nblk, kGramScratchBytes);
+  return gram_launch(ctx, n, k, A, lda, l, B, ldb, G, k, (int)nblk, ctx->gram_scratch);
 }
 
 airga_status airga_global_orth(airga_ctx ctx, int32_t m, int32_t nb, const double* V, int64_t ldv,

@@ -550,6 +550,12 @@ airga_status airga_create(airga_ctx* out, int device, void* stream) {
     }
     c->own_stream = true;
   }
+  const airga_status st = gram_scratch_address(device, &c->gram_scratch);
+  if (st != AIRGA_OK) {
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return st;
+  }
   *out = c;
   return AIRGA_OK;
 }
