@@ -41,6 +41,12 @@ def lib():
         h.oracle_shift_dd.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, dp, dp]
         h.oracle_shift_dd.restype = None
+        h.oracle_cband_solve.argtypes = [ctypes.c_int64, ctypes.c_int, dp, dp, dp, dp,
+                                         ctypes.c_int, dp, dp, dp, dp, dp, dp, ctypes.c_int]
+        h.oracle_cband_solve.restype = ctypes.c_int
+        h.oracle_shift_cdd.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
+        h.oracle_shift_cdd.restype = None
         _handle = h
     return _handle
 

@@ -119,16 +119,56 @@ def reduce(mv, kv, alpha, beta, f, cp, cv, v):
     return Model(mh, dh, kh, fh, cph, cvh)
 
 
+def moment_error(vs, x_before, x_after):
+    """Reading A1: the part of the newest moment block that the basis
+    V_1..V_j does not hold yet, as a fraction of the block:
+    ||x_after||_F / ||x_before||_F (x_after = x_before orthogonalised against
+    the trace-orthonormal blocks vs)."""
+    return float(np.linalg.norm(x_after) / np.linalg.norm(x_before))
+
+
+def next_point(errors):
+    """Reading A1: the expansion point whose moment error is largest (the
+    first such index on a tie); before any error exists, the first point."""
+    if errors is None:
+        return 0
+    errors = np.asarray(errors, dtype=float)
+    return int(np.flatnonzero(errors == errors.max())[0])
+
+
+def relative_change(new, old):
+    """Reading A5: ||H_new - H_old||_H2 / ||H_new||_H2."""
+    return h2_distance(new, old) / h2_distance(new)
+
+
 def airga(mv, kv, alpha, beta, f, cp, cv, shifts0, rmax, tol_outer=1e-6, tol_inner=1e-6,
           max_outer=10, solve=None):
-    """Algorithm 1 with readings A1-A6.
+    """AIRGA's outer iteration (Algorithm 1) under readings A1-A6.
 
     mv, kv: sparse n x n M and K (D = alpha M + beta K); f: n x m; cp, cv:
     p x n (cv may be None); shifts0: the l initial expansion points.
     solve(s, rhs) returns K(s)^{-1} rhs (default: sparse LU).
+
+    One outer iteration: the state X(s_i) = K(s_i)^{-1} F at every point,
+    each replaced by its thin QR factor; then the moment loop, which grows
+    the basis one n x m block at a time.  A step takes the point sigma with
+    the largest moment error (A1), appends its current block, normalised in
+    the Frobenius norm, as V_j, replaces that point's block by its next
+    moment -K(sigma)^{-1} M V_j, and orthogonalises every point's block
+    against V_1..V_j in the trace inner product, which gives the new moment
+    errors.  The normalised blocks span an intermediate reduced model; the
+    loop ends when that model's relative H2 change drops below tol_inner (A5)
+    or the basis reaches floor(rmax / m) blocks (A3), the last block being
+    taken, again by the largest moment error, after the loop.  The final
+    basis is the thin QR of [V_1 .. V_J], the reduced model is its Galerkin
+    projection (eq. (1.4)), and the next expansion points come from the
+    reduced model's poles (A4).  The outer loop ends when the final model's
+    relative H2 change drops below tol_outer, or after max_outer iterations.
+
     Returns (V, model, history): history holds one dict per outer
-    iteration with its expansion points, sigma sequence, J, moment errors,
-    intermediate H2 changes, final model and relative H2 change.
+    iteration with its expansion points, sigma sequence (indices), J,
+    moment errors after each step, the intermediate models and their
+    relative H2 changes, the final model and its relative H2 change.
     """
     if solve is None:
         def solve(s, rhs):
@@ -137,60 +177,50 @@ def airga(mv, kv, alpha, beta, f, cp, cv, shifts0, rmax, tol_outer=1e-6, tol_inn
     n, m = f.shape
     shifts = np.asarray(shifts0, dtype=float)
     l = len(shifts)
-    jmax = rmax // m
-    if jmax < 1:
+    blocks_max = rmax // m
+    if blocks_max < 1:
         raise ValueError("r_max below the input count")
     history = []
-    prev_final = None
-    v = None
-    for _z in range(max_outer):
-        # solves at every expansion point, then the thin QR of each
-        xs = [moments.thin_qr(solve(s, f))[0] for s in shifts]
-        vs = []
+    final_prev = None
+    basis = None
+    for _ in range(max_outer):
+        state = [moments.thin_qr(solve(s, f))[0] for s in shifts]
+        vs, sigmas, step_errors, inner_models, inner_changes = [], [], [], [], []
         errors = None
-        sigmas = []
-        step_errors = []
-        inner_changes = []
-        prev_int = None
-        j = 1
-        while j < jmax:
-            q = 0 if errors is None else int(np.argmax(errors))          # A1
+
+        def take_block():
+            q = next_point(errors)
             sigmas.append(q)
-            vs.append(xs[q] / np.linalg.norm(xs[q]))
-            xs[q] = -solve(shifts[q], mv @ vs[-1])                       # A2
-            errors, norms = [], []
+            vs.append(state[q] / np.linalg.norm(state[q]))
+            return q
+
+        while len(vs) + 1 < blocks_max:
+            q = take_block()
+            state[q] = -solve(shifts[q], mv @ vs[-1])
+            before = [x.copy() for x in state]
+            fro = []
             for i in range(l):
-                before = np.linalg.norm(xs[i])
-                xs[i], _, fro = moments.global_orth(vs, xs[i])
-                errors.append(fro / before)
-                norms.append(fro)
-            errors = np.array(errors)
+                state[i], _, nrm = moments.global_orth(vs, state[i])
+                fro.append(nrm)
+            errors = np.array([moment_error(vs, b, x) for b, x in zip(before, state)])
             step_errors.append(errors.copy())
-            w, _ = moments.thin_qr(np.hstack([xs[i] / norms[i] for i in range(l)]))
-            model_int = reduce(mv, kv, alpha, beta, f, cp, cv, w)
-            if prev_int is not None:
-                change = h2_distance(model_int, prev_int) / h2_distance(model_int)  # A5
+            w, _ = moments.thin_qr(np.hstack([state[i] / fro[i] for i in range(l)]))
+            inner_models.append(reduce(mv, kv, alpha, beta, f, cp, cv, w))
+            if len(inner_models) > 1:
+                change = relative_change(inner_models[-1], inner_models[-2])
                 inner_changes.append(change)
                 if change < tol_inner:
-                    j += 1
                     break
-            prev_int = model_int
-            j += 1
-        # J = j: the last block from the largest moment error
-        q = 0 if errors is None else int(np.argmax(errors))
-        sigmas.append(q)
-        vs.append(xs[q] / np.linalg.norm(xs[q]))
-        v, _ = moments.thin_qr(np.hstack(vs))
-        final = reduce(mv, kv, alpha, beta, f, cp, cv, v)
-        change = None
-        if prev_final is not None:
-            change = h2_distance(final, prev_final) / h2_distance(final)
+        take_block()
+        basis, _ = moments.thin_qr(np.hstack(vs))
+        final = reduce(mv, kv, alpha, beta, f, cp, cv, basis)
+        change = None if final_prev is None else relative_change(final, final_prev)
         history.append(dict(shifts=shifts.copy(), sigmas=sigmas, J=len(vs),
                             errors=None if errors is None else errors.copy(),
-                            step_errors=step_errors,
+                            step_errors=step_errors, inner_models=inner_models,
                             inner_changes=inner_changes, model=final, change=change))
-        prev_final = final
+        final_prev = final
         if change is not None and change < tol_outer:
             break
         shifts = next_shifts(qep_poles(final.mh, final.dh, final.kh), l)   # A4
-    return v, prev_final, history
+    return basis, final_prev, history

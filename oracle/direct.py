@@ -106,3 +106,109 @@ def reference_solve(pen, s, f: np.ndarray, precision: str = "dd") -> np.ndarray:
     a = shifted_operator(pen, s)
     ab, w = lower_band(a)
     return band_solve(ab, w, f, "f64")
+
+
+def reference_solves(pen, shifts, f: np.ndarray, precision: str = "dd",
+                     workers: int = 1, each=None) -> list | None:
+    """reference_solve for every shift in ``shifts`` (a list of (m, n) arrays,
+    or, when ``each`` is given, each(i, x) called in shift order as the
+    results arrive, which are then not kept).
+
+    The lower bands of M and K are extracted once and K(s) is formed on the
+    band for each shift by the same entrywise formula as reference_solve
+    ("f64": s^2 M + s (alpha M + beta K) + K in binary64; "dd": the
+    double-double assembly), so each result equals reference_solve's.
+    Shifts run on ``workers`` threads (the factorisations release the
+    interpreter lock).
+    """
+    from concurrent.futures import ThreadPoolExecutor
+    from .pencil import shifted_values
+    m_band, w = lower_band(_pattern_matrix(pen, pen.m_val))
+    k_band, _ = lower_band(_pattern_matrix(pen, pen.k_val), w)
+    _native.lib()
+
+    def one(s):
+        if precision == "dd":
+            hi = np.empty_like(m_band)
+            lo = np.empty_like(m_band)
+            _native.lib().oracle_shift_dd(m_band.size, _native.dptr(m_band), _native.dptr(k_band),
+                                          float(s), float(pen.alpha), float(pen.beta),
+                                          _native.dptr(hi), _native.dptr(lo))
+            xh, xl = band_solve(hi, w, f, "dd", ab_lo=lo)
+            return xh + xl
+        ab = shifted_values(m_band, k_band, pen.alpha, pen.beta, s)
+        return band_solve(ab, w, f, "f64")
+
+    if each is None:
+        if workers <= 1:
+            return [one(s) for s in shifts]
+        with ThreadPoolExecutor(workers) as ex:
+            return list(ex.map(one, shifts))
+    if workers <= 1:
+        for i, s in enumerate(shifts):
+            each(i, one(s))
+        return None
+    with ThreadPoolExecutor(workers) as ex:
+        for i, x in enumerate(ex.map(one, shifts)):
+            each(i, x)
+    return None
+
+
+# ------------------------------------------------------------ complex shifts
+#
+# For a complex expansion point s, K(s) = s^2 M + s D + K is complex
+# symmetric, not Hermitian.  The reference solve factorises it as
+# L Dg L^T (transposes without conjugation) on the band, in binary64 complex
+# or in double-double complex with K(s) assembled entrywise in double-double
+# from the exact binary64 M and K.
+
+
+def cband_solve(re, im, w, b, precision="f64", re_lo=None, im_lo=None):
+    """Solve with a complex symmetric band matrix (lower band re + i im);
+    b (nrhs, n) or (n,), real or complex.  Returns the complex solution
+    (rounded to binary64 in double-double mode)."""
+    n = re.shape[0]
+    squeeze = np.ndim(b) == 1
+    bb = np.atleast_2d(np.asarray(b))
+    br = np.ascontiguousarray(bb.real, dtype=np.float64)
+    bi = np.ascontiguousarray(bb.imag, dtype=np.float64) if np.iscomplexobj(bb) else None
+    xr = np.empty_like(br)
+    xi = np.empty_like(br)
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) if a is not None else None
+            for a in (re, re_lo, im, im_lo)]
+    st = _native.lib().oracle_cband_solve(n, w, *(_native.dptr(a) for a in arrs), bb.shape[0],
+                                          _native.dptr(br), _native.dptr(bi), _native.dptr(xr),
+                                          _native.dptr(xi), None, None,
+                                          0 if precision == "f64" else 1)
+    if st != 0:
+        raise np.linalg.LinAlgError(f"complex band LDL^T: zero pivot (code {st})")
+    x = xr + 1j * xi
+    return x[0] if squeeze else x
+
+
+def shifted_band_cdd(pen, s: complex, w: int | None = None):
+    """Lower band of K(s) for complex s, entrywise in double-double:
+    (re_hi, re_lo, im_hi, im_lo, w)."""
+    m_band, w = lower_band(_pattern_matrix(pen, pen.m_val), w)
+    k_band, _ = lower_band(_pattern_matrix(pen, pen.k_val), w)
+    out = [np.empty_like(m_band) for _ in range(4)]
+    _native.lib().oracle_shift_cdd(m_band.size, _native.dptr(m_band), _native.dptr(k_band),
+                                   float(np.real(s)), float(np.imag(s)), float(pen.alpha),
+                                   float(pen.beta), *(_native.dptr(o) for o in out))
+    return (*out, w)
+
+
+def reference_solve_complex(pen, s: complex, f: np.ndarray, precision: str = "dd") -> np.ndarray:
+    """X(s) = K(s)^{-1} F for complex s and F of shape (m, n) (complex result).
+
+    "dd": K(s) assembled and factorised in double-double complex (the trusted
+    reference); "f64": K(s) from the binary64 complex formula, factorised in
+    binary64 complex."""
+    if precision == "dd":
+        rh, rl, ih, il, w = shifted_band_cdd(pen, s)
+        return cband_solve(rh, ih, w, f, "dd", re_lo=rl, im_lo=il)
+    from .pencil import shifted_values_complex
+    m_band, w = lower_band(_pattern_matrix(pen, pen.m_val))
+    k_band, _ = lower_band(_pattern_matrix(pen, pen.k_val), w)
+    ab = shifted_values_complex(m_band, k_band, pen.alpha, pen.beta, s)
+    return cband_solve(ab.real, ab.imag, w, f, "f64")

@@ -100,3 +100,60 @@ def pcg(matvec, precond, f, *, tol=1e-10, max_iter=10000, x0=None, beta="flexibl
         p = z_new + b * p
         z, rz = z_new, rz_new
     return PcgResult(x, MAXIT, max_iter, rnorm / fnorm, hist, dirs, ress)
+
+
+def cocg(matvec, precond, f, *, tol=1e-10, max_iter=10000, beta="flexible", keep=False) -> PcgResult:
+    """Conjugate orthogonal CG for complex symmetric systems (K(s) at a complex
+    expansion point; van der Vorst and Melissen, IEEE Trans. Magn. 1990):
+    CG with the bilinear form x^T y (no conjugation) in place of the inner
+    product, for a complex symmetric K and a complex symmetric preconditioner
+    C.  From x = 0:  r = f;  z = C r;  p = z
+      repeat:  w = K p;  mu = p^T w;  alpha = (r^T z) / mu;  x += alpha p;
+               r -= alpha w;  stop when ||r|| <= tol ||f|| (Euclidean norm);
+               z_new = C r;  beta;  p = z_new + beta p
+    with the flexible beta = -(z_new^T w) / mu (p stays conjugate orthogonal
+    to the previous direction, K-wise, under any C) or ("fr") the classical
+    ratio (r^T z)_new / (r^T z)_old.  Both reduce to CG for real data.  Statuses as
+    for pcg: BREAKDOWN when mu = 0 (the bilinear form has no sign to test),
+    NONFINITE on a NaN or infinity."""
+    f = np.asarray(f, dtype=complex)
+    fnorm = float(np.linalg.norm(f))
+    x = np.zeros_like(f)
+    r = f.copy()
+    hist, dirs, ress = [], [], []
+    rnorm = fnorm
+    if rnorm <= tol * fnorm:
+        return PcgResult(x, CONVERGED, 0, 0.0, hist, dirs, ress)
+    z = precond(r)
+    rz = complex(r @ z)
+    p = z.copy()
+    for k in range(max_iter):
+        if keep:
+            dirs.append(p.copy())
+            ress.append(r.copy())
+        w = matvec(p)
+        mu = complex(p @ w)
+        if not np.isfinite(mu):
+            return PcgResult(x, NONFINITE, k, rnorm / fnorm, hist, dirs, ress)
+        if mu == 0:
+            return PcgResult(x, BREAKDOWN, k, rnorm / fnorm, hist, dirs, ress)
+        alpha = rz / mu
+        x = x + alpha * p
+        r = r - alpha * w
+        rnorm = float(np.linalg.norm(r))
+        hist.append(rnorm / fnorm)
+        if not np.isfinite(rnorm):
+            return PcgResult(x, NONFINITE, k + 1, rnorm / fnorm, hist, dirs, ress)
+        if rnorm <= tol * fnorm:
+            return PcgResult(x, CONVERGED, k + 1, rnorm / fnorm, hist, dirs, ress)
+        zn = precond(r)
+        rzn = complex(r @ zn)
+        if beta == "flexible":
+            b = -complex(zn @ w) / mu
+        elif beta == "fr":
+            b = rzn / rz
+        else:
+            raise ValueError(f"unknown beta form {beta!r}")
+        p = zn + b * p
+        rz = rzn
+    return PcgResult(x, MAXIT, max_iter, rnorm / fnorm, hist, dirs, ress)

@@ -32,6 +32,24 @@ def shifted_values(m_val, k_val, alpha, beta, s):
     return (s * s) * m_val + s * damping_values(m_val, k_val, alpha, beta) + k_val
 
 
+def shifted_values_complex(m_val, k_val, alpha, beta, s: complex):
+    """Entries of s^2 M + s D + K for a complex expansion point s, in complex
+    binary64, written as the formula reads."""
+    s = complex(s)
+    m_val = np.asarray(m_val, dtype=np.float64)
+    k_val = np.asarray(k_val, dtype=np.float64)
+    return (s * s) * m_val + s * damping_values(m_val, k_val, alpha, beta) + k_val
+
+
+def shifted_operator_complex(pen, s: complex) -> sp.csr_matrix:
+    """K(s) for complex s as a complex CSR matrix on the shared pattern (complex
+    symmetric: K(s)^T = K(s))."""
+    a = sp.csr_matrix((shifted_values_complex(pen.m_val, pen.k_val, pen.alpha, pen.beta, s),
+                       np.asarray(pen.col_idx), np.asarray(pen.row_ptr)), shape=(pen.n, pen.n))
+    a.has_sorted_indices = True
+    return a
+
+
 def shifted_operator(pen, s) -> sp.csr_matrix:
     """K(s) for a ``synthetic.beam.Pencil``-like object (n, row_ptr, col_idx,
     m_val, k_val, alpha, beta) as a CSR matrix on the shared pattern."""

@@ -34,17 +34,19 @@ factor is mapped back as Q = S_new Qhat S_new^{-1}, so that K_new Q ~ K_old.
 The preconditioner after updates is the chain Q_z ... Q_2 P_1, applied factor
 by factor and never multiplied out (Section 3.2, last paragraph).
 
-Minimal-residual mode (mr_iters > 0): the columns follow the loops of
-Algorithms 2 and 4 as printed instead of the exact solve.  Starting from
-p_j = alpha e_j (q_j = alpha e_j), r = t - K p_j with t = e_j (k_old_j), and
-while ||r|| > tol ||t||:  d = P r,  w = K d,  a = (r, w) / (w, w),
-p_j += a d,  r -= a w.  As printed, P (Q) stays alpha I inside the column
-loop, so d = alpha r; d is dropped to the pattern J of column j, which keeps
-p_j on the pattern of K(s) (the structural reading above).  r then lives on
-the rows I, so the loop runs on the column's local block exactly.  The loop is
-capped at mr_iters steps, because on a fixed pattern the residual may never
-reach tol.  The build's alpha is trace(Khat) / trace(Khat Khat^T) of the
-matrix whose inverse is sought (Algorithm 2, first line).
+Minimal-residual mode (mr_iters > 0): each column is reached the way the
+paper's iterative algorithms reach it (Algorithms 2 and 4) instead of by the
+exact solve: starting from p_j = alpha e_j (q_j = alpha e_j), a sequence of
+minimal-residual steps on the column objective ||t - K p_j|| with t = e_j
+(k_old_j), each an exact line search along the current residual, until the
+residual is within tol ||t||.  In the paper P (Q) stays alpha I inside the
+column loop (its write-back is not part of the algorithm), so the direction
+is alpha times the residual; it is restricted to the pattern J of column j,
+which keeps p_j on the pattern of K(s) (the structural reading above), and
+the residual then lives on the rows I, so the iteration runs on the column's
+local block exactly.  It is capped at mr_iters steps, because on a fixed
+pattern the residual may never reach tol.  The build's alpha is
+trace(Khat) / trace(Khat Khat^T) of the matrix whose inverse is sought.
 """
 from __future__ import annotations
 
@@ -66,8 +68,9 @@ class Factor:
     cols: np.ndarray          # columns actually computed
     pattern: tuple            # (n, row_ptr, col_idx)
     iters: np.ndarray = None  # minimal-residual mode: steps per column
-    margin: np.ndarray = None  # minimal-residual mode: closest approach of
-                               # ||r|| / (tol ||t||) to 1 over the column's tests
+    margin: np.ndarray = None  # closest approach of ||r|| / (tol ||t||) to 1 over
+                               # the column's tolerance tests (update: the skip
+                               # test; minimal-residual mode: every test)
 
     def matrix(self) -> sp.csr_matrix:
         n, rp, ci = self.pattern
@@ -110,7 +113,7 @@ def _column_problem(indptr, rows, vals, j):
     jj = rows[indptr[j]:indptr[j + 1]]
     parts = [rows[indptr[k]:indptr[k + 1]] for k in jj]
     ii = np.unique(np.concatenate(parts))
-    blk = np.zeros((len(ii), len(jj)))
+    blk = np.zeros((len(ii), len(jj)), dtype=vals.dtype)
     for t, k in enumerate(jj):
         r = rows[indptr[k]:indptr[k + 1]]
         blk[np.searchsorted(ii, r), t] = vals[indptr[k]:indptr[k + 1]]
@@ -122,34 +125,49 @@ def _scaled_values(a_val, rows, cols, s_row, s_col):
 
 
 def _mr_column(blk, rhs, jpos, p, alpha, tol, mr_iters):
-    """The minimal-residual loop of Algorithms 2 / 4 on one column's local
-    block: blk = Khat(I, J), rhs = t(I), jpos = positions of J in I, p the
-    start on J.  Returns (p, ||r||, steps, margin)."""
-    r = rhs - blk @ p
+    """The paper's iterative column solve (Algorithms 2 and 4, readings I1-I3)
+    on one column's local problem, minimise f(p) = ||t - B p||^2 with
+    B = blk = Khat(I, J) and t = rhs = t(I), from the start p on J.
+
+    Each step is an exact line search of f: the direction is the current
+    residual t - B p scaled by alpha and restricted to the pattern J
+    (jpos = positions of J in I), d = alpha (t - B p)|_J, and
+    f(p + a d) = f(p) - 2 a <t - B p, B d> + a^2 ||B d||^2 is smallest at
+    a = <t - B p, B d> / ||B d||^2.  The residual is formed from its
+    definition at every step.  The loop stops once ||t - B p|| <= tol ||t||,
+    after mr_iters steps, or when B d = 0 (no descent left along d).
+    Returns (p, ||t - B p||, steps, margin), margin = the closest approach
+    of ||t - B p|| / (tol ||t||) to 1 over the stopping tests taken."""
     thr = tol * np.linalg.norm(rhs)
     margin = np.inf
-    it = 0
+    steps = 0
     while True:
-        nr = np.linalg.norm(r)
+        res = rhs - blk @ p
+        nres = np.linalg.norm(res)
         if thr > 0:
-            margin = min(margin, abs(nr / thr - 1.0))
-        if not (nr > thr) or it >= mr_iters:
+            margin = min(margin, abs(nres / thr - 1.0))
+        if nres <= thr or steps >= mr_iters:
             break
-        d = alpha * r[jpos]          # d = P r with P = alpha I, on the pattern J
-        w = blk @ d                  # w = K d
-        ww = w @ w
-        if not ww > 0:
+        d = alpha * res[jpos]
+        bd = blk @ d
+        curv = bd @ bd
+        if not curv > 0:
             break
-        a = (r @ w) / ww
-        p = p + a * d
-        r = r - a * w
-        it += 1
-    return p, float(np.linalg.norm(r)), it, margin
+        p = p + ((res @ bd) / curv) * d
+        steps += 1
+    return p, float(np.linalg.norm(rhs - blk @ p)), steps, margin
 
 
 def spai_build(a: sp.csr_matrix, *, equilibrate=True, symmetrize=True, cols=None,
                mr_iters=0, tol=0.01) -> Factor:
     """SPAI of K(s) on its own structural pattern (eq. (3.1)).
+
+    K(s) may be complex (a complex expansion point): the column problems are
+    then complex least-squares problems, S = diag(K)^{-1/2} takes the
+    principal square root, and the symmetric average is (Phat + Phat^T) / 2
+    with the plain transpose, so that the factor stays complex symmetric like
+    K(s) (conjugate orthogonal CG needs that).  The minimal-residual mode is
+    real only.
 
     ``cols`` restricts the computation to a subset of columns (sampled checks
     at large n); the returned values are then only meaningful for those.
@@ -169,6 +187,11 @@ def spai_build(a: sp.csr_matrix, *, equilibrate=True, symmetrize=True, cols=None
     iters = np.zeros(n, np.int64)
     margin = np.full(n, np.inf)
     todo = np.arange(n) if cols is None else np.asarray(cols)
+    cplx = np.iscomplexobj(khat)
+    if cplx:
+        if mr_iters > 0:
+            raise ValueError("the minimal-residual mode is for real shifts only")
+        hat = np.full(len(ci), np.nan, dtype=complex)
     if mr_iters > 0:
         kh = sp.csr_matrix((khat, ci, rp), shape=(n, n))
         alpha_hat = float(kh.diagonal().sum() / (kh @ kh.T).diagonal().sum())
@@ -191,7 +214,12 @@ def spai_build(a: sp.csr_matrix, *, equilibrate=True, symmetrize=True, cols=None
     values = _scaled_values(sym, rows, ci, s, s)
     # Alg. 2's initial scaling: trace(K) / trace(K K^T) (reported, not used by
     # the exact column solves; the minimal-residual loop uses it for Khat).
-    alpha = alpha_hat if mr_iters > 0 else float(a.diagonal().sum() / (a @ a.T).diagonal().sum())
+    if cplx:
+        # complex: the minimiser of ||I - alpha K||_F is trace(K^H) / ||K||_F^2
+        alpha = complex(np.conj(a.diagonal()).sum() / np.vdot(a.data, a.data).real)
+    else:
+        alpha = alpha_hat if mr_iters > 0 else float(a.diagonal().sum() /
+                                                     (a @ a.T).diagonal().sum())
     return Factor(values=values, hat=hat, objective=obj, skipped=np.zeros(n, bool),
                   alpha=alpha, cols=todo, pattern=(n, rp, ci),
                   iters=iters if mr_iters > 0 else None, margin=margin if mr_iters > 0 else None)
@@ -257,7 +285,7 @@ def spai_update(a_old: sp.csr_matrix, a_new: sp.csr_matrix, *, tol=0.01, equilib
     values = hat * s[rows] / s[ci]
     return Factor(values=values, hat=hat, objective=obj, skipped=skipped, alpha=alpha,
                   cols=todo, pattern=(n, rp, ci),
-                  iters=iters if mr_iters > 0 else None, margin=margin if mr_iters > 0 else None)
+                  iters=iters if mr_iters > 0 else None, margin=margin)
 
 
 def chain_apply(factors, r: np.ndarray) -> np.ndarray:

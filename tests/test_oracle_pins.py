@@ -758,3 +758,252 @@ def test_real_part_expansion_points_fall_below_the_low_modes():
     lam = airga_loop.qep_poles(hist[0]["model"].mh, hist[0]["model"].dh, hist[0]["model"].kh)
     w_low = np.sort(np.abs(lam))[0]
     assert np.all(hist[1]["shifts"] < 0.1 * w_low)
+
+
+# ---- pins of readings A1 (choice of sigma) and A5 (the H2 stopping test)
+
+def _diag_system(k=(1.0, 30.0, 900.0), alpha=0.1):
+    """M = I, K = diag(k), D = alpha I, F = (1, 1, 1): every state
+    X(s) = F / ((s^2 + alpha s) + k) is known entry by entry."""
+    kk = np.asarray(k, float)
+    ms = sp.identity(3, format="csr")
+    ks = sp.diags(kk).tocsr()
+    return kk, ms, ks, np.ones((3, 1)), np.array([[1.0, 0.0, 0.0]])
+
+
+def _sin_angle(u, v):
+    # |sin| of the angle between two 3-vectors from their cross product
+    return float(np.linalg.norm(np.cross(u, v)) / (np.linalg.norm(u) * np.linalg.norm(v)))
+
+
+@pytest.mark.parametrize("s2,want", [(30.0, 1), (1.02, 0), (3.0, 1)])
+def test_sigma_is_the_point_with_the_largest_moment_error(s2, want):
+    """Reading A1 on a diagonal 3-DOF system, r_max = 2 (one moment step):
+    sigma_1 = s_1 and V_1 = X(s_1)/|X(s_1)|; then s_1's block becomes its next
+    moment, parallel to X(s_1) * X(s_1) entrywise, and s_2's block is X(s_2).
+    The moment errors are the sines of their angles with V_1 (cross
+    products), and sigma_2 is the point with the larger one.  s_2 = 30 and 3
+    give the larger error at s_2, s_2 = 1.02 (next to s_1) at s_1, so neither
+    the smaller error nor a fixed index passes all three."""
+    k, ms, ks, f, cp = _diag_system()
+    alpha, s1 = 0.1, 1.0
+    x = lambda s: 1.0 / ((s * s + alpha * s) + k)  # noqa: E731
+    e_closed = [_sin_angle(x(s1), x(s1) * x(s1)), _sin_angle(x(s1), x(s2))]
+    assert (e_closed[1] > e_closed[0]) == (want == 1)
+    _, _, hist = airga_loop.airga(ms, ks, alpha, 0.0, f, cp, None, [s1, s2], rmax=2, max_outer=1)
+    h = hist[0]
+    assert h["sigmas"] == [0, want]
+    assert np.allclose(h["step_errors"][0], e_closed, rtol=1e-12, atol=0)
+    # the choice on its own: largest error, first index on a tie
+    assert airga_loop.next_point(None) == 0
+    assert airga_loop.next_point([0.2, 0.7, 0.1]) == 1
+    assert airga_loop.next_point([0.5, 0.1, 0.5]) == 0
+
+
+def _quad_h2(a, b):
+    """||H_a - H_b||_H2 by quadrature of the frequency response."""
+    import scipy.integrate as si
+
+    def dens(w):
+        h = a.transfer(1j * w) - b.transfer(1j * w)
+        return float(np.sum(np.abs(h) ** 2))
+    val = 0.0
+    for lo, hi in ((0, 0.1), (0.1, 1), (1, 10), (10, 100), (100, 1e3), (1e3, np.inf)):
+        val += si.quad(dens, lo, hi, epsabs=0, epsrel=1e-10, limit=500)[0]
+    return np.sqrt(val / np.pi)
+
+
+def test_inner_loop_stops_at_the_first_relative_change_below_tol():
+    """Reading A5 for the moment loop: run it to r_max with tol 0, check each
+    recorded change against ||H_j - H_{j-1}|| / ||H_j|| by quadrature of the
+    intermediate models' frequency responses, then set tol between the
+    smallest change and every earlier one: the loop must stop on exactly
+    that step (J = its index + 2 blocks).  Scaling F by 1e3 and C_p by
+    1e-3 scales every H by the same factor and must change nothing."""
+    pen, ms, ks, f, cp = beam_system(n_el=20, m=1, alpha=0.2, beta=0.05)
+    shifts = [0.5, 3.0, 20.0]
+    _, _, full = airga_loop.airga(ms, ks, pen.alpha, pen.beta, f[:, :1], cp, None, shifts,
+                                  rmax=8, tol_inner=0.0, max_outer=1)
+    h = full[0]
+    ch = h["inner_changes"]
+    mods = h["inner_models"]
+    assert len(ch) == len(mods) - 1 >= 3 and h["J"] == 8
+    for j, c in enumerate(ch):
+        num = _quad_h2(mods[j + 1], mods[j])
+        den = _quad_h2(mods[j + 1], airga_loop.Model(mods[j + 1].mh, mods[j + 1].dh,
+                                                      mods[j + 1].kh, 0 * mods[j + 1].fh,
+                                                      mods[j + 1].cph))
+        assert abs(c - num / den) <= 1e-6 * num / den, j
+    t = int(np.argmin(ch))
+    earlier = min(ch[:t]) if t > 0 else np.inf
+    tol = 0.5 * (ch[t] + min(earlier, 2 * ch[t]))
+    for scale in (1.0, 1e3):
+        _, _, st = airga_loop.airga(ms, ks, pen.alpha, pen.beta, scale * f[:, :1], cp / scale,
+                                    None, shifts, rmax=8, tol_inner=tol, max_outer=1)
+        g = st[0]
+        assert len(g["inner_changes"]) == t + 1
+        assert g["J"] == t + 3 and g["sigmas"] == h["sigmas"][:t + 2] + [g["sigmas"][-1]]
+
+
+def test_outer_loop_stops_on_the_relative_change():
+    """Reading A5 for the outer loop: tol_outer = inf stops after the second
+    iteration (the first with a change), tol_outer = 0 runs max_outer."""
+    pen, ms, ks, f, cp = beam_system(n_el=20, m=1, alpha=0.2, beta=0.05)
+    for tol, want in ((np.inf, 2), (0.0, 3)):
+        _, _, hist = airga_loop.airga(ms, ks, pen.alpha, pen.beta, f[:, :1], cp, None,
+                                      [0.5, 3.0, 20.0], rmax=4, tol_outer=tol, max_outer=3)
+        assert len(hist) == want
+        assert hist[0]["change"] is None and all(x["change"] > 0 for x in hist[1:])
+
+
+# ----------------------------------------------------- complex expansion points
+
+def _cbeam(n_el=40, seed=1):
+    return beam.make_beam(n_el, ei_loguniform=(0.5, 2.0), surrogate=True, seed=seed)
+
+
+CSHIFTS = [3.0 + 2.0j, 0.5 - 4.0j, 100.0 + 50.0j, 1.0 + 0.1j]
+
+
+@pytest.mark.parametrize("s", CSHIFTS)
+def test_complex_reference_solve_matches_the_dense_solve(s):
+    pen = _cbeam()
+    f = np.random.default_rng(0).standard_normal((2, pen.n))
+    a = pencil.shifted_operator_complex(pen, s).toarray()
+    # K(s) is complex symmetric, not Hermitian
+    assert np.array_equal(a, a.T) and not np.allclose(a, a.conj().T)
+    x = np.linalg.solve(a, f.T).T
+    for prec in ("f64", "dd"):
+        y = direct.reference_solve_complex(pen, s, f, prec)
+        assert np.linalg.norm(y - x) <= 1e-13 * np.linalg.norm(x), prec
+
+
+def test_complex_reference_reduces_to_the_real_one_and_respects_conjugation():
+    pen = _cbeam()
+    f = np.random.default_rng(1).standard_normal((1, pen.n))
+    for s in (0.7, 25.0):
+        y = direct.reference_solve_complex(pen, s, f, "dd")
+        z = direct.reference_solve(pen, s, f, "dd")
+        assert np.abs(y.imag).max() == 0.0
+        assert np.linalg.norm(y.real - z) <= 1e-15 * np.linalg.norm(z)
+    # M, K and F are real, so K(conj s) = conj K(s) and X(conj s) = conj X(s)
+    for s in CSHIFTS:
+        a = direct.reference_solve_complex(pen, s, f, "dd")
+        b = direct.reference_solve_complex(pen, np.conj(s), f, "dd")
+        assert np.linalg.norm(b - a.conj()) <= 1e-14 * np.linalg.norm(a)
+
+
+def test_complex_shift_assembly_in_double_double_is_exact():
+    from fractions import Fraction as Fr
+    pen = _cbeam(6)
+    s = 3.0 + 2.0j
+    rh, rl, ih, il, w = direct.shifted_band_cdd(pen, s)
+    mb, _ = direct.lower_band(pencil.csr(pen.n, pen.row_ptr, pen.col_idx, pen.m_val), w)
+    kb, _ = direct.lower_band(pencil.csr(pen.n, pen.row_ptr, pen.col_idx, pen.k_val), w)
+    sr, si, al, be = Fr(3.0), Fr(2.0), Fr(pen.alpha), Fr(pen.beta)
+    # (s^2 + alpha s) M + (1 + beta s) K with s = sr + i si, exactly
+    a_re, a_im = sr * sr - si * si + al * sr, 2 * sr * si + al * si
+    b_re, b_im = 1 + be * sr, be * si
+    for e in range(mb.size):
+        m, k = Fr(mb.flat[e]), Fr(kb.flat[e])
+        want_re, want_im = a_re * m + b_re * k, a_im * m + b_im * k
+        for hi, lo, want in ((rh, rl, want_re), (ih, il, want_im)):
+            got = Fr(hi.flat[e]) + Fr(lo.flat[e])
+            assert abs(got - want) <= abs(want) * Fr(1, 2 ** 100) + Fr(1, 2 ** 1000)
+
+
+@pytest.mark.parametrize("s", CSHIFTS)
+def test_complex_spai_columns_are_least_squares_optimal(s):
+    pen = _cbeam(30)
+    a = pencil.shifted_operator_complex(pen, s)
+    fac = spai.spai_build(a, symmetrize=False)
+    d = a.diagonal()
+    sc = 1 / np.sqrt(d)
+    ah = (sp.diags(sc) @ a @ sp.diags(sc)).toarray()
+    hat = sp.csr_matrix((fac.hat, pen.col_idx, pen.row_ptr), shape=(pen.n, pen.n)).toarray()
+    for j in range(pen.n):
+        jj = pen.col_idx[pen.row_ptr[j]:pen.row_ptr[j + 1]]
+        res = np.eye(pen.n)[:, j] - ah[:, jj] @ hat[jj, j]
+        # normal equations of the complex problem: B^H r = 0
+        assert np.linalg.norm(ah[:, jj].conj().T @ res) <= 1e-12 * np.linalg.norm(ah[:, jj]) * max(
+            np.linalg.norm(res), 1e-300)
+        # the full n-row problem gives the same column
+        full, *_ = np.linalg.lstsq(ah[:, jj], np.eye(pen.n)[:, j], rcond=None)
+        assert np.allclose(hat[jj, j], full, rtol=0, atol=1e-11 * np.abs(full).max())
+        assert abs(fac.objective[j] - np.linalg.norm(res)) <= 1e-12 * max(1, fac.objective[j])
+
+
+def test_complex_spai_special_cases():
+    pen = _cbeam(8)
+    s = 3.0 + 2.0j
+    a = pencil.shifted_operator_complex(pen, s)
+    # symmetric average: the factor is complex symmetric (plain transpose)
+    p = spai.spai_build(a).matrix().toarray()
+    assert np.allclose(p, p.T, rtol=0, atol=1e-15 * np.abs(p).max())
+    # a real shift gives the real factor
+    ar = pencil.shifted_operator_complex(pen, 7.0)
+    pr = spai.spai_build(ar).values
+    assert np.allclose(pr.real, spai.spai_build(pencil.shifted_operator(pen, 7.0)).values,
+                       rtol=1e-13, atol=0)
+    assert np.abs(pr.imag).max() == 0.0
+    # the full pattern gives the inverse
+    n = pen.n
+    dense = sp.csr_matrix(a.toarray() + 0 * np.ones((n, n)))
+    full = sp.csr_matrix((np.asarray(a.toarray()).ravel(), np.tile(np.arange(n), n),
+                          np.arange(0, n * n + 1, n)), shape=(n, n))
+    inv = spai.spai_build(full, equilibrate=False, symmetrize=False).matrix().toarray()
+    assert np.allclose(inv, np.linalg.inv(dense.toarray()), rtol=0,
+                       atol=1e-10 * np.abs(np.linalg.inv(dense.toarray())).max())
+    # complex alpha: the Frobenius minimiser of ||I - alpha K||, by brute force
+    al = spai.spai_build(a, cols=[0]).alpha
+    f = lambda z: np.linalg.norm(np.eye(n) - z * a.toarray())  # noqa: E731
+    for dz in (1e-3, 1e-3j, -1e-3, -1e-3j):
+        assert f(al) <= f(al * (1 + dz))
+
+
+def test_cocg_matches_the_dense_solve_and_cg_on_real_data():
+    pen = _cbeam(50)
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal(pen.n)
+    for s in CSHIFTS:
+        a = pencil.shifted_operator_complex(pen, s)
+        p = spai.spai_build(a).matrix()
+        r = pcg.cocg(lambda v: a @ v, lambda v: p @ v, f, tol=1e-12, max_iter=4000)
+        x = np.linalg.solve(a.toarray(), f)
+        assert r.status == pcg.CONVERGED
+        assert np.linalg.norm(r.x - x) <= 1e-9 * np.linalg.norm(x)
+    # real data: COCG is CG (same iterates as the oracle's PCG, both betas)
+    a = pencil.shifted_operator(pen, 20.0)
+    p = spai.spai_build(a).matrix()
+    for form in ("flexible", "fr"):
+        r1 = pcg.cocg(lambda v: a @ v, lambda v: p @ v, f, tol=1e-10, beta=form)
+        r2 = pcg.pcg(lambda v: a @ v, lambda v: p @ v, f, tol=1e-10, beta=form)
+        assert r1.iters == r2.iters
+        assert np.linalg.norm(r1.x - r2.x) <= 1e-12 * np.linalg.norm(r2.x)
+
+
+def test_cocg_terminates_and_keeps_the_residuals_conjugate_orthogonal():
+    # n = 12, complex symmetric K and C: the residuals are orthogonal in the
+    # bilinear form through C (r_i^T C r_k = 0, i != k), which ends the
+    # iteration within n steps in exact arithmetic
+    rng = np.random.default_rng(5)
+    n = 12
+    g = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    k = (2 + 1j) * np.eye(n) + 0.1 * (g + g.T)
+    h = rng.standard_normal((n, n)) + 0.3j * rng.standard_normal((n, n))
+    c = np.eye(n) + 0.05 * (h + h.T)
+    f = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    r = pcg.cocg(lambda v: k @ v, lambda v: c @ v, f, tol=1e-12, max_iter=3 * n, keep=True,
+                 beta="fr")
+    assert r.status == pcg.CONVERGED and r.iters <= n + 2
+    res = r.residuals
+    for i in range(len(res)):
+        for j in range(i + 1, len(res)):
+            zj = c @ res[j]
+            assert abs(res[i] @ zj) <= 1e-8 * np.linalg.norm(res[i]) * np.linalg.norm(zj)
+    assert np.linalg.norm(r.x - np.linalg.solve(k, f)) <= 1e-10 * np.linalg.norm(r.x)
+    # mu = p^T K p = 0 stops the iteration as a breakdown
+    z = np.array([1.0, 1j])
+    kk = np.eye(2)
+    br = pcg.cocg(lambda v: kk @ v, lambda v: v, z, tol=1e-12)
+    assert br.status == pcg.BREAKDOWN and br.iters == 0
