@@ -1007,3 +1007,19 @@ def test_cocg_terminates_and_keeps_the_residuals_conjugate_orthogonal():
     kk = np.eye(2)
     br = pcg.cocg(lambda v: kk @ v, lambda v: v, z, tol=1e-12)
     assert br.status == pcg.BREAKDOWN and br.iters == 0
+
+
+def test_reference_solves_equal_the_single_shift_reference():
+    # the bands of M and K extracted once give bit-identical references
+    pen = beam.make_beam(150, ei_loguniform=(0.5, 2.0), surrogate=True, seed=4)
+    f = np.random.default_rng(2).standard_normal((2, pen.n))
+    shifts = [1.0, 37.0, 2500.0]
+    for prec in ("f64", "dd"):
+        many = direct.reference_solves(pen, shifts, f, prec, workers=2)
+        seen = []
+        direct.reference_solves(pen, shifts, f, prec, workers=2,
+                                each=lambda i, x: seen.append((i, x)))
+        for k, s in enumerate(shifts):
+            one = direct.reference_solve(pen, s, f, prec)
+            assert np.array_equal(many[k], one)
+            assert seen[k][0] == k and np.array_equal(seen[k][1], one)
