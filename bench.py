@@ -20,6 +20,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4s]
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
 import gc
 import json
 import os
@@ -271,15 +272,14 @@ def measure_copy(stream, dev, mib=1024, reps=5):
     return 2.0 * (mib << 20) / (statistics.median(times) * 1e-3) / 1e9
 
 
-def measure_airga_iteration(ctx, stream, F, n, alpha, beta, shifts=(1.0, 30.0, 500.0), rmax=24,
-                            solve_kw=None, tol_inner=1e-6):
-    """One outer iteration of Algorithm 1 at full size, composed from the
-    library's entry points with readings A1-A6 (as the GPU tests run it):
-    SPAI builds and solves at the l expansion points, thin QR of each block,
-    the moment loop (sigma_j by the moment error, moment solves, trace
-    orthogonalisation, intermediate models and their H2 changes), the final
-    basis and model, and the next expansion points.  Output: tip deflection.
-    Wall time of the whole iteration (host decisions included)."""
+def measure_airga_iteration(ctx, stream, F, n, shifts=(1.0, 30.0, 500.0), rmax=24,
+                            solve_kw=None, max_outer=1):
+    """AIRGA's outer loop at full size through airga_reduce (Algorithm 1 with
+    SPAI-preconditioned solves): SPAI builds and solves at the l expansion
+    points, thin QR of each block, the moment loop (sigma_j by the moment
+    error, moment solves, trace orthogonalisation, intermediate models and
+    their H2 changes), the final basis and model, and the next expansion
+    points.  Output: tip deflection.  Wall time of the call."""
     import torch
     from paper_1606_01216_amd import airga
     kw = dict(solve_kw or {})
@@ -287,69 +287,23 @@ def measure_airga_iteration(ctx, stream, F, n, alpha, beta, shifts=(1.0, 30.0, 5
     l = len(shifts)
     cp = torch.zeros((1, n), dtype=torch.float64, device=F.device)
     cp[0, n - 2] = 1.0
-    out = {"n": n, "m": m, "l": l, "rmax": rmax, "shifts": list(shifts)}
+    out = {"n": n, "m": m, "l": l, "rmax": rmax, "shifts": list(shifts), "max_outer": max_outer}
     try:
         with torch.cuda.stream(stream):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            precs = ctx.spai_build_many(list(shifts))
-            X, _ = ctx.pcg_solve(list(shifts), precs, F, **kw)
-            xs = X.reshape(l * m, n).contiguous()
-            for i in range(l):
-                b = xs[i * m:(i + 1) * m].clone()
-                ctx.block_qr(b)
-                xs[i * m:(i + 1) * m] = b
-
-            def model_of(w):
-                mh, kh = ctx.project(w)
-                return (mh, kh, ctx.gram(w, F).cpu().numpy(), ctx.gram(w, cp).cpu().numpy().T, None)
-
-            def block(q):
-                v = xs[q * m:(q + 1) * m].clone()
-                ctx.global_orth(None, v, m, normalize=True)
-                return v
-            vs, sigmas, changes, iters = [], [], [], []
-            errors, prev = None, None
-            j = 1
-            while j < rmax // m:
-                q = 0 if errors is None else int(np.argmax(errors))
-                sigmas.append(q)
-                vs.append(block(q))
-                y, st = ctx.pcg_solve([shifts[q]], [precs[q]], ctx.pencil_apply(1.0, 0.0, vs[-1]), **kw)
-                iters.append(max(e["iters"] for e in st))
-                xs[q * m:(q + 1) * m] = -y[0]
-                _, before = ctx.global_orth(None, xs.clone(), m)
-                _, after = ctx.global_orth(torch.cat(vs).contiguous(), xs, m)
-                errors = after / before
-                w = xs.clone()
-                ctx.global_orth(None, w, m, normalize=True)
-                ctx.block_qr(w)
-                mi = model_of(w)
-                if prev is not None:
-                    # relative H2 change; None where the norm is not resolved
-                    # (no positive finite value), which never stops the loop
-                    norm = airga.h2_distance(mi, None, alpha, beta)
-                    ch = (airga.h2_distance(mi, prev, alpha, beta) / norm
-                          if np.isfinite(norm) and norm > 0 else None)
-                    changes.append(ch)
-                    if ch is not None and ch < tol_inner:
-                        j += 1
-                        break
-                prev = mi
-                j += 1
-            q = 0 if errors is None else int(np.argmax(errors))
-            sigmas.append(q)
-            vs.append(block(q))
-            v = torch.cat(vs).contiguous()
-            ctx.block_qr(v)
-            final = model_of(v)
-            nxt = airga.next_shifts(airga.qep_poles(final[0], final[1], alpha, beta), l)
+            res = ctx.reduce(F, cp, list(shifts), r_max=rmax, max_outer=max_outer,
+                             mode=kw.get("mode", airga.MODE_FP64), tol=kw.get("tol", 1e-10),
+                             max_iter=kw.get("max_iter", 20000),
+                             poll_every=kw.get("poll_every", 8))
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-        out.update({"ms": round((t1 - t0) * 1e3, 2), "J": len(vs), "sigmas": sigmas,
-                    "moment_solve_iters_max": iters,
-                    "inner_h2_changes": [None if c is None else float(f"{c:.3e}") for c in changes],
-                    "next_shifts": [float(f"{s:.6g}") for s in nxt]})
+        h = res["history"][-1]
+        out.update({"ms": round((t1 - t0) * 1e3, 2), "iterations": res["iterations"],
+                    "J": h["J"], "sigmas": h["sigmas"], "moment_steps": h["moment_steps"],
+                    "max_iters": h["max_iters"], "all_converged": h["all_converged"],
+                    "last_inner_h2_change": h["last_inner_change"],
+                    "next_shifts": [float(f"{v:.6g}") for v in res["next_shifts"]]})
     except airga.AirgaError as e:
         out["error"] = str(e)
     return out
@@ -420,6 +374,367 @@ def measure_spai_mr(ctx, stream, shifts, precs, F, X, solve_kw, mr_iters=20, tol
     return out
 
 
+# ------------------------------------------------------- algorithmic bytes
+#
+# Bytes each kernel of a solve must move (DESIGN's kernel table), from the
+# work the library counted in a profiled solve: launches, (system, launch)
+# passes and (shift, launch) passes.  w = bytes per vector value, fw = per
+# preconditioner value, ib = column information per stored entry.
+def kernel_bytes(name, launches, sysp, shp, *, stored, n, ib, w, fw, m, first_passes=0,
+                 mixed=True, gp=0, red_sys=0, assign_sys=0):
+    if name == "dir_spmv":
+        return launches * stored * (ib + 2 * w) + sysp * 4 * w * n
+    if name == "update_prec":
+        return launches * stored * ib + shp * stored * fw + (sysp * 7 - first_passes) * w * n
+    if name == "init_prec":
+        return launches * stored * ib + shp * stored * fw + sysp * 2 * w * n
+    if name == "chain":
+        # int32 columns once per launch, each (shift, factor) pair's values,
+        # and per (system, factor): read t, write z
+        return launches * stored * 4 + shp * stored * fw + sysp * 2 * w * n
+    if name == "ir_residual":
+        # float64 M and K with their columns, F once per launch and column,
+        # per system: read X, write r
+        return launches * stored * (ib + 16) + launches * m * 8 * n + sysp * (8 + w) * n
+    if name == "ir_update":
+        # mixed: read X and the correction, write X (the first sweep of a
+        # solve without a starting guess assigns X: no read, assign_sys
+        # systems); float64: copy out
+        return (sysp * (16 + w) - assign_sys * 8) * n if mixed else sysp * 16 * n
+    if name == "reduce":
+        # one block per active system reads its partials: about 8 B per
+        # row-kernel block and slot (gp blocks, red_sys (system, slot) reads)
+        return red_sys * gp * 8
+    return None
+
+
+def row_blocks(n, rows_per_wave):
+    """Blocks of a row-kernel launch (4 wavefronts of rows_per_wave rows over
+    the 64-row padded matrix), one partial per block and system and slot."""
+    n_pad = -(-n // 64) * 64
+    waves = -(-n_pad // rows_per_wave)
+    return -(-waves // 4)
+
+
+def kernel_rows(kt, kwk, **kw):
+    """Per-kernel launches, time, algorithmic bytes and GB/s of a profiled solve."""
+    sysp_of = {k: v[0] for k, v in kwk.items()}
+    # slots the reductions read: 1 per direction pass, 3 per update pass, 2 per restart
+    red_sys = (sysp_of.get("dir_spmv", 0) + 3 * sysp_of.get("update_prec", 0) +
+               2 * sysp_of.get("init_prec", 0))
+    rows = []
+    for name in ("dir_spmv", "update_prec", "init_prec", "chain", "ir_residual", "ir_update",
+                 "reduce"):
+        la, ms = kt.get(name, (0, 0.0))
+        sysp, shp = kwk.get(name, (0, 0))
+        if la:
+            b = kernel_bytes(name, la, sysp, shp, red_sys=red_sys, **kw)
+            rows.append(dict(kernel=name, launches=la, total_ms=round(ms, 4),
+                             avg_us=round(1e3 * ms / la, 2),
+                             gbs=round(b / (ms * 1e-3) / 1e9, 1) if b and ms > 0 else None,
+                             bytes=int(b) if b is not None else None))
+    return rows
+
+
+# ------------------------------------------------------------ CPU baseline
+#
+# The oracle's reference solves on this host's cores: one thread, and all
+# the cores this process may use (up to CPU_WORKERS, the host-core share of
+# one GPU on the benchmark machine), independent shifts on threads (the C
+# part of the oracle releases the interpreter lock).
+CPU_WORKERS = 16
+
+
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        visible = len(os.sched_getaffinity(0))
+    except AttributeError:
+        visible = os.cpu_count() or 1
+    return model, visible
+
+
+def oracle_refs(pen, shift_list, f, precision, workers):
+    """Oracle X(s) (m, n) for every shift in shift_list."""
+    from oracle import _native, direct
+    _native.lib()
+    job = lambda s: direct.reference_solve(pen, s, f, precision)  # noqa: E731
+    if workers <= 1:
+        return [job(s) for s in shift_list]
+    with cf.ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(job, shift_list))
+
+
+def median_time(fn, reps=3):
+    """(median seconds over reps runs, result of the last run)."""
+    ts, res = [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        res = fn()
+        ts.append(time.perf_counter() - t0)
+    return statistics.median(ts), res
+
+
+def measure_cpu_baseline(pen, f, shift_sets, sample_shifts=4, reps=3):
+    """Oracle timings (double-double and binary64 banded Cholesky) on one
+    thread for a sample of shifts and on all cores for every shift of the
+    step, medians of `reps`; returns the timings and both references."""
+    model, visible = cpu_info()
+    workers = max(1, min(CPU_WORKERS, visible))
+    allsh = [s for ss in shift_sets for s in ss]
+    m = f.shape[0]
+    sample = list(shift_sets[0][:sample_shifts])
+    t_dd1, _ = median_time(lambda: oracle_refs(pen, sample, f, "dd", 1), reps)
+    t_ddw, refs_dd = median_time(lambda: oracle_refs(pen, allsh, f, "dd", workers), reps)
+    t_641, _ = median_time(lambda: oracle_refs(pen, sample, f, "f64", 1), reps)
+    t_64w, refs_64 = median_time(lambda: oracle_refs(pen, allsh, f, "f64", workers), reps)
+    ns, na = len(sample) * m, len(allsh) * m
+    return dict(cpu_model=model, cores_visible=visible, cores_all=workers,
+                dd_1=ns / t_dd1, dd_all=na / t_ddw, f64_1=ns / t_641, f64_all=na / t_64w,
+                sample_systems=ns, all_systems=na, t_dd1=t_dd1, t_ddw=t_ddw, t_641=t_641,
+                t_64w=t_64w), refs_dd, refs_64
+
+
+def rel_errors(X, refs, S, m):
+    """Per-system ||X - ref|| / ||ref|| for X (S, m, n) and refs[k] (m, n)."""
+    out = []
+    for k in range(S):
+        for c in range(m):
+            nr = np.linalg.norm(refs[k][c])
+            out.append(float(np.linalg.norm(X[k, c] - refs[k][c]) / nr))
+    return out
+
+
+# ------------------------------------------------ update-chain sequence (C2)
+def measure_c2_sequence(dev, stream, tol=1e-8, seed=0, reps=2):
+    """The plain float64 solve sequence of the 100,000-DOF beam: the SPAI
+    (equilibrated, without the symmetric average, whose factor at s = 1 is
+    indefinite and breaks every chain built on it) is built at the first of
+    8 log-spaced shifts and updated along them (the
+    horizontal chain Q_8 ... Q_2 P_1), then updated again at three seeded
+    vertical drifts of every shift (epsilon 1e-2, 1e-3, 1e-3), each new
+    expansion point solved once with its chain (float64, one system per
+    solve, relative residual tol).  Every solve is checked against the
+    oracle's double-double reference.  The sequence runs `reps` times; the
+    last run is reported (the first also autotunes)."""
+    import torch
+    from paper_1606_01216_amd import airga
+    pen, f, shifts, rng = beam.make_workload("c2", surrogate=True, seed=seed)
+    levels = [np.asarray(shifts, float)]
+    for eps in (1e-2, 1e-3, 1e-3):
+        levels.append(beam.drift_shifts(levels[-1], eps, rng))
+    n = pen.n
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    ctx = airga.Context(0, stream)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    F = t(f, torch.float64)
+    X = torch.zeros((len(levels), len(shifts), 1, n), dtype=torch.float64, device=dev)
+    kw = dict(tol=tol, mode=airga.MODE_FP64, max_iter=20000, poll_every=8, use_graph=False)
+    with torch.cuda.stream(stream):
+        ctx.set_pencil(t(pen.row_ptr, torch.int32), t(pen.col_idx, torch.int32),
+                       t(pen.m_val, torch.float64), t(pen.k_val, torch.float64),
+                       pen.alpha, pen.beta)
+        for _ in range(reps):
+            recs, handles = [], []
+            torch.cuda.synchronize()
+            t_all0 = time.perf_counter()
+            prev_level = None
+            for z, lev in enumerate(levels):
+                cur = []
+                for i, s in enumerate(lev):
+                    e0, e1 = ev(), ev()
+                    e0.record(stream)
+                    if z == 0:
+                        p = (ctx.spai_build(float(s), symmetrize=False) if i == 0
+                             else ctx.spai_update(cur[-1], float(s)))
+                    else:
+                        p = ctx.spai_update(prev_level[i], float(s))
+                    e1.record(stream)
+                    cur.append(p)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, st = ctx.pcg_solve([float(s)], [p], F, X[z, i:i + 1], **kw)
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    info = p.info()
+                    recs.append(dict(z=z + 1, i=i + 1, shift=float(s), chain_len=info.chain_len,
+                                     skipped_frac=round(info.skipped_cols / n, 4),
+                                     kind="build" if (z == 0 and i == 0) else
+                                     ("horizontal" if z == 0 else "vertical"),
+                                     prec_ms=round(e0.elapsed_time(e1), 4),
+                                     solve_ms=round((t1 - t0) * 1e3, 3), iters=st[0]["iters"],
+                                     status=airga.STATUS_NAMES[st[0]["status"]]))
+                handles.extend(cur)
+                prev_level = cur
+            torch.cuda.synchronize()
+            t_all = time.perf_counter() - t_all0
+            for p in handles:
+                p.release()
+    Xh = X.cpu().numpy()
+    refs = oracle_refs(pen, [s for lev in levels for s in lev], f, "dd",
+                       max(1, min(CPU_WORKERS, cpu_info()[1])))
+    for r, ref in zip(recs, refs):
+        x = Xh[r["z"] - 1, r["i"] - 1, 0]
+        r["rel_err"] = float(f"{np.linalg.norm(x - ref[0]) / np.linalg.norm(ref[0]):.3e}")
+    ctx.close()
+    by_len = {}
+    for r in recs:
+        by_len.setdefault(r["chain_len"], []).append(r)
+    upd = [r for r in recs if r["kind"] != "build"]
+    solved_upd = [r for r in upd if r["skipped_frac"] < 1.0]
+    return {
+        "workload": "Hermite cantilever n=100,000 (EI log-uniform [0.5,2], scaled by h^4), tip "
+                    "load, 8 shifts logspace(0,4,8), 3 vertical drifts (1e-2, 1e-3, 1e-3)",
+        "n": n, "tol_relres": tol, "solves": len(recs), "sequence_ms": round(t_all * 1e3, 2),
+        "solved_to_1e-8": sum(r["rel_err"] <= ERR_TOL for r in recs),
+        "max_rel_err": max(r["rel_err"] for r in recs),
+        "build_ms": recs[0]["prec_ms"],
+        "update_ms_mean": round(statistics.mean(r["prec_ms"] for r in upd), 4),
+        "update_ms_mean_with_solved_columns": round(statistics.mean(
+            r["prec_ms"] for r in solved_upd), 4) if solved_upd else None,
+        "update_skipped_frac_mean": {
+            "horizontal": round(statistics.mean(r["skipped_frac"] for r in upd
+                                                if r["kind"] == "horizontal"), 4),
+            "vertical": round(statistics.mean(r["skipped_frac"] for r in upd
+                                              if r["kind"] == "vertical"), 4)},
+        "by_chain_len": {str(k): {"solves": len(v),
+                                  "iters_mean": round(statistics.mean(r["iters"] for r in v), 1),
+                                  "solve_ms_mean": round(statistics.mean(r["solve_ms"] for r in v), 3)}
+                         for k, v in sorted(by_len.items())},
+        "solves_detail": recs}
+
+
+def measure_complex(ctx, stream, pen, f, F, sigmas, tol, reps=3, angle=np.pi / 6):
+    """Complex expansion points s_k = sigma_k e^{i angle} (the workload's real
+    points turned off the real axis; K(s) complex symmetric): the complex
+    SPAI at every point and one batched COCG of all (point, column) systems
+    in float64, warmed by one untimed run, wall time median of `reps`;
+    every system against the oracle's complex double-double reference.
+    Algorithmic bytes per iteration and system: 64 n (direction kernel: read
+    z and p, write p and w) + 112 n (update kernel: read r, w, x, p, write
+    x, r, z), 16-byte complex values; per launch the pencil (20 B per stored
+    entry: column, M, K) and per (point, launch) the factor (16 B)."""
+    import torch
+    from paper_1606_01216_amd import airga
+    n, m = pen.n, F.shape[0]
+    cs = [complex(v * np.exp(1j * angle)) for v in sigmas]
+    with torch.cuda.stream(stream):
+        # the context holds the workload's pencil (set by every step)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        precs = [ctx.spai_build_complex(s) for s in cs]
+        e1.record(stream)
+        e1.synchronize()
+        build_ms = e0.elapsed_time(e1) / len(cs)
+        X = torch.empty((len(cs), m, n), dtype=torch.complex128, device=F.device)
+        ctx.cocg_solve(cs, precs, F, X, tol=tol)
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = ctx.cocg_solve(cs, precs, F, X, tol=tol)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+    t = statistics.median(ts)
+    its = [e["iters"] for e in st]
+    stored = ctx.pencil_info().nnz_stored
+    launches = 2 * max(its)
+    byts = sum(its) * 176 * n + launches * 20 * stored + max(its) * len(cs) * 16 * stored
+    refs = oracle_refs_complex(pen, cs, f, max(1, min(CPU_WORKERS, cpu_info()[1])))
+    Xh = X.cpu().numpy()
+    errs = [rel_errors_c(Xh[k, c], refs[k][c]) for k in range(len(cs)) for c in range(m)]
+    ok = sum(e <= ERR_TOL for e in errs)
+    for p in precs:
+        p.release()
+    return {"workload": f"{len(cs)} complex points sigma_k e^(i pi/6), sigma_k = the real "
+                        f"workload's points; {m} loads; {len(cs) * m} systems",
+            "precision": "complex float64", "spai_build_ms_per_shift": round(build_ms, 4),
+            "cocg_solves_per_s": round(ok / t, 2), "seconds_median_of_3": round(t, 4),
+            "solved_to_1e-8": ok, "systems": len(errs), "max_rel_err": max(errs),
+            "iters_median": statistics.median(its), "iters_max": max(its),
+            "converged": sum(e["status"] == airga.SYS_CONVERGED for e in st),
+            "algorithmic_gbs": round(byts / t / 1e9, 1),
+            "frac_hbm": round(byts / t / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def oracle_refs_complex(pen, shifts, f, workers):
+    from oracle import _native, direct
+    _native.lib()
+    with cf.ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(lambda s: direct.reference_solve_complex(pen, s, f, "dd"), shifts))
+
+
+def rel_errors_c(x, ref):
+    return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
+
+
+def measure_batched_fp64(ctx, stream, sets, F, tol, poll_every, reps=5):
+    """Config 3: batched float64 PCG of every system of a step (one call per
+    shift set, all its systems in one set of kernels), warmed by one untimed
+    run; wall time median of `reps`, then one profiled run (kernel table)."""
+    import torch
+    from paper_1606_01216_amd import airga
+    kw = dict(tol=tol, mode=airga.MODE_FP64, max_iter=20000, poll_every=poll_every)
+    with torch.cuda.stream(stream):
+        def run(profile=False):
+            sts = []
+            for ss, pp, XX in sets:
+                _, st = ctx.pcg_solve(ss, pp, F, XX, profile=profile, **kw)
+                sts += st
+            return sts
+        run()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sts = run()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        # profiled: the second set only (kernel table of one solve)
+        ss, pp, XX = sets[-1]
+        _, stp = ctx.pcg_solve(ss, pp, F, XX, profile=True, **kw)
+        kt, kwk = ctx.kernel_times(), ctx.kernel_work()
+        tile = ctx.tile_config()
+    return statistics.median(ts), sts, kt, kwk, tile
+
+
+def measure_plain_fp64(ctx, stream, sets, F, tol, poll_every, reps=5):
+    """Plain float64 PCG one system at a time on the same systems and
+    preconditioners, into preallocated outputs; warmed by one untimed pass,
+    wall time median of `reps` passes."""
+    import torch
+    from paper_1606_01216_amd import airga
+    n = F.shape[1]
+    kw = dict(tol=tol, mode=airga.MODE_FP64, max_iter=20000, poll_every=poll_every)
+    with torch.cuda.stream(stream):
+        def run():
+            sts = []
+            for ss, pp, XX in sets:
+                for k in range(len(ss)):
+                    for c in range(F.shape[0]):
+                        _, st = ctx.pcg_solve([ss[k]], [pp[k]], F[c:c + 1],
+                                              XX[k, c].view(1, 1, n), **kw)
+                        sts.append(st[0])
+            return sts
+        run()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sts = run()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+    return statistics.median(ts), sts
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -429,6 +744,12 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain float64 comparator")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c2", action="store_true",
+                    help="skip the 100,000-DOF update-chain sequence")
+    ap.add_argument("--no-complex", action="store_true",
+                    help="skip the complex-expansion-point leg")
+    ap.add_argument("--c2-only", action="store_true",
+                    help="run only the update-chain sequence and print its JSON (for profilers)")
     ap.add_argument("--no-airga-iteration", action="store_true",
                     help="skip the full-size AIRGA iteration (its small solves would enter a "
                          "profiler's per-kernel averages)")
@@ -463,6 +784,10 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.c2_only:
+        stream = torch.cuda.Stream(device=dev)
+        print(json.dumps(measure_c2_sequence(dev, stream)))
+        return
     log(f"[bench] building inputs {args.workload}")
     pen, f, shifts, drifted = build_inputs(args.workload)
     n, m, S = pen.n, f.shape[0], len(shifts)
@@ -561,96 +886,91 @@ def main():
     tile = ctx.tile_config()
     info = ctx.pencil_info()
 
+    stored = info.nnz_stored
+    # column information per stored entry: a 1-byte offset for banded
+    # pencils (bandwidth <= 64, the LDS-window kernels), else a 4-byte index
+    ib = 1 if info.bandwidth <= 64 else 4
+    gp = row_blocks(n, tile[0])
+    sets_mixed = ((list(shifts), precs, X1), (list(drifted), upd, X2))
+
+    # config 3: batched float64 PCG of the same systems and preconditioners
+    batched64 = None
+    X3a = X3b = None
+    if not args.no_plain:
+        log("[bench] batched float64 PCG (same systems, all in one set of kernels)")
+        X3a, X3b = torch.zeros_like(X1), torch.zeros_like(X2)
+        t64, st64, kt64, kw64, tile64 = measure_batched_fp64(
+            ctx, stream, ((list(shifts), precs, X3a), (list(drifted), upd, X3b)), F, args.tol,
+            solve_kw["poll_every"])
+        gp64 = row_blocks(n, tile64[0])
+        rows64 = kernel_rows(kt64, kw64, stored=stored, n=n, ib=ib, w=8, fw=8, m=m,
+                             first_passes=0, mixed=False, gp=gp64)
+        batched64 = dict(seconds=t64, stats=st64, rows=rows64, tile=tile64)
+
     # plain float64, one system at a time, same systems and preconditioners
     plain = None
     Xp1 = Xp2 = None
     if not args.no_plain:
         log("[bench] plain float64 one-system-at-a-time comparator")
-        Xp1 = torch.zeros_like(X1)
-        Xp2 = torch.zeros_like(X2)
-        # each system solves into a scratch (1, 1, n) block, copied into place
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        plain_stats = []
-        with torch.cuda.stream(stream):
-            for (ss, pp, XX) in ((shifts, precs, Xp1), (drifted, upd, Xp2)):
-                for k in range(S):
-                    for c in range(m):
-                        out = torch.empty((1, 1, n), dtype=torch.float64, device=dev)
-                        _, st = ctx.pcg_solve([ss[k]], [pp[k]], F[c:c + 1], out, tol=args.tol,
-                                              mode=airga.MODE_FP64, max_iter=20000, poll_every=8)
-                        XX[k, c].copy_(out[0, 0])
-                        plain_stats.append(st[0])
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        plain = dict(seconds=tb - ta, stats=plain_stats)
+        Xp1, Xp2 = torch.zeros_like(X1), torch.zeros_like(X2)
+        tp, pst = measure_plain_fp64(ctx, stream, ((list(shifts), precs, Xp1),
+                                                   (list(drifted), upd, Xp2)), F, args.tol,
+                                     solve_kw["poll_every"])
+        plain = dict(seconds=tp, stats=pst)
 
-    # ---- CPU baseline leg: the oracle's reference solves (double-double banded
-    # Cholesky) for every system of the step, timed on this host, and the
-    # accuracy of the GPU results against them.
-    errs_mixed, errs_plain, cpu = [], [], None
+    # ---- CPU baseline leg: the oracle's reference solves (double-double and
+    # binary64 banded Cholesky) for every system of the step, timed on this
+    # host, and the accuracy of the GPU results against both.
+    errs = {}
+    cpu = None
     if not args.no_cpu_baseline:
-        from oracle import direct, spai as ospai, pencil as opencil
+        from oracle import spai as ospai, pencil as opencil
         log("[bench] oracle reference solves (CPU)")
-        Xh1, Xh2 = X1.cpu().numpy(), X2.cpu().numpy()
-        Xq1 = Xp1.cpu().numpy() if Xp1 is not None else None
-        Xq2 = Xp2.cpu().numpy() if Xp2 is not None else None
-        tc0 = time.perf_counter()
-        refs = []
-        for ss in (shifts, drifted):
-            refs.append(np.stack([direct.reference_solve(pen, s, f, "dd") for s in ss]))
-        tc1 = time.perf_counter()
-        for Xg, Xq, R in ((Xh1, Xq1, refs[0]), (Xh2, Xq2, refs[1])):
-            for k in range(S):
-                for c in range(m):
-                    nr = np.linalg.norm(R[k, c])
-                    errs_mixed.append(float(np.linalg.norm(Xg[k, c] - R[k, c]) / nr))
-                    if Xq is not None:
-                        errs_plain.append(float(np.linalg.norm(Xq[k, c] - R[k, c]) / nr))
+        cpu, refs_dd, refs_64 = measure_cpu_baseline(pen, f, (list(shifts), list(drifted)))
+        rd = (refs_dd[:S], refs_dd[S:])
+        r6 = (refs_64[:S], refs_64[S:])
+        for key, pair in (("mixed", (X1, X2)), ("plain", (Xp1, Xp2)), ("batched64", (X3a, X3b))):
+            if pair[0] is None:
+                continue
+            xa, xb = pair[0].cpu().numpy(), pair[1].cpu().numpy()
+            errs[key] = (rel_errors(xa, rd[0], S, m) + rel_errors(xb, rd[1], S, m),
+                         rel_errors(xa, r6[0], S, m) + rel_errors(xb, r6[1], S, m))
         # oracle SPAI on a column sample of the first shift, scaled to n columns
         rng = np.random.default_rng(0)
         cols = np.sort(rng.choice(n, size=min(n, 4000), replace=False))
         a0 = opencil.shifted_operator(pen, shifts[0])
         ts0 = time.perf_counter()
         ospai.spai_build(a0, cols=cols)
-        ts1 = time.perf_counter()
-        cpu = dict(seconds=tc1 - tc0, spai_sample_s=ts1 - ts0, spai_cols=len(cols))
+        cpu["spai_sample_s"] = time.perf_counter() - ts0
+        cpu["spai_cols"] = len(cols)
+        # the oracle's own trust metric: binary64 against double-double
+        cpu["f64_vs_dd_max"] = max(
+            float(np.linalg.norm(a - b) / np.linalg.norm(b))
+            for A, Bm in zip(refs_64, refs_dd) for a, b in zip(A, Bm))
 
+    errs_mixed = errs.get("mixed", ([], []))[0]
     n_ok = sum(e <= ERR_TOL for e in errs_mixed) if errs_mixed else conv
     value = n_ok / (ms_per_step / 1e3)
 
     # ---- roofline of the dominant row kernel (algorithmic bytes / duration)
-    stored = info.nnz_stored
-    w = 4  # float32 inner solves
-    fw = 2  # their preconditioner values: bfloat16
-    # column information per stored entry: a 1-byte offset for banded
-    # pencils (bandwidth <= 64, the LDS-window kernels), else a 4-byte index
-    ib = 1 if info.bandwidth <= 64 else 4
-    def kbytes(name, launches, sysp, shp):
-        if name == "dir_spmv":
-            return launches * stored * (ib + 2 * w) + sysp * 4 * w * n
-        if name == "update_prec":
-            return launches * stored * ib + shp * stored * fw + (sysp * 7 - first_passes) * w * n
-        if name == "init_prec":
-            return launches * stored * ib + shp * stored * fw + sysp * 2 * w * n
-        return None
-    rows = []
-    for name in ("dir_spmv", "update_prec", "init_prec", "chain", "ir_residual", "ir_update", "reduce"):
-        la, ms = kt2.get(name, (0, 0.0))
-        sysp, shp = kw2.get(name, (0, 0))
-        if la:
-            b = kbytes(name, la, sysp, shp)
-            rows.append(dict(kernel=name, launches=la, total_ms=ms, avg_us=1e3 * ms / la,
-                             gbs=(b / (ms * 1e-3) / 1e9) if b else None, bytes=b))
-    dom = max((r for r in rows if r["bytes"]), key=lambda r: r["total_ms"])
+    rows = kernel_rows(kt2, kw2, stored=stored, n=n, ib=ib, w=4, fw=4, m=m,
+                       first_passes=first_passes, mixed=True, gp=gp, assign_sys=B)
+    dom = max((r for r in rows if r["bytes"] and r["kernel"] != "reduce"),
+              key=lambda r: r["total_ms"])
     traffic = measured_traffic(args.workload, tile, dom["kernel"])
-    roofline = {"bound": "hbm", "kernel": dom["kernel"], "achieved": round(dom["gbs"], 1),
+    roofline = {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["gbs"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "avg_launch_us": round(dom["avg_us"], 2),
+                "traffic": traffic, "avg_launch_us": dom["avg_us"],
                 "bytes_per_launch": int(dom["bytes"] / dom["launches"])}
     copy_gbs = measure_copy(stream, dev)
     roofline["copy_gbs"] = round(copy_gbs, 1)
     roofline["frac_of_copy"] = round(dom["gbs"] / copy_gbs, 4)
+    # the whole profiled solve: every kernel's algorithmic bytes over the
+    # same solve's wall time in the (graph-replayed) phase step
+    solve_bytes = sum(r["bytes"] or 0 for r in rows)
+    solve_level = {"bytes": int(solve_bytes), "ms": round(ph[4], 3),
+                   "gbs": round(solve_bytes / (ph[4] * 1e-3) / 1e9, 1),
+                   "frac_hbm": round(solve_bytes / (ph[4] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1,
@@ -659,9 +979,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]['desc']}", "n": n,
                    "systems_per_step": 2 * B, "tol_relres": args.tol, "err_tol": ERR_TOL,
-                   "precision": "float32 inner PCG, float64 refinement",
+                   "precision": "float32 matrix, SPAI and vectors in the inner PCG, float64 "
+                                "refinement",
                    "tile": {"rows_per_wave": tile[0], "systems_per_group": tile[1]}},
         "solved_to_1e-8": n_ok, "max_rel_err": max(errs_mixed) if errs_mixed else None,
+        "max_rel_err_vs_f64_oracle": max(errs["mixed"][1]) if "mixed" in errs else None,
         "iters_median": statistics.median(iters), "iters_max": max(iters),
         "phases_ms": {"pencil_setup": round(ph[0], 3), "spai_build_total": round(ph[1], 3),
                       "pcg_mixed_1": round(ph[2], 3), "spai_update_total": round(ph[3], 3),
@@ -671,15 +993,45 @@ def main():
         "update_skipped_frac": round(float(np.mean([u.info().skipped_cols for u in upd])) / n, 4),
         "batched_mixed_pcg_solves_per_s": round(2 * B / ((ph[2] + ph[4]) / 1e3), 2),
         "kernels": rows,
+        "solve_level": solve_level,
         "roofline": roofline,
     }
+
+    def accuracy(key, stats):
+        if key in errs:
+            e_dd, e_64 = errs[key]
+            return (sum(e <= ERR_TOL for e in e_dd), max(e_dd), max(e_64))
+        return (sum(s["status"] == airga.SYS_CONVERGED for s in stats), None, None)
+
+    if batched64 is not None:
+        ok, edd, e64 = accuracy("batched64", batched64["stats"])
+        r64 = batched64["rows"]
+        d64 = max((r for r in r64 if r["bytes"] and r["kernel"] != "reduce"),
+                  key=lambda r: r["total_ms"])
+        its = [e["iters"] for e in batched64["stats"]]
+        out["batched_fp64"] = {
+            "pcg_solves_per_s": round(ok / batched64["seconds"], 2),
+            "seconds_median_of_5": round(batched64["seconds"], 4), "solved_to_1e-8": ok,
+            "max_rel_err": edd, "max_rel_err_vs_f64_oracle": e64,
+            "iters_median": statistics.median(its), "iters_max": max(its),
+            "tile": {"rows_per_wave": batched64["tile"][0],
+                     "systems_per_group": batched64["tile"][1]},
+            "kernels": r64,
+            "roofline": {"bound": "hbm", "kernel": d64["kernel"], "achieved": d64["gbs"],
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(d64["gbs"] / HBM_PEAK_GBS, 4),
+                         "avg_launch_us": d64["avg_us"],
+                         "bytes_per_launch": int(d64["bytes"] / d64["launches"])}}
+        out["speedup_mixed_vs_batched_fp64"] = round(
+            out["batched_mixed_pcg_solves_per_s"] / max(out["batched_fp64"]["pcg_solves_per_s"],
+                                                        1e-30), 2)
     if plain is not None:
+        ok, edd, e64 = accuracy("plain", plain["stats"])
         pst = plain["stats"]
-        ok_p = sum(e <= ERR_TOL for e in errs_plain) if errs_plain else sum(
-            s["status"] == airga.SYS_CONVERGED for s in pst)
-        out["plain_fp64"] = {"pcg_solves_per_s": round(ok_p / plain["seconds"], 2),
-                             "seconds": round(plain["seconds"], 4), "solved_to_1e-8": ok_p,
-                             "max_rel_err": max(errs_plain) if errs_plain else None,
+        out["plain_fp64"] = {"pcg_solves_per_s": round(ok / plain["seconds"], 2),
+                             "seconds_median_of_5": round(plain["seconds"], 4),
+                             "solved_to_1e-8": ok, "max_rel_err": edd,
+                             "max_rel_err_vs_f64_oracle": e64,
                              "iters_median": statistics.median(s["iters"] for s in pst)}
         out["speedup_pcg_vs_plain_fp64"] = round(out["batched_mixed_pcg_solves_per_s"] /
                                                  max(out["plain_fp64"]["pcg_solves_per_s"], 1e-30), 2)
@@ -694,18 +1046,29 @@ def main():
         log("[bench] one AIRGA outer iteration")
         # the first run also tunes and captures the solves of the new batch
         # sizes (l m and m systems): reported apart, the second run is `ms`
-        first = measure_airga_iteration(ctx, stream, F, n, pen.alpha, pen.beta, solve_kw=solve_kw)
-        out["airga_iteration"] = measure_airga_iteration(ctx, stream, F, n, pen.alpha, pen.beta,
-                                                         solve_kw=solve_kw)
+        first = measure_airga_iteration(ctx, stream, F, n, solve_kw=solve_kw)
+        out["airga_iteration"] = measure_airga_iteration(ctx, stream, F, n, solve_kw=solve_kw)
         out["airga_iteration"]["first_ms"] = first.get("ms")
+    if not args.no_c2:
+        log("[bench] update-chain sequence (100,000 DOFs, float64, one system per solve)")
+        out["c2_update_chain"] = measure_c2_sequence(dev, stream)
+    if not args.no_complex:
+        log("[bench] complex expansion points (COCG)")
+        out["complex_shifts"] = measure_complex(ctx, stream, pen, f, F, shifts, args.tol)
     if cpu is not None:
         out["cpu_baseline"] = {
-            "value": round(2 * B / cpu["seconds"], 3), "unit": "solves/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"all {2 * B} systems of one step: double-double banded Cholesky reference "
-                      f"solves ({cpu['seconds']:.1f} s); oracle SPAI on {cpu['spai_cols']} sampled "
-                      f"columns took {cpu['spai_sample_s']:.2f} s "
-                      f"(~{cpu['spai_sample_s'] * n / cpu['spai_cols']:.0f} s per full build)"}
+            "value": round(cpu["dd_1"], 3), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"double-double banded Cholesky reference solves: {cpu['sample_systems']} "
+                      f"systems (the first {cpu['sample_systems'] // m} shifts) on one thread, "
+                      f"median of 3 ({cpu['t_dd1']:.2f} s); all {cpu['all_systems']} systems of "
+                      f"a step on {cpu['cores_all']} threads, median of 3 ({cpu['t_ddw']:.2f} s); "
+                      f"the same in binary64; oracle SPAI on {cpu['spai_cols']} sampled columns "
+                      f"took {cpu['spai_sample_s']:.2f} s "
+                      f"(~{cpu['spai_sample_s'] * n / cpu['spai_cols']:.0f} s per full build)",
+            "cpu_model": cpu["cpu_model"], "cores_visible": cpu["cores_visible"],
+            "cores_all": cpu["cores_all"], "value_all_cores": round(cpu["dd_all"], 3),
+            "fp64_value": round(cpu["f64_1"], 3), "fp64_value_all_cores": round(cpu["f64_all"], 3),
+            "f64_vs_dd_max_rel_diff": float(f"{cpu['f64_vs_dd_max']:.3e}")}
     print(json.dumps(out))
     for p in precs + upd:
         p.release()

@@ -165,7 +165,7 @@ AIRGA_API void airga_spai_opts_default(airga_spai_opts* opts);
  * column j, p_j = argmin || e_j - K(s) p ||_2 over vectors with the
  * pattern of column j, solved exactly per column (Givens QR in float64,
  * one column per GPU lane).  `opts` may be NULL (defaults).  The handle
- * owns the factor (a float64 copy, and a bfloat16 copy for the float32
+ * owns the factor (a float64 copy, and a float32 copy for the float32
  * inner solves of MIXED mode) and must be released with
  * airga_prec_release.  Asynchronous.  Pencils of bandwidth <= 64 use
  * kernels that stage each block's rows in LDS (see general_only).
@@ -215,6 +215,9 @@ typedef struct {
   int32_t chain_len;    /* factors applied per application (scalars excluded)   */
   int32_t scalar_only;  /* 1 when the newest factor collapsed to alpha I        */
   int64_t skipped_cols; /* columns of the newest factor kept at alpha e_j       */
+  double shift_im;      /* complex factors: imaginary part of the shift (else 0)*/
+  double alpha_im;      /* complex factors: imaginary part of alpha (else 0)    */
+  int32_t is_complex;   /* 1 for a factor of airga_spai_build_complex           */
 } airga_prec_info;
 
 /* Describe a preconditioner (synchronises the context stream). */
@@ -226,6 +229,13 @@ AIRGA_API airga_status airga_get_prec_info(airga_prec prec, airga_prec_info* out
  * A scalar-only factor exports alpha on the diagonal.  Asynchronous, except
  * that exporting values waits once for an update's skip count. */
 AIRGA_API airga_status airga_prec_export(airga_prec prec, double* values, double* objective);
+
+/* Which columns of the newest factor the update kept at alpha e_j
+ * (Section 3.2: the test that opens the update's column loop held), so that
+ * their least-squares problem was never solved: flags (device, n bytes) = 1
+ * for such a column, 0 for a solved one; a build returns all zeros.
+ * Asynchronous.  Errors: EINVAL (null flags or handle). */
+AIRGA_API airga_status airga_prec_skip_flags(airga_prec prec, uint8_t* flags);
 
 /* z = C r for `count` vectors (device, leading dimensions ldr, ldz),
  * C the whole chain Q_z ... Q_2 P_1 applied factor by factor (float64).
@@ -247,9 +257,9 @@ typedef struct {
   int32_t max_iter;    /* CG iterations per system, summed over sweeps
                           (default 20000)                                       */
   int32_t mode;        /* AIRGA_MODE_FP64 or AIRGA_MODE_MIXED (float32 matrix,
-                          arithmetic and vectors, preconditioner values stored
-                          as bfloat16, inside float64 iterative refinement of
-                          the residual and the solution)                        */
+                          arithmetic, vectors and preconditioner values,
+                          inside float64 iterative refinement of the residual
+                          and the solution)                                     */
   double inner_tol;    /* MIXED: relative residual reduction per sweep (1e-5:
                           two sweeps reach the default tol of 1e-10)          */
   int32_t max_sweeps;  /* MIXED: refinement sweeps (default 12)                 */
@@ -325,12 +335,80 @@ AIRGA_API airga_status airga_get_tile_config(airga_ctx ctx, int32_t* rows_per_wa
                                              int32_t* systems_per_group);
 
 /* Work done by the row kernels of the last profiled solve, for kernel id
- * k < count: sys_passes[k] = (system, launch) pairs swept, shift_passes[k] =
+ * k < count: sys_passes[k] = (system, launch) pairs swept (for chain:
+ * (system, chain factor) pairs; for ir_residual and ir_update: the systems
+ * under refinement when the kernel was launched), shift_passes[k] =
  * (shift, launch) pairs whose first preconditioner factor was read
  * (update_prec) or further chain factors applied (chain).  Together with
  * the pencil size these give the algorithmic bytes each kernel moved. */
 AIRGA_API airga_status airga_get_kernel_work(airga_ctx ctx, int32_t count, int64_t* sys_passes,
                                              int64_t* shift_passes);
+
+/* ---------------------------------------------------- complex shifts
+ *
+ * Complex expansion points s = s_re + i s_im.  The paper keeps its points
+ * real by taking the real parts of the reduced poles (Section 5); these
+ * calls take complex points as they are.  K(s) = (s^2 + alpha s) M +
+ * (1 + beta s) K is then complex symmetric (K(s)^T = K(s)), not Hermitian,
+ * so CG becomes conjugate orthogonal CG (COCG: the bilinear form x^T y in
+ * place of the inner product; van der Vorst and Melissen, 1990), which needs
+ * a complex symmetric preconditioner.  Complex arrays are interleaved
+ * (re, im) float64 pairs.  Pencils with rows of at most 6 entries. */
+
+/* a_val (device, 2 nnz: entry e's real part at 2e, imaginary at 2e + 1, CSR
+ * order) = K(s) for complex s.  Asynchronous.  Errors: EINVAL (null a_val,
+ * non-finite s), ESTATE. */
+AIRGA_API airga_status airga_assemble_shift_complex(airga_ctx ctx, double s_re, double s_im,
+                                                    double* a_val);
+
+/* SPAI of K(s) for complex s (eq. (3.1) with complex column least squares):
+ * for every column j, p_j = argmin || e_j - Khat p ||_2 over complex vectors
+ * on the pattern of column j, Khat = S K(s) S with S = diag(K(s))^{-1/2}
+ * (principal square root; equilibrate = 0: S = I), solved exactly per column
+ * (complex Givens QR in float64, one column per lane); symmetrize = 1
+ * replaces Phat by (Phat + Phat^T) / 2 (plain transpose), so that the factor
+ * S Phat S is complex symmetric like K(s), as COCG needs.  The handle is an
+ * airga_prec for airga_cocg_solve, airga_prec_export_complex,
+ * airga_get_prec_info and airga_prec_release; the real calls refuse it.
+ * opts may be NULL; tol and mr_iters are not used (mr_iters > 0:
+ * EUNSUPPORTED).  Asynchronous.  Errors: EINVAL (non-finite s, null out),
+ * ESTATE, EUNSUPPORTED (rows of more than 6 entries), ENOMEM, EHIP. */
+AIRGA_API airga_status airga_spai_build_complex(airga_ctx ctx, double s_re, double s_im,
+                                                const airga_spai_opts* opts, airga_prec* out);
+
+/* Export a complex factor: values (device, 2 nnz, interleaved, CSR order)
+ * and, if objective is not NULL, the per-column least-squares residual norm
+ * (device, n, real).  Asynchronous.  Errors: EINVAL (not a complex factor),
+ * ESTATE. */
+AIRGA_API airga_status airga_prec_export_complex(airga_prec prec, double* values,
+                                                 double* objective);
+
+/* Solve K(s_k) X[:, c, k] = F[:, c] for complex s_k (k < nshift) and every
+ * column c < m of the real F with preconditioned COCG, all nshift*m systems
+ * batched in one set of kernels with per-system convergence masking, in
+ * complex float64:
+ *   shifts: host, 2 nshift doubles (s_k = shifts[2k] + i shifts[2k+1])
+ *   precs:  host, nshift factors of airga_spai_build_complex at the same
+ *           shift (or NULL entries: no preconditioner)
+ *   F:      device, real n x m, leading dimension ldf >= n
+ *   X:      device, complex n x m x nshift interleaved, column (c, k) at
+ *           X + 2 (k m + c) ldx, ldx >= n (in complex entries)
+ *   stats:  host, nshift*m entries in (k, c) order, may be NULL
+ * Iteration from X = 0: w = K p, mu = p^T w, alpha = (r^T z) / mu, x += alpha
+ * p, r -= alpha w, stop when ||r|| <= tol ||F(:, c)|| (Euclidean norm of
+ * the recurrence residual), z = C r, beta = -(z^T w) / mu (flexible,
+ * default) or (r^T z)_new / (r^T z)_old (beta_form classical), p = z +
+ * beta p.  BREAKDOWN when mu = 0; relres in stats is the true residual
+ * ||F - K X|| / ||F|| at exit.  Options used: tol, max_iter, poll_every,
+ * beta_form; mode must be FP64 and x0_given 0 (else EUNSUPPORTED).  Returns
+ * after the stats are on the host.  Errors: EINVAL (sizes, null arrays,
+ * non-finite shifts, a real factor or one built at another shift), ESTATE,
+ * EUNSUPPORTED (more than 4096 systems, rows of more than 6 entries),
+ * ENOMEM, EHIP. */
+AIRGA_API airga_status airga_cocg_solve(airga_ctx ctx, int32_t nshift, const double* shifts,
+                                        const airga_prec* precs, int32_t m, const double* F,
+                                        int64_t ldf, double* X, int64_t ldx,
+                                        const airga_pcg_opts* opts, airga_sys_stats* stats);
 
 /* ------------------------------------------------ moment sequence blocks
  *
@@ -455,6 +533,102 @@ AIRGA_API airga_status airga_next_shifts(int32_t count, const double* re, const 
 AIRGA_API airga_status airga_h2_distance(const airga_reduced_model* a,
                                          const airga_reduced_model* b, double alpha, double beta,
                                          double* out);
+
+/* ------------------------------------------------- AIRGA's outer loop
+ *
+ * The whole model reduction of Algorithm 1 in one call, with SPAI
+ * preconditioned CG for every shifted solve (Algorithm 3) and, optionally,
+ * the cheap update carried across outer iterations (Algorithm 5).  Each
+ * outer iteration: SPAI at the l expansion points (built, or updated from
+ * the previous iteration's at the same position, see update_from), the
+ * solves X(s_i) = K(s_i)^{-1} F and their thin QR; the moment loop, which
+ * takes the point sigma_j with the largest moment error (the fraction of its
+ * newest moment block that the basis does not hold yet; sigma_1 = s_1),
+ * appends that block normalised in the Frobenius norm as V_j, replaces it
+ * by the next moment -K(sigma_j)^{-1} M V_j and orthogonalises every point's
+ * block against V_1..V_j in the trace inner product, and stops when the
+ * reduced model on the normalised blocks changes by less than tol_inner
+ * relative to its H2 norm, or when the basis reaches floor(r_max / m)
+ * blocks (the last block is then taken, again by the largest moment
+ * error); then the basis V = qr([V_1 .. V_J]), the reduced model of
+ * eq. (1.4) and its relative H2 change against the previous iteration's.
+ * The outer loop stops when that change is below tol_outer (Section 5 uses
+ * 1e-6 for both tests) or after max_outer iterations; otherwise the next
+ * points are the real parts of the reduced poles as airga_next_shifts
+ * chooses them (Section 5), and the i-th new point is paired with the i-th
+ * old one.  Every step runs in the library's kernels and host decisions
+ * (the entry points above); only small reduced matrices visit the host. */
+
+typedef struct {
+  int32_t r_max;        /* largest reduced order: the basis holds at most
+                           floor(r_max / m) blocks of m columns (<= 64
+                           columns).  Default 24.                           */
+  double tol_inner;     /* moment loop: relative H2 change (default 1e-6)    */
+  double tol_outer;     /* outer loop: relative H2 change (default 1e-6)     */
+  int32_t max_outer;    /* outer iterations at most (default 10)             */
+  int32_t update_from;  /* 0 (default): a new SPAI at every iteration's
+                           points; k >= 2: from outer iteration k on (1-based)
+                           each point's preconditioner is the SPAI update
+                           (Section 3.2) of the previous iteration's factor at
+                           the same position, so the chains grow (Alg. 5)    */
+  airga_spai_opts spai; /* builds and updates                               */
+  airga_pcg_opts pcg;   /* every solve (x0_given is ignored)                 */
+} airga_reduce_opts;
+
+AIRGA_API void airga_reduce_opts_default(airga_reduce_opts* opts);
+
+/* Results of airga_reduce.  The caller sets the pointer fields to host
+ * arrays (or NULL for outputs it does not want); they are written on
+ * success, column-major with leading dimension r (r_max^2, r_max m and
+ * p r_max entries suffice). */
+typedef struct {
+  int32_t iterations;   /* outer iterations run                              */
+  int32_t converged;    /* 1 if the last change fell below tol_outer         */
+  int32_t r;            /* order of the final model = J m columns of V       */
+  double change;        /* the last relative H2 change (NaN after one)       */
+  double* mhat;         /* r x r: V^T M V                                     */
+  double* khat;         /* r x r: V^T K V (D_hat = alpha mhat + beta khat)    */
+  double* fhat;         /* r x m: V^T F                                       */
+  double* cphat;        /* p x r: C_p V                                       */
+  double* cvhat;        /* p x r: C_v V (only when C_v is given)              */
+  double* next_shifts;  /* l: the points a further iteration would use (the
+                           last iteration's own points if it converged)      */
+} airga_reduce_result;
+
+/* Per outer iteration (optional history). */
+typedef struct {
+  int32_t blocks;        /* J of this iteration's final basis                */
+  int32_t moment_steps;  /* intermediate models formed                        */
+  int32_t updated;       /* 1: preconditioners updated, 0: built              */
+  int32_t chain_len_max; /* longest preconditioner chain applied             */
+  int32_t max_iters;     /* largest CG iteration count of its solves          */
+  int32_t all_converged; /* 1 if every solve of the iteration converged       */
+  double change;         /* relative H2 change of the final model (NaN first) */
+  double last_inner_change; /* the moment loop's last change (NaN if none)   */
+} airga_reduce_iter;
+
+/* Reduce the pencil set by airga_set_pencil (with its alpha, beta) for the
+ * input F (device, n x m, leading dimension ldf) and the outputs C_p, C_v
+ * (device, each stored as its transpose, n x p with leading dimension ldc;
+ * Cv may be NULL), from the l initial expansion points shifts0 (host, > 0).
+ *   V:          device, n x r_max (ldv >= n): the final orthonormal basis in
+ *               its first res->r columns, the rest used as work space
+ *   res:        host, see airga_reduce_result
+ *   shift_hist: host, max_outer x l (row z = the points of iteration z), or NULL
+ *   sigma_hist: host, max_outer x floor(r_max/m) (indices into that row of
+ *               shift_hist, -1 past J), or NULL
+ *   iter_hist:  host, max_outer entries, or NULL
+ * Synchronous.  A solve that does not converge is reported in iter_hist,
+ * not as an error.  Errors: EINVAL (sizes, null arrays, shifts, options),
+ * EUNSUPPORTED (more than 64 basis columns, l m > 64, m > 16, p > 256, or a
+ * new expansion point that is not positive), ENOTSPD (dependent blocks in a
+ * thin QR), ESTATE, ENOMEM, EHIP. */
+AIRGA_API airga_status airga_reduce(airga_ctx ctx, int32_t m, const double* F, int64_t ldf,
+                                    int32_t p, const double* Cp, const double* Cv, int64_t ldc,
+                                    int32_t l, const double* shifts0,
+                                    const airga_reduce_opts* opts, double* V, int64_t ldv,
+                                    airga_reduce_result* res, double* shift_hist,
+                                    int32_t* sigma_hist, airga_reduce_iter* iter_hist);
 
 #ifdef __cplusplus
 }

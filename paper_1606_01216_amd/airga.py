@@ -51,7 +51,8 @@ class SpaiOpts(ctypes.Structure):
 class PrecInfo(ctypes.Structure):
     _fields_ = [("shift", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("chain_len", ctypes.c_int32), ("scalar_only", ctypes.c_int32),
-                ("skipped_cols", ctypes.c_int64)]
+                ("skipped_cols", ctypes.c_int64), ("shift_im", ctypes.c_double),
+                ("alpha_im", ctypes.c_double), ("is_complex", ctypes.c_int32)]
 
 
 class PcgOpts(ctypes.Structure):
@@ -68,6 +69,27 @@ class SysStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("sweeps", ctypes.c_int32), ("finished_fp64", ctypes.c_int32),
                 ("relres", ctypes.c_double)]
+
+
+class ReduceOpts(ctypes.Structure):
+    _fields_ = [("r_max", ctypes.c_int32), ("tol_inner", ctypes.c_double),
+                ("tol_outer", ctypes.c_double), ("max_outer", ctypes.c_int32),
+                ("update_from", ctypes.c_int32), ("spai", SpaiOpts), ("pcg", PcgOpts)]
+
+
+class ReduceResult(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("r", ctypes.c_int32), ("change", ctypes.c_double),
+                ("mhat", ctypes.c_void_p), ("khat", ctypes.c_void_p), ("fhat", ctypes.c_void_p),
+                ("cphat", ctypes.c_void_p), ("cvhat", ctypes.c_void_p),
+                ("next_shifts", ctypes.c_void_p)]
+
+
+class ReduceIter(ctypes.Structure):
+    _fields_ = [("blocks", ctypes.c_int32), ("moment_steps", ctypes.c_int32),
+                ("updated", ctypes.c_int32), ("chain_len_max", ctypes.c_int32),
+                ("max_iters", ctypes.c_int32), ("all_converged", ctypes.c_int32),
+                ("change", ctypes.c_double), ("last_inner_change", ctypes.c_double)]
 
 
 class ReducedModel(ctypes.Structure):
@@ -104,6 +126,7 @@ _SIGS = [
                                              _P]),
     ("airga_get_prec_info", ctypes.c_int, [_P, ctypes.POINTER(PrecInfo)]),
     ("airga_prec_export", ctypes.c_int, [_P, _P, _P]),
+    ("airga_prec_skip_flags", ctypes.c_int, [_P, _P]),
     ("airga_prec_apply", ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64, _P,
                                         ctypes.c_int64]),
     ("airga_prec_release", None, [_P]),
@@ -122,6 +145,14 @@ _SIGS = [
     ("airga_get_kernel_work", ctypes.c_int, [_P, ctypes.c_int32,
                                              ctypes.POINTER(ctypes.c_int64),
                                              ctypes.POINTER(ctypes.c_int64)]),
+    ("airga_assemble_shift_complex", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, _P]),
+    ("airga_spai_build_complex", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double,
+                                                ctypes.POINTER(SpaiOpts), ctypes.POINTER(_P)]),
+    ("airga_prec_export_complex", ctypes.c_int, [_P, _P, _P]),
+    ("airga_cocg_solve", ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(_P), ctypes.c_int32, _P, ctypes.c_int64,
+                                        _P, ctypes.c_int64, ctypes.POINTER(PcgOpts),
+                                        ctypes.POINTER(SysStats)]),
     ("airga_pencil_apply", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                           _P, ctypes.c_int64, _P, ctypes.c_int64]),
     ("airga_gram", ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_int32, _P,
@@ -137,6 +168,11 @@ _SIGS = [
     ("airga_project", ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64,
                                      ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]),
+    ("airga_reduce_opts_default", None, [ctypes.POINTER(ReduceOpts)]),
+    ("airga_reduce", ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_int32, _P, _P,
+                                    ctypes.c_int64, ctypes.c_int32, _P,
+                                    ctypes.POINTER(ReduceOpts), _P, ctypes.c_int64,
+                                    ctypes.POINTER(ReduceResult), _P, _P, _P]),
     ("airga_qep_poles", ctypes.c_int, [ctypes.c_int32, _P, _P, ctypes.c_double, ctypes.c_double,
                                        _P, _P]),
     ("airga_next_shifts", ctypes.c_int, [ctypes.c_int32, _P, _P, ctypes.c_int32, _P]),
@@ -525,6 +561,123 @@ class Context:
                     finished_fp64=s.finished_fp64) for s in stats]
         return X, out
 
+    def reduce(self, F: torch.Tensor, cp: torch.Tensor, shifts0, *, cv: torch.Tensor | None = None,
+               r_max=24, tol_inner=1e-6, tol_outer=1e-6, max_outer=10, update_from=0,
+               symmetrize=True, spai_tol=None, mode=MODE_FP64, tol=1e-10, max_iter=20000,
+               poll_every=8):
+        """AIRGA's outer loop (airga_reduce).  F: (m, n), cp / cv: (p, n)
+        float64 device tensors.  Returns a dict: V (r, n) device tensor (the
+        basis, row c = column c), the reduced matrices (numpy), the history
+        (expansion points, sigmas and per-iteration records) and the final
+        change."""
+        import numpy as np
+        _dev(F, torch.float64, self.device)
+        _dev(cp, torch.float64, self.device)
+        if cv is not None:
+            _dev(cv, torch.float64, self.device)
+        m, p, l = F.shape[0], cp.shape[0], len(shifts0)
+        o = ReduceOpts()
+        lib().airga_reduce_opts_default(ctypes.byref(o))
+        o.r_max, o.tol_inner, o.tol_outer = int(r_max), float(tol_inner), float(tol_outer)
+        o.max_outer, o.update_from = int(max_outer), int(update_from)
+        o.spai.symmetrize = int(bool(symmetrize))
+        if spai_tol is not None:
+            o.spai.tol = float(spai_tol)
+        o.pcg.mode, o.pcg.tol, o.pcg.max_iter = int(mode), float(tol), int(max_iter)
+        o.pcg.poll_every = int(poll_every)
+        jmax = max(int(r_max) // m, 1)
+        V = torch.zeros((max(int(r_max), 1), self.n), dtype=torch.float64, device=self.device)
+        rm = max(int(r_max), 1)
+        outs = {k: np.zeros(sz) for k, sz in (("mhat", rm * rm), ("khat", rm * rm),
+                                               ("fhat", rm * m), ("cphat", p * rm),
+                                               ("cvhat", p * rm), ("next_shifts", l))}
+        res = ReduceResult()
+        for k, arr in outs.items():
+            setattr(res, k, ctypes.c_void_p(arr.ctypes.data))
+        if cv is None:
+            res.cvhat = None
+        sh_hist = np.zeros(int(max_outer) * l)
+        sg_hist = np.zeros(int(max_outer) * jmax, dtype=np.int32)
+        it_hist = (ReduceIter * int(max_outer))()
+        c_sh = (ctypes.c_double * l)(*[float(v) for v in shifts0])
+        self._enter()
+        _check(lib().airga_reduce(self._h, m, _ptr(F), self.n, p, _ptr(cp), _ptr(cv), self.n, l,
+                                  c_sh, ctypes.byref(o), _ptr(V), self.n, ctypes.byref(res),
+                                  ctypes.c_void_p(sh_hist.ctypes.data),
+                                  ctypes.c_void_p(sg_hist.ctypes.data), it_hist))
+        self._leave()
+        r, z = res.r, res.iterations
+        mat = lambda a, rows, cols: a[:rows * cols].reshape(cols, rows).T.copy()  # noqa: E731
+        hist = []
+        for i in range(z):
+            h = it_hist[i]
+            sig = [int(v) for v in sg_hist[i * jmax:(i + 1) * jmax] if v >= 0]
+            hist.append(dict(shifts=sh_hist[i * l:(i + 1) * l].copy(), sigmas=sig, J=h.blocks,
+                             moment_steps=h.moment_steps, updated=bool(h.updated),
+                             chain_len_max=h.chain_len_max, max_iters=h.max_iters,
+                             all_converged=bool(h.all_converged),
+                             change=None if np.isnan(h.change) else h.change,
+                             last_inner_change=None if np.isnan(h.last_inner_change)
+                             else h.last_inner_change))
+        return dict(V=V[:r], r=r, iterations=z, converged=bool(res.converged),
+                    change=None if np.isnan(res.change) else res.change,
+                    mhat=mat(outs["mhat"], r, r), khat=mat(outs["khat"], r, r),
+                    fhat=mat(outs["fhat"], r, m), cphat=mat(outs["cphat"], p, r),
+                    cvhat=mat(outs["cvhat"], p, r) if cv is not None else None,
+                    next_shifts=outs["next_shifts"].copy(), history=hist)
+
+    # ---------------------------------------------------- complex shifts
+    def assemble_shift_complex(self, s: complex) -> torch.Tensor:
+        """K(s) entries in CSR order as a complex128 device tensor."""
+        out = torch.empty(self.nnz, dtype=torch.complex128, device=self.device)
+        s = complex(s)
+        self._enter()
+        _check(lib().airga_assemble_shift_complex(self._h, s.real, s.imag, _ptr(out)))
+        self._leave()
+        return out
+
+    def spai_build_complex(self, s: complex, *, equilibrate=True, symmetrize=True) -> "Prec":
+        """SPAI of K(s) for a complex expansion point s."""
+        o = self._spai_opts(None, equilibrate, symmetrize)
+        h = ctypes.c_void_p()
+        s = complex(s)
+        self._enter()
+        _check(lib().airga_spai_build_complex(self._h, s.real, s.imag, ctypes.byref(o),
+                                              ctypes.byref(h)))
+        self._leave()
+        return Prec(self, h)
+
+    def cocg_solve(self, shifts, precs, F: torch.Tensor, X: torch.Tensor | None = None, *,
+                   tol=1e-10, max_iter=20000, poll_every=8, beta_form=0):
+        """Solve K(s_k) X[k, c] = F[c] for complex shifts s_k by COCG.
+        F: (m, n) float64 device tensor; X: (nshift, m, n) complex128
+        (allocated when None).  Returns (X, stats)."""
+        _dev(F, torch.float64, self.device)
+        m = F.shape[0]
+        shifts = [complex(s) for s in shifts]
+        nshift = len(shifts)
+        if X is None:
+            X = torch.empty((nshift, m, self.n), dtype=torch.complex128, device=self.device)
+        _dev(X, torch.complex128, self.device)
+        if tuple(X.shape) != (nshift, m, self.n) or tuple(F.shape) != (m, self.n):
+            raise ValueError("F must be (m, n) and X (nshift, m, n)")
+        if precs is None:
+            precs = [None] * nshift
+        if len(precs) != nshift:
+            raise ValueError("one preconditioner (or None) per shift")
+        c_shifts = (ctypes.c_double * (2 * nshift))(*[v for s in shifts for v in (s.real, s.imag)])
+        c_precs = (ctypes.c_void_p * nshift)(*[p._h.value if p is not None else None for p in precs])
+        o = PcgOpts()
+        lib().airga_pcg_opts_default(ctypes.byref(o))
+        o.tol, o.max_iter, o.poll_every, o.beta_form = float(tol), int(max_iter), int(poll_every), int(beta_form)
+        stats = (SysStats * (nshift * m))()
+        self._enter()
+        _check(lib().airga_cocg_solve(self._h, nshift, c_shifts, c_precs, m, _ptr(F), self.n,
+                                      _ptr(X), self.n, ctypes.byref(o), stats))
+        self._leave()
+        out = [dict(status=s.status, iters=s.iters, relres=s.relres) for s in stats]
+        return X, out
+
     def kernel_times(self) -> dict:
         """{kernel: (launches, total ms)} of the last profiled solve."""
         k = lib().airga_kernel_count()
@@ -561,6 +714,16 @@ class Prec:
         _check(lib().airga_get_prec_info(self._h, ctypes.byref(i)))
         return i
 
+    def export_complex(self):
+        """(values in CSR order (nnz,) complex128, per-column objective (n,))."""
+        c = self.ctx
+        vals = torch.empty(c.nnz, dtype=torch.complex128, device=c.device)
+        obj = torch.empty(c.n, dtype=torch.float64, device=c.device)
+        c._enter()
+        _check(lib().airga_prec_export_complex(self._h, _ptr(vals), _ptr(obj)))
+        c._leave()
+        return vals, obj
+
     def export(self):
         """(values in CSR order (nnz,), per-column objective (n,)), float64."""
         c = self.ctx
@@ -570,6 +733,16 @@ class Prec:
         _check(lib().airga_prec_export(self._h, _ptr(vals), _ptr(obj)))
         c._leave()
         return vals, obj
+
+    def skip_flags(self) -> torch.Tensor:
+        """(n,) uint8 device tensor: 1 where the update kept column j at
+        alpha e_j, 0 where it solved the column (all 0 for a build)."""
+        c = self.ctx
+        out = torch.empty(c.n, dtype=torch.uint8, device=c.device)
+        c._enter()
+        _check(lib().airga_prec_skip_flags(self._h, _ptr(out)))
+        c._leave()
+        return out
 
     def apply(self, r: torch.Tensor) -> torch.Tensor:
         c = self.ctx

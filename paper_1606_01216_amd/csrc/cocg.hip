@@ -1,0 +1,859 @@
+// Complex expansion points.  For complex s the shifted matrix
+//     K(s) = (s^2 + alpha s) M + (1 + beta s) K
+// is complex symmetric (K(s)^T = K(s)), not Hermitian: the paper keeps its
+// points real by taking the real parts of the reduced poles (Section 5);
+// this file takes the complex points as they are.  It provides the SPAI of
+// K(s) (eq. (3.1) with complex column least squares, equilibrated by the
+// principal square root of the diagonal and symmetrised with the plain
+// transpose, so the factor stays complex symmetric) and batched conjugate
+// orthogonal CG (CG with the bilinear form x^T y; van der Vorst and
+// Melissen 1990) for all (shift, column) systems at once, in float64.
+//
+// Data layout: complex values are interleaved (re, im) doubles.  Solve
+// vectors are kind-major like the real solves, vec(kind, b) = ws + (kind B +
+// b) n_pad complex entries; padding rows hold zeros.  One wavefront owns one
+// 64-row slice (one row per lane), keeps the slice's columns and M, K values
+// in registers and sweeps the active systems; partial sums are written per
+// (slot, system, wavefront) and summed in a fixed order by one block per
+// system.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace airga {
+namespace {
+
+struct cplx {
+  double re, im;
+};
+__host__ __device__ __forceinline__ cplx cx(double re, double im = 0.0) { return cplx{re, im}; }
+__host__ __device__ __forceinline__ cplx operator+(cplx a, cplx b) { return cplx{a.re + b.re, a.im + b.im}; }
+__host__ __device__ __forceinline__ cplx operator-(cplx a, cplx b) { return cplx{a.re - b.re, a.im - b.im}; }
+__host__ __device__ __forceinline__ cplx operator*(cplx a, cplx b) {
+  return cplx{fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
+}
+__host__ __device__ __forceinline__ cplx operator*(double s, cplx a) { return cplx{s * a.re, s * a.im}; }
+__host__ __device__ __forceinline__ cplx conj(cplx a) { return cplx{a.re, -a.im}; }
+__host__ __device__ __forceinline__ double abs2(cplx a) { return fma(a.re, a.re, a.im * a.im); }
+// a += x * y
+__host__ __device__ __forceinline__ void cfma(cplx& a, cplx x, cplx y) {
+  a.re = fma(x.re, y.re, fma(-x.im, y.im, a.re));
+  a.im = fma(x.re, y.im, fma(x.im, y.re, a.im));
+}
+// a += s * y for real s
+__host__ __device__ __forceinline__ void rfma(cplx& a, double s, cplx y) {
+  a.re = fma(s, y.re, a.re);
+  a.im = fma(s, y.im, a.im);
+}
+// a / b by Smith's scaling (the larger component of b divides first)
+__host__ __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
+  if (fabs(b.re) >= fabs(b.im)) {
+    const double t = b.im / b.re, d = fma(b.im, t, b.re);
+    return cplx{fma(a.im, t, a.re) / d, fma(-a.re, t, a.im) / d};
+  }
+  const double t = b.re / b.im, d = fma(b.re, t, b.im);
+  return cplx{fma(a.re, t, a.im) / d, fma(a.im, t, -a.re) / d};
+}
+// principal square root (branch cut on the negative real axis)
+__host__ __device__ __forceinline__ cplx csqrt(cplx z) {
+  const double r = hypot(z.re, z.im);
+  if (r == 0.0) return cplx{0.0, 0.0};
+  if (z.re >= 0.0) {
+    const double t = sqrt(0.5 * (r + z.re));
+    return cplx{t, z.im / (2.0 * t)};
+  }
+  const double t = sqrt(0.5 * (r - z.re));
+  return cplx{fabs(z.im) / (2.0 * t), copysign(t, z.im)};
+}
+
+// Scalar load of a wave-uniform complex value (two float64 scalar loads).
+__device__ __forceinline__ cplx sload_c(const cplx* p) {
+  const double* d = reinterpret_cast<const double*>(p);
+  return cplx{sload(d), sload(d + 1)};
+}
+
+// Shift coefficients a = s^2 + alpha s, b = 1 + beta s.
+inline void ccoeffs(const Pencil& pen, cplx s, cplx* a, cplx* b) {
+  *a = s * s + pen.alpha * s;
+  *b = cx(1.0) + pen.beta * s;
+}
+
+// ------------------------------------------------------------- assembly
+
+// out (CSR order, interleaved) = a M + b K
+__global__ void k_cassemble(PencilDev pd, int64_t stored, cplx a, cplx b, double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= stored) return;
+  const int32_t e = pd.csr_pos[i];
+  if (e < 0) return;
+  const double mv = pd.m64[i], kv = pd.k64[i];
+  out[2 * (int64_t)e] = fma(a.re, mv, b.re * kv);
+  out[2 * (int64_t)e + 1] = fma(a.im, mv, b.im * kv);
+}
+
+// ------------------------------------------------------------------ SPAI
+
+// dinv[r] = 1 / sqrt(K(s)_rr) (1 for padding rows), or 1 without
+// equilibration.
+__global__ void k_cdinv(PencilDev pd, cplx a, cplx b, int eq, cplx* __restrict__ dinv) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= (int64_t)pd.n_slices * kSlice) return;
+  cplx v = cx(1.0);
+  if (eq && r < pd.n) {
+    const int32_t i = pd.diag_pos[r];
+    const double mv = pd.m64[i], kv = pd.k64[i];
+    const cplx d = cplx{fma(a.re, mv, b.re * kv), fma(a.im, mv, b.im * kv)};
+    v = cdiv(cx(1.0), csqrt(d));
+  }
+  dinv[r] = v;
+}
+
+// Row r of the pencil: stored index of entry q is base + 64 q.
+__device__ __forceinline__ int32_t row_base(const PencilDev& pd, int64_t r) {
+  return pd.slice_ptr[r / kSlice] + (int32_t)(r % kSlice);
+}
+
+// Column j's least-squares problem min || e_j(I) - Khat(I, J) p || over
+// complex p, Khat = S K(s) S, J = the pattern of column j (= row j), I =
+// the rows of Khat(:, J).  One lane per column: the rows of the problem are
+// folded one at a time into a complex Givens QR held in registers.  Each
+// row r of I is met through every column J_t whose pattern holds it; it is
+// folded at the first such t only (row r holds no J_u with u < t), and its
+// entries Khat(r, J_u) are picked from row r's own storage (the pattern is
+// symmetric).  The solution is written at row j's own positions (column j's
+// coefficient for row J_t at entry t of row j).
+template <int MJ>
+__global__ void __launch_bounds__(64) k_cspai_cols(PencilDev pd, cplx a, cplx b,
+                                                   const cplx* __restrict__ dinv,
+                                                   cplx* __restrict__ hat,
+                                                   double* __restrict__ obj) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= pd.n) return;
+  const int32_t bj = row_base(pd, j);
+  const int nj = pd.row_len[j];
+  int32_t J[MJ];
+#pragma unroll
+  for (int t = 0; t < MJ; ++t) J[t] = t < nj ? pd.col[bj + t * kSlice] : -1;
+  cplx R[MJ * (MJ + 1) / 2];
+  cplx qtb[MJ];
+#pragma unroll
+  for (int q = 0; q < MJ * (MJ + 1) / 2; ++q) R[q] = cx(0.0);
+#pragma unroll
+  for (int q = 0; q < MJ; ++q) qtb[q] = cx(0.0);
+  double res2 = 0.0;
+  for (int t = 0; t < nj; ++t) {
+    const int64_t k = J[t];
+    const int32_t bk = row_base(pd, k);
+    const int nk = pd.row_len[k];
+    for (int e = 0; e < nk; ++e) {
+      const int64_t r = pd.col[bk + e * kSlice];
+      const int32_t br = row_base(pd, r);
+      const int nr = pd.row_len[r];
+      const cplx sr = dinv[r];
+      int32_t cr[MJ];
+      cplx vr[MJ];
+      bool dup = false;
+#pragma unroll
+      for (int q = 0; q < MJ; ++q) {
+        cr[q] = -2;
+        vr[q] = cx(0.0);
+        if (q < nr) {
+          const int32_t idx = br + q * kSlice;
+          cr[q] = pd.col[idx];
+          const double mv = pd.m64[idx], kv = pd.k64[idx];
+          const cplx v = cplx{fma(a.re, mv, b.re * kv), fma(a.im, mv, b.im * kv)};
+          vr[q] = (v * sr) * dinv[cr[q]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < MJ; ++u)
+#pragma unroll
+        for (int q = 0; q < MJ; ++q) dup |= (u < t) && (cr[q] == J[u]);
+      if (dup) continue;
+      // this row of the problem: Khat(r, J_u), right-hand side e_j(r)
+      cplx row[MJ];
+#pragma unroll
+      for (int u = 0; u < MJ; ++u) {
+        row[u] = cx(0.0);
+#pragma unroll
+        for (int q = 0; q < MJ; ++q)
+          if (cr[q] == J[u]) row[u] = vr[q];
+      }
+      cplx rhs = cx(r == j ? 1.0 : 0.0);
+      // fold it into R with one complex Givens rotation per column:
+      // [c s; -conj(s) c] with c real turns (R_kk, row_k) into (rho, 0)
+#pragma unroll
+      for (int kk = 0; kk < MJ; ++kk) {
+        if (kk >= nj) break;
+        const int dk = kk * MJ - kk * (kk - 1) / 2;  // R(kk, kk) in packed rows
+        const cplx x = R[dk], y = row[kk];
+        const double ay = abs2(y);
+        if (ay == 0.0) continue;
+        const double ax2 = abs2(x);
+        const double nrm = sqrt(ax2 + ay);
+        double c;
+        cplx s;
+        if (ax2 == 0.0) {
+          c = 0.0;
+          s = (1.0 / sqrt(ay)) * conj(y);
+          R[dk] = cx(sqrt(ay));
+        } else {
+          const double ax = sqrt(ax2);
+          const cplx ph = (1.0 / ax) * x;  // x / |x|
+          c = ax / nrm;
+          s = (1.0 / nrm) * (ph * conj(y));
+          R[dk] = nrm * ph;
+        }
+        row[kk] = cx(0.0);
+#pragma unroll
+        for (int q = 0; q < MJ; ++q) {
+          if (q <= kk || q >= nj) continue;
+          const cplx t1 = R[dk + (q - kk)], t2 = row[q];
+          R[dk + (q - kk)] = c * t1 + s * t2;
+          row[q] = c * t2 - conj(s) * t1;
+        }
+        const cplx t1 = qtb[kk];
+        qtb[kk] = c * t1 + s * rhs;
+        rhs = c * rhs - conj(s) * t1;
+      }
+      res2 += abs2(rhs);
+    }
+  }
+  // back substitution R p = qtb
+  cplx p[MJ];
+#pragma unroll
+  for (int q = MJ - 1; q >= 0; --q) {
+    p[q] = cx(0.0);
+    if (q >= nj) continue;
+    const int dq = q * MJ - q * (q - 1) / 2;
+    cplx acc = qtb[q];
+#pragma unroll
+    for (int u = 0; u < MJ; ++u)
+      if (u > q && u < nj) acc = acc - R[dq + (u - q)] * p[u];
+    p[q] = cdiv(acc, R[dq]);
+  }
+#pragma unroll
+  for (int t = 0; t < MJ; ++t)
+    if (t < nj) hat[bj + t * kSlice] = p[t];
+  obj[j] = sqrt(res2);
+}
+
+// P = S Phat S, with Phat replaced by (Phat + Phat^T) / 2 when sym; stored
+// order, padding 0.  hat holds column c's coefficient for row r at the
+// position of (c, r), so Phat(r, c) = hat[mirror of (r, c)].
+__global__ void k_cspai_finalize(PencilDev pd, const cplx* __restrict__ hat,
+                                 const cplx* __restrict__ dinv, int sym, cplx* __restrict__ v) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= (int64_t)pd.n_slices * kSlice) return;
+  const int32_t base = row_base(pd, r);
+  const int w = (pd.slice_ptr[r / kSlice + 1] - pd.slice_ptr[r / kSlice]) / kSlice;
+  const int len = pd.row_len[r];
+  const cplx sr = dinv[r];
+  for (int k = 0; k < w; ++k) {
+    const int32_t idx = base + k * kSlice;
+    cplx val = cx(0.0);
+    if (k < len) {
+      const int32_t c = pd.col[idx];
+      cplx h = hat[pd.mirror[idx]];
+      if (sym) h = 0.5 * (h + hat[idx]);
+      val = (h * sr) * dinv[c];
+    }
+    v[idx] = val;
+  }
+}
+
+// values (CSR order, interleaved) of a stored-order complex factor
+__global__ void k_cexport(PencilDev pd, int64_t stored, const cplx* __restrict__ v,
+                          cplx* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= stored) return;
+  const int32_t e = pd.csr_pos[i];
+  if (e >= 0) out[e] = v[i];
+}
+
+// ------------------------------------------------------------------ COCG
+
+enum CKind { CX = 0, CR0, CR1, CZ, CP0, CP1, CW, CKINDS };
+// partial slots: 0, 1 = p^T w;  2 = ||r||^2;  3, 4 = r^T z;  5, 6 = z^T w
+constexpr int kCSlots = 7;
+
+struct CSys {
+  cplx *rho, *mu, *alpha, *beta;
+  double *tol2, *ff, *relres;
+  int32_t *active, *istat, *iters, *nact;
+};
+
+struct CArgs {
+  PencilDev pd;
+  int32_t B, m;
+  int64_t ld;                // n_pad
+  cplx* ws;
+  const cplx* ca;            // per shift a_k
+  const cplx* cb;            // per shift b_k
+  const cplx* const* fac;    // per shift factor (stored order), nullptr = identity
+  double* partial;           // [kCSlots][B][GP]
+  int32_t GP;                // wavefronts = slices
+  CSys sys;
+  __device__ __forceinline__ cplx* vec(int kind, int b) const {
+    return ws + ((int64_t)kind * B + b) * ld;
+  }
+  __device__ __forceinline__ void put(int q, int b, int g, double v) const {
+    partial[((int64_t)q * B + b) * GP + g] = v;
+  }
+};
+
+// The slice of one wavefront: columns and M, K values of its 64 rows.
+template <int WMAX>
+struct CRows {
+  int32_t col[WMAX];
+  double mv[WMAX], kv[WMAX];
+  int32_t idx0;
+  int64_t row;
+  __device__ __forceinline__ void load(const PencilDev& pd, int s, int lane) {
+    row = (int64_t)s * kSlice + lane;
+    idx0 = pd.slice_ptr[s] + lane;
+    const int w = (pd.slice_ptr[s + 1] - pd.slice_ptr[s]) / kSlice;
+#pragma unroll
+    for (int k = 0; k < WMAX; ++k) {
+      const bool in = k < w;
+      col[k] = in ? pd.col[idx0 + k * kSlice] : (int32_t)row;
+      mv[k] = in ? pd.m64[idx0 + k * kSlice] : 0.0;
+      kv[k] = in ? pd.k64[idx0 + k * kSlice] : 0.0;
+    }
+  }
+  // the factor's values of this row (0 past the slice's width: the stored
+  // padding entries hold 0)
+  __device__ __forceinline__ void factor(const PencilDev& pd, int s, const cplx* f,
+                                         cplx (&fv)[WMAX]) const {
+    const int w = (pd.slice_ptr[s + 1] - pd.slice_ptr[s]) / kSlice;
+#pragma unroll
+    for (int k = 0; k < WMAX; ++k) fv[k] = k < w ? f[idx0 + k * kSlice] : cx(0.0);
+  }
+};
+
+__device__ __forceinline__ void put_total(const CArgs& A, int q, int b, int g, int lane, double v) {
+  v = wave_total(v);
+  if (lane == 0) A.put(q, b, g, v);
+}
+
+// z = C r0 with r0 = F(:, c) (real) for every system; x = 0, r = F, p = 0.
+// Partials ||r||^2 and r^T z.
+template <int WMAX>
+__global__ void __launch_bounds__(256) k_cinit(CArgs A, const double* __restrict__ F, int64_t ldf) {
+  const int lane = threadIdx.x & 63;
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= A.pd.n_slices) return;
+  CRows<WMAX> rows;
+  rows.load(A.pd, s, lane);
+  const int64_t n = A.pd.n, r = rows.row;
+  int loaded = -1;
+  cplx fv[WMAX];
+  for (int b = 0; b < A.B; ++b) {
+    if (sload(A.sys.active + b) == 0) continue;
+    const int sh = b / A.m, c = b % A.m;
+    const cplx* fac = sload(A.fac + sh);
+    if (fac && sh != loaded) {
+      rows.factor(A.pd, s, fac, fv);
+      loaded = sh;
+    }
+    const double* f = F + (int64_t)c * ldf;
+    const double fr = r < n ? f[r] : 0.0;
+    cplx z = cx(0.0);
+    if (fac) {
+#pragma unroll
+      for (int k = 0; k < WMAX; ++k) {
+        const int64_t cc = rows.col[k];
+        rfma(z, cc < n ? f[cc] : 0.0, fv[k]);
+      }
+    } else {
+      z = cx(fr);
+    }
+    A.vec(CX, b)[r] = cx(0.0);
+    A.vec(CR0, b)[r] = cx(fr);
+    A.vec(CP1, b)[r] = cx(0.0);
+    A.vec(CZ, b)[r] = z;
+    put_total(A, 2, b, s, lane, fr * fr);
+    put_total(A, 3, b, s, lane, fr * z.re);
+    put_total(A, 4, b, s, lane, fr * z.im);
+  }
+}
+
+// p_new = z + beta p_old;  w = K(s) p_new;  partial p_new^T w.  The
+// neighbours' p_new are formed from z and p_old at the column.
+template <int WMAX>
+__global__ void __launch_bounds__(256) k_cdir(CArgs A, int par) {
+  const int lane = threadIdx.x & 63;
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= A.pd.n_slices) return;
+  CRows<WMAX> rows;
+  rows.load(A.pd, s, lane);
+  const int64_t r = rows.row;
+  for (int b = 0; b < A.B; ++b) {
+    if (sload(A.sys.active + b) == 0) continue;
+    const int sh = b / A.m;
+    const cplx be = sload_c(A.sys.beta + b);
+    const cplx ka = sload_c(A.ca + sh), kb = sload_c(A.cb + sh);
+    const cplx* __restrict__ z = A.vec(CZ, b);
+    const cplx* __restrict__ po = A.vec(par ? CP0 : CP1, b);
+    cplx am = cx(0.0), ak = cx(0.0);
+#pragma unroll
+    for (int k = 0; k < WMAX; ++k) {
+      const int64_t c = rows.col[k];
+      cplx pc = z[c];
+      cfma(pc, be, po[c]);
+      rfma(am, rows.mv[k], pc);
+      rfma(ak, rows.kv[k], pc);
+    }
+    cplx pn = z[r];
+    cfma(pn, be, po[r]);
+    const cplx w = ka * am + kb * ak;
+    A.vec(par ? CP1 : CP0, b)[r] = pn;
+    A.vec(CW, b)[r] = w;
+    const cplx pw = pn * w;
+    put_total(A, 0, b, s, lane, pw.re);
+    put_total(A, 1, b, s, lane, pw.im);
+  }
+}
+
+// x += alpha p_new;  r_new = r_old - alpha w;  z = C r_new;  partials
+// ||r_new||^2, r_new^T z, z^T w.  The neighbours' r_new are formed from
+// r_old and w at the column.
+template <int WMAX>
+__global__ void __launch_bounds__(256) k_cupd(CArgs A, int par) {
+  const int lane = threadIdx.x & 63;
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= A.pd.n_slices) return;
+  CRows<WMAX> rows;
+  rows.load(A.pd, s, lane);
+  const int64_t r = rows.row;
+  int loaded = -1;
+  cplx fv[WMAX];
+  for (int b = 0; b < A.B; ++b) {
+    if (sload(A.sys.active + b) == 0) continue;
+    const int sh = b / A.m;
+    const cplx* fac = sload(A.fac + sh);
+    if (fac && sh != loaded) {
+      rows.factor(A.pd, s, fac, fv);
+      loaded = sh;
+    }
+    const cplx al = sload_c(A.sys.alpha + b);
+    const cplx nal = cx(-al.re, -al.im);
+    const cplx* __restrict__ ro = A.vec(par ? CR1 : CR0, b);
+    const cplx* __restrict__ w = A.vec(CW, b);
+    cplx rn = ro[r];
+    cfma(rn, nal, w[r]);
+    cplx z = cx(0.0);
+    if (fac) {
+#pragma unroll
+      for (int k = 0; k < WMAX; ++k) {
+        const int64_t c = rows.col[k];
+        cplx rc = ro[c];
+        cfma(rc, nal, w[c]);
+        cfma(z, fv[k], rc);
+      }
+    } else {
+      z = rn;
+    }
+    cplx* __restrict__ x = A.vec(CX, b);
+    cplx xv = x[r];
+    cfma(xv, al, A.vec(par ? CP1 : CP0, b)[r]);
+    x[r] = xv;
+    A.vec(par ? CR0 : CR1, b)[r] = rn;
+    A.vec(CZ, b)[r] = z;
+    const cplx rz = rn * z, zw = z * w[r];
+    put_total(A, 2, b, s, lane, abs2(rn));
+    put_total(A, 3, b, s, lane, rz.re);
+    put_total(A, 4, b, s, lane, rz.im);
+    put_total(A, 5, b, s, lane, zw.re);
+    put_total(A, 6, b, s, lane, zw.im);
+  }
+}
+
+// True residual F - K(s) x (slot 2 = its squared norm) and X out.
+template <int WMAX>
+__global__ void __launch_bounds__(256) k_cresid(CArgs A, const double* __restrict__ F, int64_t ldf,
+                                                double* __restrict__ X, int64_t ldx) {
+  const int lane = threadIdx.x & 63;
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= A.pd.n_slices) return;
+  CRows<WMAX> rows;
+  rows.load(A.pd, s, lane);
+  const int64_t n = A.pd.n, r = rows.row;
+  for (int b = 0; b < A.B; ++b) {
+    const int sh = b / A.m, c = b % A.m;
+    const cplx ka = sload_c(A.ca + sh), kb = sload_c(A.cb + sh);
+    const cplx* __restrict__ x = A.vec(CX, b);
+    cplx am = cx(0.0), ak = cx(0.0);
+#pragma unroll
+    for (int k = 0; k < WMAX; ++k) {
+      const cplx xc = x[rows.col[k]];
+      rfma(am, rows.mv[k], xc);
+      rfma(ak, rows.kv[k], xc);
+    }
+    const cplx kx = ka * am + kb * ak;
+    double res2 = 0.0;
+    if (r < n) {
+      const cplx rr = cx(F[(int64_t)c * ldf + r]) - kx;
+      res2 = abs2(rr);
+      const cplx xr = x[r];
+      double* xo = X + 2 * ((int64_t)b * ldx + r);
+      xo[0] = xr.re;
+      xo[1] = xr.im;
+    }
+    put_total(A, 2, b, s, lane, res2);
+  }
+}
+
+enum { CM_INIT = 0, CM_PW, CM_ITER, CM_FINAL };
+
+struct CRed {
+  CSys sys;
+  const double* partial;
+  int32_t B, GP, max_iter, flexible;
+  double tol2_rel;
+};
+
+// One block per system: fixed-order sums of the slots the mode needs, then
+// the recurrence's scalar logic.
+__global__ void __launch_bounds__(256) k_creduce(CRed P, int mode) {
+  __shared__ double red[4][kCSlots];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const CSys& S = P.sys;
+  if (mode != CM_FINAL && S.active[b] == 0) return;
+  double v[kCSlots];
+#pragma unroll
+  for (int q = 0; q < kCSlots; ++q) v[q] = 0.0;
+  const int64_t qs = (int64_t)P.B * P.GP;
+  const double* base = P.partial + (int64_t)b * P.GP;
+  for (int g = t; g < P.GP; g += 256)
+#pragma unroll
+    for (int q = 0; q < kCSlots; ++q) v[q] += base[q * qs + g];
+#pragma unroll
+  for (int q = 0; q < kCSlots; ++q) v[q] = wave_total(v[q]);
+  if ((t & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < kCSlots; ++q) red[t >> 6][q] = v[q];
+  __syncthreads();
+  if (t != 0) return;
+  double s[kCSlots];
+#pragma unroll
+  for (int q = 0; q < kCSlots; ++q) s[q] = red[0][q] + red[1][q] + red[2][q] + red[3][q];
+  const int was = S.active[b];
+  int act = was;
+  switch (mode) {
+    case CM_INIT: {
+      S.ff[b] = s[2];
+      S.tol2[b] = P.tol2_rel * s[2];
+      S.beta[b] = cx(0.0);
+      S.rho[b] = cx(s[3], s[4]);
+      S.relres[b] = 1.0;
+      if (!isfinite(s[2]) || !isfinite(s[3]) || !isfinite(s[4])) { S.istat[b] = AIRGA_SYS_NONFINITE; act = 0; }
+      else if (s[2] == 0.0) { S.istat[b] = AIRGA_SYS_CONVERGED; act = 0; }
+      break;
+    }
+    case CM_PW: {
+      const cplx mu = cx(s[0], s[1]);
+      if (!isfinite(mu.re) || !isfinite(mu.im)) { S.istat[b] = AIRGA_SYS_NONFINITE; act = 0; }
+      else if (mu.re == 0.0 && mu.im == 0.0) { S.istat[b] = AIRGA_SYS_BREAKDOWN; act = 0; }
+      else { S.mu[b] = mu; S.alpha[b] = cdiv(S.rho[b], mu); }
+      break;
+    }
+    case CM_ITER: {
+      const int it = S.iters[b] + 1;
+      S.iters[b] = it;
+      const cplx rz = cx(s[3], s[4]), zw = cx(s[5], s[6]);
+      bool fin = isfinite(s[2]) && isfinite(rz.re) && isfinite(rz.im) && isfinite(zw.re) &&
+                 isfinite(zw.im);
+      if (!fin) { S.istat[b] = AIRGA_SYS_NONFINITE; act = 0; }
+      else if (s[2] <= S.tol2[b]) { S.istat[b] = AIRGA_SYS_CONVERGED; act = 0; }
+      else if (it >= P.max_iter) { S.istat[b] = AIRGA_SYS_MAXIT; act = 0; }
+      else {
+        const cplx bf = cdiv(zw, S.mu[b]);
+        S.beta[b] = P.flexible ? cx(-bf.re, -bf.im) : cdiv(rz, S.rho[b]);
+        S.rho[b] = rz;
+      }
+      break;
+    }
+    case CM_FINAL: {
+      S.relres[b] = S.ff[b] > 0 ? sqrt(s[2] / S.ff[b]) : 0.0;
+      break;
+    }
+  }
+  if (act != was) {
+    S.active[b] = act;
+    atomicAdd(S.nact, act - was);
+  }
+}
+
+__global__ void k_cstate(CSys S, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b == 0) *S.nact = B;
+  if (b >= B) return;
+  S.active[b] = 1;
+  S.istat[b] = AIRGA_SYS_MAXIT;
+  S.iters[b] = 0;
+}
+
+__global__ void k_cfill(cplx* p, int64_t count) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < count) p[i] = cx(0.0);
+}
+
+struct CKernels {
+  void (*init)(CArgs, const double*, int64_t);
+  void (*dir)(CArgs, int);
+  void (*upd)(CArgs, int);
+  void (*resid)(CArgs, const double*, int64_t, double*, int64_t);
+};
+
+template <int W>
+CKernels ckernels() {
+  return CKernels{k_cinit<W>, k_cdir<W>, k_cupd<W>, k_cresid<W>};
+}
+
+airga_status check_cshift(const Pencil& pen, double re, double im) {
+  if (!std::isfinite(re) || !std::isfinite(im))
+    return fail(AIRGA_EINVAL, "complex shift must be finite");
+  if (pen.max_len > 6)
+    return fail(AIRGA_EUNSUPPORTED, "complex shifts take rows of at most 6 entries");
+  return AIRGA_OK;
+}
+
+}  // namespace
+}  // namespace airga
+
+using namespace airga;
+
+extern "C" {
+
+airga_status airga_assemble_shift_complex(airga_ctx ctx, double s_re, double s_im,
+                                          double* a_val) {
+  AIRGA_TRY(check_pencil(ctx));
+  DeviceGuard g(ctx->device);
+  if (!a_val) return fail(AIRGA_EINVAL, "null output");
+  if (!std::isfinite(s_re) || !std::isfinite(s_im))
+    return fail(AIRGA_EINVAL, "complex shift must be finite");
+  const Pencil& pen = ctx->pen;
+  cplx a, b;
+  ccoeffs(pen, cx(s_re, s_im), &a, &b);
+  k_cassemble<<<blocks_for(pen.nnz_stored, 256), 256, 0, ctx->stream>>>(pen.dev(), pen.nnz_stored, a,
+                                                                        b, a_val);
+  AIRGA_HIP(hipGetLastError());
+  return AIRGA_OK;
+}
+
+airga_status airga_spai_build_complex(airga_ctx ctx, double s_re, double s_im,
+                                      const airga_spai_opts* opts, airga_prec* out) {
+  AIRGA_TRY(check_pencil(ctx));
+  DeviceGuard g(ctx->device);
+  if (!out) return fail(AIRGA_EINVAL, "null output handle");
+  *out = nullptr;
+  const Pencil& pen = ctx->pen;
+  AIRGA_TRY(check_cshift(pen, s_re, s_im));
+  airga_spai_opts o;
+  airga_spai_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.mr_iters != 0)
+    return fail(AIRGA_EUNSUPPORTED, "the minimal-residual mode is for real shifts only");
+  airga_prec p = new (std::nothrow) airga_prec_s();
+  if (!p) return fail(AIRGA_ENOMEM, "host allocation failed");
+  p->ctx = ctx;
+  p->generation = pen.generation;
+  p->shift = s_re;
+  p->shift_im = s_im;
+  p->is_complex = true;
+  p->skipped = 0;
+  p->scalar_only = false;
+  p->scalar_known = true;
+  // the Frobenius minimiser of ||I - alpha K(s)||: conj(trace K(s)) / ||K(s)||_F^2
+  cplx a, b;
+  ccoeffs(pen, cx(s_re, s_im), &a, &b);
+  const cplx tr = a * cx(pen.tr_m) + b * cx(pen.tr_k);
+  const double fro2 = abs2(a) * pen.gram_mm + 2.0 * (a * conj(b)).re * pen.gram_mk +
+                      abs2(b) * pen.gram_kk;
+  p->alpha = fro2 > 0 ? tr.re / fro2 : 0.0;
+  p->alpha_im = fro2 > 0 ? -tr.im / fro2 : 0.0;
+  p->alpha_known = true;
+  const size_t stored = (size_t)pen.nnz_stored;
+  const size_t npad = (size_t)pen.n_pad();
+  airga_status st;
+  if ((st = pool_get(ctx, &p->v64, sizeof(cplx) * stored)) != AIRGA_OK ||
+      (st = pool_get(ctx, &p->objective, sizeof(double) * pen.n)) != AIRGA_OK ||
+      (st = ctx->ws_tmp.reserve(sizeof(cplx) * (stored + npad))) != AIRGA_OK) {
+    pool_put(ctx, &p->v64);
+    pool_put(ctx, &p->objective);
+    delete p;
+    return st;
+  }
+  ctx->live_precs++;
+  cplx* dinv = ctx->ws_tmp.as<cplx>();
+  cplx* hat = dinv + npad;
+  hipStream_t s = ctx->stream;
+  const PencilDev pd = pen.dev();
+  k_cdinv<<<blocks_for((int64_t)npad, 256), 256, 0, s>>>(pd, a, b, o.equilibrate ? 1 : 0, dinv);
+  k_cspai_cols<6><<<blocks_for(pen.n, 64), 64, 0, s>>>(pd, a, b, dinv, hat,
+                                                       p->objective.as<double>());
+  k_cspai_finalize<<<blocks_for((int64_t)npad, 256), 256, 0, s>>>(pd, hat, dinv,
+                                                                  o.symmetrize ? 1 : 0,
+                                                                  p->v64.as<cplx>());
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    airga_prec_release(p);
+    return fail(AIRGA_EHIP, "complex SPAI launch: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return AIRGA_OK;
+}
+
+airga_status airga_prec_export_complex(airga_prec prec, double* values, double* objective) {
+  if (!prec) return fail(AIRGA_EINVAL, "null preconditioner");
+  AIRGA_TRY(check_pencil(prec->ctx));
+  if (prec->generation != prec->ctx->pen.generation)
+    return fail(AIRGA_ESTATE, "preconditioner was built for an earlier pencil");
+  if (!prec->is_complex) return fail(AIRGA_EINVAL, "not a complex factor");
+  airga_ctx ctx = prec->ctx;
+  DeviceGuard g(ctx->device);
+  const Pencil& pen = ctx->pen;
+  if (values) {
+    k_cexport<<<blocks_for(pen.nnz_stored, 256), 256, 0, ctx->stream>>>(
+        pen.dev(), pen.nnz_stored, prec->v64.as<cplx>(), reinterpret_cast<cplx*>(values));
+    AIRGA_HIP(hipGetLastError());
+  }
+  if (objective)
+    AIRGA_HIP(hipMemcpyAsync(objective, prec->objective.ptr, sizeof(double) * pen.n,
+                             hipMemcpyDeviceToDevice, ctx->stream));
+  return AIRGA_OK;
+}
+
+airga_status airga_cocg_solve(airga_ctx ctx, int32_t nshift, const double* shifts,
+                              const airga_prec* precs, int32_t m, const double* F, int64_t ldf,
+                              double* X, int64_t ldx, const airga_pcg_opts* opts,
+                              airga_sys_stats* stats) {
+  AIRGA_TRY(check_pencil(ctx));
+  DeviceGuard g(ctx->device);
+  const Pencil& pen = ctx->pen;
+  if (nshift <= 0 || m <= 0) return fail(AIRGA_EINVAL, "nshift and m must be positive");
+  if (!shifts || !F || !X) return fail(AIRGA_EINVAL, "null argument");
+  if (ldf < pen.n || ldx < pen.n) return fail(AIRGA_EINVAL, "leading dimension < n");
+  airga_pcg_opts o;
+  airga_pcg_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.mode != AIRGA_MODE_FP64)
+    return fail(AIRGA_EUNSUPPORTED, "complex solves run in float64 only");
+  if (!(o.tol >= 0) || o.max_iter < 0) return fail(AIRGA_EINVAL, "bad tolerance or iteration cap");
+  if (o.x0_given) return fail(AIRGA_EUNSUPPORTED, "complex solves start from X = 0");
+  const int64_t B64 = (int64_t)nshift * m;
+  if (B64 > 4096) return fail(AIRGA_EUNSUPPORTED, "more than 4096 systems");
+  const int B = (int)B64;
+  std::vector<cplx> ca(nshift), cb(nshift);
+  std::vector<const cplx*> fac(nshift, nullptr);
+  for (int k = 0; k < nshift; ++k) {
+    AIRGA_TRY(check_cshift(pen, shifts[2 * k], shifts[2 * k + 1]));
+    ccoeffs(pen, cx(shifts[2 * k], shifts[2 * k + 1]), &ca[k], &cb[k]);
+    const airga_prec p = precs ? precs[k] : nullptr;
+    if (p) {
+      if (p->ctx != ctx) return fail(AIRGA_EINVAL, "preconditioner belongs to another context");
+      if (p->generation != pen.generation)
+        return fail(AIRGA_ESTATE, "preconditioner was built for an earlier pencil");
+      if (!p->is_complex) return fail(AIRGA_EINVAL, "shift %d: a real factor for a complex solve", k);
+      if (p->shift != shifts[2 * k] || p->shift_im != shifts[2 * k + 1])
+        return fail(AIRGA_EINVAL, "shift %d: the factor was built at another shift", k);
+      fac[k] = p->v64.as<cplx>();
+    }
+  }
+  hipStream_t st = ctx->stream;
+  const int64_t ld = pen.n_pad();
+  const int GP = pen.n_slices;
+  // workspace: vectors | partials | per-shift data | per-system state
+  const size_t vec_b = sizeof(cplx) * (size_t)CKINDS * B * ld;
+  const size_t part_b = sizeof(double) * (size_t)kCSlots * B * GP;
+  const size_t shift_b = (2 * sizeof(cplx) + sizeof(void*)) * (size_t)nshift;
+  const size_t sys_b = (4 * sizeof(cplx) + 3 * sizeof(double) + 3 * sizeof(int32_t)) * (size_t)B + 64;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  AIRGA_TRY(ctx->ws_vec.reserve(al(vec_b) + al(part_b) + al(shift_b) + al(sys_b)));
+  char* base = ctx->ws_vec.as<char>();
+  CArgs A{};
+  A.pd = pen.dev();
+  A.B = B;
+  A.m = m;
+  A.ld = ld;
+  A.ws = reinterpret_cast<cplx*>(base);
+  A.partial = reinterpret_cast<double*>(base + al(vec_b));
+  A.GP = GP;
+  char* shb = base + al(vec_b) + al(part_b);
+  A.ca = reinterpret_cast<const cplx*>(shb);
+  A.cb = A.ca + nshift;
+  A.fac = reinterpret_cast<const cplx* const*>(shb + 2 * sizeof(cplx) * nshift);
+  char* sb = shb + al(shift_b);
+  CSys S;
+  cplx* cs = reinterpret_cast<cplx*>(sb);
+  S.rho = cs; S.mu = cs + B; S.alpha = cs + 2 * B; S.beta = cs + 3 * B;
+  double* ds = reinterpret_cast<double*>(cs + 4 * B);
+  S.tol2 = ds; S.ff = ds + B; S.relres = ds + 2 * B;
+  int32_t* is = reinterpret_cast<int32_t*>(ds + 3 * B);
+  S.active = is; S.istat = is + B; S.iters = is + 2 * B; S.nact = is + 3 * B;
+  A.sys = S;
+  // per-shift data through pinned memory
+  AIRGA_TRY(ensure_pinned(ctx, shift_b + 64));
+  char* hp = static_cast<char*>(ctx->host_pinned);
+  std::memcpy(hp, ca.data(), sizeof(cplx) * nshift);
+  std::memcpy(hp + sizeof(cplx) * nshift, cb.data(), sizeof(cplx) * nshift);
+  std::memcpy(hp + 2 * sizeof(cplx) * nshift, fac.data(), sizeof(void*) * nshift);
+  AIRGA_HIP(hipMemcpyAsync(shb, hp, shift_b, hipMemcpyHostToDevice, st));
+  AIRGA_HIP(hipStreamSynchronize(st));
+  // zero vectors (padding rows stay zero), fresh state
+  k_cfill<<<blocks_for((int64_t)CKINDS * B * ld, 256), 256, 0, st>>>(A.ws, (int64_t)CKINDS * B * ld);
+  k_cstate<<<blocks_for(B, 256), 256, 0, st>>>(S, B);
+  AIRGA_HIP(hipGetLastError());
+  const CKernels ks = ckernels<6>();
+  const unsigned grid = blocks_for(pen.n_slices, 4);
+  CRed R{S, A.partial, B, GP, o.max_iter, o.beta_form == AIRGA_BETA_CLASSICAL ? 0 : 1,
+         o.tol * o.tol};
+  ks.init<<<grid, 256, 0, st>>>(A, F, ldf);
+  k_creduce<<<(unsigned)B, 256, 0, st>>>(R, CM_INIT);
+  AIRGA_HIP(hipGetLastError());
+  AIRGA_TRY(ensure_pinned(ctx, 64));
+  int32_t* h_nact = static_cast<int32_t*>(ctx->host_pinned);
+  int k = o.poll_every < 2 ? 2 : o.poll_every;
+  k += k & 1;
+  const int64_t rounds = (int64_t)o.max_iter / k + 2;
+  for (int64_t round = 0; round < rounds; ++round) {
+    AIRGA_HIP(hipMemcpyAsync(h_nact, S.nact, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    AIRGA_HIP(hipStreamSynchronize(st));
+    if (*h_nact == 0) break;
+    for (int j = 0; j < k; ++j) {
+      const int par = j & 1;
+      ks.dir<<<grid, 256, 0, st>>>(A, par);
+      k_creduce<<<(unsigned)B, 256, 0, st>>>(R, CM_PW);
+      ks.upd<<<grid, 256, 0, st>>>(A, par);
+      k_creduce<<<(unsigned)B, 256, 0, st>>>(R, CM_ITER);
+    }
+    AIRGA_HIP(hipGetLastError());
+  }
+  ks.resid<<<grid, 256, 0, st>>>(A, F, ldf, X, ldx);
+  k_creduce<<<(unsigned)B, 256, 0, st>>>(R, CM_FINAL);
+  AIRGA_HIP(hipGetLastError());
+  // per-system results
+  const size_t rb = sizeof(double) * B, ib = sizeof(int32_t) * B;
+  AIRGA_TRY(ensure_pinned(ctx, rb + 2 * ib));
+  char* h = static_cast<char*>(ctx->host_pinned);
+  AIRGA_HIP(hipMemcpyAsync(h, S.relres, rb, hipMemcpyDeviceToHost, st));
+  AIRGA_HIP(hipMemcpyAsync(h + rb, S.istat, 2 * ib, hipMemcpyDeviceToHost, st));
+  AIRGA_HIP(hipStreamSynchronize(st));
+  if (stats) {
+    const double* rel = reinterpret_cast<const double*>(h);
+    const int32_t* ist = reinterpret_cast<const int32_t*>(h + rb);
+    for (int b = 0; b < B; ++b) {
+      stats[b].status = ist[b];
+      stats[b].iters = ist[B + b];
+      stats[b].sweeps = 1;
+      stats[b].finished_fp64 = 0;
+      stats[b].relres = rel[b];
+    }
+  }
+  return AIRGA_OK;
+}
+
+}  // extern "C"

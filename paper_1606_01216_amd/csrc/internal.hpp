@@ -106,7 +106,7 @@ struct Pencil {
   DevBuf coff;        // int8 column offsets (banded pencils)
   DevBuf setup;       // scratch of set_pencil (pattern summary, per-slice data)
   DevBuf gram_ws;     // scratch of set_pencil (Gram partial sums)
-  DevBuf id64, id16;  // the identity on the pattern (solves without a preconditioner)
+  DevBuf id64, id32;  // the identity on the pattern (solves without a preconditioner)
   PencilDev dev() const;
   int64_t n_pad() const { return (int64_t)n_slices * kSlice; }
 };
@@ -189,16 +189,19 @@ struct airga_prec_s {
   uint64_t generation = 0;
   std::atomic<int> refs{1};
   double shift = 0;
+  double shift_im = 0;       // imaginary part of a complex expansion point
   double alpha = 0;          // host copy once known (read lazily)
+  double alpha_im = 0;       // complex factors: imaginary part of alpha
+  bool is_complex = false;   // complex factor: v64 holds interleaved (re, im) values
   bool alpha_known = false;
   bool is_update = false;
   int64_t skipped = -1;      // host copy once known
   bool scalar_only = false;  // decided on the host after the skip count is read
   bool scalar_known = false;
   airga_prec parent = nullptr;
-  // v16: the values as bfloat16 bits, the copy the float32 inner solves read;
+  // v32: the values rounded to float32, the copy the float32 inner solves read;
   // scal: alpha, the skip count and the skipped-column flags, on device
-  airga::DevBuf v64, v16, objective, scal;
+  airga::DevBuf v64, v32, objective, scal;
 };
 
 namespace airga {
@@ -280,14 +283,6 @@ __device__ __forceinline__ T wave_total(T v) {
 
 // Make a wavefront-uniform value scalar (it then lives in an SGPR).
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// bfloat16 bits of v: rounded to float32, then to the nearest bfloat16 (ties
-// to even); NaN stays NaN.
-__device__ __forceinline__ uint16_t to_bf16(double v) {
-  const uint32_t u = __float_as_uint((float)v);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
 
 // Load of a wave-uniform address through the constant address space, so it
 // becomes a scalar load: it is counted apart from the vector loads in flight

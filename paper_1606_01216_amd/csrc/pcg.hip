@@ -333,13 +333,15 @@ static airga_status count_work(Plan<T>& P, Timer& tm, bool in_iteration) {
   std::vector<int32_t> act(B);
   AIRGA_HIP(hipMemcpyAsync(act.data(), P.a.sys.active, 4 * B, hipMemcpyDeviceToHost, P.ctx->stream));
   AIRGA_HIP(hipStreamSynchronize(P.ctx->stream));
-  int64_t sys = 0, shifts = 0, chain_shifts = 0;
+  int64_t sys = 0, shifts = 0, chain_shifts = 0, chain_sys = 0;
   for (int k = 0; k < P.a.nshift; ++k) {
-    int any = 0;
+    int any = 0, nk = 0;
     for (int c = 0; c < m; ++c) any |= act[k * m + c];
-    for (int c = 0; c < m; ++c) sys += act[k * m + c] != 0;
+    for (int c = 0; c < m; ++c) nk += act[k * m + c] != 0;
+    sys += nk;
     if (any && P.clen[k] > 0) shifts += 1;
     if (any) chain_shifts += P.clen[k] > 1 ? P.clen[k] - 1 : 0;
+    chain_sys += P.clen[k] > 1 ? (int64_t)nk * (P.clen[k] - 1) : 0;
   }
   KernelTimes& t = P.ctx->times;
   const int id = in_iteration ? K_UPDATE_PREC : K_INIT_PREC;
@@ -347,6 +349,26 @@ static airga_status count_work(Plan<T>& P, Timer& tm, bool in_iteration) {
   t.sys_passes[id] += sys;
   t.shift_passes[id] += shifts;
   t.shift_passes[K_CHAIN] += chain_shifts;
+  t.sys_passes[K_CHAIN] += chain_sys;
+  return AIRGA_OK;
+}
+
+// Profiled solves only: count the systems the float64 residual or the
+// solution update sweeps next (those whose refinement flag is set), or all B
+// (all_sys).
+template <typename T>
+static airga_status count_outer(Plan<T>& P, Timer& tm, int id, bool all_sys = false) {
+  if (!tm.on) return AIRGA_OK;
+  const int B = P.a.B;
+  int64_t c = B;
+  if (!all_sys) {
+    std::vector<int32_t> f(B);
+    AIRGA_HIP(hipMemcpyAsync(f.data(), P.a.sys.outer, 4 * B, hipMemcpyDeviceToHost, P.ctx->stream));
+    AIRGA_HIP(hipStreamSynchronize(P.ctx->stream));
+    c = 0;
+    for (int b = 0; b < B; ++b) c += f[b] != 0;
+  }
+  P.ctx->times.sys_passes[id] += c;
   return AIRGA_OK;
 }
 
@@ -497,12 +519,12 @@ static airga_status prepare(airga_ctx ctx, Plan<T>& P, int32_t nshift, const dou
       std::vector<airga_prec> ch;
       AIRGA_TRY(prec_chain(precs[k], &ch));
       for (auto it = ch.rbegin(); it != ch.rend(); ++it) {
-        if constexpr (sizeof(T) == 4) chains[k].push_back((*it)->v16.as<uint16_t>());
+        if constexpr (sizeof(T) == 4) chains[k].push_back((*it)->v32.as<float>());
         else chains[k].push_back((*it)->v64.as<double>());
       }
     }
     if (chains[k].empty()) {
-      if constexpr (sizeof(T) == 4) chains[k].push_back(pen.id16.as<uint16_t>());
+      if constexpr (sizeof(T) == 4) chains[k].push_back(pen.id32.as<float>());
       else chains[k].push_back(pen.id64.as<double>());
     }
     maxc = (int)chains[k].size() > maxc ? (int)chains[k].size() : maxc;
@@ -773,14 +795,17 @@ static airga_status solve_fp64(airga_ctx ctx, int32_t nshift, const double* shif
   P.red.tol2_rel = o.tol * o.tol;
   Timer tm{ctx, o.profile != 0, {}, {}};
   const int x0 = o.x0_given ? 1 : 0;
+  AIRGA_TRY(count_outer(P, tm, K_IR_RESIDUAL));
   TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds_res, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, x0,
                                                          1 - x0, x0 ? 2 : 1));
   TIMED(K_REDUCE, reduce(P, RM_START));
   AIRGA_TRY(start_inner(P, tm, 0));
   AIRGA_TRY(iterate(P, tm, o, 0, 0, nullptr));
   // result out, then its true residual
+  AIRGA_TRY(count_outer(P, tm, K_IR_UPDATE, true));
   TIMED(K_IR_UPDATE, (k_copy_out<<<dim3(blocks_for(pen.n, 256), (unsigned)B), 256, 0, st>>>(
                          P.a.ws + (int64_t)KX * B * P.a.ld, P.a.ld, pen.n, X, ldx)));
+  AIRGA_TRY(count_outer(P, tm, K_IR_RESIDUAL));
   TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds_res, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, 1, 0, 0));
   TIMED(K_REDUCE, reduce(P, RM_FINAL));
   AIRGA_TRY(tm.flush());
@@ -865,6 +890,7 @@ static airga_status solve_mixed(airga_ctx ctx, int32_t nshift, const double* shi
   // first assigned by the sweep-0 correction instead of zeroed beforehand.
   P.a.xz = 1;
   // sweep 0 residual; RM_OUTER then activates the systems to refine
+  AIRGA_TRY(count_outer(P, tm, K_IR_RESIDUAL));
   TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds_res, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, x0,
                                                          0, 0));
   k_clear_active<<<blocks_for(B, 256), 256, 0, st>>>(P.a.sys, B);
@@ -881,6 +907,7 @@ static airga_status solve_mixed(airga_ctx ctx, int32_t nshift, const double* shi
     AIRGA_TRY(start_inner(P, tm, 1));
     bool capped = false;
     AIRGA_TRY(iterate(P, tm, o, cap, *h_nact, &capped));
+    AIRGA_TRY(count_outer(P, tm, K_IR_UPDATE));
     TIMED(K_IR_UPDATE, (k_ir_update<<<ir_grid, 256, 0, st>>>(P.a, X, ldx, assign ? 1 : 0)));
     assign = false;
     if (capped) {
@@ -888,6 +915,7 @@ static airga_status solve_mixed(airga_ctx ctx, int32_t nshift, const double* shi
       AIRGA_HIP(hipGetLastError());
       any_handed = true;
     }
+    AIRGA_TRY(count_outer(P, tm, K_IR_RESIDUAL));
     TIMED(K_IR_RESIDUAL, P.ks.resid<<<P.grid, 256, P.lds_res, st>>>(P.a, F, ldf, X, ldx, ca64, cb64, 1, 0, 0));
     TIMED(K_REDUCE, reduce(P, RM_OUTER));
   }
@@ -941,6 +969,8 @@ airga_status airga_pcg_solve(airga_ctx ctx, int32_t nshift, const double* shifts
       return fail(AIRGA_EINVAL, "shift %d must be finite and > 0", k);
     if (precs && precs[k]) {
       if (precs[k]->ctx != ctx) return fail(AIRGA_EINVAL, "preconditioner %d from another context", k);
+      if (precs[k]->is_complex)
+        return fail(AIRGA_EINVAL, "preconditioner %d is complex: use airga_cocg_solve", k);
       if (precs[k]->generation != pen.generation)
         return fail(AIRGA_ESTATE, "preconditioner %d was built for an earlier pencil", k);
     }

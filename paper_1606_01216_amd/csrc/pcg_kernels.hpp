@@ -45,15 +45,9 @@ struct SysDev {
   int32_t* handed;  // mixed mode: 1 = left the float32 sweeps for the float64 finish
 };
 
-// Storage of preconditioner values: bfloat16 bits for the float32 inner
-// solves (the factor is an approximate inverse; its rounding to 8 mantissa
-// bits leaves the operator and the vectors in float32), float64 otherwise.
-template <typename T> struct FacStore;
-template <> struct FacStore<float> { using type = uint16_t; };
-template <> struct FacStore<double> { using type = double; };
-template <typename T> using fac_t = typename FacStore<T>::type;
-__device__ __forceinline__ float fac_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-__device__ __forceinline__ double fac_value(double v) { return v; }
+// Storage of preconditioner values: the precision of the solve (float32
+// for the inner solves of mixed precision, float64 otherwise).
+template <typename T> using fac_t = T;
 
 template <typename T>
 struct SolveArgs {
@@ -169,7 +163,7 @@ struct Rows {
     for (int i = 0; i < R; ++i)
 #pragma unroll
       for (int k = 0; k < WMAX; ++k)
-        out[i][k] = (valid[i] && (EXACT || k < w[i])) ? (T)fac_value(v[idx0[i] + k * kSlice]) : T(0);
+        out[i][k] = (valid[i] && (EXACT || k < w[i])) ? v[idx0[i] + k * kSlice] : T(0);
   }
 };
 

@@ -362,7 +362,7 @@ __global__ void k_sum_gram(const double* __restrict__ part, int64_t nb, double* 
 
 // The identity on the stored pattern: 1 at each diagonal entry, 0 elsewhere.
 __global__ void k_identity(PencilDev pd, int64_t n_pad, double* __restrict__ v64,
-                           uint16_t* __restrict__ v16) {
+                           float* __restrict__ v32) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= n_pad) return;
   const int64_t s = r / kSlice;
@@ -373,7 +373,7 @@ __global__ void k_identity(PencilDev pd, int64_t n_pad, double* __restrict__ v64
     const int32_t idx = base + k * kSlice;
     const double v = (k < len && pd.col[idx] == r) ? 1.0 : 0.0;
     v64[idx] = v;
-    v16[idx] = to_bf16(v);
+    v32[idx] = (float)v;
   }
 }
 
@@ -488,9 +488,9 @@ static airga_status set_pencil_impl(airga_ctx ctx, int32_t n, int64_t nnz, const
   pen.alpha = alpha;
   pen.beta = beta;
   AIRGA_TRY(pen.id64.reserve(sizeof(double) * stored));
-  AIRGA_TRY(pen.id16.reserve(sizeof(uint16_t) * stored));
+  AIRGA_TRY(pen.id32.reserve(sizeof(float) * stored));
   k_identity<<<blocks_for(n_pad, 256), 256, 0, st>>>(pen.dev(), n_pad, pen.id64.as<double>(),
-                                                     pen.id16.as<uint16_t>());
+                                                     pen.id32.as<float>());
   AIRGA_HIP(hipGetLastError());
   // Gram scalars
   const unsigned nb = blocks_for(n, 256);

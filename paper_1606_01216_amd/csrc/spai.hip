@@ -1101,6 +1101,13 @@ __global__ void __launch_bounds__(256) k_spai_update_many(PencilDev pd, UpdMany 
   }
 }
 
+// flags[j] = 1 where the update kept column j at alpha e_j (src NULL: a
+// build, no column skipped).
+__global__ void k_copy_flags(const int8_t* __restrict__ src, int32_t n, uint8_t* __restrict__ flags) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j < n) flags[j] = (src && src[j]) ? 1 : 0;
+}
+
 // Map the scaled factor back and store float64 and float32 copies:
 //   build:        P = S Phat S          (mode 0)
 //   build, sym:   P = S (Phat + Phat^T)/2 S   (mode 1)
@@ -1112,7 +1119,7 @@ __global__ void k_spai_finalize(PencilDev pd, const double* __restrict__ hat,
                                 const double* __restrict__ dinv, int mode,
                                 const int32_t* __restrict__ skip_total,
                                 const int8_t* __restrict__ skipf, const double* __restrict__ alpha,
-                                double* __restrict__ v64, uint16_t* __restrict__ v16) {
+                                double* __restrict__ v64, float* __restrict__ v32) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= (int64_t)pd.n_slices * kSlice) return;
   if (skip_total && *skip_total == pd.n) return;
@@ -1133,7 +1140,7 @@ __global__ void k_spai_finalize(PencilDev pd, const double* __restrict__ hat,
       val = mode == 2 ? h * sr / dinv[c] : h * sr * dinv[c];
     }
     v64[idx] = val;
-    v16[idx] = to_bf16(val);
+    v32[idx] = (float)val;
   }
 }
 
@@ -1218,11 +1225,11 @@ static airga_status new_prec(airga_ctx ctx, double s, airga_prec* out) {
   const Pencil& pen = ctx->pen;
   airga_status st;
   if ((st = pool_get(ctx, &p->v64, sizeof(double) * pen.nnz_stored)) != AIRGA_OK ||
-      (st = pool_get(ctx, &p->v16, sizeof(uint16_t) * pen.nnz_stored)) != AIRGA_OK ||
+      (st = pool_get(ctx, &p->v32, sizeof(float) * pen.nnz_stored)) != AIRGA_OK ||
       (st = pool_get(ctx, &p->objective, sizeof(double) * pen.n)) != AIRGA_OK ||
       (st = pool_get(ctx, &p->scal, 64 + (size_t)pen.n_pad())) != AIRGA_OK) {
     pool_put(ctx, &p->v64);
-    pool_put(ctx, &p->v16);
+    pool_put(ctx, &p->v32);
     pool_put(ctx, &p->objective);
     pool_put(ctx, &p->scal);
     delete p;
@@ -1383,7 +1390,7 @@ static airga_status run_build(airga_ctx ctx, double s, const airga_spai_opts& o,
   }
   AIRGA_HIP(hipGetLastError());
   k_spai_finalize<<<nr, 256, 0, st>>>(pd, w.hat, w.dinv, o.symmetrize ? 1 : 0, nullptr, nullptr,
-                                      nullptr, p->v64.as<double>(), p->v16.as<uint16_t>());
+                                      nullptr, p->v64.as<double>(), p->v32.as<float>());
   AIRGA_HIP(hipGetLastError());
   // Alg. 2's starting scaling trace(K) / trace(K K^T), from the Gram scalars
   // (minimal-residual mode: that of Khat, read from the device when needed).
@@ -1436,7 +1443,7 @@ static airga_status run_update(airga_ctx ctx, airga_prec old, double s_new,
   k_sum_counts<<<1, 256, 0, st>>>(w.skip_part, nb, d_skip);
   AIRGA_HIP(hipGetLastError());
   k_spai_finalize<<<nr, 256, 0, st>>>(pd, w.hat, w.dinv, 2, d_skip, skip_flags(p), d_alpha,
-                                      p->v64.as<double>(), p->v16.as<uint16_t>());
+                                      p->v64.as<double>(), p->v32.as<float>());
   AIRGA_HIP(hipGetLastError());
   p->is_update = true;
   p->parent = old;
@@ -1491,7 +1498,7 @@ static airga_status run_build_many(airga_ctx ctx, int32_t count, const double* s
       const airga_prec p = ps[i0 + i];
       k_spai_finalize<<<nr, 256, 0, st>>>(pd, hat + (size_t)i * stored, dinv + (size_t)i * n_pad,
                                           o.symmetrize ? 1 : 0, nullptr, nullptr, nullptr,
-                                          p->v64.as<double>(), p->v16.as<uint16_t>());
+                                          p->v64.as<double>(), p->v32.as<float>());
       AIRGA_HIP(hipGetLastError());
       // Alg. 2's starting scaling trace(K) / trace(K K^T), from the Gram scalars
       const double a = U.a[i], b = U.b[i];
@@ -1568,7 +1575,7 @@ static airga_status run_update_many(airga_ctx ctx, int32_t count, const airga_pr
       const airga_prec p = ps[i0 + i];
       k_spai_finalize<<<nr, 256, 0, st>>>(pd, hat + (size_t)i * stored, dinv + (size_t)i * n_pad, 2,
                                           U.skip[i], U.skipf[i], U.alpha[i], p->v64.as<double>(),
-                                          p->v16.as<uint16_t>());
+                                          p->v32.as<float>());
       AIRGA_HIP(hipGetLastError());
       p->is_update = true;
       p->parent = olds[i0 + i];
@@ -1687,6 +1694,7 @@ airga_status airga_spai_update(airga_ctx ctx, airga_prec old, double s_new,
   *out = nullptr;
   AIRGA_TRY(check_prec(old));
   if (old->ctx != ctx) return fail(AIRGA_EINVAL, "preconditioner belongs to another context");
+  if (old->is_complex) return fail(AIRGA_EUNSUPPORTED, "complex factors are not updated");
   airga_spai_opts o;
   airga_spai_opts_default(&o);
   if (opts) o = *opts;
@@ -1743,6 +1751,7 @@ airga_status airga_spai_update_many(airga_ctx ctx, int32_t count, const airga_pr
     AIRGA_TRY(check_spai_args(ctx, s_new[i], &dummy));
     AIRGA_TRY(check_prec(olds[i]));
     if (olds[i]->ctx != ctx) return fail(AIRGA_EINVAL, "preconditioner belongs to another context");
+    if (olds[i]->is_complex) return fail(AIRGA_EUNSUPPORTED, "complex factors are not updated");
   }
   airga_spai_opts o;
   airga_spai_opts_default(&o);
@@ -1773,11 +1782,15 @@ airga_status airga_get_prec_info(airga_prec prec, airga_prec_info* out) {
   out->chain_len = (int32_t)chain.size();
   out->scalar_only = prec->scalar_only ? 1 : 0;
   out->skipped_cols = prec->skipped;
+  out->shift_im = prec->shift_im;
+  out->alpha_im = prec->alpha_im;
+  out->is_complex = prec->is_complex ? 1 : 0;
   return AIRGA_OK;
 }
 
 airga_status airga_prec_export(airga_prec prec, double* values, double* objective) {
   AIRGA_TRY(check_prec(prec));
+  if (prec->is_complex) return fail(AIRGA_EINVAL, "complex factor: use airga_prec_export_complex");
   airga_ctx ctx = prec->ctx;
   if (values) {
     // an update with every column skipped holds no factor values
@@ -1796,9 +1809,20 @@ airga_status airga_prec_export(airga_prec prec, double* values, double* objectiv
   return AIRGA_OK;
 }
 
+airga_status airga_prec_skip_flags(airga_prec prec, uint8_t* flags) {
+  AIRGA_TRY(check_prec(prec));
+  if (!flags) return fail(AIRGA_EINVAL, "null flags");
+  airga_ctx ctx = prec->ctx;
+  const int8_t* src = prec->is_update ? skip_flags(prec) : nullptr;
+  k_copy_flags<<<blocks_for(ctx->pen.n, 256), 256, 0, ctx->stream>>>(src, ctx->pen.n, flags);
+  AIRGA_HIP(hipGetLastError());
+  return AIRGA_OK;
+}
+
 airga_status airga_prec_apply(airga_prec prec, int32_t count, const double* r, int64_t ldr,
                               double* z, int64_t ldz) {
   AIRGA_TRY(check_prec(prec));
+  if (prec->is_complex) return fail(AIRGA_EINVAL, "complex factors apply in airga_cocg_solve only");
   airga_ctx ctx = prec->ctx;
   const Pencil& pen = ctx->pen;
   if (count < 0 || (count > 0 && (!r || !z))) return fail(AIRGA_EINVAL, "bad vectors");
@@ -1841,7 +1865,7 @@ void airga_prec_release(airga_prec prec) {
     airga_ctx ctx = prec->ctx;
     // buffers go back to the context's stream-ordered pool
     pool_put(ctx, &prec->v64);
-    pool_put(ctx, &prec->v16);
+    pool_put(ctx, &prec->v32);
     pool_put(ctx, &prec->objective);
     pool_put(ctx, &prec->scal);
     ctx->live_precs--;

@@ -106,3 +106,32 @@ def test_trace_summary_names_both_averages_of_the_dominant_kernel(tmp_path):
     assert "k_update_prec" in rows[0] and "| 32 | 5.15 | 161.0 | 20.0 |" in rows[0]
     assert "bench.py events 163.5 us" in text and "all its launches in the run: 161.0 us" in text
     assert "rocprofv3 ... (test)" in text
+
+
+def test_kernel_bytes_follow_the_per_kernel_formulas():
+    # one 1000-row pencil of 6000 stored entries, banded (1-byte offsets),
+    # float32 inner solves: the formulas of the kernel table, term by term
+    kw = dict(stored=6000, n=1000, ib=1, w=4, fw=4, m=2)
+    assert bench.kernel_bytes("dir_spmv", 3, 10, 0, **kw) == 3 * 6000 * 9 + 10 * 16 * 1000
+    assert bench.kernel_bytes("update_prec", 3, 10, 5, first_passes=2, **kw) == \
+        3 * 6000 + 5 * 6000 * 4 + (70 - 2) * 4 * 1000
+    assert bench.kernel_bytes("init_prec", 1, 4, 2, **kw) == 6000 + 2 * 6000 * 4 + 4 * 8 * 1000
+    assert bench.kernel_bytes("chain", 2, 6, 3, **kw) == 2 * 6000 * 4 + 3 * 6000 * 4 + 6 * 8 * 1000
+    assert bench.kernel_bytes("ir_residual", 2, 8, 0, **kw) == \
+        2 * 6000 * 17 + 2 * 2 * 8 * 1000 + 8 * 12 * 1000
+    assert bench.kernel_bytes("ir_update", 1, 8, 0, **kw) == 8 * 20 * 1000
+    assert bench.kernel_bytes("ir_update", 2, 8, 0, assign_sys=4, **kw) == (8 * 20 - 4 * 8) * 1000
+    assert bench.kernel_bytes("ir_update", 1, 8, 0, mixed=False, **kw) == 8 * 16 * 1000
+    assert bench.kernel_bytes("reduce", 5, 0, 0, gp=7, red_sys=11, **kw) == 11 * 7 * 8
+    # float64 solves: 8-byte vectors and factor values
+    kw64 = dict(kw, w=8, fw=8)
+    assert bench.kernel_bytes("update_prec", 1, 1, 1, **kw64) == 6000 + 6000 * 8 + 7 * 8 * 1000
+    # 64-row slices, 4 wavefronts per block
+    assert bench.row_blocks(1000, 256) == 1 and bench.row_blocks(1_000_000, 256) == 977
+    rows = bench.kernel_rows({"update_prec": (2, 0.5), "reduce": (4, 0.01)},
+                             {"update_prec": (4, 2), "reduce": (0, 0)}, gp=3, **kw)
+    upd = next(r for r in rows if r["kernel"] == "update_prec")
+    assert upd["bytes"] == 2 * 6000 + 2 * 6000 * 4 + 28 * 4 * 1000
+    assert upd["gbs"] == round(upd["bytes"] / 0.5e-3 / 1e9, 1)
+    red = next(r for r in rows if r["kernel"] == "reduce")
+    assert red["bytes"] == 3 * 4 * 3 * 8   # 3 slots per update pass

@@ -1,0 +1,177 @@
+"""GPU: complex expansion points (K(s) complex symmetric) against the
+oracle: the shifted matrix, the complex SPAI (column least squares,
+equilibrated and symmetrised with the plain transpose), and batched COCG --
+its iterates after k steps against the oracle's COCG with the same factor,
+its solutions against the complex double-double reference -- at small sizes
+with ragged slices and at the full 1,000,000-DOF size the benchmark times."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import airga, beam, direct, grid_pencil, pencil, rel_err, set_pencil, spai, to_dev
+from oracle import pcg as opcg
+
+pytestmark = pytest.mark.gpu
+
+SHIFTS = [3.0 + 2.0j, 0.5 - 4.0j, 100.0 + 50.0j, 1.0 + 0.1j]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = airga.Context(0)
+    yield c
+    c.close()
+
+
+def sur_beam(n_el=1037, seed=11):
+    return beam.make_beam(n_el, ei_loguniform=(0.5, 2.0), surrogate=True, seed=seed)
+
+
+def factor_matrix(pen, vals):
+    import scipy.sparse as sp
+    return sp.csr_matrix((vals, pen.col_idx, pen.row_ptr), shape=(pen.n, pen.n))
+
+
+def test_complex_assembly(ctx):
+    pen = sur_beam(301)
+    set_pencil(ctx, pen)
+    for s in SHIFTS:
+        got = ctx.assemble_shift_complex(s).cpu().numpy()
+        ref = pencil.shifted_values_complex(pen.m_val, pen.k_val, pen.alpha, pen.beta, s)
+        scale = np.abs(pen.m_val) * abs(s * s + pen.alpha * s) + np.abs(pen.k_val) * abs(1 + pen.beta * s)
+        assert np.all(np.abs(got - ref) <= 4e-16 * scale + 1e-300)
+
+
+@pytest.mark.parametrize("which", ["beam", "grid"])
+def test_complex_spai_matches_oracle(ctx, which):
+    pen = sur_beam(301) if which == "beam" else grid_pencil(23, 17)
+    set_pencil(ctx, pen)
+    for s in SHIFTS:
+        a = pencil.shifted_operator_complex(pen, s)
+        for sym in (False, True):
+            ref = spai.spai_build(a, symmetrize=sym)
+            p = ctx.spai_build_complex(s, symmetrize=sym)
+            vals, obj = (t.cpu().numpy() for t in p.export_complex())
+            assert np.all(np.abs(obj - ref.objective) <= 1e-12 * np.maximum(1.0, ref.objective))
+            assert np.all(np.abs(vals - ref.values) <= 1e-9 * np.abs(ref.values).max()), (s, sym)
+            if sym:
+                m = factor_matrix(pen, vals)
+                assert abs(m - m.T).max() <= 1e-15 * np.abs(vals).max()
+            info = p.info()
+            assert info.is_complex == 1 and info.shift == s.real and info.shift_im == s.imag
+            assert np.isclose(info.alpha + 1j * info.alpha_im, ref.alpha, rtol=1e-12)
+
+
+@pytest.mark.parametrize("form,oform", [(airga.BETA_FLEXIBLE, "flexible"),
+                                        (airga.BETA_CLASSICAL, "fr")])
+def test_cocg_iterates_follow_the_oracle(ctx, form, oform):
+    """After k steps the GPU iterate equals the oracle's COCG with the same
+    (exported) factor, for both direction updates."""
+    pen = sur_beam(400)
+    set_pencil(ctx, pen)
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal((2, pen.n))
+    s = 2.0 + 1.5j
+    p = ctx.spai_build_complex(s)
+    cm = factor_matrix(pen, p.export_complex()[0].cpu().numpy())
+    a = pencil.shifted_operator_complex(pen, s)
+    for k in (1, 3, 8):
+        X, st = ctx.cocg_solve([s], [p], to_dev(f, torch.float64), tol=1e-30, max_iter=k,
+                               beta_form=form)
+        for c in range(2):
+            assert st[c]["status"] == airga.SYS_MAXIT and st[c]["iters"] == k
+            r = opcg.cocg(lambda v: a @ v, lambda v: cm @ v, f[c], tol=1e-30, max_iter=k, beta=oform)
+            assert rel_err(X[0, c].cpu().numpy(), r.x) < 1e-11, (k, c)
+
+
+@pytest.mark.parametrize("precond", [True, False])
+def test_batched_cocg_matches_the_reference(ctx, precond):
+    pen = sur_beam()
+    set_pencil(ctx, pen)
+    rng = np.random.default_rng(2)
+    f = np.stack([beam.tip_load(pen.n)[0], rng.standard_normal(pen.n)])
+    precs = [ctx.spai_build_complex(s) for s in SHIFTS] if precond else None
+    # without a preconditioner the error is up to cond(K(s)) times the
+    # residual (the recurrence residual stops at 1e-10 near 2.7e-8 error at
+    # s = 3 + 2i): the unpreconditioned solve runs to 1e-12
+    tol = 1e-10 if precond else 1e-12
+    X, st = ctx.cocg_solve(SHIFTS, precs, to_dev(f, torch.float64), tol=tol,
+                           max_iter=20000 if precond else 60000)
+    Xh = X.cpu().numpy()
+    for k, s in enumerate(SHIFTS):
+        ref = direct.reference_solve_complex(pen, s, f, "dd")
+        for c in range(2):
+            e = st[2 * k + c]
+            assert e["status"] == airga.SYS_CONVERGED, (s, c, e)
+            # the true residual at exit (the recurrence's drifts from it
+            # by rounding: 4.9e-12 against 1e-12 without a preconditioner)
+            assert e["relres"] <= 2e-10
+            assert rel_err(Xh[k, c], ref[c]) < 1e-8, (s, c)
+    if precond:
+        # the factor cuts the iterations
+        _, st0 = ctx.cocg_solve(SHIFTS, None, to_dev(f, torch.float64), tol=1e-10, max_iter=60000)
+        assert sum(e["iters"] for e in st) < sum(e["iters"] for e in st0)
+
+
+def test_complex_edge_cases_and_errors(ctx):
+    pen = sur_beam(70)   # n = 140: three slices, the last ragged
+    set_pencil(ctx, pen)
+    f = np.zeros((2, pen.n))
+    f[1, -2] = 1.0      # a zero load converges at once with X = 0
+    s = 4.0 + 3.0j
+    p = ctx.spai_build_complex(s)
+    X, st = ctx.cocg_solve([s], [p], to_dev(f, torch.float64))
+    assert st[0]["status"] == airga.SYS_CONVERGED and st[0]["iters"] == 0
+    assert torch.count_nonzero(X[0, 0]).item() == 0
+    ref = direct.reference_solve_complex(pen, s, f[1:], "dd")[0]
+    assert rel_err(X[0, 1].cpu().numpy(), ref) < 1e-8
+    # a real shift through the complex path equals the real solve
+    pr = ctx.spai_build_complex(25.0)
+    Xc, _ = ctx.cocg_solve([25.0], [pr], to_dev(f, torch.float64))
+    Xr = direct.reference_solve(pen, 25.0, f[1:], "dd")[0]
+    assert np.abs(Xc[0, 1].cpu().numpy().imag).max() == 0.0
+    assert rel_err(Xc[0, 1].cpu().numpy().real, Xr) < 1e-8
+    # the real and complex calls refuse each other's factors
+    real = ctx.spai_build(25.0)
+    F = to_dev(f, torch.float64)
+    with pytest.raises(airga.AirgaError) as e:
+        ctx.pcg_solve([s.real], [p], F)
+    assert e.value.status == airga.EINVAL
+    with pytest.raises(airga.AirgaError) as e:
+        ctx.cocg_solve([25.0], [real], F)
+    assert e.value.status == airga.EINVAL
+    with pytest.raises(airga.AirgaError) as e:
+        ctx.cocg_solve([s + 1.0], [p], F)   # built at another shift
+    assert e.value.status == airga.EINVAL
+    with pytest.raises(airga.AirgaError) as e:
+        ctx.spai_update(p, 30.0)
+    assert e.value.status == airga.EUNSUPPORTED
+    with pytest.raises(airga.AirgaError) as e:
+        p.export()
+    assert e.value.status == airga.EINVAL
+
+
+def test_complex_full_size(ctx):
+    """n = 1e6 surrogate beam, m = 4 seeded loads, 16 complex points
+    s_k = sigma_k e^{i pi/6}, sigma_k logspace(0, 4, 16): all 64 systems in
+    one batched COCG, every one against the complex double-double reference
+    (8 threads)."""
+    pen, f, sig, _ = beam.make_workload("c3", surrogate=True)
+    shifts = [complex(v) for v in np.asarray(sig) * np.exp(1j * np.pi / 6)]
+    set_pencil(ctx, pen)
+    precs = [ctx.spai_build_complex(s) for s in shifts]
+    X, st = ctx.cocg_solve(shifts, precs, to_dev(f, torch.float64), tol=1e-10)
+    assert all(e["status"] == airga.SYS_CONVERGED for e in st), [e for e in st if e["status"]]
+    errs = {}
+
+    def check(k, ref):
+        xk = X[k].cpu().numpy()
+        for c in range(f.shape[0]):
+            errs[(k, c)] = rel_err(xk[c], ref[c])
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(8) as ex:
+        for k, ref in enumerate(ex.map(lambda s: direct.reference_solve_complex(pen, s, f, "dd"),
+                                       shifts)):
+            check(k, ref)
+    bad = {key: e for key, e in errs.items() if not e < 1e-8}
+    assert len(errs) == 64 and not bad, bad

@@ -23,6 +23,9 @@ def _sample_cols(n, rng, k=300):
     return np.unique(np.concatenate([edge, rng.choice(n, k, replace=False)]))
 
 
+WORKERS = 8  # threads for the oracle's reference solves (independent shifts)
+
+
 def test_c4_surrogate_full_size(ctx):
     """n = 1e6, m = 4 seeded loads, 16 shifts logspace(0, 4, 16), mixed."""
     pen, f, shifts, rng = beam.make_workload("c3", surrogate=True)
@@ -38,73 +41,112 @@ def test_c4_surrogate_full_size(ctx):
     X, st = ctx.pcg_solve(list(shifts), precs, to_dev(f, torch.float64), tol=1e-10,
                           mode=airga.MODE_MIXED)
     Xh = X.cpu().numpy()
+    refs = direct.reference_solves(pen, list(shifts), f, "dd", WORKERS)
     for k, s in enumerate(shifts):
-        ref = direct.reference_solve(pen, s, f, "dd")
         for c in range(f.shape[0]):
             e = st[k * f.shape[0] + c]
             assert e["status"] == airga.SYS_CONVERGED, (s, c, e)
-            assert rel_err(Xh[k, c], ref[c]) < 1e-8, (s, c)
+            assert rel_err(Xh[k, c], refs[k][c]) < 1e-8, (s, c)
 
 
 def test_c3_batched_fp64_full_size(ctx):
-    """Same systems in float64 (batched, no refinement)."""
+    """The same 64 systems in float64, batched in one set of kernels (no
+    refinement), every one against the double-double reference."""
     pen, f, shifts, rng = beam.make_workload("c3", surrogate=True)
     set_pencil(ctx, pen)
-    sel = [0, 5, 10, 15]
-    precs = [ctx.spai_build(shifts[k]) for k in sel]
-    X, st = ctx.pcg_solve([shifts[k] for k in sel], precs, to_dev(f, torch.float64), tol=1e-10,
+    precs = ctx.spai_build_many(list(shifts))
+    X, st = ctx.pcg_solve(list(shifts), precs, to_dev(f, torch.float64), tol=1e-10,
                           mode=airga.MODE_FP64)
     Xh = X.cpu().numpy()
-    for i, k in enumerate(sel):
-        ref = direct.reference_solve(pen, shifts[k], f, "dd")
+    refs = direct.reference_solves(pen, list(shifts), f, "dd", WORKERS)
+    assert len(st) == 64
+    for k in range(len(shifts)):
         for c in range(f.shape[0]):
-            assert st[i * f.shape[0] + c]["status"] == airga.SYS_CONVERGED
-            assert rel_err(Xh[i, c], ref[c]) < 1e-8
+            assert st[k * f.shape[0] + c]["status"] == airga.SYS_CONVERGED, (k, c)
+            assert rel_err(Xh[k, c], refs[k][c]) < 1e-8, (k, c)
 
 
-def test_c2_surrogate_update_sequence(ctx):
-    """n = 1e5, tip load, 8 shifts: build at every shift, then vertical
-    updates to drifted shifts (all columns skip -> scalar factors)."""
+def test_c2_update_chain_sequence(ctx):
+    """n = 1e5 heterogeneous beam, tip load, 8 shifts logspace(0, 4, 8): the
+    SPAI is built at s_1 and updated along the shifts (the horizontal chain
+    Q_8 ... Q_2 P_1 of the update algorithm), then once more at drifted
+    points (vertical, relative drift 1e-2).  Every point is solved in float64
+    through its chain, against the oracle's double-double reference.  The
+    first factor is the equilibrated SPAI without the symmetric average (the
+    paper's own z = P r): at s = 1 the averaged factor is indefinite on this
+    beam, which CG tolerates alone, but every chain built on it fails to
+    converge, in the oracle's PCG as on the GPU.  The
+    update's per-column skip decisions are compared with the oracle's both
+    ways: on every column for the update that solves part of its columns
+    and for one that keeps all of them, on sampled columns for updates that
+    solve all of theirs."""
     pen, f, shifts, rng = beam.make_workload("c2", surrogate=True)
-    drifted = beam.drift_shifts(shifts, 1e-3, rng)
+    drifted = beam.drift_shifts(shifts, 1e-2, rng)
     set_pencil(ctx, pen)
-    precs = [ctx.spai_build(s) for s in shifts]
-    upd = [ctx.spai_update(p, s) for p, s in zip(precs, drifted)]
-    X, st = ctx.pcg_solve(list(drifted), upd, to_dev(f, torch.float64), tol=1e-10,
-                          mode=airga.MODE_MIXED)
+    precs = [ctx.spai_build(shifts[0], symmetrize=False)]
+    for s in shifts[1:]:
+        precs.append(ctx.spai_update(precs[-1], s))
+    vert = ctx.spai_update_many(precs, list(drifted))
+    lens = [p.info().chain_len for p in precs + vert]
+    # chains of up to six real factors are solved through
+    assert lens[:5] == [1, 2, 3, 4, 5] and max(lens) >= 6, lens
+    X, st = ctx.pcg_solve(list(shifts) + list(drifted), precs + vert, to_dev(f, torch.float64),
+                          tol=1e-10, mode=airga.MODE_FP64)
     Xh = X.cpu().numpy()
-    for k, s in enumerate(drifted):
-        ref = direct.reference_solve(pen, s, f, "dd")
-        assert st[k]["status"] == airga.SYS_CONVERGED
-        assert rel_err(Xh[k, 0], ref[0]) < 1e-8
-    # update skip counts against the oracle at sampled columns
-    cols = _sample_cols(pen.n, np.random.default_rng(2))
-    for k in (0, 4, 7):
-        ref = spai.spai_update(pencil.shifted_operator(pen, shifts[k]),
-                               pencil.shifted_operator(pen, drifted[k]), tol=0.01, cols=cols)
-        info = upd[k].info()
+    refs = direct.reference_solves(pen, list(shifts) + list(drifted), f, "dd", WORKERS)
+    for k in range(len(refs)):
+        assert st[k]["status"] == airga.SYS_CONVERGED, (k, st[k])
+        assert rel_err(Xh[k, 0], refs[k][0]) < 1e-8, (k, lens[k])
+    # skip decisions column by column (exact integer parity; columns within
+    # 1e-12 of the threshold would be borderline and are excluded)
+    samp = _sample_cols(pen.n, np.random.default_rng(2))
+    cases = [(shifts[4], shifts[5], precs[5], None), (shifts[6], shifts[7], precs[7], None),
+             (shifts[0], shifts[1], precs[1], samp), (shifts[3], shifts[4], precs[4], samp),
+             (shifts[5], drifted[5], vert[5], samp)]
+    partial = False
+    for s_old, s_new, p, cols in cases:
+        ref = spai.spai_update(pencil.shifted_operator(pen, s_old),
+                               pencil.shifted_operator(pen, s_new), tol=0.01, cols=cols)
+        idx = np.arange(pen.n) if cols is None else cols
+        flags = p.skip_flags().cpu().numpy().astype(bool)
+        sure = ref.margin[idx] > 1e-12
+        assert np.array_equal(flags[idx][sure], ref.skipped[idx][sure]), (s_old, s_new)
+        info = p.info()
         assert np.isclose(info.alpha, ref.alpha, rtol=1e-12)
-        if info.skipped_cols == pen.n:
-            assert ref.skipped[cols].all()
+        if cols is None:
+            assert abs(int(info.skipped_cols) - int(ref.skipped.sum())) <= int((~sure).sum())
+            partial |= 0 < ref.skipped.sum() < pen.n
+    assert partial  # one update solved only part of its columns
 
 
-def test_c5_surrogate_full_size_sampled(ctx):
-    """n = 1e7, heterogeneous EI, m = 4, 32 shifts (128 systems) mixed;
-    every system must converge, and a sample of shifts is checked against
-    the oracle's float64 reference solve (the surrogate is well conditioned:
-    float64 and double-double references agree to 1e-13)."""
+def test_c5_surrogate_full_size(ctx):
+    """n = 1e7, heterogeneous EI, m = 4, 32 shifts (128 systems) mixed: every
+    system against the oracle's binary64 reference solve, which is pinned to
+    the double-double reference at the lowest and highest shift (the
+    surrogate is well conditioned: the two agree far below 1e-8)."""
     pen, f, shifts, rng = beam.make_workload("c5", surrogate=True)
     set_pencil(ctx, pen)
-    precs = [ctx.spai_build(s) for s in shifts]
+    precs = ctx.spai_build_many(list(shifts))
     X, st = ctx.pcg_solve(list(shifts), precs, to_dev(f, torch.float64), tol=1e-10,
                           mode=airga.MODE_MIXED)
     assert all(e["status"] == airga.SYS_CONVERGED for e in st), [e for e in st if e["status"]]
     assert max(e["relres"] for e in st) <= 1e-10
-    for k in (0, 13, 31):
-        ref = direct.reference_solve(pen, shifts[k], f, "f64")
-        Xk = X[k].cpu().numpy()
+    dd = direct.reference_solves(pen, [shifts[0], shifts[-1]], f, "dd", 2)
+    errs = {}
+
+    def check(k, ref):
+        if k in (0, len(shifts) - 1):
+            rdd = dd[0 if k == 0 else 1]
+            for c in range(f.shape[0]):
+                assert rel_err(ref[c], rdd[c]) < 1e-12, (k, c)
+        xk = X[k].cpu().numpy()
         for c in range(f.shape[0]):
-            assert rel_err(Xk[c], ref[c]) < 1e-8, (k, c)
+            errs[(k, c)] = rel_err(xk[c], ref[c])
+    # the 10 GB of references are compared shift by shift as they arrive
+    direct.reference_solves(pen, list(shifts), f, "f64", WORKERS, each=check)
+    assert len(errs) == 128
+    bad = {key: e for key, e in errs.items() if not e < 1e-8}
+    assert not bad, bad
 
 
 def test_moment_blocks_full_size(ctx):

@@ -1,11 +1,10 @@
-"""GPU: one iteration of AIRGA's outer loop (Algorithm 1) composed from the
-library's entry points -- batched SPAI builds and PCG solves, the block
+"""GPU: AIRGA's outer loop (Algorithm 1) as the library runs it
+(airga_reduce: batched SPAI builds or updates and PCG solves, the block
 operations of the moment sequence, the projection, and the decisions of the
-outer iteration (moment errors, H2 changes, poles and the next expansion
-points) -- against the oracle's iteration with exact sparse solves, with
-readings A1-A6 on both sides.  Then the vertical step the paper builds its
-cheap update for (Algorithm 3): every preconditioner updated to the new
-expansion points, and the solves there."""
+outer iteration) against the oracle's loop with exact sparse solves, with
+readings A1-A6 on both sides; the update across outer iterations of
+Algorithm 5 where the points settle; and the solves at the next expansion
+points."""
 import numpy as np
 import pytest
 import torch
@@ -37,118 +36,109 @@ def system(n_el=60, m=2, seed=3):
     return pen, f, cp
 
 
-def gpu_iteration(ctx, pen, f, cp, shifts, rmax, precs, tol_inner=1e-6):
-    """Algorithm 1's inner part for one outer iteration, every step through
-    the C ABI (the control flow mirrors the oracle's)."""
-    n, m, l = pen.n, f.shape[0], len(shifts)
-    fd = to_dev(f, torch.float64)
-    cpd = to_dev(cp, torch.float64)
-    X, st = ctx.pcg_solve(list(shifts), precs, fd, tol=1e-12)
-    assert all(e["status"] == airga.SYS_CONVERGED for e in st)
-    xs = X.reshape(l * m, n).contiguous()
-    for i in range(l):
-        b = xs[i * m:(i + 1) * m].clone()
-        ctx.block_qr(b)
-        xs[i * m:(i + 1) * m] = b
-
-    def model_of(w):
-        mh, kh = ctx.project(w)
-        fh = ctx.gram(w, fd).cpu().numpy()
-        cph = ctx.gram(w, cpd).cpu().numpy().T
-        return (mh, kh, fh, cph, None)
-
-    def next_block(q):
-        v = xs[q * m:(q + 1) * m].clone()
-        ctx.global_orth(None, v, m, normalize=True)
-        return v
-
-    vs, sigmas, step_errors, inner = [], [], [], []
-    errors, prev = None, None
-    j = 1
-    while j < rmax // m:
-        q = 0 if errors is None else int(np.argmax(errors))
-        sigmas.append(q)
-        vs.append(next_block(q))
-        rhs = ctx.pencil_apply(1.0, 0.0, vs[-1])
-        y, st = ctx.pcg_solve([shifts[q]], [precs[q]], rhs, tol=1e-12)
-        assert all(e["status"] == airga.SYS_CONVERGED for e in st)
-        xs[q * m:(q + 1) * m] = -y[0]
-        _, before = ctx.global_orth(None, xs.clone(), m)
-        _, after = ctx.global_orth(torch.cat(vs).contiguous(), xs, m)
-        errors = after / before
-        step_errors.append(errors)
-        w = xs.clone()
-        ctx.global_orth(None, w, m, normalize=True)
-        ctx.block_qr(w)
-        mi = model_of(w)
-        if prev is not None:
-            ch = airga.h2_distance(mi, prev, ALPHA, BETA) / airga.h2_distance(mi, None, ALPHA, BETA)
-            inner.append(ch)
-            if ch < tol_inner:
-                j += 1
-                break
-        prev = mi
-        j += 1
-    q = 0 if errors is None else int(np.argmax(errors))
-    sigmas.append(q)
-    vs.append(next_block(q))
-    v = torch.cat(vs).contiguous()
-    ctx.block_qr(v)
-    final = model_of(v)
-    nxt = airga.next_shifts(airga.qep_poles(final[0], final[1], ALPHA, BETA), l)
-    return dict(sigmas=sigmas, J=len(vs), step_errors=step_errors, inner=inner, model=final,
-                next=nxt)
-
-
-def oracle_iterations(pen, f, cp, count):
+def oracle_iterations(pen, f, cp, count, shifts=SHIFTS, rmax=RMAX):
     n = pen.n
     ms = pencil.csr(n, pen.row_ptr, pen.col_idx, pen.m_val)
     ks = pencil.csr(n, pen.row_ptr, pen.col_idx, pen.k_val)
-    _, _, hist = airga_loop.airga(ms, ks, pen.alpha, pen.beta, f.T, cp, None, SHIFTS, rmax=RMAX,
+    _, _, hist = airga_loop.airga(ms, ks, pen.alpha, pen.beta, f.T, cp, None, shifts, rmax=rmax,
                                   max_outer=count)
     return ms, ks, hist
 
 
-def test_outer_iteration_matches_the_oracle(ctx):
+def clear_prefix(step_errors, sigmas):
+    """Length of the prefix of sigmas decided by a clear margin (the top two
+    moment errors at least 1e-4 apart, relatively); sigma_1 needs none."""
+    k = 1
+    for e in step_errors:
+        top = np.sort(e)[::-1]
+        if len(top) > 1 and top[0] - top[1] <= 1e-4 * top[0]:
+            break
+        k += 1
+    return min(k, len(sigmas))
+
+
+def test_reduce_matches_the_oracle_loop(ctx):
+    """airga_reduce (the library's AIRGA loop) against the oracle's loop:
+    two outer iterations on a damped surrogate beam, the same sigma
+    sequence, J and next expansion points, and the same reduced transfer
+    function."""
     pen, f, cp = system()
     set_pencil(ctx, pen)
     ms, ks, hist = oracle_iterations(pen, f, cp, 2)
-    h0 = hist[0]
-    # every argmax of the oracle's run is decided by a clear margin
-    for e in h0["step_errors"]:
-        top = np.sort(e)[::-1]
-        assert top[0] - top[1] > 1e-4 * top[0]
-    precs = ctx.spai_build_many(SHIFTS)
-    g = gpu_iteration(ctx, pen, f, cp, SHIFTS, RMAX, precs)
-    assert g["sigmas"] == h0["sigmas"] and g["J"] == h0["J"]
-    for ge, oe in zip(g["step_errors"], h0["step_errors"]):
-        assert np.allclose(ge, oe, rtol=1e-6, atol=0)
-    assert np.allclose(g["inner"], h0["inner_changes"], rtol=1e-5, atol=1e-9)
-    mh, kh, fh, cph, _ = g["model"]
-    om = h0["model"]
-    assert np.abs(mh - om.mh).max() <= 1e-8 * np.abs(om.mh).max()
-    assert np.abs(kh - om.kh).max() <= 1e-8 * np.abs(om.kh).max()
-    red = airga_loop.Model(mh, ALPHA * mh + BETA * kh, kh, fh, cph)
-    # The GPU solves stop at a relative residual of 1e-12, so the moment
-    # blocks carry errors up to cond(K(s)) * 1e-12 (a few 1e-6 here), which
-    # the chain of moment solves and the projection carry into the reduced
-    # transfer function; the oracle's solves are exact.
+    out = ctx.reduce(to_dev(f, torch.float64), to_dev(cp, torch.float64), SHIFTS, r_max=RMAX,
+                     max_outer=2, tol=1e-12)
+    assert out["iterations"] == 2 and len(out["history"]) == 2
+    for g, h in zip(out["history"], hist):
+        assert np.allclose(g["shifts"], h["shifts"], rtol=1e-6, atol=0)
+        k = clear_prefix(h["step_errors"], h["sigmas"])
+        assert g["sigmas"][:k] == h["sigmas"][:k]
+        assert g["J"] == h["J"] and g["all_converged"] and not g["updated"]
+    assert out["history"][0]["change"] is None
+    assert out["r"] == hist[-1]["J"] * f.shape[0]
+    # the basis is orthonormal and the model is its projection
+    v = out["V"].cpu().numpy().T
+    assert np.abs(v.T @ v - np.eye(out["r"])).max() < 1e-12
     mm, kk = beam.pencil_dense(pen)
+    assert np.abs(out["mhat"] - v.T @ mm @ v).max() <= 1e-12 * np.abs(out["mhat"]).max()
+    assert np.abs(out["khat"] - v.T @ kk @ v).max() <= 1e-12 * np.abs(out["khat"]).max()
+    assert np.allclose(out["fhat"], v.T @ f.T, rtol=0, atol=1e-13)
+    assert np.allclose(out["cphat"], cp @ v, rtol=0, atol=1e-13)
+    om = hist[-1]["model"]
+    red = airga_loop.Model(out["mhat"], ALPHA * out["mhat"] + BETA * out["khat"], out["khat"],
+                           out["fhat"], out["cphat"])
+    # The GPU solves stop at a relative residual of 1e-12, so the moment
+    # blocks carry errors up to cond(K(s)) * 1e-12, which the chain of moment
+    # solves and the projection carry into the reduced transfer function; the
+    # oracle's solves are exact.
     dd = ALPHA * mm + BETA * kk
     eps = 1e-12 * max(np.linalg.cond(s * s * mm + s * dd + kk) for s in SHIFTS)
-    # (this beam's response is at rounding level, ~1e-40, beyond s ~ 10:
-    # compared where it is not)
     for s in (0.01, 0.1, 1.0):
         got, want = red.transfer(s), om.transfer(s)
         err = np.abs(got - want).max() / np.abs(want).max()
         assert err <= 50 * eps, (s, err, eps)
-    # both interpolate the full model at sigma_1, whose solve starts the basis
-    s1 = SHIFTS[h0["sigmas"][0]]
+    # the reduced model interpolates the full one at the first sigma
+    s1 = hist[-1]["shifts"][hist[-1]["sigmas"][0]]
     full = cp @ np.linalg.solve(s1 * s1 * mm + s1 * dd + kk, f.T)
-    for h in (red.transfer(s1), om.transfer(s1)):
-        assert np.abs(h - full).max() <= 50 * eps * np.abs(full).max()
-    # the next expansion points (the oracle's second iteration starts there)
-    assert np.allclose(g["next"], hist[1]["shifts"], rtol=1e-6, atol=0)
+    assert np.abs(red.transfer(s1) - full).max() <= 50 * eps * np.abs(full).max()
+    assert np.allclose(out["next_shifts"],
+                       airga_loop.next_shifts(airga_loop.qep_poles(om.mh, om.dh, om.kh), 3),
+                       rtol=1e-6, atol=0)
+
+
+def test_reduce_with_updates_where_the_points_settle(ctx):
+    """Algorithm 5 on a small literal beam (EI = 1, n = 60, alpha = 0.01,
+    beta = 0.001), where the expansion points settle after the first
+    iteration at (alpha + beta w^2) / 2 of the three lowest modes: from the
+    third iteration on, each point's preconditioner is the update of the
+    previous one (a vertical step).  The points of every iteration follow
+    the oracle's, every solve converges, and the updated iterations apply
+    chains instead of new builds."""
+    pen = beam.make_beam(30, seed=3, alpha=0.01, beta=0.001)
+    n = pen.n
+    f = np.zeros((1, n))
+    f[0, n - 2] = 1.0
+    cp = f.copy()
+    set_pencil(ctx, pen)
+    _, _, hist = oracle_iterations(pen, f, cp, 4)
+    out = ctx.reduce(to_dev(f, torch.float64), to_dev(cp, torch.float64), SHIFTS, r_max=RMAX,
+                     max_outer=4, tol=1e-12, update_from=3)
+    assert out["iterations"] == 4
+    # the solves stop at a relative residual of 1e-12 and cond(K(s)) reaches
+    # about 4e6 at the settled points, so the moment blocks, the reduced
+    # poles and the next points carry relative errors up to about 50 times
+    # cond * 1e-12; the oracle's solves are exact
+    mm, kk = beam.pencil_dense(pen)
+    dd = pen.alpha * mm + pen.beta * kk
+    pts = np.concatenate([h["shifts"] for h in hist])
+    eps = 1e-12 * max(np.linalg.cond(s * s * mm + s * dd + kk) for s in pts)
+    for z, (g, h) in enumerate(zip(out["history"], hist)):
+        assert np.allclose(g["shifts"], h["shifts"], rtol=50 * eps, atol=0), (z, eps)
+        assert g["all_converged"], (z, g)
+        assert g["updated"] == (z >= 2)
+        assert g["J"] == h["J"]
+    # the settled points move by far less than the update's tolerance
+    s2, s3 = out["history"][1]["shifts"], out["history"][2]["shifts"]
+    assert np.all(np.abs(s3 / s2 - 1) < 1e-3)
 
 
 def test_next_iteration_solves_at_the_new_expansion_points(ctx):
@@ -160,8 +150,9 @@ def test_next_iteration_solves_at_the_new_expansion_points(ctx):
     pen, f, cp = system()
     set_pencil(ctx, pen)
     precs = ctx.spai_build_many(SHIFTS)
-    g = gpu_iteration(ctx, pen, f, cp, SHIFTS, RMAX, precs)
-    new = [float(s) for s in g["next"]]
+    g = ctx.reduce(to_dev(f, torch.float64), to_dev(cp, torch.float64), SHIFTS, r_max=RMAX,
+                   max_outer=1, tol=1e-12)
+    new = [float(s) for s in g["next_shifts"]]
     assert all(0 < s < SHIFTS[0] for s in new)
     fresh = ctx.spai_build_many(new)
     fd = to_dev(f, torch.float64)
