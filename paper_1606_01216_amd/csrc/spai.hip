@@ -832,6 +832,8 @@ struct UpdMany {
   int32_t* skip[kManyMax];            // each new factor's skipped-column count
   double* obj[kManyMax];              // each new factor's objective
   int8_t* skipf[kManyMax];            // each new factor's skipped-column flags
+  double* v64[kManyMax];              // each new factor's values (build from K^2)
+  float* v32[kManyMax];
 };
 
 // dinv of every shift of the batch: [count][n_pad]; the diagonal is read once.
@@ -928,6 +930,279 @@ __host__ __device__ inline size_t spai_build_many_lds(int bw) {
   const size_t S = 256 + 4 * (size_t)bw;
   return S * (MJ * (3 * sizeof(double) + sizeof(int32_t)) + sizeof(int32_t)) +
          sizeof(double) * (S + 2 * (size_t)bw);
+}
+
+// ---------------------------------------------------------------------------
+// Batched build from the normal equations (equilibrated builds on pencils
+// whose rows are consecutive runs of columns in a narrow band, like the
+// beam's; Section 3.1 for every shift of the batch).
+//
+// Column j's problem min || e_j - Khat(I, J) p || has the normal equations
+//     G p = g,  G = Khat(I, J)^T Khat(I, J) = (Khat^2)(J, J),  g = Khat(J, j),
+// because the columns J of Khat vanish outside the rows I, and Khat is
+// symmetric.  So the Gram matrix of every column is a block of one banded
+// matrix, Khat^2, whose entries are formed once per shift and shared by the
+// columns around them; a column then needs a 6 x 6 Cholesky and two
+// triangular solves instead of a Givens rotation per row of its problem.
+// Its residual norm follows from the objective's exact quadratic form,
+// ||e_j - B p||^2 = 1 - 2 g^T p + p^T G p, which is off the minimum only to
+// second order in the error of p.  Normal equations square the local
+// condition number; after equilibration (which this path requires) it is
+// below about 250 on every workload here, and a column whose Cholesky
+// loses more than 8 digits (a pivot below 1e-8 of its diagonal) is solved
+// by Givens rotations over its rows instead.
+//
+// Every wavefront works alone (no block barriers): it solves 64 consecutive
+// columns and writes the final factor, P = S (Phat + Phat^T) / 2 S (or
+// S Phat S), of the 64 - 2 bw rows whose averages those columns cover, in
+// float64 and float32, with the coefficients kept in its LDS.
+constexpr int kGramWave = 64;
+
+// Per-wavefront LDS of k_spai_gram_wave: window rows [o0 - 3 bw, o0 + 64 +
+// 2 bw): their scaled values (MJ each), columns and lengths, the diagonal
+// scaling of those rows +- bw, and the upper band of Khat^2 (2 bw + 1
+// entries for rows [o0 - 2 bw, o0 + 64)), which then holds the columns'
+// coefficients.
+template <int MJ>
+__host__ __device__ inline size_t spai_gram_wave_lds(int bw) {
+  const size_t wr = kGramWave + 5 * (size_t)bw;
+  const size_t band = (kGramWave + 2 * (size_t)bw) * (2 * (size_t)bw + 1);
+  const size_t hatw = (size_t)kGramWave * MJ;
+  return wr * (MJ * (sizeof(double) + sizeof(int32_t)) + sizeof(int32_t)) +
+         sizeof(double) * (wr + 2 * (size_t)bw) + sizeof(double) * (band > hatw ? band : hatw);
+}
+
+template <int MJ>
+__global__ void __launch_bounds__(256) k_spai_gram_wave(PencilDev pd, UpdMany U,
+                                                        const double* __restrict__ dinv,
+                                                        int64_t n_pad, int bw, int sym,
+                                                        size_t wave_lds) {
+  extern __shared__ double lds_all[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int out = kGramWave - 2 * bw;             // rows finished per wavefront
+  const int WR = kGramWave + 5 * bw;              // window rows
+  const int BW2 = 2 * bw + 1;
+  const int R2 = kGramWave + 2 * bw;              // rows of the Khat^2 band
+  double* vn = reinterpret_cast<double*>(reinterpret_cast<char*>(lds_all) + wv * wave_lds);
+  double* dl = vn + MJ * WR;                      // rows [w0 - bw, w0 + WR + bw)
+  double* k2 = dl + WR + 2 * bw;
+  const int K2N = R2 * BW2 > kGramWave * MJ ? R2 * BW2 : kGramWave * MJ;
+  int32_t* cl = reinterpret_cast<int32_t*>(k2 + K2N);
+  int32_t* ln = cl + MJ * WR;
+  const int64_t n = pd.n;
+  const int64_t o0 = ((int64_t)blockIdx.x * 4 + wv) * out;  // first output row
+  if (o0 >= n_pad) return;                                  // whole wavefront
+  const int64_t c0 = o0 - bw;                               // first solved column
+  const int64_t w0 = o0 - 3 * bw;                           // first window row
+  const int64_t k0 = o0 - 2 * bw;                           // first Khat^2 row
+  for (int r = lane; r < WR; r += 64) {
+    const int64_t row = w0 + r;
+    const bool in = row >= 0 && row < n;
+    const int len = in ? pd.row_len[row] : 0;
+    ln[r] = len;
+    const int32_t base = in ? pd.slice_ptr[row / kSlice] + (int32_t)(row % kSlice) : 0;
+#pragma unroll
+    for (int k = 0; k < MJ; ++k) cl[k * WR + r] = k < len ? pd.col[base + k * kSlice] : -1;
+  }
+  const int64_t j = c0 + lane;  // this lane's column
+  const bool jin = j >= 0 && j < n;
+  const int jr = (int)(j - w0);
+  for (int s = 0; s < U.count; ++s) {
+    const double* __restrict__ dv = dinv + (int64_t)s * n_pad;
+    __builtin_amdgcn_wave_barrier();
+    for (int r = lane; r < WR + 2 * bw; r += 64) {
+      const int64_t row = w0 - bw + r;
+      dl[r] = (row >= 0 && row < n) ? dv[row] : 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // scaled values Khat(r, c) = S_r K(s)_rc S_c of the window rows
+    for (int r = lane; r < WR; r += 64) {
+      const int64_t row = w0 + r;
+      const int len = ln[r];
+      const int32_t base = len > 0 ? pd.slice_ptr[row / kSlice] + (int32_t)(row % kSlice) : 0;
+      const double sr = dl[r + bw];
+#pragma unroll
+      for (int k = 0; k < MJ; ++k) {
+        double v = 0.0;
+        if (k < len) {
+          const int32_t idx = base + k * kSlice;
+          const int32_t c = cl[k * WR + r];
+          v = fma(U.a[s], pd.m64[idx], U.b[s] * pd.k64[idx]) * sr * dl[(int)(c - w0) + bw];
+        }
+        vn[k * WR + r] = v;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // upper band of Khat^2, one (row, offset) pair per lane and pass:
+    // Khat^2(i, i + d) = sum over k of Khat(i, k) Khat(i + d, k)
+    for (int e = lane; e < R2 * BW2; e += 64) {
+      const int q = e / BW2, d = e - q * BW2;
+      const int ir = (int)(k0 - w0) + q;  // window index of row i
+      const int cr = ir + d;              // window index of row i + d
+      double acc = 0.0;
+      if (cr < WR) {
+        const int li = ln[ir], lc = ln[cr];
+        if (li > 0 && lc > 0) {
+          const int i0 = cl[ir], cf = cl[cr];
+          const int lo = i0 > cf ? i0 : cf;
+          const int hi = (i0 + li < cf + lc) ? i0 + li : cf + lc;
+          for (int k = lo; k < hi; ++k) acc = fma(vn[(k - i0) * WR + ir], vn[(k - cf) * WR + cr], acc);
+        }
+      }
+      k2[e] = acc;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // column j: Cholesky G = U^T U of G = Khat^2(J, J), g = Khat(J, j)
+    double p[MJ];
+#pragma unroll
+    for (int u = 0; u < MJ; ++u) p[u] = 0.0;
+    double res2 = 0.0;
+    const int nj = jin ? ln[jr] : 0;
+    if (nj > 0) {
+      const int J0 = cl[jr];  // J = J0, J0 + 1, ..., J0 + nj - 1
+      double Uf[MJ * (MJ + 1) / 2], iu[MJ], y[MJ], g[MJ];
+      bool good = true;
+#pragma unroll
+      for (int k = 0; k < MJ; ++k) {
+        y[k] = 0.0;
+        iu[k] = 0.0;
+        g[k] = 0.0;
+        if (k < nj) {
+          const double* gk = k2 + (J0 + k - (int)k0) * BW2;   // Khat^2(J_k, J_k + d)
+          g[k] = vn[k * WR + jr];                             // Khat(j, J_k)
+          double dkk = gk[0];
+#pragma unroll
+          for (int m = 0; m < MJ; ++m)
+            if (m < k) dkk = fma(-Uf[tri<MJ>(m, k)], Uf[tri<MJ>(m, k)], dkk);
+          good = good && dkk > 1e-8 * gk[0];
+          const double inv = dkk > 0.0 ? rsqrt_newton(dkk) : 0.0;
+          iu[k] = inv;
+          Uf[tri<MJ>(k, k)] = dkk * inv;
+#pragma unroll
+          for (int i = 0; i < MJ; ++i) {
+            if (i > k && i < nj) {
+              double gik = gk[i - k];
+#pragma unroll
+              for (int m = 0; m < MJ; ++m)
+                if (m < k) gik = fma(-Uf[tri<MJ>(m, i)], Uf[tri<MJ>(m, k)], gik);
+              Uf[tri<MJ>(k, i)] = gik * inv;
+            }
+          }
+          double yk = g[k];
+#pragma unroll
+          for (int m = 0; m < MJ; ++m)
+            if (m < k) yk = fma(-Uf[tri<MJ>(m, k)], y[m], yk);
+          y[k] = yk * inv;
+        }
+      }
+      if (good) {
+#pragma unroll
+        for (int k = MJ - 1; k >= 0; --k) {
+          if (k < nj) {
+            double acc = y[k];
+#pragma unroll
+            for (int i = 0; i < MJ; ++i)
+              if (i > k && i < nj) acc = fma(-Uf[tri<MJ>(k, i)], p[i], acc);
+            p[k] = acc * iu[k];
+          }
+        }
+        // ||e_j - B p||^2 = 1 - 2 g^T p + p^T G p, G from the band of Khat^2
+        double gp = 0.0, pgp = 0.0;
+#pragma unroll
+        for (int k = 0; k < MJ; ++k) {
+          if (k < nj) {
+            const double* gk = k2 + (J0 + k - (int)k0) * BW2;
+            gp = fma(g[k], p[k], gp);
+            double row = gk[0] * p[k];
+#pragma unroll
+            for (int i = 0; i < MJ; ++i)
+              if (i > k && i < nj) row = fma(2.0 * gk[i - k], p[i], row);
+            pgp = fma(p[k], row, pgp);
+          }
+        }
+        res2 = fma(-2.0, gp, 1.0) + pgp;
+        res2 = res2 > 0.0 ? res2 : 0.0;
+      } else {
+        // Givens rotations over the rows I (the span of the patterns of J)
+        int lo = (int)j, hi = (int)j;
+#pragma unroll
+        for (int u = 0; u < MJ; ++u) {
+          if (u < nj) {
+            const int kr = J0 + u - (int)w0;
+            const int first = cl[kr], last = cl[(ln[kr] - 1) * WR + kr];
+            lo = first < lo ? first : lo;
+            hi = last > hi ? last : hi;
+          }
+        }
+        double R[MJ * (MJ + 1) / 2];
+        double qtb[MJ];
+#pragma unroll
+        for (int q = 0; q < MJ * (MJ + 1) / 2; ++q) R[q] = 0.0;
+#pragma unroll
+        for (int q = 0; q < MJ; ++q) qtb[q] = 0.0;
+        for (int i = lo; i <= hi; ++i) {
+          const int ir = (int)(i - w0);
+          const int i0 = cl[ir], li = ln[ir];
+          double v[MJ];
+#pragma unroll
+          for (int u = 0; u < MJ; ++u) {
+            const int q = J0 + u - i0;
+            const bool ok = u < nj && q >= 0 && q < li;
+            const double val = vn[(ok ? q : 0) * WR + ir];
+            v[u] = ok ? val : 0.0;
+          }
+          double rhs = i == (int)j ? 1.0 : 0.0;
+          givens_row<MJ>(R, qtb, v, rhs, nj);
+          res2 = fma(rhs, rhs, res2);
+        }
+#pragma unroll
+        for (int q = MJ - 1; q >= 0; --q) {
+          if (q < nj) {
+            double acc = qtb[q];
+#pragma unroll
+            for (int u = q + 1; u < MJ; ++u)
+              if (u < nj) acc = fma(-R[tri<MJ>(q, u)], p[u], acc);
+            const double d = R[tri<MJ>(q, q)];
+            p[q] = d != 0.0 ? acc / d : 0.0;
+          }
+        }
+      }
+      if (lane >= bw && lane < bw + out) U.obj[s][j] = sqrt(res2);
+    }
+    __builtin_amdgcn_wave_barrier();  // every lane has read the band
+    // coefficient u of column c0 + lane (row J0 + u of Phat)
+#pragma unroll
+    for (int u = 0; u < MJ; ++u) k2[lane * MJ + u] = p[u];
+    __builtin_amdgcn_wave_barrier();
+    // the final factor for rows [o0, o0 + out): P(r, c) = S_r Pbar(r, c) S_c
+    const int64_t r = o0 + (lane - bw);
+    if (lane >= bw && lane < bw + out && r < n_pad) {
+      const int64_t sl = r / kSlice;
+      const int32_t base = pd.slice_ptr[sl] + (int32_t)(r % kSlice);
+      const int w = (pd.slice_ptr[sl + 1] - pd.slice_ptr[sl]) / kSlice;
+      const int rr = (int)(r - w0);
+      const int len = r < n ? ln[rr] : 0;
+      const double sr = r < n ? dl[rr + bw] : 0.0;
+      const int r0 = len > 0 ? cl[rr] : 0;
+      double* __restrict__ o64 = U.v64[s];
+      float* __restrict__ o32 = U.v32[s];
+      for (int k = 0; k < w; ++k) {
+        double val = 0.0;
+        if (k < len) {
+          const int c = r0 + k;
+          const int cr = (int)(c - w0);
+          const int cf = cl[cr];
+          double h = k2[(int)(c - c0) * MJ + (int)(r - cf)];  // column c at row r
+          if (sym) h = 0.5 * (h + k2[lane * MJ + k]);         // column r at row c
+          val = h * sr * dl[cr + bw];
+        }
+        const int32_t idx = base + k * kSlice;
+        o64[idx] = val;
+        o32[idx] = (float)val;
+      }
+    }
+  }
 }
 
 // The banded build column kernel for every shift of the batch (Section 3.1
@@ -1455,6 +1730,19 @@ static airga_status run_update(airga_ctx ctx, airga_prec old, double s_new,
 // otherwise one after the other.
 // Several builds at once (banded pencils whose staged rows fit in LDS);
 // otherwise one after the other.  Each factor equals its single build.
+// Builds from the Gram matrices of Khat^2 (k_spai_gram_wave): the staged
+// batched path on a pencil whose rows are consecutive columns in a narrow
+// band (bandwidth at most 8 for rows of 6 entries, like the beam's).
+static bool spai_gram_path(const Pencil& pen, const airga_spai_opts& o) {
+  const int bw = pen.bandwidth;
+  // only the equilibrated problems: without the diagonal scaling the local
+  // problems mix rows and columns of very different sizes, and squaring their
+  // condition number costs digits the pivot test does not see
+  return o.equilibrate && spai_banded(pen, o, false) && pen.max_len <= 6 && pen.contiguous &&
+         4 * bw + 1 <= pen.max_len * pen.max_len && 2 * bw < kGramWave / 4 &&
+         4 * spai_gram_wave_lds<6>(bw) <= 64 * 1024;
+}
+
 static airga_status run_build_many(airga_ctx ctx, int32_t count, const double* shifts,
                                    const airga_spai_opts& o, airga_prec* ps) {
   const Pencil& pen = ctx->pen;
@@ -1472,6 +1760,13 @@ static airga_status run_build_many(airga_ctx ctx, int32_t count, const double* s
   const int bw = pen.bandwidth;
   const bool range = 4 * bw + 1 <= pen.max_len * pen.max_len;
   const size_t lds = spai_build_many_lds<6>(bw);
+  // rows of consecutive columns in a narrow band: Gram matrices from Khat^2
+  // with the finalize fused in
+  const bool gram = spai_gram_path(pen, o);
+  // wavefronts of kGramWave - 2 bw output rows, four per block, cover every
+  // padded row (padding rows of a factor hold zeros)
+  const unsigned ng = blocks_for(n_pad, 4 * (kGramWave - 2 * bw));
+  const size_t wave_lds = (spai_gram_wave_lds<6>(bw) + 15) & ~(size_t)15;
   for (int i0 = 0; i0 < count; i0 += kManyMax) {
     const int cnt = count - i0 < kManyMax ? count - i0 : kManyMax;
     // scratch: [dinv (cnt n_pad) | hat (cnt stored)]
@@ -1487,7 +1782,15 @@ static airga_status run_build_many(airga_ctx ctx, int32_t count, const double* s
     }
     k_dinv_many<<<nr, 256, 0, st>>>(pd, U, o.equilibrate, n_pad, dinv);
     AIRGA_HIP(hipGetLastError());
-    if (range && pen.contiguous)
+    if (gram) {
+      for (int i = 0; i < cnt; ++i) {
+        U.v64[i] = ps[i0 + i]->v64.as<double>();
+        U.v32[i] = ps[i0 + i]->v32.as<float>();
+      }
+      k_spai_gram_wave<6><<<ng, 256, 4 * wave_lds, st>>>(pd, U, dinv, n_pad, bw,
+                                                          o.symmetrize ? 1 : 0, wave_lds);
+      AIRGA_HIP(hipGetLastError());
+    } else if (range && pen.contiguous)
       k_spai_build_many<6, 2><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, hat);
     else if (range)
       k_spai_build_many<6, 1><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, hat);
@@ -1496,10 +1799,13 @@ static airga_status run_build_many(airga_ctx ctx, int32_t count, const double* s
     AIRGA_HIP(hipGetLastError());
     for (int i = 0; i < cnt; ++i) {
       const airga_prec p = ps[i0 + i];
-      k_spai_finalize<<<nr, 256, 0, st>>>(pd, hat + (size_t)i * stored, dinv + (size_t)i * n_pad,
-                                          o.symmetrize ? 1 : 0, nullptr, nullptr, nullptr,
-                                          p->v64.as<double>(), p->v32.as<float>());
-      AIRGA_HIP(hipGetLastError());
+      if (!gram) {
+        k_spai_finalize<<<nr, 256, 0, st>>>(pd, hat + (size_t)i * stored,
+                                            dinv + (size_t)i * n_pad, o.symmetrize ? 1 : 0,
+                                            nullptr, nullptr, nullptr, p->v64.as<double>(),
+                                            p->v32.as<float>());
+        AIRGA_HIP(hipGetLastError());
+      }
       // Alg. 2's starting scaling trace(K) / trace(K K^T), from the Gram scalars
       const double a = U.a[i], b = U.b[i];
       const double nn = a * a * pen.gram_mm + 2 * a * b * pen.gram_mk + b * b * pen.gram_kk;
@@ -1679,7 +1985,10 @@ airga_status airga_spai_build(airga_ctx ctx, double s, const airga_spai_opts* op
   if (!(o.tol >= 0)) return fail(AIRGA_EINVAL, "tolerance must be >= 0");
   airga_prec p = nullptr;
   AIRGA_TRY(new_prec(ctx, s, &p));
-  airga_status st = run_build(ctx, s, o, p);
+  // the Gram-matrix kernel of the batched builds serves single builds too,
+  // so a factor does not depend on the batch it was built in
+  airga_status st = spai_gram_path(ctx->pen, o) ? run_build_many(ctx, 1, &s, o, &p)
+                                                : run_build(ctx, s, o, p);
   if (st != AIRGA_OK) {
     airga_prec_release(p);
     return st;

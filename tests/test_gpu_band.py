@@ -30,13 +30,20 @@ def pencils():
             "grid64": grid_pencil(64, 23, seed=1), "grid65": grid_pencil(65, 9, seed=2)}
 
 
-def _same(a, b, exact):
+def _same(a, b, exact, tol=1e-13):
     """Bit-equal when the staged kernel folds rows in the general kernel's
     order; otherwise (narrow bands fold the row span in ascending order)
     equal up to rounding."""
     if exact:
         return np.array_equal(a, b)
-    return np.all(np.abs(a - b) <= 1e-13 * max(np.abs(b).max(), 1e-300))
+    return np.all(np.abs(a - b) <= tol * max(np.abs(b).max(), 1e-300))
+
+
+# Equilibrated builds on the beam solve each column from its normal equations
+# (Gram matrices taken from Khat^2) where the general kernels rotate row by row:
+# the two agree to cond(Khat(I, J))^2 eps, with cond below 60 on this beam
+# after equilibration (about 8e-13).
+GRAM_TOL = 1e-11
 
 
 @pytest.mark.parametrize("name", ["beam", "grid64", "grid65"])
@@ -49,7 +56,8 @@ def test_spai_staged_equals_general(ctx, name):
         g = ctx.spai_build(s, equilibrate=eq, symmetrize=sym, general_only=True)
         va, oa = (t.cpu().numpy() for t in a.export())
         vg, og = (t.cpu().numpy() for t in g.export())
-        assert _same(va, vg, exact) and _same(oa, og, exact), (name, s)
+        btol = GRAM_TOL if (name == "beam" and eq) else 1e-13
+        assert _same(va, vg, exact, btol) and _same(oa, og, exact, btol), (name, s)
         # updates from the same old factor: some columns skipped, some solved
         for s_new, tol in ((s * 1.001, 0.01), (s * 1.3, 0.01), (s * 1.05, 0.0)):
             qa = ctx.spai_update(a, s_new, tol=tol)
