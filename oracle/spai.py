@@ -47,6 +47,18 @@ the residual then lives on the rows I, so the iteration runs on the column's
 local block exactly.  It is capped at mr_iters steps, because on a fixed
 pattern the residual may never reach tol.  The build's alpha is
 trace(Khat) / trace(Khat Khat^T) of the matrix whose inverse is sought.
+
+Pattern control (lfil > 0, minimal-residual mode only): the sparsity-pattern
+step that the paper leaves out of Algorithms 2 and 4 (and says can be added)
+is the one of Chow and Saad's minimal-residual iteration: the direction takes
+the entries of t = alpha r on the current pattern of p_j, and while that
+pattern holds fewer than lfil entries it also admits the largest remaining
+entry of t in absolute value.  Readings: the pattern starts as {j} (the start
+alpha e_j); the remaining entries are those of J outside the current pattern,
+so p_j stays on the structural pattern of K(s) and the factor keeps its
+layout; entries within a relative PICK_TIE of the largest count as equal and
+the lowest row wins, so that rounding at the level of eps never decides the
+pattern; an entry that is exactly zero is never admitted.
 """
 from __future__ import annotations
 
@@ -71,6 +83,9 @@ class Factor:
     margin: np.ndarray = None  # closest approach of ||r|| / (tol ||t||) to 1 over
                                # the column's tolerance tests (update: the skip
                                # test; minimal-residual mode: every test)
+    pick_margin: np.ndarray = None  # pattern control: per column, the smallest
+                                    # distance of a pattern decision from its
+                                    # tie threshold
 
     def matrix(self) -> sp.csr_matrix:
         n, rp, ci = self.pattern
@@ -124,7 +139,29 @@ def _scaled_values(a_val, rows, cols, s_row, s_col):
     return a_val * s_row[rows] * s_col[cols]
 
 
-def _mr_column(blk, rhs, jpos, p, alpha, tol, mr_iters):
+PICK_TIE = 1e-10
+
+
+def _pick_entry(tv, inside, tie=PICK_TIE):
+    """Pattern control: the position of the largest |tv| outside the
+    current pattern (`inside`), ties within a relative `tie` going to the
+    lowest position; None when every remaining entry is zero.  Also returns
+    how far the decision is from flipping: the smallest distance of any
+    remaining |tv_u| / max from the tie threshold 1 - tie (1.0 when there
+    is nothing to compare)."""
+    cand = np.flatnonzero(~inside)
+    if len(cand) == 0:
+        return None, 1.0
+    mag = np.abs(tv[cand])
+    top = mag.max()
+    if not top > 0:
+        return None, 1.0
+    ratio = mag / top
+    pick = cand[np.flatnonzero(ratio >= 1.0 - tie)[0]]
+    return int(pick), float(np.min(np.abs(ratio - (1.0 - tie))))
+
+
+def _mr_column(blk, rhs, jpos, p, alpha, tol, mr_iters, lfil=0, jself=None):
     """The paper's iterative column solve (Algorithms 2 and 4, readings I1-I3)
     on one column's local problem, minimise f(p) = ||t - B p||^2 with
     B = blk = Khat(I, J) and t = rhs = t(I), from the start p on J.
@@ -136,11 +173,22 @@ def _mr_column(blk, rhs, jpos, p, alpha, tol, mr_iters):
     a = <t - B p, B d> / ||B d||^2.  The residual is formed from its
     definition at every step.  The loop stops once ||t - B p|| <= tol ||t||,
     after mr_iters steps, or when B d = 0 (no descent left along d).
-    Returns (p, ||t - B p||, steps, margin), margin = the closest approach
-    of ||t - B p|| / (tol ||t||) to 1 over the stopping tests taken."""
+    With lfil > 0 the direction is confined to the current pattern of p,
+    which starts as {jself} (the position of j in J) and admits the largest
+    remaining entry of alpha r|_J at each step while it holds fewer than
+    lfil entries (pattern control, see the module notes).
+    Returns (p, ||t - B p||, steps, margin, pick_margin), margin = the
+    closest approach of ||t - B p|| / (tol ||t||) to 1 over the stopping
+    tests taken, pick_margin = the smallest distance of a pattern decision
+    from its tie threshold (inf without pattern control)."""
     thr = tol * np.linalg.norm(rhs)
     margin = np.inf
+    pick_margin = np.inf
     steps = 0
+    inside = None
+    if lfil > 0:
+        inside = np.zeros(len(jpos), bool)
+        inside[jself] = True
     while True:
         res = rhs - blk @ p
         nres = np.linalg.norm(res)
@@ -149,17 +197,24 @@ def _mr_column(blk, rhs, jpos, p, alpha, tol, mr_iters):
         if nres <= thr or steps >= mr_iters:
             break
         d = alpha * res[jpos]
+        if inside is not None:
+            if inside.sum() < lfil:
+                u, pm = _pick_entry(d, inside)
+                pick_margin = min(pick_margin, pm)
+                if u is not None:
+                    inside[u] = True
+            d = np.where(inside, d, 0.0)
         bd = blk @ d
         curv = bd @ bd
         if not curv > 0:
             break
         p = p + ((res @ bd) / curv) * d
         steps += 1
-    return p, float(np.linalg.norm(rhs - blk @ p)), steps, margin
+    return p, float(np.linalg.norm(rhs - blk @ p)), steps, margin, pick_margin
 
 
 def spai_build(a: sp.csr_matrix, *, equilibrate=True, symmetrize=True, cols=None,
-               mr_iters=0, tol=0.01) -> Factor:
+               mr_iters=0, tol=0.01, lfil=0) -> Factor:
     """SPAI of K(s) on its own structural pattern (eq. (3.1)).
 
     K(s) may be complex (a complex expansion point): the column problems are
@@ -172,8 +227,11 @@ def spai_build(a: sp.csr_matrix, *, equilibrate=True, symmetrize=True, cols=None
     ``cols`` restricts the computation to a subset of columns (sampled checks
     at large n); the returned values are then only meaningful for those.
     ``mr_iters`` > 0 selects the minimal-residual loop of Algorithm 2 with
-    stopping tolerance ``tol`` instead of the exact column solves.
+    stopping tolerance ``tol`` instead of the exact column solves, and
+    ``lfil`` > 0 adds its pattern control (at most lfil entries per column).
     """
+    if lfil < 0 or (lfil > 0 and mr_iters <= 0):
+        raise ValueError("lfil applies to the minimal-residual mode")
     n = a.shape[0]
     rp, ci = a.indptr, a.indices
     rows = _rows_of(rp, n)
@@ -186,6 +244,7 @@ def spai_build(a: sp.csr_matrix, *, equilibrate=True, symmetrize=True, cols=None
     obj = np.full(n, np.nan)
     iters = np.zeros(n, np.int64)
     margin = np.full(n, np.inf)
+    pick = np.full(n, np.inf)
     todo = np.arange(n) if cols is None else np.asarray(cols)
     cplx = np.iscomplexobj(khat)
     if cplx:
@@ -200,8 +259,9 @@ def spai_build(a: sp.csr_matrix, *, equilibrate=True, symmetrize=True, cols=None
         rhs = (ii == j).astype(np.float64)
         if mr_iters > 0:
             p0 = alpha_hat * (jj == j).astype(np.float64)
-            p, obj[j], iters[j], margin[j] = _mr_column(blk, rhs, np.searchsorted(ii, jj), p0,
-                                                        alpha_hat, tol, mr_iters)
+            p, obj[j], iters[j], margin[j], pick[j] = _mr_column(
+                blk, rhs, np.searchsorted(ii, jj), p0, alpha_hat, tol, mr_iters, lfil,
+                int(np.flatnonzero(jj == j)[0]))
         else:
             p, *_ = np.linalg.lstsq(blk, rhs, rcond=None)
             obj[j] = np.linalg.norm(rhs - blk @ p)
@@ -222,7 +282,8 @@ def spai_build(a: sp.csr_matrix, *, equilibrate=True, symmetrize=True, cols=None
                                                      (a @ a.T).diagonal().sum())
     return Factor(values=values, hat=hat, objective=obj, skipped=np.zeros(n, bool),
                   alpha=alpha, cols=todo, pattern=(n, rp, ci),
-                  iters=iters if mr_iters > 0 else None, margin=margin if mr_iters > 0 else None)
+                  iters=iters if mr_iters > 0 else None, margin=margin if mr_iters > 0 else None,
+                  pick_margin=pick if lfil > 0 else None)
 
 
 def update_alpha(k_old: sp.csr_matrix, k_new: sp.csr_matrix) -> float:
@@ -232,9 +293,12 @@ def update_alpha(k_old: sp.csr_matrix, k_new: sp.csr_matrix) -> float:
 
 
 def spai_update(a_old: sp.csr_matrix, a_new: sp.csr_matrix, *, tol=0.01, equilibrate=True,
-                cols=None, mr_iters=0) -> Factor:
+                cols=None, mr_iters=0, lfil=0) -> Factor:
     """Q with K_new Q ~ K_old (Section 3.2), on the structural pattern;
-    ``mr_iters`` > 0 selects the minimal-residual loop of Algorithm 4."""
+    ``mr_iters`` > 0 selects the minimal-residual loop of Algorithm 4, and
+    ``lfil`` > 0 its pattern control."""
+    if lfil < 0 or (lfil > 0 and mr_iters <= 0):
+        raise ValueError("lfil applies to the minimal-residual mode")
     n = a_new.shape[0]
     rp, ci = a_new.indptr, a_new.indices
     if not (np.array_equal(a_old.indptr, rp) and np.array_equal(a_old.indices, ci)):
@@ -255,6 +319,7 @@ def spai_update(a_old: sp.csr_matrix, a_new: sp.csr_matrix, *, tol=0.01, equilib
     skipped = np.zeros(n, bool)
     iters = np.zeros(n, np.int64)
     margin = np.full(n, np.inf)
+    pick = np.full(n, np.inf)
     todo = np.arange(n) if cols is None else np.asarray(cols)
     for j in todo:
         sl = slice(indptr[j], indptr[j + 1])
@@ -275,7 +340,9 @@ def spai_update(a_old: sp.csr_matrix, a_new: sp.csr_matrix, *, tol=0.01, equilib
             rhs[jpos] = kold_j
             if mr_iters > 0:
                 q0 = alpha * (jj == j).astype(np.float64)
-                q, obj[j], iters[j], m2 = _mr_column(blk, rhs, jpos, q0, alpha, tol, mr_iters)
+                q, obj[j], iters[j], m2, pick[j] = _mr_column(
+                    blk, rhs, jpos, q0, alpha, tol, mr_iters, lfil,
+                    int(np.flatnonzero(jj == j)[0]))
                 margin[j] = min(margin[j], m2)
             else:
                 q, *_ = np.linalg.lstsq(blk, rhs, rcond=None)
@@ -285,7 +352,8 @@ def spai_update(a_old: sp.csr_matrix, a_new: sp.csr_matrix, *, tol=0.01, equilib
     values = hat * s[rows] / s[ci]
     return Factor(values=values, hat=hat, objective=obj, skipped=skipped, alpha=alpha,
                   cols=todo, pattern=(n, rp, ci),
-                  iters=iters if mr_iters > 0 else None, margin=margin)
+                  iters=iters if mr_iters > 0 else None, margin=margin,
+                  pick_margin=pick if lfil > 0 else None)
 
 
 def chain_apply(factors, r: np.ndarray) -> np.ndarray:

@@ -629,6 +629,82 @@ def test_spai_mr_update_skips_exactly_the_exact_mode_skips():
     assert np.all(mr.objective[solved] >= ex.objective[solved] * (1 - 1e-12))
 
 
+# ------------------------------- SPAI minimal-residual pattern control (lfil)
+
+def test_spai_lfil_one_entry_is_the_one_dimensional_least_squares():
+    # lfil = 1 keeps p_j = c e_j: the line search along e_j reaches the
+    # minimiser of ||e_j - c k_j|| in its first step, c = k_jj / ||k_j||^2,
+    # and later steps leave it there
+    p = small_pencil(12)
+    a = pencil.shifted_operator(p, 5.0)
+    k = a.toarray()
+    f = spai.spai_build(a, equilibrate=False, symmetrize=False, mr_iters=7, tol=0.0, lfil=1)
+    got = f.matrix().toarray()
+    c = np.diag(k) / np.sum(k * k, axis=0)
+    assert np.allclose(np.diag(got), c, rtol=1e-13, atol=0)
+    assert np.count_nonzero(got - np.diag(np.diag(got))) == 0
+
+
+def test_spai_lfil_admits_the_largest_remaining_entry():
+    # K = I + c e_j^T + e_j c^T with the entries of c of distinct sizes: from
+    # p = alpha e_j, r = e_j - alpha (e_j + c + c_j e_j) is -alpha c off j,
+    # so the first step with lfil = 2 must admit the row of the largest |c_i|
+    # and nothing else; lfil = 3 admits the two largest after two steps
+    n, j = 7, 3
+    cvec = np.array([0.05, -0.31, 0.12, 0.0, 0.27, -0.08, 0.2])
+    k = np.eye(n)
+    k[:, j] += cvec
+    k[j, :] += cvec
+    a = sp.csr_matrix(k)
+    f1 = spai.spai_build(a, equilibrate=False, symmetrize=False, mr_iters=1, tol=0.0, lfil=2)
+    col = f1.matrix().toarray()[:, j]
+    assert set(np.flatnonzero(col)) == {j, 1}
+    f2 = spai.spai_build(a, equilibrate=False, symmetrize=False, mr_iters=2, tol=0.0, lfil=3)
+    col = f2.matrix().toarray()[:, j]
+    assert set(np.flatnonzero(col)) <= {j, 1, 4} and col[1] != 0 and col[j] != 0
+    # the cap: no column ever holds more than lfil entries
+    f9 = spai.spai_build(a, equilibrate=False, symmetrize=False, mr_iters=50, tol=0.0, lfil=3)
+    assert np.all(np.count_nonzero(f9.matrix().toarray(), axis=0) <= 3)
+
+
+def test_spai_lfil_grown_to_a_full_pattern_converges_to_the_inverse():
+    # on a dense SPD matrix with lfil = n the pattern reaches every row after
+    # n - 1 steps; from then on d = alpha r is the plain minimal-residual
+    # iteration for K p = e_j, which converges to the inverse
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal((6, 6))
+    k = b @ b.T + 6 * np.eye(6)
+    a = sp.csr_matrix(k)
+    f = spai.spai_build(a, equilibrate=False, symmetrize=False, mr_iters=4000, tol=1e-13,
+                        lfil=6)
+    assert np.allclose(f.matrix().toarray(), np.linalg.inv(k), atol=1e-11)
+    # with a smaller cap the columns stay sparser than the inverse
+    g = spai.spai_build(a, equilibrate=False, symmetrize=False, mr_iters=4000, tol=1e-13,
+                        lfil=4)
+    assert np.all(np.count_nonzero(g.matrix().toarray(), axis=0) == 4)
+
+
+def test_spai_lfil_residuals_fall_and_patterns_stay_within_the_cap():
+    p = small_pencil(30)
+    a = pencil.shifted_operator(p, 12.0)
+    prev = None
+    for it in (1, 2, 3, 5, 9):
+        f = spai.spai_build(a, symmetrize=False, mr_iters=it, tol=0.0, lfil=3)
+        if prev is not None:
+            assert np.all(f.objective <= prev * (1 + 1e-12))
+        prev = f.objective
+        # after `it` steps a column holds at most min(1 + it, 3) entries
+        nnz = np.count_nonzero(f.matrix().toarray(), axis=0)
+        assert np.all(nnz <= min(1 + it, 3))
+    # the update: Q's columns obey the same cap; the skipped ones stay alpha e_j
+    a_new = pencil.shifted_operator(p, 15.0)
+    q = spai.spai_update(a, a_new, tol=0.01, mr_iters=9, lfil=2)
+    nnz = np.count_nonzero(q.matrix().toarray(), axis=0)
+    assert np.all(nnz <= 2) and np.all(nnz[q.skipped] == 1)
+    with pytest.raises(ValueError):
+        spai.spai_build(a, lfil=2)
+
+
 # ------------------------------------------------- AIRGA's outer iteration
 
 from oracle import airga_loop  # noqa: E402
