@@ -56,9 +56,10 @@ pattern holds fewer than lfil entries it also admits the largest remaining
 entry of t in absolute value.  Readings: the pattern starts as {j} (the start
 alpha e_j); the remaining entries are those of J outside the current pattern,
 so p_j stays on the structural pattern of K(s) and the factor keeps its
-layout; entries within a relative PICK_TIE of the largest count as equal and
-the lowest row wins, so that rounding at the level of eps never decides the
-pattern; an entry that is exactly zero is never admitted.
+layout; entries within a relative PICK_TIE (1e-8) of the largest count as
+equal and the lowest row wins, so that rounding (two correct evaluations of
+a small entry of r can differ by far more than eps relative) never decides
+the pattern; an entry that is exactly zero is never admitted.
 """
 from __future__ import annotations
 
@@ -139,7 +140,7 @@ def _scaled_values(a_val, rows, cols, s_row, s_col):
     return a_val * s_row[rows] * s_col[cols]
 
 
-PICK_TIE = 1e-10
+PICK_TIE = 1e-8
 
 
 def _pick_entry(tv, inside, tie=PICK_TIE):
