@@ -157,6 +157,15 @@ typedef struct {
                           pattern of the column, a = (r, w) / (w, w) with
                           w = K d, until ||r|| <= tol ||t|| (t = e_j or
                           k_old_j), at most mr_iters steps (<= 100000).       */
+  int32_t lfil;        /* minimal-residual mode only: 0 (default) steps on the
+                          whole pattern of the column from the start; 1..8:
+                          pattern control (the sparsity step the paper leaves
+                          out of Algorithms 2 and 4): the column's pattern
+                          starts as {j} and each step first admits the entry
+                          of the pattern of column j of K(s) with the largest
+                          |alpha r| outside it, up to lfil entries (ties
+                          within a relative 1e-8 go to the lowest row).
+                          EINVAL outside [0, 8] or with mr_iters = 0.         */
 } airga_spai_opts;
 
 AIRGA_API void airga_spai_opts_default(airga_spai_opts* opts);

@@ -45,7 +45,7 @@ class PencilInfo(ctypes.Structure):
 class SpaiOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("equilibrate", ctypes.c_int32),
                 ("symmetrize", ctypes.c_int32), ("general_only", ctypes.c_int32),
-                ("mr_iters", ctypes.c_int32)]
+                ("mr_iters", ctypes.c_int32), ("lfil", ctypes.c_int32)]
 
 
 class PrecInfo(ctypes.Structure):
@@ -451,7 +451,7 @@ class Context:
 
     # ------------------------------------------------------- preconditioners
     @staticmethod
-    def _spai_opts(tol, equilibrate, symmetrize, general_only=False, mr_iters=0):
+    def _spai_opts(tol, equilibrate, symmetrize, general_only=False, mr_iters=0, lfil=0):
         o = SpaiOpts()
         lib().airga_spai_opts_default(ctypes.byref(o))
         if tol is not None:
@@ -460,14 +460,16 @@ class Context:
         o.symmetrize = int(bool(symmetrize))
         o.general_only = int(bool(general_only))
         o.mr_iters = int(mr_iters)
+        o.lfil = int(lfil)
         return o
 
     def spai_build(self, s: float, *, equilibrate=True, symmetrize=True,
-                   general_only=False, mr_iters=0, tol=None) -> "Prec":
+                   general_only=False, mr_iters=0, tol=None, lfil=0) -> "Prec":
         """SPAI of K(s); mr_iters > 0 selects the paper's minimal-residual
         column loop (stopping tolerance tol, default 0.01) instead of the exact
-        column solves."""
-        o = self._spai_opts(tol, equilibrate, symmetrize, general_only, mr_iters)
+        column solves, lfil > 0 its pattern control (at most lfil entries per
+        column)."""
+        o = self._spai_opts(tol, equilibrate, symmetrize, general_only, mr_iters, lfil)
         h = ctypes.c_void_p()
         self._enter()
         _check(lib().airga_spai_build(self._h, float(s), ctypes.byref(o), ctypes.byref(h)))
@@ -475,10 +477,10 @@ class Context:
         return Prec(self, h)
 
     def spai_build_many(self, shifts, *, equilibrate=True, symmetrize=True, general_only=False,
-                        mr_iters=0, tol=None) -> list:
+                        mr_iters=0, tol=None, lfil=0) -> list:
         """[SPAI of K(s) for s in shifts], each block's rows staged once per batch."""
         k = len(shifts)
-        o = self._spai_opts(tol, equilibrate, symmetrize, general_only, mr_iters)
+        o = self._spai_opts(tol, equilibrate, symmetrize, general_only, mr_iters, lfil)
         c_s = (ctypes.c_double * max(k, 1))(*[float(v) for v in shifts])
         c_out = (ctypes.c_void_p * max(k, 1))()
         self._enter()
@@ -487,8 +489,8 @@ class Context:
         return [Prec(self, ctypes.c_void_p(c_out[i])) for i in range(k)]
 
     def spai_update(self, old: "Prec", s_new: float, *, tol=0.01, equilibrate=True,
-                    general_only=False, mr_iters=0) -> "Prec":
-        o = self._spai_opts(tol, equilibrate, False, general_only, mr_iters)
+                    general_only=False, mr_iters=0, lfil=0) -> "Prec":
+        o = self._spai_opts(tol, equilibrate, False, general_only, mr_iters, lfil)
         h = ctypes.c_void_p()
         self._enter()
         _check(lib().airga_spai_update(self._h, old._h, float(s_new), ctypes.byref(o),
@@ -497,12 +499,12 @@ class Context:
         return Prec(self, h)
 
     def spai_update_many(self, olds, s_new, *, tol=0.01, equilibrate=True,
-                         general_only=False, mr_iters=0) -> list:
+                         general_only=False, mr_iters=0, lfil=0) -> list:
         """[update of olds[i] to s_new[i]], the pencil read once per batch."""
         k = len(olds)
         if len(s_new) != k:
             raise ValueError("one new shift per preconditioner")
-        o = self._spai_opts(tol, equilibrate, False, general_only, mr_iters)
+        o = self._spai_opts(tol, equilibrate, False, general_only, mr_iters, lfil)
         c_old = (ctypes.c_void_p * max(k, 1))(*[p._h.value for p in olds])
         c_s = (ctypes.c_double * max(k, 1))(*[float(v) for v in s_new])
         c_out = (ctypes.c_void_p * max(k, 1))()

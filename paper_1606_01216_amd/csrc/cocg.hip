@@ -655,7 +655,7 @@ airga_status airga_spai_build_complex(airga_ctx ctx, double s_re, double s_im,
   airga_spai_opts o;
   airga_spai_opts_default(&o);
   if (opts) o = *opts;
-  if (o.mr_iters != 0)
+  if (o.mr_iters != 0 || o.lfil != 0)
     return fail(AIRGA_EUNSUPPORTED, "the minimal-residual mode is for real shifts only");
   airga_prec p = new (std::nothrow) airga_prec_s();
   if (!p) return fail(AIRGA_ENOMEM, "host allocation failed");

@@ -359,6 +359,10 @@ __global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, const double* _
   if constexpr (UPDATE) block_count(skipped, skip_count);
 }
 
+// Pattern control: relative gap below which two candidate entries count as
+// equally large (so that rounding near eps never decides the pattern).
+constexpr double kPickTie = 1e-8;
+
 // The paper's minimal-residual column loop (Algorithm 2; Algorithm 4 for the
 // update), one lane per column j.  As printed, P (Q) stays alpha I inside the
 // loop, so the direction is d = alpha r, dropped to the pattern J of column
@@ -371,11 +375,16 @@ __global__ void __launch_bounds__(256) k_spai_cols(PencilDev pd, const double* _
 // It stops once |r| <= tol |t|, when (w, w) is not positive, or after maxit
 // steps.  The update's start test is the exact mode's skip test, so a column
 // that takes no step is flagged as alpha e_j.
+// Pattern control (lfil > 0): d takes alpha r only on the column's current
+// pattern, which starts as {j}; while it holds fewer than lfil entries, each
+// step first admits the position of J with the largest |alpha r| outside it
+// (ratios to the largest within kPickTie of 1 count as ties: the lowest
+// column wins; an exact zero is never admitted).
 template <int MJ, bool UPDATE, bool CONTIG>
 __global__ void __launch_bounds__(256) k_spai_mr(PencilDev pd, const double* __restrict__ ahat,
                                                  const double* __restrict__ aold,
                                                  const double* __restrict__ alpha_d, double tol,
-                                                 int maxit, double* __restrict__ hat,
+                                                 int maxit, int lfil, double* __restrict__ hat,
                                                  double* __restrict__ obj,
                                                  int32_t* __restrict__ skip_count,
                                                  int8_t* __restrict__ skipf) {
@@ -545,9 +554,36 @@ __global__ void __launch_bounds__(256) k_spai_mr(PencilDev pd, const double* __r
       for (int u = 0; u < MJ; ++u) rJ[u] = tJ[u] - y[u];
       double r2 = resid2(p);
       const double thr = tol * tol * t2;
+      // the column's current pattern (all of J without pattern control)
+      bool in[MJ];
+      int cnt = 0;
+#pragma unroll
+      for (int u = 0; u < MJ; ++u) {
+        in[u] = u < nj && (lfil <= 0 || J[u] == (int)j);
+        cnt += in[u] ? 1 : 0;
+      }
       for (int it = 0; it < maxit && r2 > thr; ++it) {
 #pragma unroll
         for (int u = 0; u < MJ; ++u) d[u] = u < nj ? al * rJ[u] : 0.0;
+        if (lfil > 0 && cnt < lfil) {
+          double top = 0.0;
+#pragma unroll
+          for (int u = 0; u < MJ; ++u)
+            if (u < nj && !in[u]) top = fmax(top, fabs(d[u]));
+          if (top > 0.0) {
+            int pick = -1;
+#pragma unroll
+            for (int u = MJ - 1; u >= 0; --u)
+              if (u < nj && !in[u] && fabs(d[u]) / top >= 1.0 - kPickTie) pick = u;
+#pragma unroll
+            for (int u = 0; u < MJ; ++u)
+              if (u == pick) in[u] = true;
+            cnt += pick >= 0 ? 1 : 0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < MJ; ++u)
+          if (!in[u]) d[u] = 0.0;
         symv(G, d, y);
         double rw = 0.0, ww = 0.0;
 #pragma unroll
@@ -1611,22 +1647,34 @@ constexpr int kMrMaxIters = 100000;
 // The minimal-residual column kernels, sized to the longest row.
 template <bool UPDATE>
 static void launch_mr(airga_ctx ctx, const SpaiScratch& w, const double* alpha, double tol,
-                      int maxit, double* obj, int32_t* skip, int8_t* skipf) {
+                      int maxit, int lfil, double* obj, int32_t* skip, int8_t* skipf) {
   const Pencil& pen = ctx->pen;
   const unsigned nb = blocks_for(pen.n, 256);
   const PencilDev pd = pen.dev();
   if (pen.max_len <= 6 && pen.contiguous)
     k_spai_mr<6, UPDATE, true><<<nb, 256, 0, ctx->stream>>>(pd, w.ahat, w.aold, alpha, tol, maxit,
-                                                           w.hat, obj, skip, skipf);
+                                                           lfil, w.hat, obj, skip, skipf);
   else if (pen.max_len <= 6)
     k_spai_mr<6, UPDATE, false><<<nb, 256, 0, ctx->stream>>>(pd, w.ahat, w.aold, alpha, tol, maxit,
-                                                            w.hat, obj, skip, skipf);
+                                                            lfil, w.hat, obj, skip, skipf);
   else if (pen.contiguous)
-    k_spai_mr<kSpaiMaxJ, UPDATE, true><<<nb, 256, 0, ctx->stream>>>(pd, w.ahat, w.aold, alpha, tol,
-                                                                   maxit, w.hat, obj, skip, skipf);
+    k_spai_mr<kSpaiMaxJ, UPDATE, true><<<nb, 256, 0, ctx->stream>>>(
+        pd, w.ahat, w.aold, alpha, tol, maxit, lfil, w.hat, obj, skip, skipf);
   else
-    k_spai_mr<kSpaiMaxJ, UPDATE, false><<<nb, 256, 0, ctx->stream>>>(pd, w.ahat, w.aold, alpha, tol,
-                                                                    maxit, w.hat, obj, skip, skipf);
+    k_spai_mr<kSpaiMaxJ, UPDATE, false><<<nb, 256, 0, ctx->stream>>>(
+        pd, w.ahat, w.aold, alpha, tol, maxit, lfil, w.hat, obj, skip, skipf);
+}
+
+// The minimal-residual options: the step cap, and pattern control only with
+// it (lfil up to the longest column the kernels hold).
+static airga_status check_mr_opts(const airga_spai_opts& o) {
+  if (o.mr_iters < 0 || o.mr_iters > kMrMaxIters)
+    return fail(AIRGA_EINVAL, "mr_iters must be in [0, %d]", kMrMaxIters);
+  if (o.lfil < 0 || o.lfil > kSpaiMaxJ)
+    return fail(AIRGA_EINVAL, "lfil must be in [0, %d]", kSpaiMaxJ);
+  if (o.lfil > 0 && o.mr_iters == 0)
+    return fail(AIRGA_EINVAL, "lfil applies to the minimal-residual mode (mr_iters > 0)");
+  return AIRGA_OK;
 }
 
 static airga_status run_build(airga_ctx ctx, double s, const airga_spai_opts& o, airga_prec p) {
@@ -1657,7 +1705,7 @@ static airga_status run_build(airga_ctx ctx, double s, const airga_spai_opts& o,
       AIRGA_HIP(hipGetLastError());
       k_fill_i32<<<1, 64, 0, st>>>(reinterpret_cast<int32_t*>(p->scal.as<char>() + 8), 1, 0);
       AIRGA_HIP(hipGetLastError());
-      launch_mr<false>(ctx, w, d_alpha, o.tol, o.mr_iters, p->objective.as<double>(), nullptr,
+      launch_mr<false>(ctx, w, d_alpha, o.tol, o.mr_iters, o.lfil, p->objective.as<double>(), nullptr,
                        nullptr);
     } else {
       launch_cols<false>(ctx, w, nullptr, 0.0, p->objective.as<double>(), nullptr, nullptr);
@@ -1709,7 +1757,7 @@ static airga_status run_update(airga_ctx ctx, airga_prec old, double s_new,
     launch_band<true>(ctx, a, b, ao, bo, w.dinv, d_alpha, o.tol, w.hat, p->objective.as<double>(),
                       w.skip_part, skip_flags(p));
   else if (o.mr_iters > 0)
-    launch_mr<true>(ctx, w, d_alpha, o.tol, o.mr_iters, p->objective.as<double>(), w.skip_part,
+    launch_mr<true>(ctx, w, d_alpha, o.tol, o.mr_iters, o.lfil, p->objective.as<double>(), w.skip_part,
                     skip_flags(p));
   else
     launch_cols<true>(ctx, w, d_alpha, o.tol, p->objective.as<double>(), w.skip_part,
@@ -1980,8 +2028,7 @@ airga_status airga_spai_build(airga_ctx ctx, double s, const airga_spai_opts* op
   airga_spai_opts o;
   airga_spai_opts_default(&o);
   if (opts) o = *opts;
-  if (o.mr_iters < 0 || o.mr_iters > kMrMaxIters)
-    return fail(AIRGA_EINVAL, "mr_iters must be in [0, %d]", kMrMaxIters);
+  AIRGA_TRY(check_mr_opts(o));
   if (!(o.tol >= 0)) return fail(AIRGA_EINVAL, "tolerance must be >= 0");
   airga_prec p = nullptr;
   AIRGA_TRY(new_prec(ctx, s, &p));
@@ -2008,8 +2055,7 @@ airga_status airga_spai_update(airga_ctx ctx, airga_prec old, double s_new,
   airga_spai_opts_default(&o);
   if (opts) o = *opts;
   if (!(o.tol >= 0)) return fail(AIRGA_EINVAL, "update tolerance must be >= 0");
-  if (o.mr_iters < 0 || o.mr_iters > kMrMaxIters)
-    return fail(AIRGA_EINVAL, "mr_iters must be in [0, %d]", kMrMaxIters);
+  AIRGA_TRY(check_mr_opts(o));
   airga_prec p = nullptr;
   AIRGA_TRY(new_prec(ctx, s_new, &p));
   airga_status st = run_update(ctx, old, s_new, o, p);
@@ -2033,8 +2079,7 @@ airga_status airga_spai_build_many(airga_ctx ctx, int32_t count, const double* s
   airga_spai_opts o;
   airga_spai_opts_default(&o);
   if (opts) o = *opts;
-  if (o.mr_iters < 0 || o.mr_iters > kMrMaxIters)
-    return fail(AIRGA_EINVAL, "mr_iters must be in [0, %d]", kMrMaxIters);
+  AIRGA_TRY(check_mr_opts(o));
   if (!(o.tol >= 0)) return fail(AIRGA_EINVAL, "tolerance must be >= 0");
   std::vector<airga_prec> ps(count, nullptr);
   airga_status st = AIRGA_OK;
@@ -2066,8 +2111,7 @@ airga_status airga_spai_update_many(airga_ctx ctx, int32_t count, const airga_pr
   airga_spai_opts_default(&o);
   if (opts) o = *opts;
   if (!(o.tol >= 0)) return fail(AIRGA_EINVAL, "update tolerance must be >= 0");
-  if (o.mr_iters < 0 || o.mr_iters > kMrMaxIters)
-    return fail(AIRGA_EINVAL, "mr_iters must be in [0, %d]", kMrMaxIters);
+  AIRGA_TRY(check_mr_opts(o));
   std::vector<airga_prec> ps(count, nullptr);
   airga_status st = AIRGA_OK;
   for (int32_t i = 0; i < count && st == AIRGA_OK; ++i) st = new_prec(ctx, s_new[i], &ps[i]);

@@ -53,6 +53,7 @@ def test_library_loads_and_answers_host_only_calls():
     s = airga.SpaiOpts()
     h.airga_spai_opts_default(s)
     assert s.tol == 0.01 and s.equilibrate == 1 and s.symmetrize == 1
+    assert s.mr_iters == 0 and s.lfil == 0
 
 
 def test_null_context_is_rejected_without_a_gpu():

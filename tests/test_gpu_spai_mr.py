@@ -1,5 +1,6 @@
 """GPU: the SPAI minimal-residual mode (the paper's column loops of Algorithms
-2 and 4, option mr_iters) against the oracle's loop.  A column whose stopping
+2 and 4, option mr_iters, with the pattern control of option lfil) against
+the oracle's loop.  A column whose stopping
 test came within 1e-8 (relative) of the tolerance in the oracle may stop one
 step apart on the GPU, which evaluates |r| by another formula; such columns
 are only checked to meet their stopping rule, every other column must agree
@@ -108,6 +109,94 @@ def test_solves_with_mr_preconditioners_meet_the_oracle(ctx, mode):
             assert rel_err(Xh[k, c], ref[k, c]) < 1e-8
 
 
+# ------------------------------------------------ pattern control (lfil)
+
+def lfil_pencils():
+    # the uniform beam has exactly equal candidates (mirror-image rows), the
+    # graded one none, the grid rows of up to five entries
+    return {"beam": pencils()["beam"], "grid": pencils()["grid"],
+            "uniform": beam.make_beam(300, surrogate=True)}
+
+
+def _cols_agree_lfil(pen, got_vals, got_obj, ref):
+    """As _cols_agree, with the columns whose pattern decisions came within
+    1e-10 of the tie threshold also left to validity checks."""
+    tie = (ref.margin < 1e-8) | (ref.pick_margin < 1e-10)
+    col = pen.col_idx
+    row = np.repeat(np.arange(pen.n), np.diff(pen.row_ptr))
+    scale = np.abs(ref.values).max()
+    ok_v = np.abs(got_vals - ref.values) <= 1e-10 * scale
+    allowed = tie[col] | tie[row]
+    assert np.all(allowed[~ok_v]), np.flatnonzero(~ok_v & ~allowed)[:10]
+    sure = ~tie
+    assert np.all(np.abs(got_obj[sure] - ref.objective[sure]) <=
+                  1e-10 * np.maximum(1.0, ref.objective[sure]))
+    assert np.all(np.isfinite(got_obj))
+    return int(tie.sum())
+
+
+def _column_nnz(pen, vals):
+    return np.bincount(pen.col_idx, weights=(vals != 0).astype(float), minlength=pen.n)
+
+
+@pytest.mark.parametrize("name", ["beam", "grid", "uniform"])
+@pytest.mark.parametrize("lfil,iters,tol", [(1, 4, 0.0), (2, 8, 0.0), (3, 30, 0.05),
+                                            (5, 200, 0.0)])
+def test_mr_lfil_build_matches_oracle(ctx, name, lfil, iters, tol):
+    pen = lfil_pencils()[name]
+    set_pencil(ctx, pen)
+    for s in (2.0, 300.0):
+        f = ctx.spai_build(s, mr_iters=iters, tol=tol, lfil=lfil, symmetrize=False)
+        vals, obj = (t.cpu().numpy() for t in f.export())
+        ref = spai.spai_build(pencil.shifted_operator(pen, s), mr_iters=iters, tol=tol,
+                              lfil=lfil, symmetrize=False)
+        ties = _cols_agree_lfil(pen, vals, obj, ref)
+        assert ties <= pen.n // 50, ties
+        # every column within the cap (unsymmetrised: a column's entries are its own)
+        assert np.all(_column_nnz(pen, vals) <= lfil)
+    # the symmetric average of a grown factor
+    f = ctx.spai_build(7.0, mr_iters=iters, tol=tol, lfil=lfil)
+    vals, obj = (t.cpu().numpy() for t in f.export())
+    ref = spai.spai_build(pencil.shifted_operator(pen, 7.0), mr_iters=iters, tol=tol, lfil=lfil)
+    _cols_agree_lfil(pen, vals, obj, ref)
+
+
+@pytest.mark.parametrize("lfil", [2, 4])
+def test_mr_lfil_update_matches_oracle(ctx, lfil):
+    pen = lfil_pencils()["beam"]
+    set_pencil(ctx, pen)
+    s_old, s_new, tol = 4.0, 4.6, 0.05
+    old = ctx.spai_build(s_old)
+    q = ctx.spai_update(old, s_new, tol=tol, mr_iters=12, lfil=lfil)
+    vals, obj = (t.cpu().numpy() for t in q.export())
+    a_old, a_new = (pencil.shifted_operator(pen, s) for s in (s_old, s_new))
+    ref = spai.spai_update(a_old, a_new, tol=tol, mr_iters=12, lfil=lfil)
+    assert abs(q.info().skipped_cols - int(ref.skipped.sum())) <= int((ref.margin < 1e-8).sum())
+    _cols_agree_lfil(pen, vals, obj, ref)
+    # the update maps Qhat back with S_new (.) S_new^-1, which keeps zeros
+    assert np.all(_column_nnz(pen, vals) <= lfil)
+    many = ctx.spai_update_many([old], [s_new], tol=tol, mr_iters=12, lfil=lfil)
+    vm, om = (t.cpu().numpy() for t in many[0].export())
+    assert np.array_equal(vm, vals) and np.array_equal(om, obj)
+
+
+def test_solves_with_lfil_preconditioners_meet_the_oracle(ctx):
+    pen = lfil_pencils()["beam"]
+    set_pencil(ctx, pen)
+    rng = np.random.default_rng(7)
+    f, _ = beam.node_loads(pen.n, 2, rng)
+    shifts = [1.5, 60.0, 900.0]
+    precs = [ctx.spai_build(s, mr_iters=10, tol=0.01, lfil=3) for s in shifts]
+    X, st = ctx.pcg_solve(shifts, precs, to_dev(f, torch.float64), tol=1e-10,
+                          mode=airga.MODE_MIXED)
+    ref = reference(pen, shifts, f)
+    Xh = X.cpu().numpy()
+    for k in range(len(shifts)):
+        for c in range(2):
+            assert st[2 * k + c]["status"] == airga.SYS_CONVERGED
+            assert rel_err(Xh[k, c], ref[k, c]) < 1e-8
+
+
 def test_mr_option_is_validated(ctx):
     pen = pencils()["grid"]
     set_pencil(ctx, pen)
@@ -116,4 +205,16 @@ def test_mr_option_is_validated(ctx):
     assert ei.value.status == airga.EINVAL
     with pytest.raises(airga.AirgaError) as ei:
         ctx.spai_build(2.0, mr_iters=5, tol=-1.0)
+    assert ei.value.status == airga.EINVAL
+    # pattern control: within [0, 8] and only with the minimal-residual mode
+    for kw in (dict(mr_iters=5, lfil=-1), dict(mr_iters=5, lfil=9), dict(lfil=2)):
+        with pytest.raises(airga.AirgaError) as ei:
+            ctx.spai_build(2.0, **kw)
+        assert ei.value.status == airga.EINVAL, kw
+    old = ctx.spai_build(2.0)
+    with pytest.raises(airga.AirgaError) as ei:
+        ctx.spai_update(old, 2.2, lfil=3)
+    assert ei.value.status == airga.EINVAL
+    with pytest.raises(airga.AirgaError) as ei:
+        ctx.spai_build_many([2.0, 3.0], lfil=3)
     assert ei.value.status == airga.EINVAL
