@@ -676,6 +676,330 @@ def rel_errors_c(x, ref):
     return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
 
 
+def measure_c1_literal(dev, stream):
+    """The literal 1000-DOF cantilever (EI = 1, s = 100, tip load, SPAI on
+    the pattern of K(s), CG to 1e-10): float64 and mixed solves, their
+    errors against the oracle's double-double and binary64 references, and
+    the binary64 floor (the oracle's binary64 Cholesky against double-double;
+    no float64 solver gets much below it at cond(K(s)) ~ 3e10)."""
+    import torch
+    from oracle import direct
+    from paper_1606_01216_amd import airga
+    pen, f, shifts, _ = beam.make_workload("c1")
+    s = float(shifts[0])
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    ctx = airga.Context(0, stream)
+    out = {"workload": "Hermite cantilever n=1000, EI=1 (literal), tip load, s=100", "n": pen.n}
+    ref = direct.reference_solve(pen, s, f, "dd")[0]
+    r64 = direct.reference_solve(pen, s, f, "f64")[0]
+    nr = np.linalg.norm(ref)
+    out["f64_cholesky_vs_dd"] = float(f"{np.linalg.norm(r64 - ref) / nr:.3e}")
+    with torch.cuda.stream(stream):
+        ctx.set_pencil(t(pen.row_ptr, torch.int32), t(pen.col_idx, torch.int32),
+                       t(pen.m_val, torch.float64), t(pen.k_val, torch.float64), pen.alpha,
+                       pen.beta)
+        p = ctx.spai_build(s)
+        F = t(f, torch.float64)
+        for name, mode in (("fp64", airga.MODE_FP64), ("mixed", airga.MODE_MIXED)):
+            ctx.pcg_solve([s], [p], F, tol=1e-10, max_iter=40000, mode=mode)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            X, st = ctx.pcg_solve([s], [p], F, tol=1e-10, max_iter=40000, mode=mode)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            x = X[0, 0].cpu().numpy()
+            out[name] = {"status": airga.STATUS_NAMES[st[0]["status"]], "iters": st[0]["iters"],
+                         "ms": round(ms, 3),
+                         "rel_err_vs_dd": float(f"{np.linalg.norm(x - ref) / nr:.3e}"),
+                         "rel_err_vs_f64": float(f"{np.linalg.norm(x - r64) / np.linalg.norm(r64):.3e}"),
+                         "finished_fp64": bool(st[0]["finished_fp64"])}
+        p.release()
+    ctx.close()
+    return out
+
+
+def measure_airga_updates(dev, stream, max_outer=4, update_from=3):
+    """AIRGA's loop with the cheap update across outer iterations (Algorithm
+    5) where the expansion points settle: the literal 60-DOF cantilever (EI =
+    1, alpha = 0.01, beta = 0.001), points 1, 30, 500, tip input and output,
+    r_max = 12; from outer iteration update_from on each point's
+    preconditioner is the update of the previous one.  Per iteration: the
+    points, J, whether the factors were updated, the longest chain, the
+    largest CG iteration count and the relative H2 change."""
+    import torch
+    from paper_1606_01216_amd import airga
+    pen = beam.make_beam(30, seed=3, alpha=0.01, beta=0.001)
+    n = pen.n
+    f = np.zeros((1, n))
+    f[0, n - 2] = 1.0
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    ctx = airga.Context(0, stream)
+    with torch.cuda.stream(stream):
+        ctx.set_pencil(t(pen.row_ptr, torch.int32), t(pen.col_idx, torch.int32),
+                       t(pen.m_val, torch.float64), t(pen.k_val, torch.float64), pen.alpha,
+                       pen.beta)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.reduce(t(f, torch.float64), t(f, torch.float64), [1.0, 30.0, 500.0], r_max=12,
+                         max_outer=max_outer, update_from=update_from, tol=1e-12)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+    ctx.close()
+    return {"workload": "literal Hermite cantilever n=60, EI=1, alpha=0.01, beta=0.001, points "
+                        "1, 30, 500, tip input and output, r_max=12",
+            "update_from": update_from, "ms": round(ms, 2), "iterations": res["iterations"],
+            "history": [{"shifts": [float(f"{v:.6g}") for v in h["shifts"]], "J": h["J"],
+                         "updated": h["updated"], "chain_len_max": h["chain_len_max"],
+                         "max_iters": h["max_iters"], "all_converged": h["all_converged"],
+                         "change": None if h["change"] is None else float(f"{h['change']:.3e}")}
+                        for h in res["history"]]}
+
+
+# ------------------------------------------------------------ literal shapes
+#
+# The unscaled beams (EI as stated, h = 1 / n_el) have equilibrated condition
+# numbers of about 3e11 (n / 1e3)^4 at s = 1: from n = 1e5 on, no float64 CG
+# reaches 1e-8 and float32 refinement cannot contract.  Their solves are
+# timed at a fixed iteration count instead (tolerance 1e-30, so every system
+# runs exactly `cap` iterations, the same for batched and one-at-a-time
+# solves); the statuses at the cap and the errors against the oracle's
+# double-double reference are reported as observed.
+LITERAL_TOL = 1e-30
+
+
+def literal_refs(pen, shift_list, f, workers):
+    """The oracle's double-double reference per shift, or None where the
+    stored K(s) is not positive definite even in double-double: the binary64
+    rounding of the unscaled beam's entries (relative 1e-16 of entries near
+    12 EI / h^3) exceeds the smallest eigenvalue once cond(K(s)) passes about
+    1e16, so the matrix that was stored may have no Cholesky factor at all.
+    Returns (refs, notes)."""
+    from oracle import _native, direct
+    _native.lib()
+
+    def job(s):
+        try:
+            return direct.reference_solve(pen, s, f, "dd"), "dd"
+        except np.linalg.LinAlgError as e:
+            return None, f"none: {e}"
+    with cf.ThreadPoolExecutor(max(1, workers)) as ex:
+        out = list(ex.map(job, shift_list))
+    return [o[0] for o in out], [o[1] for o in out]
+
+
+def _literal_solve(ctx, stream, shifts, precs, F, X, kw, rows_kw, reps=3):
+    """Median wall time of `reps` capped solves (after one untimed run),
+    then one profiled run: (seconds, stats, kernel rows, solve-level GB/s)."""
+    import torch
+    with torch.cuda.stream(stream):
+        ctx.pcg_solve(shifts, precs, F, X, **kw)
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = ctx.pcg_solve(shifts, precs, F, X, **kw)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ctx.pcg_solve(shifts, precs, F, X, profile=True, **kw)
+        kt, kwk = ctx.kernel_times(), ctx.kernel_work()
+        tile = ctx.tile_config()
+    n = F.shape[1]
+    rows = kernel_rows(kt, kwk, gp=row_blocks(n, tile[0]), **rows_kw)
+    sec = statistics.median(ts)
+    tot = sum(r["bytes"] for r in rows if r["bytes"])
+    return sec, st, rows, round(tot / sec / 1e9, 1), tile
+
+
+def _status_counts(st):
+    from paper_1606_01216_amd import airga
+    out = {}
+    for e in st:
+        k = airga.STATUS_NAMES[e["status"]]
+        out[k] = out.get(k, 0) + 1
+    return out
+
+
+def _err_summary(errs):
+    if not errs:
+        return {"systems": 0}
+    return {"systems": len(errs), "min": float(f"{min(errs):.3e}"),
+            "median": float(f"{statistics.median(errs):.3e}"), "max": float(f"{max(errs):.3e}"),
+            "within_1e-8": sum(e <= ERR_TOL for e in errs)}
+
+
+def measure_literal_batched(dev, stream, base, cap, err_idx, fp64=True, plain=2, reps=3):
+    """One literal workload (c3 or c5): the batched SPAI build of all its
+    shifts (median of 3), then the batched solves of every system at `cap`
+    iterations: float64 (config 3) if `fp64`, mixed (config 4: one float32
+    sweep of `cap` iterations, then the float64 residual), and `plain`
+    systems one at a time in float64.  Errors against the double-double
+    reference for the shifts `err_idx` (all their loads)."""
+    import torch
+    from paper_1606_01216_amd import airga
+    pen, f, shifts, _ = beam.make_workload(base)
+    n, m, S = pen.n, f.shape[0], len(shifts)
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    ctx = airga.Context(0, stream)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    out = {"n": n, "m": m, "shifts": S, "systems": S * m, "cap_iters": cap}
+    with torch.cuda.stream(stream):
+        ctx.set_pencil(t(pen.row_ptr, torch.int32), t(pen.col_idx, torch.int32),
+                       t(pen.m_val, torch.float64), t(pen.k_val, torch.float64), pen.alpha,
+                       pen.beta)
+        info = ctx.pencil_info()
+        F = t(f, torch.float64)
+        bms = []
+        for _ in range(3):
+            e0, e1 = ev(), ev()
+            e0.record(stream)
+            precs = ctx.spai_build_many(list(shifts))
+            e1.record(stream)
+            torch.cuda.synchronize()
+            bms.append(e0.elapsed_time(e1))
+            if len(bms) < 3:
+                for p in precs:
+                    p.release()
+        out["spai_build_ms_per_shift"] = round(statistics.median(bms) / S, 4)
+    stored = info.nnz_stored
+    ib = 1 if info.bandwidth <= 64 else 4
+    base_kw = dict(shifts=list(shifts), precs=precs, F=F)
+    X = torch.zeros((S, m, n), dtype=torch.float64, device=dev)
+    refs, notes = literal_refs(pen, [shifts[i] for i in err_idx], f,
+                               min(CPU_WORKERS, cpu_info()[1], len(err_idx)))
+    out["reference"] = {f"{shifts[i]:.6g}": note for i, note in zip(err_idx, notes)}
+
+    def errors(Xd):
+        xs = Xd[list(err_idx)].cpu().numpy()
+        return [float(np.linalg.norm(xs[a, c] - refs[a][c]) / np.linalg.norm(refs[a][c]))
+                for a in range(len(err_idx)) if refs[a] is not None for c in range(m)]
+
+    legs = []
+    if fp64:
+        legs.append(("batched_fp64", dict(tol=LITERAL_TOL, mode=airga.MODE_FP64, max_iter=cap,
+                                          poll_every=8),
+                     dict(w=8, fw=8, first_passes=0, mixed=False)))
+    legs.append(("batched_mixed", dict(tol=LITERAL_TOL, mode=airga.MODE_MIXED, max_iter=cap,
+                                       inner_max=cap, inner_tol=LITERAL_TOL, max_sweeps=1,
+                                       poll_every=8),
+                 dict(w=4, fw=4, first_passes=S * m, mixed=True, assign_sys=S * m)))
+    for name, kw, rkw in legs:
+        log(f"[bench] literal {base}: {name} at {cap} iterations")
+        sec, st, rows, gbs, tile = _literal_solve(
+            ctx, stream, base_kw["shifts"], precs, F, X, kw,
+            dict(stored=stored, n=n, ib=ib, m=m, **rkw), reps)
+        iters = [e["iters"] for e in st]
+        out[name] = {"seconds_median_of_3": round(sec, 4),
+                     "ms_per_iteration": round(sec * 1e3 / max(iters), 4),
+                     "system_iterations_per_s": round(sum(iters) / sec, 1),
+                     "iters_min": min(iters), "iters_max": max(iters),
+                     "status": _status_counts(st), "algorithmic_gbs": gbs,
+                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "tile": list(tile),
+                     "kernels": rows, "rel_err_vs_dd": _err_summary(errors(X))}
+    if plain:
+        log(f"[bench] literal {base}: plain float64 one system at a time")
+        kw = dict(tol=LITERAL_TOL, mode=airga.MODE_FP64, max_iter=cap, poll_every=8)
+        Xp = torch.zeros((1, 1, n), dtype=torch.float64, device=dev)
+        with torch.cuda.stream(stream):
+            ctx.pcg_solve([float(shifts[0])], [precs[0]], F[0:1], Xp, **kw)
+            ts, sts = [], []
+            for k in range(plain):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, st = ctx.pcg_solve([float(shifts[k])], [precs[k]], F[0:1], Xp, **kw)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+                sts += st
+        sec = statistics.mean(ts)
+        out["plain_fp64"] = {"systems_timed": plain, "seconds_per_system": round(sec, 4),
+                             "ms_per_iteration": round(sec * 1e3 / cap, 4),
+                             "system_iterations_per_s": round(cap / sec, 1),
+                             "status": _status_counts(sts)}
+        if fp64:
+            out["batched_fp64_vs_plain_per_iteration"] = round(
+                out["batched_fp64"]["system_iterations_per_s"] /
+                out["plain_fp64"]["system_iterations_per_s"], 2)
+    out["batched_mixed_vs_plain_per_iteration"] = round(
+        out["batched_mixed"]["system_iterations_per_s"] /
+        out["plain_fp64"]["system_iterations_per_s"], 2) if plain else None
+    out["err_shifts"] = [float(f"{shifts[i]:.6g}") for i in err_idx]
+    for p in precs:
+        p.release()
+    ctx.close()
+    del X, F
+    torch.cuda.empty_cache()
+    return out
+
+
+def measure_literal_c2(dev, stream, cap):
+    """Config 2 literal: the 100,000-DOF beam (EI log-uniform [0.5, 2]),
+    tip load; SPAI built at s_1 and updated along the 8 log-spaced shifts
+    (the horizontal chain), each solved once in float64 at `cap`
+    iterations; per shift the build or update ms, the chain length, the
+    skipped fraction, the status and the error against double-double."""
+    import torch
+    from paper_1606_01216_amd import airga
+    pen, f, shifts, _ = beam.make_workload("c2")
+    n = pen.n
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    ctx = airga.Context(0, stream)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    F = t(f, torch.float64)
+    X = torch.zeros((len(shifts), 1, n), dtype=torch.float64, device=dev)
+    kw = dict(tol=LITERAL_TOL, mode=airga.MODE_FP64, max_iter=cap, poll_every=8, use_graph=False)
+    recs, handles = [], []
+    with torch.cuda.stream(stream):
+        ctx.set_pencil(t(pen.row_ptr, torch.int32), t(pen.col_idx, torch.int32),
+                       t(pen.m_val, torch.float64), t(pen.k_val, torch.float64), pen.alpha,
+                       pen.beta)
+        for i, s in enumerate(shifts):
+            e0, e1 = ev(), ev()
+            e0.record(stream)
+            p = (ctx.spai_build(float(s), symmetrize=False) if i == 0
+                 else ctx.spai_update(handles[-1], float(s)))
+            e1.record(stream)
+            handles.append(p)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = ctx.pcg_solve([float(s)], [p], F, X[i:i + 1], **kw)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            info = p.info()
+            recs.append(dict(shift=float(f"{s:.6g}"), kind="build" if i == 0 else "update",
+                             chain_len=info.chain_len,
+                             skipped_frac=round(info.skipped_cols / n, 4),
+                             prec_ms=round(e0.elapsed_time(e1), 4),
+                             solve_ms=round((t1 - t0) * 1e3, 3), iters=st[0]["iters"],
+                             status=airga.STATUS_NAMES[st[0]["status"]],
+                             relres=float(f"{st[0]['relres']:.3e}")))
+        for p in handles:
+            p.release()
+    refs, notes = literal_refs(pen, list(shifts), f, min(CPU_WORKERS, cpu_info()[1]))
+    Xh = X.cpu().numpy()
+    for r, x, ref, note in zip(recs, Xh, refs, notes):
+        r["reference"] = note
+        r["rel_err_vs_dd"] = (None if ref is None else
+                              float(f"{np.linalg.norm(x[0] - ref[0]) / np.linalg.norm(ref[0]):.3e}"))
+    ctx.close()
+    return {"n": n, "cap_iters": cap, "solves": recs}
+
+
+def measure_literal(dev, stream, cap=200, c5_cap=100):
+    return {
+        "note": "unscaled beams, every system run to a fixed iteration count (tolerance 1e-30); "
+                "statuses and errors as observed",
+        "c2": dict(workload="Hermite cantilever n=100,000, EI log-uniform [0.5,2] (literal), tip "
+                            "load, 8 shifts logspace(0,4,8): build at s_1, horizontal update chain",
+                   **measure_literal_c2(dev, stream, cap)),
+        "c3_c4": dict(workload="Hermite cantilever n=1,000,000, EI=1 (literal), m=4 seeded unit "
+                               "loads, 16 shifts logspace(0,4,16)",
+                      **measure_literal_batched(dev, stream, "c3", cap, err_idx=(0, 5, 10, 15))),
+        "c5": dict(workload="Hermite cantilever n=10,000,000, EI log-uniform [0.1,10] (literal), "
+                            "m=4, 32 shifts logspace(0,5,32)",
+                   **measure_literal_batched(dev, stream, "c5", c5_cap, err_idx=(0, 10, 21, 31),
+                                             fp64=False, plain=1)),
+    }
+
+
 def measure_batched_fp64(ctx, stream, sets, F, tol, poll_every, reps=5):
     """Config 3: batched float64 PCG of every system of a step (one call per
     shift set, all its systems in one set of kernels), warmed by one untimed
@@ -748,11 +1072,18 @@ def main():
                     help="skip the 100,000-DOF update-chain sequence")
     ap.add_argument("--no-complex", action="store_true",
                     help="skip the complex-expansion-point leg")
+    ap.add_argument("--complex-only", action="store_true",
+                    help="run only the complex-expansion-point leg and print its JSON")
     ap.add_argument("--c2-only", action="store_true",
                     help="run only the update-chain sequence and print its JSON (for profilers)")
     ap.add_argument("--no-airga-iteration", action="store_true",
                     help="skip the full-size AIRGA iteration (its small solves would enter a "
                          "profiler's per-kernel averages)")
+    ap.add_argument("--no-literal", action="store_true",
+                    help="skip the literal shapes at a fixed iteration count")
+    ap.add_argument("--literal-only", action="store_true",
+                    help="run only the literal shapes, the literal 1000-DOF beam and the "
+                         "AIRGA loop with updates, and print their JSON")
     ap.add_argument("--quick", action="store_true", help="timed steps only (for profilers)")
     ap.add_argument("--tile", default=None,
                     help="force the tile 'ROWS,SYSTEMS' (matrix rows per wavefront, systems per "
@@ -787,6 +1118,25 @@ def main():
     if args.c2_only:
         stream = torch.cuda.Stream(device=dev)
         print(json.dumps(measure_c2_sequence(dev, stream)))
+        return
+    if args.literal_only:
+        stream = torch.cuda.Stream(device=dev)
+        print(json.dumps({"literal": measure_literal(dev, stream),
+                          "c1_literal": measure_c1_literal(dev, stream),
+                          "airga_updates": measure_airga_updates(dev, stream)}))
+        return
+    if args.complex_only:
+        pen, f, shifts, _ = build_inputs(args.workload)
+        stream = torch.cuda.Stream(device=dev)
+        ctx = airga.Context(0, stream)
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+        with torch.cuda.stream(stream):
+            ctx.set_pencil(t(pen.row_ptr, torch.int32), t(pen.col_idx, torch.int32),
+                           t(pen.m_val, torch.float64), t(pen.k_val, torch.float64),
+                           pen.alpha, pen.beta)
+        print(json.dumps(measure_complex(ctx, stream, pen, f, t(f, torch.float64), shifts,
+                                         args.tol)))
+        ctx.close()
         return
     log(f"[bench] building inputs {args.workload}")
     pen, f, shifts, drifted = build_inputs(args.workload)
@@ -1055,6 +1405,13 @@ def main():
     if not args.no_complex:
         log("[bench] complex expansion points (COCG)")
         out["complex_shifts"] = measure_complex(ctx, stream, pen, f, F, shifts, args.tol)
+    if not args.no_literal:
+        log("[bench] literal shapes at a fixed iteration count")
+        out["literal"] = measure_literal(dev, stream)
+    if not args.no_airga_iteration:
+        log("[bench] literal 1000-DOF beam; AIRGA loop with updates")
+        out["c1_literal"] = measure_c1_literal(dev, stream)
+        out["airga_updates"] = measure_airga_updates(dev, stream)
     if cpu is not None:
         out["cpu_baseline"] = {
             "value": round(cpu["dd_1"], 3), "unit": "solves/s", "cores": 1, "kind": "oracle",
