@@ -1008,11 +1008,14 @@ __host__ __device__ inline size_t spai_gram_wave_lds(int bw) {
          sizeof(double) * (wr + 2 * (size_t)bw) + sizeof(double) * (band > hatw ? band : hatw);
 }
 
-template <int MJ>
+// BWC > 0: the bandwidth as a compile-time constant (the window sizes and
+// the band's index arithmetic then fold); 0: bw_rt at run time.
+template <int MJ, int BWC>
 __global__ void __launch_bounds__(256) k_spai_gram_wave(PencilDev pd, UpdMany U,
                                                         const double* __restrict__ dinv,
-                                                        int64_t n_pad, int bw, int sym,
+                                                        int64_t n_pad, int bw_rt, int sym,
                                                         size_t wave_lds) {
+  const int bw = BWC > 0 ? BWC : bw_rt;
   extern __shared__ double lds_all[];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -1835,8 +1838,12 @@ static airga_status run_build_many(airga_ctx ctx, int32_t count, const double* s
         U.v64[i] = ps[i0 + i]->v64.as<double>();
         U.v32[i] = ps[i0 + i]->v32.as<float>();
       }
-      k_spai_gram_wave<6><<<ng, 256, 4 * wave_lds, st>>>(pd, U, dinv, n_pad, bw,
-                                                          o.symmetrize ? 1 : 0, wave_lds);
+      if (bw == 3)
+        k_spai_gram_wave<6, 3><<<ng, 256, 4 * wave_lds, st>>>(pd, U, dinv, n_pad, bw,
+                                                             o.symmetrize ? 1 : 0, wave_lds);
+      else
+        k_spai_gram_wave<6, 0><<<ng, 256, 4 * wave_lds, st>>>(pd, U, dinv, n_pad, bw,
+                                                             o.symmetrize ? 1 : 0, wave_lds);
       AIRGA_HIP(hipGetLastError());
     } else if (range && pen.contiguous)
       k_spai_build_many<6, 2><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, hat);
