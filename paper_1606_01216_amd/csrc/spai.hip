@@ -910,15 +910,25 @@ __global__ void k_alpha_partial_many(PencilDev pd, UpdMany U, const double* __re
       kk[k] = pd.k64[idx];
     }
   }
+  // the diagonal scalings of the row and its columns for shift q; the next
+  // shift's are loaded while the current one is used
+  auto scal = [&](int q, double& sr, double (&dc)[kSpaiMaxJ]) {
+    const double* __restrict__ dv = dinv + (int64_t)q * n_pad;
+    sr = dv[r];
+#pragma unroll
+    for (int k = 0; k < kSpaiMaxJ; ++k) dc[k] = k < len ? dv[c[k]] : 0.0;
+  };
+  double sr0 = 0.0, dc0[kSpaiMaxJ] = {};
+  if (r < pd.n && U.count > 0) scal(0, sr0, dc0);
   for (int s = 0; s < U.count; ++s) {
-    const double* __restrict__ dv = dinv + (int64_t)s * n_pad;
+    double sr1 = 0.0, dc1[kSpaiMaxJ] = {};
+    if (r < pd.n && s + 1 < U.count) scal(s + 1, sr1, dc1);
     double num = 0, den = 0;
     if (r < pd.n) {
-      const double sr = dv[r];
 #pragma unroll
       for (int k = 0; k < kSpaiMaxJ; ++k) {
         if (k < len) {
-          const double sc = sr * dv[c[k]];
+          const double sc = sr0 * dc0[k];
           const double an = fma(U.a[s], m[k], U.b[s] * kk[k]) * sc;
           const double ao = fma(U.ao[s], m[k], U.bo[s] * kk[k]) * sc;
           num = fma(ao, an, num);
@@ -926,6 +936,9 @@ __global__ void k_alpha_partial_many(PencilDev pd, UpdMany U, const double* __re
         }
       }
     }
+    sr0 = sr1;
+#pragma unroll
+    for (int k = 0; k < kSpaiMaxJ; ++k) dc0[k] = dc1[k];
     num = wave_sum(num);
     den = wave_sum(den);
     if ((threadIdx.x & 63) == 0) {
@@ -1311,15 +1324,122 @@ __global__ void __launch_bounds__(256) k_spai_build_many(PencilDev pd, UpdMany U
   }
 }
 
+// The update's skip test for every column and shift of the batch, straight
+// from the pencil (one lane per column j, whose pattern is that of row j):
+// the same scaled values, in the same association, as the staged test of
+// k_spai_update_many below, so the flags agree bit for bit.  Writes the
+// flags, the objective of skipped columns, and per (shift, block of 256
+// columns) the skipped count and whether any column needs its solve, so the
+// staged kernel only visits blocks and shifts with work left.
+template <int MJ>
+__global__ void __launch_bounds__(256) k_update_test_many(PencilDev pd, UpdMany U,
+                                                         const double* __restrict__ dinv,
+                                                         int64_t n_pad, double tol,
+                                                         int32_t* __restrict__ skip_part,
+                                                         int32_t* __restrict__ need) {
+  __shared__ int32_t cnt[kManyMax][4], req[kManyMax][4];
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int wv = threadIdx.x >> 6;
+  const bool in = j < pd.n;
+  int len = 0;
+  int32_t col[MJ];
+  double mm[MJ], kq[MJ];
+  if (in) {
+    const int32_t base = pd.slice_ptr[j / kSlice] + (int32_t)(j % kSlice);
+    len = pd.row_len[j];
+#pragma unroll
+    for (int u = 0; u < MJ; ++u) {
+      col[u] = 0;
+      mm[u] = kq[u] = 0.0;
+      if (u < len) {
+        const int32_t idx = base + u * kSlice;
+        col[u] = pd.col[idx];
+        mm[u] = pd.m64[idx];
+        kq[u] = pd.k64[idx];
+      }
+    }
+  }
+  // alpha and the diagonal scalings of the row and its columns for shift q;
+  // the next shift's are loaded while the current one is tested
+  auto scal = [&](int q, double& al, double& sr, double (&dc)[MJ]) {
+    const double* __restrict__ dv = dinv + (int64_t)q * n_pad;
+    al = *U.alpha[q];
+    sr = dv[j];
+#pragma unroll
+    for (int u = 0; u < MJ; ++u) dc[u] = u < len ? dv[col[u]] : 0.0;
+  };
+  double al0 = 0.0, sr0 = 0.0, dc0[MJ] = {};
+  if (in && U.count > 0) scal(0, al0, sr0, dc0);
+  for (int s = 0; s < U.count; ++s) {
+    double al1 = 0.0, sr1 = 0.0, dc1[MJ] = {};
+    if (in && s + 1 < U.count) scal(s + 1, al1, sr1, dc1);
+    bool skipped = false, solve = false;
+    if (in) {
+      const double al = al0, sr = sr0;
+      double n_old = 0, n_res = 0;
+#pragma unroll
+      for (int u = 0; u < MJ; ++u) {
+        if (u < len) {
+          const double dc = dc0[u];
+          const double v_n = fma(U.a[s], mm[u], U.b[s] * kq[u]) * sr * dc;
+          const double v_o = fma(U.ao[s], mm[u], U.bo[s] * kq[u]) * sr * dc;
+          const double d = fma(-al, v_n, v_o);
+          n_old = fma(v_o, v_o, n_old);
+          n_res = fma(d, d, n_res);
+        }
+      }
+      if (sqrt(n_res) <= tol * sqrt(n_old)) {
+        skipped = true;
+        U.obj[s][j] = sqrt(n_res);
+      } else {
+        solve = true;
+      }
+      U.skipf[s][j] = skipped ? 1 : 0;
+    }
+    al0 = al1;
+    sr0 = sr1;
+#pragma unroll
+    for (int u = 0; u < MJ; ++u) dc0[u] = dc1[u];
+    const unsigned long long bs = __ballot(skipped), bn = __ballot(solve);
+    if ((threadIdx.x & 63) == 0) {
+      cnt[s][wv] = (int32_t)__popcll(bs);
+      req[s][wv] = bn != 0ull ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  const int64_t nb = gridDim.x;
+  if ((int)threadIdx.x < U.count) {
+    const int s = threadIdx.x;
+    int32_t c = 0, r = 0;
+    for (int w = 0; w < 4; ++w) {
+      c += cnt[s][w];
+      r |= req[s][w];
+    }
+    skip_part[(int64_t)s * nb + blockIdx.x] = c;
+    need[(int64_t)s * nb + blockIdx.x] = r;
+  }
+}
+
 // The banded update column kernel for every shift of the batch: the block's
 // rows are staged once (M, K, columns), then per shift their scaled values
 // are formed and the columns solved as in k_spai_band.  hat: [count][stored].
+// need (NULL: every block and shift): per (shift, block) whether any column
+// failed the skip test of k_update_test_many, which has already written the
+// flags, objectives and skipped counts; a block with nothing to solve for
+// any shift returns before staging, and a shift with nothing to solve is
+// passed over.
 template <int MJ, int RANGE>
 __global__ void __launch_bounds__(256) k_spai_update_many(PencilDev pd, UpdMany U,
                                                           const double* __restrict__ dinv,
                                                           int64_t n_pad, int64_t stored, int bw,
                                                           double tol, double* __restrict__ hat,
-                                                          int32_t* __restrict__ skip_part) {
+                                                          int32_t* __restrict__ skip_part,
+                                                          const int32_t* __restrict__ need) {
+  if (need) {
+    bool any = false;
+    for (int s = 0; s < U.count; ++s) any = any || need[(int64_t)s * gridDim.x + blockIdx.x] != 0;
+    if (!any) return;  // the whole block: before any barrier
+  }
   extern __shared__ double lds[];
   const int S = 256 + 4 * bw;
   double* mm = lds;
@@ -1355,6 +1475,8 @@ __global__ void __launch_bounds__(256) k_spai_update_many(PencilDev pd, UpdMany 
   }
   const int64_t nb = gridDim.x;
   for (int s = 0; s < U.count; ++s) {
+    // the same for every thread of the block
+    if (need && need[(int64_t)s * nb + blockIdx.x] == 0) continue;
     const double* __restrict__ dv = dinv + (int64_t)s * n_pad;
     double* __restrict__ hs = hat + (int64_t)s * stored;
     __syncthreads();  // staged rows ready; the previous shift's columns done
@@ -1429,12 +1551,13 @@ __global__ void k_copy_flags(const int8_t* __restrict__ src, int32_t n, uint8_t*
 // Padding entries are 0.  An update whose every column was skipped
 // (skip_total = n) is the scalar alpha I: it is never applied as a factor,
 // so nothing is written.
-__global__ void k_spai_finalize(PencilDev pd, const double* __restrict__ hat,
-                                const double* __restrict__ dinv, int mode,
-                                const int32_t* __restrict__ skip_total,
-                                const int8_t* __restrict__ skipf, const double* __restrict__ alpha,
-                                double* __restrict__ v64, float* __restrict__ v32) {
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__device__ __forceinline__ void finalize_row(const PencilDev& pd, int64_t r,
+                                             const double* __restrict__ hat,
+                                             const double* __restrict__ dinv, int mode,
+                                             const int32_t* __restrict__ skip_total,
+                                             const int8_t* __restrict__ skipf,
+                                             const double* __restrict__ alpha,
+                                             double* __restrict__ v64, float* __restrict__ v32) {
   if (r >= (int64_t)pd.n_slices * kSlice) return;
   if (skip_total && *skip_total == pd.n) return;
   const int64_t s = r / kSlice;
@@ -1456,6 +1579,26 @@ __global__ void k_spai_finalize(PencilDev pd, const double* __restrict__ hat,
     v64[idx] = val;
     v32[idx] = (float)val;
   }
+}
+
+__global__ void k_spai_finalize(PencilDev pd, const double* __restrict__ hat,
+                                const double* __restrict__ dinv, int mode,
+                                const int32_t* __restrict__ skip_total,
+                                const int8_t* __restrict__ skipf, const double* __restrict__ alpha,
+                                double* __restrict__ v64, float* __restrict__ v32) {
+  finalize_row(pd, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, hat, dinv, mode, skip_total,
+               skipf, alpha, v64, v32);
+}
+
+// k_spai_finalize of the updates of a batch, one grid row (blockIdx.y) per
+// update: hat [count][stored], dinv [count][n_pad].
+__global__ void k_update_finalize_many(PencilDev pd, UpdMany U, const double* __restrict__ hat,
+                                       const double* __restrict__ dinv, int64_t stored,
+                                       int64_t n_pad) {
+  const int s = blockIdx.y;
+  finalize_row(pd, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, hat + (int64_t)s * stored,
+               dinv + (int64_t)s * n_pad, 2, U.skip[s], U.skipf[s], U.alpha[s], U.v64[s],
+               U.v32[s]);
 }
 
 // out[e] (CSR order) = values[stored idx]
@@ -1892,14 +2035,16 @@ static airga_status run_update_many(airga_ctx ctx, int32_t count, const airga_pr
   const bool range = 4 * bw + 1 <= pen.max_len * pen.max_len;
   for (int i0 = 0; i0 < count; i0 += kManyMax) {
     const int cnt = count - i0 < kManyMax ? count - i0 : kManyMax;
-    // scratch: [dinv (cnt n_pad) | hat (cnt stored) | alpha partials | skip counts]
-    const size_t need = sizeof(double) * ((size_t)cnt * (n_pad + stored) + 2 * (size_t)cnt * nb) +
-                        sizeof(int32_t) * (size_t)cnt * nb + 64;
-    AIRGA_TRY(ctx->ws_tmp.reserve(need));
+    // scratch: [dinv (cnt n_pad) | hat (cnt stored) | alpha partials | skip
+    // counts | blocks with columns to solve]
+    const size_t bytes = sizeof(double) * ((size_t)cnt * (n_pad + stored) + 2 * (size_t)cnt * nb) +
+                         2 * sizeof(int32_t) * (size_t)cnt * nb + 64;
+    AIRGA_TRY(ctx->ws_tmp.reserve(bytes));
     double* dinv = ctx->ws_tmp.as<double>();
     double* hat = dinv + (size_t)cnt * n_pad;
     double* part = hat + (size_t)cnt * stored;
     int32_t* skp = reinterpret_cast<int32_t*>(part + 2 * (size_t)cnt * nb);
+    int32_t* need = skp + (size_t)cnt * nb;
     UpdMany U;
     std::memset(static_cast<void*>(&U), 0, sizeof U);
     U.count = cnt;
@@ -1918,26 +2063,30 @@ static airga_status run_update_many(airga_ctx ctx, int32_t count, const airga_pr
     AIRGA_HIP(hipGetLastError());
     k_alpha_final_many<<<(unsigned)cnt, 256, 0, st>>>(U, part, nb);
     AIRGA_HIP(hipGetLastError());
+    k_update_test_many<6><<<nb, 256, 0, st>>>(pd, U, dinv, n_pad, o.tol, skp, need);
+    AIRGA_HIP(hipGetLastError());
     const size_t lds = spai_many_lds<6>(bw);
     if (range && pen.contiguous)
       k_spai_update_many<6, 2><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, o.tol, hat,
-                                                     skp);
+                                                     skp, need);
     else if (range)
       k_spai_update_many<6, 1><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, o.tol, hat,
-                                                     skp);
+                                                     skp, need);
     else
       k_spai_update_many<6, 0><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, o.tol, hat,
-                                                     skp);
+                                                     skp, need);
     AIRGA_HIP(hipGetLastError());
     k_sum_counts_many<<<(unsigned)cnt, 256, 0, st>>>(U, skp, nb);
     AIRGA_HIP(hipGetLastError());
-    const unsigned nr = blocks_for(n_pad, 256);
+    for (int i = 0; i < cnt; ++i) {
+      U.v64[i] = ps[i0 + i]->v64.as<double>();
+      U.v32[i] = ps[i0 + i]->v32.as<float>();
+    }
+    k_update_finalize_many<<<dim3(blocks_for(n_pad, 256), (unsigned)cnt), 256, 0, st>>>(
+        pd, U, hat, dinv, stored, n_pad);
+    AIRGA_HIP(hipGetLastError());
     for (int i = 0; i < cnt; ++i) {
       const airga_prec p = ps[i0 + i];
-      k_spai_finalize<<<nr, 256, 0, st>>>(pd, hat + (size_t)i * stored, dinv + (size_t)i * n_pad, 2,
-                                          U.skip[i], U.skipf[i], U.alpha[i], p->v64.as<double>(),
-                                          p->v32.as<float>());
-      AIRGA_HIP(hipGetLastError());
       p->is_update = true;
       p->parent = olds[i0 + i];
       olds[i0 + i]->refs++;
