@@ -638,9 +638,11 @@ class Context:
         self._leave()
         return out
 
-    def spai_build_complex(self, s: complex, *, equilibrate=True, symmetrize=True) -> "Prec":
-        """SPAI of K(s) for a complex expansion point s."""
-        o = self._spai_opts(None, equilibrate, symmetrize)
+    def spai_build_complex(self, s: complex, *, equilibrate=True, symmetrize=True,
+                           general_only=False) -> "Prec":
+        """SPAI of K(s) for a complex expansion point s (general_only: the
+        Givens column kernel even where the normal-equation kernel applies)."""
+        o = self._spai_opts(None, equilibrate, symmetrize, general_only)
         h = ctypes.c_void_p()
         s = complex(s)
         self._enter()

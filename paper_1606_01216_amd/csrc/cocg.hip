@@ -124,13 +124,16 @@ __device__ __forceinline__ int32_t row_base(const PencilDev& pd, int64_t r) {
 // entries Khat(r, J_u) are picked from row r's own storage (the pattern is
 // symmetric).  The solution is written at row j's own positions (column j's
 // coefficient for row J_t at entry t of row j).
+// redo (NULL: every column): only the columns flagged there.
 template <int MJ>
 __global__ void __launch_bounds__(64) k_cspai_cols(PencilDev pd, cplx a, cplx b,
                                                    const cplx* __restrict__ dinv,
                                                    cplx* __restrict__ hat,
-                                                   double* __restrict__ obj) {
+                                                   double* __restrict__ obj,
+                                                   const int8_t* __restrict__ redo) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= pd.n) return;
+  if (redo && !redo[j]) return;
   const int32_t bj = row_base(pd, j);
   const int nj = pd.row_len[j];
   int32_t J[MJ];
@@ -234,6 +237,167 @@ __global__ void __launch_bounds__(64) k_cspai_cols(PencilDev pd, cplx a, cplx b,
       if (u > q && u < nj) acc = acc - R[dq + (u - q)] * p[u];
     p[q] = cdiv(acc, R[dq]);
   }
+#pragma unroll
+  for (int t = 0; t < MJ; ++t)
+    if (t < nj) hat[bj + t * kSlice] = p[t];
+  obj[j] = sqrt(res2);
+}
+
+// The same column problems from their normal equations, for pencils whose
+// rows are consecutive columns in a narrow band (the beam's).  With Khat
+// complex symmetric, B = Khat(I, J) has
+//     B^H B = (conj(Khat) Khat)(J, J),   B^H e_j = conj(Khat(J, j)),
+// because the columns J vanish outside the rows I: every column's Gram
+// matrix is a block of the one banded Hermitian matrix H = conj(Khat) Khat,
+//     H(i, i + d) = sum over k of conj(Khat(i, k)) Khat(i + d, k).
+// One wavefront solves 64 consecutive columns: it stages the scaled rows
+// of its window in LDS, forms the upper band of H for the rows the columns'
+// patterns cover, and each lane takes the complex Cholesky G = U^H U of its
+// column's block (real positive diagonal) and the two triangular solves.
+// The residual follows from ||e_j - B p||^2 = 1 - 2 Re(g^H p) + p^H G p.
+// After equilibration the blocks are well conditioned on the beam (cond(B)
+// below 15 at the points sigma e^(i pi/6)); a column whose Cholesky loses
+// more than 8 digits (a pivot below 1e-8 of its diagonal) is flagged in
+// redo and solved by k_cspai_cols instead.  The solution is written as
+// k_cspai_cols writes it (column j's coefficients at row j's positions).
+//   LDS per wavefront: scaled values vn[MJ][WR] (complex), first column and
+//   length of each window row, the band hb[R2][2 bw + 1] (complex);
+//   WR = R2 = 64 + 2 bw.
+constexpr int kCGramMaxBw = 8;
+// packed upper-triangular index of (k, l), k <= l, in an MJ x MJ factor
+template <int MJ>
+__device__ constexpr int ctri(int k, int l) {
+  return k * MJ - (k * (k - 1)) / 2 + (l - k);
+}
+__host__ __device__ inline size_t cspai_gram_lds(int bw, int mj) {
+  const size_t wr = 64 + 2 * (size_t)bw;
+  return wr * (mj * sizeof(cplx) + 2 * sizeof(int32_t)) + wr * (2 * (size_t)bw + 1) * sizeof(cplx);
+}
+
+template <int MJ>
+__global__ void __launch_bounds__(64) k_cspai_gram(PencilDev pd, cplx a, cplx b,
+                                                   const cplx* __restrict__ dinv, int bw,
+                                                   cplx* __restrict__ hat,
+                                                   double* __restrict__ obj,
+                                                   int8_t* __restrict__ redo) {
+  extern __shared__ double lds_c[];
+  const int lane = threadIdx.x;
+  const int WR = 64 + 2 * bw;   // window rows [o0 - bw, o0 + 64 + bw)
+  const int BW2 = 2 * bw + 1;
+  cplx* vn = reinterpret_cast<cplx*>(lds_c);
+  int32_t* f0 = reinterpret_cast<int32_t*>(vn + MJ * WR);
+  int32_t* ln = f0 + WR;
+  cplx* hb = reinterpret_cast<cplx*>(ln + WR);
+  const int64_t n = pd.n;
+  const int64_t o0 = (int64_t)blockIdx.x * 64;  // first column
+  const int64_t w0 = o0 - bw;                   // first window row
+  for (int r = lane; r < WR; r += 64) {
+    const int64_t row = w0 + r;
+    const bool in = row >= 0 && row < n;
+    const int len = in ? pd.row_len[row] : 0;
+    const int32_t base = in ? row_base(pd, row) : 0;
+    ln[r] = len;
+    f0[r] = len > 0 ? pd.col[base] : 0;
+    const cplx sr = in ? dinv[row] : cx(0.0);
+#pragma unroll
+    for (int k = 0; k < MJ; ++k) {
+      cplx v = cx(0.0);
+      if (k < len) {
+        const int32_t idx = base + k * kSlice;
+        const double mv = pd.m64[idx], kv = pd.k64[idx];
+        const cplx kv2 = cplx{fma(a.re, mv, b.re * kv), fma(a.im, mv, b.im * kv)};
+        v = (kv2 * sr) * dinv[pd.col[idx]];
+      }
+      vn[k * WR + r] = v;
+    }
+  }
+  __syncthreads();
+  // upper band of H, one (row, offset) entry per lane and pass
+  for (int e = lane; e < WR * BW2; e += 64) {
+    const int q = e / BW2, d = e - q * BW2;
+    const int cr = q + d;
+    cplx acc = cx(0.0);
+    if (cr < WR) {
+      const int li = ln[q], lc = ln[cr];
+      if (li > 0 && lc > 0) {
+        const int i0 = f0[q], cf = f0[cr];
+        const int lo = i0 > cf ? i0 : cf;
+        const int hi = (i0 + li < cf + lc) ? i0 + li : cf + lc;
+        for (int k = lo; k < hi; ++k) cfma(acc, conj(vn[(k - i0) * WR + q]), vn[(k - cf) * WR + cr]);
+      }
+    }
+    hb[e] = acc;
+  }
+  __syncthreads();
+  const int64_t j = o0 + lane;
+  if (j >= n) return;
+  const int jr = (int)(j - w0);
+  const int nj = ln[jr];
+  const int J0 = f0[jr];  // J = J0 .. J0 + nj - 1
+  cplx Uf[MJ * (MJ + 1) / 2], y[MJ], g[MJ], p[MJ];
+  double iu[MJ];
+  bool good = nj > 0;
+#pragma unroll
+  for (int k = 0; k < MJ; ++k) {
+    y[k] = g[k] = p[k] = cx(0.0);
+    iu[k] = 0.0;
+    if (k < nj) {
+      const cplx* hk = hb + (J0 + k - (int)w0) * BW2;  // H(J_k, J_k + d)
+      g[k] = conj(vn[k * WR + jr]);                     // conj(Khat(j, J_k))
+      double dkk = hk[0].re;
+#pragma unroll
+      for (int m = 0; m < MJ; ++m)
+        if (m < k) dkk -= abs2(Uf[ctri<MJ>(m, k)]);
+      good = good && dkk > 1e-8 * hk[0].re;
+      const double inv = dkk > 0.0 ? 1.0 / sqrt(dkk) : 0.0;
+      iu[k] = inv;
+      Uf[ctri<MJ>(k, k)] = cx(dkk * inv);
+#pragma unroll
+      for (int i = 0; i < MJ; ++i) {
+        if (i > k && i < nj) {
+          cplx gik = hk[i - k];  // G(k, i) = H(J_k, J_i), i > k
+#pragma unroll
+          for (int m = 0; m < MJ; ++m)
+            if (m < k) gik = gik - conj(Uf[ctri<MJ>(m, k)]) * Uf[ctri<MJ>(m, i)];
+          Uf[ctri<MJ>(k, i)] = inv * gik;
+        }
+      }
+      cplx yk = g[k];
+#pragma unroll
+      for (int m = 0; m < MJ; ++m)
+        if (m < k) yk = yk - conj(Uf[ctri<MJ>(m, k)]) * y[m];
+      y[k] = inv * yk;
+    }
+  }
+  redo[j] = good ? 0 : 1;
+  if (!good) return;
+#pragma unroll
+  for (int k = MJ - 1; k >= 0; --k) {
+    if (k < nj) {
+      cplx acc = y[k];
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i > k && i < nj) acc = acc - Uf[ctri<MJ>(k, i)] * p[i];
+      p[k] = iu[k] * acc;
+    }
+  }
+  // ||e_j - B p||^2 = 1 - 2 Re(g^H p) + p^H G p, G Hermitian from the band
+  double ghp = 0.0, pgp = 0.0;
+#pragma unroll
+  for (int k = 0; k < MJ; ++k) {
+    if (k < nj) {
+      const cplx* hk = hb + (J0 + k - (int)w0) * BW2;
+      ghp += (conj(g[k]) * p[k]).re;
+      double row = hk[0].re * abs2(p[k]);
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i > k && i < nj) row += 2.0 * (conj(p[k]) * (hk[i - k] * p[i])).re;
+      pgp += row;
+    }
+  }
+  double res2 = fma(-2.0, ghp, 1.0) + pgp;
+  res2 = res2 > 0.0 ? res2 : 0.0;
+  const int32_t bj = row_base(pd, j);
 #pragma unroll
   for (int t = 0; t < MJ; ++t)
     if (t < nj) hat[bj + t * kSlice] = p[t];
@@ -693,8 +857,22 @@ airga_status airga_spai_build_complex(airga_ctx ctx, double s_re, double s_im,
   hipStream_t s = ctx->stream;
   const PencilDev pd = pen.dev();
   k_cdinv<<<blocks_for((int64_t)npad, 256), 256, 0, s>>>(pd, a, b, o.equilibrate ? 1 : 0, dinv);
+  // equilibrated builds on narrow bands of consecutive columns: normal
+  // equations, with the Givens kernel for the columns they cannot take
+  const bool gram = !o.general_only && o.equilibrate && pen.contiguous && pen.max_len <= 6 &&
+                    pen.bandwidth <= kCGramMaxBw;
+  int8_t* redo = nullptr;
+  if (gram) {
+    if ((st = ctx->ws_gather.reserve((size_t)pen.n)) != AIRGA_OK) {
+      airga_prec_release(p);
+      return st;
+    }
+    redo = ctx->ws_gather.as<int8_t>();
+    k_cspai_gram<6><<<blocks_for(pen.n, 64), 64, cspai_gram_lds(pen.bandwidth, 6), s>>>(
+        pd, a, b, dinv, pen.bandwidth, hat, p->objective.as<double>(), redo);
+  }
   k_cspai_cols<6><<<blocks_for(pen.n, 64), 64, 0, s>>>(pd, a, b, dinv, hat,
-                                                       p->objective.as<double>());
+                                                       p->objective.as<double>(), redo);
   k_cspai_finalize<<<blocks_for((int64_t)npad, 256), 256, 0, s>>>(pd, hat, dinv,
                                                                   o.symmetrize ? 1 : 0,
                                                                   p->v64.as<cplx>());
