@@ -287,8 +287,17 @@ def spai_build(a: sp.csr_matrix, *, equilibrate=True, symmetrize=True, cols=None
                   pick_margin=pick if lfil > 0 else None)
 
 
-def update_alpha(k_old: sp.csr_matrix, k_new: sp.csr_matrix) -> float:
-    """Minimiser of ||K_old - alpha K_new||_F as derived in Section 3.2."""
+def update_alpha(k_old: sp.csr_matrix, k_new: sp.csr_matrix):
+    """Minimiser of ||K_old - alpha K_new||_F as derived in Section 3.2.
+
+    For complex matrices (complex expansion points) alpha ranges over the
+    complex numbers and the minimiser is <K_new, K_old> / <K_new, K_new>
+    with the Hermitian inner product <A, B> = trace(A^H B); for real
+    matrices this is the formula of Section 3.2."""
+    if np.iscomplexobj(k_old.data) or np.iscomplexobj(k_new.data):
+        num = (k_new.conj().T @ k_old).diagonal().sum()
+        den = (k_new.conj().T @ k_new).diagonal().sum().real
+        return complex(num / den)
     num = 0.5 * ((k_old.T @ k_new).diagonal().sum() + (k_new.T @ k_old).diagonal().sum())
     return float(num / (k_new.T @ k_new).diagonal().sum())
 
@@ -297,7 +306,10 @@ def spai_update(a_old: sp.csr_matrix, a_new: sp.csr_matrix, *, tol=0.01, equilib
                 cols=None, mr_iters=0, lfil=0) -> Factor:
     """Q with K_new Q ~ K_old (Section 3.2), on the structural pattern;
     ``mr_iters`` > 0 selects the minimal-residual loop of Algorithm 4, and
-    ``lfil`` > 0 its pattern control."""
+    ``lfil`` > 0 its pattern control.  Complex K_old, K_new (complex
+    expansion points): complex alpha (update_alpha), S_new from the principal
+    square root, complex column least squares; the minimal-residual mode is
+    real only."""
     if lfil < 0 or (lfil > 0 and mr_iters <= 0):
         raise ValueError("lfil applies to the minimal-residual mode")
     n = a_new.shape[0]
@@ -305,17 +317,21 @@ def spai_update(a_old: sp.csr_matrix, a_new: sp.csr_matrix, *, tol=0.01, equilib
     if not (np.array_equal(a_old.indptr, rp) and np.array_equal(a_old.indices, ci)):
         raise ValueError("K_old and K_new must share one pattern")
     rows = _rows_of(rp, n)
-    d = a_new.diagonal()
-    s = 1.0 / np.sqrt(d) if equilibrate else np.ones(n)
-    new_hat = _scaled_values(a_new.data, rows, ci, s, s)
-    old_hat = _scaled_values(a_old.data, rows, ci, s, s)
+    cplx = np.iscomplexobj(a_new.data) or np.iscomplexobj(a_old.data)
+    if cplx and mr_iters > 0:
+        raise ValueError("the minimal-residual mode is for real shifts only")
+    dt = complex if cplx else np.float64
+    d = a_new.diagonal().astype(dt)
+    s = 1.0 / np.sqrt(d) if equilibrate else np.ones(n, dtype=dt)
+    new_hat = _scaled_values(a_new.data.astype(dt), rows, ci, s, s)
+    old_hat = _scaled_values(a_old.data.astype(dt), rows, ci, s, s)
     k_new_hat = sp.csr_matrix((new_hat, ci, rp), shape=(n, n))
     k_old_hat = sp.csr_matrix((old_hat, ci, rp), shape=(n, n))
     alpha = update_alpha(k_old_hat, k_new_hat)
     indptr, crow, cpos = _csc_positions(n, rp, ci)
     cnew = new_hat[cpos]
     cold = old_hat[cpos]
-    hat = np.full(len(ci), np.nan)
+    hat = np.full(len(ci), np.nan, dtype=dt)
     obj = np.full(n, np.nan)
     skipped = np.zeros(n, bool)
     iters = np.zeros(n, np.int64)
@@ -332,11 +348,11 @@ def spai_update(a_old: sp.csr_matrix, a_new: sp.csr_matrix, *, tol=0.01, equilib
             margin[j] = abs(np.linalg.norm(r0) / thr - 1.0)
         if np.linalg.norm(r0) <= thr:
             skipped[j] = True
-            q = alpha * (jj == j).astype(np.float64)
+            q = alpha * (jj == j).astype(dt)
             obj[j] = np.linalg.norm(r0)
         else:
             ii, jj2, blk = _column_problem(indptr, crow, cnew, j)
-            rhs = np.zeros(len(ii))
+            rhs = np.zeros(len(ii), dtype=dt)
             jpos = np.searchsorted(ii, jj)
             rhs[jpos] = kold_j
             if mr_iters > 0:
@@ -361,7 +377,9 @@ def chain_apply(factors, r: np.ndarray) -> np.ndarray:
     """z = Q_z ( ... Q_2 ( P_1 r ) ): ``factors`` lists P_1 first, then each
     update factor in the order it was computed; only products with vectors
     are formed."""
-    z = np.asarray(r, dtype=np.float64)
+    z = np.asarray(r)
+    if not np.iscomplexobj(z):
+        z = z.astype(np.float64)
     for fac in factors:
         z = fac.matrix() @ z
     return z

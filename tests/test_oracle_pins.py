@@ -1037,6 +1037,83 @@ def test_complex_spai_special_cases():
         assert f(al) <= f(al * (1 + dz))
 
 
+def test_complex_update_alpha_is_the_frobenius_minimiser():
+    # ||K_old - alpha K_new||_F over complex alpha = x + i y is a real linear
+    # least-squares problem in (x, y): stack the real and imaginary parts
+    pen = _cbeam(12)
+    for s_old, s_new in ((3.0 + 2.0j, 3.3 + 2.1j), (1.0 + 0.1j, 0.5 - 4.0j)):
+        ko = pencil.shifted_operator_complex(pen, s_old).toarray().ravel()
+        kn = pencil.shifted_operator_complex(pen, s_new).toarray().ravel()
+        a = np.stack([np.concatenate([kn.real, kn.imag]),
+                      np.concatenate([-kn.imag, kn.real])], axis=1)
+        xy, *_ = np.linalg.lstsq(a, np.concatenate([ko.real, ko.imag]), rcond=None)
+        al = spai.update_alpha(pencil.shifted_operator_complex(pen, s_old),
+                               pencil.shifted_operator_complex(pen, s_new))
+        assert abs(al - complex(xy[0], xy[1])) <= 1e-13 * abs(al)
+    # real matrices: the formula of Section 3.2 (a real number)
+    ar, br = pencil.shifted_operator(pen, 2.0), pencil.shifted_operator(pen, 2.5)
+    al = spai.update_alpha(ar, br)
+    assert isinstance(al, float)
+    assert abs(al - np.vdot(br.toarray(), ar.toarray()) / np.vdot(br.toarray(), br.toarray())) <= \
+        1e-14 * abs(al)
+
+
+@pytest.mark.parametrize("s_old,s_new", [(3.0 + 2.0j, 3.6 + 2.3j), (100.0 + 50.0j, 60.0 + 45.0j),
+                                         (1.0 + 2.0j, 1.5 + 2.5j)])
+def test_complex_update_columns_are_least_squares_optimal(s_old, s_new):
+    # solved columns satisfy the normal equations of min ||khat_old_j -
+    # Khat_new(:, J) q|| (Khat = S K S, S from the principal square root of
+    # diag K(s_new)); skipped ones are alpha e_j; Q = S Qhat S^{-1}
+    pen = _cbeam(30)
+    ao = pencil.shifted_operator_complex(pen, s_old)
+    an = pencil.shifted_operator_complex(pen, s_new)
+    q = spai.spai_update(ao, an, tol=0.05)
+    assert 0 < q.skipped.sum() < pen.n, q.skipped.sum()
+    sc = 1 / np.sqrt(an.diagonal())
+    kn = (sp.diags(sc) @ an @ sp.diags(sc)).toarray()
+    ko = (sp.diags(sc) @ ao @ sp.diags(sc)).toarray()
+    qm = q.matrix().toarray()
+    qhat = np.diag(1 / sc) @ qm @ np.diag(sc)
+    for j in range(pen.n):
+        jj = pen.col_idx[pen.row_ptr[j]:pen.row_ptr[j + 1]]
+        assert np.count_nonzero(qhat[:, j][np.setdiff1d(np.arange(pen.n), jj)]) == 0
+        if q.skipped[j]:
+            want = np.zeros(pen.n, complex)
+            want[j] = q.alpha
+            assert np.allclose(qhat[:, j], want, rtol=1e-14, atol=0)
+            continue
+        res = ko[:, j] - kn[:, jj] @ qhat[jj, j]
+        assert np.linalg.norm(kn[:, jj].conj().T @ res) <= 1e-12 * np.linalg.norm(kn[:, jj]) * \
+            np.linalg.norm(ko[:, j])
+        assert abs(q.objective[j] - np.linalg.norm(res)) <= 1e-12 * np.linalg.norm(ko[:, j])
+    # real shifts given as complex numbers: the real update
+    qr = spai.spai_update(pencil.shifted_operator_complex(pen, 4.0),
+                          pencil.shifted_operator_complex(pen, 4.6), tol=0.05)
+    qx = spai.spai_update(pencil.shifted_operator(pen, 4.0), pencil.shifted_operator(pen, 4.6),
+                          tol=0.05)
+    assert np.array_equal(qr.skipped, qx.skipped)
+    # (the complex and real least-squares routines round differently)
+    assert np.allclose(qr.values.real, qx.values, rtol=0, atol=1e-12 * np.abs(qx.values).max())
+    assert np.abs(qr.values.imag).max() == 0.0
+
+
+def test_cocg_with_an_update_chain_reaches_the_solution():
+    # the chain Q P (P built at s_old, Q its update to s_new) preconditions
+    # COCG on K(s_new) to the dense solution, with the flexible beta
+    pen = _cbeam(50)
+    f = np.random.default_rng(5).standard_normal(pen.n)
+    s_old, s_new = 3.0 + 2.0j, 3.9 + 2.6j
+    ao = pencil.shifted_operator_complex(pen, s_old)
+    an = pencil.shifted_operator_complex(pen, s_new)
+    p1 = spai.spai_build(ao)
+    q2 = spai.spai_update(ao, an, tol=0.01)
+    r = pcg.cocg(lambda v: an @ v, lambda v: spai.chain_apply([p1, q2], v), f, tol=1e-12,
+                 max_iter=4000)
+    x = np.linalg.solve(an.toarray(), f)
+    assert r.status == pcg.CONVERGED
+    assert np.linalg.norm(r.x - x) <= 1e-9 * np.linalg.norm(x)
+
+
 def test_cocg_matches_the_dense_solve_and_cg_on_real_data():
     pen = _cbeam(50)
     rng = np.random.default_rng(3)
