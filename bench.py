@@ -473,13 +473,16 @@ def oracle_refs(pen, shift_list, f, precision, workers):
         return list(ex.map(job, shift_list))
 
 
-def median_time(fn, reps=3):
-    """(median seconds over reps runs, result of the last run)."""
+def median_time(fn, reps=3, label=None):
+    """(median seconds over reps runs, result of the last run); with a label,
+    one progress line per run."""
     ts, res = [], None
-    for _ in range(reps):
+    for i in range(reps):
         t0 = time.perf_counter()
         res = fn()
         ts.append(time.perf_counter() - t0)
+        if label:
+            log(f"[bench] {label}: run {i + 1} of {reps}, {ts[-1]:.2f} s")
     return statistics.median(ts), res
 
 
@@ -492,10 +495,14 @@ def measure_cpu_baseline(pen, f, shift_sets, sample_shifts=4, reps=3):
     allsh = [s for ss in shift_sets for s in ss]
     m = f.shape[0]
     sample = list(shift_sets[0][:sample_shifts])
-    t_dd1, _ = median_time(lambda: oracle_refs(pen, sample, f, "dd", 1), reps)
-    t_ddw, refs_dd = median_time(lambda: oracle_refs(pen, allsh, f, "dd", workers), reps)
-    t_641, _ = median_time(lambda: oracle_refs(pen, sample, f, "f64", 1), reps)
-    t_64w, refs_64 = median_time(lambda: oracle_refs(pen, allsh, f, "f64", workers), reps)
+    t_dd1, _ = median_time(lambda: oracle_refs(pen, sample, f, "dd", 1), reps,
+                           "oracle double-double, one thread")
+    t_ddw, refs_dd = median_time(lambda: oracle_refs(pen, allsh, f, "dd", workers), reps,
+                                 f"oracle double-double, {workers} threads")
+    t_641, _ = median_time(lambda: oracle_refs(pen, sample, f, "f64", 1), reps,
+                           "oracle binary64, one thread")
+    t_64w, refs_64 = median_time(lambda: oracle_refs(pen, allsh, f, "f64", workers), reps,
+                                 f"oracle binary64, {workers} threads")
     ns, na = len(sample) * m, len(allsh) * m
     return dict(cpu_model=model, cores_visible=visible, cores_all=workers,
                 dd_1=ns / t_dd1, dd_all=na / t_ddw, f64_1=ns / t_641, f64_all=na / t_64w,
@@ -652,10 +659,52 @@ def measure_complex(ctx, stream, pen, f, F, sigmas, tol, reps=3, angle=np.pi / 6
     Xh = X.cpu().numpy()
     errs = [rel_errors_c(Xh[k, c], refs[k][c]) for k in range(len(cs)) for c in range(m)]
     ok = sum(e <= ERR_TOL for e in errs)
-    for p in precs:
+    # the update to nearby points (each sigma_k moved by a seeded factor
+    # 1 + 0.05 U(-1, 1), same angle) and the solves with the chains Q P
+    drift = np.random.default_rng(7).uniform(-1.0, 1.0, len(cs))
+    cs2 = [complex(z * (1.0 + 0.05 * d)) for z, d in zip(cs, drift)]
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        upd = [ctx.spai_update_complex(p, z) for p, z in zip(precs, cs2)]
+        e1.record(stream)
+        e1.synchronize()
+        upd_ms = e0.elapsed_time(e1) / len(cs)
+        X2 = torch.empty_like(X)
+        # capped: a system whose recurrence residual stalls above tol is
+        # reported as such (with its error) rather than run to 20000 steps
+        ctx.cocg_solve(cs2, upd, F, X2, tol=tol, max_iter=2000)
+        ts2 = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st2 = ctx.cocg_solve(cs2, upd, F, X2, tol=tol, max_iter=2000)
+            torch.cuda.synchronize()
+            ts2.append(time.perf_counter() - t0)
+    infos = [u.info() for u in upd]
+    refs2 = oracle_refs_complex(pen, cs2, f, max(1, min(CPU_WORKERS, cpu_info()[1])))
+    X2h = X2.cpu().numpy()
+    errs2 = [rel_errors_c(X2h[k, c], refs2[k][c]) for k in range(len(cs2)) for c in range(m)]
+    t2 = statistics.median(ts2)
+    its2 = [e["iters"] for e in st2]
+    updates = {"drift": "sigma_k (1 + 0.05 U(-1, 1)), seeded",
+               "spai_update_ms_per_point": round(upd_ms, 4),
+               "skipped_frac_mean": round(statistics.mean(i.skipped_cols / n for i in infos), 4),
+               "chain_len_max": max(i.chain_len for i in infos),
+               "cocg_solves_per_s": round(sum(e <= ERR_TOL for e in errs2) / t2, 2),
+               "seconds_median_of_3": round(t2, 4),
+               "solved_to_1e-8": sum(e <= ERR_TOL for e in errs2), "max_rel_err": max(errs2),
+               "iters_median": statistics.median(its2), "iters_max": max(its2),
+               "converged": sum(e["status"] == airga.SYS_CONVERGED for e in st2),
+               "not_converged": [{"sigma": float(f"{abs(cs2[i // m]):.6g}"), "column": i % m,
+                                  "status": airga.STATUS_NAMES[e["status"]], "iters": e["iters"],
+                                  "relres": float(f"{e['relres']:.3e}"),
+                                  "rel_err": float(f"{errs2[i]:.3e}")}
+                                 for i, e in enumerate(st2) if e["status"] != airga.SYS_CONVERGED]}
+    for p in upd + precs:
         p.release()
     return {"workload": f"{len(cs)} complex points sigma_k e^(i pi/6), sigma_k = the real "
                         f"workload's points; {m} loads; {len(cs) * m} systems",
+            "updates": updates,
             "precision": "complex float64", "spai_build_ms_per_shift": round(build_ms, 4),
             "cocg_solves_per_s": round(ok / t, 2), "seconds_median_of_3": round(t, 4),
             "solved_to_1e-8": ok, "systems": len(errs), "max_rel_err": max(errs),

@@ -226,7 +226,7 @@ typedef struct {
   int64_t skipped_cols; /* columns of the newest factor kept at alpha e_j       */
   double shift_im;      /* complex factors: imaginary part of the shift (else 0)*/
   double alpha_im;      /* complex factors: imaginary part of alpha (else 0)    */
-  int32_t is_complex;   /* 1 for a factor of airga_spai_build_complex           */
+  int32_t is_complex;   /* 1 for a complex factor (build or update)             */
 } airga_prec_info;
 
 /* Describe a preconditioner (synchronises the context stream). */
@@ -385,6 +385,26 @@ AIRGA_API airga_status airga_assemble_shift_complex(airga_ctx ctx, double s_re, 
 AIRGA_API airga_status airga_spai_build_complex(airga_ctx ctx, double s_re, double s_im,
                                                 const airga_spai_opts* opts, airga_prec* out);
 
+/* The SPAI update (Section 3.2, Algorithm 4) from a complex factor `old`
+ * (built or updated at s_old) to the complex point s_new = s_re + i s_im:
+ * Q with K(s_new) Q ~ K(s_old), started from alpha I where alpha minimises
+ * ||Khat_old - alpha Khat_new||_F over complex alpha,
+ *   alpha = <Khat_new, Khat_old> / <Khat_new, Khat_new>
+ * (Hermitian inner product; the paper's formula for real matrices), both
+ * matrices scaled by S = diag(K(s_new))^{-1/2} (principal square root).
+ * Column j keeps q_j = alpha e_j when ||khat_old_j - alpha khat_new_j|| <=
+ * tol ||khat_old_j|| (opts->tol, default 0.01), else it is the complex least
+ * squares min ||khat_old_j - Khat_new(I, J) q|| on the pattern (complex
+ * Givens QR, one column per lane); Q = S Qhat S^{-1}.  The new handle holds
+ * a reference to `old`: airga_cocg_solve applies the chain Q_z ... Q_2 P_1
+ * factor by factor (a fully skipped factor, the scalar alpha I, is dropped).
+ * Synchronises once (alpha and the skip count).  Errors: EINVAL (null
+ * arguments, a real `old`, non-finite s_new, tol < 0, a factor of another
+ * context), ESTATE, EUNSUPPORTED (mr_iters or lfil set), ENOMEM, EHIP. */
+AIRGA_API airga_status airga_spai_update_complex(airga_ctx ctx, airga_prec old, double s_re,
+                                                 double s_im, const airga_spai_opts* opts,
+                                                 airga_prec* out);
+
 /* Export a complex factor: values (device, 2 nnz, interleaved, CSR order)
  * and, if objective is not NULL, the per-column least-squares residual norm
  * (device, n, real).  Asynchronous.  Errors: EINVAL (not a complex factor),
@@ -397,15 +417,17 @@ AIRGA_API airga_status airga_prec_export_complex(airga_prec prec, double* values
  * batched in one set of kernels with per-system convergence masking, in
  * complex float64:
  *   shifts: host, 2 nshift doubles (s_k = shifts[2k] + i shifts[2k+1])
- *   precs:  host, nshift factors of airga_spai_build_complex at the same
- *           shift (or NULL entries: no preconditioner)
+ *   precs:  host, nshift complex factors (airga_spai_build_complex or
+ *           airga_spai_update_complex) at the same shift, or NULL entries
+ *           (no preconditioner); an update applies its whole chain
  *   F:      device, real n x m, leading dimension ldf >= n
  *   X:      device, complex n x m x nshift interleaved, column (c, k) at
  *           X + 2 (k m + c) ldx, ldx >= n (in complex entries)
  *   stats:  host, nshift*m entries in (k, c) order, may be NULL
  * Iteration from X = 0: w = K p, mu = p^T w, alpha = (r^T z) / mu, x += alpha
  * p, r -= alpha w, stop when ||r|| <= tol ||F(:, c)|| (Euclidean norm of
- * the recurrence residual), z = C r, beta = -(z^T w) / mu (flexible,
+ * the recurrence residual), z = C r (C the chain, factor by factor), beta =
+ * -(z^T w) / mu (flexible,
  * default) or (r^T z)_new / (r^T z)_old (beta_form classical), p = z +
  * beta p.  BREAKDOWN when mu = 0; relres in stats is the true residual
  * ||F - K X|| / ||F|| at exit.  Options used: tol, max_iter, poll_every,

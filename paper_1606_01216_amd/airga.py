@@ -148,6 +148,8 @@ _SIGS = [
     ("airga_assemble_shift_complex", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, _P]),
     ("airga_spai_build_complex", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double,
                                                 ctypes.POINTER(SpaiOpts), ctypes.POINTER(_P)]),
+    ("airga_spai_update_complex", ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double,
+                                                 ctypes.POINTER(SpaiOpts), ctypes.POINTER(_P)]),
     ("airga_prec_export_complex", ctypes.c_int, [_P, _P, _P]),
     ("airga_cocg_solve", ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(_P), ctypes.c_int32, _P, ctypes.c_int64,
@@ -648,6 +650,18 @@ class Context:
         self._enter()
         _check(lib().airga_spai_build_complex(self._h, s.real, s.imag, ctypes.byref(o),
                                               ctypes.byref(h)))
+        self._leave()
+        return Prec(self, h)
+
+    def spai_update_complex(self, old: "Prec", s_new: complex, *, tol=0.01,
+                            equilibrate=True) -> "Prec":
+        """Update of the complex factor old to the complex point s_new."""
+        o = self._spai_opts(tol, equilibrate, False)
+        h = ctypes.c_void_p()
+        s_new = complex(s_new)
+        self._enter()
+        _check(lib().airga_spai_update_complex(self._h, old._h, s_new.real, s_new.imag,
+                                               ctypes.byref(o), ctypes.byref(h)))
         self._leave()
         return Prec(self, h)
 

@@ -115,22 +115,83 @@ __device__ __forceinline__ int32_t row_base(const PencilDev& pd, int64_t r) {
   return pd.slice_ptr[r / kSlice] + (int32_t)(r % kSlice);
 }
 
-// Column j's least-squares problem min || e_j(I) - Khat(I, J) p || over
-// complex p, Khat = S K(s) S, J = the pattern of column j (= row j), I =
-// the rows of Khat(:, J).  One lane per column: the rows of the problem are
-// folded one at a time into a complex Givens QR held in registers.  Each
-// row r of I is met through every column J_t whose pattern holds it; it is
-// folded at the first such t only (row r holds no J_u with u < t), and its
-// entries Khat(r, J_u) are picked from row r's own storage (the pattern is
-// symmetric).  The solution is written at row j's own positions (column j's
-// coefficient for row J_t at entry t of row j).
-// redo (NULL: every column): only the columns flagged there.
+// Folds one row (row[0..nj), right-hand side rhs) of a column problem into
+// the complex Givens QR (R packed upper triangular, qtb = Q^H t): one
+// rotation [c s; -conj(s) c] with c real per column turns (R_kk, row_k)
+// into (rho, 0).  Returns what is left of the right-hand side, whose
+// squared modulus adds to the residual.
 template <int MJ>
+__device__ __forceinline__ cplx cgivens_row(cplx (&R)[MJ * (MJ + 1) / 2], cplx (&qtb)[MJ],
+                                            cplx (&row)[MJ], cplx rhs, int nj) {
+#pragma unroll
+  for (int kk = 0; kk < MJ; ++kk) {
+    if (kk >= nj) break;
+    const int dk = kk * MJ - kk * (kk - 1) / 2;  // R(kk, kk) in packed rows
+    const cplx x = R[dk], y = row[kk];
+    const double ay = abs2(y);
+    if (ay == 0.0) continue;
+    const double ax2 = abs2(x);
+    const double nrm = sqrt(ax2 + ay);
+    double c;
+    cplx sn;
+    if (ax2 == 0.0) {
+      c = 0.0;
+      sn = (1.0 / sqrt(ay)) * conj(y);
+      R[dk] = cx(sqrt(ay));
+    } else {
+      const double ax = sqrt(ax2);
+      const cplx ph = (1.0 / ax) * x;  // x / |x|
+      c = ax / nrm;
+      sn = (1.0 / nrm) * (ph * conj(y));
+      R[dk] = nrm * ph;
+    }
+    row[kk] = cx(0.0);
+#pragma unroll
+    for (int q = 0; q < MJ; ++q) {
+      if (q <= kk || q >= nj) continue;
+      const cplx t1 = R[dk + (q - kk)], t2 = row[q];
+      R[dk + (q - kk)] = c * t1 + sn * t2;
+      row[q] = c * t2 - conj(sn) * t1;
+    }
+    const cplx t1 = qtb[kk];
+    qtb[kk] = c * t1 + sn * rhs;
+    rhs = c * rhs - conj(sn) * t1;
+  }
+  return rhs;
+}
+
+// Scaled entry Khat(r, c) = (K(s)_rc S_r) S_c of a shifted matrix with
+// coefficients (a, b) from the pencil's stored entry idx.
+__device__ __forceinline__ cplx cscaled(const PencilDev& pd, int32_t idx, cplx a, cplx b, cplx sr,
+                                        cplx sc) {
+  const double mv = pd.m64[idx], kv = pd.k64[idx];
+  const cplx v = cplx{fma(a.re, mv, b.re * kv), fma(a.im, mv, b.im * kv)};
+  return (v * sr) * sc;
+}
+
+// Column j's least-squares problem min || t(I) - Khat(I, J) p || over
+// complex p, Khat = S K(s) S, J = the pattern of column j (= row j), I =
+// the rows of Khat(:, J); t = e_j (build) or, for the update (Section 3.2
+// at a complex point), t = khat_old_j, the column of S K(s_old) S.  One
+// lane per column: the rows of the problem are folded one at a time into a
+// complex Givens QR held in registers.  Each row r of I is met through
+// every column J_t whose pattern holds it; it is folded at the first such t
+// only (row r holds no J_u with u < t), and its entries Khat(r, J_u) are
+// picked from row r's own storage (the pattern is symmetric).  The solution
+// is written at row j's own positions (column j's coefficient for row J_t at
+// entry t of row j).  redo (NULL: every column): only the columns flagged
+// there.  The update first tests the column: it keeps q_j = alpha e_j
+// (flag skipf[j], counted in *skip_count) when
+// ||khat_old_j - alpha khat_new_j|| <= tol ||khat_old_j||.
+template <int MJ, bool UPDATE>
 __global__ void __launch_bounds__(64) k_cspai_cols(PencilDev pd, cplx a, cplx b,
                                                    const cplx* __restrict__ dinv,
                                                    cplx* __restrict__ hat,
                                                    double* __restrict__ obj,
-                                                   const int8_t* __restrict__ redo) {
+                                                   const int8_t* __restrict__ redo, cplx ao,
+                                                   cplx bo, const double* __restrict__ alpha_d,
+                                                   double tol, int8_t* __restrict__ skipf,
+                                                   int32_t* __restrict__ skip_count) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= pd.n) return;
   if (redo && !redo[j]) return;
@@ -139,6 +200,31 @@ __global__ void __launch_bounds__(64) k_cspai_cols(PencilDev pd, cplx a, cplx b,
   int32_t J[MJ];
 #pragma unroll
   for (int t = 0; t < MJ; ++t) J[t] = t < nj ? pd.col[bj + t * kSlice] : -1;
+  const cplx sj = dinv[j];
+  if constexpr (UPDATE) {
+    const cplx al = cplx{alpha_d[0], alpha_d[1]};
+    double n_old = 0.0, n_res = 0.0;
+#pragma unroll
+    for (int t = 0; t < MJ; ++t) {
+      if (t < nj) {
+        const int32_t idx = bj + t * kSlice;
+        const cplx sc = dinv[J[t]];
+        const cplx vo = cscaled(pd, idx, ao, bo, sj, sc);
+        const cplx d = vo - al * cscaled(pd, idx, a, b, sj, sc);
+        n_old += abs2(vo);
+        n_res += abs2(d);
+      }
+    }
+    const bool skipped = sqrt(n_res) <= tol * sqrt(n_old);
+    skipf[j] = skipped ? 1 : 0;
+    const unsigned long long bal = __ballot(skipped);
+    if ((threadIdx.x & 63) == __ffsll((long long)__ballot(1)) - 1)
+      atomicAdd(skip_count, (int32_t)__popcll(bal));
+    if (skipped) {
+      obj[j] = sqrt(n_res);
+      return;
+    }
+  }
   cplx R[MJ * (MJ + 1) / 2];
   cplx qtb[MJ];
 #pragma unroll
@@ -157,6 +243,7 @@ __global__ void __launch_bounds__(64) k_cspai_cols(PencilDev pd, cplx a, cplx b,
       const cplx sr = dinv[r];
       int32_t cr[MJ];
       cplx vr[MJ];
+      cplx rhs = cx(0.0);
       bool dup = false;
 #pragma unroll
       for (int q = 0; q < MJ; ++q) {
@@ -165,17 +252,20 @@ __global__ void __launch_bounds__(64) k_cspai_cols(PencilDev pd, cplx a, cplx b,
         if (q < nr) {
           const int32_t idx = br + q * kSlice;
           cr[q] = pd.col[idx];
-          const double mv = pd.m64[idx], kv = pd.k64[idx];
-          const cplx v = cplx{fma(a.re, mv, b.re * kv), fma(a.im, mv, b.im * kv)};
-          vr[q] = (v * sr) * dinv[cr[q]];
+          const cplx sc = dinv[cr[q]];
+          vr[q] = cscaled(pd, idx, a, b, sr, sc);
+          if constexpr (UPDATE) {
+            if (cr[q] == (int32_t)j) rhs = cscaled(pd, idx, ao, bo, sr, sc);
+          }
         }
       }
+      if constexpr (!UPDATE) rhs = cx(r == j ? 1.0 : 0.0);
 #pragma unroll
       for (int u = 0; u < MJ; ++u)
 #pragma unroll
         for (int q = 0; q < MJ; ++q) dup |= (u < t) && (cr[q] == J[u]);
       if (dup) continue;
-      // this row of the problem: Khat(r, J_u), right-hand side e_j(r)
+      // this row of the problem: Khat(r, J_u) and t(r)
       cplx row[MJ];
 #pragma unroll
       for (int u = 0; u < MJ; ++u) {
@@ -184,44 +274,7 @@ __global__ void __launch_bounds__(64) k_cspai_cols(PencilDev pd, cplx a, cplx b,
         for (int q = 0; q < MJ; ++q)
           if (cr[q] == J[u]) row[u] = vr[q];
       }
-      cplx rhs = cx(r == j ? 1.0 : 0.0);
-      // fold it into R with one complex Givens rotation per column:
-      // [c s; -conj(s) c] with c real turns (R_kk, row_k) into (rho, 0)
-#pragma unroll
-      for (int kk = 0; kk < MJ; ++kk) {
-        if (kk >= nj) break;
-        const int dk = kk * MJ - kk * (kk - 1) / 2;  // R(kk, kk) in packed rows
-        const cplx x = R[dk], y = row[kk];
-        const double ay = abs2(y);
-        if (ay == 0.0) continue;
-        const double ax2 = abs2(x);
-        const double nrm = sqrt(ax2 + ay);
-        double c;
-        cplx s;
-        if (ax2 == 0.0) {
-          c = 0.0;
-          s = (1.0 / sqrt(ay)) * conj(y);
-          R[dk] = cx(sqrt(ay));
-        } else {
-          const double ax = sqrt(ax2);
-          const cplx ph = (1.0 / ax) * x;  // x / |x|
-          c = ax / nrm;
-          s = (1.0 / nrm) * (ph * conj(y));
-          R[dk] = nrm * ph;
-        }
-        row[kk] = cx(0.0);
-#pragma unroll
-        for (int q = 0; q < MJ; ++q) {
-          if (q <= kk || q >= nj) continue;
-          const cplx t1 = R[dk + (q - kk)], t2 = row[q];
-          R[dk + (q - kk)] = c * t1 + s * t2;
-          row[q] = c * t2 - conj(s) * t1;
-        }
-        const cplx t1 = qtb[kk];
-        qtb[kk] = c * t1 + s * rhs;
-        rhs = c * rhs - conj(s) * t1;
-      }
-      res2 += abs2(rhs);
+      res2 += abs2(cgivens_row<MJ>(R, qtb, row, rhs, nj));
     }
   }
   // back substitution R p = qtb
@@ -241,6 +294,66 @@ __global__ void __launch_bounds__(64) k_cspai_cols(PencilDev pd, cplx a, cplx b,
   for (int t = 0; t < MJ; ++t)
     if (t < nj) hat[bj + t * kSlice] = p[t];
   obj[j] = sqrt(res2);
+}
+
+// Update alpha at a complex point: the minimiser of ||Khat_old - alpha
+// Khat_new||_F over complex alpha, <Khat_new, Khat_old> / <Khat_new,
+// Khat_new> (Hermitian inner product), both scaled by S_new.  Per block of
+// 256 rows: part[3 block + (0, 1, 2)] = (Re, Im) of sum conj(khat_new)
+// khat_old, and sum |khat_new|^2, summed in a fixed order.
+__global__ void __launch_bounds__(256) k_calpha_partial(PencilDev pd, cplx a, cplx b, cplx ao,
+                                                        cplx bo, const cplx* __restrict__ dinv,
+                                                        double* __restrict__ part) {
+  __shared__ double red[3][4];
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  cplx num = cx(0.0);
+  double den = 0.0;
+  if (r < pd.n) {
+    const int32_t br = row_base(pd, r);
+    const int nr = pd.row_len[r];
+    const cplx sr = dinv[r];
+    for (int q = 0; q < nr; ++q) {
+      const int32_t idx = br + q * kSlice;
+      const cplx sc = dinv[pd.col[idx]];
+      const cplx kn = cscaled(pd, idx, a, b, sr, sc);
+      cfma(num, conj(kn), cscaled(pd, idx, ao, bo, sr, sc));
+      den += abs2(kn);
+    }
+  }
+  const double v[3] = {wave_sum(num.re), wave_sum(num.im), wave_sum(den)};
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int q = 0; q < 3; ++q) red[q][w] = v[q];
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double t = 0.0;
+    for (int i = 0; i < 4; ++i) t += red[threadIdx.x][i];
+    part[3 * (int64_t)blockIdx.x + threadIdx.x] = t;
+  }
+}
+
+// alpha_d[0..1] = the quotient of the block sums (one block, fixed order);
+// *skip_count = 0 for the column kernel that follows.
+__global__ void __launch_bounds__(256) k_calpha_final(const double* __restrict__ part, int64_t nb,
+                                                      double* __restrict__ alpha_d,
+                                                      int32_t* __restrict__ skip_count) {
+  __shared__ double red[3][256];
+  double t[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = threadIdx.x; i < nb; i += 256)
+    for (int q = 0; q < 3; ++q) t[q] += part[3 * i + q];
+  for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = t[q];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double den = red[2][0];
+    alpha_d[0] = den > 0.0 ? red[0][0] / den : 0.0;
+    alpha_d[1] = den > 0.0 ? red[1][0] / den : 0.0;
+    *skip_count = 0;
+  }
 }
 
 // The same column problems from their normal equations, for pencils whose
@@ -407,10 +520,17 @@ __global__ void __launch_bounds__(64) k_cspai_gram(PencilDev pd, cplx a, cplx b,
 // P = S Phat S, with Phat replaced by (Phat + Phat^T) / 2 when sym; stored
 // order, padding 0.  hat holds column c's coefficient for row r at the
 // position of (c, r), so Phat(r, c) = hat[mirror of (r, c)].
+// The update (skipf given): Q = S Qhat S^{-1}, a skipped column c being
+// alpha e_c; nothing is written when every column was skipped (the factor
+// is the scalar alpha I, which the solves drop).
 __global__ void k_cspai_finalize(PencilDev pd, const cplx* __restrict__ hat,
-                                 const cplx* __restrict__ dinv, int sym, cplx* __restrict__ v) {
+                                 const cplx* __restrict__ dinv, int sym, cplx* __restrict__ v,
+                                 const int8_t* __restrict__ skipf,
+                                 const double* __restrict__ alpha_d,
+                                 const int32_t* __restrict__ skip_count) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= (int64_t)pd.n_slices * kSlice) return;
+  if (skipf && *skip_count == pd.n) return;
   const int32_t base = row_base(pd, r);
   const int w = (pd.slice_ptr[r / kSlice + 1] - pd.slice_ptr[r / kSlice]) / kSlice;
   const int len = pd.row_len[r];
@@ -420,11 +540,29 @@ __global__ void k_cspai_finalize(PencilDev pd, const cplx* __restrict__ hat,
     cplx val = cx(0.0);
     if (k < len) {
       const int32_t c = pd.col[idx];
-      cplx h = hat[pd.mirror[idx]];
-      if (sym) h = 0.5 * (h + hat[idx]);
-      val = (h * sr) * dinv[c];
+      if (skipf) {
+        const cplx h = skipf[c] ? (c == (int32_t)r ? cplx{alpha_d[0], alpha_d[1]} : cx(0.0))
+                                : hat[pd.mirror[idx]];
+        val = cdiv(h * sr, dinv[c]);
+      } else {
+        cplx h = hat[pd.mirror[idx]];
+        if (sym) h = 0.5 * (h + hat[idx]);
+        val = (h * sr) * dinv[c];
+      }
     }
     v[idx] = val;
+  }
+}
+
+// The scalar factor alpha I in CSR order (interleaved complex).
+__global__ void k_cexport_scalar(PencilDev pd, cplx alpha, cplx* __restrict__ out) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= pd.n) return;
+  const int32_t base = row_base(pd, r);
+  const int len = pd.row_len[r];
+  for (int k = 0; k < len; ++k) {
+    const int32_t idx = base + k * kSlice;
+    out[pd.csr_pos[idx]] = pd.col[idx] == (int32_t)r ? alpha : cx(0.0);
   }
 }
 
@@ -439,7 +577,9 @@ __global__ void k_cexport(PencilDev pd, int64_t stored, const cplx* __restrict__
 
 // ------------------------------------------------------------------ COCG
 
-enum CKind { CX = 0, CR0, CR1, CZ, CP0, CP1, CW, CKINDS };
+// CT: the intermediate vector of a preconditioner chain (Q_z ... Q_2 P_1 r
+// is applied factor by factor; the last factor writes CZ).
+enum CKind { CX = 0, CR0, CR1, CZ, CP0, CP1, CW, CT, CKINDS };
 // partial slots: 0, 1 = p^T w;  2 = ||r||^2;  3, 4 = r^T z;  5, 6 = z^T w
 constexpr int kCSlots = 7;
 
@@ -456,13 +596,20 @@ struct CArgs {
   cplx* ws;
   const cplx* ca;            // per shift a_k
   const cplx* cb;            // per shift b_k
-  const cplx* const* fac;    // per shift factor (stored order), nullptr = identity
+  // per shift its chain of factors (stored order), P_1 first:
+  // fac[shift * maxc + q] for q < clen[shift]; clen 0 = identity
+  const cplx* const* fac;
+  const int32_t* clen;
+  int32_t maxc;
   double* partial;           // [kCSlots][B][GP]
   int32_t GP;                // wavefronts = slices
   CSys sys;
   __device__ __forceinline__ cplx* vec(int kind, int b) const {
     return ws + ((int64_t)kind * B + b) * ld;
   }
+  // where chain position q of a chain of length L writes: the positions
+  // alternate between CT and CZ so that the last one writes CZ
+  __device__ __forceinline__ int chain_out(int q, int L) const { return ((L - 1 - q) & 1) ? CT : CZ; }
   __device__ __forceinline__ void put(int q, int b, int g, double v) const {
     partial[((int64_t)q * B + b) * GP + g] = v;
   }
@@ -517,7 +664,8 @@ __global__ void __launch_bounds__(256) k_cinit(CArgs A, const double* __restrict
   for (int b = 0; b < A.B; ++b) {
     if (sload(A.sys.active + b) == 0) continue;
     const int sh = b / A.m, c = b % A.m;
-    const cplx* fac = sload(A.fac + sh);
+    const int L = sload(A.clen + sh);
+    const cplx* fac = L > 0 ? sload(A.fac + (int64_t)sh * A.maxc) : nullptr;
     if (fac && sh != loaded) {
       rows.factor(A.pd, s, fac, fv);
       loaded = sh;
@@ -537,10 +685,12 @@ __global__ void __launch_bounds__(256) k_cinit(CArgs A, const double* __restrict
     A.vec(CX, b)[r] = cx(0.0);
     A.vec(CR0, b)[r] = cx(fr);
     A.vec(CP1, b)[r] = cx(0.0);
-    A.vec(CZ, b)[r] = z;
+    A.vec(L > 1 ? A.chain_out(0, L) : CZ, b)[r] = z;
     put_total(A, 2, b, s, lane, fr * fr);
-    put_total(A, 3, b, s, lane, fr * z.re);
-    put_total(A, 4, b, s, lane, fr * z.im);
+    if (L <= 1) {  // otherwise the chain's last factor forms r^T z
+      put_total(A, 3, b, s, lane, fr * z.re);
+      put_total(A, 4, b, s, lane, fr * z.im);
+    }
   }
 }
 
@@ -597,7 +747,8 @@ __global__ void __launch_bounds__(256) k_cupd(CArgs A, int par) {
   for (int b = 0; b < A.B; ++b) {
     if (sload(A.sys.active + b) == 0) continue;
     const int sh = b / A.m;
-    const cplx* fac = sload(A.fac + sh);
+    const int L = sload(A.clen + sh);
+    const cplx* fac = L > 0 ? sload(A.fac + (int64_t)sh * A.maxc) : nullptr;
     if (fac && sh != loaded) {
       rows.factor(A.pd, s, fac, fv);
       loaded = sh;
@@ -625,13 +776,58 @@ __global__ void __launch_bounds__(256) k_cupd(CArgs A, int par) {
     cfma(xv, al, A.vec(par ? CP1 : CP0, b)[r]);
     x[r] = xv;
     A.vec(par ? CR0 : CR1, b)[r] = rn;
-    A.vec(CZ, b)[r] = z;
-    const cplx rz = rn * z, zw = z * w[r];
+    A.vec(L > 1 ? A.chain_out(0, L) : CZ, b)[r] = z;
     put_total(A, 2, b, s, lane, abs2(rn));
-    put_total(A, 3, b, s, lane, rz.re);
-    put_total(A, 4, b, s, lane, rz.im);
-    put_total(A, 5, b, s, lane, zw.re);
-    put_total(A, 6, b, s, lane, zw.im);
+    if (L <= 1) {  // otherwise the chain's last factor forms the products
+      const cplx rz = rn * z, zw = z * w[r];
+      put_total(A, 3, b, s, lane, rz.re);
+      put_total(A, 4, b, s, lane, rz.im);
+      put_total(A, 5, b, s, lane, zw.re);
+      put_total(A, 6, b, s, lane, zw.im);
+    }
+  }
+}
+
+// Chain position q >= 1 (the factor Q_{q+1} of Algorithm 5's chain) for
+// every active system whose chain is longer than q: z_q = Q z_{q-1}, the
+// neighbours' z_{q-1} read from the previous position's vector.  At a
+// chain's last position the products of the step: r^T z (init: r = r_0)
+// and, in an iteration, z^T w (r = r_new of parity par).
+template <int WMAX>
+__global__ void __launch_bounds__(256) k_cchain(CArgs A, int q, int init, int par) {
+  const int lane = threadIdx.x & 63;
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= A.pd.n_slices) return;
+  CRows<WMAX> rows;
+  rows.load(A.pd, s, lane);
+  const int64_t r = rows.row;
+  int loaded = -1;
+  cplx fv[WMAX];
+  for (int b = 0; b < A.B; ++b) {
+    if (sload(A.sys.active + b) == 0) continue;
+    const int sh = b / A.m;
+    const int L = sload(A.clen + sh);
+    if (L <= q) continue;
+    if (sh != loaded) {
+      rows.factor(A.pd, s, sload(A.fac + (int64_t)sh * A.maxc + q), fv);
+      loaded = sh;
+    }
+    const cplx* __restrict__ zi = A.vec(A.chain_out(q - 1, L), b);
+    cplx z = cx(0.0);
+#pragma unroll
+    for (int k = 0; k < WMAX; ++k) cfma(z, fv[k], zi[rows.col[k]]);
+    A.vec(A.chain_out(q, L), b)[r] = z;
+    if (q == L - 1) {
+      const cplx rv = A.vec(init ? CR0 : (par ? CR0 : CR1), b)[r];
+      const cplx rz = rv * z;
+      put_total(A, 3, b, s, lane, rz.re);
+      put_total(A, 4, b, s, lane, rz.im);
+      if (!init) {
+        const cplx zw = z * A.vec(CW, b)[r];
+        put_total(A, 5, b, s, lane, zw.re);
+        put_total(A, 6, b, s, lane, zw.im);
+      }
+    }
   }
 }
 
@@ -770,11 +966,12 @@ struct CKernels {
   void (*dir)(CArgs, int);
   void (*upd)(CArgs, int);
   void (*resid)(CArgs, const double*, int64_t, double*, int64_t);
+  void (*chain)(CArgs, int, int, int);
 };
 
 template <int W>
 CKernels ckernels() {
-  return CKernels{k_cinit<W>, k_cdir<W>, k_cupd<W>, k_cresid<W>};
+  return CKernels{k_cinit<W>, k_cdir<W>, k_cupd<W>, k_cresid<W>, k_cchain<W>};
 }
 
 airga_status check_cshift(const Pencil& pen, double re, double im) {
@@ -871,16 +1068,106 @@ airga_status airga_spai_build_complex(airga_ctx ctx, double s_re, double s_im,
     k_cspai_gram<6><<<blocks_for(pen.n, 64), 64, cspai_gram_lds(pen.bandwidth, 6), s>>>(
         pd, a, b, dinv, pen.bandwidth, hat, p->objective.as<double>(), redo);
   }
-  k_cspai_cols<6><<<blocks_for(pen.n, 64), 64, 0, s>>>(pd, a, b, dinv, hat,
-                                                       p->objective.as<double>(), redo);
-  k_cspai_finalize<<<blocks_for((int64_t)npad, 256), 256, 0, s>>>(pd, hat, dinv,
-                                                                  o.symmetrize ? 1 : 0,
-                                                                  p->v64.as<cplx>());
+  k_cspai_cols<6, false><<<blocks_for(pen.n, 64), 64, 0, s>>>(
+      pd, a, b, dinv, hat, p->objective.as<double>(), redo, cx(0.0), cx(0.0), nullptr, 0.0,
+      nullptr, nullptr);
+  k_cspai_finalize<<<blocks_for((int64_t)npad, 256), 256, 0, s>>>(
+      pd, hat, dinv, o.symmetrize ? 1 : 0, p->v64.as<cplx>(), nullptr, nullptr, nullptr);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     airga_prec_release(p);
     return fail(AIRGA_EHIP, "complex SPAI launch: %s", hipGetErrorString(e));
   }
+  *out = p;
+  return AIRGA_OK;
+}
+
+airga_status airga_spai_update_complex(airga_ctx ctx, airga_prec old, double s_re, double s_im,
+                                       const airga_spai_opts* opts, airga_prec* out) {
+  AIRGA_TRY(check_pencil(ctx));
+  DeviceGuard g(ctx->device);
+  if (!out) return fail(AIRGA_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!old) return fail(AIRGA_EINVAL, "null preconditioner");
+  const Pencil& pen = ctx->pen;
+  if (old->ctx != ctx) return fail(AIRGA_EINVAL, "preconditioner belongs to another context");
+  if (old->generation != pen.generation)
+    return fail(AIRGA_ESTATE, "preconditioner was built for an earlier pencil");
+  if (!old->is_complex)
+    return fail(AIRGA_EINVAL, "the old factor is real: build it with airga_spai_build_complex");
+  AIRGA_TRY(check_cshift(pen, s_re, s_im));
+  airga_spai_opts o;
+  airga_spai_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.mr_iters != 0 || o.lfil != 0)
+    return fail(AIRGA_EUNSUPPORTED, "the minimal-residual mode is for real shifts only");
+  if (!(o.tol >= 0)) return fail(AIRGA_EINVAL, "update tolerance must be >= 0");
+  airga_prec p = new (std::nothrow) airga_prec_s();
+  if (!p) return fail(AIRGA_ENOMEM, "host allocation failed");
+  p->ctx = ctx;
+  p->generation = pen.generation;
+  p->shift = s_re;
+  p->shift_im = s_im;
+  p->is_complex = true;
+  p->is_update = true;
+  const size_t stored = (size_t)pen.nnz_stored;
+  const size_t npad = (size_t)pen.n_pad();
+  const unsigned nb = blocks_for(pen.n, 256);
+  airga_status st;
+  // scal: alpha (2 doubles) | skip count (int32 at 16) | skipped flags (from 64)
+  if ((st = pool_get(ctx, &p->v64, sizeof(cplx) * stored)) != AIRGA_OK ||
+      (st = pool_get(ctx, &p->objective, sizeof(double) * pen.n)) != AIRGA_OK ||
+      (st = pool_get(ctx, &p->scal, 64 + npad)) != AIRGA_OK ||
+      (st = ctx->ws_tmp.reserve(sizeof(cplx) * (stored + npad) + 3 * sizeof(double) * nb)) !=
+          AIRGA_OK) {
+    pool_put(ctx, &p->v64);
+    pool_put(ctx, &p->objective);
+    pool_put(ctx, &p->scal);
+    delete p;
+    return st;
+  }
+  ctx->live_precs++;
+  cplx a, b, ao, bo;
+  ccoeffs(pen, cx(s_re, s_im), &a, &b);
+  ccoeffs(pen, cx(old->shift, old->shift_im), &ao, &bo);
+  cplx* dinv = ctx->ws_tmp.as<cplx>();
+  cplx* hat = dinv + npad;
+  double* part = reinterpret_cast<double*>(hat + stored);
+  double* alpha_d = p->scal.as<double>();
+  int32_t* skip = reinterpret_cast<int32_t*>(p->scal.as<char>() + 16);
+  int8_t* skipf = reinterpret_cast<int8_t*>(p->scal.as<char>() + 64);
+  hipStream_t hs = ctx->stream;
+  const PencilDev pd = pen.dev();
+  // both matrices scaled by the new diagonal: Khat_x = S_new K(s_x) S_new
+  k_cdinv<<<blocks_for((int64_t)npad, 256), 256, 0, hs>>>(pd, a, b, o.equilibrate ? 1 : 0, dinv);
+  k_calpha_partial<<<nb, 256, 0, hs>>>(pd, a, b, ao, bo, dinv, part);
+  k_calpha_final<<<1, 256, 0, hs>>>(part, nb, alpha_d, skip);
+  k_cspai_cols<6, true><<<blocks_for(pen.n, 64), 64, 0, hs>>>(
+      pd, a, b, dinv, hat, p->objective.as<double>(), nullptr, ao, bo, alpha_d, o.tol, skipf, skip);
+  k_cspai_finalize<<<blocks_for((int64_t)npad, 256), 256, 0, hs>>>(pd, hat, dinv, 0,
+                                                                   p->v64.as<cplx>(), skipf,
+                                                                   alpha_d, skip);
+  hipError_t e = hipGetLastError();
+  // alpha and the skip count, read once (the solves need to know whether
+  // the factor is the scalar alpha I)
+  struct {
+    double alpha[2];
+    int32_t skipped, pad;
+  } h{};
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, alpha_d, sizeof h, hipMemcpyDeviceToHost, hs);
+  if (e == hipSuccess) e = hipStreamSynchronize(hs);
+  if (e != hipSuccess) {
+    airga_prec_release(p);
+    return fail(AIRGA_EHIP, "complex SPAI update: %s", hipGetErrorString(e));
+  }
+  p->alpha = h.alpha[0];
+  p->alpha_im = h.alpha[1];
+  p->alpha_known = true;
+  p->skipped = h.skipped;
+  p->scalar_only = h.skipped == pen.n;
+  p->scalar_known = true;
+  p->parent = old;
+  old->refs++;
   *out = p;
   return AIRGA_OK;
 }
@@ -895,8 +1182,12 @@ airga_status airga_prec_export_complex(airga_prec prec, double* values, double* 
   DeviceGuard g(ctx->device);
   const Pencil& pen = ctx->pen;
   if (values) {
-    k_cexport<<<blocks_for(pen.nnz_stored, 256), 256, 0, ctx->stream>>>(
-        pen.dev(), pen.nnz_stored, prec->v64.as<cplx>(), reinterpret_cast<cplx*>(values));
+    if (prec->scalar_only)
+      k_cexport_scalar<<<blocks_for(pen.n, 256), 256, 0, ctx->stream>>>(
+          pen.dev(), cplx{prec->alpha, prec->alpha_im}, reinterpret_cast<cplx*>(values));
+    else
+      k_cexport<<<blocks_for(pen.nnz_stored, 256), 256, 0, ctx->stream>>>(
+          pen.dev(), pen.nnz_stored, prec->v64.as<cplx>(), reinterpret_cast<cplx*>(values));
     AIRGA_HIP(hipGetLastError());
   }
   if (objective)
@@ -926,7 +1217,10 @@ airga_status airga_cocg_solve(airga_ctx ctx, int32_t nshift, const double* shift
   if (B64 > 4096) return fail(AIRGA_EUNSUPPORTED, "more than 4096 systems");
   const int B = (int)B64;
   std::vector<cplx> ca(nshift), cb(nshift);
-  std::vector<const cplx*> fac(nshift, nullptr);
+  // each shift's chain P_1, Q_2, ..., Q_z of non-scalar factors (a factor
+  // that is a scalar alpha I leaves COCG's iterates unchanged and is dropped)
+  std::vector<std::vector<const cplx*>> chains(nshift);
+  int maxc = 1;
   for (int k = 0; k < nshift; ++k) {
     AIRGA_TRY(check_cshift(pen, shifts[2 * k], shifts[2 * k + 1]));
     ccoeffs(pen, cx(shifts[2 * k], shifts[2 * k + 1]), &ca[k], &cb[k]);
@@ -938,7 +1232,10 @@ airga_status airga_cocg_solve(airga_ctx ctx, int32_t nshift, const double* shift
       if (!p->is_complex) return fail(AIRGA_EINVAL, "shift %d: a real factor for a complex solve", k);
       if (p->shift != shifts[2 * k] || p->shift_im != shifts[2 * k + 1])
         return fail(AIRGA_EINVAL, "shift %d: the factor was built at another shift", k);
-      fac[k] = p->v64.as<cplx>();
+      std::vector<airga_prec> ch;  // newest first
+      AIRGA_TRY(prec_chain(p, &ch));
+      for (auto it = ch.rbegin(); it != ch.rend(); ++it) chains[k].push_back((*it)->v64.as<cplx>());
+      maxc = (int)chains[k].size() > maxc ? (int)chains[k].size() : maxc;
     }
   }
   hipStream_t st = ctx->stream;
@@ -947,7 +1244,7 @@ airga_status airga_cocg_solve(airga_ctx ctx, int32_t nshift, const double* shift
   // workspace: vectors | partials | per-shift data | per-system state
   const size_t vec_b = sizeof(cplx) * (size_t)CKINDS * B * ld;
   const size_t part_b = sizeof(double) * (size_t)kCSlots * B * GP;
-  const size_t shift_b = (2 * sizeof(cplx) + sizeof(void*)) * (size_t)nshift;
+  const size_t shift_b = (2 * sizeof(cplx) + sizeof(void*) * maxc + sizeof(int32_t)) * (size_t)nshift;
   const size_t sys_b = (4 * sizeof(cplx) + 3 * sizeof(double) + 3 * sizeof(int32_t)) * (size_t)B + 64;
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   AIRGA_TRY(ctx->ws_vec.reserve(al(vec_b) + al(part_b) + al(shift_b) + al(sys_b)));
@@ -964,6 +1261,9 @@ airga_status airga_cocg_solve(airga_ctx ctx, int32_t nshift, const double* shift
   A.ca = reinterpret_cast<const cplx*>(shb);
   A.cb = A.ca + nshift;
   A.fac = reinterpret_cast<const cplx* const*>(shb + 2 * sizeof(cplx) * nshift);
+  A.clen = reinterpret_cast<const int32_t*>(shb + 2 * sizeof(cplx) * nshift +
+                                            sizeof(void*) * maxc * (size_t)nshift);
+  A.maxc = maxc;
   char* sb = shb + al(shift_b);
   CSys S;
   cplx* cs = reinterpret_cast<cplx*>(sb);
@@ -978,7 +1278,16 @@ airga_status airga_cocg_solve(airga_ctx ctx, int32_t nshift, const double* shift
   char* hp = static_cast<char*>(ctx->host_pinned);
   std::memcpy(hp, ca.data(), sizeof(cplx) * nshift);
   std::memcpy(hp + sizeof(cplx) * nshift, cb.data(), sizeof(cplx) * nshift);
-  std::memcpy(hp + 2 * sizeof(cplx) * nshift, fac.data(), sizeof(void*) * nshift);
+  {
+    const cplx** hf = reinterpret_cast<const cplx**>(hp + 2 * sizeof(cplx) * nshift);
+    int32_t* hl = reinterpret_cast<int32_t*>(hp + 2 * sizeof(cplx) * nshift +
+                                             sizeof(void*) * maxc * (size_t)nshift);
+    for (int k = 0; k < nshift; ++k) {
+      hl[k] = (int32_t)chains[k].size();
+      for (int q = 0; q < maxc; ++q)
+        hf[(size_t)k * maxc + q] = q < hl[k] ? chains[k][q] : nullptr;
+    }
+  }
   AIRGA_HIP(hipMemcpyAsync(shb, hp, shift_b, hipMemcpyHostToDevice, st));
   AIRGA_HIP(hipStreamSynchronize(st));
   // zero vectors (padding rows stay zero), fresh state
@@ -990,6 +1299,7 @@ airga_status airga_cocg_solve(airga_ctx ctx, int32_t nshift, const double* shift
   CRed R{S, A.partial, B, GP, o.max_iter, o.beta_form == AIRGA_BETA_CLASSICAL ? 0 : 1,
          o.tol * o.tol};
   ks.init<<<grid, 256, 0, st>>>(A, F, ldf);
+  for (int q = 1; q < maxc; ++q) ks.chain<<<grid, 256, 0, st>>>(A, q, 1, 0);
   k_creduce<<<(unsigned)B, 256, 0, st>>>(R, CM_INIT);
   AIRGA_HIP(hipGetLastError());
   AIRGA_TRY(ensure_pinned(ctx, 64));
@@ -1006,6 +1316,7 @@ airga_status airga_cocg_solve(airga_ctx ctx, int32_t nshift, const double* shift
       ks.dir<<<grid, 256, 0, st>>>(A, par);
       k_creduce<<<(unsigned)B, 256, 0, st>>>(R, CM_PW);
       ks.upd<<<grid, 256, 0, st>>>(A, par);
+      for (int q = 1; q < maxc; ++q) ks.chain<<<grid, 256, 0, st>>>(A, q, 0, par);
       k_creduce<<<(unsigned)B, 256, 0, st>>>(R, CM_ITER);
     }
     AIRGA_HIP(hipGetLastError());

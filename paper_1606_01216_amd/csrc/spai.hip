@@ -2206,7 +2206,8 @@ airga_status airga_spai_update(airga_ctx ctx, airga_prec old, double s_new,
   *out = nullptr;
   AIRGA_TRY(check_prec(old));
   if (old->ctx != ctx) return fail(AIRGA_EINVAL, "preconditioner belongs to another context");
-  if (old->is_complex) return fail(AIRGA_EUNSUPPORTED, "complex factors are not updated");
+  if (old->is_complex)
+    return fail(AIRGA_EUNSUPPORTED, "a complex factor: use airga_spai_update_complex");
   airga_spai_opts o;
   airga_spai_opts_default(&o);
   if (opts) o = *opts;
@@ -2261,7 +2262,8 @@ airga_status airga_spai_update_many(airga_ctx ctx, int32_t count, const airga_pr
     AIRGA_TRY(check_spai_args(ctx, s_new[i], &dummy));
     AIRGA_TRY(check_prec(olds[i]));
     if (olds[i]->ctx != ctx) return fail(AIRGA_EINVAL, "preconditioner belongs to another context");
-    if (olds[i]->is_complex) return fail(AIRGA_EUNSUPPORTED, "complex factors are not updated");
+    if (olds[i]->is_complex)
+      return fail(AIRGA_EUNSUPPORTED, "a complex factor: use airga_spai_update_complex");
   }
   airga_spai_opts o;
   airga_spai_opts_default(&o);
