@@ -654,9 +654,10 @@ class Context:
         return Prec(self, h)
 
     def spai_update_complex(self, old: "Prec", s_new: complex, *, tol=0.01,
-                            equilibrate=True) -> "Prec":
-        """Update of the complex factor old to the complex point s_new."""
-        o = self._spai_opts(tol, equilibrate, False)
+                            equilibrate=True, general_only=False) -> "Prec":
+        """Update of the complex factor old to the complex point s_new
+        (general_only: the Givens column kernel only)."""
+        o = self._spai_opts(tol, equilibrate, False, general_only)
         h = ctypes.c_void_p()
         s_new = complex(s_new)
         self._enter()

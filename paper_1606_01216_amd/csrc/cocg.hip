@@ -373,32 +373,42 @@ __global__ void __launch_bounds__(256) k_calpha_final(const double* __restrict__
 // more than 8 digits (a pivot below 1e-8 of its diagonal) is flagged in
 // redo and solved by k_cspai_cols instead.  The solution is written as
 // k_cspai_cols writes it (column j's coefficients at row j's positions).
-//   LDS per wavefront: scaled values vn[MJ][WR] (complex), first column and
-//   length of each window row, the band hb[R2][2 bw + 1] (complex);
-//   WR = R2 = 64 + 2 bw.
+// The update (UPDATE) solves min ||khat_old_j - B q|| the same way: the Gram
+// matrix is the same block, the right-hand side B^H khat_old_j is
+//     g_a = sum over k of conj(Khat_new(J_a, k)) Khat_old(j, k)
+// (both matrices complex symmetric), ||t||^2 = ||khat_old_j||^2, and the
+// skip test comes first, in the same arithmetic as k_cspai_cols<UPDATE>.
+//   LDS per wavefront: scaled values vn[MJ][WR] (complex; the update also
+//   vo[MJ][WR] of Khat_old), first column and length of each window row,
+//   the band hb[R2][2 bw + 1] (complex); WR = R2 = 64 + 2 bw.
 constexpr int kCGramMaxBw = 8;
 // packed upper-triangular index of (k, l), k <= l, in an MJ x MJ factor
 template <int MJ>
 __device__ constexpr int ctri(int k, int l) {
   return k * MJ - (k * (k - 1)) / 2 + (l - k);
 }
-__host__ __device__ inline size_t cspai_gram_lds(int bw, int mj) {
+__host__ __device__ inline size_t cspai_gram_lds(int bw, int mj, bool update) {
   const size_t wr = 64 + 2 * (size_t)bw;
-  return wr * (mj * sizeof(cplx) + 2 * sizeof(int32_t)) + wr * (2 * (size_t)bw + 1) * sizeof(cplx);
+  return wr * ((update ? 2 : 1) * mj * sizeof(cplx) + 2 * sizeof(int32_t)) +
+         wr * (2 * (size_t)bw + 1) * sizeof(cplx);
 }
 
-template <int MJ>
+template <int MJ, bool UPDATE>
 __global__ void __launch_bounds__(64) k_cspai_gram(PencilDev pd, cplx a, cplx b,
                                                    const cplx* __restrict__ dinv, int bw,
                                                    cplx* __restrict__ hat,
                                                    double* __restrict__ obj,
-                                                   int8_t* __restrict__ redo) {
+                                                   int8_t* __restrict__ redo, cplx ao, cplx bo,
+                                                   const double* __restrict__ alpha_d, double tol,
+                                                   int8_t* __restrict__ skipf,
+                                                   int32_t* __restrict__ skip_count) {
   extern __shared__ double lds_c[];
   const int lane = threadIdx.x;
   const int WR = 64 + 2 * bw;   // window rows [o0 - bw, o0 + 64 + bw)
   const int BW2 = 2 * bw + 1;
   cplx* vn = reinterpret_cast<cplx*>(lds_c);
-  int32_t* f0 = reinterpret_cast<int32_t*>(vn + MJ * WR);
+  cplx* vo = vn + MJ * WR;  // update only
+  int32_t* f0 = reinterpret_cast<int32_t*>(vn + (UPDATE ? 2 : 1) * MJ * WR);
   int32_t* ln = f0 + WR;
   cplx* hb = reinterpret_cast<cplx*>(ln + WR);
   const int64_t n = pd.n;
@@ -414,14 +424,15 @@ __global__ void __launch_bounds__(64) k_cspai_gram(PencilDev pd, cplx a, cplx b,
     const cplx sr = in ? dinv[row] : cx(0.0);
 #pragma unroll
     for (int k = 0; k < MJ; ++k) {
-      cplx v = cx(0.0);
+      cplx v = cx(0.0), w = cx(0.0);
       if (k < len) {
         const int32_t idx = base + k * kSlice;
-        const double mv = pd.m64[idx], kv = pd.k64[idx];
-        const cplx kv2 = cplx{fma(a.re, mv, b.re * kv), fma(a.im, mv, b.im * kv)};
-        v = (kv2 * sr) * dinv[pd.col[idx]];
+        const cplx sc = dinv[pd.col[idx]];
+        v = cscaled(pd, idx, a, b, sr, sc);
+        if constexpr (UPDATE) w = cscaled(pd, idx, ao, bo, sr, sc);
       }
       vn[k * WR + r] = v;
+      if constexpr (UPDATE) vo[k * WR + r] = w;
     }
   }
   __syncthreads();
@@ -447,6 +458,31 @@ __global__ void __launch_bounds__(64) k_cspai_gram(PencilDev pd, cplx a, cplx b,
   const int jr = (int)(j - w0);
   const int nj = ln[jr];
   const int J0 = f0[jr];  // J = J0 .. J0 + nj - 1
+  double t2 = 1.0;        // ||t||^2
+  if constexpr (UPDATE) {
+    // the skip test, as in k_cspai_cols<UPDATE> (column j = row j)
+    const cplx al = cplx{alpha_d[0], alpha_d[1]};
+    double n_old = 0.0, n_res = 0.0;
+#pragma unroll
+    for (int t = 0; t < MJ; ++t) {
+      if (t < nj) {
+        const cplx w = vo[t * WR + jr];
+        const cplx d = w - al * vn[t * WR + jr];
+        n_old += abs2(w);
+        n_res += abs2(d);
+      }
+    }
+    const bool skipped = sqrt(n_res) <= tol * sqrt(n_old);
+    skipf[j] = skipped ? 1 : 0;
+    const unsigned long long bal = __ballot(skipped);
+    if (lane == __ffsll((long long)__ballot(1)) - 1) atomicAdd(skip_count, (int32_t)__popcll(bal));
+    if (skipped) {
+      obj[j] = sqrt(n_res);
+      redo[j] = 0;
+      return;
+    }
+    t2 = n_old;
+  }
   cplx Uf[MJ * (MJ + 1) / 2], y[MJ], g[MJ], p[MJ];
   double iu[MJ];
   bool good = nj > 0;
@@ -456,7 +492,18 @@ __global__ void __launch_bounds__(64) k_cspai_gram(PencilDev pd, cplx a, cplx b,
     iu[k] = 0.0;
     if (k < nj) {
       const cplx* hk = hb + (J0 + k - (int)w0) * BW2;  // H(J_k, J_k + d)
-      g[k] = conj(vn[k * WR + jr]);                     // conj(Khat(j, J_k))
+      if constexpr (UPDATE) {
+        // sum over k' of conj(Khat_new(J_k, k')) Khat_old(j, k')
+        const int ra = J0 + k - (int)w0;
+        const int fa = f0[ra], la = ln[ra];
+        const int lo = fa > J0 ? fa : J0;
+        const int hi = (fa + la < J0 + nj) ? fa + la : J0 + nj;
+        cplx acc = cx(0.0);
+        for (int c = lo; c < hi; ++c) cfma(acc, conj(vn[(c - fa) * WR + ra]), vo[(c - J0) * WR + jr]);
+        g[k] = acc;
+      } else {
+        g[k] = conj(vn[k * WR + jr]);                   // conj(Khat(j, J_k))
+      }
       double dkk = hk[0].re;
 #pragma unroll
       for (int m = 0; m < MJ; ++m)
@@ -508,7 +555,7 @@ __global__ void __launch_bounds__(64) k_cspai_gram(PencilDev pd, cplx a, cplx b,
       pgp += row;
     }
   }
-  double res2 = fma(-2.0, ghp, 1.0) + pgp;
+  double res2 = fma(-2.0, ghp, t2) + pgp;
   res2 = res2 > 0.0 ? res2 : 0.0;
   const int32_t bj = row_base(pd, j);
 #pragma unroll
@@ -1065,8 +1112,9 @@ airga_status airga_spai_build_complex(airga_ctx ctx, double s_re, double s_im,
       return st;
     }
     redo = ctx->ws_gather.as<int8_t>();
-    k_cspai_gram<6><<<blocks_for(pen.n, 64), 64, cspai_gram_lds(pen.bandwidth, 6), s>>>(
-        pd, a, b, dinv, pen.bandwidth, hat, p->objective.as<double>(), redo);
+    k_cspai_gram<6, false><<<blocks_for(pen.n, 64), 64, cspai_gram_lds(pen.bandwidth, 6, false), s>>>(
+        pd, a, b, dinv, pen.bandwidth, hat, p->objective.as<double>(), redo, cx(0.0), cx(0.0),
+        nullptr, 0.0, nullptr, nullptr);
   }
   k_cspai_cols<6, false><<<blocks_for(pen.n, 64), 64, 0, s>>>(
       pd, a, b, dinv, hat, p->objective.as<double>(), redo, cx(0.0), cx(0.0), nullptr, 0.0,
@@ -1142,8 +1190,23 @@ airga_status airga_spai_update_complex(airga_ctx ctx, airga_prec old, double s_r
   k_cdinv<<<blocks_for((int64_t)npad, 256), 256, 0, hs>>>(pd, a, b, o.equilibrate ? 1 : 0, dinv);
   k_calpha_partial<<<nb, 256, 0, hs>>>(pd, a, b, ao, bo, dinv, part);
   k_calpha_final<<<1, 256, 0, hs>>>(part, nb, alpha_d, skip);
+  // equilibrated updates on narrow bands of consecutive columns: normal
+  // equations first, rotations for the columns they flag
+  const bool gram = !o.general_only && o.equilibrate && pen.contiguous && pen.max_len <= 6 &&
+                    pen.bandwidth <= kCGramMaxBw;
+  int8_t* redo = nullptr;
+  if (gram) {
+    if ((st = ctx->ws_gather.reserve((size_t)pen.n)) != AIRGA_OK) {
+      airga_prec_release(p);
+      return st;
+    }
+    redo = ctx->ws_gather.as<int8_t>();
+    k_cspai_gram<6, true><<<blocks_for(pen.n, 64), 64, cspai_gram_lds(pen.bandwidth, 6, true), hs>>>(
+        pd, a, b, dinv, pen.bandwidth, hat, p->objective.as<double>(), redo, ao, bo, alpha_d,
+        o.tol, skipf, skip);
+  }
   k_cspai_cols<6, true><<<blocks_for(pen.n, 64), 64, 0, hs>>>(
-      pd, a, b, dinv, hat, p->objective.as<double>(), nullptr, ao, bo, alpha_d, o.tol, skipf, skip);
+      pd, a, b, dinv, hat, p->objective.as<double>(), redo, ao, bo, alpha_d, o.tol, skipf, skip);
   k_cspai_finalize<<<blocks_for((int64_t)npad, 256), 256, 0, hs>>>(pd, hat, dinv, 0,
                                                                    p->v64.as<cplx>(), skipf,
                                                                    alpha_d, skip);

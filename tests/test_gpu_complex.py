@@ -115,6 +115,13 @@ def test_complex_update_matches_oracle(ctx, which, s_old, s_new):
     assert np.all(np.abs(vals - ref.values)[sel] <= 1e-9 * np.abs(ref.values).max()), (s_old, s_new)
     assert np.all(np.abs(obj - ref.objective)[~tie] <= 1e-12 * np.maximum(1.0, ref.objective[~tie]))
     assert row.size == vals.size
+    # the normal-equation kernel (beam) and the rotations agree, flags exactly
+    qg = ctx.spai_update_complex(old, s_new, tol=0.05, general_only=True)
+    assert torch.equal(qg.skip_flags(), q.skip_flags())
+    assert qg.info().skipped_cols == info.skipped_cols
+    vg, og = (t.cpu().numpy() for t in qg.export_complex())
+    assert np.abs(vg - vals).max() <= 1e-12 * np.abs(vals).max()
+    assert np.all(np.abs(og - obj) <= 1e-12 * np.maximum(1.0, obj))
 
 
 def test_cocg_with_a_complex_update_chain(ctx):
