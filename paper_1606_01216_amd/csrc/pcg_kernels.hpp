@@ -706,9 +706,13 @@ __global__ void __launch_bounds__(256) k_residual(SolveArgs<TO> A, const double*
   extern __shared__ double lds_part[];
   Rows<WMAX, R, EXACT> rows;
   rows.template load<BAND>(A.pd, wg, lane);
-  double mv[R][WMAX], kv[R][WMAX];
-  rows.values(A.pd.m64, mv);
-  rows.values(A.pd.k64, kv);
+  // without X (the first residual of a solve from X = 0) r = F: the pencil
+  // is not read, and |r|^2 = |F|^2 is summed once
+  double mv[R][WMAX] = {}, kv[R][WMAX] = {};
+  if (xread) {
+    rows.values(A.pd.m64, mv);
+    rows.values(A.pd.k64, kv);
+  }
   const int64_t n = A.pd.n;
   Window<WMAX, R> win;
   double* stg = nullptr;
@@ -836,8 +840,8 @@ __global__ void __launch_bounds__(256) k_residual(SolveArgs<TO> A, const double*
         rr = fma(res[u][i], res[u][i], rr);
         ff = fma(fr[u][i], fr[u][i], ff);
       }
-      rr = wave_total(rr);
       ff = wave_total(ff);
+      rr = xread ? wave_total(rr) : ff;  // X = 0: res is F, bit for bit
       A.put(lds_part, 0, b, wg, lane, rr);
       A.put(lds_part, 1, b, wg, lane, ff);
     }
