@@ -381,7 +381,7 @@ def measure_spai_mr(ctx, stream, shifts, precs, F, X, solve_kw, mr_iters=20, tol
 # passes and (shift, launch) passes.  w = bytes per vector value, fw = per
 # preconditioner value, ib = column information per stored entry.
 def kernel_bytes(name, launches, sysp, shp, *, stored, n, ib, w, fw, m, first_passes=0,
-                 mixed=True, gp=0, red_sys=0, assign_sys=0):
+                 mixed=True, gp=0, red_sys=0, assign_sys=0, zs_launches=0, zs_sys=0):
     if name == "dir_spmv":
         return launches * stored * (ib + 2 * w) + sysp * 4 * w * n
     if name == "update_prec":
@@ -394,8 +394,11 @@ def kernel_bytes(name, launches, sysp, shp, *, stored, n, ib, w, fw, m, first_pa
         return launches * stored * 4 + shp * stored * fw + sysp * 2 * w * n
     if name == "ir_residual":
         # float64 M and K with their columns, F once per launch and column,
-        # per system: read X, write r
-        return launches * stored * (ib + 16) + launches * m * 8 * n + sysp * (8 + w) * n
+        # per system: read X, write r; the first residual of a solve from
+        # X = 0 (zs_launches launches) reads no pencil, and in mixed mode no
+        # X either (zs_sys systems; float64 solves write the zero X instead)
+        return ((launches - zs_launches) * stored * (ib + 16) + launches * m * 8 * n +
+                sysp * (8 + w) * n - zs_sys * 8 * n)
     if name == "ir_update":
         # mixed: read X and the correction, write X (the first sweep of a
         # solve without a starting guess assigns X: no read, assign_sys
@@ -926,11 +929,12 @@ def measure_literal_batched(dev, stream, base, cap, err_idx, fp64=True, plain=2,
     if fp64:
         legs.append(("batched_fp64", dict(tol=LITERAL_TOL, mode=airga.MODE_FP64, max_iter=cap,
                                           poll_every=8),
-                     dict(w=8, fw=8, first_passes=0, mixed=False)))
+                     dict(w=8, fw=8, first_passes=0, mixed=False, zs_launches=1)))
     legs.append(("batched_mixed", dict(tol=LITERAL_TOL, mode=airga.MODE_MIXED, max_iter=cap,
                                        inner_max=cap, inner_tol=LITERAL_TOL, max_sweeps=1,
                                        poll_every=8),
-                 dict(w=4, fw=4, first_passes=S * m, mixed=True, assign_sys=S * m)))
+                 dict(w=4, fw=4, first_passes=S * m, mixed=True, assign_sys=S * m, zs_launches=1,
+                      zs_sys=S * m)))
     for name, kw, rkw in legs:
         log(f"[bench] literal {base}: {name} at {cap} iterations")
         sec, st, rows, gbs, tile = _literal_solve(
@@ -1303,7 +1307,7 @@ def main():
             solve_kw["poll_every"])
         gp64 = row_blocks(n, tile64[0])
         rows64 = kernel_rows(kt64, kw64, stored=stored, n=n, ib=ib, w=8, fw=8, m=m,
-                             first_passes=0, mixed=False, gp=gp64)
+                             first_passes=0, mixed=False, gp=gp64, zs_launches=1)
         batched64 = dict(seconds=t64, stats=st64, rows=rows64, tile=tile64)
 
     # plain float64, one system at a time, same systems and preconditioners
@@ -1353,7 +1357,8 @@ def main():
 
     # ---- roofline of the dominant row kernel (algorithmic bytes / duration)
     rows = kernel_rows(kt2, kw2, stored=stored, n=n, ib=ib, w=4, fw=4, m=m,
-                       first_passes=first_passes, mixed=True, gp=gp, assign_sys=B)
+                       first_passes=first_passes, mixed=True, gp=gp, assign_sys=B, zs_launches=1,
+                       zs_sys=B)
     dom = max((r for r in rows if r["bytes"] and r["kernel"] != "reduce"),
               key=lambda r: r["total_ms"])
     traffic = measured_traffic(args.workload, tile, dom["kernel"])

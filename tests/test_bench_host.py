@@ -119,6 +119,9 @@ def test_kernel_bytes_follow_the_per_kernel_formulas():
     assert bench.kernel_bytes("chain", 2, 6, 3, **kw) == 2 * 6000 * 4 + 3 * 6000 * 4 + 6 * 8 * 1000
     assert bench.kernel_bytes("ir_residual", 2, 8, 0, **kw) == \
         2 * 6000 * 17 + 2 * 2 * 8 * 1000 + 8 * 12 * 1000
+    # one of the two launches is a solve's first residual from X = 0 (4 systems)
+    assert bench.kernel_bytes("ir_residual", 2, 8, 0, zs_launches=1, zs_sys=4, **kw) == \
+        6000 * 17 + 2 * 2 * 8 * 1000 + 8 * 12 * 1000 - 4 * 8 * 1000
     assert bench.kernel_bytes("ir_update", 1, 8, 0, **kw) == 8 * 20 * 1000
     assert bench.kernel_bytes("ir_update", 2, 8, 0, assign_sys=4, **kw) == (8 * 20 - 4 * 8) * 1000
     assert bench.kernel_bytes("ir_update", 1, 8, 0, mixed=False, **kw) == 8 * 16 * 1000
