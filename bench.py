@@ -523,7 +523,7 @@ def rel_errors(X, refs, S, m):
     return out
 
 
-# ------------------------------------------------ update-chain sequence (C2)
+# ------------------------------------------ update-chain sequence (1e5 DOF)
 def measure_c2_sequence(dev, stream, tol=1e-8, seed=0, reps=2):
     """The plain float64 solve sequence of the 100,000-DOF beam: the SPAI
     (equilibrated, without the symmetric average, whose factor at s = 1 is
@@ -658,10 +658,33 @@ def measure_complex(ctx, stream, pen, f, F, sigmas, tol, reps=3, angle=np.pi / 6
     stored = ctx.pencil_info().nnz_stored
     launches = 2 * max(its)
     byts = sum(its) * 176 * n + launches * 20 * stored + max(its) * len(cs) * 16 * stored
+    # the same systems in MIXED mode (float32 COCG inside float64 refinement)
+    with torch.cuda.stream(stream):
+        Xm = torch.empty_like(X)
+        ctx.cocg_solve(cs, precs, F, Xm, tol=tol, mode=airga.MODE_MIXED)
+        tsm = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, stm = ctx.cocg_solve(cs, precs, F, Xm, tol=tol, mode=airga.MODE_MIXED)
+            torch.cuda.synchronize()
+            tsm.append(time.perf_counter() - t0)
     refs = oracle_refs_complex(pen, cs, f, max(1, min(CPU_WORKERS, cpu_info()[1])))
     Xh = X.cpu().numpy()
     errs = [rel_errors_c(Xh[k, c], refs[k][c]) for k in range(len(cs)) for c in range(m)]
     ok = sum(e <= ERR_TOL for e in errs)
+    Xmh = Xm.cpu().numpy()
+    del Xm
+    errsm = [rel_errors_c(Xmh[k, c], refs[k][c]) for k in range(len(cs)) for c in range(m)]
+    tm = statistics.median(tsm)
+    mixed = {"precision": "float32 COCG inside float64 refinement",
+             "cocg_solves_per_s": round(sum(e <= ERR_TOL for e in errsm) / tm, 2),
+             "seconds_median_of_3": round(tm, 4),
+             "solved_to_1e-8": sum(e <= ERR_TOL for e in errsm), "max_rel_err": max(errsm),
+             "iters_median": statistics.median(e["iters"] for e in stm),
+             "iters_max": max(e["iters"] for e in stm),
+             "sweeps_max": max(e["sweeps"] for e in stm),
+             "converged": sum(e["status"] == airga.SYS_CONVERGED for e in stm)}
     # the update to nearby points (each sigma_k moved by a seeded factor
     # 1 + 0.05 U(-1, 1), same angle) and the solves with the chains Q P
     drift = np.random.default_rng(7).uniform(-1.0, 1.0, len(cs))
@@ -683,10 +706,22 @@ def measure_complex(ctx, stream, pen, f, F, sigmas, tol, reps=3, angle=np.pi / 6
             _, st2 = ctx.cocg_solve(cs2, upd, F, X2, tol=tol, max_iter=2000)
             torch.cuda.synchronize()
             ts2.append(time.perf_counter() - t0)
+        # and in MIXED mode: every sweep restarts from the float64 residual
+        ctx.cocg_solve(cs2, upd, F, X, tol=tol, max_iter=2000, mode=airga.MODE_MIXED)
+        ts3 = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st3 = ctx.cocg_solve(cs2, upd, F, X, tol=tol, max_iter=2000, mode=airga.MODE_MIXED)
+            torch.cuda.synchronize()
+            ts3.append(time.perf_counter() - t0)
     infos = [u.info() for u in upd]
     refs2 = oracle_refs_complex(pen, cs2, f, max(1, min(CPU_WORKERS, cpu_info()[1])))
     X2h = X2.cpu().numpy()
     errs2 = [rel_errors_c(X2h[k, c], refs2[k][c]) for k in range(len(cs2)) for c in range(m)]
+    X3h = X.cpu().numpy()
+    errs3 = [rel_errors_c(X3h[k, c], refs2[k][c]) for k in range(len(cs2)) for c in range(m)]
+    t3 = statistics.median(ts3)
     t2 = statistics.median(ts2)
     its2 = [e["iters"] for e in st2]
     updates = {"drift": "sigma_k (1 + 0.05 U(-1, 1)), seeded",
@@ -702,12 +737,20 @@ def measure_complex(ctx, stream, pen, f, F, sigmas, tol, reps=3, angle=np.pi / 6
                                   "status": airga.STATUS_NAMES[e["status"]], "iters": e["iters"],
                                   "relres": float(f"{e['relres']:.3e}"),
                                   "rel_err": float(f"{errs2[i]:.3e}")}
-                                 for i, e in enumerate(st2) if e["status"] != airga.SYS_CONVERGED]}
+                                 for i, e in enumerate(st2) if e["status"] != airga.SYS_CONVERGED],
+               "mixed": {"cocg_solves_per_s": round(sum(e <= ERR_TOL for e in errs3) / t3, 2),
+                         "seconds_median_of_3": round(t3, 4),
+                         "solved_to_1e-8": sum(e <= ERR_TOL for e in errs3),
+                         "max_rel_err": max(errs3),
+                         "iters_median": statistics.median(e["iters"] for e in st3),
+                         "iters_max": max(e["iters"] for e in st3),
+                         "sweeps_max": max(e["sweeps"] for e in st3),
+                         "converged": sum(e["status"] == airga.SYS_CONVERGED for e in st3)}}
     for p in upd + precs:
         p.release()
     return {"workload": f"{len(cs)} complex points sigma_k e^(i pi/6), sigma_k = the real "
                         f"workload's points; {m} loads; {len(cs) * m} systems",
-            "updates": updates,
+            "updates": updates, "mixed": mixed,
             "precision": "complex float64", "spai_build_ms_per_shift": round(build_ms, 4),
             "cocg_solves_per_s": round(ok / t, 2), "seconds_median_of_3": round(t, 4),
             "solved_to_1e-8": ok, "systems": len(errs), "max_rel_err": max(errs),

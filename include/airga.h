@@ -431,9 +431,18 @@ AIRGA_API airga_status airga_prec_export_complex(airga_prec prec, double* values
  * default) or (r^T z)_new / (r^T z)_old (beta_form classical), p = z +
  * beta p.  BREAKDOWN when mu = 0; relres in stats is the true residual
  * ||F - K X|| / ||F|| at exit.  Options used: tol, max_iter, poll_every,
- * beta_form; mode must be FP64 and x0_given 0 (else EUNSUPPORTED).  Returns
+ * beta_form, mode; x0_given must be 0 (else EUNSUPPORTED).  mode MIXED:
+ * iterative refinement from X = 0, each sweep forming r = F - K X in
+ * float64 and solving K d = r by the COCG above in float32 (pencil, factors
+ * and vectors; float64 scalars) to a reduction inner_tol or inner_max
+ * iterations (default 96, rounded up to a multiple of poll_every), then X +=
+ * d; a system stops CONVERGED when its float64 residual meets tol, MAXIT
+ * after max_sweeps sweeps or max_iter inner iterations in all, BREAKDOWN or
+ * NONFINITE when an inner solve does (no float64 hand-over); stats give the
+ * iterations summed over sweeps and the sweep count.  Returns
  * after the stats are on the host.  Errors: EINVAL (sizes, null arrays,
- * non-finite shifts, a real factor or one built at another shift), ESTATE,
+ * non-finite shifts, a real factor or one built at another shift, refinement
+ * options out of range), ESTATE,
  * EUNSUPPORTED (more than 4096 systems, rows of more than 6 entries),
  * ENOMEM, EHIP. */
 AIRGA_API airga_status airga_cocg_solve(airga_ctx ctx, int32_t nshift, const double* shifts,

@@ -16,7 +16,7 @@ the eigenvalues of the reduced quadratic pencil, taking their real parts
 H2 change below 1e-6 (Section 5).
 
 The paper leaves these to Bonin et al. and does not fix them; the readings
-taken here (also listed with the design notes) are:
+taken here are:
   A1  the moment error at s_i is the fraction of the newest moment block
       X^{(j)}(s_i) that the orthogonalisation against V_1..V_j leaves,
       ||X after||_F / ||X before||_F (the part the basis does not hold

@@ -163,8 +163,8 @@ def _pick_entry(tv, inside, tie=PICK_TIE):
 
 
 def _mr_column(blk, rhs, jpos, p, alpha, tol, mr_iters, lfil=0, jself=None):
-    """The paper's iterative column solve (Algorithms 2 and 4, readings I1-I3)
-    on one column's local problem, minimise f(p) = ||t - B p||^2 with
+    """The paper's iterative column solve (Algorithms 2 and 4) on one
+    column's local problem, minimise f(p) = ||t - B p||^2 with
     B = blk = Khat(I, J) and t = rhs = t(I), from the start p on J.
 
     Each step is an exact line search of f: the direction is the current

@@ -667,10 +667,14 @@ class Context:
         return Prec(self, h)
 
     def cocg_solve(self, shifts, precs, F: torch.Tensor, X: torch.Tensor | None = None, *,
-                   tol=1e-10, max_iter=20000, poll_every=8, beta_form=0):
+                   tol=1e-10, max_iter=20000, poll_every=8, beta_form=0, mode=MODE_FP64,
+                   inner_tol=1e-5, inner_max=0, max_sweeps=12):
         """Solve K(s_k) X[k, c] = F[c] for complex shifts s_k by COCG.
         F: (m, n) float64 device tensor; X: (nshift, m, n) complex128
-        (allocated when None).  Returns (X, stats)."""
+        (allocated when None).  mode MODE_MIXED: float32 inner solves inside
+        float64 refinement (inner_tol per sweep, inner_max float32
+        iterations per sweep, 0 = the library's default, max_sweeps).
+        Returns (X, stats)."""
         _dev(F, torch.float64, self.device)
         m = F.shape[0]
         shifts = [complex(s) for s in shifts]
@@ -689,12 +693,13 @@ class Context:
         o = PcgOpts()
         lib().airga_pcg_opts_default(ctypes.byref(o))
         o.tol, o.max_iter, o.poll_every, o.beta_form = float(tol), int(max_iter), int(poll_every), int(beta_form)
+        o.mode, o.inner_tol, o.inner_max, o.max_sweeps = int(mode), float(inner_tol), int(inner_max), int(max_sweeps)
         stats = (SysStats * (nshift * m))()
         self._enter()
         _check(lib().airga_cocg_solve(self._h, nshift, c_shifts, c_precs, m, _ptr(F), self.n,
                                       _ptr(X), self.n, ctypes.byref(o), stats))
         self._leave()
-        out = [dict(status=s.status, iters=s.iters, relres=s.relres) for s in stats]
+        out = [dict(status=s.status, iters=s.iters, relres=s.relres, sweeps=s.sweeps) for s in stats]
         return X, out
 
     def kernel_times(self) -> dict:

@@ -74,6 +74,39 @@ __device__ __forceinline__ cplx sload_c(const cplx* p) {
   return cplx{sload(d), sload(d + 1)};
 }
 
+// Float complex values for the float32 inner solves of MIXED mode (the
+// same operations as cplx, in float).
+struct cf {
+  float re, im;
+};
+__device__ __forceinline__ cf operator+(cf a, cf b) { return cf{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cf operator-(cf a, cf b) { return cf{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cf operator*(cf a, cf b) {
+  return cf{fmaf(a.re, b.re, -a.im * b.im), fmaf(a.re, b.im, a.im * b.re)};
+}
+__device__ __forceinline__ cf conj(cf a) { return cf{a.re, -a.im}; }
+__device__ __forceinline__ float abs2(cf a) { return fmaf(a.re, a.re, a.im * a.im); }
+__device__ __forceinline__ void cfma(cf& a, cf x, cf y) {
+  a.re = fmaf(x.re, y.re, fmaf(-x.im, y.im, a.re));
+  a.im = fmaf(x.re, y.im, fmaf(x.im, y.re, a.im));
+}
+__device__ __forceinline__ void rfma(cf& a, float s, cf y) {
+  a.re = fmaf(s, y.re, a.re);
+  a.im = fmaf(s, y.im, a.im);
+}
+// real type, zero, and conversion from float64 complex, per value type
+template <typename V> struct cvt;
+template <> struct cvt<cplx> {
+  using R = double;
+  __device__ static cplx from(cplx z) { return z; }
+  __device__ static cplx real(double v) { return cplx{v, 0.0}; }
+};
+template <> struct cvt<cf> {
+  using R = float;
+  __device__ static cf from(cplx z) { return cf{(float)z.re, (float)z.im}; }
+  __device__ static cf real(double v) { return cf{(float)v, 0.0f}; }
+};
+
 // Shift coefficients a = s^2 + alpha s, b = 1 + beta s.
 inline void ccoeffs(const Pencil& pen, cplx s, cplx* a, cplx* b) {
   *a = s * s + pen.alpha * s;
@@ -565,14 +598,15 @@ __global__ void __launch_bounds__(64) k_cspai_gram(PencilDev pd, cplx a, cplx b,
 }
 
 // P = S Phat S, with Phat replaced by (Phat + Phat^T) / 2 when sym; stored
-// order, padding 0.  hat holds column c's coefficient for row r at the
+// order, padding 0; v32 the same values rounded to float (interleaved), the
+// copy the float32 inner solves of MIXED mode read.  hat holds column c's coefficient for row r at the
 // position of (c, r), so Phat(r, c) = hat[mirror of (r, c)].
 // The update (skipf given): Q = S Qhat S^{-1}, a skipped column c being
 // alpha e_c; nothing is written when every column was skipped (the factor
 // is the scalar alpha I, which the solves drop).
 __global__ void k_cspai_finalize(PencilDev pd, const cplx* __restrict__ hat,
                                  const cplx* __restrict__ dinv, int sym, cplx* __restrict__ v,
-                                 const int8_t* __restrict__ skipf,
+                                 float* __restrict__ v32, const int8_t* __restrict__ skipf,
                                  const double* __restrict__ alpha_d,
                                  const int32_t* __restrict__ skip_count) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -598,6 +632,8 @@ __global__ void k_cspai_finalize(PencilDev pd, const cplx* __restrict__ hat,
       }
     }
     v[idx] = val;
+    v32[2 * (int64_t)idx] = (float)val.re;
+    v32[2 * (int64_t)idx + 1] = (float)val.im;
   }
 }
 
@@ -634,24 +670,32 @@ struct CSys {
   cplx *rho, *mu, *alpha, *beta;
   double *tol2, *ff, *relres;
   int32_t *active, *istat, *iters, *nact;
+  // MIXED mode: refinement state per system (outer active, final status,
+  // sweeps, iterations of finished sweeps, ||F||^2) and the count of
+  // systems still refined
+  int32_t *outer, *ostat, *sweeps, *itot, *nout;
+  double* fo;
 };
 
-struct CArgs {
+// V: the value type of the vectors and factors (cplx for float64 solves,
+// cf for the float32 inner solves of MIXED mode).
+template <typename V>
+struct CArgsT {
   PencilDev pd;
   int32_t B, m;
   int64_t ld;                // n_pad
-  cplx* ws;
+  V* ws;
   const cplx* ca;            // per shift a_k
   const cplx* cb;            // per shift b_k
   // per shift its chain of factors (stored order), P_1 first:
   // fac[shift * maxc + q] for q < clen[shift]; clen 0 = identity
-  const cplx* const* fac;
+  const V* const* fac;
   const int32_t* clen;
   int32_t maxc;
   double* partial;           // [kCSlots][B][GP]
   int32_t GP;                // wavefronts = slices
   CSys sys;
-  __device__ __forceinline__ cplx* vec(int kind, int b) const {
+  __device__ __forceinline__ V* vec(int kind, int b) const {
     return ws + ((int64_t)kind * B + b) * ld;
   }
   // where chain position q of a chain of length L writes: the positions
@@ -661,45 +705,63 @@ struct CArgs {
     partial[((int64_t)q * B + b) * GP + g] = v;
   }
 };
+using CArgs = CArgsT<cplx>;
 
-// The slice of one wavefront: columns and M, K values of its 64 rows.
-template <int WMAX>
+// The slice of one wavefront: columns and M, K values of its 64 rows (R:
+// float64 from the pencil, or its float32 copy).
+template <int WMAX, typename R = double>
 struct CRows {
   int32_t col[WMAX];
-  double mv[WMAX], kv[WMAX];
+  R mv[WMAX], kv[WMAX];
   int32_t idx0;
   int64_t row;
   __device__ __forceinline__ void load(const PencilDev& pd, int s, int lane) {
     row = (int64_t)s * kSlice + lane;
     idx0 = pd.slice_ptr[s] + lane;
     const int w = (pd.slice_ptr[s + 1] - pd.slice_ptr[s]) / kSlice;
+    const R* __restrict__ mp;
+    const R* __restrict__ kp;
+    if constexpr (sizeof(R) == 8) {
+      mp = pd.m64;
+      kp = pd.k64;
+    } else {
+      mp = pd.m32;
+      kp = pd.k32;
+    }
 #pragma unroll
     for (int k = 0; k < WMAX; ++k) {
       const bool in = k < w;
       col[k] = in ? pd.col[idx0 + k * kSlice] : (int32_t)row;
-      mv[k] = in ? pd.m64[idx0 + k * kSlice] : 0.0;
-      kv[k] = in ? pd.k64[idx0 + k * kSlice] : 0.0;
+      mv[k] = in ? mp[idx0 + k * kSlice] : R(0);
+      kv[k] = in ? kp[idx0 + k * kSlice] : R(0);
     }
   }
   // the factor's values of this row (0 past the slice's width: the stored
   // padding entries hold 0)
-  __device__ __forceinline__ void factor(const PencilDev& pd, int s, const cplx* f,
-                                         cplx (&fv)[WMAX]) const {
+  template <typename V>
+  __device__ __forceinline__ void factor(const PencilDev& pd, int s, const V* f,
+                                         V (&fv)[WMAX]) const {
     const int w = (pd.slice_ptr[s + 1] - pd.slice_ptr[s]) / kSlice;
 #pragma unroll
-    for (int k = 0; k < WMAX; ++k) fv[k] = k < w ? f[idx0 + k * kSlice] : cx(0.0);
+    for (int k = 0; k < WMAX; ++k) fv[k] = k < w ? f[idx0 + k * kSlice] : cvt<V>::real(0.0);
   }
 };
 
-__device__ __forceinline__ void put_total(const CArgs& A, int q, int b, int g, int lane, double v) {
+template <typename V>
+__device__ __forceinline__ void put_total(const CArgsT<V>& A, int q, int b, int g, int lane,
+                                          double v) {
   v = wave_total(v);
   if (lane == 0) A.put(q, b, g, v);
 }
 
-// z = C r0 with r0 = F(:, c) (real) for every system; x = 0, r = F, p = 0.
-// Partials ||r||^2 and r^T z.
-template <int WMAX>
-__global__ void __launch_bounds__(256) k_cinit(CArgs A, const double* __restrict__ F, int64_t ldf) {
+// z = C r0 for every active system, with r0 = F(:, c) (real; written to
+// r) or, rhs_vec = 1 (the inner solves of MIXED mode), the r0 already in r;
+// x = 0, p = 0.  Partials ||r0||^2 and r0^T z.  V: value type (float64
+// complex, or float complex for the inner solves).
+template <int WMAX, typename V>
+__global__ void __launch_bounds__(256) k_cinit(CArgsT<V> A, const double* __restrict__ F,
+                                               int64_t ldf, int rhs_vec) {
+  using R = typename cvt<V>::R;
   const int lane = threadIdx.x & 63;
   const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (s >= A.pd.n_slices) return;
@@ -707,82 +769,102 @@ __global__ void __launch_bounds__(256) k_cinit(CArgs A, const double* __restrict
   rows.load(A.pd, s, lane);
   const int64_t n = A.pd.n, r = rows.row;
   int loaded = -1;
-  cplx fv[WMAX];
+  V fv[WMAX];
   for (int b = 0; b < A.B; ++b) {
     if (sload(A.sys.active + b) == 0) continue;
     const int sh = b / A.m, c = b % A.m;
     const int L = sload(A.clen + sh);
-    const cplx* fac = L > 0 ? sload(A.fac + (int64_t)sh * A.maxc) : nullptr;
+    const V* fac = L > 0 ? sload(A.fac + (int64_t)sh * A.maxc) : nullptr;
     if (fac && sh != loaded) {
       rows.factor(A.pd, s, fac, fv);
       loaded = sh;
     }
-    const double* f = F + (int64_t)c * ldf;
-    const double fr = r < n ? f[r] : 0.0;
-    cplx z = cx(0.0);
-    if (fac) {
+    V z = cvt<V>::real(0.0);
+    double rr, rz_re, rz_im;
+    if (rhs_vec) {
+      const V* __restrict__ r0 = A.vec(CR0, b);
+      const V own = r0[r];
+      if (fac) {
 #pragma unroll
-      for (int k = 0; k < WMAX; ++k) {
-        const int64_t cc = rows.col[k];
-        rfma(z, cc < n ? f[cc] : 0.0, fv[k]);
+        for (int k = 0; k < WMAX; ++k) cfma(z, fv[k], r0[rows.col[k]]);
+      } else {
+        z = own;
       }
+      const V rzv = own * z;
+      rr = (double)abs2(own);
+      rz_re = (double)rzv.re;
+      rz_im = (double)rzv.im;
     } else {
-      z = cx(fr);
+      const double* f = F + (int64_t)c * ldf;
+      const R fr = r < n ? (R)f[r] : R(0);
+      if (fac) {
+#pragma unroll
+        for (int k = 0; k < WMAX; ++k) {
+          const int64_t cc = rows.col[k];
+          rfma(z, cc < n ? (R)f[cc] : R(0), fv[k]);
+        }
+      } else {
+        z = cvt<V>::real(fr);
+      }
+      A.vec(CR0, b)[r] = cvt<V>::real(fr);
+      rr = (double)(fr * fr);
+      rz_re = (double)(fr * z.re);
+      rz_im = (double)(fr * z.im);
     }
-    A.vec(CX, b)[r] = cx(0.0);
-    A.vec(CR0, b)[r] = cx(fr);
-    A.vec(CP1, b)[r] = cx(0.0);
+    A.vec(CX, b)[r] = cvt<V>::real(0.0);
+    A.vec(CP1, b)[r] = cvt<V>::real(0.0);
     A.vec(L > 1 ? A.chain_out(0, L) : CZ, b)[r] = z;
-    put_total(A, 2, b, s, lane, fr * fr);
+    put_total(A, 2, b, s, lane, rr);
     if (L <= 1) {  // otherwise the chain's last factor forms r^T z
-      put_total(A, 3, b, s, lane, fr * z.re);
-      put_total(A, 4, b, s, lane, fr * z.im);
+      put_total(A, 3, b, s, lane, rz_re);
+      put_total(A, 4, b, s, lane, rz_im);
     }
   }
 }
 
 // p_new = z + beta p_old;  w = K(s) p_new;  partial p_new^T w.  The
 // neighbours' p_new are formed from z and p_old at the column.
-template <int WMAX>
-__global__ void __launch_bounds__(256) k_cdir(CArgs A, int par) {
+template <int WMAX, typename V>
+__global__ void __launch_bounds__(256) k_cdir(CArgsT<V> A, int par) {
+  using R = typename cvt<V>::R;
   const int lane = threadIdx.x & 63;
   const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (s >= A.pd.n_slices) return;
-  CRows<WMAX> rows;
+  CRows<WMAX, R> rows;
   rows.load(A.pd, s, lane);
   const int64_t r = rows.row;
   for (int b = 0; b < A.B; ++b) {
     if (sload(A.sys.active + b) == 0) continue;
     const int sh = b / A.m;
-    const cplx be = sload_c(A.sys.beta + b);
-    const cplx ka = sload_c(A.ca + sh), kb = sload_c(A.cb + sh);
-    const cplx* __restrict__ z = A.vec(CZ, b);
-    const cplx* __restrict__ po = A.vec(par ? CP0 : CP1, b);
-    cplx am = cx(0.0), ak = cx(0.0);
+    const V be = cvt<V>::from(sload_c(A.sys.beta + b));
+    const V ka = cvt<V>::from(sload_c(A.ca + sh)), kb = cvt<V>::from(sload_c(A.cb + sh));
+    const V* __restrict__ z = A.vec(CZ, b);
+    const V* __restrict__ po = A.vec(par ? CP0 : CP1, b);
+    V am = cvt<V>::real(0.0), ak = cvt<V>::real(0.0);
 #pragma unroll
     for (int k = 0; k < WMAX; ++k) {
       const int64_t c = rows.col[k];
-      cplx pc = z[c];
+      V pc = z[c];
       cfma(pc, be, po[c]);
       rfma(am, rows.mv[k], pc);
       rfma(ak, rows.kv[k], pc);
     }
-    cplx pn = z[r];
+    V pn = z[r];
     cfma(pn, be, po[r]);
-    const cplx w = ka * am + kb * ak;
+    const V w = ka * am + kb * ak;
     A.vec(par ? CP1 : CP0, b)[r] = pn;
     A.vec(CW, b)[r] = w;
-    const cplx pw = pn * w;
-    put_total(A, 0, b, s, lane, pw.re);
-    put_total(A, 1, b, s, lane, pw.im);
+    const V pw = pn * w;
+    put_total(A, 0, b, s, lane, (double)pw.re);
+    put_total(A, 1, b, s, lane, (double)pw.im);
   }
 }
 
 // x += alpha p_new;  r_new = r_old - alpha w;  z = C r_new;  partials
 // ||r_new||^2, r_new^T z, z^T w.  The neighbours' r_new are formed from
 // r_old and w at the column.
-template <int WMAX>
-__global__ void __launch_bounds__(256) k_cupd(CArgs A, int par) {
+template <int WMAX, typename V>
+__global__ void __launch_bounds__(256) k_cupd(CArgsT<V> A, int par) {
   const int lane = threadIdx.x & 63;
   const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (s >= A.pd.n_slices) return;
@@ -790,47 +872,48 @@ __global__ void __launch_bounds__(256) k_cupd(CArgs A, int par) {
   rows.load(A.pd, s, lane);
   const int64_t r = rows.row;
   int loaded = -1;
-  cplx fv[WMAX];
+  V fv[WMAX];
   for (int b = 0; b < A.B; ++b) {
     if (sload(A.sys.active + b) == 0) continue;
     const int sh = b / A.m;
     const int L = sload(A.clen + sh);
-    const cplx* fac = L > 0 ? sload(A.fac + (int64_t)sh * A.maxc) : nullptr;
+    const V* fac = L > 0 ? sload(A.fac + (int64_t)sh * A.maxc) : nullptr;
     if (fac && sh != loaded) {
       rows.factor(A.pd, s, fac, fv);
       loaded = sh;
     }
-    const cplx al = sload_c(A.sys.alpha + b);
-    const cplx nal = cx(-al.re, -al.im);
-    const cplx* __restrict__ ro = A.vec(par ? CR1 : CR0, b);
-    const cplx* __restrict__ w = A.vec(CW, b);
-    cplx rn = ro[r];
+    const cplx al64 = sload_c(A.sys.alpha + b);
+    const V al = cvt<V>::from(al64);
+    const V nal = cvt<V>::from(cx(-al64.re, -al64.im));
+    const V* __restrict__ ro = A.vec(par ? CR1 : CR0, b);
+    const V* __restrict__ w = A.vec(CW, b);
+    V rn = ro[r];
     cfma(rn, nal, w[r]);
-    cplx z = cx(0.0);
+    V z = cvt<V>::real(0.0);
     if (fac) {
 #pragma unroll
       for (int k = 0; k < WMAX; ++k) {
         const int64_t c = rows.col[k];
-        cplx rc = ro[c];
+        V rc = ro[c];
         cfma(rc, nal, w[c]);
         cfma(z, fv[k], rc);
       }
     } else {
       z = rn;
     }
-    cplx* __restrict__ x = A.vec(CX, b);
-    cplx xv = x[r];
+    V* __restrict__ x = A.vec(CX, b);
+    V xv = x[r];
     cfma(xv, al, A.vec(par ? CP1 : CP0, b)[r]);
     x[r] = xv;
     A.vec(par ? CR0 : CR1, b)[r] = rn;
     A.vec(L > 1 ? A.chain_out(0, L) : CZ, b)[r] = z;
-    put_total(A, 2, b, s, lane, abs2(rn));
+    put_total(A, 2, b, s, lane, (double)abs2(rn));
     if (L <= 1) {  // otherwise the chain's last factor forms the products
-      const cplx rz = rn * z, zw = z * w[r];
-      put_total(A, 3, b, s, lane, rz.re);
-      put_total(A, 4, b, s, lane, rz.im);
-      put_total(A, 5, b, s, lane, zw.re);
-      put_total(A, 6, b, s, lane, zw.im);
+      const V rz = rn * z, zw = z * w[r];
+      put_total(A, 3, b, s, lane, (double)rz.re);
+      put_total(A, 4, b, s, lane, (double)rz.im);
+      put_total(A, 5, b, s, lane, (double)zw.re);
+      put_total(A, 6, b, s, lane, (double)zw.im);
     }
   }
 }
@@ -840,8 +923,8 @@ __global__ void __launch_bounds__(256) k_cupd(CArgs A, int par) {
 // neighbours' z_{q-1} read from the previous position's vector.  At a
 // chain's last position the products of the step: r^T z (init: r = r_0)
 // and, in an iteration, z^T w (r = r_new of parity par).
-template <int WMAX>
-__global__ void __launch_bounds__(256) k_cchain(CArgs A, int q, int init, int par) {
+template <int WMAX, typename V>
+__global__ void __launch_bounds__(256) k_cchain(CArgsT<V> A, int q, int init, int par) {
   const int lane = threadIdx.x & 63;
   const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (s >= A.pd.n_slices) return;
@@ -849,7 +932,7 @@ __global__ void __launch_bounds__(256) k_cchain(CArgs A, int q, int init, int pa
   rows.load(A.pd, s, lane);
   const int64_t r = rows.row;
   int loaded = -1;
-  cplx fv[WMAX];
+  V fv[WMAX];
   for (int b = 0; b < A.B; ++b) {
     if (sload(A.sys.active + b) == 0) continue;
     const int sh = b / A.m;
@@ -859,20 +942,20 @@ __global__ void __launch_bounds__(256) k_cchain(CArgs A, int q, int init, int pa
       rows.factor(A.pd, s, sload(A.fac + (int64_t)sh * A.maxc + q), fv);
       loaded = sh;
     }
-    const cplx* __restrict__ zi = A.vec(A.chain_out(q - 1, L), b);
-    cplx z = cx(0.0);
+    const V* __restrict__ zi = A.vec(A.chain_out(q - 1, L), b);
+    V z = cvt<V>::real(0.0);
 #pragma unroll
     for (int k = 0; k < WMAX; ++k) cfma(z, fv[k], zi[rows.col[k]]);
     A.vec(A.chain_out(q, L), b)[r] = z;
     if (q == L - 1) {
-      const cplx rv = A.vec(init ? CR0 : (par ? CR0 : CR1), b)[r];
-      const cplx rz = rv * z;
-      put_total(A, 3, b, s, lane, rz.re);
-      put_total(A, 4, b, s, lane, rz.im);
+      const V rv = A.vec(init ? CR0 : (par ? CR0 : CR1), b)[r];
+      const V rz = rv * z;
+      put_total(A, 3, b, s, lane, (double)rz.re);
+      put_total(A, 4, b, s, lane, (double)rz.im);
       if (!init) {
-        const cplx zw = z * A.vec(CW, b)[r];
-        put_total(A, 5, b, s, lane, zw.re);
-        put_total(A, 6, b, s, lane, zw.im);
+        const V zw = z * A.vec(CW, b)[r];
+        put_total(A, 5, b, s, lane, (double)zw.re);
+        put_total(A, 6, b, s, lane, (double)zw.im);
       }
     }
   }
@@ -913,13 +996,17 @@ __global__ void __launch_bounds__(256) k_cresid(CArgs A, const double* __restric
   }
 }
 
-enum { CM_INIT = 0, CM_PW, CM_ITER, CM_FINAL };
+enum { CM_INIT = 0, CM_PW, CM_ITER, CM_FINAL, CM_OUTER };
 
 struct CRed {
   CSys sys;
   const double* partial;
   int32_t B, GP, max_iter, flexible;
   double tol2_rel;
+  // CM_OUTER (MIXED): stop when ||F - K X||^2 <= tol2_abs ||F||^2, after
+  // max_sweeps sweeps, or once max_iter_total inner iterations are spent
+  double tol2_abs;
+  int32_t max_sweeps, max_iter_total;
 };
 
 // One block per system: fixed-order sums of the slots the mode needs, then
@@ -928,7 +1015,7 @@ __global__ void __launch_bounds__(256) k_creduce(CRed P, int mode) {
   __shared__ double red[4][kCSlots];
   const int b = blockIdx.x, t = threadIdx.x;
   const CSys& S = P.sys;
-  if (mode != CM_FINAL && S.active[b] == 0) return;
+  if (mode == CM_OUTER ? S.outer[b] == 0 : (mode != CM_FINAL && S.active[b] == 0)) return;
   double v[kCSlots];
 #pragma unroll
   for (int q = 0; q < kCSlots; ++q) v[q] = 0.0;
@@ -987,6 +1074,27 @@ __global__ void __launch_bounds__(256) k_creduce(CRed P, int mode) {
       S.relres[b] = S.ff[b] > 0 ? sqrt(s[2] / S.ff[b]) : 0.0;
       break;
     }
+    case CM_OUTER: {
+      // slot 2 = ||F - K X||^2 in float64, slot 3 = ||F||^2 (first time)
+      const int sw = S.sweeps[b];
+      if (sw == 0) S.fo[b] = s[3];
+      const double ff = S.fo[b];
+      S.relres[b] = ff > 0 ? sqrt(s[2] / ff) : 0.0;
+      S.itot[b] += S.iters[b];
+      S.iters[b] = 0;
+      int st = -1;
+      if (!isfinite(s[2])) st = AIRGA_SYS_NONFINITE;
+      else if (s[2] <= P.tol2_abs * ff) st = AIRGA_SYS_CONVERGED;
+      else if (sw > 0 && (S.istat[b] == AIRGA_SYS_BREAKDOWN || S.istat[b] == AIRGA_SYS_NONFINITE))
+        st = S.istat[b];
+      else if (sw >= P.max_sweeps || S.itot[b] >= P.max_iter_total) st = AIRGA_SYS_MAXIT;
+      if (st >= 0) {
+        S.ostat[b] = st;
+        S.outer[b] = 0;
+        atomicAdd(S.nout, -1);
+      }
+      return;
+    }
   }
   if (act != was) {
     S.active[b] = act;
@@ -1008,17 +1116,223 @@ __global__ void k_cfill(cplx* p, int64_t count) {
   if (i < count) p[i] = cx(0.0);
 }
 
+// ------------------------------------------------------------ MIXED mode
+//
+// Iterative refinement around float32 COCG, as for real points: the
+// float64 residual r = F - K(s) X of the float64 solution X, a float32 COCG
+// solve K(s) d = r to a relative reduction inner_tol (float32 pencil,
+// factors and vectors, float64 scalar recurrence), X += d.
+
+// MIXED state: every system refined, none finished.
+__global__ void k_cstate_mixed(CSys S, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b == 0) *S.nout = B;
+  if (b >= B) return;
+  S.outer[b] = 1;
+  S.ostat[b] = AIRGA_SYS_MAXIT;
+  S.sweeps[b] = 0;
+  S.itot[b] = 0;
+  S.iters[b] = 0;
+  S.istat[b] = AIRGA_SYS_MAXIT;
+}
+
+// The next inner solve: the refined systems are its active ones.
+__global__ void k_cstart_inner(CSys S, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b == 0) *S.nact = *S.nout;
+  if (b >= B) return;
+  S.active[b] = S.outer[b];
+  S.istat[b] = AIRGA_SYS_MAXIT;
+  S.iters[b] = 0;
+}
+
+// float64 residual r = F - K(s) X for the refined systems (xread = 0: X = 0,
+// r = F), written in float into the inner solve's r0; partials slot 2 =
+// ||r||^2, slot 3 = ||F||^2.  X: complex float64 interleaved, column b at
+// X + 2 b ldx (n rows); rows past n give r = 0.
+template <int WMAX>
+__global__ void __launch_bounds__(256) k_cresid_ir(CArgsT<cf> A, const double* __restrict__ F,
+                                                   int64_t ldf, const double* __restrict__ X,
+                                                   int64_t ldx, int xread) {
+  const int lane = threadIdx.x & 63;
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= A.pd.n_slices) return;
+  CRows<WMAX> rows;
+  rows.load(A.pd, s, lane);
+  const int64_t n = A.pd.n, r = rows.row;
+  const bool in = r < n;
+  for (int b = 0; b < A.B; ++b) {
+    if (sload(A.sys.outer + b) == 0) continue;
+    const int sh = b / A.m, c = b % A.m;
+    const double fr = in ? F[(int64_t)c * ldf + r] : 0.0;
+    cplx res = cx(fr);
+    if (xread) {
+      const cplx ka = sload_c(A.ca + sh), kb = sload_c(A.cb + sh);
+      const double* __restrict__ x = X + 2 * (int64_t)b * ldx;
+      cplx am = cx(0.0), ak = cx(0.0);
+#pragma unroll
+      for (int k = 0; k < WMAX; ++k) {
+        const int64_t cc = rows.col[k];
+        const int64_t ci = cc < n ? cc : 0;  // padding rows: col = row >= n
+        const cplx xc = cc < n ? cplx{x[2 * ci], x[2 * ci + 1]} : cx(0.0);
+        rfma(am, rows.mv[k], xc);
+        rfma(ak, rows.kv[k], xc);
+      }
+      res = in ? res - (ka * am + kb * ak) : cx(0.0);
+    }
+    A.vec(CR0, b)[r] = cf{(float)res.re, (float)res.im};
+    put_total(A, 2, b, s, lane, abs2(res));
+    put_total(A, 3, b, s, lane, fr * fr);
+  }
+}
+
+// X = 0 (complex float64 interleaved, n rows per column b).
+__global__ void k_czero_x(double* __restrict__ X, int64_t ldx, int64_t n) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double* x = X + 2 * ((int64_t)blockIdx.y * ldx + r);
+  x[0] = 0.0;
+  x[1] = 0.0;
+}
+
+// X += d (float32 solution of the inner solve) for the refined systems;
+// assign (first sweep): X = d.  Counts the sweep.
+__global__ void k_cir_update(CArgsT<cf> A, double* __restrict__ X, int64_t ldx, int assign) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (A.sys.outer[b] == 0) return;
+  if (r < A.pd.n) {
+    const cf d = A.vec(CX, b)[r];
+    double* x = X + 2 * ((int64_t)b * ldx + r);
+    x[0] = (assign ? 0.0 : x[0]) + (double)d.re;
+    x[1] = (assign ? 0.0 : x[1]) + (double)d.im;
+  }
+  if (r == 0) A.sys.sweeps[b] += 1;
+}
+
 struct CKernels {
-  void (*init)(CArgs, const double*, int64_t);
+  void (*init)(CArgs, const double*, int64_t, int);
   void (*dir)(CArgs, int);
   void (*upd)(CArgs, int);
   void (*resid)(CArgs, const double*, int64_t, double*, int64_t);
   void (*chain)(CArgs, int, int, int);
 };
 
+struct CKernels32 {
+  void (*init)(CArgsT<cf>, const double*, int64_t, int);
+  void (*dir)(CArgsT<cf>, int);
+  void (*upd)(CArgsT<cf>, int);
+  void (*chain)(CArgsT<cf>, int, int, int);
+};
+
+template <int W>
+CKernels32 ckernels32() {
+  return CKernels32{k_cinit<W, cf>, k_cdir<W, cf>, k_cupd<W, cf>, k_cchain<W, cf>};
+}
+
 template <int W>
 CKernels ckernels() {
-  return CKernels{k_cinit<W>, k_cdir<W>, k_cupd<W>, k_cresid<W>, k_cchain<W>};
+  return CKernels{k_cinit<W, cplx>, k_cdir<W, cplx>, k_cupd<W, cplx>, k_cresid<W>,
+                  k_cchain<W, cplx>};
+}
+
+// MIXED mode: float64 refinement around float32 COCG inner solves, every
+// system from X = 0.  A: the float64 setup (workspace, shift data, chains
+// of float factor copies, state); its vectors are reused as float complex.
+// A system ends CONVERGED once its float64 residual meets tol, MAXIT after
+// max_sweeps sweeps or max_iter inner iterations in all, BREAKDOWN or
+// NONFINITE when an inner solve does.
+airga_status cocg_mixed(airga_ctx ctx, const CArgs& A, const double* F, int64_t ldf,
+                        double* X, int64_t ldx, const airga_pcg_opts& o,
+                        airga_sys_stats* stats) {
+  hipStream_t st = ctx->stream;
+  const Pencil& pen = ctx->pen;
+  const int B = A.B;
+  const CSys& S = A.sys;
+  CArgsT<cf> A32{};
+  A32.pd = A.pd;
+  A32.B = B;
+  A32.m = A.m;
+  A32.ld = A.ld;
+  A32.ws = reinterpret_cast<cf*>(A.ws);
+  A32.ca = A.ca;
+  A32.cb = A.cb;
+  A32.fac = reinterpret_cast<const cf* const*>(A.fac);
+  A32.clen = A.clen;
+  A32.maxc = A.maxc;
+  A32.partial = A.partial;
+  A32.GP = A.GP;
+  A32.sys = S;
+  const unsigned grid = blocks_for(pen.n_slices, 4);
+  int k = o.poll_every < 2 ? 2 : o.poll_every;
+  k += k & 1;
+  int64_t cap = o.inner_max > 0 ? o.inner_max : 96;
+  cap = (cap + k - 1) / k * k;
+  CRed R{S, A.partial, B, A.GP, (int32_t)cap, o.beta_form == AIRGA_BETA_CLASSICAL ? 0 : 1,
+         o.inner_tol * o.inner_tol, o.tol * o.tol, o.max_sweeps, o.max_iter};
+  // zero float vectors (half as many float64 complex slots), X = 0, state
+  const int64_t half = (int64_t)CKINDS * B * A.ld / 2;
+  k_cfill<<<blocks_for(half, 256), 256, 0, st>>>(A.ws, half);
+  k_czero_x<<<dim3(blocks_for(pen.n, 256), (unsigned)B), 256, 0, st>>>(X, ldx, pen.n);
+  k_cstate_mixed<<<blocks_for(B, 256), 256, 0, st>>>(S, B);
+  // sweep 0: r = F
+  k_cresid_ir<6><<<grid, 256, 0, st>>>(A32, F, ldf, X, ldx, 0);
+  k_creduce<<<(unsigned)B, 256, 0, st>>>(R, CM_OUTER);
+  AIRGA_HIP(hipGetLastError());
+  AIRGA_TRY(ensure_pinned(ctx, 64));
+  int32_t* h_cnt = static_cast<int32_t*>(ctx->host_pinned);
+  const CKernels32 ks = ckernels32<6>();
+  const dim3 ir_grid(blocks_for(pen.n, 256), (unsigned)B);
+  const int64_t rounds = cap / k + 2;
+  for (int sweep = 0; sweep < o.max_sweeps; ++sweep) {
+    AIRGA_HIP(hipMemcpyAsync(h_cnt, S.nout, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    AIRGA_HIP(hipStreamSynchronize(st));
+    if (*h_cnt == 0) break;
+    // inner COCG on K(s) d = r from d = 0
+    k_cstart_inner<<<blocks_for(B, 256), 256, 0, st>>>(S, B);
+    ks.init<<<grid, 256, 0, st>>>(A32, F, ldf, 1);
+    for (int q = 1; q < A.maxc; ++q) ks.chain<<<grid, 256, 0, st>>>(A32, q, 1, 0);
+    k_creduce<<<(unsigned)B, 256, 0, st>>>(R, CM_INIT);
+    AIRGA_HIP(hipGetLastError());
+    for (int64_t round = 0; round < rounds; ++round) {
+      AIRGA_HIP(hipMemcpyAsync(h_cnt, S.nact, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      AIRGA_HIP(hipStreamSynchronize(st));
+      if (*h_cnt == 0) break;
+      for (int j = 0; j < k; ++j) {
+        const int par = j & 1;
+        ks.dir<<<grid, 256, 0, st>>>(A32, par);
+        k_creduce<<<(unsigned)B, 256, 0, st>>>(R, CM_PW);
+        ks.upd<<<grid, 256, 0, st>>>(A32, par);
+        for (int q = 1; q < A.maxc; ++q) ks.chain<<<grid, 256, 0, st>>>(A32, q, 0, par);
+        k_creduce<<<(unsigned)B, 256, 0, st>>>(R, CM_ITER);
+      }
+      AIRGA_HIP(hipGetLastError());
+    }
+    // X += d, then the float64 residual decides
+    k_cir_update<<<ir_grid, 256, 0, st>>>(A32, X, ldx, 0);
+    k_cresid_ir<6><<<grid, 256, 0, st>>>(A32, F, ldf, X, ldx, 1);
+    k_creduce<<<(unsigned)B, 256, 0, st>>>(R, CM_OUTER);
+    AIRGA_HIP(hipGetLastError());
+  }
+  // per-system results: relres, then status, sweeps and iterations
+  const size_t rb = sizeof(double) * B, ib = sizeof(int32_t) * B;
+  AIRGA_TRY(ensure_pinned(ctx, rb + 3 * ib));
+  char* h = static_cast<char*>(ctx->host_pinned);
+  AIRGA_HIP(hipMemcpyAsync(h, S.relres, rb, hipMemcpyDeviceToHost, st));
+  AIRGA_HIP(hipMemcpyAsync(h + rb, S.ostat, 3 * ib, hipMemcpyDeviceToHost, st));
+  AIRGA_HIP(hipStreamSynchronize(st));
+  if (stats) {
+    const double* rel = reinterpret_cast<const double*>(h);
+    const int32_t* ist = reinterpret_cast<const int32_t*>(h + rb);
+    for (int b = 0; b < B; ++b) {
+      stats[b].status = ist[b];
+      stats[b].sweeps = ist[B + b];
+      stats[b].iters = ist[2 * B + b];
+      stats[b].finished_fp64 = 0;
+      stats[b].relres = rel[b];
+    }
+  }
+  return AIRGA_OK;
 }
 
 airga_status check_cshift(const Pencil& pen, double re, double im) {
@@ -1088,9 +1402,11 @@ airga_status airga_spai_build_complex(airga_ctx ctx, double s_re, double s_im,
   const size_t npad = (size_t)pen.n_pad();
   airga_status st;
   if ((st = pool_get(ctx, &p->v64, sizeof(cplx) * stored)) != AIRGA_OK ||
+      (st = pool_get(ctx, &p->v32, 2 * sizeof(float) * stored)) != AIRGA_OK ||
       (st = pool_get(ctx, &p->objective, sizeof(double) * pen.n)) != AIRGA_OK ||
       (st = ctx->ws_tmp.reserve(sizeof(cplx) * (stored + npad))) != AIRGA_OK) {
     pool_put(ctx, &p->v64);
+    pool_put(ctx, &p->v32);
     pool_put(ctx, &p->objective);
     delete p;
     return st;
@@ -1120,7 +1436,8 @@ airga_status airga_spai_build_complex(airga_ctx ctx, double s_re, double s_im,
       pd, a, b, dinv, hat, p->objective.as<double>(), redo, cx(0.0), cx(0.0), nullptr, 0.0,
       nullptr, nullptr);
   k_cspai_finalize<<<blocks_for((int64_t)npad, 256), 256, 0, s>>>(
-      pd, hat, dinv, o.symmetrize ? 1 : 0, p->v64.as<cplx>(), nullptr, nullptr, nullptr);
+      pd, hat, dinv, o.symmetrize ? 1 : 0, p->v64.as<cplx>(), p->v32.as<float>(), nullptr,
+      nullptr, nullptr);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     airga_prec_release(p);
@@ -1164,11 +1481,13 @@ airga_status airga_spai_update_complex(airga_ctx ctx, airga_prec old, double s_r
   airga_status st;
   // scal: alpha (2 doubles) | skip count (int32 at 16) | skipped flags (from 64)
   if ((st = pool_get(ctx, &p->v64, sizeof(cplx) * stored)) != AIRGA_OK ||
+      (st = pool_get(ctx, &p->v32, 2 * sizeof(float) * stored)) != AIRGA_OK ||
       (st = pool_get(ctx, &p->objective, sizeof(double) * pen.n)) != AIRGA_OK ||
       (st = pool_get(ctx, &p->scal, 64 + npad)) != AIRGA_OK ||
       (st = ctx->ws_tmp.reserve(sizeof(cplx) * (stored + npad) + 3 * sizeof(double) * nb)) !=
           AIRGA_OK) {
     pool_put(ctx, &p->v64);
+    pool_put(ctx, &p->v32);
     pool_put(ctx, &p->objective);
     pool_put(ctx, &p->scal);
     delete p;
@@ -1207,9 +1526,8 @@ airga_status airga_spai_update_complex(airga_ctx ctx, airga_prec old, double s_r
   }
   k_cspai_cols<6, true><<<blocks_for(pen.n, 64), 64, 0, hs>>>(
       pd, a, b, dinv, hat, p->objective.as<double>(), redo, ao, bo, alpha_d, o.tol, skipf, skip);
-  k_cspai_finalize<<<blocks_for((int64_t)npad, 256), 256, 0, hs>>>(pd, hat, dinv, 0,
-                                                                   p->v64.as<cplx>(), skipf,
-                                                                   alpha_d, skip);
+  k_cspai_finalize<<<blocks_for((int64_t)npad, 256), 256, 0, hs>>>(
+      pd, hat, dinv, 0, p->v64.as<cplx>(), p->v32.as<float>(), skipf, alpha_d, skip);
   hipError_t e = hipGetLastError();
   // alpha and the skip count, read once (the solves need to know whether
   // the factor is the scalar alpha I)
@@ -1272,9 +1590,12 @@ airga_status airga_cocg_solve(airga_ctx ctx, int32_t nshift, const double* shift
   airga_pcg_opts o;
   airga_pcg_opts_default(&o);
   if (opts) o = *opts;
-  if (o.mode != AIRGA_MODE_FP64)
-    return fail(AIRGA_EUNSUPPORTED, "complex solves run in float64 only");
+  if (o.mode != AIRGA_MODE_FP64 && o.mode != AIRGA_MODE_MIXED)
+    return fail(AIRGA_EINVAL, "unknown mode");
+  const bool mixed = o.mode == AIRGA_MODE_MIXED;
   if (!(o.tol >= 0) || o.max_iter < 0) return fail(AIRGA_EINVAL, "bad tolerance or iteration cap");
+  if (mixed && (!(o.inner_tol > 0 && o.inner_tol < 1) || o.max_sweeps < 1 || o.inner_max < 0))
+    return fail(AIRGA_EINVAL, "bad refinement options");
   if (o.x0_given) return fail(AIRGA_EUNSUPPORTED, "complex solves start from X = 0");
   const int64_t B64 = (int64_t)nshift * m;
   if (B64 > 4096) return fail(AIRGA_EUNSUPPORTED, "more than 4096 systems");
@@ -1297,7 +1618,10 @@ airga_status airga_cocg_solve(airga_ctx ctx, int32_t nshift, const double* shift
         return fail(AIRGA_EINVAL, "shift %d: the factor was built at another shift", k);
       std::vector<airga_prec> ch;  // newest first
       AIRGA_TRY(prec_chain(p, &ch));
-      for (auto it = ch.rbegin(); it != ch.rend(); ++it) chains[k].push_back((*it)->v64.as<cplx>());
+      // MIXED: the float copies of the factors (cf, as the inner solves read them)
+      for (auto it = ch.rbegin(); it != ch.rend(); ++it)
+        chains[k].push_back(mixed ? reinterpret_cast<const cplx*>((*it)->v32.ptr)
+                                  : (*it)->v64.as<cplx>());
       maxc = (int)chains[k].size() > maxc ? (int)chains[k].size() : maxc;
     }
   }
@@ -1305,10 +1629,10 @@ airga_status airga_cocg_solve(airga_ctx ctx, int32_t nshift, const double* shift
   const int64_t ld = pen.n_pad();
   const int GP = pen.n_slices;
   // workspace: vectors | partials | per-shift data | per-system state
-  const size_t vec_b = sizeof(cplx) * (size_t)CKINDS * B * ld;
+  const size_t vec_b = (mixed ? sizeof(cf) : sizeof(cplx)) * (size_t)CKINDS * B * ld;
   const size_t part_b = sizeof(double) * (size_t)kCSlots * B * GP;
   const size_t shift_b = (2 * sizeof(cplx) + sizeof(void*) * maxc + sizeof(int32_t)) * (size_t)nshift;
-  const size_t sys_b = (4 * sizeof(cplx) + 3 * sizeof(double) + 3 * sizeof(int32_t)) * (size_t)B + 64;
+  const size_t sys_b = (4 * sizeof(cplx) + 4 * sizeof(double) + 7 * sizeof(int32_t)) * (size_t)B + 64;
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   AIRGA_TRY(ctx->ws_vec.reserve(al(vec_b) + al(part_b) + al(shift_b) + al(sys_b)));
   char* base = ctx->ws_vec.as<char>();
@@ -1332,9 +1656,11 @@ airga_status airga_cocg_solve(airga_ctx ctx, int32_t nshift, const double* shift
   cplx* cs = reinterpret_cast<cplx*>(sb);
   S.rho = cs; S.mu = cs + B; S.alpha = cs + 2 * B; S.beta = cs + 3 * B;
   double* ds = reinterpret_cast<double*>(cs + 4 * B);
-  S.tol2 = ds; S.ff = ds + B; S.relres = ds + 2 * B;
-  int32_t* is = reinterpret_cast<int32_t*>(ds + 3 * B);
-  S.active = is; S.istat = is + B; S.iters = is + 2 * B; S.nact = is + 3 * B;
+  S.tol2 = ds; S.ff = ds + B; S.relres = ds + 2 * B; S.fo = ds + 3 * B;
+  int32_t* is = reinterpret_cast<int32_t*>(ds + 4 * B);
+  S.active = is; S.istat = is + B; S.iters = is + 2 * B; S.outer = is + 3 * B;
+  S.ostat = is + 4 * B; S.sweeps = is + 5 * B; S.itot = is + 6 * B;
+  S.nact = is + 7 * B; S.nout = is + 7 * B + 1;
   A.sys = S;
   // per-shift data through pinned memory
   AIRGA_TRY(ensure_pinned(ctx, shift_b + 64));
@@ -1353,6 +1679,7 @@ airga_status airga_cocg_solve(airga_ctx ctx, int32_t nshift, const double* shift
   }
   AIRGA_HIP(hipMemcpyAsync(shb, hp, shift_b, hipMemcpyHostToDevice, st));
   AIRGA_HIP(hipStreamSynchronize(st));
+  if (mixed) return cocg_mixed(ctx, A, F, ldf, X, ldx, o, stats);
   // zero vectors (padding rows stay zero), fresh state
   k_cfill<<<blocks_for((int64_t)CKINDS * B * ld, 256), 256, 0, st>>>(A.ws, (int64_t)CKINDS * B * ld);
   k_cstate<<<blocks_for(B, 256), 256, 0, st>>>(S, B);
@@ -1361,7 +1688,7 @@ airga_status airga_cocg_solve(airga_ctx ctx, int32_t nshift, const double* shift
   const unsigned grid = blocks_for(pen.n_slices, 4);
   CRed R{S, A.partial, B, GP, o.max_iter, o.beta_form == AIRGA_BETA_CLASSICAL ? 0 : 1,
          o.tol * o.tol};
-  ks.init<<<grid, 256, 0, st>>>(A, F, ldf);
+  ks.init<<<grid, 256, 0, st>>>(A, F, ldf, 0);
   for (int q = 1; q < maxc; ++q) ks.chain<<<grid, 256, 0, st>>>(A, q, 1, 0);
   k_creduce<<<(unsigned)B, 256, 0, st>>>(R, CM_INIT);
   AIRGA_HIP(hipGetLastError());

@@ -228,6 +228,94 @@ def test_batched_cocg_matches_the_reference(ctx):
     assert sum(e["iters"] for e in st) < sum(e["iters"] for e in st0)
 
 
+def test_mixed_cocg_inner_iterates_follow_the_oracle(ctx):
+    """MIXED mode, one sweep of k float32 COCG steps from X = 0: X is the
+    oracle's float64 COCG iterate after k steps to float32 accuracy."""
+    pen = sur_beam(400)
+    set_pencil(ctx, pen)
+    f = np.random.default_rng(4).standard_normal((2, pen.n))
+    s = 2.0 + 1.5j
+    p = ctx.spai_build_complex(s)
+    a = pencil.shifted_operator_complex(pen, s)
+    cm = spai.spai_build(a).matrix()
+    for k in (2, 4, 8):
+        X, st = ctx.cocg_solve([s], [p], to_dev(f, torch.float64), tol=1e-30, mode=airga.MODE_MIXED,
+                               inner_tol=1e-12, inner_max=k, poll_every=2, max_sweeps=1)
+        for c in range(2):
+            assert st[c]["status"] == airga.SYS_MAXIT and st[c]["iters"] == k
+            assert st[c]["sweeps"] == 1
+            r = opcg.cocg(lambda v: a @ v, lambda v: cm @ v, f[c], tol=1e-30, max_iter=k)
+            assert rel_err(X[0, c].cpu().numpy(), r.x) < 1e-3, (k, c)
+
+
+def test_mixed_cocg_matches_the_reference(ctx):
+    """MIXED mode on the four points (factors and an update chain): every
+    system reaches the float64 residual tol and the complex double-double
+    reference, in a few sweeps."""
+    pen = sur_beam()
+    set_pencil(ctx, pen)
+    rng = np.random.default_rng(2)
+    f = np.stack([beam.tip_load(pen.n)[0], rng.standard_normal(pen.n)])
+    F = to_dev(f, torch.float64)
+    precs = [ctx.spai_build_complex(s) for s in SHIFTS]
+    X, st = ctx.cocg_solve(SHIFTS, precs, F, tol=1e-10, mode=airga.MODE_MIXED)
+    _, s64 = ctx.cocg_solve(SHIFTS, precs, F, tol=1e-10)
+    Xh = X.cpu().numpy()
+    for k, s in enumerate(SHIFTS):
+        ref = direct.reference_solve_complex(pen, s, f, "dd")
+        for c in range(2):
+            e = st[2 * k + c]
+            assert e["status"] == airga.SYS_CONVERGED, (s, c, e)
+            assert e["relres"] <= 1e-10 and 2 <= e["sweeps"] <= 4, (s, c, e)
+            assert rel_err(Xh[k, c], ref[c]) < 1e-8, (s, c)
+            # float32 sweeps restart the Krylov space: at most a few times
+            # the float64 iterations
+            assert e["iters"] <= 3 * s64[2 * k + c]["iters"] + 64, (e, s64[2 * k + c])
+    # a chain Q_3 Q_2 P_1 (float copies of every factor)
+    pts = [complex(v * np.exp(1j * np.pi / 6)) for v in (30.0, 34.0, 38.0)]
+    q3 = ctx.spai_update_complex(ctx.spai_update_complex(ctx.spai_build_complex(pts[0]), pts[1],
+                                                         tol=0.05), pts[2], tol=0.05)
+    assert q3.info().chain_len == 3
+    X, st = ctx.cocg_solve([pts[2]], [q3], F, tol=1e-10, mode=airga.MODE_MIXED)
+    ref = direct.reference_solve_complex(pen, pts[2], f, "dd")
+    for c in range(2):
+        assert st[c]["status"] == airga.SYS_CONVERGED and st[c]["relres"] <= 1e-10, st[c]
+        assert rel_err(X[0, c].cpu().numpy(), ref[c]) < 1e-8
+
+
+def test_mixed_cocg_edges_and_errors(ctx):
+    pen = sur_beam(70)   # n = 140: three slices, the last ragged
+    set_pencil(ctx, pen)
+    f = np.zeros((2, pen.n))
+    f[1, -2] = 1.0
+    s = 4.0 + 3.0j
+    p = ctx.spai_build_complex(s)
+    F = to_dev(f, torch.float64)
+    # a zero load is settled by the first residual: X = 0, no sweep
+    X, st = ctx.cocg_solve([s], [p], F, mode=airga.MODE_MIXED)
+    assert st[0]["status"] == airga.SYS_CONVERGED and st[0]["iters"] == 0 and st[0]["sweeps"] == 0
+    assert torch.count_nonzero(X[0, 0]).item() == 0
+    ref = direct.reference_solve_complex(pen, s, f[1:], "dd")[0]
+    assert st[1]["status"] == airga.SYS_CONVERGED
+    assert rel_err(X[0, 1].cpu().numpy(), ref) < 1e-8
+    # no preconditioner; the sweep cap and the total iteration cap
+    X, st = ctx.cocg_solve([s], None, F, mode=airga.MODE_MIXED)
+    assert st[1]["status"] == airga.SYS_CONVERGED
+    assert rel_err(X[0, 1].cpu().numpy(), ref) < 1e-8
+    _, st = ctx.cocg_solve([s], [p], F, tol=1e-30, mode=airga.MODE_MIXED, max_sweeps=2)
+    assert st[1]["status"] == airga.SYS_MAXIT and st[1]["sweeps"] == 2
+    _, st = ctx.cocg_solve([s], [p], F, tol=1e-30, mode=airga.MODE_MIXED, max_iter=5,
+                           inner_tol=1e-12, inner_max=4, poll_every=2)
+    assert st[1]["status"] == airga.SYS_MAXIT and st[1]["sweeps"] == 2 and st[1]["iters"] == 8
+    for bad in (dict(inner_tol=0.0), dict(inner_tol=1.0), dict(max_sweeps=0), dict(inner_max=-1)):
+        with pytest.raises(airga.AirgaError) as e:
+            ctx.cocg_solve([s], [p], F, mode=airga.MODE_MIXED, **bad)
+        assert e.value.status == airga.EINVAL, bad
+    with pytest.raises(airga.AirgaError) as e:
+        ctx.cocg_solve([s], [p], F, mode=7)
+    assert e.value.status == airga.EINVAL
+
+
 def test_complex_edge_cases_and_errors(ctx):
     pen = sur_beam(70)   # n = 140: three slices, the last ragged
     set_pencil(ctx, pen)
@@ -269,36 +357,46 @@ def test_complex_edge_cases_and_errors(ctx):
 def test_complex_full_size(ctx):
     """n = 1e6 surrogate beam, m = 4 seeded loads, 16 complex points
     s_k = sigma_k e^{i pi/6}, sigma_k logspace(0, 4, 16): all 64 systems in
-    one batched COCG, every one against the complex double-double reference
-    (8 threads)."""
+    one batched COCG, in float64 and in MIXED mode, every one against the
+    complex double-double reference (8 threads)."""
     pen, f, sig, _ = beam.make_workload("c3", surrogate=True)
     shifts = [complex(v) for v in np.asarray(sig) * np.exp(1j * np.pi / 6)]
     set_pencil(ctx, pen)
     precs = [ctx.spai_build_complex(s) for s in shifts]
-    X, st = ctx.cocg_solve(shifts, precs, to_dev(f, torch.float64), tol=1e-10)
+    F = to_dev(f, torch.float64)
+    X, st = ctx.cocg_solve(shifts, precs, F, tol=1e-10)
     assert all(e["status"] == airga.SYS_CONVERGED for e in st), [e for e in st if e["status"]]
+    Xh = X.cpu().numpy()
+    del X
+    X, sm = ctx.cocg_solve(shifts, precs, F, tol=1e-10, mode=airga.MODE_MIXED)
+    assert all(e["status"] == airga.SYS_CONVERGED and e["relres"] <= 1e-10 for e in sm), \
+        [e for e in sm if e["status"]]
+    Xm = X.cpu().numpy()
+    del X
     errs = {}
 
     def check(k, ref):
-        xk = X[k].cpu().numpy()
         for c in range(f.shape[0]):
-            errs[(k, c)] = rel_err(xk[c], ref[c])
+            errs[(k, c)] = rel_err(Xh[k, c], ref[c])
+            errs[("mixed", k, c)] = rel_err(Xm[k, c], ref[c])
     from concurrent.futures import ThreadPoolExecutor
     with ThreadPoolExecutor(8) as ex:
         for k, ref in enumerate(ex.map(lambda s: direct.reference_solve_complex(pen, s, f, "dd"),
                                        shifts)):
             check(k, ref)
     bad = {key: e for key, e in errs.items() if not e < 1e-8}
-    assert len(errs) == 64 and not bad, bad
+    assert len(errs) == 128 and not bad, bad
 
 
 def test_complex_updates_full_size(ctx):
     """n = 1e6: the 16 complex points' factors updated to points moved by
     up to 5% (seeded), every column's skip decision and every solved
     column's least squares on the full pencil, then COCG with the chains on
-    all 64 systems, every one within 1e-8 of the complex double-double
-    reference.  Systems whose recurrence residual stalls above tol (reading
-    X3) stop at the cap and must still meet 1e-8."""
+    all 64 systems, in float64 and in MIXED mode, every one within 1e-8 of
+    the complex double-double reference.  Systems whose recurrence residual
+    stalls above tol (COCG's short recurrences assume a complex symmetric
+    preconditioner, which a chain is not) stop at the cap and must still
+    meet 1e-8."""
     pen, f, sig, _ = beam.make_workload("c3", surrogate=True)
     e = np.exp(1j * np.pi / 6)
     drift = np.random.default_rng(7).uniform(-1.0, 1.0, len(sig))
@@ -309,16 +407,25 @@ def test_complex_updates_full_size(ctx):
     upd = [ctx.spai_update_complex(p, s) for p, s in zip(old, new)]
     infos = [u.info() for u in upd]
     assert any(0 < i.skipped_cols < pen.n for i in infos)
-    X, st = ctx.cocg_solve(new, upd, to_dev(f, torch.float64), tol=1e-10, max_iter=2000)
+    F = to_dev(f, torch.float64)
+    X, st = ctx.cocg_solve(new, upd, F, tol=1e-10, max_iter=2000)
     assert all(s["status"] in (airga.SYS_CONVERGED, airga.SYS_MAXIT) for s in st)
     assert sum(s["status"] == airga.SYS_CONVERGED for s in st) >= 56
+    Xh = X.cpu().numpy()
+    del X
+    # MIXED mode: each sweep restarts from the float64 residual
+    X, sm = ctx.cocg_solve(new, upd, F, tol=1e-10, max_iter=2000, mode=airga.MODE_MIXED)
+    assert all(s["status"] in (airga.SYS_CONVERGED, airga.SYS_MAXIT) for s in sm)
+    assert sum(s["status"] == airga.SYS_CONVERGED for s in sm) >= 56
+    Xm = X.cpu().numpy()
+    del X
     from concurrent.futures import ThreadPoolExecutor
     errs = {}
     with ThreadPoolExecutor(8) as ex:
         for k, ref in enumerate(ex.map(lambda s: direct.reference_solve_complex(pen, s, f, "dd"),
                                        new)):
-            xk = X[k].cpu().numpy()
             for c in range(f.shape[0]):
-                errs[(k, c)] = rel_err(xk[c], ref[c])
+                errs[(k, c)] = rel_err(Xh[k, c], ref[c])
+                errs[("mixed", k, c)] = rel_err(Xm[k, c], ref[c])
     bad = {key: v for key, v in errs.items() if not v < 1e-8}
-    assert len(errs) == 64 and not bad, bad
+    assert len(errs) == 128 and not bad, bad

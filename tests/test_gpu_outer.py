@@ -2,7 +2,7 @@
 (airga_reduce: batched SPAI builds or updates and PCG solves, the block
 operations of the moment sequence, the projection, and the decisions of the
 outer iteration) against the oracle's loop with exact sparse solves, with
-readings A1-A6 on both sides; the update across outer iterations of
+the readings A1-A6 of the oracle's airga_loop module on both sides; the update across outer iterations of
 Algorithm 5 where the points settle; and the solves at the next expansion
 points."""
 import numpy as np

@@ -836,7 +836,8 @@ def test_real_part_expansion_points_fall_below_the_low_modes():
     assert np.all(hist[1]["shifts"] < 0.1 * w_low)
 
 
-# ---- pins of readings A1 (choice of sigma) and A5 (the H2 stopping test)
+# ---- pins of the oracle's readings A1 (choice of sigma) and A5 (the H2
+# stopping test), as its airga_loop module states them
 
 def _diag_system(k=(1.0, 30.0, 900.0), alpha=0.1):
     """M = I, K = diag(k), D = alpha I, F = (1, 1, 1): every state
