@@ -281,6 +281,27 @@ def test_fp64_iterates_follow_the_oracle_recurrence(ctx, form, oracle_beta):
         assert rel_err(X6.cpu().numpy()[0, 0], r6.x) < 1e-12
 
 
+def test_mixed_inner_iterates_follow_the_oracle(ctx):
+    """MIXED mode stopped by max_iter inside its first sweep: X is the float32
+    PCG iterate after k steps (the sweep's correction added to X = 0), the
+    oracle's float64 iterate to float32 accuracy, for odd and even k."""
+    pen = sur_beam(700)
+    set_pencil(ctx, pen)
+    f = beam.tip_load(pen.n)
+    F = to_dev(f, torch.float64)
+    for s in (1.0, 100.0):
+        a = pencil.shifted_operator(pen, s)
+        pm = spai.spai_build(a).matrix()
+        p = ctx.spai_build(s)
+        for k in (1, 2, 3, 6, 7):
+            r = opcg.pcg(lambda v: a @ v, lambda v: pm @ v, f[0], tol=0.0, max_iter=k,
+                         beta="flexible")
+            X, st = ctx.pcg_solve([s], [p], F, tol=1e-30, mode=airga.MODE_MIXED, max_iter=k,
+                                  inner_tol=1e-12, max_sweeps=1, poll_every=2)
+            assert st[0]["status"] == airga.SYS_MAXIT and st[0]["iters"] == k, (s, k, st[0])
+            assert rel_err(X.cpu().numpy()[0, 0], r.x) < 1e-3, (s, k)
+
+
 def test_solve_with_update_chain(ctx):
     pen = sur_beam(900)
     set_pencil(ctx, pen)
