@@ -1008,23 +1008,98 @@ __host__ __device__ inline size_t spai_build_many_lds(int bw) {
 constexpr int kGramWave = 64;
 
 // Per-wavefront LDS of k_spai_gram_wave: window rows [o0 - 3 bw, o0 + 64 +
-// 2 bw): their scaled values (MJ each), columns and lengths, the diagonal
-// scaling of those rows +- bw, and the upper band of Khat^2 (2 bw + 1
+// 2 bw): their scaled values (MJ each, zero past a row's length), the
+// diagonal scaling of those rows +- bw, the upper band of Khat^2 (2 bw + 1
 // entries for rows [o0 - 2 bw, o0 + 64)), which then holds the columns'
-// coefficients.
+// coefficients, and per row its length, first column and stored position.
 template <int MJ>
 __host__ __device__ inline size_t spai_gram_wave_lds(int bw) {
   const size_t wr = kGramWave + 5 * (size_t)bw;
   const size_t band = (kGramWave + 2 * (size_t)bw) * (2 * (size_t)bw + 1);
   const size_t hatw = (size_t)kGramWave * MJ;
-  return wr * (MJ * (sizeof(double) + sizeof(int32_t)) + sizeof(int32_t)) +
-         sizeof(double) * (wr + 2 * (size_t)bw) + sizeof(double) * (band > hatw ? band : hatw);
+  return sizeof(double) * (MJ * wr + wr + 2 * (size_t)bw + (band > hatw ? band : hatw)) +
+         3 * sizeof(int32_t) * wr;
+}
+
+// Column j's normal equations from the band of Khat^2: G = U^T U (Cholesky,
+// G(k, i) = band row jb + k, offset i - k), U^T y = g, U p = y, with g(k) =
+// Khat(j, J_k) at vn[k * WR + jr], and the residual norm^2 from the
+// quadratic form.  FULL: every lane's column has MJ entries (no per-entry
+// tests).  Returns false when a pivot falls below 1e-8 of its diagonal (p is
+// then not set).
+template <int MJ, bool FULL>
+__device__ __forceinline__ bool gram_solve(const double* k2, int BW2, int jb, const double* vn,
+                                           int WR, int jr, int nj, double (&p)[MJ],
+                                           double& res2) {
+  double Uf[MJ * (MJ + 1) / 2], iu[MJ], y[MJ], g[MJ];
+  bool good = true;
+#pragma unroll
+  for (int k = 0; k < MJ; ++k) {
+    y[k] = 0.0;
+    iu[k] = 0.0;
+    g[k] = 0.0;
+    if (FULL || k < nj) {
+      const double* gk = k2 + (jb + k) * BW2;   // Khat^2(J_k, J_k + d)
+      g[k] = vn[k * WR + jr];                   // Khat(j, J_k)
+      double dkk = gk[0];
+#pragma unroll
+      for (int m = 0; m < MJ; ++m)
+        if (m < k) dkk = fma(-Uf[tri<MJ>(m, k)], Uf[tri<MJ>(m, k)], dkk);
+      good = good && dkk > 1e-8 * gk[0];
+      const double inv = dkk > 0.0 ? rsqrt_newton(dkk) : 0.0;
+      iu[k] = inv;
+      Uf[tri<MJ>(k, k)] = dkk * inv;
+#pragma unroll
+      for (int i = 0; i < MJ; ++i) {
+        if (i > k && (FULL || i < nj)) {
+          double gik = gk[i - k];
+#pragma unroll
+          for (int m = 0; m < MJ; ++m)
+            if (m < k) gik = fma(-Uf[tri<MJ>(m, i)], Uf[tri<MJ>(m, k)], gik);
+          Uf[tri<MJ>(k, i)] = gik * inv;
+        }
+      }
+      double yk = g[k];
+#pragma unroll
+      for (int m = 0; m < MJ; ++m)
+        if (m < k) yk = fma(-Uf[tri<MJ>(m, k)], y[m], yk);
+      y[k] = yk * inv;
+    }
+  }
+  if (!good) return false;
+#pragma unroll
+  for (int k = MJ - 1; k >= 0; --k) {
+    if (FULL || k < nj) {
+      double acc = y[k];
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i > k && (FULL || i < nj)) acc = fma(-Uf[tri<MJ>(k, i)], p[i], acc);
+      p[k] = acc * iu[k];
+    }
+  }
+  // ||e_j - B p||^2 = 1 - 2 g^T p + p^T G p, G from the band of Khat^2
+  double gp = 0.0, pgp = 0.0;
+#pragma unroll
+  for (int k = 0; k < MJ; ++k) {
+    if (FULL || k < nj) {
+      const double* gk = k2 + (jb + k) * BW2;
+      gp = fma(g[k], p[k], gp);
+      double row = gk[0] * p[k];
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i > k && (FULL || i < nj)) row = fma(2.0 * gk[i - k], p[i], row);
+      pgp = fma(p[k], row, pgp);
+    }
+  }
+  res2 = fma(-2.0, gp, 1.0) + pgp;
+  res2 = res2 > 0.0 ? res2 : 0.0;
+  return true;
 }
 
 // BWC > 0: the bandwidth as a compile-time constant (the window sizes and
 // the band's index arithmetic then fold); 0: bw_rt at run time.
 template <int MJ, int BWC>
-__global__ void __launch_bounds__(256) k_spai_gram_wave(PencilDev pd, UpdMany U,
+__global__ void __launch_bounds__(256, 3) k_spai_gram_wave(PencilDev pd, UpdMany U,
                                                         const double* __restrict__ dinv,
                                                         int64_t n_pad, int bw_rt, int sym,
                                                         size_t wave_lds) {
@@ -1040,8 +1115,9 @@ __global__ void __launch_bounds__(256) k_spai_gram_wave(PencilDev pd, UpdMany U,
   double* dl = vn + MJ * WR;                      // rows [w0 - bw, w0 + WR + bw)
   double* k2 = dl + WR + 2 * bw;
   const int K2N = R2 * BW2 > kGramWave * MJ ? R2 * BW2 : kGramWave * MJ;
-  int32_t* cl = reinterpret_cast<int32_t*>(k2 + K2N);
-  int32_t* ln = cl + MJ * WR;
+  int32_t* ln = reinterpret_cast<int32_t*>(k2 + K2N);
+  int32_t* cf = ln + WR;                          // first column (rows are consecutive runs)
+  int32_t* bs = cf + WR;                          // stored position of the first entry
   const int64_t n = pd.n;
   const int64_t o0 = ((int64_t)blockIdx.x * 4 + wv) * out;  // first output row
   if (o0 >= n_pad) return;                                  // whole wavefront
@@ -1052,16 +1128,19 @@ __global__ void __launch_bounds__(256) k_spai_gram_wave(PencilDev pd, UpdMany U,
     const int64_t row = w0 + r;
     const bool in = row >= 0 && row < n;
     const int len = in ? pd.row_len[row] : 0;
-    ln[r] = len;
     const int32_t base = in ? pd.slice_ptr[row / kSlice] + (int32_t)(row % kSlice) : 0;
-#pragma unroll
-    for (int k = 0; k < MJ; ++k) cl[k * WR + r] = k < len ? pd.col[base + k * kSlice] : -1;
+    ln[r] = len;
+    bs[r] = base;
+    cf[r] = len > 0 ? pd.col[base] : 0;
   }
   const int64_t j = c0 + lane;  // this lane's column
   const bool jin = j >= 0 && j < n;
   const int jr = (int)(j - w0);
+  // up to 2 bw + 1 band offsets, unrolled (bw <= 7 at run time)
+  constexpr int DMAX = BWC > 0 ? 2 * BWC + 1 : 15;
   for (int s = 0; s < U.count; ++s) {
     const double* __restrict__ dv = dinv + (int64_t)s * n_pad;
+    const double sa = U.a[s], sb = U.b[s];
     __builtin_amdgcn_wave_barrier();
     for (int r = lane; r < WR + 2 * bw; r += 64) {
       const int64_t row = w0 - bw + r;
@@ -1070,39 +1149,47 @@ __global__ void __launch_bounds__(256) k_spai_gram_wave(PencilDev pd, UpdMany U,
     __builtin_amdgcn_wave_barrier();
     // scaled values Khat(r, c) = S_r K(s)_rc S_c of the window rows
     for (int r = lane; r < WR; r += 64) {
-      const int64_t row = w0 + r;
       const int len = ln[r];
-      const int32_t base = len > 0 ? pd.slice_ptr[row / kSlice] + (int32_t)(row % kSlice) : 0;
+      const int32_t base = bs[r];
+      const int cw = cf[r] - (int)w0 + bw;  // scaling index of the first column
       const double sr = dl[r + bw];
 #pragma unroll
       for (int k = 0; k < MJ; ++k) {
         double v = 0.0;
         if (k < len) {
           const int32_t idx = base + k * kSlice;
-          const int32_t c = cl[k * WR + r];
-          v = fma(U.a[s], pd.m64[idx], U.b[s] * pd.k64[idx]) * sr * dl[(int)(c - w0) + bw];
+          v = fma(sa, pd.m64[idx], sb * pd.k64[idx]) * sr * dl[cw + k];
         }
         vn[k * WR + r] = v;
       }
     }
     __builtin_amdgcn_wave_barrier();
-    // upper band of Khat^2, one (row, offset) pair per lane and pass:
-    // Khat^2(i, i + d) = sum over k of Khat(i, k) Khat(i + d, k)
-    for (int e = lane; e < R2 * BW2; e += 64) {
-      const int q = e / BW2, d = e - q * BW2;
-      const int ir = (int)(k0 - w0) + q;  // window index of row i
-      const int cr = ir + d;              // window index of row i + d
-      double acc = 0.0;
-      if (cr < WR) {
-        const int li = ln[ir], lc = ln[cr];
-        if (li > 0 && lc > 0) {
-          const int i0 = cl[ir], cf = cl[cr];
-          const int lo = i0 > cf ? i0 : cf;
-          const int hi = (i0 + li < cf + lc) ? i0 + li : cf + lc;
-          for (int k = lo; k < hi; ++k) acc = fma(vn[(k - i0) * WR + ir], vn[(k - cf) * WR + cr], acc);
+    // upper band of Khat^2, one row per lane and pass: Khat^2(i, i + d) =
+    // sum over k of Khat(i, k) Khat(i + d, k), the values of row i kept in
+    // registers for its 2 bw + 1 offsets (entries past a row's length are
+    // zero, so every product of the overlap is taken)
+    for (int q = lane; q < R2; q += 64) {
+      const int ir = bw + q;  // window index of row k0 + q
+      const int ci = cf[ir];
+      double vi[MJ];
+#pragma unroll
+      for (int u = 0; u < MJ; ++u) vi[u] = vn[u * WR + ir];
+#pragma unroll
+      for (int d = 0; d < DMAX; ++d) {
+        if (d < BW2) {
+          const int cr = ir + d;
+          const int dc = cf[cr] - ci;
+          double acc = 0.0;
+#pragma unroll
+          for (int u = 0; u < MJ; ++u) {
+            const int qq = u - dc;
+            const bool ok = qq >= 0 && qq < MJ;
+            const double xv = vn[(ok ? qq : 0) * WR + cr];
+            acc = fma(vi[u], ok ? xv : 0.0, acc);
+          }
+          k2[q * BW2 + d] = acc;
         }
       }
-      k2[e] = acc;
     }
     __builtin_amdgcn_wave_barrier();
     // column j: Cholesky G = U^T U of G = Khat^2(J, J), g = Khat(J, j)
@@ -1111,117 +1198,61 @@ __global__ void __launch_bounds__(256) k_spai_gram_wave(PencilDev pd, UpdMany U,
     for (int u = 0; u < MJ; ++u) p[u] = 0.0;
     double res2 = 0.0;
     const int nj = jin ? ln[jr] : 0;
-    if (nj > 0) {
-      const int J0 = cl[jr];  // J = J0, J0 + 1, ..., J0 + nj - 1
-      double Uf[MJ * (MJ + 1) / 2], iu[MJ], y[MJ], g[MJ];
-      bool good = true;
+    const int J0 = nj > 0 ? cf[jr] : 0;  // J = J0, J0 + 1, ..., J0 + nj - 1
+    const int jb = J0 - (int)k0;
+    bool good = true;
+    if (__all(nj == MJ)) {
+      good = gram_solve<MJ, true>(k2, BW2, jb, vn, WR, jr, nj, p, res2);
+    } else if (nj > 0) {
+      good = gram_solve<MJ, false>(k2, BW2, jb, vn, WR, jr, nj, p, res2);
+    }
+    if (nj > 0 && !good) {
+      // Givens rotations over the rows I (the span of the patterns of J)
+      res2 = 0.0;
+      int lo = (int)j, hi = (int)j;
 #pragma unroll
-      for (int k = 0; k < MJ; ++k) {
-        y[k] = 0.0;
-        iu[k] = 0.0;
-        g[k] = 0.0;
-        if (k < nj) {
-          const double* gk = k2 + (J0 + k - (int)k0) * BW2;   // Khat^2(J_k, J_k + d)
-          g[k] = vn[k * WR + jr];                             // Khat(j, J_k)
-          double dkk = gk[0];
-#pragma unroll
-          for (int m = 0; m < MJ; ++m)
-            if (m < k) dkk = fma(-Uf[tri<MJ>(m, k)], Uf[tri<MJ>(m, k)], dkk);
-          good = good && dkk > 1e-8 * gk[0];
-          const double inv = dkk > 0.0 ? rsqrt_newton(dkk) : 0.0;
-          iu[k] = inv;
-          Uf[tri<MJ>(k, k)] = dkk * inv;
-#pragma unroll
-          for (int i = 0; i < MJ; ++i) {
-            if (i > k && i < nj) {
-              double gik = gk[i - k];
-#pragma unroll
-              for (int m = 0; m < MJ; ++m)
-                if (m < k) gik = fma(-Uf[tri<MJ>(m, i)], Uf[tri<MJ>(m, k)], gik);
-              Uf[tri<MJ>(k, i)] = gik * inv;
-            }
-          }
-          double yk = g[k];
-#pragma unroll
-          for (int m = 0; m < MJ; ++m)
-            if (m < k) yk = fma(-Uf[tri<MJ>(m, k)], y[m], yk);
-          y[k] = yk * inv;
+      for (int u = 0; u < MJ; ++u) {
+        if (u < nj) {
+          const int kr = J0 + u - (int)w0;
+          const int first = cf[kr], last = cf[kr] + ln[kr] - 1;
+          lo = first < lo ? first : lo;
+          hi = last > hi ? last : hi;
         }
       }
-      if (good) {
+      double R[MJ * (MJ + 1) / 2];
+      double qtb[MJ];
 #pragma unroll
-        for (int k = MJ - 1; k >= 0; --k) {
-          if (k < nj) {
-            double acc = y[k];
+      for (int q = 0; q < MJ * (MJ + 1) / 2; ++q) R[q] = 0.0;
 #pragma unroll
-            for (int i = 0; i < MJ; ++i)
-              if (i > k && i < nj) acc = fma(-Uf[tri<MJ>(k, i)], p[i], acc);
-            p[k] = acc * iu[k];
-          }
-        }
-        // ||e_j - B p||^2 = 1 - 2 g^T p + p^T G p, G from the band of Khat^2
-        double gp = 0.0, pgp = 0.0;
-#pragma unroll
-        for (int k = 0; k < MJ; ++k) {
-          if (k < nj) {
-            const double* gk = k2 + (J0 + k - (int)k0) * BW2;
-            gp = fma(g[k], p[k], gp);
-            double row = gk[0] * p[k];
-#pragma unroll
-            for (int i = 0; i < MJ; ++i)
-              if (i > k && i < nj) row = fma(2.0 * gk[i - k], p[i], row);
-            pgp = fma(p[k], row, pgp);
-          }
-        }
-        res2 = fma(-2.0, gp, 1.0) + pgp;
-        res2 = res2 > 0.0 ? res2 : 0.0;
-      } else {
-        // Givens rotations over the rows I (the span of the patterns of J)
-        int lo = (int)j, hi = (int)j;
+      for (int q = 0; q < MJ; ++q) qtb[q] = 0.0;
+      for (int i = lo; i <= hi; ++i) {
+        const int ir = (int)(i - w0);
+        const int i0 = cf[ir], li = ln[ir];
+        double v[MJ];
 #pragma unroll
         for (int u = 0; u < MJ; ++u) {
-          if (u < nj) {
-            const int kr = J0 + u - (int)w0;
-            const int first = cl[kr], last = cl[(ln[kr] - 1) * WR + kr];
-            lo = first < lo ? first : lo;
-            hi = last > hi ? last : hi;
-          }
+          const int q = J0 + u - i0;
+          const bool ok = u < nj && q >= 0 && q < li;
+          const double val = vn[(ok ? q : 0) * WR + ir];
+          v[u] = ok ? val : 0.0;
         }
-        double R[MJ * (MJ + 1) / 2];
-        double qtb[MJ];
+        double rhs = i == (int)j ? 1.0 : 0.0;
+        givens_row<MJ>(R, qtb, v, rhs, nj);
+        res2 = fma(rhs, rhs, res2);
+      }
 #pragma unroll
-        for (int q = 0; q < MJ * (MJ + 1) / 2; ++q) R[q] = 0.0;
+      for (int q = MJ - 1; q >= 0; --q) {
+        if (q < nj) {
+          double acc = qtb[q];
 #pragma unroll
-        for (int q = 0; q < MJ; ++q) qtb[q] = 0.0;
-        for (int i = lo; i <= hi; ++i) {
-          const int ir = (int)(i - w0);
-          const int i0 = cl[ir], li = ln[ir];
-          double v[MJ];
-#pragma unroll
-          for (int u = 0; u < MJ; ++u) {
-            const int q = J0 + u - i0;
-            const bool ok = u < nj && q >= 0 && q < li;
-            const double val = vn[(ok ? q : 0) * WR + ir];
-            v[u] = ok ? val : 0.0;
-          }
-          double rhs = i == (int)j ? 1.0 : 0.0;
-          givens_row<MJ>(R, qtb, v, rhs, nj);
-          res2 = fma(rhs, rhs, res2);
-        }
-#pragma unroll
-        for (int q = MJ - 1; q >= 0; --q) {
-          if (q < nj) {
-            double acc = qtb[q];
-#pragma unroll
-            for (int u = q + 1; u < MJ; ++u)
-              if (u < nj) acc = fma(-R[tri<MJ>(q, u)], p[u], acc);
-            const double d = R[tri<MJ>(q, q)];
-            p[q] = d != 0.0 ? acc / d : 0.0;
-          }
+          for (int u = q + 1; u < MJ; ++u)
+            if (u < nj) acc = fma(-R[tri<MJ>(q, u)], p[u], acc);
+          const double d = R[tri<MJ>(q, q)];
+          p[q] = d != 0.0 ? acc / d : 0.0;
         }
       }
-      if (lane >= bw && lane < bw + out) U.obj[s][j] = sqrt(res2);
     }
+    if (nj > 0 && lane >= bw && lane < bw + out) U.obj[s][j] = sqrt(res2);
     __builtin_amdgcn_wave_barrier();  // every lane has read the band
     // coefficient u of column c0 + lane (row J0 + u of Phat)
 #pragma unroll
@@ -1236,7 +1267,7 @@ __global__ void __launch_bounds__(256) k_spai_gram_wave(PencilDev pd, UpdMany U,
       const int rr = (int)(r - w0);
       const int len = r < n ? ln[rr] : 0;
       const double sr = r < n ? dl[rr + bw] : 0.0;
-      const int r0 = len > 0 ? cl[rr] : 0;
+      const int r0 = len > 0 ? cf[rr] : 0;
       double* __restrict__ o64 = U.v64[s];
       float* __restrict__ o32 = U.v32[s];
       for (int k = 0; k < w; ++k) {
@@ -1244,9 +1275,9 @@ __global__ void __launch_bounds__(256) k_spai_gram_wave(PencilDev pd, UpdMany U,
         if (k < len) {
           const int c = r0 + k;
           const int cr = (int)(c - w0);
-          const int cf = cl[cr];
-          double h = k2[(int)(c - c0) * MJ + (int)(r - cf)];  // column c at row r
-          if (sym) h = 0.5 * (h + k2[lane * MJ + k]);         // column r at row c
+          const int cfc = cf[cr];
+          double h = k2[(int)(c - c0) * MJ + (int)(r - cfc)];  // column c at row r
+          if (sym) h = 0.5 * (h + k2[lane * MJ + k]);          // column r at row c
           val = h * sr * dl[cr + bw];
         }
         const int32_t idx = base + k * kSlice;
