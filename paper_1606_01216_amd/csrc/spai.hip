@@ -1011,14 +1011,15 @@ constexpr int kGramWave = 64;
 // 2 bw): their scaled values (MJ each, zero past a row's length), the
 // diagonal scaling of those rows +- bw, the upper band of Khat^2 (2 bw + 1
 // entries for rows [o0 - 2 bw, o0 + 64)), which then holds the columns'
-// coefficients, and per row its length, first column and stored position.
+// coefficients, and per row its length, first column, stored position and
+// slice width.
 template <int MJ>
 __host__ __device__ inline size_t spai_gram_wave_lds(int bw) {
   const size_t wr = kGramWave + 5 * (size_t)bw;
   const size_t band = (kGramWave + 2 * (size_t)bw) * (2 * (size_t)bw + 1);
   const size_t hatw = (size_t)kGramWave * MJ;
   return sizeof(double) * (MJ * wr + wr + 2 * (size_t)bw + (band > hatw ? band : hatw)) +
-         3 * sizeof(int32_t) * wr;
+         4 * sizeof(int32_t) * wr;
 }
 
 // Column j's normal equations from the band of Khat^2: G = U^T U (Cholesky,
@@ -1118,6 +1119,7 @@ __global__ void __launch_bounds__(256, 3) k_spai_gram_wave(PencilDev pd, UpdMany
   int32_t* ln = reinterpret_cast<int32_t*>(k2 + K2N);
   int32_t* cf = ln + WR;                          // first column (rows are consecutive runs)
   int32_t* bs = cf + WR;                          // stored position of the first entry
+  int32_t* wd = bs + WR;                          // width of the row's slice
   const int64_t n = pd.n;
   const int64_t o0 = ((int64_t)blockIdx.x * 4 + wv) * out;  // first output row
   if (o0 >= n_pad) return;                                  // whole wavefront
@@ -1127,10 +1129,17 @@ __global__ void __launch_bounds__(256, 3) k_spai_gram_wave(PencilDev pd, UpdMany
   for (int r = lane; r < WR; r += 64) {
     const int64_t row = w0 + r;
     const bool in = row >= 0 && row < n;
+    const bool stored = row >= 0 && row < n_pad;  // padding rows hold zeros
     const int len = in ? pd.row_len[row] : 0;
-    const int32_t base = in ? pd.slice_ptr[row / kSlice] + (int32_t)(row % kSlice) : 0;
+    int32_t base = 0, w = 0;
+    if (stored) {
+      const int32_t sp0 = pd.slice_ptr[row / kSlice];
+      base = sp0 + (int32_t)(row % kSlice);
+      w = (pd.slice_ptr[row / kSlice + 1] - sp0) / kSlice;
+    }
     ln[r] = len;
     bs[r] = base;
+    wd[r] = w;
     cf[r] = len > 0 ? pd.col[base] : 0;
   }
   const int64_t j = c0 + lane;  // this lane's column
@@ -1164,11 +1173,12 @@ __global__ void __launch_bounds__(256, 3) k_spai_gram_wave(PencilDev pd, UpdMany
       }
     }
     __builtin_amdgcn_wave_barrier();
-    // upper band of Khat^2, one row per lane and pass: Khat^2(i, i + d) =
-    // sum over k of Khat(i, k) Khat(i + d, k), the values of row i kept in
-    // registers for its 2 bw + 1 offsets (entries past a row's length are
-    // zero, so every product of the overlap is taken)
-    for (int q = lane; q < R2; q += 64) {
+    // upper band of Khat^2: Khat^2(i, i + d) = sum over k of Khat(i, k)
+    // Khat(i + d, k) (entries past a row's length are zero, so every product
+    // of the overlap is taken).  Rows 0..63 of the band one per lane, the
+    // values of row i kept in registers for its 2 bw + 1 offsets:
+    {
+      const int q = lane;
       const int ir = bw + q;  // window index of row k0 + q
       const int ci = cf[ir];
       double vi[MJ];
@@ -1190,6 +1200,23 @@ __global__ void __launch_bounds__(256, 3) k_spai_gram_wave(PencilDev pd, UpdMany
           k2[q * BW2 + d] = acc;
         }
       }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // the last 2 bw rows: one (row, offset) pair per lane
+    for (int e = lane; e < (R2 - 64) * BW2; e += 64) {
+      const int q = 64 + e / BW2, d = e - (q - 64) * BW2;
+      const int ir = bw + q;
+      const int cr = ir + d;
+      const int dc = cf[cr] - cf[ir];
+      double acc = 0.0;
+#pragma unroll
+      for (int u = 0; u < MJ; ++u) {
+        const int qq = u - dc;
+        const bool ok = qq >= 0 && qq < MJ;
+        const double xv = vn[(ok ? qq : 0) * WR + cr];
+        acc = fma(vn[u * WR + ir], ok ? xv : 0.0, acc);
+      }
+      k2[q * BW2 + d] = acc;
     }
     __builtin_amdgcn_wave_barrier();
     // column j: Cholesky G = U^T U of G = Khat^2(J, J), g = Khat(J, j)
@@ -1261,10 +1288,9 @@ __global__ void __launch_bounds__(256, 3) k_spai_gram_wave(PencilDev pd, UpdMany
     // the final factor for rows [o0, o0 + out): P(r, c) = S_r Pbar(r, c) S_c
     const int64_t r = o0 + (lane - bw);
     if (lane >= bw && lane < bw + out && r < n_pad) {
-      const int64_t sl = r / kSlice;
-      const int32_t base = pd.slice_ptr[sl] + (int32_t)(r % kSlice);
-      const int w = (pd.slice_ptr[sl + 1] - pd.slice_ptr[sl]) / kSlice;
       const int rr = (int)(r - w0);
+      const int32_t base = bs[rr];
+      const int w = wd[rr];
       const int len = r < n ? ln[rr] : 0;
       const double sr = r < n ? dl[rr + bw] : 0.0;
       const int r0 = len > 0 ? cf[rr] : 0;
