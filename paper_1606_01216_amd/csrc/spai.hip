@@ -1156,21 +1156,41 @@ __global__ void __launch_bounds__(256, 3) k_spai_gram_wave(PencilDev pd, UpdMany
       dl[r] = (row >= 0 && row < n) ? dv[row] : 0.0;
     }
     __builtin_amdgcn_wave_barrier();
-    // scaled values Khat(r, c) = S_r K(s)_rc S_c of the window rows
-    for (int r = lane; r < WR; r += 64) {
+    // scaled values Khat(r, c) = S_r K(s)_rc S_c of the window rows: rows
+    // 0..63 one per lane (no per-entry tests where every row is full), the
+    // last 5 bw rows one (row, entry) pair per lane
+    {
+      const int r = lane;
       const int len = ln[r];
       const int32_t base = bs[r];
       const int cw = cf[r] - (int)w0 + bw;  // scaling index of the first column
       const double sr = dl[r + bw];
+      if (__all(len == MJ)) {
 #pragma unroll
-      for (int k = 0; k < MJ; ++k) {
-        double v = 0.0;
-        if (k < len) {
+        for (int k = 0; k < MJ; ++k) {
           const int32_t idx = base + k * kSlice;
-          v = fma(sa, pd.m64[idx], sb * pd.k64[idx]) * sr * dl[cw + k];
+          vn[k * WR + r] = fma(sa, pd.m64[idx], sb * pd.k64[idx]) * sr * dl[cw + k];
         }
-        vn[k * WR + r] = v;
+      } else {
+#pragma unroll
+        for (int k = 0; k < MJ; ++k) {
+          double v = 0.0;
+          if (k < len) {
+            const int32_t idx = base + k * kSlice;
+            v = fma(sa, pd.m64[idx], sb * pd.k64[idx]) * sr * dl[cw + k];
+          }
+          vn[k * WR + r] = v;
+        }
       }
+    }
+    for (int e = lane; e < (WR - 64) * MJ; e += 64) {
+      const int r = 64 + e / MJ, k = e - (r - 64) * MJ;
+      double v = 0.0;
+      if (k < ln[r]) {
+        const int32_t idx = bs[r] + k * kSlice;
+        v = fma(sa, pd.m64[idx], sb * pd.k64[idx]) * dl[r + bw] * dl[cf[r] - (int)w0 + bw + k];
+      }
+      vn[k * WR + r] = v;
     }
     __builtin_amdgcn_wave_barrier();
     // upper band of Khat^2: Khat^2(i, i + d) = sum over k of Khat(i, k)
@@ -1287,7 +1307,31 @@ __global__ void __launch_bounds__(256, 3) k_spai_gram_wave(PencilDev pd, UpdMany
     __builtin_amdgcn_wave_barrier();
     // the final factor for rows [o0, o0 + out): P(r, c) = S_r Pbar(r, c) S_c
     const int64_t r = o0 + (lane - bw);
-    if (lane >= bw && lane < bw + out && r < n_pad) {
+    const bool wr_row = lane >= bw && lane < bw + out && r < n_pad;
+    const int rw = lane + 2 * bw;  // window index of row r
+    const bool fullrow = r < n && wd[rw] == MJ && ln[rw] == MJ;
+    if (__all(fullrow || !wr_row)) {
+      // every written row is full: no per-entry tests
+      if (wr_row) {
+        const int32_t base = bs[rw];
+        const double sr = dl[rw + bw];
+        const int r0 = cf[rw];
+        double* __restrict__ o64 = U.v64[s];
+        float* __restrict__ o32 = U.v32[s];
+#pragma unroll
+        for (int k = 0; k < MJ; ++k) {
+          const int c = r0 + k;
+          const int cr = (int)(c - w0);
+          const int cfc = cf[cr];
+          double h = k2[(int)(c - c0) * MJ + (int)(r - cfc)];  // column c at row r
+          if (sym) h = 0.5 * (h + k2[lane * MJ + k]);          // column r at row c
+          const double val = h * sr * dl[cr + bw];
+          const int32_t idx = base + k * kSlice;
+          o64[idx] = val;
+          o32[idx] = (float)val;
+        }
+      }
+    } else if (wr_row) {
       const int rr = (int)(r - w0);
       const int32_t base = bs[rr];
       const int w = wd[rr];
