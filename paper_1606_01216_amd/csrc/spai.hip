@@ -1009,16 +1009,17 @@ constexpr int kGramWave = 64;
 
 // Per-wavefront LDS of k_spai_gram_wave: window rows [o0 - 3 bw, o0 + 64 +
 // 2 bw): their scaled values (MJ each, zero past a row's length), the
-// diagonal scaling of those rows +- bw, the upper band of Khat^2 (2 bw + 1
-// entries for rows [o0 - 2 bw, o0 + 64)), which then holds the columns'
-// coefficients, and per row its length, first column, stored position and
-// slice width.
+// diagonal scaling of those rows +- bw and their diagonal entries of M and
+// K, the upper band of Khat^2 (2 bw + 1 entries for rows [o0 - 2 bw, o0 +
+// 64)), which then holds the columns' coefficients, and per row its length,
+// first column, stored position and slice width.
 template <int MJ>
 __host__ __device__ inline size_t spai_gram_wave_lds(int bw) {
   const size_t wr = kGramWave + 5 * (size_t)bw;
   const size_t band = (kGramWave + 2 * (size_t)bw) * (2 * (size_t)bw + 1);
   const size_t hatw = (size_t)kGramWave * MJ;
-  return sizeof(double) * (MJ * wr + wr + 2 * (size_t)bw + (band > hatw ? band : hatw)) +
+  return sizeof(double) *
+             (MJ * wr + 3 * (wr + 2 * (size_t)bw) + (band > hatw ? band : hatw)) +
          4 * sizeof(int32_t) * wr;
 }
 
@@ -1101,7 +1102,6 @@ __device__ __forceinline__ bool gram_solve(const double* k2, int BW2, int jb, co
 // the band's index arithmetic then fold); 0: bw_rt at run time.
 template <int MJ, int BWC>
 __global__ void __launch_bounds__(256, 3) k_spai_gram_wave(PencilDev pd, UpdMany U,
-                                                        const double* __restrict__ dinv,
                                                         int64_t n_pad, int bw_rt, int sym,
                                                         size_t wave_lds) {
   const int bw = BWC > 0 ? BWC : bw_rt;
@@ -1114,7 +1114,9 @@ __global__ void __launch_bounds__(256, 3) k_spai_gram_wave(PencilDev pd, UpdMany
   const int R2 = kGramWave + 2 * bw;              // rows of the Khat^2 band
   double* vn = reinterpret_cast<double*>(reinterpret_cast<char*>(lds_all) + wv * wave_lds);
   double* dl = vn + MJ * WR;                      // rows [w0 - bw, w0 + WR + bw)
-  double* k2 = dl + WR + 2 * bw;
+  double* md = dl + WR + 2 * bw;                  // diag(M), diag(K) of those rows
+  double* kd = md + WR + 2 * bw;
+  double* k2 = kd + WR + 2 * bw;
   const int K2N = R2 * BW2 > kGramWave * MJ ? R2 * BW2 : kGramWave * MJ;
   int32_t* ln = reinterpret_cast<int32_t*>(k2 + K2N);
   int32_t* cf = ln + WR;                          // first column (rows are consecutive runs)
@@ -1142,18 +1144,30 @@ __global__ void __launch_bounds__(256, 3) k_spai_gram_wave(PencilDev pd, UpdMany
     wd[r] = w;
     cf[r] = len > 0 ? pd.col[base] : 0;
   }
+  for (int r = lane; r < WR + 2 * bw; r += 64) {
+    const int64_t row = w0 - bw + r;
+    double m = 0.0, k = 0.0;
+    if (row >= 0 && row < n) {
+      const int32_t q = pd.diag_pos[row];
+      m = pd.m64[q];
+      k = pd.k64[q];
+    }
+    md[r] = m;
+    kd[r] = k;
+  }
   const int64_t j = c0 + lane;  // this lane's column
   const bool jin = j >= 0 && j < n;
   const int jr = (int)(j - w0);
   // up to 2 bw + 1 band offsets, unrolled (bw <= 7 at run time)
   constexpr int DMAX = BWC > 0 ? 2 * BWC + 1 : 15;
   for (int s = 0; s < U.count; ++s) {
-    const double* __restrict__ dv = dinv + (int64_t)s * n_pad;
     const double sa = U.a[s], sb = U.b[s];
     __builtin_amdgcn_wave_barrier();
+    // the diagonal scaling diag(K(s))^{-1/2} of the rows (equilibrated
+    // builds only), 0 outside the matrix
     for (int r = lane; r < WR + 2 * bw; r += 64) {
       const int64_t row = w0 - bw + r;
-      dl[r] = (row >= 0 && row < n) ? dv[row] : 0.0;
+      dl[r] = (row >= 0 && row < n) ? 1.0 / sqrt(fma(sa, md[r], sb * kd[r])) : 0.0;
     }
     __builtin_amdgcn_wave_barrier();
     // scaled values Khat(r, c) = S_r K(s)_rc S_c of the window rows: rows
@@ -2075,26 +2089,27 @@ static airga_status run_build_many(airga_ctx ctx, int32_t count, const double* s
       shift_coeffs(pen, shifts[i0 + i], &U.a[i], &U.b[i]);
       U.obj[i] = ps[i0 + i]->objective.as<double>();
     }
-    k_dinv_many<<<nr, 256, 0, st>>>(pd, U, o.equilibrate, n_pad, dinv);
-    AIRGA_HIP(hipGetLastError());
     if (gram) {
+      // the diagonal scaling is formed inside the kernel from diag(M), diag(K)
       for (int i = 0; i < cnt; ++i) {
         U.v64[i] = ps[i0 + i]->v64.as<double>();
         U.v32[i] = ps[i0 + i]->v32.as<float>();
       }
       if (bw == 3)
-        k_spai_gram_wave<6, 3><<<ng, 256, 4 * wave_lds, st>>>(pd, U, dinv, n_pad, bw,
+        k_spai_gram_wave<6, 3><<<ng, 256, 4 * wave_lds, st>>>(pd, U, n_pad, bw,
                                                              o.symmetrize ? 1 : 0, wave_lds);
       else
-        k_spai_gram_wave<6, 0><<<ng, 256, 4 * wave_lds, st>>>(pd, U, dinv, n_pad, bw,
+        k_spai_gram_wave<6, 0><<<ng, 256, 4 * wave_lds, st>>>(pd, U, n_pad, bw,
                                                              o.symmetrize ? 1 : 0, wave_lds);
-      AIRGA_HIP(hipGetLastError());
-    } else if (range && pen.contiguous)
-      k_spai_build_many<6, 2><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, hat);
-    else if (range)
-      k_spai_build_many<6, 1><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, hat);
-    else
-      k_spai_build_many<6, 0><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, hat);
+    } else {
+      k_dinv_many<<<nr, 256, 0, st>>>(pd, U, o.equilibrate, n_pad, dinv);
+      if (range && pen.contiguous)
+        k_spai_build_many<6, 2><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, hat);
+      else if (range)
+        k_spai_build_many<6, 1><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, hat);
+      else
+        k_spai_build_many<6, 0><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, hat);
+    }
     AIRGA_HIP(hipGetLastError());
     for (int i = 0; i < cnt; ++i) {
       const airga_prec p = ps[i0 + i];
