@@ -1313,7 +1313,10 @@ __global__ void __launch_bounds__(256, 3) k_spai_gram_wave(PencilDev pd, UpdMany
         }
       }
     }
-    if (nj > 0 && lane >= bw && lane < bw + out) U.obj[s][j] = sqrt(res2);
+    // streaming stores for the objective and the factors (written once, read
+    // by later kernels), so they do not push the window rows' M and K values,
+    // re-read for every shift, out of the cache
+    if (nj > 0 && lane >= bw && lane < bw + out) __builtin_nontemporal_store(sqrt(res2), &U.obj[s][j]);
     __builtin_amdgcn_wave_barrier();  // every lane has read the band
     // coefficient u of column c0 + lane (row J0 + u of Phat)
 #pragma unroll
@@ -1341,8 +1344,8 @@ __global__ void __launch_bounds__(256, 3) k_spai_gram_wave(PencilDev pd, UpdMany
           if (sym) h = 0.5 * (h + k2[lane * MJ + k]);          // column r at row c
           const double val = h * sr * dl[cr + bw];
           const int32_t idx = base + k * kSlice;
-          o64[idx] = val;
-          o32[idx] = (float)val;
+          __builtin_nontemporal_store(val, &o64[idx]);
+          __builtin_nontemporal_store((float)val, &o32[idx]);
         }
       }
     } else if (wr_row) {
@@ -1365,8 +1368,8 @@ __global__ void __launch_bounds__(256, 3) k_spai_gram_wave(PencilDev pd, UpdMany
           val = h * sr * dl[cr + bw];
         }
         const int32_t idx = base + k * kSlice;
-        o64[idx] = val;
-        o32[idx] = (float)val;
+        __builtin_nontemporal_store(val, &o64[idx]);
+        __builtin_nontemporal_store((float)val, &o32[idx]);
       }
     }
   }
