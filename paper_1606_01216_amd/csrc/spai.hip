@@ -1048,7 +1048,9 @@ __device__ __forceinline__ bool gram_solve(const double* k2, int BW2, int jb, co
       for (int m = 0; m < MJ; ++m)
         if (m < k) dkk = fma(-Uf[tri<MJ>(m, k)], Uf[tri<MJ>(m, k)], dkk);
       good = good && dkk > 1e-8 * gk[0];
-      const double inv = dkk > 0.0 ? rsqrt_newton(dkk) : 0.0;
+      // without a branch: the reciprocal root of a stand-in 1 where dkk <= 0
+      const double inv0 = rsqrt_newton(dkk > 0.0 ? dkk : 1.0);
+      const double inv = dkk > 0.0 ? inv0 : 0.0;
       iu[k] = inv;
       Uf[tri<MJ>(k, k)] = dkk * inv;
 #pragma unroll
