@@ -228,9 +228,12 @@ def test_batched_cocg_matches_the_reference(ctx):
     assert sum(e["iters"] for e in st) < sum(e["iters"] for e in st0)
 
 
-def test_mixed_cocg_inner_iterates_follow_the_oracle(ctx):
+@pytest.mark.parametrize("form,oform", [(airga.BETA_FLEXIBLE, "flexible"),
+                                        (airga.BETA_CLASSICAL, "fr")])
+def test_mixed_cocg_inner_iterates_follow_the_oracle(ctx, form, oform):
     """MIXED mode, one sweep of k float32 COCG steps from X = 0: X is the
-    oracle's float64 COCG iterate after k steps to float32 accuracy."""
+    oracle's float64 COCG iterate after k steps to float32 accuracy, for
+    both direction updates."""
     pen = sur_beam(400)
     set_pencil(ctx, pen)
     f = np.random.default_rng(4).standard_normal((2, pen.n))
@@ -240,11 +243,38 @@ def test_mixed_cocg_inner_iterates_follow_the_oracle(ctx):
     cm = spai.spai_build(a).matrix()
     for k in (2, 4, 8):
         X, st = ctx.cocg_solve([s], [p], to_dev(f, torch.float64), tol=1e-30, mode=airga.MODE_MIXED,
-                               inner_tol=1e-12, inner_max=k, poll_every=2, max_sweeps=1)
+                               inner_tol=1e-12, inner_max=k, poll_every=2, max_sweeps=1,
+                               beta_form=form)
         for c in range(2):
             assert st[c]["status"] == airga.SYS_MAXIT and st[c]["iters"] == k
             assert st[c]["sweeps"] == 1
-            r = opcg.cocg(lambda v: a @ v, lambda v: cm @ v, f[c], tol=1e-30, max_iter=k)
+            r = opcg.cocg(lambda v: a @ v, lambda v: cm @ v, f[c], tol=1e-30, max_iter=k,
+                          beta=oform)
+            assert rel_err(X[0, c].cpu().numpy(), r.x) < 1e-3, (k, c)
+
+
+def test_mixed_cocg_chain_iterates_follow_the_oracle(ctx):
+    """MIXED mode with an update chain Q_3 Q_2 P_1 (the float copies of
+    every factor), one sweep of k steps: the oracle's float64 COCG with the
+    oracle's own chain, to float32 accuracy."""
+    pen = sur_beam(1037)
+    set_pencil(ctx, pen)
+    pts = [complex(v * np.exp(1j * np.pi / 6)) for v in (30.0, 34.0, 38.0)]
+    q3 = ctx.spai_update_complex(ctx.spai_update_complex(ctx.spai_build_complex(pts[0]), pts[1],
+                                                         tol=0.05), pts[2], tol=0.05)
+    assert q3.info().chain_len == 3
+    ops = [pencil.shifted_operator_complex(pen, z) for z in pts]
+    chain = [spai.spai_build(ops[0]), spai.spai_update(ops[0], ops[1], tol=0.05),
+             spai.spai_update(ops[1], ops[2], tol=0.05)]
+    f = np.random.default_rng(9).standard_normal((2, pen.n))
+    for k in (2, 6):
+        X, st = ctx.cocg_solve([pts[2]], [q3], to_dev(f, torch.float64), tol=1e-30,
+                               mode=airga.MODE_MIXED, inner_tol=1e-12, inner_max=k, poll_every=2,
+                               max_sweeps=1)
+        for c in range(2):
+            assert st[c]["iters"] == k
+            r = opcg.cocg(lambda v: ops[2] @ v, lambda v: spai.chain_apply(chain, v), f[c],
+                          tol=1e-30, max_iter=k)
             assert rel_err(X[0, c].cpu().numpy(), r.x) < 1e-3, (k, c)
 
 
