@@ -405,6 +405,28 @@ AIRGA_API airga_status airga_spai_update_complex(airga_ctx ctx, airga_prec old, 
                                                  double s_im, const airga_spai_opts* opts,
                                                  airga_prec* out);
 
+/* airga_spai_build_complex for `count` complex points at once: shifts (host,
+ * 2 count doubles, s_k = shifts[2k] + i shifts[2k+1]), out (host, count
+ * handles), each factor equal to its single build.  On an error no handle is
+ * returned (every out[k] NULL).  Asynchronous.  Errors: as
+ * airga_spai_build_complex, EINVAL (count < 0, null arrays). */
+AIRGA_API airga_status airga_spai_build_complex_many(airga_ctx ctx, int32_t count,
+                                                     const double* shifts,
+                                                     const airga_spai_opts* opts, airga_prec* out);
+
+/* airga_spai_update_complex for `count` (old factor, new point) pairs at
+ * once: olds (host, count handles, repeats allowed), shifts (host, 2 count
+ * doubles), out (host, count handles), each factor equal to its single
+ * update.  All updates are launched before one synchronisation reads every
+ * alpha and skip count.  On an error no handle is returned (every out[k]
+ * NULL).  Errors: as airga_spai_update_complex, EINVAL (count < 0, null
+ * arrays). */
+AIRGA_API airga_status airga_spai_update_complex_many(airga_ctx ctx, int32_t count,
+                                                      const airga_prec* olds,
+                                                      const double* shifts,
+                                                      const airga_spai_opts* opts,
+                                                      airga_prec* out);
+
 /* Export a complex factor: values (device, 2 nnz, interleaved, CSR order)
  * and, if objective is not NULL, the per-column least-squares residual norm
  * (device, n, real).  Asynchronous.  Errors: EINVAL (not a complex factor),

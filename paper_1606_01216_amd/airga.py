@@ -150,6 +150,14 @@ _SIGS = [
                                                 ctypes.POINTER(SpaiOpts), ctypes.POINTER(_P)]),
     ("airga_spai_update_complex", ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double,
                                                  ctypes.POINTER(SpaiOpts), ctypes.POINTER(_P)]),
+    ("airga_spai_build_complex_many", ctypes.c_int, [_P, ctypes.c_int32,
+                                                     ctypes.POINTER(ctypes.c_double),
+                                                     ctypes.POINTER(SpaiOpts),
+                                                     ctypes.POINTER(_P)]),
+    ("airga_spai_update_complex_many", ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(_P),
+                                                      ctypes.POINTER(ctypes.c_double),
+                                                      ctypes.POINTER(SpaiOpts),
+                                                      ctypes.POINTER(_P)]),
     ("airga_prec_export_complex", ctypes.c_int, [_P, _P, _P]),
     ("airga_cocg_solve", ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(_P), ctypes.c_int32, _P, ctypes.c_int64,
@@ -652,6 +660,36 @@ class Context:
                                               ctypes.byref(h)))
         self._leave()
         return Prec(self, h)
+
+    def spai_build_complex_many(self, shifts, *, equilibrate=True, symmetrize=True,
+                                general_only=False) -> list:
+        """spai_build_complex for several complex points in one call."""
+        o = self._spai_opts(None, equilibrate, symmetrize, general_only)
+        shifts = [complex(z) for z in shifts]
+        k = len(shifts)
+        c_s = (ctypes.c_double * max(2 * k, 1))(*[v for z in shifts for v in (z.real, z.imag)])
+        hs = (ctypes.c_void_p * max(k, 1))()
+        self._enter()
+        _check(lib().airga_spai_build_complex_many(self._h, k, c_s, ctypes.byref(o), hs))
+        self._leave()
+        return [Prec(self, ctypes.c_void_p(hs[i])) for i in range(k)]
+
+    def spai_update_complex_many(self, olds, shifts, *, tol=0.01, equilibrate=True,
+                                 general_only=False) -> list:
+        """spai_update_complex for several (old factor, new point) pairs in one
+        call (one synchronisation for all)."""
+        o = self._spai_opts(tol, equilibrate, False, general_only)
+        shifts = [complex(z) for z in shifts]
+        k = len(shifts)
+        if len(olds) != k:
+            raise ValueError("one old factor per point")
+        c_s = (ctypes.c_double * max(2 * k, 1))(*[v for z in shifts for v in (z.real, z.imag)])
+        c_o = (ctypes.c_void_p * max(k, 1))(*[p._h.value for p in olds])
+        hs = (ctypes.c_void_p * max(k, 1))()
+        self._enter()
+        _check(lib().airga_spai_update_complex_many(self._h, k, c_o, c_s, ctypes.byref(o), hs))
+        self._leave()
+        return [Prec(self, ctypes.c_void_p(hs[i])) for i in range(k)]
 
     def spai_update_complex(self, old: "Prec", s_new: complex, *, tol=0.01,
                             equilibrate=True, general_only=False) -> "Prec":

@@ -1343,6 +1343,115 @@ airga_status check_cshift(const Pencil& pen, double re, double im) {
   return AIRGA_OK;
 }
 
+// The complex update's launches (everything but the readback of alpha and
+// the skip count, which cupdate_finish takes); *out is the new factor, not
+// yet chained to old.
+airga_status cupdate_launch(airga_ctx ctx, airga_prec old, double s_re, double s_im,
+                            const airga_spai_opts* opts, airga_prec* out) {
+  *out = nullptr;
+  if (!old) return fail(AIRGA_EINVAL, "null preconditioner");
+  const Pencil& pen = ctx->pen;
+  if (old->ctx != ctx) return fail(AIRGA_EINVAL, "preconditioner belongs to another context");
+  if (old->generation != pen.generation)
+    return fail(AIRGA_ESTATE, "preconditioner was built for an earlier pencil");
+  if (!old->is_complex)
+    return fail(AIRGA_EINVAL, "the old factor is real: build it with airga_spai_build_complex");
+  AIRGA_TRY(check_cshift(pen, s_re, s_im));
+  airga_spai_opts o;
+  airga_spai_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.mr_iters != 0 || o.lfil != 0)
+    return fail(AIRGA_EUNSUPPORTED, "the minimal-residual mode is for real shifts only");
+  if (!(o.tol >= 0)) return fail(AIRGA_EINVAL, "update tolerance must be >= 0");
+  airga_prec p = new (std::nothrow) airga_prec_s();
+  if (!p) return fail(AIRGA_ENOMEM, "host allocation failed");
+  p->ctx = ctx;
+  p->generation = pen.generation;
+  p->shift = s_re;
+  p->shift_im = s_im;
+  p->is_complex = true;
+  p->is_update = true;
+  const size_t stored = (size_t)pen.nnz_stored;
+  const size_t npad = (size_t)pen.n_pad();
+  const unsigned nb = blocks_for(pen.n, 256);
+  airga_status st;
+  // scal: alpha (2 doubles) | skip count (int32 at 16) | skipped flags (from 64)
+  if ((st = pool_get(ctx, &p->v64, sizeof(cplx) * stored)) != AIRGA_OK ||
+      (st = pool_get(ctx, &p->v32, 2 * sizeof(float) * stored)) != AIRGA_OK ||
+      (st = pool_get(ctx, &p->objective, sizeof(double) * pen.n)) != AIRGA_OK ||
+      (st = pool_get(ctx, &p->scal, 64 + npad)) != AIRGA_OK ||
+      (st = ctx->ws_tmp.reserve(sizeof(cplx) * (stored + npad) + 3 * sizeof(double) * nb)) !=
+          AIRGA_OK) {
+    pool_put(ctx, &p->v64);
+    pool_put(ctx, &p->v32);
+    pool_put(ctx, &p->objective);
+    pool_put(ctx, &p->scal);
+    delete p;
+    return st;
+  }
+  ctx->live_precs++;
+  cplx a, b, ao, bo;
+  ccoeffs(pen, cx(s_re, s_im), &a, &b);
+  ccoeffs(pen, cx(old->shift, old->shift_im), &ao, &bo);
+  cplx* dinv = ctx->ws_tmp.as<cplx>();
+  cplx* hat = dinv + npad;
+  double* part = reinterpret_cast<double*>(hat + stored);
+  double* alpha_d = p->scal.as<double>();
+  int32_t* skip = reinterpret_cast<int32_t*>(p->scal.as<char>() + 16);
+  int8_t* skipf = reinterpret_cast<int8_t*>(p->scal.as<char>() + 64);
+  hipStream_t hs = ctx->stream;
+  const PencilDev pd = pen.dev();
+  // both matrices scaled by the new diagonal: Khat_x = S_new K(s_x) S_new
+  k_cdinv<<<blocks_for((int64_t)npad, 256), 256, 0, hs>>>(pd, a, b, o.equilibrate ? 1 : 0, dinv);
+  k_calpha_partial<<<nb, 256, 0, hs>>>(pd, a, b, ao, bo, dinv, part);
+  k_calpha_final<<<1, 256, 0, hs>>>(part, nb, alpha_d, skip);
+  // equilibrated updates on narrow bands of consecutive columns: normal
+  // equations first, rotations for the columns they flag
+  const bool gram = !o.general_only && o.equilibrate && pen.contiguous && pen.max_len <= 6 &&
+                    pen.bandwidth <= kCGramMaxBw;
+  int8_t* redo = nullptr;
+  if (gram) {
+    if ((st = ctx->ws_gather.reserve((size_t)pen.n)) != AIRGA_OK) {
+      airga_prec_release(p);
+      return st;
+    }
+    redo = ctx->ws_gather.as<int8_t>();
+    k_cspai_gram<6, true><<<blocks_for(pen.n, 64), 64, cspai_gram_lds(pen.bandwidth, 6, true), hs>>>(
+        pd, a, b, dinv, pen.bandwidth, hat, p->objective.as<double>(), redo, ao, bo, alpha_d,
+        o.tol, skipf, skip);
+  }
+  k_cspai_cols<6, true><<<blocks_for(pen.n, 64), 64, 0, hs>>>(
+      pd, a, b, dinv, hat, p->objective.as<double>(), redo, ao, bo, alpha_d, o.tol, skipf, skip);
+  k_cspai_finalize<<<blocks_for((int64_t)npad, 256), 256, 0, hs>>>(
+      pd, hat, dinv, 0, p->v64.as<cplx>(), p->v32.as<float>(), skipf, alpha_d, skip);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    airga_prec_release(p);
+    return fail(AIRGA_EHIP, "complex SPAI update: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return AIRGA_OK;
+}
+
+// alpha (2 doubles) and the skip count at the head of a complex update's
+// scal block
+struct CUpdScal {
+  double alpha[2];
+  int32_t skipped, pad;
+};
+
+// The update's scalars once read back; the factor joins old's chain.
+void cupdate_finish(airga_prec p, airga_prec old, const CUpdScal& h) {
+  p->alpha = h.alpha[0];
+  p->alpha_im = h.alpha[1];
+  p->alpha_known = true;
+  p->skipped = h.skipped;
+  p->scalar_only = h.skipped == p->ctx->pen.n;
+  p->scalar_known = true;
+  p->parent = old;
+  old->refs++;
+}
+
 }  // namespace
 }  // namespace airga
 
@@ -1453,103 +1562,80 @@ airga_status airga_spai_update_complex(airga_ctx ctx, airga_prec old, double s_r
   DeviceGuard g(ctx->device);
   if (!out) return fail(AIRGA_EINVAL, "null output handle");
   *out = nullptr;
-  if (!old) return fail(AIRGA_EINVAL, "null preconditioner");
-  const Pencil& pen = ctx->pen;
-  if (old->ctx != ctx) return fail(AIRGA_EINVAL, "preconditioner belongs to another context");
-  if (old->generation != pen.generation)
-    return fail(AIRGA_ESTATE, "preconditioner was built for an earlier pencil");
-  if (!old->is_complex)
-    return fail(AIRGA_EINVAL, "the old factor is real: build it with airga_spai_build_complex");
-  AIRGA_TRY(check_cshift(pen, s_re, s_im));
-  airga_spai_opts o;
-  airga_spai_opts_default(&o);
-  if (opts) o = *opts;
-  if (o.mr_iters != 0 || o.lfil != 0)
-    return fail(AIRGA_EUNSUPPORTED, "the minimal-residual mode is for real shifts only");
-  if (!(o.tol >= 0)) return fail(AIRGA_EINVAL, "update tolerance must be >= 0");
-  airga_prec p = new (std::nothrow) airga_prec_s();
-  if (!p) return fail(AIRGA_ENOMEM, "host allocation failed");
-  p->ctx = ctx;
-  p->generation = pen.generation;
-  p->shift = s_re;
-  p->shift_im = s_im;
-  p->is_complex = true;
-  p->is_update = true;
-  const size_t stored = (size_t)pen.nnz_stored;
-  const size_t npad = (size_t)pen.n_pad();
-  const unsigned nb = blocks_for(pen.n, 256);
-  airga_status st;
-  // scal: alpha (2 doubles) | skip count (int32 at 16) | skipped flags (from 64)
-  if ((st = pool_get(ctx, &p->v64, sizeof(cplx) * stored)) != AIRGA_OK ||
-      (st = pool_get(ctx, &p->v32, 2 * sizeof(float) * stored)) != AIRGA_OK ||
-      (st = pool_get(ctx, &p->objective, sizeof(double) * pen.n)) != AIRGA_OK ||
-      (st = pool_get(ctx, &p->scal, 64 + npad)) != AIRGA_OK ||
-      (st = ctx->ws_tmp.reserve(sizeof(cplx) * (stored + npad) + 3 * sizeof(double) * nb)) !=
-          AIRGA_OK) {
-    pool_put(ctx, &p->v64);
-    pool_put(ctx, &p->v32);
-    pool_put(ctx, &p->objective);
-    pool_put(ctx, &p->scal);
-    delete p;
-    return st;
-  }
-  ctx->live_precs++;
-  cplx a, b, ao, bo;
-  ccoeffs(pen, cx(s_re, s_im), &a, &b);
-  ccoeffs(pen, cx(old->shift, old->shift_im), &ao, &bo);
-  cplx* dinv = ctx->ws_tmp.as<cplx>();
-  cplx* hat = dinv + npad;
-  double* part = reinterpret_cast<double*>(hat + stored);
-  double* alpha_d = p->scal.as<double>();
-  int32_t* skip = reinterpret_cast<int32_t*>(p->scal.as<char>() + 16);
-  int8_t* skipf = reinterpret_cast<int8_t*>(p->scal.as<char>() + 64);
-  hipStream_t hs = ctx->stream;
-  const PencilDev pd = pen.dev();
-  // both matrices scaled by the new diagonal: Khat_x = S_new K(s_x) S_new
-  k_cdinv<<<blocks_for((int64_t)npad, 256), 256, 0, hs>>>(pd, a, b, o.equilibrate ? 1 : 0, dinv);
-  k_calpha_partial<<<nb, 256, 0, hs>>>(pd, a, b, ao, bo, dinv, part);
-  k_calpha_final<<<1, 256, 0, hs>>>(part, nb, alpha_d, skip);
-  // equilibrated updates on narrow bands of consecutive columns: normal
-  // equations first, rotations for the columns they flag
-  const bool gram = !o.general_only && o.equilibrate && pen.contiguous && pen.max_len <= 6 &&
-                    pen.bandwidth <= kCGramMaxBw;
-  int8_t* redo = nullptr;
-  if (gram) {
-    if ((st = ctx->ws_gather.reserve((size_t)pen.n)) != AIRGA_OK) {
-      airga_prec_release(p);
-      return st;
-    }
-    redo = ctx->ws_gather.as<int8_t>();
-    k_cspai_gram<6, true><<<blocks_for(pen.n, 64), 64, cspai_gram_lds(pen.bandwidth, 6, true), hs>>>(
-        pd, a, b, dinv, pen.bandwidth, hat, p->objective.as<double>(), redo, ao, bo, alpha_d,
-        o.tol, skipf, skip);
-  }
-  k_cspai_cols<6, true><<<blocks_for(pen.n, 64), 64, 0, hs>>>(
-      pd, a, b, dinv, hat, p->objective.as<double>(), redo, ao, bo, alpha_d, o.tol, skipf, skip);
-  k_cspai_finalize<<<blocks_for((int64_t)npad, 256), 256, 0, hs>>>(
-      pd, hat, dinv, 0, p->v64.as<cplx>(), p->v32.as<float>(), skipf, alpha_d, skip);
-  hipError_t e = hipGetLastError();
+  airga_prec p = nullptr;
+  AIRGA_TRY(cupdate_launch(ctx, old, s_re, s_im, opts, &p));
   // alpha and the skip count, read once (the solves need to know whether
   // the factor is the scalar alpha I)
-  struct {
-    double alpha[2];
-    int32_t skipped, pad;
-  } h{};
-  if (e == hipSuccess) e = hipMemcpyAsync(&h, alpha_d, sizeof h, hipMemcpyDeviceToHost, hs);
-  if (e == hipSuccess) e = hipStreamSynchronize(hs);
+  CUpdScal h{};
+  hipError_t e = hipMemcpyAsync(&h, p->scal.ptr, sizeof h, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     airga_prec_release(p);
     return fail(AIRGA_EHIP, "complex SPAI update: %s", hipGetErrorString(e));
   }
-  p->alpha = h.alpha[0];
-  p->alpha_im = h.alpha[1];
-  p->alpha_known = true;
-  p->skipped = h.skipped;
-  p->scalar_only = h.skipped == pen.n;
-  p->scalar_known = true;
-  p->parent = old;
-  old->refs++;
+  cupdate_finish(p, old, h);
   *out = p;
+  return AIRGA_OK;
+}
+
+airga_status airga_spai_update_complex_many(airga_ctx ctx, int32_t count, const airga_prec* olds,
+                                            const double* shifts, const airga_spai_opts* opts,
+                                            airga_prec* out) {
+  AIRGA_TRY(check_pencil(ctx));
+  DeviceGuard g(ctx->device);
+  if (count < 0) return fail(AIRGA_EINVAL, "negative count");
+  if (count > 0 && (!olds || !shifts || !out)) return fail(AIRGA_EINVAL, "null array");
+  for (int i = 0; i < count; ++i) out[i] = nullptr;
+  std::vector<airga_prec> ps(count, nullptr);
+  auto drop = [&]() {
+    for (airga_prec q : ps) airga_prec_release(q);
+  };
+  for (int i = 0; i < count; ++i) {
+    const airga_status st = cupdate_launch(ctx, olds[i], shifts[2 * i], shifts[2 * i + 1], opts, &ps[i]);
+    if (st != AIRGA_OK) {
+      drop();
+      return st;
+    }
+  }
+  if (count == 0) return AIRGA_OK;
+  // one readback of every update's scalars
+  const airga_status pst = ensure_pinned(ctx, sizeof(CUpdScal) * (size_t)count);
+  if (pst != AIRGA_OK) {
+    drop();
+    return pst;
+  }
+  CUpdScal* h = static_cast<CUpdScal*>(ctx->host_pinned);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < count && e == hipSuccess; ++i)
+    e = hipMemcpyAsync(h + i, ps[i]->scal.ptr, sizeof(CUpdScal), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    drop();
+    return fail(AIRGA_EHIP, "complex SPAI updates: %s", hipGetErrorString(e));
+  }
+  for (int i = 0; i < count; ++i) {
+    cupdate_finish(ps[i], olds[i], h[i]);
+    out[i] = ps[i];
+  }
+  return AIRGA_OK;
+}
+
+airga_status airga_spai_build_complex_many(airga_ctx ctx, int32_t count, const double* shifts,
+                                           const airga_spai_opts* opts, airga_prec* out) {
+  AIRGA_TRY(check_pencil(ctx));
+  if (count < 0) return fail(AIRGA_EINVAL, "negative count");
+  if (count > 0 && (!shifts || !out)) return fail(AIRGA_EINVAL, "null array");
+  for (int i = 0; i < count; ++i) out[i] = nullptr;
+  for (int i = 0; i < count; ++i) {
+    const airga_status st = airga_spai_build_complex(ctx, shifts[2 * i], shifts[2 * i + 1], opts, out + i);
+    if (st != AIRGA_OK) {
+      for (int k = 0; k < i; ++k) {
+        airga_prec_release(out[k]);
+        out[k] = nullptr;
+      }
+      return st;
+    }
+  }
   return AIRGA_OK;
 }
 

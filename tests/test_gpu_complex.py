@@ -124,6 +124,45 @@ def test_complex_update_matches_oracle(ctx, which, s_old, s_new):
     assert np.all(np.abs(og - obj) <= 1e-12 * np.maximum(1.0, obj))
 
 
+def test_complex_builds_and_updates_many_equal_single_calls(ctx):
+    """The many-point calls give exactly the single calls' factors (values,
+    objectives, alpha, skip counts), including an update that skips every
+    column (the scalar alpha I) and a repeated old factor; a bad entry
+    fails the whole call."""
+    pen = sur_beam(400)
+    set_pencil(ctx, pen)
+    pts = [3.0 + 2.0j, 30.0 * np.exp(1j * np.pi / 6), 100.0 + 50.0j]
+    many = ctx.spai_build_complex_many(pts)
+    one = [ctx.spai_build_complex(z) for z in pts]
+    for m_, o_ in zip(many, one):
+        vm, om = (t.cpu().numpy() for t in m_.export_complex())
+        vo, oo = (t.cpu().numpy() for t in o_.export_complex())
+        assert np.array_equal(vm, vo) and np.array_equal(om, oo)
+    new = [pts[0] * 1.2, pts[1] * (1 + 1e-9), pts[2] * 0.9, pts[0] * 0.8]
+    olds = [one[0], one[1], one[2], one[0]]
+    um = ctx.spai_update_complex_many(olds, new, tol=0.05)
+    uo = [ctx.spai_update_complex(p, z, tol=0.05) for p, z in zip(olds, new)]
+    assert um[1].info().scalar_only == 1
+    for m_, o_ in zip(um, uo):
+        im, io = m_.info(), o_.info()
+        assert (im.alpha, im.alpha_im, im.skipped_cols, im.chain_len, im.scalar_only) == \
+            (io.alpha, io.alpha_im, io.skipped_cols, io.chain_len, io.scalar_only)
+        vm, om = (t.cpu().numpy() for t in m_.export_complex())
+        vo, oo = (t.cpu().numpy() for t in o_.export_complex())
+        assert np.array_equal(vm, vo) and np.array_equal(om, oo)
+    F = to_dev(np.random.default_rng(3).standard_normal((1, pen.n)), torch.float64)
+    Xm, _ = ctx.cocg_solve(new, um, F, tol=1e-10)
+    Xo, _ = ctx.cocg_solve(new, uo, F, tol=1e-10)
+    assert torch.equal(Xm, Xo)
+    assert ctx.spai_build_complex_many([]) == [] and ctx.spai_update_complex_many([], []) == []
+    with pytest.raises(airga.AirgaError) as e:
+        ctx.spai_update_complex_many([one[0], ctx.spai_build(5.0)], [pts[0], pts[1]])
+    assert e.value.status == airga.EINVAL
+    with pytest.raises(airga.AirgaError) as e:
+        ctx.spai_build_complex_many([1.0 + 1.0j, complex(float("nan"), 0.0)])
+    assert e.value.status == airga.EINVAL
+
+
 def test_cocg_with_a_complex_update_chain(ctx):
     """P_1 built at s_1, Q_2 and Q_3 its updates along s_2, s_3 (each with
     solved columns): COCG at s_3 with the chain Q_3 Q_2 P_1 follows the
