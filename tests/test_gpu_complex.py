@@ -376,6 +376,15 @@ def test_mixed_cocg_edges_and_errors(ctx):
     _, st = ctx.cocg_solve([s], [p], F, tol=1e-30, mode=airga.MODE_MIXED, max_iter=5,
                            inner_tol=1e-12, inner_max=4, poll_every=2)
     assert st[1]["status"] == airga.SYS_MAXIT and st[1]["sweeps"] == 2 and st[1]["iters"] == 8
+    # a non-finite load: that system NONFINITE at once (X = 0), the other
+    # one unaffected
+    fn = f.copy()
+    fn[0, 5] = np.nan
+    X, st = ctx.cocg_solve([s], [p], to_dev(fn, torch.float64), mode=airga.MODE_MIXED)
+    assert st[0]["status"] == airga.SYS_NONFINITE and st[0]["sweeps"] == 0
+    assert torch.count_nonzero(X[0, 0]).item() == 0
+    assert st[1]["status"] == airga.SYS_CONVERGED
+    assert rel_err(X[0, 1].cpu().numpy(), ref) < 1e-8
     for bad in (dict(inner_tol=0.0), dict(inner_tol=1.0), dict(max_sweeps=0), dict(inner_max=-1)):
         with pytest.raises(airga.AirgaError) as e:
             ctx.cocg_solve([s], [p], F, mode=airga.MODE_MIXED, **bad)
