@@ -426,6 +426,92 @@ __host__ __device__ inline size_t cspai_gram_lds(int bw, int mj, bool update) {
          wr * (2 * (size_t)bw + 1) * sizeof(cplx);
 }
 
+// Column j's normal equations from the band of H (the solve of k_cspai_gram):
+// Cholesky of G = H(J, J) (real positive diagonal), the two triangular
+// solves and the residual from the quadratic form.  FULL: every lane's
+// column has MJ entries (no per-entry tests).  Returns false (p and res2
+// then not final) when a pivot falls below 1e-8 of its diagonal.
+template <int MJ, bool UPDATE, bool FULL>
+__device__ __forceinline__ bool cgram_column(const cplx* hb, int BW2, int64_t w0, int J0, int nj,
+                                             const cplx* vn, const cplx* vo, int WR, int jr,
+                                             const int32_t* f0, const int32_t* ln, double t2,
+                                             cplx (&p)[MJ], double& res2) {
+  cplx Uf[MJ * (MJ + 1) / 2], y[MJ], g[MJ];
+  double iu[MJ];
+  bool good = FULL || nj > 0;
+#pragma unroll
+  for (int k = 0; k < MJ; ++k) {
+    y[k] = g[k] = p[k] = cx(0.0);
+    iu[k] = 0.0;
+    if (FULL || k < nj) {
+      const cplx* hk = hb + (J0 + k - (int)w0) * BW2;  // H(J_k, J_k + d)
+      if constexpr (UPDATE) {
+        // sum over k' of conj(Khat_new(J_k, k')) Khat_old(j, k')
+        const int ra = J0 + k - (int)w0;
+        const int fa = f0[ra], la = ln[ra];
+        const int lo = fa > J0 ? fa : J0;
+        const int hi = (fa + la < J0 + nj) ? fa + la : J0 + nj;
+        cplx acc = cx(0.0);
+        for (int c = lo; c < hi; ++c) cfma(acc, conj(vn[(c - fa) * WR + ra]), vo[(c - J0) * WR + jr]);
+        g[k] = acc;
+      } else {
+        g[k] = conj(vn[k * WR + jr]);                   // conj(Khat(j, J_k))
+      }
+      double dkk = hk[0].re;
+#pragma unroll
+      for (int m = 0; m < MJ; ++m)
+        if (m < k) dkk -= abs2(Uf[ctri<MJ>(m, k)]);
+      good = good && dkk > 1e-8 * hk[0].re;
+      const double inv = dkk > 0.0 ? 1.0 / sqrt(dkk) : 0.0;
+      iu[k] = inv;
+      Uf[ctri<MJ>(k, k)] = cx(dkk * inv);
+#pragma unroll
+      for (int i = 0; i < MJ; ++i) {
+        if (i > k && (FULL || i < nj)) {
+          cplx gik = hk[i - k];  // G(k, i) = H(J_k, J_i), i > k
+#pragma unroll
+          for (int m = 0; m < MJ; ++m)
+            if (m < k) gik = gik - conj(Uf[ctri<MJ>(m, k)]) * Uf[ctri<MJ>(m, i)];
+          Uf[ctri<MJ>(k, i)] = inv * gik;
+        }
+      }
+      cplx yk = g[k];
+#pragma unroll
+      for (int m = 0; m < MJ; ++m)
+        if (m < k) yk = yk - conj(Uf[ctri<MJ>(m, k)]) * y[m];
+      y[k] = inv * yk;
+    }
+  }
+  if (!good) return false;
+#pragma unroll
+  for (int k = MJ - 1; k >= 0; --k) {
+    if (FULL || k < nj) {
+      cplx acc = y[k];
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i > k && (FULL || i < nj)) acc = acc - Uf[ctri<MJ>(k, i)] * p[i];
+      p[k] = iu[k] * acc;
+    }
+  }
+  // ||e_j - B p||^2 = 1 - 2 Re(g^H p) + p^H G p, G Hermitian from the band
+  double ghp = 0.0, pgp = 0.0;
+#pragma unroll
+  for (int k = 0; k < MJ; ++k) {
+    if (FULL || k < nj) {
+      const cplx* hk = hb + (J0 + k - (int)w0) * BW2;
+      ghp += (conj(g[k]) * p[k]).re;
+      double row = hk[0].re * abs2(p[k]);
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i > k && (FULL || i < nj)) row += 2.0 * (conj(p[k]) * (hk[i - k] * p[i])).re;
+      pgp += row;
+    }
+  }
+  res2 = fma(-2.0, ghp, t2) + pgp;
+  res2 = res2 > 0.0 ? res2 : 0.0;
+  return true;
+}
+
 template <int MJ, bool UPDATE>
 __global__ void __launch_bounds__(64) k_cspai_gram(PencilDev pd, cplx a, cplx b,
                                                    const cplx* __restrict__ dinv, int bw,
@@ -469,21 +555,48 @@ __global__ void __launch_bounds__(64) k_cspai_gram(PencilDev pd, cplx a, cplx b,
     }
   }
   __syncthreads();
-  // upper band of H, one (row, offset) entry per lane and pass
-  for (int e = lane; e < WR * BW2; e += 64) {
-    const int q = e / BW2, d = e - q * BW2;
+  // upper band of H: H(i, i + d) = sum over k of conj(Khat(i, k)) Khat(i +
+  // d, k) (entries past a row's length are zero, so every product of the
+  // overlap is taken).  Rows 0..63 one per lane, the conjugated values of
+  // row i kept in registers for its 2 bw + 1 offsets; the last 2 bw rows one
+  // (row, offset) pair per lane.
+  {
+    const int q = lane;
+    cplx vi[MJ];
+#pragma unroll
+    for (int u = 0; u < MJ; ++u) vi[u] = conj(vn[u * WR + q]);
+    const int i0 = f0[q];
+    for (int d = 0; d < BW2; ++d) {
+      const int cr = q + d;
+      cplx acc = cx(0.0);
+      if (cr < WR) {
+        const int dc = f0[cr] - i0;
+#pragma unroll
+        for (int u = 0; u < MJ; ++u) {
+          const int qq = u - dc;
+          const bool ok = qq >= 0 && qq < MJ;
+          const cplx x = vn[(ok ? qq : 0) * WR + cr];
+          cfma(acc, vi[u], ok ? x : cx(0.0));
+        }
+      }
+      hb[q * BW2 + d] = acc;
+    }
+  }
+  for (int e = lane; e < (WR - 64) * BW2; e += 64) {
+    const int q = 64 + e / BW2, d = e - (q - 64) * BW2;
     const int cr = q + d;
     cplx acc = cx(0.0);
     if (cr < WR) {
-      const int li = ln[q], lc = ln[cr];
-      if (li > 0 && lc > 0) {
-        const int i0 = f0[q], cf = f0[cr];
-        const int lo = i0 > cf ? i0 : cf;
-        const int hi = (i0 + li < cf + lc) ? i0 + li : cf + lc;
-        for (int k = lo; k < hi; ++k) cfma(acc, conj(vn[(k - i0) * WR + q]), vn[(k - cf) * WR + cr]);
+      const int dc = f0[cr] - f0[q];
+#pragma unroll
+      for (int u = 0; u < MJ; ++u) {
+        const int qq = u - dc;
+        const bool ok = qq >= 0 && qq < MJ;
+        const cplx x = vn[(ok ? qq : 0) * WR + cr];
+        cfma(acc, conj(vn[u * WR + q]), ok ? x : cx(0.0));
       }
     }
-    hb[e] = acc;
+    hb[q * BW2 + d] = acc;
   }
   __syncthreads();
   const int64_t j = o0 + lane;
@@ -516,80 +629,13 @@ __global__ void __launch_bounds__(64) k_cspai_gram(PencilDev pd, cplx a, cplx b,
     }
     t2 = n_old;
   }
-  cplx Uf[MJ * (MJ + 1) / 2], y[MJ], g[MJ], p[MJ];
-  double iu[MJ];
-  bool good = nj > 0;
-#pragma unroll
-  for (int k = 0; k < MJ; ++k) {
-    y[k] = g[k] = p[k] = cx(0.0);
-    iu[k] = 0.0;
-    if (k < nj) {
-      const cplx* hk = hb + (J0 + k - (int)w0) * BW2;  // H(J_k, J_k + d)
-      if constexpr (UPDATE) {
-        // sum over k' of conj(Khat_new(J_k, k')) Khat_old(j, k')
-        const int ra = J0 + k - (int)w0;
-        const int fa = f0[ra], la = ln[ra];
-        const int lo = fa > J0 ? fa : J0;
-        const int hi = (fa + la < J0 + nj) ? fa + la : J0 + nj;
-        cplx acc = cx(0.0);
-        for (int c = lo; c < hi; ++c) cfma(acc, conj(vn[(c - fa) * WR + ra]), vo[(c - J0) * WR + jr]);
-        g[k] = acc;
-      } else {
-        g[k] = conj(vn[k * WR + jr]);                   // conj(Khat(j, J_k))
-      }
-      double dkk = hk[0].re;
-#pragma unroll
-      for (int m = 0; m < MJ; ++m)
-        if (m < k) dkk -= abs2(Uf[ctri<MJ>(m, k)]);
-      good = good && dkk > 1e-8 * hk[0].re;
-      const double inv = dkk > 0.0 ? 1.0 / sqrt(dkk) : 0.0;
-      iu[k] = inv;
-      Uf[ctri<MJ>(k, k)] = cx(dkk * inv);
-#pragma unroll
-      for (int i = 0; i < MJ; ++i) {
-        if (i > k && i < nj) {
-          cplx gik = hk[i - k];  // G(k, i) = H(J_k, J_i), i > k
-#pragma unroll
-          for (int m = 0; m < MJ; ++m)
-            if (m < k) gik = gik - conj(Uf[ctri<MJ>(m, k)]) * Uf[ctri<MJ>(m, i)];
-          Uf[ctri<MJ>(k, i)] = inv * gik;
-        }
-      }
-      cplx yk = g[k];
-#pragma unroll
-      for (int m = 0; m < MJ; ++m)
-        if (m < k) yk = yk - conj(Uf[ctri<MJ>(m, k)]) * y[m];
-      y[k] = inv * yk;
-    }
-  }
+  cplx p[MJ];
+  double res2 = 0.0;
+  const bool good = __all(nj == MJ)
+                        ? cgram_column<MJ, UPDATE, true>(hb, BW2, w0, J0, nj, vn, vo, WR, jr, f0, ln, t2, p, res2)
+                        : cgram_column<MJ, UPDATE, false>(hb, BW2, w0, J0, nj, vn, vo, WR, jr, f0, ln, t2, p, res2);
   redo[j] = good ? 0 : 1;
   if (!good) return;
-#pragma unroll
-  for (int k = MJ - 1; k >= 0; --k) {
-    if (k < nj) {
-      cplx acc = y[k];
-#pragma unroll
-      for (int i = 0; i < MJ; ++i)
-        if (i > k && i < nj) acc = acc - Uf[ctri<MJ>(k, i)] * p[i];
-      p[k] = iu[k] * acc;
-    }
-  }
-  // ||e_j - B p||^2 = 1 - 2 Re(g^H p) + p^H G p, G Hermitian from the band
-  double ghp = 0.0, pgp = 0.0;
-#pragma unroll
-  for (int k = 0; k < MJ; ++k) {
-    if (k < nj) {
-      const cplx* hk = hb + (J0 + k - (int)w0) * BW2;
-      ghp += (conj(g[k]) * p[k]).re;
-      double row = hk[0].re * abs2(p[k]);
-#pragma unroll
-      for (int i = 0; i < MJ; ++i)
-        if (i > k && i < nj) row += 2.0 * (conj(p[k]) * (hk[i - k] * p[i])).re;
-      pgp += row;
-    }
-  }
-  double res2 = fma(-2.0, ghp, t2) + pgp;
-  res2 = res2 > 0.0 ? res2 : 0.0;
   const int32_t bj = row_base(pd, j);
 #pragma unroll
   for (int t = 0; t < MJ; ++t)
