@@ -80,11 +80,9 @@ struct cf {
   float re, im;
 };
 __device__ __forceinline__ cf operator+(cf a, cf b) { return cf{a.re + b.re, a.im + b.im}; }
-__device__ __forceinline__ cf operator-(cf a, cf b) { return cf{a.re - b.re, a.im - b.im}; }
 __device__ __forceinline__ cf operator*(cf a, cf b) {
   return cf{fmaf(a.re, b.re, -a.im * b.im), fmaf(a.re, b.im, a.im * b.re)};
 }
-__device__ __forceinline__ cf conj(cf a) { return cf{a.re, -a.im}; }
 __device__ __forceinline__ float abs2(cf a) { return fmaf(a.re, a.re, a.im * a.im); }
 __device__ __forceinline__ void cfma(cf& a, cf x, cf y) {
   a.re = fmaf(x.re, y.re, fmaf(-x.im, y.im, a.re));
