@@ -111,8 +111,8 @@ __global__ void k_alpha_partial(PencilDev pd, double a, double b, double a_old, 
       den = fma(an, an, den);
     }
   }
-  num = wave_sum(num);
-  den = wave_sum(den);
+  num = wave_total(num);
+  den = wave_total(den);
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     red[0][w] = num;
@@ -888,14 +888,54 @@ __global__ void k_dinv_many(PencilDev pd, UpdMany U, int equilibrate, int64_t n_
     dinv[(int64_t)s * n_pad + r] = eq ? 1.0 / sqrt(fma(U.a[s], m, U.b[s] * k)) : 1.0;
 }
 
+// diag(K(s))_row^{-1/2} for K(s) = a M + b K, as k_dinv forms it (1 without
+// equilibration or past the last row).
+__device__ __forceinline__ double row_dinv(const PencilDev& pd, double a, double b, int eq,
+                                           int64_t row) {
+  if (!eq || row >= pd.n) return 1.0;
+  const int32_t q = pd.diag_pos[row];
+  return 1.0 / sqrt(fma(a, pd.m64[q], b * pd.k64[q]));
+}
+
+// The diagonal scalings of rows [d0, d1) for every shift of the batch, in
+// LDS: dl[s * W + (row - d0)] = diag(K(s))_row^{-1/2}, formed as k_dinv_many
+// forms them (1 without equilibration); each row's diagonal is read once.
+// Every thread of the block calls it (it ends with a barrier).
+__device__ __forceinline__ void stage_dinv_many(const PencilDev& pd, const UpdMany& U, int eq,
+                                                int64_t d0, int64_t d1, int W, double* dl) {
+  for (int64_t row = d0 + threadIdx.x; row < d1; row += blockDim.x) {
+    double m = 0, k = 0;
+    if (eq) {
+      const int32_t q = pd.diag_pos[row];
+      m = pd.m64[q];
+      k = pd.k64[q];
+    }
+    for (int s = 0; s < U.count; ++s)
+      dl[s * W + (int)(row - d0)] = eq ? 1.0 / sqrt(fma(U.a[s], m, U.b[s] * k)) : 1.0;
+  }
+  __syncthreads();
+}
+
+// LDS of stage_dinv_many for a 256-row block of a pencil of bandwidth bw.
+inline size_t dinv_many_lds(int count, int bw) {
+  return sizeof(double) * (size_t)count * (256 + 2 * (size_t)bw);
+}
+
 // k_alpha_partial for every shift, each row of the pencil read once:
-// part[(s * nb + block) * 2 + {0, 1}].
-__global__ void k_alpha_partial_many(PencilDev pd, UpdMany U, const double* __restrict__ dinv,
-                                     int64_t n_pad, double* __restrict__ part) {
+// part[(s * nb + block) * 2 + {0, 1}].  The block's rows and the bw rows on
+// either side (the columns of a banded pattern) have their scalings staged
+// for every shift first.
+__global__ void k_alpha_partial_many(PencilDev pd, UpdMany U, int bw, int eq,
+                                     double* __restrict__ part) {
+  extern __shared__ double dl[];
   __shared__ double red[kManyMax][2][4];
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int w = threadIdx.x >> 6;
   const int64_t nb = gridDim.x;
+  const int64_t j0 = blockIdx.x * (int64_t)blockDim.x;
+  const int64_t d0 = j0 - bw > 0 ? j0 - bw : 0;
+  const int64_t d1 = j0 + 256 + bw < pd.n ? j0 + 256 + bw : pd.n;
+  const int W = 256 + 2 * bw;
   int len = 0;
   int32_t c[kSpaiMaxJ];
   double m[kSpaiMaxJ], kk[kSpaiMaxJ];
@@ -910,25 +950,16 @@ __global__ void k_alpha_partial_many(PencilDev pd, UpdMany U, const double* __re
       kk[k] = pd.k64[idx];
     }
   }
-  // the diagonal scalings of the row and its columns for shift q; the next
-  // shift's are loaded while the current one is used
-  auto scal = [&](int q, double& sr, double (&dc)[kSpaiMaxJ]) {
-    const double* __restrict__ dv = dinv + (int64_t)q * n_pad;
-    sr = dv[r];
-#pragma unroll
-    for (int k = 0; k < kSpaiMaxJ; ++k) dc[k] = k < len ? dv[c[k]] : 0.0;
-  };
-  double sr0 = 0.0, dc0[kSpaiMaxJ] = {};
-  if (r < pd.n && U.count > 0) scal(0, sr0, dc0);
+  stage_dinv_many(pd, U, eq, d0, d1, W, dl);
   for (int s = 0; s < U.count; ++s) {
-    double sr1 = 0.0, dc1[kSpaiMaxJ] = {};
-    if (r < pd.n && s + 1 < U.count) scal(s + 1, sr1, dc1);
     double num = 0, den = 0;
     if (r < pd.n) {
+      const double* __restrict__ ds = dl + s * W;
+      const double sr = ds[r - d0];
 #pragma unroll
       for (int k = 0; k < kSpaiMaxJ; ++k) {
         if (k < len) {
-          const double sc = sr0 * dc0[k];
+          const double sc = sr * ds[c[k] - d0];
           const double an = fma(U.a[s], m[k], U.b[s] * kk[k]) * sc;
           const double ao = fma(U.ao[s], m[k], U.bo[s] * kk[k]) * sc;
           num = fma(ao, an, num);
@@ -936,11 +967,8 @@ __global__ void k_alpha_partial_many(PencilDev pd, UpdMany U, const double* __re
         }
       }
     }
-    sr0 = sr1;
-#pragma unroll
-    for (int k = 0; k < kSpaiMaxJ; ++k) dc0[k] = dc1[k];
-    num = wave_sum(num);
-    den = wave_sum(den);
+    num = wave_total(num);
+    den = wave_total(den);
     if ((threadIdx.x & 63) == 0) {
       red[s][0][w] = num;
       red[s][1][w] = den;
@@ -1452,15 +1480,19 @@ __global__ void __launch_bounds__(256) k_spai_build_many(PencilDev pd, UpdMany U
 // columns) the skipped count and whether any column needs its solve, so the
 // staged kernel only visits blocks and shifts with work left.
 template <int MJ>
-__global__ void __launch_bounds__(256) k_update_test_many(PencilDev pd, UpdMany U,
-                                                         const double* __restrict__ dinv,
-                                                         int64_t n_pad, double tol,
+__global__ void __launch_bounds__(256) k_update_test_many(PencilDev pd, UpdMany U, int bw, int eq,
+                                                         double tol,
                                                          int32_t* __restrict__ skip_part,
                                                          int32_t* __restrict__ need) {
+  extern __shared__ double dl[];
   __shared__ int32_t cnt[kManyMax][4], req[kManyMax][4];
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * 256;
+  const int64_t j = j0 + threadIdx.x;
   const int wv = threadIdx.x >> 6;
   const bool in = j < pd.n;
+  const int64_t d0 = j0 - bw > 0 ? j0 - bw : 0;
+  const int64_t d1 = j0 + 256 + bw < pd.n ? j0 + 256 + bw : pd.n;
+  const int W = 256 + 2 * bw;
   int len = 0;
   int32_t col[MJ];
   double mm[MJ], kq[MJ];
@@ -1469,7 +1501,7 @@ __global__ void __launch_bounds__(256) k_update_test_many(PencilDev pd, UpdMany 
     len = pd.row_len[j];
 #pragma unroll
     for (int u = 0; u < MJ; ++u) {
-      col[u] = 0;
+      col[u] = (int32_t)j;
       mm[u] = kq[u] = 0.0;
       if (u < len) {
         const int32_t idx = base + u * kSlice;
@@ -1479,28 +1511,18 @@ __global__ void __launch_bounds__(256) k_update_test_many(PencilDev pd, UpdMany 
       }
     }
   }
-  // alpha and the diagonal scalings of the row and its columns for shift q;
-  // the next shift's are loaded while the current one is tested
-  auto scal = [&](int q, double& al, double& sr, double (&dc)[MJ]) {
-    const double* __restrict__ dv = dinv + (int64_t)q * n_pad;
-    al = *U.alpha[q];
-    sr = dv[j];
-#pragma unroll
-    for (int u = 0; u < MJ; ++u) dc[u] = u < len ? dv[col[u]] : 0.0;
-  };
-  double al0 = 0.0, sr0 = 0.0, dc0[MJ] = {};
-  if (in && U.count > 0) scal(0, al0, sr0, dc0);
+  stage_dinv_many(pd, U, eq, d0, d1, W, dl);
   for (int s = 0; s < U.count; ++s) {
-    double al1 = 0.0, sr1 = 0.0, dc1[MJ] = {};
-    if (in && s + 1 < U.count) scal(s + 1, al1, sr1, dc1);
     bool skipped = false, solve = false;
     if (in) {
-      const double al = al0, sr = sr0;
+      const double al = *U.alpha[s];
+      const double* __restrict__ ds = dl + s * W;
+      const double sr = ds[j - d0];
       double n_old = 0, n_res = 0;
 #pragma unroll
       for (int u = 0; u < MJ; ++u) {
         if (u < len) {
-          const double dc = dc0[u];
+          const double dc = ds[col[u] - d0];
           const double v_n = fma(U.a[s], mm[u], U.b[s] * kq[u]) * sr * dc;
           const double v_o = fma(U.ao[s], mm[u], U.bo[s] * kq[u]) * sr * dc;
           const double d = fma(-al, v_n, v_o);
@@ -1516,10 +1538,6 @@ __global__ void __launch_bounds__(256) k_update_test_many(PencilDev pd, UpdMany 
       }
       U.skipf[s][j] = skipped ? 1 : 0;
     }
-    al0 = al1;
-    sr0 = sr1;
-#pragma unroll
-    for (int u = 0; u < MJ; ++u) dc0[u] = dc1[u];
     const unsigned long long bs = __ballot(skipped), bn = __ballot(solve);
     if ((threadIdx.x & 63) == 0) {
       cnt[s][wv] = (int32_t)__popcll(bs);
@@ -1549,9 +1567,8 @@ __global__ void __launch_bounds__(256) k_update_test_many(PencilDev pd, UpdMany 
 // any shift returns before staging, and a shift with nothing to solve is
 // passed over.
 template <int MJ, int RANGE>
-__global__ void __launch_bounds__(256) k_spai_update_many(PencilDev pd, UpdMany U,
-                                                          const double* __restrict__ dinv,
-                                                          int64_t n_pad, int64_t stored, int bw,
+__global__ void __launch_bounds__(256) k_spai_update_many(PencilDev pd, UpdMany U, int eq,
+                                                          int64_t stored, int bw,
                                                           double tol, double* __restrict__ hat,
                                                           int32_t* __restrict__ skip_part,
                                                           const int32_t* __restrict__ need) {
@@ -1597,10 +1614,9 @@ __global__ void __launch_bounds__(256) k_spai_update_many(PencilDev pd, UpdMany 
   for (int s = 0; s < U.count; ++s) {
     // the same for every thread of the block
     if (need && need[(int64_t)s * nb + blockIdx.x] == 0) continue;
-    const double* __restrict__ dv = dinv + (int64_t)s * n_pad;
     double* __restrict__ hs = hat + (int64_t)s * stored;
     __syncthreads();  // staged rows ready; the previous shift's columns done
-    for (int64_t row = d0 + t; row < d1; row += 256) dl[row - d0] = dv[row];
+    for (int64_t row = d0 + t; row < d1; row += 256) dl[row - d0] = row_dinv(pd, U.a[s], U.b[s], eq, row);
     __syncthreads();
     // skip test of column j straight from the staged rows (the scaled
     // values below and in spai_band_column are formed the same way)
@@ -1671,9 +1687,10 @@ __global__ void k_copy_flags(const int8_t* __restrict__ src, int32_t n, uint8_t*
 // Padding entries are 0.  An update whose every column was skipped
 // (skip_total = n) is the scalar alpha I: it is never applied as a factor,
 // so nothing is written.
+// dinv(i): the diagonal scaling of row i.
+template <class Dinv>
 __device__ __forceinline__ void finalize_row(const PencilDev& pd, int64_t r,
-                                             const double* __restrict__ hat,
-                                             const double* __restrict__ dinv, int mode,
+                                             const double* __restrict__ hat, Dinv dinv, int mode,
                                              const int32_t* __restrict__ skip_total,
                                              const int8_t* __restrict__ skipf,
                                              const double* __restrict__ alpha,
@@ -1684,7 +1701,7 @@ __device__ __forceinline__ void finalize_row(const PencilDev& pd, int64_t r,
   const int32_t base = pd.slice_ptr[s] + (int32_t)(r % kSlice);
   const int w = (pd.slice_ptr[s + 1] - pd.slice_ptr[s]) / kSlice;
   const int len = pd.row_len[r];
-  const double sr = dinv[r];
+  const double sr = dinv(r);
   for (int k = 0; k < w; ++k) {
     const int32_t idx = base + k * kSlice;
     double val = 0.0;
@@ -1694,7 +1711,7 @@ __device__ __forceinline__ void finalize_row(const PencilDev& pd, int64_t r,
       // column c (update) is alpha e_c
       double h = (skipf && skipf[c]) ? (c == (int)r ? *alpha : 0.0) : hat[pd.mirror[idx]];
       if (mode == 1) h = 0.5 * (h + hat[idx]);
-      val = mode == 2 ? h * sr / dinv[c] : h * sr * dinv[c];
+      val = mode == 2 ? h * sr / dinv(c) : h * sr * dinv(c);
     }
     v64[idx] = val;
     v32[idx] = (float)val;
@@ -1706,19 +1723,19 @@ __global__ void k_spai_finalize(PencilDev pd, const double* __restrict__ hat,
                                 const int32_t* __restrict__ skip_total,
                                 const int8_t* __restrict__ skipf, const double* __restrict__ alpha,
                                 double* __restrict__ v64, float* __restrict__ v32) {
-  finalize_row(pd, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, hat, dinv, mode, skip_total,
-               skipf, alpha, v64, v32);
+  finalize_row(pd, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, hat,
+               [=](int64_t i) { return dinv[i]; }, mode, skip_total, skipf, alpha, v64, v32);
 }
 
 // k_spai_finalize of the updates of a batch, one grid row (blockIdx.y) per
-// update: hat [count][stored], dinv [count][n_pad].
+// update: hat [count][stored]; the scalings are formed from the diagonal.
 __global__ void k_update_finalize_many(PencilDev pd, UpdMany U, const double* __restrict__ hat,
-                                       const double* __restrict__ dinv, int64_t stored,
-                                       int64_t n_pad) {
+                                       int eq, int64_t stored) {
   const int s = blockIdx.y;
+  const double a = U.a[s], b = U.b[s];
   finalize_row(pd, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, hat + (int64_t)s * stored,
-               dinv + (int64_t)s * n_pad, 2, U.skip[s], U.skipf[s], U.alpha[s], U.v64[s],
-               U.v32[s]);
+               [&](int64_t i) { return row_dinv(pd, a, b, eq, i); }, 2, U.skip[s], U.skipf[s],
+               U.alpha[s], U.v64[s], U.v32[s]);
 }
 
 // out[e] (CSR order) = values[stored idx]
@@ -2143,7 +2160,8 @@ static airga_status run_update_many(airga_ctx ctx, int32_t count, const airga_pr
                                     airga_prec* ps) {
   const Pencil& pen = ctx->pen;
   const bool fits = spai_banded(pen, o, true) && pen.max_len <= 6 &&
-                    spai_many_lds<6>(pen.bandwidth) <= 64 * 1024;
+                    spai_many_lds<6>(pen.bandwidth) <= 64 * 1024 &&
+                    dinv_many_lds(kManyMax, pen.bandwidth) + 1024 <= 64 * 1024;
   if (!fits) {
     for (int i = 0; i < count; ++i) AIRGA_TRY(run_update(ctx, olds[i], s_new[i], o, ps[i]));
     return AIRGA_OK;
@@ -2156,13 +2174,12 @@ static airga_status run_update_many(airga_ctx ctx, int32_t count, const airga_pr
   const bool range = 4 * bw + 1 <= pen.max_len * pen.max_len;
   for (int i0 = 0; i0 < count; i0 += kManyMax) {
     const int cnt = count - i0 < kManyMax ? count - i0 : kManyMax;
-    // scratch: [dinv (cnt n_pad) | hat (cnt stored) | alpha partials | skip
-    // counts | blocks with columns to solve]
-    const size_t bytes = sizeof(double) * ((size_t)cnt * (n_pad + stored) + 2 * (size_t)cnt * nb) +
+    // scratch: [hat (cnt stored) | alpha partials | skip counts | blocks
+    // with columns to solve]
+    const size_t bytes = sizeof(double) * ((size_t)cnt * stored + 2 * (size_t)cnt * nb) +
                          2 * sizeof(int32_t) * (size_t)cnt * nb + 64;
     AIRGA_TRY(ctx->ws_tmp.reserve(bytes));
-    double* dinv = ctx->ws_tmp.as<double>();
-    double* hat = dinv + (size_t)cnt * n_pad;
+    double* hat = ctx->ws_tmp.as<double>();
     double* part = hat + (size_t)cnt * stored;
     int32_t* skp = reinterpret_cast<int32_t*>(part + 2 * (size_t)cnt * nb);
     int32_t* need = skp + (size_t)cnt * nb;
@@ -2178,23 +2195,22 @@ static airga_status run_update_many(airga_ctx ctx, int32_t count, const airga_pr
       U.obj[i] = p->objective.as<double>();
       U.skipf[i] = skip_flags(p);
     }
-    k_dinv_many<<<blocks_for(n_pad, 256), 256, 0, st>>>(pd, U, o.equilibrate, n_pad, dinv);
-    AIRGA_HIP(hipGetLastError());
-    k_alpha_partial_many<<<nb, 256, 0, st>>>(pd, U, dinv, n_pad, part);
+    const size_t dl_lds = dinv_many_lds(cnt, bw);
+    k_alpha_partial_many<<<nb, 256, dl_lds, st>>>(pd, U, bw, o.equilibrate, part);
     AIRGA_HIP(hipGetLastError());
     k_alpha_final_many<<<(unsigned)cnt, 256, 0, st>>>(U, part, nb);
     AIRGA_HIP(hipGetLastError());
-    k_update_test_many<6><<<nb, 256, 0, st>>>(pd, U, dinv, n_pad, o.tol, skp, need);
+    k_update_test_many<6><<<nb, 256, dl_lds, st>>>(pd, U, bw, o.equilibrate, o.tol, skp, need);
     AIRGA_HIP(hipGetLastError());
     const size_t lds = spai_many_lds<6>(bw);
     if (range && pen.contiguous)
-      k_spai_update_many<6, 2><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, o.tol, hat,
+      k_spai_update_many<6, 2><<<nb, 256, lds, st>>>(pd, U, o.equilibrate, stored, bw, o.tol, hat,
                                                      skp, need);
     else if (range)
-      k_spai_update_many<6, 1><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, o.tol, hat,
+      k_spai_update_many<6, 1><<<nb, 256, lds, st>>>(pd, U, o.equilibrate, stored, bw, o.tol, hat,
                                                      skp, need);
     else
-      k_spai_update_many<6, 0><<<nb, 256, lds, st>>>(pd, U, dinv, n_pad, stored, bw, o.tol, hat,
+      k_spai_update_many<6, 0><<<nb, 256, lds, st>>>(pd, U, o.equilibrate, stored, bw, o.tol, hat,
                                                      skp, need);
     AIRGA_HIP(hipGetLastError());
     k_sum_counts_many<<<(unsigned)cnt, 256, 0, st>>>(U, skp, nb);
@@ -2204,7 +2220,7 @@ static airga_status run_update_many(airga_ctx ctx, int32_t count, const airga_pr
       U.v32[i] = ps[i0 + i]->v32.as<float>();
     }
     k_update_finalize_many<<<dim3(blocks_for(n_pad, 256), (unsigned)cnt), 256, 0, st>>>(
-        pd, U, hat, dinv, stored, n_pad);
+        pd, U, hat, o.equilibrate, stored);
     AIRGA_HIP(hipGetLastError());
     for (int i = 0; i < cnt; ++i) {
       const airga_prec p = ps[i0 + i];
