@@ -160,7 +160,8 @@ def test_batched_updates_equal_single_updates(ctx, name):
     """airga_spai_update_many gives exactly the single updates: factor values,
     objectives, alpha and skip counts, for skipped and solved columns, over
     more than one batch of 16 (and through the one-by-one fallback where the
-    staged rows do not fit, or with general_only)."""
+    staged rows do not fit, or with general_only), with and without the
+    diagonal equilibration."""
     pen = {"beam": beam.make_beam(1037, ei_loguniform=(0.5, 2.0), surrogate=True, seed=5),
            "grid8": grid_pencil(8, 150, seed=3), "grid65": grid_pencil(65, 9, seed=2)}[name]
     set_pencil(ctx, pen)
@@ -168,10 +169,11 @@ def test_batched_updates_equal_single_updates(ctx, name):
     olds = [ctx.spai_build(s) for s in base]
     # drifts from none (all columns skip) to large (columns solved)
     new = [s * (1.0 + (0.0 if k % 3 == 0 else 1e-4 if k % 3 == 1 else 0.2)) for k, s in enumerate(base)]
-    for tol, general in ((0.01, False), (0.0, False), (0.01, True)):
-        many = ctx.spai_update_many(olds, new, tol=tol, general_only=general)
+    for tol, general, eq in ((0.01, False, True), (0.0, False, True), (0.01, True, True),
+                             (0.01, False, False)):
+        many = ctx.spai_update_many(olds, new, tol=tol, general_only=general, equilibrate=eq)
         for k, (p, s) in enumerate(zip(olds, new)):
-            one = ctx.spai_update(p, s, tol=tol, general_only=general)
+            one = ctx.spai_update(p, s, tol=tol, general_only=general, equilibrate=eq)
             vm, om = (t.cpu().numpy() for t in many[k].export())
             vo, oo = (t.cpu().numpy() for t in one.export())
             im, io = many[k].info(), one.info()
