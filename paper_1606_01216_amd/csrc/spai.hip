@@ -1573,9 +1573,10 @@ __global__ void __launch_bounds__(256) k_spai_update_many(PencilDev pd, UpdMany 
                                                           int32_t* __restrict__ skip_part,
                                                           const int32_t* __restrict__ need) {
   if (need) {
-    bool any = false;
-    for (int s = 0; s < U.count; ++s) any = any || need[(int64_t)s * gridDim.x + blockIdx.x] != 0;
-    if (!any) return;  // the whole block: before any barrier
+    // one flag per thread, all loads in flight together
+    const int t = threadIdx.x;
+    const int mine = t < U.count ? need[(int64_t)t * gridDim.x + blockIdx.x] : 0;
+    if (!__syncthreads_or(mine != 0)) return;  // the whole block
   }
   extern __shared__ double lds[];
   const int S = 256 + 4 * bw;
@@ -1729,13 +1730,19 @@ __global__ void k_spai_finalize(PencilDev pd, const double* __restrict__ hat,
 
 // k_spai_finalize of the updates of a batch, one grid row (blockIdx.y) per
 // update: hat [count][stored]; the scalings are formed from the diagonal.
+// A grid-stride loop over the rows, so an update whose every column was
+// skipped costs few blocks.
 __global__ void k_update_finalize_many(PencilDev pd, UpdMany U, const double* __restrict__ hat,
                                        int eq, int64_t stored) {
   const int s = blockIdx.y;
+  if (*U.skip[s] == pd.n) return;  // the scalar alpha I: nothing written
   const double a = U.a[s], b = U.b[s];
-  finalize_row(pd, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, hat + (int64_t)s * stored,
-               [&](int64_t i) { return row_dinv(pd, a, b, eq, i); }, 2, U.skip[s], U.skipf[s],
-               U.alpha[s], U.v64[s], U.v32[s]);
+  const int64_t rows = (int64_t)pd.n_slices * kSlice;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows;
+       r += (int64_t)gridDim.x * blockDim.x)
+    finalize_row(pd, r, hat + (int64_t)s * stored,
+                 [&](int64_t i) { return row_dinv(pd, a, b, eq, i); }, 2, U.skip[s], U.skipf[s],
+                 U.alpha[s], U.v64[s], U.v32[s]);
 }
 
 // out[e] (CSR order) = values[stored idx]
@@ -2219,8 +2226,9 @@ static airga_status run_update_many(airga_ctx ctx, int32_t count, const airga_pr
       U.v64[i] = ps[i0 + i]->v64.as<double>();
       U.v32[i] = ps[i0 + i]->v32.as<float>();
     }
-    k_update_finalize_many<<<dim3(blocks_for(n_pad, 256), (unsigned)cnt), 256, 0, st>>>(
-        pd, U, hat, o.equilibrate, stored);
+    const unsigned fb = blocks_for(n_pad, 256) < 512 ? blocks_for(n_pad, 256) : 512;
+    k_update_finalize_many<<<dim3(fb, (unsigned)cnt), 256, 0, st>>>(pd, U, hat, o.equilibrate,
+                                                                    stored);
     AIRGA_HIP(hipGetLastError());
     for (int i = 0; i < cnt; ++i) {
       const airga_prec p = ps[i0 + i];
