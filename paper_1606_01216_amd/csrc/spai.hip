@@ -1486,6 +1486,7 @@ __global__ void __launch_bounds__(256) k_update_test_many(PencilDev pd, UpdMany 
                                                          int32_t* __restrict__ need) {
   extern __shared__ double dl[];
   __shared__ int32_t cnt[kManyMax][4], req[kManyMax][4];
+  __shared__ double als[kManyMax];
   const int64_t j0 = (int64_t)blockIdx.x * 256;
   const int64_t j = j0 + threadIdx.x;
   const int wv = threadIdx.x >> 6;
@@ -1511,11 +1512,13 @@ __global__ void __launch_bounds__(256) k_update_test_many(PencilDev pd, UpdMany 
       }
     }
   }
+  // every shift's alpha, loaded once per block (the staging ends with a barrier)
+  if ((int)threadIdx.x < U.count) als[threadIdx.x] = *U.alpha[threadIdx.x];
   stage_dinv_many(pd, U, eq, d0, d1, W, dl);
   for (int s = 0; s < U.count; ++s) {
     bool skipped = false, solve = false;
     if (in) {
-      const double al = *U.alpha[s];
+      const double al = als[s];
       const double* __restrict__ ds = dl + s * W;
       const double sr = ds[j - d0];
       double n_old = 0, n_res = 0;
