@@ -921,6 +921,10 @@ inline size_t dinv_many_lds(int count, int bw) {
   return sizeof(double) * (size_t)count * (256 + 2 * (size_t)bw);
 }
 
+// Longest row of a pencil whose updates are batched (longer rows take the
+// one-by-one path).
+constexpr int kManyJ = 6;
+
 // k_alpha_partial for every shift, each row of the pencil read once:
 // part[(s * nb + block) * 2 + {0, 1}].  The block's rows and the bw rows on
 // either side (the columns of a banded pattern) have their scalings staged
@@ -937,13 +941,13 @@ __global__ void k_alpha_partial_many(PencilDev pd, UpdMany U, int bw, int eq,
   const int64_t d1 = j0 + 256 + bw < pd.n ? j0 + 256 + bw : pd.n;
   const int W = 256 + 2 * bw;
   int len = 0;
-  int32_t c[kSpaiMaxJ];
-  double m[kSpaiMaxJ], kk[kSpaiMaxJ];
+  int32_t c[kManyJ];
+  double m[kManyJ], kk[kManyJ];
   if (r < pd.n) {
     const int32_t base = pd.slice_ptr[r / kSlice] + (int32_t)(r % kSlice);
     len = pd.row_len[r];
 #pragma unroll
-    for (int k = 0; k < kSpaiMaxJ; ++k) {
+    for (int k = 0; k < kManyJ; ++k) {
       const int32_t idx = base + (k < len ? k : 0) * kSlice;
       c[k] = pd.col[idx];
       m[k] = pd.m64[idx];
@@ -957,7 +961,7 @@ __global__ void k_alpha_partial_many(PencilDev pd, UpdMany U, int bw, int eq,
       const double* __restrict__ ds = dl + s * W;
       const double sr = ds[r - d0];
 #pragma unroll
-      for (int k = 0; k < kSpaiMaxJ; ++k) {
+      for (int k = 0; k < kManyJ; ++k) {
         if (k < len) {
           const double sc = sr * ds[c[k] - d0];
           const double an = fma(U.a[s], m[k], U.b[s] * kk[k]) * sc;
@@ -2169,7 +2173,7 @@ static airga_status run_update_many(airga_ctx ctx, int32_t count, const airga_pr
                                     const double* s_new, const airga_spai_opts& o,
                                     airga_prec* ps) {
   const Pencil& pen = ctx->pen;
-  const bool fits = spai_banded(pen, o, true) && pen.max_len <= 6 &&
+  const bool fits = spai_banded(pen, o, true) && pen.max_len <= kManyJ &&
                     spai_many_lds<6>(pen.bandwidth) <= 64 * 1024 &&
                     dinv_many_lds(kManyMax, pen.bandwidth) + 1024 <= 64 * 1024;
   if (!fits) {
